@@ -1,0 +1,385 @@
+"""Seeded synthetic inputs for the metric-graph particle step.
+
+This module only builds inputs: graph tables (edges, lengths, drift and
+diffusion coefficients, vertex-edge jump probabilities in CSR form) and run
+settings.  It holds none of the method's arithmetic, so both the FP64 CPU
+oracle and the GPU library read the same inputs from here without sharing
+any code with each other.
+
+Graph description (same fields as the C-ABI ``mg_graph_desc``):
+
+* ``edge_init[e]``, ``edge_term[e]``: the two vertices of edge e; positions
+  on e are measured from ``edge_init[e]`` (x in [0, length[e]]).
+* ``drift_a[e] + drift_c[e] * x``: the drift mu_e(x) in that coordinate.
+* ``sigma[e]``: the diffusion coefficient on e.
+* ``vtx_offsets``/``slot_edge``/``slot_orient``/``slot_jump_prob``: per
+  vertex v, slots ``vtx_offsets[v] .. vtx_offsets[v+1]-1`` list the incident
+  edge ends; orient 0 means v is the edge's initial vertex (a particle enters
+  at x = 0), 1 means its terminal vertex (enters at x = L).  The jump
+  probabilities b_{v,e} of the standard gluing conditions sum to 1 per vertex.
+* ``vtx_kind[v]``: 0 standard vertex, 1 absorbing vertex.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "GraphDesc", "from_edges", "star_graph", "segment", "random_tree",
+    "config1", "config2", "config3", "config4", "paper_star5",
+]
+
+
+@dataclass
+class GraphDesc:
+    n_vertices: int
+    n_edges: int
+    edge_init: np.ndarray
+    edge_term: np.ndarray
+    length: np.ndarray
+    drift_a: np.ndarray
+    drift_c: np.ndarray
+    sigma: np.ndarray
+    vtx_offsets: np.ndarray
+    slot_edge: np.ndarray
+    slot_orient: np.ndarray
+    slot_jump_prob: np.ndarray
+    vtx_kind: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.vtx_offsets[-1])
+
+
+def from_edges(n_vertices, edge_init, edge_term, length, drift_a=None,
+               drift_c=None, sigma=1.0, weight_init=None, weight_term=None,
+               vtx_kind=None, meta=None) -> GraphDesc:
+    """Build the CSR slot table from an edge list.
+
+    ``weight_init[e]``/``weight_term[e]`` are nonnegative weights of edge e at
+    its initial/terminal vertex; they are divided by their per-vertex sum to
+    give the jump probabilities (all ones = uniform jump probabilities).
+    Slots of a vertex are ordered by edge id, the initial end before the
+    terminal end for a self-loop.
+    """
+    ei = np.asarray(edge_init, dtype=np.int32)
+    et = np.asarray(edge_term, dtype=np.int32)
+    E = int(ei.shape[0])
+    V = int(n_vertices)
+    L = np.broadcast_to(np.asarray(length, dtype=np.float64), (E,)).copy()
+    a = np.zeros(E) if drift_a is None else np.broadcast_to(np.asarray(drift_a, np.float64), (E,)).copy()
+    c = np.zeros(E) if drift_c is None else np.broadcast_to(np.asarray(drift_c, np.float64), (E,)).copy()
+    s = np.broadcast_to(np.asarray(sigma, dtype=np.float64), (E,)).copy()
+    wi = np.ones(E) if weight_init is None else np.asarray(weight_init, np.float64)
+    wt = np.ones(E) if weight_term is None else np.asarray(weight_term, np.float64)
+    kind = np.zeros(V, np.uint8) if vtx_kind is None else np.asarray(vtx_kind, np.uint8).copy()
+
+    # (vertex, edge, end) triples sorted by vertex, then edge, then end.
+    verts = np.concatenate([ei, et])
+    edges = np.concatenate([np.arange(E), np.arange(E)]).astype(np.int32)
+    ends = np.concatenate([np.zeros(E, np.uint8), np.ones(E, np.uint8)])
+    w = np.concatenate([wi, wt])
+    order = np.lexsort((ends, edges, verts))
+    verts, edges, ends, w = verts[order], edges[order], ends[order], w[order]
+    counts = np.bincount(verts, minlength=V)
+    offsets = np.zeros(V + 1, np.int32)
+    np.cumsum(counts, out=offsets[1:])
+    tot = np.bincount(verts, weights=w, minlength=V)
+    b = np.where(tot[verts] > 0, w / np.where(tot[verts] > 0, tot[verts], 1.0), 0.0)
+    return GraphDesc(V, E, ei, et, L, a, c, s, offsets, edges.astype(np.int32),
+                     ends.astype(np.uint8), b.astype(np.float64), kind,
+                     dict(meta or {}))
+
+
+def star_graph(n_edges, length=1.0, drift_a=None, drift_c=None, sigma=1.0,
+               b_center=None, meta=None) -> GraphDesc:
+    """Finite star: centre vertex 0, leaf vertex i+1 at the far end of edge i.
+
+    Edge i runs from the centre (x = 0) to leaf i+1 (x = L_i); each leaf is a
+    degree-1 vertex (jump probability 1, i.e. reflecting)."""
+    E = int(n_edges)
+    ei = np.zeros(E, np.int32)
+    et = np.arange(1, E + 1, dtype=np.int32)
+    wi = np.ones(E) if b_center is None else np.asarray(b_center, np.float64)
+    return from_edges(E + 1, ei, et, length, drift_a, drift_c, sigma,
+                      weight_init=wi, meta=meta)
+
+
+def segment(length=1.0, drift_a=0.0, drift_c=0.0, sigma=1.0) -> GraphDesc:
+    """One edge between two degree-1 (reflecting) vertices."""
+    return from_edges(2, [0], [1], [length], [drift_a], [drift_c], sigma)
+
+
+def random_tree(n_edges, rng, length_range=(0.2, 3.0), sigma=np.sqrt(2.0),
+                quadratic=False, meta=None) -> GraphDesc:
+    """Random recursive tree: vertex i >= 1 hangs from a uniform earlier vertex.
+
+    With ``quadratic`` each edge carries the potential k (x - m)^2
+    (k ~ U[0.5, 4], m ~ U[0, L]), i.e. drift 2 k m - 2 k x; otherwise no drift.
+    Jump probabilities are uniform per vertex."""
+    E = int(n_edges)
+    parents = np.array([rng.integers(0, i) for i in range(1, E + 1)], np.int32)
+    ei = parents
+    et = np.arange(1, E + 1, dtype=np.int32)
+    L = rng.uniform(*length_range, size=E)
+    a = c = None
+    if quadratic:
+        k = rng.uniform(0.5, 4.0, size=E)
+        m = rng.uniform(0.0, 1.0, size=E) * L
+        a, c = 2.0 * k * m, -2.0 * k
+    return from_edges(E + 1, ei, et, L, a, c, sigma, meta=meta)
+
+
+# ----------------------------------------------------------------- configs
+
+def config1() -> tuple[GraphDesc, dict]:
+    """Plain EM on a 3-edge star: lengths 1, no drift, sigma 1, b = 1/3;
+    1e4 particles start at the centre; dt 1e-3, 1000 steps, 8 splits per step
+    at most, Philox seed 0, 100 bins per edge."""
+    g = star_graph(3, 1.0, None, None, 1.0, meta={"name": "star3"})
+    run = dict(n_particles=10_000, init="vertex", vertex=0, dt=1e-3,
+               n_steps=1000, max_splits=8, seed=0, bins=100)
+    return g, run
+
+
+def config2(seed: int = 2) -> tuple[GraphDesc, dict]:
+    """Langevin on a 64-edge star: L ~ U[0.5, 2], potential
+    V_e(x) = k_e (x - m_e)^2 with k_e ~ U[0.5, 4], m_e ~ U[0, L_e], sigma =
+    sqrt(2) (so the stationary law is exp(-V) up to the vertex weights), jump
+    probabilities proportional to the diffusivity (all equal: 1/64); 1e7
+    particles uniform by length, dt in {1e-2, 1e-3}, 1e4 steps, 256 bins."""
+    rng = np.random.default_rng(seed)
+    E = 64
+    L = rng.uniform(0.5, 2.0, size=E)
+    k = rng.uniform(0.5, 4.0, size=E)
+    m = rng.uniform(0.0, 1.0, size=E) * L
+    sig = np.sqrt(2.0)
+    diff = np.full(E, 0.5 * sig * sig)
+    g = star_graph(E, L, 2.0 * k * m, -2.0 * k, sig, b_center=diff,
+                   meta={"name": "langevin_star64", "k": k, "m": m})
+    run = dict(n_particles=10_000_000, init="uniform", dts=(1e-2, 1e-3),
+               n_steps=10_000, max_splits=8, seed=0, bins=256)
+    return g, run
+
+
+def paper_star5(potential: str = "linear", length: float = 2.0,
+                sigma: float = 1.0) -> GraphDesc:
+    """The 5-edge star of the paper's experiments (Sec. 4), edges truncated to
+    a finite length with reflecting leaves: mu_i = -10 i (linear potential) or
+    mu_i = -10 i x (quadratic potential), uniform b = 1/5."""
+    i = np.arange(1, 6, dtype=np.float64)
+    if potential == "linear":
+        a, c = -10.0 * i, np.zeros(5)
+    elif potential == "quadratic":
+        a, c = np.zeros(5), -10.0 * i
+    else:
+        raise ValueError(potential)
+    return star_graph(5, length, a, c, sigma,
+                      meta={"name": f"paper_star5_{potential}"})
+
+
+def _vascular_topology(rng, n_vertices, n_edges, n_leaves, side):
+    """Connected spatial graph with degree 3 at internal vertices and degree 1
+    at leaves: a degree-capped nearest-neighbour spanning tree of the internal
+    points, leaves hung on the nearest internal vertex with a free stub, then
+    the remaining stubs paired with nearby vertices (each such pair closes one
+    independent cycle)."""
+    from scipy.spatial import cKDTree
+    import heapq
+
+    n_int = n_vertices - n_leaves
+    pts = rng.uniform(0.0, side, size=(n_vertices, 3))
+    ip = pts[:n_int]
+    tree = cKDTree(ip)
+    deg = np.zeros(n_vertices, np.int64)
+    adj = [set() for _ in range(n_vertices)]
+    edges = []
+
+    def add(u, v):
+        edges.append((u, v))
+        adj[u].add(v)
+        adj[v].add(u)
+        deg[u] += 1
+        deg[v] += 1
+
+    # 1. spanning tree of internal vertices, tree degree <= 3 (Prim order).
+    in_tree = np.zeros(n_int, bool)
+    heap = []
+    knn = 10
+
+    def push(u):
+        d, nb = tree.query(ip[u], k=knn)
+        for dd, v in zip(np.atleast_1d(d), np.atleast_1d(nb)):
+            if v != u and not in_tree[v]:
+                heapq.heappush(heap, (float(dd), int(u), int(v)))
+
+    in_tree[0] = True
+    push(0)
+    n_in = 1
+    while n_in < n_int:
+        while heap:
+            d, u, v = heapq.heappop(heap)
+            if in_tree[v] or deg[u] >= 3:
+                continue
+            add(u, v)
+            in_tree[v] = True
+            n_in += 1
+            push(v)
+        if n_in < n_int:
+            # restart: nearest free-capacity tree vertex for some outsider
+            out = np.flatnonzero(~in_tree)
+            cap = np.flatnonzero(in_tree & (deg[:n_int] < 2))
+            ct = cKDTree(ip[cap])
+            d, j = ct.query(ip[out[0]])
+            add(int(cap[j]), int(out[0]))
+            in_tree[out[0]] = True
+            n_in += 1
+            push(int(out[0]))
+    # 2. leaves hang on the nearest internal vertex with a free stub.
+    for lf in range(n_int, n_vertices):
+        k = 8
+        while True:
+            d, nb = tree.query(pts[lf], k=min(k, n_int))
+            cand = [int(v) for v in np.atleast_1d(nb) if deg[v] < 3]
+            if cand:
+                add(cand[0], lf)
+                break
+            k *= 4
+    # 3. pair the remaining internal stubs with nearby free vertices.
+    free = [v for v in rng.permutation(n_int) for _ in range(3 - deg[v])]
+    pending = set(int(v) for v in free)
+    for u in free:
+        u = int(u)
+        if deg[u] >= 3:
+            continue
+        d, nb = tree.query(ip[u], k=24)
+        for v in np.atleast_1d(nb):
+            v = int(v)
+            if v != u and deg[v] < 3 and v not in adj[u]:
+                add(u, v)
+                break
+    left = [v for v in range(n_int) for _ in range(3 - deg[v])]
+    cycle_edges = [i for i, (u, v) in enumerate(edges) if u < n_int and v < n_int]
+    while left:
+        u = left.pop()
+        partner = None
+        for j, v in enumerate(left):
+            if v != u and v not in adj[u]:
+                partner = j
+                break
+        if partner is not None:
+            v = left.pop(partner)
+            add(u, v)
+            continue
+        # u holds the last free stub(s): trade an existing edge (c, d) for
+        # (u, c) and (u, d); needs two free stubs on u.
+        left.remove(u) if u in left else None
+        while True:
+            i = int(rng.integers(len(edges)))
+            c, d = edges[i]
+            if c >= n_int or d >= n_int or u in (c, d) or c in adj[u] or d in adj[u]:
+                continue
+            edges.pop(i)
+            adj[c].discard(d)
+            adj[d].discard(c)
+            deg[c] -= 1
+            deg[d] -= 1
+            add(u, c)
+            add(u, d)
+            break
+    del pending, cycle_edges
+    return pts, np.array(edges, dtype=np.int64)
+
+
+def config3(seed: int = 3) -> tuple[GraphDesc, dict]:
+    """Synthetic stand-in for a cortical microvascular network (tracer
+    transport, Sec. 4.2 of the paper): 20k vertices / 26k edges in a cube,
+    degree 3 inside and 1 at the 4k boundary vertices; lengths lognormal
+    (median 40 um, sigma_log 0.6); radii lognormal (median 4 um, sigma_log
+    0.3); Poiseuille flow under random boundary pressures; drift = mean
+    velocity Q/(pi r^2) scaled to a median speed of 1 mm/s; diffusivity
+    1e-9 m^2/s; jump probabilities proportional to the cross-section pi r^2;
+    inflow boundary vertices reflect, outflow ones absorb.  Units are
+    made dimensionless with L0 = 40 um and T0 = L0^2 / D, so sigma = sqrt(2).
+    dt is ten times the upwind finite-volume CFL limit with 64 cells per
+    edge; 1e8 particles uniform by length, 1e4 steps, 64 bins per edge."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+
+    rng = np.random.default_rng(seed)
+    V, E, n_leaf = 20_000, 26_000, 4_000
+    pts, edges = _vascular_topology(rng, V, E, n_leaf, side=1.2e-3)
+    assert edges.shape[0] == E
+    flip = rng.random(E) < 0.5
+    ei = np.where(flip, edges[:, 1], edges[:, 0]).astype(np.int32)
+    et = np.where(flip, edges[:, 0], edges[:, 1]).astype(np.int32)
+    L0, D, eta = 40e-6, 1e-9, 3.5e-3
+    T0 = L0 * L0 / D
+    Lm = 40e-6 * np.exp(0.6 * rng.standard_normal(E))
+    r = 4e-6 * np.exp(0.3 * rng.standard_normal(E))
+    G = np.pi * r ** 4 / (8.0 * eta * Lm)
+    deg = np.bincount(np.concatenate([ei, et]), minlength=V)
+    leaf = deg == 1
+    p = np.zeros(V)
+    p[leaf] = rng.uniform(0.0, 1.0, size=int(leaf.sum()))
+    # Kirchhoff: sum_e G_e (p_v - p_w) = 0 at internal vertices.
+    lap = sp.coo_matrix((np.concatenate([G, G, -G, -G]),
+                         (np.concatenate([ei, et, ei, et]),
+                          np.concatenate([ei, et, et, ei]))), shape=(V, V)).tocsr()
+    inner = np.flatnonzero(~leaf)
+    bnd = np.flatnonzero(leaf)
+    A = lap[inner][:, inner].tocsc()
+    rhs = -(lap[inner][:, bnd] @ p[bnd])
+    p[inner] = spla.spsolve(A, rhs)
+    Q = G * (p[ei] - p[et])              # > 0: flow from init to term
+    u = Q / (np.pi * r * r)
+    u *= 1e-3 / np.median(np.abs(u))
+    # boundary vertices: inflow (reflecting) or outflow (absorbing)
+    kind = np.zeros(V, np.uint8)
+    for lf in bnd:
+        e = int(np.flatnonzero((ei == lf) | (et == lf))[0])
+        out_flow = (ei[e] == lf and Q[e] < 0) or (et[e] == lf and Q[e] > 0)
+        kind[lf] = 1 if out_flow else 0
+    area = np.pi * r * r
+    Lh = Lm / L0
+    mu = u * T0 / L0
+    sig = np.sqrt(2.0)
+    dx = Lh / 64.0
+    dt_cfl = np.min(1.0 / (np.abs(mu) / dx + 2.0 * (0.5 * sig * sig) / (dx * dx)))
+    g = from_edges(V, ei, et, Lh, mu, None, sig, weight_init=area,
+                   weight_term=area, vtx_kind=kind,
+                   meta={"name": "vascular20k", "T0": T0, "L0": L0,
+                         "dt_cfl": float(dt_cfl)})
+    run = dict(n_particles=100_000_000, init="uniform", dt=10.0 * float(dt_cfl),
+               n_steps=10_000, max_splits=8, seed=0, bins=64)
+    return g, run
+
+
+def config4(seed: int = 4) -> tuple[list, list, dict]:
+    """512 independent graphs of uneven size: even ids stars, odd ids random
+    recursive trees; edges round(loguniform[3, 4096]); L ~ U[0.2, 3];
+    particle counts loguniform[1e4, 1e6]; even graphs without drift, odd
+    graphs with per-edge quadratic potentials (Langevin); sigma = sqrt(2);
+    uniform jump probabilities; dt 1e-3, 1000 steps, 64 bins per edge."""
+    rng = np.random.default_rng(seed)
+    graphs, counts = [], []
+    for gi in range(512):
+        E = int(np.rint(np.exp(rng.uniform(np.log(3), np.log(4096)))))
+        quad = gi % 2 == 1
+        if gi % 4 < 2:
+            L = rng.uniform(0.2, 3.0, size=E)
+            a = c = None
+            if quad:
+                k = rng.uniform(0.5, 4.0, size=E)
+                m = rng.uniform(0.0, 1.0, size=E) * L
+                a, c = 2.0 * k * m, -2.0 * k
+            g = star_graph(E, L, a, c, np.sqrt(2.0), meta={"name": f"batch{gi}"})
+        else:
+            g = random_tree(E, rng, quadratic=quad, meta={"name": f"batch{gi}"})
+        graphs.append(g)
+        counts.append(int(np.rint(np.exp(rng.uniform(np.log(1e4), np.log(1e6))))))
+    run = dict(init="uniform", dt=1e-3, n_steps=1000, max_splits=8, seed=0,
+               bins=64)
+    return graphs, counts, run
