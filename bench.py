@@ -1,0 +1,187 @@
+"""Benchmark of the timestep-splitting EM particle step on one MI355X.
+
+Workload (the metric's configuration): the 64-edge Langevin star
+(quadratic potentials, sigma = sqrt(2), b = 1/64), 1e7 particles uniform by
+length, 1e4 steps at dt = 1e-2 and at dt = 1e-3, 256 bins per edge.  One
+benchmark step is one pass of the whole hot path for both dt: particle
+initialisation, the fused multi-step kernel, exit counts and the histogram.
+The FP32 path is the headline value; the FP64 path is timed beside it and
+the FP32 histograms and exit probabilities are compared with FP64's under
+common random numbers.
+
+Prints one JSON line.  Only one GPU: --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-substeps/s at 1 GPU, FP32 vs FP64, + % VALU peak at TV≤2e-3"
+PEAK_LANE_CYCLES = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock
+
+# Algorithmic VALU work of the method in full-rate lane-cycles (a
+# quarter-rate operation -- 32x32->64 product, transcendental -- counts 4).
+# Derivation in DESIGN.md ("Roofline").
+ALG_FP32_STEP = 49.5     # per particle-step: 1/4 Philox + 1/2 Box-Muller pair + EM
+ALG_FP32_HIT = 166.0     # per vertex hit: Philox, one normal, root, slot, edge
+ALG_FP64_STEP = 70.0
+ALG_FP64_HIT = 190.0
+
+
+def alg_work(prec: int, steps: int, hits: int) -> float:
+    if prec == 1:
+        return ALG_FP32_STEP * steps + ALG_FP32_HIT * hits
+    return ALG_FP64_STEP * steps + ALG_FP64_HIT * hits
+
+
+def exit_probs(ex, offsets):
+    import numpy as np
+    p = np.zeros(ex.size)
+    for v in range(offsets.size - 1):
+        s0, s1 = offsets[v], offsets[v + 1]
+        t = ex[s0:s1].sum()
+        if t:
+            p[s0:s1] = ex[s0:s1] / t
+    return p
+
+
+def run_pass(B, G, g, run, prec, dt, torch, kernel_times):
+    """One pass of the path at one dt: init, simulate, exit counts, histogram."""
+    p = B.mg_particles_init(G, run["n_particles"], B.MG_INIT_UNIFORM_LENGTH, init_seed=0,
+                            precision=prec, max_splits=run["max_splits"])
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    B.mg_simulate(p, run["n_steps"], dt, run["seed"])
+    e1.record()
+    ex, ab, tot = B.mg_exit_counts(p)
+    hist = B.mg_histogram(p, run["bins"])
+    kernel_times.append(e0.elapsed_time(e1) * 1e-3)
+    return dict(substeps=int(tot[1]), hits=int(tot[2]), steps=int(tot[3]),
+                trunc=int(tot[0]), exit=ex, hist=hist)
+
+
+def cpu_baseline(g, run, n_sample: int):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    st = oracle.init(g, run["n_particles"], oracle.INIT_UNIFORM_LENGTH, seed=0,
+                     pids=__import__("numpy").arange(n_sample))
+    t0 = time.perf_counter()
+    c = oracle.simulate(g, st, 0, run["n_steps"], 1e-3, run["seed"], threads=threads,
+                        max_splits=run["max_splits"])
+    dt = time.perf_counter() - t0
+    return {"value": c.substeps / dt, "unit": "particle-substeps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"particle ids 0..{n_sample - 1} of the same workload at dt=1e-3, "
+                      f"{run['n_steps']} steps, FP64 ({c.substeps} sub-steps in {dt:.2f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
+    ap.add_argument("--cpu-sample", type=int, default=40_000)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); the "
+              "particle step shards by particle range with no communication but no "
+              "multi-GPU path is built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2512_02175_amd import binding as B
+
+    torch.cuda.set_device(0)
+    g, run = workloads.config2()
+    G = B.mg_graph_create(g)
+    dts = run["dts"]
+
+    def step(prec, ktimes):
+        return [run_pass(B, G, g, run, prec, dt, torch, ktimes) for dt in dts]
+
+    # FP32: the headline path
+    for _ in range(args.warmup):
+        step(1, [])
+    torch.cuda.synchronize()
+    ktimes32 = []
+    t0 = time.perf_counter()
+    res32 = None
+    for _ in range(args.steps):
+        res32 = step(1, ktimes32)
+    torch.cuda.synchronize()
+    wall32 = time.perf_counter() - t0
+    sub32 = sum(r["substeps"] for r in res32) * args.steps
+    value = sub32 / wall32
+
+    out_fp64 = None
+    tv = exit_err = None
+    if not args.no_fp64:
+        ktimes64 = []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res64 = step(0, ktimes64)
+        torch.cuda.synchronize()
+        wall64 = time.perf_counter() - t1
+        sub64 = sum(r["substeps"] for r in res64)
+        tv = [0.5 * float(np.abs(a["hist"].astype(float) - b["hist"].astype(float)).sum())
+              / float(b["hist"].sum()) for a, b in zip(res32, res64)]
+        exit_err = [float(np.abs(exit_probs(a["exit"], g.vtx_offsets)
+                                 - exit_probs(b["exit"], g.vtx_offsets)).max())
+                    for a, b in zip(res32, res64)]
+        k64 = sum(ktimes64)
+        w64 = sum(alg_work(0, r["steps"], r["hits"]) for r in res64)
+        out_fp64 = {"value": sub64 / wall64, "unit": "particle-substeps/s",
+                    "kernel_substeps_per_s": sub64 / k64,
+                    "alg_frac_of_alu_peak": w64 / k64 / PEAK_LANE_CYCLES,
+                    "fp32_speedup": value / (sub64 / wall64)}
+
+    # roofline of the dominant kernel (the fused step kernel), per launch
+    k32 = float(np.mean(ktimes32))
+    per_launch = [alg_work(1, r["steps"], r["hits"]) for r in res32]
+    achieved = float(np.mean(per_launch)) / k32
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_CYCLES / 1e12,
+            "unit": "T lane-cycles/s", "frac": achieved / PEAK_LANE_CYCLES, "traffic": None,
+            "kernel": "k_step<fp32>", "kernel_ms_per_launch": k32 * 1e3,
+            "alg_lane_cycles_per_particle_step": ALG_FP32_STEP,
+            "alg_lane_cycles_per_hit": ALG_FP32_HIT}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "particle-substeps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall32 / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "langevin_star64: 64-edge star, V_e=k(x-m)^2, sigma=sqrt(2), "
+                               "b=1/64, 1e7 particles uniform by length, 1e4 steps at "
+                               "dt=1e-2 and dt=1e-3, M=8, 256 bins/edge",
+                   "n_particles": run["n_particles"], "n_steps": run["n_steps"],
+                   "dts": list(dts), "bins_per_edge": run["bins"]},
+        "particle_steps_per_s": sum(r["steps"] for r in res32) * args.steps / wall32,
+        "kernel_substeps_per_s": sum(r["substeps"] for r in res32) / sum(ktimes32) * args.steps,
+        "hits_per_step": [r["hits"] / r["steps"] for r in res32],
+        "truncations": [r["trunc"] for r in res32],
+        "fp64": out_fp64,
+        "tv_fp32_vs_fp64": tv,
+        "exit_prob_err_fp32_vs_fp64": exit_err,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(g, run, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * metricgraph.h -- C ABI of the MI355X (gfx950) timestep-splitting
+ * Euler-Maruyama particle step on metric graphs.
+ *
+ * Method: Dwaraknath & Ying, "Sampling on Metric Graphs".  A particle is a
+ * pair (edge e, position x in [0, L_e]) with x measured from the edge's
+ * initial vertex.  Each step is the EM move x + mu_e(x) dt + sigma_e sqrt(dt) W
+ * (Sec. 3, Eq. euler_maruyama_real_line); when the move leaves the edge
+ * through a vertex, the step is split at the crossing, a new incident edge
+ * is drawn from the vertex-edge jump probabilities b_v of the standard
+ * gluing conditions (Def. 4), and the particle continues with the remaining
+ * time (Alg. 2; Alg. 1 for the move from a vertex), at most M times per step.
+ *
+ * Conventions for every call:
+ *  - Functions return mg_status; mg_last_error() describes the last failure
+ *    of the calling thread (valid until that thread's next call).
+ *  - Input arrays are read during the call and copied; the caller keeps
+ *    ownership.  Output pointers may be host or device memory (the library
+ *    copies with unified addressing); their lengths are checked and a short
+ *    buffer gives MG_EINVAL.
+ *  - Handles belong to the caller and are released by the matching
+ *    *_destroy (NULL is accepted).  A handle must not be used by two threads
+ *    at once.
+ *  - Work is enqueued on the HIP stream given in mg_options (NULL: the null
+ *    stream).  Calls that return results synchronise that stream.  An error
+ *    found by a kernel (state out of range, non-finite position) is reported
+ *    as MG_EDEVICE by the next call that synchronises.
+ */
+#ifndef METRICGRAPH_H
+#define METRICGRAPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MG_OK = 0,
+  MG_EINVAL = 1,   /* invalid argument or graph */
+  MG_ENOMEM = 2,   /* device or host allocation failed, or arena too small */
+  MG_EDEVICE = 3,  /* HIP runtime error or kernel-reported error */
+  MG_ESTATE = 4    /* call not valid in the handle's current state */
+} mg_status;
+
+typedef enum { MG_FP64 = 0, MG_FP32 = 1 } mg_precision;
+
+typedef enum { MG_VTX_STANDARD = 0, MG_VTX_ABSORBING = 1 } mg_vertex_kind;
+
+typedef struct mg_graph mg_graph;          /* opaque */
+typedef struct mg_particles mg_particles;  /* opaque */
+typedef struct mg_batch mg_batch;          /* opaque */
+
+/*
+ * Graph description (Def. 1 metric graph; Def. 4 jump probabilities;
+ * Alg. 2's vertex tables).  All pointers are host memory.
+ *   n_vertices, n_edges  V >= 1, E >= 1.
+ *   edge_init/edge_term  [E] vertex ids; x = 0 at edge_init, x = L at edge_term.
+ *   length               [E] finite, > 0.
+ *   drift_a, drift_c     [E] drift mu_e(x) = a_e + c_e x (NULL: 0); finite.
+ *   sigma                [E] finite, > 0 (the paper takes sigma continuous
+ *                        at vertices; that is the caller's responsibility).
+ *   vtx_offsets          [V+1] CSR offsets, offsets[0] = 0, nondecreasing.
+ *   slot_edge            [nnz] incident edge of each slot.
+ *   slot_orient          [nnz] 0: the vertex is the edge's initial vertex (a
+ *                        particle enters at x = 0); 1: terminal (enters at L).
+ *   slot_jump_prob       [nnz] b_{v,e} >= 0, summing to 1 per vertex within
+ *                        1e-9 (the library divides by the sum).
+ *   vtx_kind             [V] mg_vertex_kind, or NULL for all standard.  An
+ *                        absorbing vertex removes a particle that hits it
+ *                        (Wentzell killing term a_v = 1, Sec. 2.2).
+ * Every edge must appear exactly once at its initial vertex with orient 0
+ * and once at its terminal vertex with orient 1 (a self-loop twice at its
+ * vertex).  A standard vertex needs at least one slot with b > 0.
+ */
+typedef struct {
+  int32_t n_vertices, n_edges;
+  const int32_t *edge_init, *edge_term;
+  const double *length;
+  const double *drift_a, *drift_c;
+  const double *sigma;
+  const int32_t *vtx_offsets;
+  const int32_t *slot_edge;
+  const uint8_t *slot_orient;
+  const double *slot_jump_prob;
+  const uint8_t *vtx_kind;
+} mg_graph_desc;
+
+/* Validates and packs the graph into device tables (edge records, slot
+ * thresholds, vertex records).  *out is NULL on failure. */
+mg_status mg_graph_create(const mg_graph_desc *desc, mg_graph **out);
+void mg_graph_destroy(mg_graph *g);
+
+/*
+ * Options of a particle set.
+ *   precision     MG_FP64 (reference arithmetic) or MG_FP32 (positions held
+ *                 relative to the nearer edge end, compensated remaining
+ *                 time, FP64 crossing solve within 1e-6 L of a vertex).
+ *   max_splits    M >= 1, the most vertex hits per step (0: default 8).
+ *   graph_tag     fourth Philox counter word; independent streams for sets
+ *                 that share seeds (e.g. the members of a batch).
+ *   trace         nonzero: keep a per-particle hit-sequence hash and hit
+ *                 count, readable with mg_particles_read.
+ *   steps_per_launch  steps fused in one kernel launch (0: automatic).
+ *   hip_stream    hipStream_t to enqueue on (NULL: null stream).
+ *   arena, arena_bytes  optional caller-owned device memory for all of the
+ *                 set's device arrays (size from mg_particles_arena_bytes);
+ *                 NULL: the library allocates.  The arena must outlive the
+ *                 set.
+ */
+typedef struct {
+  mg_precision precision;
+  int32_t max_splits;
+  uint32_t graph_tag;
+  int32_t trace;
+  int32_t steps_per_launch;
+  void *hip_stream;
+  void *arena;
+  int64_t arena_bytes;
+} mg_options;
+
+typedef enum {
+  MG_INIT_EXPLICIT = 0,        /* edge[i], pos[i] given (host arrays) */
+  MG_INIT_AT_VERTEX = 1,       /* all on `vertex`; edge drawn from b_vertex */
+  MG_INIT_UNIFORM_LENGTH = 2   /* edge with prob. L_e / sum L, x ~ U(0, L_e) */
+} mg_init_mode;
+
+/* Bytes of device memory a particle set of n particles needs. */
+int64_t mg_particles_arena_bytes(const mg_graph *g, int64_t n,
+                                 const mg_options *opt);
+
+/*
+ * Creates n particles (1 <= n <= 2^32 - 1) on graph g.  Random draws of
+ * the non-explicit modes use the init stream of Philox keyed by init_seed.
+ * EXPLICIT needs 0 <= pos[i] <= L_{edge[i]}; a position on an end means the
+ * particle sits on that vertex.  AT_VERTEX needs a standard vertex.  The set
+ * keeps a reference to g, which must outlive it.  The step counter starts
+ * at 0.
+ */
+mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
+                            const int32_t *edge, const double *pos,
+                            int32_t vertex, uint64_t init_seed,
+                            const mg_options *opt, mg_particles **out);
+void mg_particles_destroy(mg_particles *p);
+
+/*
+ * Advances every particle by n_steps steps of size dt > 0 (Alg. 2), using
+ * Philox keyed by seed; the set's step counter advances by n_steps, so
+ * k calls of n steps equal one call of k*n steps bit for bit.  The step
+ * counter must stay below 2^32.  Exit counts, absorbed counts, truncations
+ * and sub-step counts accumulate across calls.
+ */
+mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed);
+
+/*
+ * Uniform-bin histogram of the alive particles (appendix kernels):
+ * out[e * bins_per_edge + b] = number of particles on e with
+ * min(bins_per_edge - 1, floor(x * bins_per_edge / L_e)) = b.
+ * out_len must be >= E * bins_per_edge.  Synchronises the stream.
+ */
+mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge,
+                       uint64_t *out, int64_t out_len);
+
+/*
+ * Accumulated counters (Corollary 1 exit edges): slot_counts[nnz] counts,
+ * per slot, the steps whose last vertex hit drew that slot (alive
+ * particles); absorbed[V] the particles removed at each vertex;
+ * totals[4] = {truncated steps, sub-steps (consumed normals), vertex hits,
+ * steps}.  Any pointer may be NULL.  Synchronises the stream.
+ */
+mg_status mg_exit_counts(const mg_particles *p, uint64_t *slot_counts,
+                         uint64_t *absorbed, uint64_t *totals);
+
+/*
+ * Copies particles [first, first + count): edge id, position from the
+ * edge's initial vertex (FP64; FP32 sets are converted), alive flag, and,
+ * for traced sets, the hit-sequence hash (FNV-1a over 32-bit words
+ * (step, slot) per hit, (step, 0x80000000 | vertex) for an absorption) and
+ * the hit count.  Any pointer may be NULL.  Synchronises the stream.
+ */
+mg_status mg_particles_read(const mg_particles *p, int64_t first, int64_t count,
+                            int32_t *edge, double *pos, uint8_t *alive,
+                            uint64_t *seqhash, uint32_t *hits);
+
+/* Steps taken so far (the set's step counter). */
+int64_t mg_particles_step(const mg_particles *p);
+
+/*
+ * Batch of independent particle sets (possibly on different graphs) that
+ * mg_batch_simulate advances in one launch per steps_per_launch chunk.  All
+ * sets must have the same precision and the same max_splits; each keeps its
+ * own graph_tag, counters and step counter, and every set's results equal
+ * those of mg_simulate on that set alone.  The batch references the sets,
+ * which must outlive it; it launches on the first set's stream.
+ */
+mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **out);
+mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t seed);
+void mg_batch_destroy(mg_batch *b);
+
+/* Description of the calling thread's last error ("" if none). */
+const char *mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* METRICGRAPH_H */

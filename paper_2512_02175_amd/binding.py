@@ -1,0 +1,297 @@
+"""ctypes binding of libmetricgraph.so (include/metricgraph.h).
+
+Functions keep the C names and only marshal arguments: every step of the
+path runs in the library's HIP kernels.  PyTorch, when present, supplies the
+HIP stream (``torch.cuda.current_stream()``) and, on request, the device
+memory of a particle set (``arena="torch"``).  There is no fallback: if the
+library is not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmetricgraph.so")
+
+MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ESTATE = 0, 1, 2, 3, 4
+MG_FP64, MG_FP32 = 0, 1
+MG_VTX_STANDARD, MG_VTX_ABSORBING = 0, 1
+MG_INIT_EXPLICIT, MG_INIT_AT_VERTEX, MG_INIT_UNIFORM_LENGTH = 0, 1, 2
+
+EXPORTED = (
+    "mg_graph_create", "mg_graph_destroy", "mg_particles_arena_bytes",
+    "mg_particles_init", "mg_particles_destroy", "mg_simulate", "mg_histogram",
+    "mg_exit_counts", "mg_particles_read", "mg_particles_step", "mg_batch_create",
+    "mg_batch_simulate", "mg_batch_destroy", "mg_last_error",
+)
+
+
+class MgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[status {status}] {msg}")
+        self.status = status
+
+
+class mg_graph_desc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_edges", C.c_int32),
+                ("edge_init", C.c_void_p), ("edge_term", C.c_void_p),
+                ("length", C.c_void_p), ("drift_a", C.c_void_p),
+                ("drift_c", C.c_void_p), ("sigma", C.c_void_p),
+                ("vtx_offsets", C.c_void_p), ("slot_edge", C.c_void_p),
+                ("slot_orient", C.c_void_p), ("slot_jump_prob", C.c_void_p),
+                ("vtx_kind", C.c_void_p)]
+
+
+class mg_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("max_splits", C.c_int32),
+                ("graph_tag", C.c_uint32), ("trace", C.c_int32),
+                ("steps_per_launch", C.c_int32), ("hip_stream", C.c_void_p),
+                ("arena", C.c_void_p), ("arena_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2512_02175_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+        L.mg_graph_create.argtypes = [vp, vp]
+        L.mg_graph_destroy.argtypes = [vp]
+        L.mg_graph_destroy.restype = None
+        L.mg_particles_arena_bytes.argtypes = [vp, i64, vp]
+        L.mg_particles_arena_bytes.restype = i64
+        L.mg_particles_init.argtypes = [vp, i64, C.c_int, vp, vp, i32, u64, vp, vp]
+        L.mg_particles_destroy.argtypes = [vp]
+        L.mg_particles_destroy.restype = None
+        L.mg_simulate.argtypes = [vp, i64, C.c_double, u64]
+        L.mg_histogram.argtypes = [vp, i32, vp, i64]
+        L.mg_exit_counts.argtypes = [vp, vp, vp, vp]
+        L.mg_particles_read.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
+        L.mg_particles_step.argtypes = [vp]
+        L.mg_particles_step.restype = i64
+        L.mg_batch_create.argtypes = [i32, vp, vp]
+        L.mg_batch_simulate.argtypes = [vp, i64, C.c_double, u64]
+        L.mg_batch_destroy.argtypes = [vp]
+        L.mg_batch_destroy.restype = None
+        L.mg_last_error.restype = C.c_char_p
+        for name in EXPORTED:
+            if name not in ("mg_graph_destroy", "mg_particles_destroy",
+                            "mg_batch_destroy", "mg_last_error",
+                            "mg_particles_arena_bytes", "mg_particles_step"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def mg_last_error() -> str:
+    return lib().mg_last_error().decode()
+
+
+def _check(st: int):
+    if st != MG_OK:
+        raise MgError(st, mg_last_error())
+
+
+def _p(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _torch_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return None
+
+
+class Graph:
+    """Owns an mg_graph handle (destroyed with the object)."""
+
+    def __init__(self, handle, desc):
+        self.handle = handle
+        self.n_vertices = int(desc.n_vertices)
+        self.n_edges = int(desc.n_edges)
+        self.nnz = int(desc.vtx_offsets[-1])
+        self.length = np.asarray(desc.length, np.float64).copy()
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mg_graph_destroy(self.handle)
+            self.handle = None
+
+
+class Particles:
+    """Owns an mg_particles handle; keeps its graph and arena alive."""
+
+    def __init__(self, handle, graph: Graph, n: int, precision: int, arena=None):
+        self.handle = handle
+        self.graph = graph
+        self.n = n
+        self.precision = precision
+        self._arena = arena
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mg_particles_destroy(self.handle)
+            self.handle = None
+
+
+class Batch:
+    def __init__(self, handle, sets):
+        self.handle = handle
+        self.sets = list(sets)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mg_batch_destroy(self.handle)
+            self.handle = None
+
+
+def mg_graph_create(desc) -> Graph:
+    """``desc`` has the fields of mg_graph_desc as numpy arrays (see
+    ``workloads.GraphDesc``)."""
+    keep = dict(
+        edge_init=np.ascontiguousarray(desc.edge_init, np.int32),
+        edge_term=np.ascontiguousarray(desc.edge_term, np.int32),
+        length=np.ascontiguousarray(desc.length, np.float64),
+        drift_a=np.ascontiguousarray(desc.drift_a, np.float64),
+        drift_c=np.ascontiguousarray(desc.drift_c, np.float64),
+        sigma=np.ascontiguousarray(desc.sigma, np.float64),
+        vtx_offsets=np.ascontiguousarray(desc.vtx_offsets, np.int32),
+        slot_edge=np.ascontiguousarray(desc.slot_edge, np.int32),
+        slot_orient=np.ascontiguousarray(desc.slot_orient, np.uint8),
+        slot_jump_prob=np.ascontiguousarray(desc.slot_jump_prob, np.float64),
+        vtx_kind=np.ascontiguousarray(desc.vtx_kind, np.uint8),
+    )
+    d = mg_graph_desc(int(desc.n_vertices), int(desc.n_edges),
+                      *[keep[k].ctypes.data for k in (
+                          "edge_init", "edge_term", "length", "drift_a", "drift_c",
+                          "sigma", "vtx_offsets", "slot_edge", "slot_orient",
+                          "slot_jump_prob", "vtx_kind")])
+    h = C.c_void_p()
+    _check(lib().mg_graph_create(C.byref(d), C.byref(h)))
+    return Graph(h, desc)
+
+
+def mg_graph_destroy(g: Graph) -> None:
+    if g.handle:
+        lib().mg_graph_destroy(g.handle)
+        g.handle = None
+
+
+def _options(precision, max_splits, graph_tag, trace, steps_per_launch, stream,
+             arena_ptr=None, arena_bytes=0):
+    return mg_options(int(precision), int(max_splits), int(graph_tag), int(bool(trace)),
+                      int(steps_per_launch),
+                      stream if stream is not None else _torch_stream(),
+                      arena_ptr, int(arena_bytes))
+
+
+def mg_particles_arena_bytes(g: Graph, n: int, precision=MG_FP64, trace=False) -> int:
+    o = _options(precision, 0, 0, trace, 0, None)
+    return int(lib().mg_particles_arena_bytes(g.handle, int(n), C.byref(o)))
+
+
+def mg_particles_init(g: Graph, n: int, mode: int, *, edge=None, pos=None, vertex: int = 0,
+                      init_seed: int = 0, precision: int = MG_FP64, max_splits: int = 8,
+                      graph_tag: int = 0, trace: bool = False, steps_per_launch: int = 0,
+                      stream=None, arena=None) -> Particles:
+    """``arena``: None (library allocates), "torch" (a torch uint8 CUDA
+    tensor of the required size), or a torch tensor to use."""
+    e = None if edge is None else np.ascontiguousarray(edge, np.int32)
+    x = None if pos is None else np.ascontiguousarray(pos, np.float64)
+    arena_obj, aptr, abytes = None, None, 0
+    if arena is not None:
+        import torch
+        need = mg_particles_arena_bytes(g, n, precision, trace)
+        arena_obj = (torch.empty(need, dtype=torch.uint8, device="cuda")
+                     if isinstance(arena, str) else arena)
+        aptr, abytes = C.c_void_p(arena_obj.data_ptr()), arena_obj.numel() * arena_obj.element_size()
+    o = _options(precision, max_splits, graph_tag, trace, steps_per_launch, stream, aptr, abytes)
+    h = C.c_void_p()
+    _check(lib().mg_particles_init(g.handle, int(n), int(mode), _p(e), _p(x), int(vertex),
+                                   C.c_uint64(init_seed), C.byref(o), C.byref(h)))
+    return Particles(h, g, int(n), int(precision), arena_obj)
+
+
+def mg_particles_destroy(p: Particles) -> None:
+    if p.handle:
+        lib().mg_particles_destroy(p.handle)
+        p.handle = None
+
+
+def mg_simulate(p: Particles, n_steps: int, dt: float, seed: int) -> None:
+    _check(lib().mg_simulate(p.handle, int(n_steps), float(dt), C.c_uint64(seed)))
+
+
+def mg_histogram(p: Particles, bins_per_edge: int, out=None):
+    """Returns a [E, bins] uint64 numpy array, or fills ``out`` (a numpy
+    array or a torch CUDA tensor of int64/uint64 with E*bins elements)."""
+    E = p.graph.n_edges
+    if out is None:
+        out = np.zeros(E * bins_per_edge, np.uint64)
+        _check(lib().mg_histogram(p.handle, int(bins_per_edge), _p(out), out.size))
+        return out.reshape(E, bins_per_edge)
+    if isinstance(out, np.ndarray):
+        _check(lib().mg_histogram(p.handle, int(bins_per_edge), _p(out), out.size))
+    else:
+        _check(lib().mg_histogram(p.handle, int(bins_per_edge), C.c_void_p(out.data_ptr()),
+                                  out.numel()))
+    return out
+
+
+def mg_exit_counts(p: Particles):
+    """(slot_counts[nnz], absorbed[V], totals[4]) with totals =
+    (truncations, sub-steps, vertex hits, particle-steps)."""
+    s = np.zeros(max(p.graph.nnz, 1), np.uint64)
+    a = np.zeros(max(p.graph.n_vertices, 1), np.uint64)
+    t = np.zeros(4, np.uint64)
+    _check(lib().mg_exit_counts(p.handle, _p(s), _p(a), _p(t)))
+    return s[: p.graph.nnz], a[: p.graph.n_vertices], t
+
+
+def mg_particles_read(p: Particles, first: int = 0, count: int | None = None, trace=False):
+    count = p.n - first if count is None else count
+    edge = np.zeros(count, np.int32)
+    pos = np.zeros(count, np.float64)
+    alive = np.zeros(count, np.uint8)
+    sh = np.zeros(count, np.uint64) if trace else None
+    hi = np.zeros(count, np.uint32) if trace else None
+    _check(lib().mg_particles_read(p.handle, int(first), int(count), _p(edge), _p(pos),
+                                   _p(alive), _p(sh), _p(hi)))
+    out = dict(edge=edge, x=pos, alive=alive)
+    if trace:
+        out.update(seqhash=sh, hits=hi)
+    return out
+
+
+def mg_particles_step(p: Particles) -> int:
+    return int(lib().mg_particles_step(p.handle))
+
+
+def mg_batch_create(sets) -> Batch:
+    arr = (C.c_void_p * len(sets))(*[s.handle for s in sets])
+    h = C.c_void_p()
+    _check(lib().mg_batch_create(len(sets), arr, C.byref(h)))
+    return Batch(h, sets)
+
+
+def mg_batch_simulate(b: Batch, n_steps: int, dt: float, seed: int) -> None:
+    _check(lib().mg_batch_simulate(b.handle, int(n_steps), float(dt), C.c_uint64(seed)))
+
+
+def mg_batch_destroy(b: Batch) -> None:
+    if b.handle:
+        lib().mg_batch_destroy(b.handle)
+        b.handle = None

@@ -1,0 +1,651 @@
+// mg_api.hip -- host side of the C ABI declared in include/metricgraph.h:
+// graph validation and packing, particle-set memory, launch orchestration
+// and readback.  All per-particle work runs in the kernels of
+// mg_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/metricgraph.h"
+#include "mg_internal.h"
+
+using namespace mg;
+
+namespace {
+
+thread_local std::string g_err;
+
+mg_status fail(mg_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+mg_status hip_fail(hipError_t e, const char *what) {
+  return fail(MG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define MG_HIP(call, what)                       \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// Slot thresholds (the slot draw): per vertex b is divided by its sum and
+// accumulated left to right in FP64 into C_s; T_s = floor(C_s 2^32), and
+// T_s = 2^32 from the last slot with b > 0 onward.
+void slot_thresholds(int32_t V, const int32_t *off, const double *b,
+                     std::vector<uint64_t> &thr) {
+  for (int32_t v = 0; v < V; ++v) {
+    const int32_t s0 = off[v], s1 = off[v + 1];
+    double total = 0.0;
+    int32_t last_pos = -1;
+    for (int32_t s = s0; s < s1; ++s) {
+      total += b[s];
+      if (b[s] > 0.0) last_pos = s;
+    }
+    double cum = 0.0;
+    for (int32_t s = s0; s < s1; ++s) {
+      if (last_pos < 0) {
+        thr[s] = 0;
+        continue;
+      }
+      cum += b[s] / total;
+      if (s >= last_pos) {
+        thr[s] = 1ull << 32;
+      } else {
+        const double t = std::floor(cum * 4294967296.0);
+        thr[s] = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
+      }
+    }
+  }
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct mg_graph {
+  int32_t V, E, nnz;
+  std::vector<double> length;  // host copy for readback conversion
+  void *dev = nullptr;         // one allocation holding every table
+  GraphDev gd{};
+};
+
+struct mg_particles {
+  const mg_graph *g = nullptr;
+  int64_t n = 0;
+  mg_precision prec = MG_FP64;
+  int32_t max_splits = 8;
+  uint32_t tag = 0;
+  bool trace = false;
+  int32_t steps_per_launch = 0;
+  hipStream_t stream = nullptr;
+  bool owns = false;
+  void *mem = nullptr;
+  SetDev sd{};
+  uint64_t step = 0;
+};
+
+struct mg_batch {
+  std::vector<mg_particles *> sets;
+  void *dev = nullptr;  // GraphDev[n] + SetDev[n] + BatchItem[items]
+  GraphDev *d_graphs = nullptr;
+  SetDev *d_sets = nullptr;
+  BatchItem *d_items = nullptr;
+  int32_t n_items = 0;
+  int32_t max_nnz = 0;
+};
+
+namespace {
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct SetLayout {
+  size_t ef, pos, hash, hits, exitc, absorbed, totals, err, total;
+};
+
+SetLayout set_layout(int32_t V, int32_t nnz, int64_t n, mg_precision prec, bool trace) {
+  SetLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  L.ef = take((size_t)n * 4);
+  L.pos = take((size_t)n * (prec == MG_FP64 ? 8 : 4));
+  L.hash = trace ? take((size_t)n * 8) : 0;
+  L.hits = trace ? take((size_t)n * 4) : 0;
+  L.exitc = take((size_t)std::max(nnz, 1) * 8);
+  L.absorbed = take((size_t)std::max(V, 1) * 8);
+  L.totals = take(4 * 8);
+  L.err = take(4);
+  L.total = off;
+  return L;
+}
+
+mg_status check_device_error(const mg_particles *p) {
+  uint32_t err = 0;
+  MG_HIP(hipMemcpyAsync(&err, p->sd.err, 4, hipMemcpyDeviceToHost, p->stream),
+         "reading the device error word");
+  MG_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+  if (err & kErrEdge) return fail(MG_EDEVICE, "a particle's edge id is out of range");
+  if (err & kErrPos) return fail(MG_EDEVICE, "a particle's position is outside its edge");
+  return MG_OK;
+}
+
+bool is_device_pointer(const void *ptr) {
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mg_last_error(void) { return g_err.c_str(); }
+
+mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
+  g_err.clear();
+  if (!out) return fail(MG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(MG_EINVAL, "desc is NULL");
+  const int32_t V = d->n_vertices, E = d->n_edges;
+  if (V < 1 || E < 1) return fail(MG_EINVAL, "need at least one vertex and one edge");
+  if (E > kMaxEdges) return fail(MG_EINVAL, "too many edges");
+  if (!d->edge_init || !d->edge_term || !d->length || !d->sigma || !d->vtx_offsets ||
+      !d->slot_edge || !d->slot_orient || !d->slot_jump_prob)
+    return fail(MG_EINVAL, "a required array is NULL");
+  const int32_t *off = d->vtx_offsets;
+  if (off[0] != 0) return fail(MG_EINVAL, "vtx_offsets[0] must be 0");
+  for (int32_t v = 0; v < V; ++v)
+    if (off[v + 1] < off[v]) return fail(MG_EINVAL, "vtx_offsets decreases at vertex %d", v);
+  const int32_t nnz = off[V];
+  if ((int64_t)nnz != 2 * (int64_t)E)
+    return fail(MG_EINVAL, "nnz = %d, but every edge needs two slots (2E = %d)", nnz, 2 * E);
+  for (int32_t e = 0; e < E; ++e) {
+    if (d->edge_init[e] < 0 || d->edge_init[e] >= V || d->edge_term[e] < 0 ||
+        d->edge_term[e] >= V)
+      return fail(MG_EINVAL, "edge %d has a vertex out of range", e);
+    if (!is_finite(d->length[e]) || !(d->length[e] > 0.0))
+      return fail(MG_EINVAL, "edge %d: length must be finite and > 0", e);
+    if (!is_finite(d->sigma[e]) || !(d->sigma[e] > 0.0))
+      return fail(MG_EINVAL, "edge %d: sigma must be finite and > 0", e);
+    if (d->drift_a && !is_finite(d->drift_a[e])) return fail(MG_EINVAL, "edge %d: drift_a not finite", e);
+    if (d->drift_c && !is_finite(d->drift_c[e])) return fail(MG_EINVAL, "edge %d: drift_c not finite", e);
+  }
+  // every edge exactly once at each end with the right orientation
+  std::vector<uint8_t> seen((size_t)E * 2, 0);
+  for (int32_t v = 0; v < V; ++v) {
+    double sum = 0.0;
+    bool any_pos = false;
+    for (int32_t s = off[v]; s < off[v + 1]; ++s) {
+      const int32_t e = d->slot_edge[s];
+      const uint8_t o = d->slot_orient[s];
+      if (e < 0 || e >= E) return fail(MG_EINVAL, "slot %d: edge out of range", s);
+      if (o > 1) return fail(MG_EINVAL, "slot %d: orient must be 0 or 1", s);
+      const int32_t end_v = o ? d->edge_term[e] : d->edge_init[e];
+      if (end_v != v)
+        return fail(MG_EINVAL, "slot %d at vertex %d names edge %d, which does not end there", s, v, e);
+      if (seen[(size_t)e * 2 + o]++) return fail(MG_EINVAL, "edge %d end %d listed twice", e, o);
+      const double b = d->slot_jump_prob[s];
+      if (!is_finite(b) || b < 0.0) return fail(MG_EINVAL, "slot %d: jump probability must be >= 0", s);
+      sum += b;
+      any_pos |= b > 0.0;
+    }
+    const bool absorbing = d->vtx_kind && d->vtx_kind[v] == MG_VTX_ABSORBING;
+    if (d->vtx_kind && d->vtx_kind[v] > 1) return fail(MG_EINVAL, "vertex %d: unknown kind", v);
+    if (!absorbing) {
+      if (!any_pos) return fail(MG_EINVAL, "standard vertex %d has no positive jump probability", v);
+      if (std::fabs(sum - 1.0) > 1e-9)
+        return fail(MG_EINVAL, "vertex %d: jump probabilities sum to %.17g, not 1", v, sum);
+    }
+  }
+  for (size_t i = 0; i < seen.size(); ++i)
+    if (!seen[i]) return fail(MG_EINVAL, "edge %zu end %zu is missing from the slot table", i / 2, i % 2);
+
+  // pack
+  std::vector<EdgeRec64> e64(E);
+  std::vector<EdgeRec32> e32(E);
+  for (int32_t e = 0; e < E; ++e) {
+    const double a = d->drift_a ? d->drift_a[e] : 0.0;
+    const double c = d->drift_c ? d->drift_c[e] : 0.0;
+    e64[e] = {d->length[e], a, c, d->sigma[e], d->edge_init[e], d->edge_term[e], 0, 0};
+    e32[e] = {(float)d->length[e], (float)a, (float)c, (float)d->sigma[e],
+              (float)std::fma(c, d->length[e], a), d->edge_init[e], d->edge_term[e], 0.0f};
+  }
+  std::vector<uint64_t> thr(nnz);
+  slot_thresholds(V, off, d->slot_jump_prob, thr);
+  std::vector<SlotRec> slots(nnz);
+  for (int32_t s = 0; s < nnz; ++s) slots[s] = {thr[s], d->slot_edge[s], d->slot_orient[s]};
+  std::vector<VtxRec> vtx(V);
+  for (int32_t v = 0; v < V; ++v) {
+    const bool absorbing = d->vtx_kind && d->vtx_kind[v] == MG_VTX_ABSORBING;
+    vtx[v] = {off[v], absorbing ? -1 : off[v + 1] - off[v]};
+  }
+  // length-proportional init thresholds, built like the slot thresholds
+  std::vector<uint64_t> lthr(E);
+  {
+    double total = 0.0;
+    for (int32_t e = 0; e < E; ++e) total += d->length[e];
+    double cum = 0.0;
+    for (int32_t e = 0; e < E; ++e) {
+      cum += d->length[e];
+      if (e == E - 1) {
+        lthr[e] = 1ull << 32;
+      } else {
+        const double t = std::floor((cum / total) * 4294967296.0);
+        lthr[e] = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
+      }
+    }
+  }
+  mg_graph *g = new mg_graph();
+  g->V = V;
+  g->E = E;
+  g->nnz = nnz;
+  g->length.assign(d->length, d->length + E);
+  const size_t o64 = 0;
+  const size_t o32 = align_up(o64 + sizeof(EdgeRec64) * E, 256);
+  const size_t osl = align_up(o32 + sizeof(EdgeRec32) * E, 256);
+  const size_t ovx = align_up(osl + sizeof(SlotRec) * nnz, 256);
+  const size_t olt = align_up(ovx + sizeof(VtxRec) * V, 256);
+  const size_t total = align_up(olt + 8 * (size_t)E, 256);
+  hipError_t he = hipMalloc(&g->dev, total);
+  if (he != hipSuccess) {
+    delete g;
+    return fail(MG_ENOMEM, "hipMalloc of %zu bytes for the graph: %s", total, hipGetErrorString(he));
+  }
+  char *base = (char *)g->dev;
+  std::vector<char> host(total, 0);
+  std::memcpy(host.data() + o64, e64.data(), sizeof(EdgeRec64) * E);
+  std::memcpy(host.data() + o32, e32.data(), sizeof(EdgeRec32) * E);
+  std::memcpy(host.data() + osl, slots.data(), sizeof(SlotRec) * nnz);
+  std::memcpy(host.data() + ovx, vtx.data(), sizeof(VtxRec) * V);
+  std::memcpy(host.data() + olt, lthr.data(), 8 * (size_t)E);
+  he = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    (void)hipFree(g->dev);
+    delete g;
+    return hip_fail(he, "copying the graph tables");
+  }
+  g->gd.e64 = (const EdgeRec64 *)(base + o64);
+  g->gd.e32 = (const EdgeRec32 *)(base + o32);
+  g->gd.slots = (const SlotRec *)(base + osl);
+  g->gd.vtx = (const VtxRec *)(base + ovx);
+  g->gd.len_thr = (const uint64_t *)(base + olt);
+  g->gd.V = V;
+  g->gd.E = E;
+  g->gd.nnz = nnz;
+  *out = g;
+  return MG_OK;
+}
+
+void mg_graph_destroy(mg_graph *g) {
+  if (!g) return;
+  if (g->dev) (void)hipFree(g->dev);
+  delete g;
+}
+
+int64_t mg_particles_arena_bytes(const mg_graph *g, int64_t n, const mg_options *opt) {
+  if (!g || n < 1) return -1;
+  const mg_precision prec = opt ? opt->precision : MG_FP64;
+  const bool trace = opt && opt->trace;
+  return (int64_t)set_layout(g->V, g->nnz, n, prec, trace).total;
+}
+
+mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
+                            const int32_t *edge, const double *pos, int32_t vertex,
+                            uint64_t init_seed, const mg_options *opt,
+                            mg_particles **out) {
+  g_err.clear();
+  if (!out) return fail(MG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!g) return fail(MG_EINVAL, "graph is NULL");
+  if (n < 1 || n > 0xFFFFFFFFll) return fail(MG_EINVAL, "n must be in [1, 2^32 - 1]");
+  mg_options o{};
+  o.precision = MG_FP64;
+  if (opt) o = *opt;
+  if (o.precision != MG_FP64 && o.precision != MG_FP32) return fail(MG_EINVAL, "unknown precision");
+  if (o.max_splits < 0) return fail(MG_EINVAL, "max_splits must be >= 0 (0: default)");
+  if (o.max_splits == 0) o.max_splits = 8;
+  if (o.steps_per_launch < 0) return fail(MG_EINVAL, "steps_per_launch must be >= 0");
+  if (mode == MG_INIT_EXPLICIT) {
+    if (!edge || !pos) return fail(MG_EINVAL, "explicit init needs edge and pos");
+    for (int64_t i = 0; i < n; ++i) {
+      if (edge[i] < 0 || edge[i] >= g->E) return fail(MG_EINVAL, "particle %lld: edge out of range", (long long)i);
+      if (!(pos[i] >= 0.0 && pos[i] <= g->length[edge[i]]))
+        return fail(MG_EINVAL, "particle %lld: position outside [0, L]", (long long)i);
+    }
+  } else if (mode == MG_INIT_AT_VERTEX) {
+    if (vertex < 0 || vertex >= g->V) return fail(MG_EINVAL, "vertex out of range");
+    VtxRec vr;
+    if (hipMemcpy(&vr, g->gd.vtx + vertex, sizeof vr, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(MG_EDEVICE, "reading the vertex table");
+    if (vr.deg <= 0) return fail(MG_EINVAL, "vertex %d is absorbing or isolated", vertex);
+  } else if (mode != MG_INIT_UNIFORM_LENGTH) {
+    return fail(MG_EINVAL, "unknown init mode");
+  }
+  const SetLayout L = set_layout(g->V, g->nnz, n, o.precision, o.trace != 0);
+  mg_particles *p = new mg_particles();
+  p->g = g;
+  p->n = n;
+  p->prec = o.precision;
+  p->max_splits = o.max_splits;
+  p->tag = o.graph_tag;
+  p->trace = o.trace != 0;
+  p->steps_per_launch = o.steps_per_launch;
+  p->stream = (hipStream_t)o.hip_stream;
+  if (o.arena) {
+    if (o.arena_bytes < (int64_t)L.total) {
+      delete p;
+      return fail(MG_ENOMEM, "arena of %lld bytes is smaller than the %zu needed",
+                  (long long)o.arena_bytes, L.total);
+    }
+    if (((uintptr_t)o.arena) % 256) {
+      delete p;
+      return fail(MG_EINVAL, "arena must be 256-byte aligned");
+    }
+    p->mem = o.arena;
+  } else {
+    hipError_t he = hipMalloc(&p->mem, L.total);
+    if (he != hipSuccess) {
+      delete p;
+      return fail(MG_ENOMEM, "hipMalloc of %zu bytes: %s", L.total, hipGetErrorString(he));
+    }
+    p->owns = true;
+  }
+  char *base = (char *)p->mem;
+  SetDev &s = p->sd;
+  s.ef = (uint32_t *)(base + L.ef);
+  s.x64 = o.precision == MG_FP64 ? (double *)(base + L.pos) : nullptr;
+  s.y32 = o.precision == MG_FP32 ? (float *)(base + L.pos) : nullptr;
+  s.seqhash = p->trace ? (uint64_t *)(base + L.hash) : nullptr;
+  s.hits = p->trace ? (uint32_t *)(base + L.hits) : nullptr;
+  s.exit_cnt = (uint64_t *)(base + L.exitc);
+  s.absorbed = (uint64_t *)(base + L.absorbed);
+  s.totals = (uint64_t *)(base + L.totals);
+  s.err = (uint32_t *)(base + L.err);
+  s.n = (uint32_t)n;
+  s.n0 = 0;
+  s.tag = p->tag;
+  auto bail = [&](mg_status st) {
+    mg_particles_destroy(p);
+    return st;
+  };
+  // counters start at zero (a kernel-free clear: the region is contiguous)
+  hipError_t he = hipMemsetAsync(base + L.exitc, 0, L.total - L.exitc, p->stream);
+  if (he != hipSuccess) return bail(hip_fail(he, "clearing the counters"));
+  int32_t *d_edge = nullptr;
+  double *d_pos = nullptr;
+  void *tmp = nullptr;
+  if (mode == MG_INIT_EXPLICIT) {
+    he = hipMalloc(&tmp, (size_t)n * 12 + 256);
+    if (he != hipSuccess) return bail(fail(MG_ENOMEM, "staging explicit positions: %s", hipGetErrorString(he)));
+    d_pos = (double *)tmp;
+    d_edge = (int32_t *)((char *)tmp + align_up((size_t)n * 8, 256));
+    he = hipMemcpyAsync(d_pos, pos, (size_t)n * 8, hipMemcpyHostToDevice, p->stream);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(d_edge, edge, (size_t)n * 4, hipMemcpyHostToDevice, p->stream);
+    if (he != hipSuccess) {
+      (void)hipFree(tmp);
+      return bail(hip_fail(he, "copying explicit positions"));
+    }
+  }
+  he = launch_init(g->gd, s, (int)mode, vertex, (uint32_t)init_seed,
+                   (uint32_t)(init_seed >> 32), d_edge, d_pos, o.precision == MG_FP64,
+                   p->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (he != hipSuccess) return bail(hip_fail(he, "initialising particles"));
+  *out = p;
+  return MG_OK;
+}
+
+void mg_particles_destroy(mg_particles *p) {
+  if (!p) return;
+  if (p->owns && p->mem) {
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipFree(p->mem);
+  }
+  delete p;
+}
+
+int64_t mg_particles_step(const mg_particles *p) { return p ? (int64_t)p->step : -1; }
+
+static mg_status check_steps(const mg_particles *p, int64_t n_steps, double dt) {
+  if (n_steps < 0) return fail(MG_EINVAL, "n_steps must be >= 0");
+  if (!is_finite(dt) || !(dt > 0.0)) return fail(MG_EINVAL, "dt must be finite and > 0");
+  if ((uint64_t)p->step + (uint64_t)n_steps > 0xFFFFFFFFull)
+    return fail(MG_EINVAL, "the step counter would reach 2^32");
+  return MG_OK;
+}
+
+static uint32_t chunk_steps(int32_t spl) {
+  // Steps fused per launch.  Per-lane tallies are 32-bit and a launch may
+  // not run forever, so cap a chunk at 2^20 steps.
+  const uint32_t cap = 1u << 20;
+  return spl > 0 ? std::min<uint32_t>((uint32_t)spl, cap) : cap;
+}
+
+mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed) {
+  g_err.clear();
+  if (!p) return fail(MG_EINVAL, "particles is NULL");
+  mg_status st = check_steps(p, n_steps, dt);
+  if (st != MG_OK) return st;
+  StepArgs a{};
+  a.max_splits = p->max_splits;
+  a.key0 = (uint32_t)seed;
+  a.key1 = (uint32_t)(seed >> 32);
+  a.dt = dt;
+  const uint32_t chunk = chunk_steps(p->steps_per_launch);
+  int64_t left = n_steps;
+  while (left > 0) {
+    const uint32_t now = (uint32_t)std::min<int64_t>(left, chunk);
+    a.nsteps = now;
+    p->sd.n0 = (uint32_t)p->step;
+    hipError_t he = launch_step(p->g->gd, p->sd, a, p->prec == MG_FP64, p->trace, p->stream);
+    if (he != hipSuccess) return hip_fail(he, "launching the step kernel");
+    p->step += now;
+    left -= now;
+  }
+  return MG_OK;
+}
+
+mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge, uint64_t *out,
+                       int64_t out_len) {
+  g_err.clear();
+  if (!p || !out) return fail(MG_EINVAL, "NULL argument");
+  if (bins_per_edge < 1) return fail(MG_EINVAL, "bins_per_edge must be >= 1");
+  const int64_t need = (int64_t)p->g->E * bins_per_edge;
+  if (need > 0x7FFFFFFF) return fail(MG_EINVAL, "E * bins_per_edge too large");
+  if (out_len < need) return fail(MG_EINVAL, "out_len %lld < E * bins_per_edge = %lld",
+                                  (long long)out_len, (long long)need);
+  const bool dev_out = is_device_pointer(out);
+  uint64_t *d_out = out;
+  if (!dev_out) MG_HIP(hipMalloc(&d_out, (size_t)need * 8), "allocating the histogram");
+  hipError_t he = hipMemsetAsync(d_out, 0, (size_t)need * 8, p->stream);
+  if (he == hipSuccess)
+    he = launch_histogram(p->g->gd, p->sd, bins_per_edge, d_out, p->prec == MG_FP64, p->stream);
+  if (he == hipSuccess && !dev_out)
+    he = hipMemcpyAsync(out, d_out, (size_t)need * 8, hipMemcpyDeviceToHost, p->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
+  if (!dev_out) (void)hipFree(d_out);
+  if (he != hipSuccess) return hip_fail(he, "computing the histogram");
+  return check_device_error(p);
+}
+
+mg_status mg_exit_counts(const mg_particles *p, uint64_t *slot_counts, uint64_t *absorbed,
+                         uint64_t *totals) {
+  g_err.clear();
+  if (!p) return fail(MG_EINVAL, "particles is NULL");
+  if (slot_counts)
+    MG_HIP(hipMemcpyAsync(slot_counts, p->sd.exit_cnt, (size_t)p->g->nnz * 8,
+                          hipMemcpyDefault, p->stream), "copying exit counts");
+  if (absorbed)
+    MG_HIP(hipMemcpyAsync(absorbed, p->sd.absorbed, (size_t)p->g->V * 8, hipMemcpyDefault,
+                          p->stream), "copying absorbed counts");
+  if (totals)
+    MG_HIP(hipMemcpyAsync(totals, p->sd.totals, 4 * 8, hipMemcpyDefault, p->stream),
+           "copying totals");
+  MG_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+  return check_device_error(p);
+}
+
+mg_status mg_particles_read(const mg_particles *p, int64_t first, int64_t count,
+                            int32_t *edge, double *pos, uint8_t *alive, uint64_t *seqhash,
+                            uint32_t *hits) {
+  g_err.clear();
+  if (!p) return fail(MG_EINVAL, "particles is NULL");
+  if (first < 0 || count < 0 || first + count > p->n) return fail(MG_EINVAL, "range out of bounds");
+  if ((seqhash || hits) && !p->trace) return fail(MG_ESTATE, "the set was created without trace");
+  if (count == 0) return MG_OK;
+  std::vector<uint32_t> ef(count);
+  MG_HIP(hipMemcpyAsync(ef.data(), p->sd.ef + first, (size_t)count * 4, hipMemcpyDeviceToHost,
+                        p->stream), "copying states");
+  std::vector<double> x64;
+  std::vector<float> y32;
+  if (pos) {
+    if (p->prec == MG_FP64) {
+      x64.resize(count);
+      MG_HIP(hipMemcpyAsync(x64.data(), p->sd.x64 + first, (size_t)count * 8,
+                            hipMemcpyDeviceToHost, p->stream), "copying positions");
+    } else {
+      y32.resize(count);
+      MG_HIP(hipMemcpyAsync(y32.data(), p->sd.y32 + first, (size_t)count * 4,
+                            hipMemcpyDeviceToHost, p->stream), "copying positions");
+    }
+  }
+  if (seqhash)
+    MG_HIP(hipMemcpyAsync(seqhash, p->sd.seqhash + first, (size_t)count * 8, hipMemcpyDefault,
+                          p->stream), "copying hashes");
+  if (hits)
+    MG_HIP(hipMemcpyAsync(hits, p->sd.hits + first, (size_t)count * 4, hipMemcpyDefault,
+                          p->stream), "copying hit counts");
+  MG_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+  for (int64_t i = 0; i < count; ++i) {
+    const int32_t e = (int32_t)(ef[i] & kEdgeMask);
+    if (edge) edge[i] = e;
+    if (alive) alive[i] = (ef[i] & kDeadBit) ? 0 : 1;
+    if (pos) {
+      if (p->prec == MG_FP64) {
+        pos[i] = x64[i];
+      } else {
+        const double y = (double)y32[i];
+        pos[i] = (ef[i] & kSideBit) ? p->g->length[e] - y : y;
+      }
+    }
+  }
+  return check_device_error(p);
+}
+
+mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **out) {
+  g_err.clear();
+  if (!out) return fail(MG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_sets < 1 || !sets) return fail(MG_EINVAL, "need at least one set");
+  for (int32_t i = 0; i < n_sets; ++i) {
+    if (!sets[i]) return fail(MG_EINVAL, "set %d is NULL", i);
+    if (sets[i]->prec != sets[0]->prec) return fail(MG_EINVAL, "sets differ in precision");
+    if (sets[i]->max_splits != sets[0]->max_splits) return fail(MG_EINVAL, "sets differ in max_splits");
+    if (sets[i]->trace != sets[0]->trace) return fail(MG_EINVAL, "sets differ in trace");
+    for (int32_t j = 0; j < i; ++j)
+      if (sets[j] == sets[i]) return fail(MG_EINVAL, "set %d appears twice", i);
+  }
+  mg_batch *b = new mg_batch();
+  b->sets.assign(sets, sets + n_sets);
+  std::vector<BatchItem> items;
+  for (int32_t i = 0; i < n_sets; ++i) {
+    for (int64_t f = 0; f < sets[i]->n; f += kBlock) items.push_back({i, (uint32_t)f});
+    b->max_nnz = std::max(b->max_nnz, sets[i]->g->nnz);
+  }
+  // Largest sets first so the tail of the launch is made of small tiles.
+  std::stable_sort(items.begin(), items.end(), [&](const BatchItem &x, const BatchItem &y) {
+    return sets[x.set]->n > sets[y.set]->n;
+  });
+  b->n_items = (int32_t)items.size();
+  const size_t og = 0;
+  const size_t os = align_up(sizeof(GraphDev) * n_sets, 256);
+  const size_t oi = align_up(os + sizeof(SetDev) * n_sets, 256);
+  const size_t total = align_up(oi + sizeof(BatchItem) * items.size(), 256);
+  hipError_t he = hipMalloc(&b->dev, total);
+  if (he != hipSuccess) {
+    delete b;
+    return fail(MG_ENOMEM, "hipMalloc for the batch tables: %s", hipGetErrorString(he));
+  }
+  b->d_graphs = (GraphDev *)((char *)b->dev + og);
+  b->d_sets = (SetDev *)((char *)b->dev + os);
+  b->d_items = (BatchItem *)((char *)b->dev + oi);
+  std::vector<GraphDev> gds(n_sets);
+  for (int32_t i = 0; i < n_sets; ++i) gds[i] = sets[i]->g->gd;
+  he = hipMemcpy(b->d_graphs, gds.data(), sizeof(GraphDev) * n_sets, hipMemcpyHostToDevice);
+  if (he == hipSuccess)
+    he = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(),
+                   hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    mg_batch_destroy(b);
+    return hip_fail(he, "copying the batch tables");
+  }
+  *out = b;
+  return MG_OK;
+}
+
+mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t seed) {
+  g_err.clear();
+  if (!b) return fail(MG_EINVAL, "batch is NULL");
+  for (mg_particles *p : b->sets) {
+    mg_status st = check_steps(p, n_steps, dt);
+    if (st != MG_OK) return st;
+  }
+  mg_particles *p0 = b->sets[0];
+  hipStream_t stream = p0->stream;
+  StepArgs a{};
+  a.max_splits = p0->max_splits;
+  a.key0 = (uint32_t)seed;
+  a.key1 = (uint32_t)(seed >> 32);
+  a.dt = dt;
+  const uint32_t chunk = chunk_steps(p0->steps_per_launch);
+  const int32_t n_sets = (int32_t)b->sets.size();
+  std::vector<SetDev> sds(n_sets);
+  int64_t left = n_steps;
+  while (left > 0) {
+    const uint32_t now = (uint32_t)std::min<int64_t>(left, chunk);
+    a.nsteps = now;
+    for (int32_t i = 0; i < n_sets; ++i) {
+      sds[i] = b->sets[i]->sd;
+      sds[i].n0 = (uint32_t)b->sets[i]->step;
+    }
+    MG_HIP(hipMemcpyAsync(b->d_sets, sds.data(), sizeof(SetDev) * n_sets,
+                          hipMemcpyHostToDevice, stream), "copying set descriptors");
+    MG_HIP(launch_batch(b->d_graphs, b->d_sets, b->d_items, b->n_items, b->max_nnz, a,
+                        p0->prec == MG_FP64, p0->trace, stream), "launching the batch kernel");
+    // the descriptor copy above reads pageable host memory: keep it alive
+    MG_HIP(hipStreamSynchronize(stream), "synchronising the batch");
+    for (mg_particles *p : b->sets) p->step += now;
+    left -= now;
+  }
+  return MG_OK;
+}
+
+void mg_batch_destroy(mg_batch *b) {
+  if (!b) return;
+  if (b->dev) (void)hipFree(b->dev);
+  delete b;
+}
+
+}  // extern "C"

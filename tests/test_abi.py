@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point the public header declares, and rejects invalid inputs
+before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "metricgraph.h")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2512_02175_amd import binding
+    try:
+        binding.lib()
+    except ImportError as e:
+        pytest.skip(str(e))
+    return binding
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_path():
+    names = _declared()
+    for n in ("mg_graph_create", "mg_particles_init", "mg_simulate", "mg_histogram",
+              "mg_exit_counts", "mg_batch_create", "mg_batch_simulate"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(B):
+    L = B.lib()
+    for n in _declared():
+        assert hasattr(L, n), n
+    assert set(_declared()) == set(B.EXPORTED)
+
+
+def test_binding_uses_the_c_names(B):
+    for n in _declared():
+        assert callable(getattr(B, n)), n
+
+
+def _desc(**over):
+    g = workloads.star_graph(3, 1.0)
+    for k, v in over.items():
+        setattr(g, k, v)
+    return g
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda g: setattr(g, "length", np.array([1.0, -1.0, 1.0])), "length"),
+    (lambda g: setattr(g, "length", np.array([1.0, np.nan, 1.0])), "length"),
+    (lambda g: setattr(g, "sigma", np.array([1.0, 0.0, 1.0])), "sigma"),
+    (lambda g: setattr(g, "drift_a", np.array([1.0, np.inf, 1.0])), "drift_a"),
+    (lambda g: setattr(g, "slot_jump_prob", g.slot_jump_prob * 1.01), "sum"),
+    (lambda g: setattr(g, "slot_jump_prob", np.where(np.arange(6) == 0, -0.1, g.slot_jump_prob)), ">= 0"),
+    (lambda g: setattr(g, "slot_orient", np.zeros(6, np.uint8)), "does not end there"),
+    (lambda g: setattr(g, "slot_edge", np.array([0, 0, 2, 0, 1, 2], np.int32)), ""),
+    (lambda g: setattr(g, "vtx_offsets", np.array([0, 3, 2, 5, 6], np.int32)), "decreases"),
+    (lambda g: setattr(g, "edge_term", np.array([1, 2, 9], np.int32)), "out of range"),
+    (lambda g: setattr(g, "vtx_kind", np.array([7, 0, 0, 0], np.uint8)), "kind"),
+])
+def test_invalid_graphs_rejected(B, mutate, msg):
+    g = _desc()
+    mutate(g)
+    with pytest.raises(B.MgError) as ei:
+        B.mg_graph_create(g)
+    assert ei.value.status == B.MG_EINVAL
+    assert msg in str(ei.value)
+
+
+def test_zero_probability_standard_vertex_rejected(B):
+    g = workloads.star_graph(2, 1.0, b_center=[1.0, 0.0])
+    g.slot_jump_prob[g.vtx_offsets[2]] = 0.0      # leaf 2 has no way out
+    with pytest.raises(B.MgError) as ei:
+        B.mg_graph_create(g)
+    assert "no positive jump probability" in str(ei.value)
+
+
+def test_null_arguments(B):
+    L = B.lib()
+    h = C.c_void_p()
+    assert L.mg_graph_create(None, C.byref(h)) == B.MG_EINVAL
+    assert L.mg_particles_init(None, 10, 0, None, None, 0, 0, None, C.byref(h)) == B.MG_EINVAL
+    assert L.mg_simulate(None, 1, 0.1, 0) == B.MG_EINVAL
+    assert L.mg_histogram(None, 4, None, 0) == B.MG_EINVAL
+    assert L.mg_batch_create(0, None, C.byref(h)) == B.MG_EINVAL
+    L.mg_graph_destroy(None)
+    L.mg_particles_destroy(None)
+    L.mg_batch_destroy(None)
+    assert "batch" in B.mg_last_error() or B.mg_last_error() != ""

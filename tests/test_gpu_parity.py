@@ -1,0 +1,279 @@
+"""GPU parity: the HIP path against the FP64 oracle, element by element on
+the same seeded inputs, through the C ABI.
+
+Bars:
+* FP64 path: per-particle hit sequences (hash over (step, slot)) equal on
+  >= 99.99 % of particles and |dx| <= 1e-12 on those; edges, alive flags and
+  hit counts equal on them; histogram and exit counts equal as integers up
+  to the particles that differ (libm and the device math library may round
+  log/cos/sin one ulp apart).
+* FP32 path (same random integers): total-variation distance of the
+  histograms <= 2e-3 and exit-probability error <= 1e-3 against FP64.
+* Batched form: bit-identical to each set run alone.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_02175_amd import binding
+    binding.lib()
+    return binding
+
+
+def _oracle_run(orc, g, n, mode, steps, dt, seed, *, init_seed=0, vertex=0, edge=None,
+                pos=None, M=8, tag=0, pids=None, n0=0):
+    st = orc.init(g, n, mode, vertex=vertex, seed=init_seed, tag=tag, edge=edge, pos=pos,
+                  pids=pids)
+    c = orc.simulate(g, st, n0, steps, dt, seed, tag=tag, max_splits=M)
+    return st, c
+
+
+def _gpu_run(B, g, n, mode, steps, dt, seed, *, precision=0, init_seed=0, vertex=0,
+             edge=None, pos=None, M=8, tag=0, trace=True, spl=0, G=None):
+    G = G or B.mg_graph_create(g)
+    p = B.mg_particles_init(G, n, mode, edge=edge, pos=pos, vertex=vertex,
+                            init_seed=init_seed, precision=precision, max_splits=M,
+                            graph_tag=tag, trace=trace, steps_per_launch=spl)
+    if steps:
+        B.mg_simulate(p, steps, dt, seed)
+    return G, p
+
+
+def _compare_fp64(st, r, rows=None, min_frac=0.9999):
+    rows = np.arange(st.pid.size) if rows is None else rows
+    same = r["seqhash"][rows] == st.seqhash
+    frac = same.mean()
+    assert frac >= min_frac, f"hash agreement {frac}"
+    s = same
+    assert np.array_equal(r["edge"][rows][s], st.edge[s])
+    assert np.array_equal(r["alive"][rows][s], st.alive[s])
+    assert np.array_equal(r["hits"][rows][s], st.hits[s])
+    dx = np.abs(r["x"][rows][s] - st.x[s])
+    assert dx.max(initial=0.0) <= 1e-12, dx.max()
+    return ~same
+
+
+def test_init_modes_match_oracle(B, orc):
+    g, _ = workloads.config2()
+    for mode, kw in ((2, {}), (1, dict(vertex=0)),):
+        st = orc.init(g, 5000, mode, seed=11, **kw)
+        G, p = _gpu_run(B, g, 5000, mode, 0, 1e-3, 0, init_seed=11, **kw)
+        r = B.mg_particles_read(p, trace=True)
+        assert np.array_equal(r["edge"], st.edge)
+        assert np.array_equal(r["x"], st.x)
+        assert np.all(r["seqhash"] == orc.fnv_offset())
+        # FP32 sets start from the same points
+        G, p32 = _gpu_run(B, g, 5000, mode, 0, 1e-3, 0, precision=1, init_seed=11, G=G, **kw)
+        r32 = B.mg_particles_read(p32)
+        assert np.array_equal(r32["edge"], st.edge)
+        np.testing.assert_allclose(r32["x"], st.x, rtol=0, atol=2e-7)
+
+
+@pytest.mark.parametrize("n", [1, 255, 10_000])
+def test_config1_fp64_parity(B, orc, n):
+    """Config 1 (3-edge star, 1000 steps of 1e-3 from the centre), full
+    element-by-element comparison; n = 1 and 255 exercise ragged blocks."""
+    g, run = workloads.config1()
+    st, c = _oracle_run(orc, g, n, 1, run["n_steps"], run["dt"], run["seed"])
+    G, p = _gpu_run(B, g, n, 1, run["n_steps"], run["dt"], run["seed"])
+    r = B.mg_particles_read(p, trace=True)
+    diff = _compare_fp64(st, r, min_frac=0.9999 if n > 1000 else 1.0)
+    ex, ab, tot = B.mg_exit_counts(p)
+    if not diff.any():
+        assert np.array_equal(ex, c.exit_slot)
+        assert (int(tot[0]), int(tot[1]), int(tot[2])) == (c.truncations, c.substeps, c.hits)
+        h = B.mg_histogram(p, run["bins"])
+        assert np.array_equal(h, orc.histogram(g, st, run["bins"]))
+
+
+def test_config2_fp64_parity_both_dt(B, orc):
+    """Config 2's Langevin star at both of its dt, 20k particles."""
+    g, run = workloads.config2()
+    for dt in run["dts"]:
+        st, c = _oracle_run(orc, g, 20_000, 2, 2000, dt, 3, init_seed=5)
+        G, p = _gpu_run(B, g, 20_000, 2, 2000, dt, 3, init_seed=5)
+        r = B.mg_particles_read(p, trace=True)
+        diff = _compare_fp64(st, r)
+        ex, ab, tot = B.mg_exit_counts(p)
+        # counts agree up to the exits of particles that differ
+        nd = int(diff.sum())
+        assert np.abs(ex.astype(np.int64) - c.exit_slot.astype(np.int64)).sum() <= 2 * 2000 * nd
+        h = B.mg_histogram(p, 256)
+        ho = orc.histogram(g, st, 256)
+        assert np.abs(h.astype(np.int64) - ho.astype(np.int64)).sum() <= 2 * nd
+
+
+def test_absorbing_and_truncation_parity(B, orc):
+    """A star with absorbing leaves and strong inward drift, M = 3, so that
+    absorption and the split cap both occur."""
+    g = workloads.star_graph(5, [0.3, 0.5, 0.2, 0.8, 0.4], [-30.0, 5.0, -60.0, 0.0, -10.0],
+                             [0, -2.0, 0, 0, 0], 1.0, b_center=[0.3, 0.1, 0.3, 0.2, 0.1])
+    g.vtx_kind[2] = 1
+    g.vtx_kind[5] = 1
+    st, c = _oracle_run(orc, g, 4000, 1, 300, 5e-3, 9, M=3)
+    assert c.truncations > 0 and c.absorbed.sum() > 0
+    G, p = _gpu_run(B, g, 4000, 1, 300, 5e-3, 9, M=3)
+    r = B.mg_particles_read(p, trace=True)
+    diff = _compare_fp64(st, r)
+    ex, ab, tot = B.mg_exit_counts(p)
+    if not diff.any():
+        assert np.array_equal(ab, c.absorbed)
+        assert int(tot[0]) == c.truncations
+        assert np.array_equal(ex, c.exit_slot)
+
+
+def test_split_run_and_launch_chunking_bitwise(B):
+    g, _ = workloads.config2()
+    res = []
+    for calls, spl in (((1000,), 0), ((500, 500), 0), ((1000,), 7), ((333, 1, 666), 64)):
+        G, p = _gpu_run(B, g, 3000, 2, 0, 1e-2, 4, init_seed=2, spl=spl, precision=0)
+        for k in calls:
+            B.mg_simulate(p, k, 1e-2, 4)
+        assert B.mg_particles_step(p) == 1000
+        r = B.mg_particles_read(p, trace=True)
+        res.append((r, B.mg_exit_counts(p)))
+    for r, cnt in res[1:]:
+        for f in ("edge", "x", "alive", "seqhash", "hits"):
+            assert np.array_equal(r[f], res[0][0][f]), f
+        for a, b in zip(cnt, res[0][1]):
+            assert np.array_equal(a, b)
+
+
+def test_subset_of_ids_at_offset_steps(B, orc):
+    """Sampled particle ids against the oracle run on those ids alone,
+    starting from a step counter that is not a multiple of four."""
+    g, _ = workloads.config2()
+    G, p = _gpu_run(B, g, 50_000, 2, 0, 1e-2, 8, init_seed=1)
+    B.mg_simulate(p, 3, 1e-2, 8)
+    B.mg_simulate(p, 997, 1e-2, 8)
+    rows = np.random.default_rng(0).choice(50_000, 300, replace=False)
+    st = orc.init(g, 50_000, 2, seed=1, pids=rows)
+    orc.simulate(g, st, 0, 3, 1e-2, 8)
+    orc.simulate(g, st, 3, 997, 1e-2, 8)
+    r = B.mg_particles_read(p, trace=True)
+    _compare_fp64(st, r, rows=rows, min_frac=1.0)
+
+
+def _tv(h1, h2):
+    return 0.5 * np.abs(h1.astype(np.float64) - h2.astype(np.float64)).sum() / max(h1.sum(), 1)
+
+
+def _exit_probs(ex, offsets):
+    p = np.zeros(ex.size)
+    for v in range(offsets.size - 1):
+        s0, s1 = offsets[v], offsets[v + 1]
+        t = ex[s0:s1].sum()
+        if t:
+            p[s0:s1] = ex[s0:s1] / t
+    return p
+
+
+def test_fp32_against_fp64_common_random_numbers(B, orc):
+    """FP32 path vs the oracle on config 2 (both dt) with the same random
+    integers: histogram TV <= 2e-3, exit-probability error <= 1e-3."""
+    g, run = workloads.config2()
+    for dt in run["dts"]:
+        n, steps = 100_000, 2000
+        st, c = _oracle_run(orc, g, n, 2, steps, dt, 6, init_seed=3)
+        G, p = _gpu_run(B, g, n, 2, steps, dt, 6, precision=1, init_seed=3)
+        h32 = B.mg_histogram(p, 256)
+        h64 = orc.histogram(g, st, 256)
+        tv = _tv(h32, h64)
+        assert tv <= 2e-3, tv
+        ex, _, tot = B.mg_exit_counts(p)
+        err = np.abs(_exit_probs(ex, g.vtx_offsets) - _exit_probs(c.exit_slot, g.vtx_offsets)).max()
+        assert err <= 1e-3, err
+        r = B.mg_particles_read(p, trace=True)
+        agree = (r["seqhash"] == st.seqhash).mean()
+        assert agree > 0.95, agree
+
+
+def test_fp32_config1_and_absorbing(B, orc):
+    g, run = workloads.config1()
+    st, c = _oracle_run(orc, g, 10_000, 1, 1000, 1e-3, 0)
+    G, p = _gpu_run(B, g, 10_000, 1, 1000, 1e-3, 0, precision=1)
+    assert _tv(B.mg_histogram(p, 100), orc.histogram(g, st, 100)) <= 2e-3
+    r = B.mg_particles_read(p, trace=True)
+    assert (r["seqhash"] == st.seqhash).mean() > 0.99
+
+
+def test_batch_equals_individual_runs(B):
+    """Several uneven graphs (stars and trees, with and without drift) in one
+    batched launch give bit-identical results to each set run alone."""
+    rng = np.random.default_rng(3)
+    graphs = [workloads.star_graph(3, [1.0, 2.0, 0.5]),
+              workloads.random_tree(40, rng, quadratic=True),
+              workloads.config2()[0],
+              workloads.random_tree(7, rng)]
+    counts = [700, 2000, 5000, 1]
+    for prec in (0, 1):
+        sets_b, sets_a = [], []
+        for i, (g, n) in enumerate(zip(graphs, counts)):
+            G = B.mg_graph_create(g)
+            sets_b.append(B.mg_particles_init(G, n, 2, init_seed=i, precision=prec,
+                                              graph_tag=i, trace=True))
+            sets_a.append(B.mg_particles_init(G, n, 2, init_seed=i, precision=prec,
+                                              graph_tag=i, trace=True))
+        b = B.mg_batch_create(sets_b)
+        B.mg_batch_simulate(b, 300, 1e-2, 12)
+        B.mg_batch_simulate(b, 200, 1e-2, 12)
+        for pa in sets_a:
+            B.mg_simulate(pa, 500, 1e-2, 12)
+        for pa, pb in zip(sets_a, sets_b):
+            ra, rb = B.mg_particles_read(pa, trace=True), B.mg_particles_read(pb, trace=True)
+            for f in ("edge", "x", "alive", "seqhash", "hits"):
+                assert np.array_equal(ra[f], rb[f]), f
+            for x, y in zip(B.mg_exit_counts(pa), B.mg_exit_counts(pb)):
+                assert np.array_equal(x, y)
+
+
+def test_torch_arena_equals_library_memory(B):
+    import torch
+    g, _ = workloads.config2()
+    G = B.mg_graph_create(g)
+    a = B.mg_particles_init(G, 4000, 2, init_seed=1, trace=True)
+    t = B.mg_particles_init(G, 4000, 2, init_seed=1, trace=True, arena="torch")
+    B.mg_simulate(a, 400, 1e-2, 2)
+    B.mg_simulate(t, 400, 1e-2, 2)
+    ra, rt = B.mg_particles_read(a, trace=True), B.mg_particles_read(t, trace=True)
+    for f in ra:
+        assert np.array_equal(ra[f], rt[f])
+    out = torch.zeros(g.n_edges * 16, dtype=torch.int64, device="cuda")
+    B.mg_histogram(t, 16, out=out)
+    assert np.array_equal(out.cpu().numpy().astype(np.uint64), B.mg_histogram(a, 16).ravel())
+
+
+def test_full_size_config2_sampled(B, orc):
+    """Config 2 at its full size (1e7 particles, 1e4 steps, dt = 1e-3) in the
+    launch configuration the benchmark times: sampled particle ids against
+    the oracle one by one, and properties that hold at any size."""
+    g, run = workloads.config2()
+    n, steps, dt = run["n_particles"], run["n_steps"], 1e-3
+    G = B.mg_graph_create(g)
+    rows = np.sort(np.random.default_rng(1).choice(n, 64, replace=False))
+    for prec in (0, 1):
+        p = B.mg_particles_init(G, n, 2, init_seed=0, precision=prec, trace=True)
+        B.mg_simulate(p, steps, dt, 0)
+        st = orc.init(g, n, 2, seed=0, pids=rows)
+        orc.simulate(g, st, 0, steps, dt, 0)
+        r = {k: v for k, v in B.mg_particles_read(p, trace=True).items()}
+        ex, ab, tot = B.mg_exit_counts(p)
+        h = B.mg_histogram(p, run["bins"])
+        assert int(h.sum()) == n and ab.sum() == 0
+        assert int(tot[3]) == n * steps
+        assert int(tot[2]) == int(r["hits"].astype(np.int64).sum())
+        if prec == 0:
+            _compare_fp64(st, r, rows=rows, min_frac=1.0)
+            h64 = h
+        else:
+            assert (r["seqhash"][rows] == st.seqhash).mean() >= 0.9
+            assert _tv(h, h64) <= 2e-3
