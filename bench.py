@@ -24,15 +24,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "particle-substeps/s at 1 GPU, FP32 vs FP64, + % VALU peak at TV≤2e-3"
-PEAK_LANE_CYCLES = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock
+# VALU lane-operation ceiling of one MI355X: 256 CUs x 4 SIMDs x 32 lane-ops
+# per cycle (the 16-lane SIMD issuing packed/dual operations, the width
+# behind the 157.3 TFLOP/s FP32 vector figure with FMA = 2 flops) x 2.4 GHz.
+PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 
-# Algorithmic VALU work of the method in full-rate lane-cycles (a
-# quarter-rate operation -- 32x32->64 product, transcendental -- counts 4).
+# Algorithmic VALU operations of the method per unit of work: the minimal
+# gfx950 instruction sequence, counted once per operation whatever its rate.
 # Derivation in DESIGN.md ("Roofline").
-ALG_FP32_STEP = 49.5     # per particle-step: 1/4 Philox + 1/2 Box-Muller pair + EM
-ALG_FP32_HIT = 166.0     # per vertex hit: Philox, one normal, root, slot, edge
-ALG_FP64_STEP = 70.0
-ALG_FP64_HIT = 190.0
+ALG_FP32_STEP = 32.5     # per particle-step: 1/4 Philox + 1/2 Box-Muller pair + EM
+ALG_FP32_HIT = 80.0      # per vertex hit: Philox, one normal, root, time, slot, edge
+ALG_FP64_STEP = 62.5
+ALG_FP64_HIT = 130.0
+
+
+# HBM bytes per k_step<fp32> launch on this workload from the FETCH_SIZE and
+# WRITE_SIZE counter passes (scaled by a 1 GiB copy), valid for the kernel
+# source whose sha256 prefix is given; reported as null for any other build.
+TRAFFIC = {"kernel_sha256": "f6bcb02894426693", "bytes_per_launch": 212.6e6}
+
+
+def kernel_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2512_02175_amd", "csrc", "mg_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return TRAFFIC["bytes_per_launch"] if h == TRAFFIC["kernel_sha256"] else None
 
 
 def alg_work(prec: int, steps: int, hits: int) -> float:
@@ -146,18 +162,19 @@ def main():
         w64 = sum(alg_work(0, r["steps"], r["hits"]) for r in res64)
         out_fp64 = {"value": sub64 / wall64, "unit": "particle-substeps/s",
                     "kernel_substeps_per_s": sub64 / k64,
-                    "alg_frac_of_alu_peak": w64 / k64 / PEAK_LANE_CYCLES,
+                    "alg_frac_of_alu_peak": w64 / k64 / PEAK_LANE_OPS,
                     "fp32_speedup": value / (sub64 / wall64)}
 
     # roofline of the dominant kernel (the fused step kernel), per launch
     k32 = float(np.mean(ktimes32))
     per_launch = [alg_work(1, r["steps"], r["hits"]) for r in res32]
     achieved = float(np.mean(per_launch)) / k32
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_CYCLES / 1e12,
-            "unit": "T lane-cycles/s", "frac": achieved / PEAK_LANE_CYCLES, "traffic": None,
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
+            "traffic": kernel_traffic(),
             "kernel": "k_step<fp32>", "kernel_ms_per_launch": k32 * 1e3,
-            "alg_lane_cycles_per_particle_step": ALG_FP32_STEP,
-            "alg_lane_cycles_per_hit": ALG_FP32_HIT}
+            "alg_lane_ops_per_particle_step": ALG_FP32_STEP,
+            "alg_lane_ops_per_hit": ALG_FP32_HIT}
 
     line = {
         "metric": METRIC, "value": value, "unit": "particle-substeps/s", "n_gpus": 1,

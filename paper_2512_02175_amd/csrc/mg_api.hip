@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -78,6 +79,7 @@ bool is_finite(double v) { return std::isfinite(v); }
 struct mg_graph {
   int32_t V, E, nnz;
   std::vector<double> length;  // host copy for readback conversion
+  std::vector<VtxBlk> vtx_host;
   void *dev = nullptr;         // one allocation holding every table
   GraphDev gd{};
 };
@@ -105,6 +107,7 @@ struct mg_batch {
   BatchItem *d_items = nullptr;
   int32_t n_items = 0;
   int32_t max_nnz = 0;
+  int32_t max_stage = 0;  // staged table bytes if every set's graph fits, else 0
 };
 
 namespace {
@@ -232,12 +235,42 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   }
   std::vector<uint64_t> thr(nnz);
   slot_thresholds(V, off, d->slot_jump_prob, thr);
-  std::vector<SlotRec> slots(nnz);
-  for (int32_t s = 0; s < nnz; ++s) slots[s] = {thr[s], d->slot_edge[s], d->slot_orient[s]};
-  std::vector<VtxRec> vtx(V);
+  auto eo_of = [&](int32_t s) {
+    return ((uint32_t)d->slot_edge[s] << 1) | (uint32_t)d->slot_orient[s] |
+           (thr[s] >= (1ull << 32) ? kSatBit : 0u);
+  };
+  auto t_of = [&](int32_t s) { return thr[s] >= (1ull << 32) ? 0xFFFFFFFFu : (uint32_t)thr[s]; };
+  std::vector<SlotRec8> slots(nnz);
+  for (int32_t s = 0; s < nnz; ++s) slots[s] = {t_of(s), eo_of(s)};
+  std::vector<VtxBlk> vtx(V);
+  std::vector<int32_t> guide;
   for (int32_t v = 0; v < V; ++v) {
     const bool absorbing = d->vtx_kind && d->vtx_kind[v] == MG_VTX_ABSORBING;
-    vtx[v] = {off[v], absorbing ? -1 : off[v + 1] - off[v]};
+    const int32_t first = off[v], deg = off[v + 1] - off[v];
+    VtxBlk b{};
+    b.first = first;
+    b.deg = absorbing ? -1 : deg;
+    if (!absorbing && deg <= 3) {
+      if (deg > 0) b.eo0 = eo_of(first);
+      if (deg > 1) { b.t0 = t_of(first); b.eo1 = eo_of(first + 1); }
+      if (deg > 2) { b.t1 = t_of(first + 1); b.eo2 = eo_of(first + 2); }
+    } else if (!absorbing) {
+      // guide table (Chen & Asau): bucket i of the top bits of the draw
+      // holds the first slot whose threshold exceeds the bucket's lowest
+      // draw, so the scan from there picks the same slot as a scan from 0.
+      int32_t bits = 0;
+      while ((1 << bits) < deg) ++bits;
+      const uint32_t shift = 32u - (uint32_t)bits;
+      b.t0 = (uint32_t)guide.size();
+      b.t1 = shift;
+      int32_t k = 0;
+      for (int64_t i = 0; i < (1ll << bits); ++i) {
+        const uint64_t lo = (uint64_t)i << shift;
+        while (k < deg - 1 && thr[first + k] <= lo) ++k;
+        guide.push_back(k);
+      }
+    }
+    vtx[v] = b;
   }
   // length-proportional init thresholds, built like the slot thresholds
   std::vector<uint64_t> lthr(E);
@@ -260,12 +293,15 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   g->E = E;
   g->nnz = nnz;
   g->length.assign(d->length, d->length + E);
-  const size_t o64 = 0;
-  const size_t o32 = align_up(o64 + sizeof(EdgeRec64) * E, 256);
-  const size_t osl = align_up(o32 + sizeof(EdgeRec32) * E, 256);
-  const size_t ovx = align_up(osl + sizeof(SlotRec) * nnz, 256);
-  const size_t olt = align_up(ovx + sizeof(VtxRec) * V, 256);
-  const size_t total = align_up(olt + 8 * (size_t)E, 256);
+  g->vtx_host = vtx;
+  const size_t ng = guide.size();
+  const size_t o_vtx = 0;
+  const size_t o_sl = align_up(o_vtx + sizeof(VtxBlk) * V, 16);
+  const size_t o_gd = align_up(o_sl + sizeof(SlotRec8) * nnz, 16);
+  const size_t o_32 = align_up(o_gd + 4 * ng, 16);
+  const size_t o_64 = align_up(o_32 + sizeof(EdgeRec32) * E, 16);
+  const size_t o_lt = align_up(o_64 + sizeof(EdgeRec64) * E, 256);
+  const size_t total = align_up(o_lt + 8 * (size_t)E, 256);
   hipError_t he = hipMalloc(&g->dev, total);
   if (he != hipSuccess) {
     delete g;
@@ -273,22 +309,35 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   }
   char *base = (char *)g->dev;
   std::vector<char> host(total, 0);
-  std::memcpy(host.data() + o64, e64.data(), sizeof(EdgeRec64) * E);
-  std::memcpy(host.data() + o32, e32.data(), sizeof(EdgeRec32) * E);
-  std::memcpy(host.data() + osl, slots.data(), sizeof(SlotRec) * nnz);
-  std::memcpy(host.data() + ovx, vtx.data(), sizeof(VtxRec) * V);
-  std::memcpy(host.data() + olt, lthr.data(), 8 * (size_t)E);
+  std::memcpy(host.data() + o_vtx, vtx.data(), sizeof(VtxBlk) * V);
+  std::memcpy(host.data() + o_sl, slots.data(), sizeof(SlotRec8) * nnz);
+  if (ng) std::memcpy(host.data() + o_gd, guide.data(), 4 * ng);
+  std::memcpy(host.data() + o_32, e32.data(), sizeof(EdgeRec32) * E);
+  std::memcpy(host.data() + o_64, e64.data(), sizeof(EdgeRec64) * E);
+  std::memcpy(host.data() + o_lt, lthr.data(), 8 * (size_t)E);
   he = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
   if (he != hipSuccess) {
     (void)hipFree(g->dev);
     delete g;
     return hip_fail(he, "copying the graph tables");
   }
-  g->gd.e64 = (const EdgeRec64 *)(base + o64);
-  g->gd.e32 = (const EdgeRec32 *)(base + o32);
-  g->gd.slots = (const SlotRec *)(base + osl);
-  g->gd.vtx = (const VtxRec *)(base + ovx);
-  g->gd.len_thr = (const uint64_t *)(base + olt);
+  g->gd.tables = base;
+  g->gd.vtx = (const VtxBlk *)(base + o_vtx);
+  g->gd.slots = (const SlotRec8 *)(base + o_sl);
+  g->gd.guide = (const int32_t *)(base + o_gd);
+  g->gd.e32 = (const EdgeRec32 *)(base + o_32);
+  g->gd.e64 = (const EdgeRec64 *)(base + o_64);
+  g->gd.len_thr = (const uint64_t *)(base + o_lt);
+  g->gd.n_guide = (int32_t)ng;
+  g->gd.o_vtx = (int32_t)o_vtx;
+  g->gd.o_slots = (int32_t)o_sl;
+  g->gd.o_guide = (int32_t)o_gd;
+  g->gd.o_e32 = (int32_t)o_32;
+  g->gd.o_e64 = (int32_t)o_64;
+  const size_t st32 = o_32 + sizeof(EdgeRec32) * E;
+  const size_t st64 = o_32 + sizeof(EdgeRec64) * E;
+  g->gd.stage_bytes32 = st32 <= (size_t)kLdsStageMax ? (int32_t)st32 : 0;
+  g->gd.stage_bytes64 = st64 <= (size_t)kLdsStageMax ? (int32_t)st64 : 0;
   g->gd.V = V;
   g->gd.E = E;
   g->gd.nnz = nnz;
@@ -334,10 +383,8 @@ mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
     }
   } else if (mode == MG_INIT_AT_VERTEX) {
     if (vertex < 0 || vertex >= g->V) return fail(MG_EINVAL, "vertex out of range");
-    VtxRec vr;
-    if (hipMemcpy(&vr, g->gd.vtx + vertex, sizeof vr, hipMemcpyDeviceToHost) != hipSuccess)
-      return fail(MG_EDEVICE, "reading the vertex table");
-    if (vr.deg <= 0) return fail(MG_EINVAL, "vertex %d is absorbing or isolated", vertex);
+    if (g->vtx_host[vertex].deg <= 0)
+      return fail(MG_EINVAL, "vertex %d is absorbing or isolated", vertex);
   } else if (mode != MG_INIT_UNIFORM_LENGTH) {
     return fail(MG_EINVAL, "unknown init mode");
   }
@@ -570,10 +617,16 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
   mg_batch *b = new mg_batch();
   b->sets.assign(sets, sets + n_sets);
   std::vector<BatchItem> items;
+  bool all_stage = true;
   for (int32_t i = 0; i < n_sets; ++i) {
     for (int64_t f = 0; f < sets[i]->n; f += kBlock) items.push_back({i, (uint32_t)f});
     b->max_nnz = std::max(b->max_nnz, sets[i]->g->nnz);
+    const GraphDev &gd = sets[i]->g->gd;
+    const int32_t st = sets[i]->prec == MG_FP64 ? gd.stage_bytes64 : gd.stage_bytes32;
+    all_stage = all_stage && st > 0;
+    b->max_stage = std::max(b->max_stage, st);
   }
+  if (!all_stage) b->max_stage = 0;
   // Largest sets first so the tail of the launch is made of small tiles.
   std::stable_sort(items.begin(), items.end(), [&](const BatchItem &x, const BatchItem &y) {
     return sets[x.set]->n > sets[y.set]->n;
@@ -632,8 +685,9 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
     }
     MG_HIP(hipMemcpyAsync(b->d_sets, sds.data(), sizeof(SetDev) * n_sets,
                           hipMemcpyHostToDevice, stream), "copying set descriptors");
-    MG_HIP(launch_batch(b->d_graphs, b->d_sets, b->d_items, b->n_items, b->max_nnz, a,
-                        p0->prec == MG_FP64, p0->trace, stream), "launching the batch kernel");
+    MG_HIP(launch_batch(b->d_graphs, b->d_sets, b->d_items, b->n_items, b->max_nnz,
+                        b->max_stage, a, p0->prec == MG_FP64, p0->trace, stream),
+           "launching the batch kernel");
     // the descriptor copy above reads pageable host memory: keep it alive
     MG_HIP(hipStreamSynchronize(stream), "synchronising the batch");
     for (mg_particles *p : b->sets) p->step += now;

@@ -31,28 +31,48 @@ struct alignas(16) EdgeRec32 {
   float pad;
 };
 
-// Slot: T_s as a 33-bit integer (2^32 = take every remaining draw), the
-// incident edge and the end the particle enters at.
-struct alignas(16) SlotRec {
-  uint64_t thr;
-  int32_t edge;
-  int32_t orient;
-};
-
-// Vertex: first slot and degree; degree < 0 marks an absorbing vertex.
-struct VtxRec {
+// Vertex block, 32 bytes: everything a vertex hit needs in one load.
+//   first  global id of the vertex's first CSR slot (slot s = first + k);
+//   deg    number of slots, -1 for an absorbing vertex.
+// deg <= 3: t0, t1 are the thresholds T_0, T_1 of slots 0 and 1 and eo0..2
+//   the slots' (edge << 1 | orient); bit 31 of eo_k flags T_k = 2^32 (a
+//   threshold every 32-bit draw lies below).  The last slot needs none.
+// deg > 3: t0 = offset of the vertex's guide table, t1 = the shift that maps
+//   a draw to its guide bucket; slots are read from the slot table.
+struct alignas(16) VtxBlk {
   int32_t first;
   int32_t deg;
+  uint32_t t0, t1;
+  uint32_t eo0, eo1, eo2;
+  uint32_t pad;
 };
 
-// Device tables of one graph.
+// Slot table entry for vertices of degree > 3 (same encoding as above).
+struct SlotRec8 {
+  uint32_t t;
+  uint32_t eo;
+};
+
+constexpr uint32_t kSatBit = 0x80000000u;
+
+// Device tables of one graph.  The tables the step kernels read on a
+// vertex hit (vertex blocks, edge records of the kernel's precision, slot
+// table, guide tables) are contiguous so that a block can stage them in
+// LDS with one copy: stage64/stage32 give the byte range of each
+// precision's tables, offsets relative to `tables`.
 struct GraphDev {
+  const char *tables;
   const EdgeRec64 *e64;
   const EdgeRec32 *e32;
-  const SlotRec *slots;
-  const VtxRec *vtx;
+  const VtxBlk *vtx;
+  const SlotRec8 *slots;
+  const int32_t *guide;
   const uint64_t *len_thr;  // [E] init thresholds, proportional to length
-  int32_t V, E, nnz;
+  int32_t V, E, nnz, n_guide;
+  // byte offsets of vtx, slots, guide, e32, e64 inside `tables`
+  int32_t o_vtx, o_slots, o_guide, o_e32, o_e64;
+  int32_t stage_bytes32;  // vtx..e32 (FP32 kernels stage this range)
+  int32_t stage_bytes64;  // vtx..guide + e64 (FP64 kernels)
 };
 
 // Counters of one particle set: exit[nnz], absorbed[V], totals[4]
@@ -89,6 +109,7 @@ struct BatchItem {
 
 constexpr int kBlock = 256;
 constexpr int kLdsExitMax = 16384;  // slots counted in LDS (64 KiB of u32)
+constexpr int kLdsStageMax = 24576; // graph tables staged in LDS up to this size
 
 hipError_t launch_init(const GraphDev &g, const SetDev &s, int mode,
                        int32_t vertex, uint32_t key0, uint32_t key1,
@@ -98,12 +119,9 @@ hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
                        bool fp64, bool trace, hipStream_t st);
 hipError_t launch_batch(const GraphDev *graphs, const SetDev *sets,
                         const BatchItem *items, int32_t n_items,
-                        int32_t max_nnz, const StepArgs &a, bool fp64,
-                        bool trace, hipStream_t st);
+                        int32_t max_nnz, int32_t max_stage, const StepArgs &a,
+                        bool fp64, bool trace, hipStream_t st);
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,
                             uint64_t *out, bool fp64, hipStream_t st);
-hipError_t launch_read(const GraphDev &g, const SetDev &s, uint32_t first,
-                       uint32_t count, int32_t *edge, double *pos,
-                       uint8_t *alive, bool fp64, hipStream_t st);
 
 }  // namespace mg

@@ -23,6 +23,17 @@ namespace mg {
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Main-stream Philox groups (four steps each) run before the parked lanes
+// of a window resolve their vertex hits.
+#ifndef MG_WINDOW_GROUPS32
+#define MG_WINDOW_GROUPS32 1
+#endif
+#ifndef MG_WINDOW_GROUPS64
+#define MG_WINDOW_GROUPS64 2
+#endif
+constexpr int kWindowGroups32 = MG_WINDOW_GROUPS32;
+constexpr int kWindowGroups64 = MG_WINDOW_GROUPS64;
 constexpr uint64_t kFnvPrime = 0x100000001b3ull;
 
 struct U4 {
@@ -91,43 +102,102 @@ __device__ __forceinline__ float box_muller32_cos(uint32_t a, uint32_t b) {
 // Smallest u in (0, 1] with C + B u + A u^2 = 0 (C >= 0), u = sqrt(alpha):
 // Alg. 2's crossing equation in the frame of the distance to the hit
 // vertex; cancellation-free quadratic formula q = -(B + sgn(B) sqrt(disc))/2
-// with roots q/A and C/q; C = 0 (on the vertex) gives -B/A; clamped to [0,1].
-template <typename T>
-__device__ __forceinline__ T first_root(T A, T B, T Cc) {
-  T u;
-  if (Cc == T(0)) {
-    if (A == T(0)) return T(0);
-    u = -B / A;
-  } else if (A == T(0)) {
-    u = -Cc / B;
-  } else {
-    T disc = B * B - T(4) * A * Cc;
-    if (disc < T(0)) disc = T(0);
-    const T sq = sqrt(disc);
-    const T q = T(-0.5) * (B >= T(0) ? B + sq : B - sq);
-    const T r1 = q / A;
-    const T r2 = Cc / q;
-    const T lo = r1 < r2 ? r1 : r2;
-    const T hi = r1 < r2 ? r2 : r1;
-    u = lo > T(0) ? lo : hi;
-    if (!(u > T(0))) u = T(1);
-  }
-  if (!(u >= T(0))) u = T(0);
-  if (u > T(1)) u = T(1);
-  return u;
+// with roots q/A and C/q; C = 0 (on the vertex) gives -B/A, A = 0 gives
+// -C/B; clamped to [0, 1].  The three cases are computed as one pair of
+// divisions whose operands are selected, so no lane branches; in FP64 the
+// divisions are IEEE-exact, which keeps the result bit-equal to the plain
+// case-by-case evaluation.
+__device__ __forceinline__ double first_root64(double A, double B, double Cc) {
+  double disc = B * B - 4.0 * A * Cc;
+  disc = disc < 0.0 ? 0.0 : disc;
+  const double sq = sqrt(disc);
+  const double q = -0.5 * (B >= 0.0 ? B + sq : B - sq);
+  const bool c0 = Cc == 0.0, a0 = A == 0.0;
+  // general: q / A and C / q;  C = 0: -B / A;  A = 0: -C / B
+  const double n1 = c0 ? -B : (a0 ? -Cc : q);
+  const double d1 = a0 ? B : A;
+  const double d2 = (c0 || a0) ? 1.0 : q;
+  const double r1 = n1 / d1;
+  const double r2 = Cc / d2;
+  const double lo = r1 < r2 ? r1 : r2;
+  const double hi = r1 < r2 ? r2 : r1;
+  double ug = lo > 0.0 ? lo : hi;
+  ug = ug > 0.0 ? ug : 1.0;
+  double u = (c0 || a0) ? r1 : ug;
+  u = (c0 && a0) ? 0.0 : u;
+  u = u >= 0.0 ? u : 0.0;  // also maps NaN to 0
+  return u > 1.0 ? 1.0 : u;
+}
+
+// The same in FP32 with hardware reciprocals (about one ulp).
+__device__ __forceinline__ float first_root32(float A, float B, float Cc) {
+  float disc = fmaf(B, B, -4.0f * A * Cc);
+  disc = disc < 0.0f ? 0.0f : disc;
+  const float sq = __builtin_amdgcn_sqrtf(disc);
+  const float q = -0.5f * (B >= 0.0f ? B + sq : B - sq);
+  const bool c0 = Cc == 0.0f, a0 = A == 0.0f;
+  const float n1 = c0 ? -B : (a0 ? -Cc : q);
+  const float d1 = a0 ? B : A;
+  const float r1 = n1 * __builtin_amdgcn_rcpf(d1);
+  const float r2 = Cc * __builtin_amdgcn_rcpf(q);
+  const float lo = fminf(r1, r2), hi = fmaxf(r1, r2);
+  float ug = lo > 0.0f ? lo : hi;
+  ug = ug > 0.0f ? ug : 1.0f;
+  float u = (c0 || a0) ? r1 : ug;
+  u = (c0 && a0) ? 0.0f : u;
+  u = u >= 0.0f ? u : 0.0f;
+  return u > 1.0f ? 1.0f : u;
 }
 
 __device__ __forceinline__ uint64_t fnv(uint64_t h, uint32_t w) {
   return (h ^ (uint64_t)w) * kFnvPrime;
 }
 
-// First slot s of vertex v with r < T_s (the last slot takes the rest).
-__device__ __forceinline__ int32_t pick_slot(const SlotRec *slots, VtxRec vr,
-                                             uint32_t r) {
-  int32_t s = vr.first;
-  const int32_t last = vr.first + vr.deg - 1;
-  while (s < last && (uint64_t)r >= slots[s].thr) ++s;
-  return s;
+// Graph tables as the step kernels see them: global memory, or LDS when the
+// block staged them.
+struct GView {
+  const VtxBlk *vtx;
+  const SlotRec8 *slots;
+  const int32_t *guide;
+  const EdgeRec32 *e32;
+  const EdgeRec64 *e64;
+};
+
+__device__ __forceinline__ GView global_view(const GraphDev &G) {
+  return {G.vtx, G.slots, G.guide, G.e32, G.e64};
+}
+
+struct SlotPick {
+  int32_t s;    // global slot id
+  uint32_t eo;  // edge << 1 | orient (bit 31: saturated threshold)
+};
+
+__device__ __forceinline__ int32_t eo_edge(uint32_t eo) { return (int32_t)((eo & 0x7FFFFFFFu) >> 1); }
+
+// First slot k of the vertex with r < T_k (the last slot takes the rest):
+// inline thresholds for degree <= 3, else the guide bucket of r and a short
+// scan of the slot table.
+__device__ __forceinline__ SlotPick pick_slot(const GView &g, const VtxBlk &vb, uint32_t r) {
+  if (vb.deg <= 3) {
+    int32_t k = 0;
+    uint32_t eo = vb.eo0;
+    if (vb.deg > 1 && !(r < vb.t0 || (vb.eo0 & kSatBit))) {
+      k = 1;
+      eo = vb.eo1;
+      if (vb.deg > 2 && !(r < vb.t1 || (vb.eo1 & kSatBit))) {
+        k = 2;
+        eo = vb.eo2;
+      }
+    }
+    return {vb.first + k, eo};
+  }
+  int32_t k = g.guide[vb.t0 + (r >> vb.t1)];
+  SlotRec8 sr = g.slots[vb.first + k];
+  while (k < vb.deg - 1 && !(r < sr.t || (sr.eo & kSatBit))) {
+    ++k;
+    sr = g.slots[vb.first + k];
+  }
+  return {vb.first + k, sr.eo};
 }
 
 // Per-lane tallies reduced once per block.
@@ -144,100 +214,186 @@ __device__ __forceinline__ void count_exit(uint32_t *s_exit, uint64_t *g_exit,
     atomicAdd((unsigned long long *)&g_exit[slot], 1ull);
 }
 
+template <typename T, int N>
+__device__ __forceinline__ T pickw(const T (&W)[N], uint32_t j) {
+  T w = W[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) w = (j == (uint32_t)i) ? W[i] : w;
+  return w;
+}
+
+// Step loop shared by both precisions.  P is a per-lane particle (FP64 or
+// FP32) with
+//   bool fast(W)                    first sub-step of a step (h = dt); true if
+//                                   it stays inside the edge (then applied);
+//   void resolve(step, W, ...)      the rest of a step whose first sub-step
+//                                   reached a vertex: splits, edge draws,
+//                                   further sub-steps, exit record.
+// Hits are not resolved where they happen: within one group of four steps
+// (one main-stream Philox block) every lane first runs the cheap first
+// sub-steps; a lane that reaches a vertex parks there; the parked lanes then
+// resolve together and finish their group from the cached normals.  Each
+// particle's arithmetic and random numbers are those of the plain order;
+// the split code runs once per round for all parked lanes instead of once
+// per step for any lane that hit.
+template <int NG, typename P>
+__device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs &A,
+                                          uint32_t pid, Tally &t) {
+  constexpr uint32_t NW = 4 * NG;  // steps per window
+  const uint32_t n_end = S.n0 + A.nsteps;
+  uint32_t n = S.n0;
+  while (n < n_end && q.alive) {
+    const uint32_t base = n & ~(NW - 1);
+    typename P::real W[NW];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const U4 o = philox(pid, (base >> 2) + g, 0u, S.tag, A.key0, A.key1);
+      P::box_muller(o.x, o.y, W[4 * g + 0], W[4 * g + 1]);
+      P::box_muller(o.z, o.w, W[4 * g + 2], W[4 * g + 3]);
+    }
+    const uint32_t jb = n - base;
+    const uint32_t je = min(NW, n_end - base);
+    int32_t pj = -1;
+#pragma unroll
+    for (uint32_t j = 0; j < NW; ++j) {
+      if (j < jb || j >= je || pj >= 0) continue;
+      if (!q.fast(W[j])) pj = (int32_t)j;
+    }
+    while (pj >= 0) {
+      const uint32_t j0 = (uint32_t)pj;
+      q.resolve(base + j0, pickw(W, j0), pid, S, A, t);
+      pj = -1;
+      for (uint32_t j = j0 + 1; j < je && q.alive; ++j) {
+        if (!q.fast(pickw(W, j))) {
+          pj = (int32_t)j;
+          break;
+        }
+      }
+    }
+    n = base + je;
+  }
+  // every step taken has one first sub-step; resolve() counts the others
+  const uint32_t taken = q.alive ? A.nsteps : q.death_step + 1u - S.n0;
+  t.steps += taken;
+  t.sub += taken;
+}
+
 // ------------------------------------------------------------ FP64 path --
 // The canonical step in FP64, operation for operation.
 template <bool TRACE, bool LDS>
-__device__ void run64(const GraphDev &G, const SetDev &S, const StepArgs &A,
+struct Particle64 {
+  using real = double;
+  GView G;
+  uint32_t *s_exit;
+  int32_t e;
+  double x;
+  EdgeRec64 R;
+  bool alive;
+  uint64_t hash;
+  uint32_t nhit;
+  uint32_t death_step;
+
+  __device__ static void box_muller(uint32_t a, uint32_t b, double &c, double &s) {
+    box_muller64(a, b, c, s);
+  }
+
+  __device__ __forceinline__ bool fast(double w) {
+    if (x == 0.0)
+      w = fabs(w);
+    else if (x == R.L)
+      w = -fabs(w);
+    const double mu = fma(R.c, x, R.a);
+    const double g = R.sigma * sqrt(dtv);
+    const double xt = fma(g, w, fma(mu, dtv, x));
+    if (xt > 0.0 && xt < R.L) {
+      x = xt;
+      return true;
+    }
+    return false;
+  }
+
+  double dtv;
+
+  __device__ void resolve(uint32_t step, double w, uint32_t pid, const SetDev &S,
+                          const StepArgs &A, Tally &t) {
+    double h = dtv;
+    int32_t k = 0, last = -1;
+    bool first = true;
+    for (;;) {
+      if (x == 0.0)
+        w = fabs(w);
+      else if (x == R.L)
+        w = -fabs(w);
+      const double mu = fma(R.c, x, R.a);
+      const double g = R.sigma * sqrt(h);
+      const double xt = fma(g, w, fma(mu, h, x));
+      if (!first) t.sub++;
+      first = false;
+      if (xt > 0.0 && xt < R.L) {
+        x = xt;
+        break;
+      }
+      const bool at_init = xt <= 0.0;
+      const int32_t v = at_init ? R.vinit : R.vterm;
+      const double d = at_init ? x : R.L - x;
+      const double qa = at_init ? mu * h : -(mu * h);
+      const double qb = at_init ? g * w : -(g * w);
+      const double u = first_root64(qa, qb, d);
+      const double alpha = u * u;
+      h = fma(-alpha, h, h);
+      ++k;
+      ++nhit;
+      t.hits++;
+      const VtxBlk vb = G.vtx[v];
+      if (vb.deg < 0) {  // absorbing vertex
+        alive = false;
+        death_step = step;
+        atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
+        if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
+        break;
+      }
+      const U4 hd = philox(pid, step, (uint32_t)k, S.tag, A.key0, A.key1);
+      const SlotPick sp = pick_slot(G, vb, hd.x);
+      const int32_t s = sp.s;
+      e = eo_edge(sp.eo);
+      R = G.e64[e];
+      x = (sp.eo & 1u) ? R.L : 0.0;
+      last = s;
+      if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)s);
+      if (h == 0.0) break;
+      if (k == A.max_splits) {
+        t.trunc++;
+        break;
+      }
+      w = box_muller64_cos(hd.y, hd.z);
+    }
+    if (k >= 1 && alive) count_exit<LDS>(s_exit, S.exit_cnt, last);
+  }
+};
+
+template <bool TRACE, bool LDS, int NG>
+__device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const StepArgs &A,
                       uint32_t pid, uint32_t *s_exit, Tally &t) {
-  uint32_t ef = S.ef[pid];
+  const uint32_t ef = S.ef[pid];
   if (ef & kDeadBit) return;
-  int32_t e = (int32_t)(ef & kEdgeMask);
-  if (e >= G.E) {
+  const int32_t e = (int32_t)(ef & kEdgeMask);
+  if (e >= n_edges) {
     atomicOr(S.err, kErrEdge);
     return;
   }
-  double x = S.x64[pid];
-  EdgeRec64 R = G.e64[e];
-  if (!(x >= 0.0 && x <= R.L)) {
+  Particle64<TRACE, LDS> q{G, s_exit, e, S.x64[pid], G.e64[e], true,
+                           TRACE ? S.seqhash[pid] : 0ull, TRACE ? S.hits[pid] : 0u,
+                           0u, A.dt};
+  if (!(q.x >= 0.0 && q.x <= q.R.L)) {
     atomicOr(S.err, kErrPos);
     return;
   }
-  uint64_t hash = TRACE ? S.seqhash[pid] : 0;
-  uint32_t nhit = TRACE ? S.hits[pid] : 0;
-  bool alive = true;
-  const uint32_t n_end = S.n0 + A.nsteps;
-  uint32_t n = S.n0;
-  while (n < n_end && alive) {
-    const uint32_t m = n >> 2;
-    const U4 o = philox(pid, m, 0u, S.tag, A.key0, A.key1);
-    double W[4];
-    box_muller64(o.x, o.y, W[0], W[1]);
-    box_muller64(o.z, o.w, W[2], W[3]);
-    const uint32_t jb = n & 3u;
-    const uint32_t je = min(4u, n_end - (m << 2));
-#pragma unroll
-    for (uint32_t j = 0; j < 4; ++j) {
-      if (j < jb || j >= je || !alive) continue;
-      const uint32_t step = (m << 2) + j;
-      double h = A.dt;
-      int32_t k = 0, last = -1;
-      double w = W[j];
-      t.steps++;
-      for (;;) {
-        if (x == 0.0)
-          w = fabs(w);
-        else if (x == R.L)
-          w = -fabs(w);
-        const double mu = fma(R.c, x, R.a);
-        const double g = R.sigma * sqrt(h);
-        const double xt = fma(g, w, fma(mu, h, x));
-        t.sub++;
-        if (xt > 0.0 && xt < R.L) {
-          x = xt;
-          break;
-        }
-        const bool at_init = xt <= 0.0;
-        const int32_t v = at_init ? R.vinit : R.vterm;
-        const double d = at_init ? x : R.L - x;
-        const double qa = at_init ? mu * h : -(mu * h);
-        const double qb = at_init ? g * w : -(g * w);
-        const double u = first_root<double>(qa, qb, d);
-        const double alpha = u * u;
-        h = fma(-alpha, h, h);
-        ++k;
-        ++nhit;
-        t.hits++;
-        const VtxRec vr = G.vtx[v];
-        if (vr.deg < 0) {  // absorbing vertex
-          alive = false;
-          atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
-          if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
-          break;
-        }
-        const U4 hd = philox(pid, step, (uint32_t)k, S.tag, A.key0, A.key1);
-        const int32_t s = pick_slot(G.slots, vr, hd.x);
-        const SlotRec sr = G.slots[s];
-        e = sr.edge;
-        R = G.e64[e];
-        x = sr.orient ? R.L : 0.0;
-        last = s;
-        if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)s);
-        if (h == 0.0) break;
-        if (k == A.max_splits) {
-          t.trunc++;
-          break;
-        }
-        w = box_muller64_cos(hd.y, hd.z);
-      }
-      if (k >= 1 && alive) count_exit<LDS>(s_exit, S.exit_cnt, last);
-    }
-    n = (m << 2) + je;
-  }
-  S.ef[pid] = (uint32_t)e | (alive ? 0u : kDeadBit);
-  S.x64[pid] = x;
+  step_loop<NG>(q, S, A, pid, t);
+  S.ef[pid] = (uint32_t)q.e | (q.alive ? 0u : kDeadBit);
+  S.x64[pid] = q.x;
   if (TRACE) {
-    S.seqhash[pid] = hash;
-    S.hits[pid] = nhit;
+    S.seqhash[pid] = q.hash;
+    S.hits[pid] = q.nhit;
   }
 }
 
@@ -260,151 +416,151 @@ __device__ __forceinline__ Edge32 load_edge32(const EdgeRec32 *e32, int32_t e) {
 }
 
 template <bool TRACE, bool LDS>
-__device__ void run32(const GraphDev &G, const SetDev &S, const StepArgs &A,
+struct Particle32 {
+  using real = float;
+  GView G;
+  uint32_t *s_exit;
+  int32_t e;
+  uint32_t side;
+  float y;
+  Edge32 R;
+  float as, g0;   // drift constant in the local frame, sigma sqrt(dt)
+  float dt, sqdt;
+  bool alive;
+  uint64_t hash;
+  uint32_t nhit;
+  uint32_t death_step;
+
+  __device__ static void box_muller(uint32_t a, uint32_t b, float &c, float &s) {
+    box_muller32(a, b, c, s);
+  }
+
+  // Re-anchor to the nearer end: L - yt is exact for yt in [L/2, L)
+  // (Sterbenz), so the move loses nothing.
+  __device__ __forceinline__ void settle(float yt) {
+    const bool flip = yt > 0.5f * R.L;
+    y = flip ? R.L - yt : yt;
+    side ^= flip ? 1u : 0u;
+    as = side ? -R.aL : R.a;
+  }
+
+  __device__ __forceinline__ bool fast(float w) {
+    const float we = (y == 0.0f) ? fabsf(w) : (side ? -w : w);
+    const float mu = fmaf(R.c, y, as);
+    const float yt = fmaf(g0, we, fmaf(mu, dt, y));
+    if (yt > 0.0f && yt < R.L) {
+      settle(yt);
+      return true;
+    }
+    return false;
+  }
+
+  __device__ void resolve(uint32_t step, float w, uint32_t pid, const SetDev &S,
+                          const StepArgs &A, Tally &t) {
+    float hh = dt, hl = 0.0f;
+    int32_t k = 0, last = -1;
+    bool first = true;
+    for (;;) {
+      const float we = (y == 0.0f) ? fabsf(w) : (side ? -w : w);
+      const float mu = fmaf(R.c, y, as);
+      const float g = first ? g0 : R.sigma * __builtin_amdgcn_sqrtf(hh);
+      const float yt = fmaf(g, we, fmaf(mu, hh, y));
+      if (!first) t.sub++;
+      first = false;
+      if (yt > 0.0f && yt < R.L) {
+        settle(yt);
+        break;
+      }
+      const bool near = yt <= 0.0f;
+      const bool at_term = near == (side != 0u);
+      const int32_t v = at_term ? R.vterm : R.vinit;
+      const float d = near ? y : R.L - y;
+      float u;
+      if (d < 1e-6f * R.L) {
+        // crossing solve in FP64 next to the vertex
+        const double hd = (double)hh + (double)hl;
+        const double mud = fma((double)R.c, (double)y, (double)as);
+        const double gd = (double)R.sigma * sqrt(hd);
+        const double qa = near ? mud * hd : -(mud * hd);
+        const double qb = near ? gd * (double)we : -(gd * (double)we);
+        const double dd = near ? (double)y : (double)R.L - (double)y;
+        u = (float)first_root64(qa, qb, dd);
+      } else {
+        const float mh = mu * hh, gw = g * we;
+        u = first_root32(near ? mh : -mh, near ? gw : -gw, d);
+      }
+      // remaining time (1 - u^2)(hh + hl), compensated (TwoProduct by fma,
+      // TwoSum, renormalised)
+      {
+        const float al = u * u;
+        const float p = al * hh;
+        const float pe = fmaf(al, hh, -p);
+        const float s = hh - p;
+        const float bb = s - hh;
+        const float se = (hh - (s - bb)) + (-p - bb);
+        const float lo = ((se - pe) + hl) - al * hl;
+        hh = s + lo;
+        hl = lo - (hh - s);
+      }
+      ++k;
+      ++nhit;
+      t.hits++;
+      const VtxBlk vb = G.vtx[v];
+      if (vb.deg < 0) {
+        alive = false;
+        death_step = step;
+        atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
+        if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
+        break;
+      }
+      const U4 hd = philox(pid, step, (uint32_t)k, S.tag, A.key0, A.key1);
+      const SlotPick sp = pick_slot(G, vb, hd.x);
+      const int32_t s = sp.s;
+      e = eo_edge(sp.eo);
+      R = load_edge32(G.e32, e);
+      side = sp.eo & 1u;
+      y = 0.0f;
+      as = side ? -R.aL : R.a;
+      g0 = R.sigma * sqdt;
+      last = s;
+      if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)s);
+      if (hh == 0.0f) break;
+      if (k == A.max_splits) {
+        t.trunc++;
+        break;
+      }
+      w = box_muller32_cos(hd.y, hd.z);
+    }
+    if (k >= 1 && alive) count_exit<LDS>(s_exit, S.exit_cnt, last);
+  }
+};
+
+template <bool TRACE, bool LDS, int NG>
+__device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const StepArgs &A,
                       uint32_t pid, uint32_t *s_exit, Tally &t) {
-  uint32_t ef = S.ef[pid];
+  const uint32_t ef = S.ef[pid];
   if (ef & kDeadBit) return;
-  int32_t e = (int32_t)(ef & kEdgeMask);
-  if (e >= G.E) {
+  const int32_t e = (int32_t)(ef & kEdgeMask);
+  if (e >= n_edges) {
     atomicOr(S.err, kErrEdge);
     return;
   }
-  uint32_t side = (ef & kSideBit) ? 1u : 0u;
-  float y = S.y32[pid];
-  Edge32 R = load_edge32(G.e32, e);
-  if (!(y >= 0.0f && y <= R.L)) {
+  const float sqdt = (float)sqrt(A.dt);
+  const Edge32 R = load_edge32(G.e32, e);
+  const uint32_t side = (ef & kSideBit) ? 1u : 0u;
+  Particle32<TRACE, LDS> q{G, s_exit, e, side, S.y32[pid], R,
+                           side ? -R.aL : R.a, R.sigma * sqdt, (float)A.dt, sqdt, true,
+                           TRACE ? S.seqhash[pid] : 0ull, TRACE ? S.hits[pid] : 0u, 0u};
+  if (!(q.y >= 0.0f && q.y <= R.L)) {
     atomicOr(S.err, kErrPos);
     return;
   }
-  const float dt = (float)A.dt;
-  const float sqdt = (float)sqrt(A.dt);
-  float as = side ? -R.aL : R.a;
-  float g0 = R.sigma * sqdt;
-  uint64_t hash = TRACE ? S.seqhash[pid] : 0;
-  uint32_t nhit = TRACE ? S.hits[pid] : 0;
-  bool alive = true;
-  const uint32_t n_end = S.n0 + A.nsteps;
-  uint32_t n = S.n0;
-  while (n < n_end && alive) {
-    const uint32_t m = n >> 2;
-    const U4 o = philox(pid, m, 0u, S.tag, A.key0, A.key1);
-    float W[4];
-    box_muller32(o.x, o.y, W[0], W[1]);
-    box_muller32(o.z, o.w, W[2], W[3]);
-    const uint32_t jb = n & 3u;
-    const uint32_t je = min(4u, n_end - (m << 2));
-#pragma unroll
-    for (uint32_t j = 0; j < 4; ++j) {
-      if (j < jb || j >= je || !alive) continue;
-      const uint32_t step = (m << 2) + j;
-      t.steps++;
-      // first sub-step: h = dt
-      {
-        const float we = (y == 0.0f) ? fabsf(W[j]) : (side ? -W[j] : W[j]);
-        const float mu = fmaf(R.c, y, as);
-        const float yt = fmaf(g0, we, fmaf(mu, dt, y));
-        t.sub++;
-        if (yt > 0.0f && yt < R.L) {
-          if (yt > 0.5f * R.L) {
-            y = R.L - yt;  // exact (Sterbenz)
-            side ^= 1u;
-            as = side ? -R.aL : R.a;
-          } else {
-            y = yt;
-          }
-          continue;
-        }
-      }
-      // minority: the step crosses a vertex; redo the first sub-step's
-      // quantities and split
-      float hh = dt, hl = 0.0f;
-      int32_t k = 0, last = -1;
-      float w = W[j];
-      bool first = true;
-      for (;;) {
-        const float we = (y == 0.0f) ? fabsf(w) : (side ? -w : w);
-        const float mu = fmaf(R.c, y, as);
-        const float g = first ? g0 : R.sigma * __builtin_amdgcn_sqrtf(hh);
-        const float yt = fmaf(g, we, fmaf(mu, hh, y));
-        if (!first) t.sub++;
-        first = false;
-        if (yt > 0.0f && yt < R.L) {
-          if (yt > 0.5f * R.L) {
-            y = R.L - yt;
-            side ^= 1u;
-            as = side ? -R.aL : R.a;
-          } else {
-            y = yt;
-          }
-          break;
-        }
-        const bool near = yt <= 0.0f;
-        const bool at_term = near == (side != 0u);
-        const int32_t v = at_term ? R.vterm : R.vinit;
-        const float d = near ? y : R.L - y;
-        float u;
-        if (d < 1e-6f * R.L) {
-          // crossing solve in FP64 next to the vertex
-          const double hd = (double)hh + (double)hl;
-          const double mud = fma((double)R.c, (double)y, (double)as);
-          const double gd = (double)R.sigma * sqrt(hd);
-          const double qa = near ? mud * hd : -(mud * hd);
-          const double qb = near ? gd * (double)we : -(gd * (double)we);
-          const double dd = near ? (double)y : (double)R.L - (double)y;
-          u = (float)first_root<double>(qa, qb, dd);
-        } else {
-          const float mh = mu * hh, gw = g * we;
-          u = first_root<float>(near ? mh : -mh, near ? gw : -gw, d);
-        }
-        // remaining time (1 - u^2)(hh + hl), compensated
-        {
-          const float al = u * u;
-          const float p = al * hh;
-          const float pe = fmaf(al, hh, -p);
-          const float s = hh - p;
-          const float bb = s - hh;
-          const float se = (hh - (s - bb)) + (-p - bb);
-          const float lo = ((se - pe) + hl) - al * hl;
-          hh = s + lo;
-          hl = lo - (hh - s);
-        }
-        ++k;
-        ++nhit;
-        t.hits++;
-        const VtxRec vr = G.vtx[v];
-        if (vr.deg < 0) {
-          alive = false;
-          atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
-          if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
-          break;
-        }
-        const U4 hd = philox(pid, step, (uint32_t)k, S.tag, A.key0, A.key1);
-        const int32_t s = pick_slot(G.slots, vr, hd.x);
-        const SlotRec sr = G.slots[s];
-        e = sr.edge;
-        R = load_edge32(G.e32, e);
-        side = sr.orient ? 1u : 0u;
-        y = 0.0f;
-        as = side ? -R.aL : R.a;
-        g0 = R.sigma * sqdt;
-        last = s;
-        if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)s);
-        if (hh == 0.0f) break;
-        if (k == A.max_splits) {
-          t.trunc++;
-          break;
-        }
-        w = box_muller32_cos(hd.y, hd.z);
-      }
-      if (k >= 1 && alive) count_exit<LDS>(s_exit, S.exit_cnt, last);
-    }
-    n = (m << 2) + je;
-  }
-  S.ef[pid] = (uint32_t)e | (side ? kSideBit : 0u) | (alive ? 0u : kDeadBit);
-  S.y32[pid] = y;
+  step_loop<NG>(q, S, A, pid, t);
+  S.ef[pid] = (uint32_t)q.e | (q.side ? kSideBit : 0u) | (q.alive ? 0u : kDeadBit);
+  S.y32[pid] = q.y;
   if (TRACE) {
-    S.seqhash[pid] = hash;
-    S.hits[pid] = nhit;
+    S.seqhash[pid] = q.hash;
+    S.hits[pid] = q.nhit;
   }
 }
 
@@ -427,48 +583,71 @@ __device__ __forceinline__ void flush(const SetDev &S, const Tally &t,
   }
 }
 
-template <bool FP64, bool TRACE, bool LDS>
-__global__ __launch_bounds__(kBlock) void k_step(GraphDev G, SetDev S, StepArgs A) {
-  extern __shared__ uint32_t s_exit[];
-  __shared__ uint32_t s_tot[4];
+// Shared memory of a step block: [exit counters (LDS)][staged tables].
+// Staged tables keep their relative layout: vertex blocks, slot table and
+// guide tables, then the edge records of the kernel's precision.
+template <bool FP64, bool STAGED>
+__device__ __forceinline__ GView block_view(const GraphDev &G, char *smem) {
+  if (!STAGED) return global_view(G);
+  const int32_t bytes = FP64 ? G.stage_bytes64 : G.stage_bytes32;
+  const int32_t head = G.o_e32;
+  const uint4 *src_head = (const uint4 *)G.tables;
+  const uint4 *src_edge = (const uint4 *)(G.tables + (FP64 ? G.o_e64 : G.o_e32));
+  uint4 *dst = (uint4 *)smem;
+  for (int32_t i = threadIdx.x; i < head / 16; i += blockDim.x) dst[i] = src_head[i];
+  for (int32_t i = threadIdx.x; i < (bytes - head) / 16; i += blockDim.x)
+    dst[head / 16 + i] = src_edge[i];
+  GView v;
+  v.vtx = (const VtxBlk *)(smem + G.o_vtx);
+  v.slots = (const SlotRec8 *)(smem + G.o_slots);
+  v.guide = (const int32_t *)(smem + G.o_guide);
+  v.e32 = (const EdgeRec32 *)(smem + head);
+  v.e64 = (const EdgeRec64 *)(smem + head);
+  return v;
+}
+
+__device__ __forceinline__ int32_t exit_bytes(int32_t nnz) { return ((nnz * 4) + 15) & ~15; }
+
+template <bool FP64, bool TRACE, bool LDS, bool STAGED>
+__device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
+                                           const StepArgs &A, uint32_t pid,
+                                           uint32_t *s_tot, char *smem) {
+  uint32_t *s_exit = (uint32_t *)smem;
   if (threadIdx.x < 4) s_tot[threadIdx.x] = 0;
   if (LDS)
     for (int32_t s = threadIdx.x; s < G.nnz; s += blockDim.x) s_exit[s] = 0;
+  const GView view = block_view<FP64, STAGED>(G, smem + (LDS ? exit_bytes(G.nnz) : 0));
   __syncthreads();
   Tally t{0, 0, 0, 0};
-  const uint32_t pid = blockIdx.x * kBlock + threadIdx.x;
   if (pid < S.n) {
     if (FP64)
-      run64<TRACE, LDS>(G, S, A, pid, s_exit, t);
+      run64<TRACE, LDS, kWindowGroups64>(view, G.E, S, A, pid, s_exit, t);
     else
-      run32<TRACE, LDS>(G, S, A, pid, s_exit, t);
+      run32<TRACE, LDS, kWindowGroups32>(view, G.E, S, A, pid, s_exit, t);
   }
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
 }
 
-template <bool FP64, bool TRACE, bool LDS>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED>
+__global__ __launch_bounds__(kBlock) void k_step(GraphDev G, SetDev S, StepArgs A) {
+  extern __shared__ uint4 smem4[];
+  __shared__ uint32_t s_tot[4];
+  step_block<FP64, TRACE, LDS, STAGED>(G, S, A, blockIdx.x * kBlock + threadIdx.x, s_tot,
+                                       (char *)smem4);
+}
+
+template <bool FP64, bool TRACE, bool LDS, bool STAGED>
 __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
                                                   const SetDev *sets,
                                                   const BatchItem *items,
                                                   StepArgs A) {
-  extern __shared__ uint32_t s_exit[];
+  extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
   const BatchItem it = items[blockIdx.x];
   const SetDev S = sets[it.set];
   const GraphDev G = graphs[it.set];
-  if (threadIdx.x < 4) s_tot[threadIdx.x] = 0;
-  if (LDS)
-    for (int32_t s = threadIdx.x; s < G.nnz; s += blockDim.x) s_exit[s] = 0;
-  __syncthreads();
-  Tally t{0, 0, 0, 0};
-  const uint32_t pid = it.first + threadIdx.x;
-  if (pid < S.n) {
-    if (FP64)
-      run64<TRACE, LDS>(G, S, A, pid, s_exit, t);
-    else
-      run32<TRACE, LDS>(G, S, A, pid, s_exit, t);
-  }
-  flush(S, t, s_tot, s_exit, G.nnz, LDS);
+  step_block<FP64, TRACE, LDS, STAGED>(G, S, A, it.first + threadIdx.x, s_tot,
+                                       (char *)smem4);
 }
 
 // ---------------------------------------------------------------- init --
@@ -487,11 +666,9 @@ __global__ __launch_bounds__(kBlock) void k_init(GraphDev G, SetDev S, int mode,
   } else {
     const U4 o = philox(pid, 0xFFFFFFFFu, 0xFFFFFFFFu, S.tag, k0, k1);
     if (mode == 1) {
-      const VtxRec vr = G.vtx[vertex];
-      const int32_t s = pick_slot(G.slots, vr, o.x);
-      const SlotRec sr = G.slots[s];
-      e = sr.edge;
-      x = sr.orient ? G.e64[e].L : 0.0;
+      const SlotPick sp = pick_slot(global_view(G), G.vtx[vertex], o.x);
+      e = eo_edge(sp.eo);
+      x = (sp.eo & 1u) ? G.e64[e].L : 0.0;
     } else {
       // first e with r < T_e (thresholds nondecreasing; T_{E-1} = 2^32)
       int32_t lo = 0, hi = G.E - 1;
@@ -558,31 +735,44 @@ __global__ __launch_bounds__(kBlock) void k_hist(GraphDev G, SetDev S, int32_t n
   }
 }
 
+template <bool FP64, bool TRACE, bool LDS, bool STAGED>
+void launch_step_k(const GraphDev &g, const SetDev &s, const StepArgs &a, size_t shm,
+                   hipStream_t st) {
+  const uint32_t blocks = (s.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_step<FP64, TRACE, LDS, STAGED>), dim3(blocks), dim3(kBlock), shm, st,
+                     g, s, a);
+}
+
 template <bool FP64, bool TRACE>
 hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a,
                          hipStream_t st) {
-  const uint32_t blocks = (s.n + kBlock - 1) / kBlock;
-  if (g.nnz <= kLdsExitMax) {
-    hipLaunchKernelGGL((k_step<FP64, TRACE, true>), dim3(blocks), dim3(kBlock),
-                       (size_t)g.nnz * 4, st, g, s, a);
-  } else {
-    hipLaunchKernelGGL((k_step<FP64, TRACE, false>), dim3(blocks), dim3(kBlock), 0,
-                       st, g, s, a);
-  }
+  const bool lds = g.nnz <= kLdsExitMax;
+  const int32_t stage = FP64 ? g.stage_bytes64 : g.stage_bytes32;
+  const size_t shm = (lds ? (size_t)((g.nnz * 4 + 15) & ~15) : 0) + (size_t)stage;
+  if (lds && stage) launch_step_k<FP64, TRACE, true, true>(g, s, a, shm, st);
+  else if (lds) launch_step_k<FP64, TRACE, true, false>(g, s, a, shm, st);
+  else if (stage) launch_step_k<FP64, TRACE, false, true>(g, s, a, shm, st);
+  else launch_step_k<FP64, TRACE, false, false>(g, s, a, shm, st);
   return hipGetLastError();
+}
+
+template <bool FP64, bool TRACE, bool LDS, bool STAGED>
+void launch_batch_k(const GraphDev *graphs, const SetDev *sets, const BatchItem *items,
+                    int32_t n_items, const StepArgs &a, size_t shm, hipStream_t st) {
+  hipLaunchKernelGGL((k_batch<FP64, TRACE, LDS, STAGED>), dim3(n_items), dim3(kBlock), shm,
+                     st, graphs, sets, items, a);
 }
 
 template <bool FP64, bool TRACE>
 hipError_t launch_batch_t(const GraphDev *graphs, const SetDev *sets,
                           const BatchItem *items, int32_t n_items, int32_t max_nnz,
-                          const StepArgs &a, hipStream_t st) {
-  if (max_nnz <= kLdsExitMax) {
-    hipLaunchKernelGGL((k_batch<FP64, TRACE, true>), dim3(n_items), dim3(kBlock),
-                       (size_t)max_nnz * 4, st, graphs, sets, items, a);
-  } else {
-    hipLaunchKernelGGL((k_batch<FP64, TRACE, false>), dim3(n_items), dim3(kBlock), 0,
-                       st, graphs, sets, items, a);
-  }
+                          int32_t max_stage, const StepArgs &a, hipStream_t st) {
+  const bool lds = max_nnz <= kLdsExitMax;
+  const size_t shm = (lds ? (size_t)((max_nnz * 4 + 15) & ~15) : 0) + (size_t)max_stage;
+  if (lds && max_stage) launch_batch_k<FP64, TRACE, true, true>(graphs, sets, items, n_items, a, shm, st);
+  else if (lds) launch_batch_k<FP64, TRACE, true, false>(graphs, sets, items, n_items, a, shm, st);
+  else if (max_stage) launch_batch_k<FP64, TRACE, false, true>(graphs, sets, items, n_items, a, shm, st);
+  else launch_batch_k<FP64, TRACE, false, false>(graphs, sets, items, n_items, a, shm, st);
   return hipGetLastError();
 }
 
@@ -611,12 +801,13 @@ hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
 
 hipError_t launch_batch(const GraphDev *graphs, const SetDev *sets,
                         const BatchItem *items, int32_t n_items, int32_t max_nnz,
-                        const StepArgs &a, bool fp64, bool trace, hipStream_t st) {
+                        int32_t max_stage, const StepArgs &a, bool fp64, bool trace,
+                        hipStream_t st) {
   if (fp64)
-    return trace ? launch_batch_t<true, true>(graphs, sets, items, n_items, max_nnz, a, st)
-                 : launch_batch_t<true, false>(graphs, sets, items, n_items, max_nnz, a, st);
-  return trace ? launch_batch_t<false, true>(graphs, sets, items, n_items, max_nnz, a, st)
-               : launch_batch_t<false, false>(graphs, sets, items, n_items, max_nnz, a, st);
+    return trace ? launch_batch_t<true, true>(graphs, sets, items, n_items, max_nnz, max_stage, a, st)
+                 : launch_batch_t<true, false>(graphs, sets, items, n_items, max_nnz, max_stage, a, st);
+  return trace ? launch_batch_t<false, true>(graphs, sets, items, n_items, max_nnz, max_stage, a, st)
+               : launch_batch_t<false, false>(graphs, sets, items, n_items, max_nnz, max_stage, a, st);
 }
 
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,
