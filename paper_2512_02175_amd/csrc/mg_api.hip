@@ -483,6 +483,16 @@ static mg_status check_steps(const mg_particles *p, int64_t n_steps, double dt) 
   return MG_OK;
 }
 
+// FP32 step schedule: wave pools (default) or one particle per lane for the
+// whole launch (MG_FP32_KERNEL=lanes), kept for comparison runs.
+static int32_t fp32_kernel() {
+  static const int32_t v = [] {
+    const char *e = std::getenv("MG_FP32_KERNEL");
+    return (e && std::strcmp(e, "lanes") == 0) ? 0 : 1;
+  }();
+  return v;
+}
+
 static uint32_t chunk_steps(int32_t spl) {
   // Steps fused per launch.  Per-lane tallies are 32-bit and a launch may
   // not run forever, so cap a chunk at 2^20 steps.
@@ -500,6 +510,7 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   a.dt = dt;
+  a.kernel = fp32_kernel();
   const uint32_t chunk = chunk_steps(p->steps_per_launch);
   int64_t left = n_steps;
   while (left > 0) {
@@ -618,8 +629,9 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
   b->sets.assign(sets, sets + n_sets);
   std::vector<BatchItem> items;
   bool all_stage = true;
+  const int32_t tile = batch_tile(sets[0]->prec == MG_FP64, fp32_kernel());
   for (int32_t i = 0; i < n_sets; ++i) {
-    for (int64_t f = 0; f < sets[i]->n; f += kBlock) items.push_back({i, (uint32_t)f});
+    for (int64_t f = 0; f < sets[i]->n; f += tile) items.push_back({i, (uint32_t)f});
     b->max_nnz = std::max(b->max_nnz, sets[i]->g->nnz);
     const GraphDev &gd = sets[i]->g->gd;
     const int32_t st = sets[i]->prec == MG_FP64 ? gd.stage_bytes64 : gd.stage_bytes32;
@@ -672,6 +684,7 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   a.dt = dt;
+  a.kernel = fp32_kernel();
   const uint32_t chunk = chunk_steps(p0->steps_per_launch);
   const int32_t n_sets = (int32_t)b->sets.size();
   std::vector<SetDev> sds(n_sets);

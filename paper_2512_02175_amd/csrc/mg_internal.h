@@ -99,6 +99,7 @@ struct StepArgs {
   int32_t max_splits;
   uint32_t key0, key1;
   double dt;
+  int32_t kernel;  // FP32 schedule: 0 lane-per-particle windows, 1 wave pools
 };
 
 // Batched form: one work item per (set, tile of particles).
@@ -108,6 +109,8 @@ struct BatchItem {
 };
 
 constexpr int kBlock = 256;
+constexpr int kPoolPerWave = 128;                       // FP32 wave pools
+constexpr int kPoolPerBlock = kPoolPerWave * (kBlock / 64);
 constexpr int kLdsExitMax = 16384;  // slots counted in LDS (64 KiB of u32)
 constexpr int kLdsStageMax = 24576; // graph tables staged in LDS up to this size
 
@@ -117,6 +120,9 @@ hipError_t launch_init(const GraphDev &g, const SetDev &s, int mode,
                        bool fp64, hipStream_t st);
 hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
                        bool fp64, bool trace, hipStream_t st);
+// Particles per batch work item: a pool block for the FP32 wave-pool
+// kernel, a plain block otherwise.
+int32_t batch_tile(bool fp64, int32_t kernel);
 hipError_t launch_batch(const GraphDev *graphs, const SetDev *sets,
                         const BatchItem *items, int32_t n_items,
                         int32_t max_nnz, int32_t max_stage, const StepArgs &a,

@@ -650,6 +650,286 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
                                        (char *)smem4);
 }
 
+// ------------------------------------------------ FP32 wave-pool kernel --
+// Each wave owns kPoolPerWave particles: 64 ride in the lanes, the others
+// wait in the wave's private LDS home slots.  A lane runs its particle's
+// first sub-steps for one main-stream Philox group (four steps) per
+// iteration; a particle whose sub-step reaches a vertex is parked: its state
+// goes to its home slot and its slot id onto the wave's split stack, and the
+// lane takes a ready particle instead.  When 64 particles are parked (or
+// lanes would idle), one split pass resolves them with every lane busy:
+// crossing time, Philox hit stream, slot draw, continuation sub-steps, exit
+// record, and puts them back on the ready stack.  Each particle still
+// consumes exactly the random numbers of its own (step, hit) counters, so the
+// results equal the plain per-particle order bit for bit.  Waves never wait
+// for one another: the stacks and their counts are private to a wave.
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kIdleTrigger = 8;  // idle lanes that trigger a partial split pass
+
+struct PoolLds32 {
+  uint32_t ef[kPoolPerWave];
+  float y[kPoolPerWave];
+  uint32_t n[kPoolPerWave];   // next step (ready) or the step to resolve (parked)
+  float w[kPoolPerWave];      // first sub-step normal of a parked step
+  uint32_t hits[kPoolPerWave];
+  uint64_t hash[kPoolPerWave];
+  uint8_t ready[kPoolPerWave];
+  uint8_t split[kPoolPerWave];
+};
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+template <bool TRACE, bool LDS>
+__device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolLds32 &P,
+                                          uint32_t s) {
+  const uint32_t ef = P.ef[s];
+  q.e = (int32_t)(ef & kEdgeMask);
+  q.side = (ef & kSideBit) ? 1u : 0u;
+  q.y = P.y[s];
+  q.R = load_edge32(q.G.e32, q.e);
+  q.as = q.side ? -q.R.aL : q.R.a;
+  q.g0 = q.R.sigma * q.sqdt;
+  q.alive = true;
+  if (TRACE) {
+    q.nhit = P.hits[s];
+    q.hash = P.hash[s];
+  }
+}
+
+template <bool TRACE, bool LDS>
+__device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS> &q, PoolLds32 &P,
+                                           uint32_t s, uint32_t n) {
+  P.ef[s] = (uint32_t)q.e | (q.side ? kSideBit : 0u);
+  P.y[s] = q.y;
+  P.n[s] = n;
+  if (TRACE) {
+    P.hits[s] = q.nhit;
+    P.hash[s] = q.hash;
+  }
+}
+
+template <bool TRACE, bool LDS>
+__device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS> &q, const SetDev &S,
+                                            const StepArgs &A, uint32_t pid, Tally &t) {
+  S.ef[pid] = (uint32_t)q.e | (q.side ? kSideBit : 0u) | (q.alive ? 0u : kDeadBit);
+  S.y32[pid] = q.y;
+  if (TRACE) {
+    S.seqhash[pid] = q.hash;
+    S.hits[pid] = q.nhit;
+  }
+  const uint32_t taken = q.alive ? A.nsteps : q.death_step + 1u - S.n0;
+  t.steps += taken;
+  t.sub += taken;
+}
+
+template <bool TRACE, bool LDS>
+__device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
+                           const StepArgs &A, uint32_t base, PoolLds32 &P,
+                           uint32_t *s_exit, Tally &t) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const float dt = (float)A.dt;
+  const float sqdt = (float)sqrt(A.dt);
+  const uint32_t n_end = S.n0 + A.nsteps;
+  Particle32<TRACE, LDS> q{G, s_exit, 0, 0u, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
+                           true, 0ull, 0u, 0u};
+  bool has = false;
+  uint32_t slot = 0, n = 0;
+  uint32_t ready_cnt = 0, split_cnt = 0;
+
+  // Initial placement: slot `lane` rides in the lane, slot 64 + lane waits.
+#pragma unroll
+  for (uint32_t half = 0; half < 2; ++half) {
+    const uint32_t s = lane + 64u * half;
+    const uint32_t pid = base + s;
+    bool ok = false;
+    uint32_t ef = 0;
+    float y = 0.0f;
+    if (pid < S.n) {
+      ef = S.ef[pid];
+      y = S.y32[pid];
+      const int32_t e = (int32_t)(ef & kEdgeMask);
+      if (!(ef & kDeadBit)) {
+        if (e >= n_edges) {
+          atomicOr(S.err, kErrEdge);
+        } else if (!(y >= 0.0f && y <= G.e32[e].L)) {
+          atomicOr(S.err, kErrPos);
+        } else {
+          ok = true;
+        }
+      }
+    }
+    if (half == 0) {
+      if (ok) {
+        P.ef[s] = ef;
+        P.y[s] = y;
+        if (TRACE) {
+          P.hits[s] = S.hits[pid];
+          P.hash[s] = S.seqhash[pid];
+        }
+        wave_lds_fence();
+        pool_load(q, P, s);
+        has = true;
+        slot = s;
+        n = S.n0;
+      }
+    } else {
+      const uint64_t m = __ballot(ok);
+      if (ok) {
+        P.ef[s] = ef;
+        P.y[s] = y;
+        P.n[s] = S.n0;
+        if (TRACE) {
+          P.hits[s] = S.hits[pid];
+          P.hash[s] = S.seqhash[pid];
+        }
+        P.ready[ready_cnt + lane_rank(m)] = (uint8_t)s;
+      }
+      ready_cnt += (uint32_t)__popcll(m);
+    }
+  }
+  wave_lds_fence();
+
+  for (;;) {
+    // lanes without a particle take ready ones
+    {
+      const uint64_t m_empty = __ballot(!has);
+      if (!has) {
+        const uint32_t r = lane_rank(m_empty);
+        if (r < ready_cnt) {
+          slot = P.ready[ready_cnt - 1u - r];
+          n = P.n[slot];
+          pool_load(q, P, slot);
+          has = true;
+        }
+      }
+      ready_cnt -= min((uint32_t)__popcll(m_empty), ready_cnt);
+    }
+    bool do_split = false;
+    if (__ballot(has) == 0ull) {
+      if (split_cnt == 0) break;
+      do_split = true;
+    } else {
+      // one Philox group of first sub-steps for every lane with a particle
+      bool parked = false;
+      float wp = 0.0f;
+      if (has) {
+        const uint32_t m = n >> 2;
+        const U4 o = philox(base + slot, m, 0u, S.tag, A.key0, A.key1);
+        float W[4];
+        box_muller32(o.x, o.y, W[0], W[1]);
+        box_muller32(o.z, o.w, W[2], W[3]);
+        const uint32_t jb = n & 3u;
+        const uint32_t je = min(4u, n_end - (m << 2));
+        int32_t pj = -1;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+          if (j < jb || j >= je || pj >= 0) continue;
+          if (!q.fast(W[j])) {
+            pj = (int32_t)j;
+            wp = W[j];
+          }
+        }
+        if (pj >= 0) {
+          parked = true;
+          n = (m << 2) + (uint32_t)pj;
+        } else {
+          n = (m << 2) + je;
+        }
+        if (!parked && n == n_end) {
+          pool_finish(q, S, A, base + slot, t);
+          has = false;
+        }
+      }
+      const uint64_t m_park = __ballot(parked);
+      if (parked) {
+        pool_store(q, P, slot, n);
+        P.w[slot] = wp;
+        P.split[split_cnt + lane_rank(m_park)] = (uint8_t)slot;
+        has = false;
+      }
+      split_cnt += (uint32_t)__popcll(m_park);
+      wave_lds_fence();
+      const uint32_t empty = (uint32_t)__popcll(__ballot(!has));
+      const uint32_t idle = empty > ready_cnt ? empty - ready_cnt : 0u;
+      do_split = split_cnt >= 64u || (split_cnt > 0u && idle >= (uint32_t)kIdleTrigger);
+    }
+    if (do_split) {
+      // resolve up to 64 parked particles, one per lane
+      const uint32_t B = min(split_cnt, 64u);
+      const bool mine = lane < B;
+      bool back = false;
+      uint32_t s2 = 0;
+      if (mine) {
+        s2 = P.split[split_cnt - 1u - lane];
+        Particle32<TRACE, LDS> q2{G, s_exit, 0, 0u, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
+                                  true, 0ull, 0u, 0u};
+        pool_load(q2, P, s2);
+        const uint32_t step = P.n[s2];
+        q2.resolve(step, P.w[s2], base + s2, S, A, t);
+        const uint32_t n2 = step + 1u;
+        if (!q2.alive || n2 == n_end) {
+          pool_finish(q2, S, A, base + s2, t);
+        } else {
+          pool_store(q2, P, s2, n2);
+          back = true;
+        }
+      }
+      split_cnt -= B;
+      const uint64_t m_back = __ballot(back);
+      if (back) P.ready[ready_cnt + lane_rank(m_back)] = (uint8_t)s2;
+      ready_cnt += (uint32_t)__popcll(m_back);
+      wave_lds_fence();
+    }
+  }
+}
+
+template <bool TRACE, bool LDS, bool STAGED>
+__device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
+                                           const StepArgs &A, uint32_t block_first,
+                                           uint32_t *s_tot, char *smem) {
+  uint32_t *s_exit = (uint32_t *)smem;
+  if (threadIdx.x < 4) s_tot[threadIdx.x] = 0;
+  if (LDS)
+    for (int32_t s = threadIdx.x; s < G.nnz; s += blockDim.x) s_exit[s] = 0;
+  const int32_t ex = LDS ? exit_bytes(G.nnz) : 0;
+  const GView view = block_view<false, STAGED>(G, smem + ex);
+  PoolLds32 *pools =
+      (PoolLds32 *)(smem + ((ex + (STAGED ? G.stage_bytes32 : 0) + 15) & ~15));
+  __syncthreads();
+  Tally t{0, 0, 0, 0};
+  const uint32_t wave = threadIdx.x >> 6;
+  run_pool32<TRACE, LDS>(view, G.E, S, A, block_first + wave * kPoolPerWave, pools[wave],
+                         s_exit, t);
+  flush(S, t, s_tot, s_exit, G.nnz, LDS);
+}
+
+template <bool TRACE, bool LDS, bool STAGED>
+__global__ __launch_bounds__(kBlock) void k_pool32(GraphDev G, SetDev S, StepArgs A) {
+  extern __shared__ uint4 smem4[];
+  __shared__ uint32_t s_tot[4];
+  pool_block<TRACE, LDS, STAGED>(G, S, A, blockIdx.x * kPoolPerBlock, s_tot, (char *)smem4);
+}
+
+template <bool TRACE, bool LDS, bool STAGED>
+__global__ __launch_bounds__(kBlock) void k_pool32_batch(const GraphDev *graphs,
+                                                         const SetDev *sets,
+                                                         const BatchItem *items,
+                                                         StepArgs A) {
+  extern __shared__ uint4 smem4[];
+  __shared__ uint32_t s_tot[4];
+  const BatchItem it = items[blockIdx.x];
+  const SetDev S = sets[it.set];
+  const GraphDev G = graphs[it.set];
+  pool_block<TRACE, LDS, STAGED>(G, S, A, it.first, s_tot, (char *)smem4);
+}
+
 // ---------------------------------------------------------------- init --
 template <bool FP64>
 __global__ __launch_bounds__(kBlock) void k_init(GraphDev G, SetDev S, int mode,
@@ -743,9 +1023,32 @@ void launch_step_k(const GraphDev &g, const SetDev &s, const StepArgs &a, size_t
                      g, s, a);
 }
 
+template <bool TRACE, bool LDS, bool STAGED>
+void launch_pool_k(const GraphDev &g, const SetDev &s, const StepArgs &a, size_t shm,
+                   hipStream_t st) {
+  const uint32_t blocks = (s.n + kPoolPerBlock - 1) / kPoolPerBlock;
+  hipLaunchKernelGGL((k_pool32<TRACE, LDS, STAGED>), dim3(blocks), dim3(kBlock), shm, st,
+                     g, s, a);
+}
+
+template <bool TRACE>
+hipError_t launch_pool_t(const GraphDev &g, const SetDev &s, const StepArgs &a,
+                         hipStream_t st) {
+  const bool lds = g.nnz <= kLdsExitMax;
+  const int32_t stage = g.stage_bytes32;
+  const int32_t ex = lds ? ((g.nnz * 4 + 15) & ~15) : 0;
+  const size_t shm = (size_t)(((ex + stage) + 15) & ~15) + sizeof(PoolLds32) * kWavesPerBlock;
+  if (lds && stage) launch_pool_k<TRACE, true, true>(g, s, a, shm, st);
+  else if (lds) launch_pool_k<TRACE, true, false>(g, s, a, shm, st);
+  else if (stage) launch_pool_k<TRACE, false, true>(g, s, a, shm, st);
+  else launch_pool_k<TRACE, false, false>(g, s, a, shm, st);
+  return hipGetLastError();
+}
+
 template <bool FP64, bool TRACE>
 hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a,
                          hipStream_t st) {
+  if (!FP64 && a.kernel == 1) return launch_pool_t<TRACE>(g, s, a, st);
   const bool lds = g.nnz <= kLdsExitMax;
   const int32_t stage = FP64 ? g.stage_bytes64 : g.stage_bytes32;
   const size_t shm = (lds ? (size_t)((g.nnz * 4 + 15) & ~15) : 0) + (size_t)stage;
@@ -763,11 +1066,28 @@ void launch_batch_k(const GraphDev *graphs, const SetDev *sets, const BatchItem 
                      st, graphs, sets, items, a);
 }
 
+template <bool TRACE, bool LDS, bool STAGED>
+void launch_pool_batch_k(const GraphDev *graphs, const SetDev *sets, const BatchItem *items,
+                         int32_t n_items, const StepArgs &a, size_t shm, hipStream_t st) {
+  hipLaunchKernelGGL((k_pool32_batch<TRACE, LDS, STAGED>), dim3(n_items), dim3(kBlock), shm,
+                     st, graphs, sets, items, a);
+}
+
 template <bool FP64, bool TRACE>
 hipError_t launch_batch_t(const GraphDev *graphs, const SetDev *sets,
                           const BatchItem *items, int32_t n_items, int32_t max_nnz,
                           int32_t max_stage, const StepArgs &a, hipStream_t st) {
   const bool lds = max_nnz <= kLdsExitMax;
+  if (!FP64 && a.kernel == 1) {
+    const int32_t ex = lds ? ((max_nnz * 4 + 15) & ~15) : 0;
+    const size_t shm =
+        (size_t)(((ex + max_stage) + 15) & ~15) + sizeof(PoolLds32) * kWavesPerBlock;
+    if (lds && max_stage) launch_pool_batch_k<TRACE, true, true>(graphs, sets, items, n_items, a, shm, st);
+    else if (lds) launch_pool_batch_k<TRACE, true, false>(graphs, sets, items, n_items, a, shm, st);
+    else if (max_stage) launch_pool_batch_k<TRACE, false, true>(graphs, sets, items, n_items, a, shm, st);
+    else launch_pool_batch_k<TRACE, false, false>(graphs, sets, items, n_items, a, shm, st);
+    return hipGetLastError();
+  }
   const size_t shm = (lds ? (size_t)((max_nnz * 4 + 15) & ~15) : 0) + (size_t)max_stage;
   if (lds && max_stage) launch_batch_k<FP64, TRACE, true, true>(graphs, sets, items, n_items, a, shm, st);
   else if (lds) launch_batch_k<FP64, TRACE, true, false>(graphs, sets, items, n_items, a, shm, st);
@@ -797,6 +1117,10 @@ hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
                          : launch_step_t<true, false>(g, s, a, st);
   return trace ? launch_step_t<false, true>(g, s, a, st)
                : launch_step_t<false, false>(g, s, a, st);
+}
+
+int32_t batch_tile(bool fp64, int32_t kernel) {
+  return (!fp64 && kernel == 1) ? kPoolPerBlock : kBlock;
 }
 
 hipError_t launch_batch(const GraphDev *graphs, const SetDev *sets,
