@@ -107,7 +107,15 @@ void mg_graph_destroy(mg_graph *g);
  *                 set's device arrays (size from mg_particles_arena_bytes);
  *                 NULL: the library allocates.  The arena must outlive the
  *                 set.
+ *   schedule      FP32 kernel schedule: MG_SCHED_AUTO (0), MG_SCHED_LANES
+ *                 (1: one particle per lane for a whole launch) or
+ *                 MG_SCHED_POOLS (2: each wave cycles 128 particles through
+ *                 its lanes and resolves vertex hits in full-width passes).
+ *                 Results are identical; only the speed differs.  FP64 sets
+ *                 always use the lane schedule.
  */
+typedef enum { MG_SCHED_AUTO = 0, MG_SCHED_LANES = 1, MG_SCHED_POOLS = 2 } mg_schedule;
+
 typedef struct {
   mg_precision precision;
   int32_t max_splits;
@@ -117,6 +125,7 @@ typedef struct {
   void *hip_stream;
   void *arena;
   int64_t arena_bytes;
+  int32_t schedule;
 } mg_options;
 
 typedef enum {

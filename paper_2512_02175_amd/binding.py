@@ -20,6 +20,7 @@ MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ESTATE = 0, 1, 2, 3, 4
 MG_FP64, MG_FP32 = 0, 1
 MG_VTX_STANDARD, MG_VTX_ABSORBING = 0, 1
 MG_INIT_EXPLICIT, MG_INIT_AT_VERTEX, MG_INIT_UNIFORM_LENGTH = 0, 1, 2
+MG_SCHED_AUTO, MG_SCHED_LANES, MG_SCHED_POOLS = 0, 1, 2
 
 EXPORTED = (
     "mg_graph_create", "mg_graph_destroy", "mg_particles_arena_bytes",
@@ -49,7 +50,8 @@ class mg_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("max_splits", C.c_int32),
                 ("graph_tag", C.c_uint32), ("trace", C.c_int32),
                 ("steps_per_launch", C.c_int32), ("hip_stream", C.c_void_p),
-                ("arena", C.c_void_p), ("arena_bytes", C.c_int64)]
+                ("arena", C.c_void_p), ("arena_bytes", C.c_int64),
+                ("schedule", C.c_int32)]
 
 
 _lib = None
@@ -191,11 +193,11 @@ def mg_graph_destroy(g: Graph) -> None:
 
 
 def _options(precision, max_splits, graph_tag, trace, steps_per_launch, stream,
-             arena_ptr=None, arena_bytes=0):
+             arena_ptr=None, arena_bytes=0, schedule=MG_SCHED_AUTO):
     return mg_options(int(precision), int(max_splits), int(graph_tag), int(bool(trace)),
                       int(steps_per_launch),
                       stream if stream is not None else _torch_stream(),
-                      arena_ptr, int(arena_bytes))
+                      arena_ptr, int(arena_bytes), int(schedule))
 
 
 def mg_particles_arena_bytes(g: Graph, n: int, precision=MG_FP64, trace=False) -> int:
@@ -206,7 +208,7 @@ def mg_particles_arena_bytes(g: Graph, n: int, precision=MG_FP64, trace=False) -
 def mg_particles_init(g: Graph, n: int, mode: int, *, edge=None, pos=None, vertex: int = 0,
                       init_seed: int = 0, precision: int = MG_FP64, max_splits: int = 8,
                       graph_tag: int = 0, trace: bool = False, steps_per_launch: int = 0,
-                      stream=None, arena=None) -> Particles:
+                      stream=None, arena=None, schedule: int = MG_SCHED_AUTO) -> Particles:
     """``arena``: None (library allocates), "torch" (a torch uint8 CUDA
     tensor of the required size), or a torch tensor to use."""
     e = None if edge is None else np.ascontiguousarray(edge, np.int32)
@@ -218,7 +220,8 @@ def mg_particles_init(g: Graph, n: int, mode: int, *, edge=None, pos=None, verte
         arena_obj = (torch.empty(need, dtype=torch.uint8, device="cuda")
                      if isinstance(arena, str) else arena)
         aptr, abytes = C.c_void_p(arena_obj.data_ptr()), arena_obj.numel() * arena_obj.element_size()
-    o = _options(precision, max_splits, graph_tag, trace, steps_per_launch, stream, aptr, abytes)
+    o = _options(precision, max_splits, graph_tag, trace, steps_per_launch, stream, aptr, abytes,
+                 schedule)
     h = C.c_void_p()
     _check(lib().mg_particles_init(g.handle, int(n), int(mode), _p(e), _p(x), int(vertex),
                                    C.c_uint64(init_seed), C.byref(o), C.byref(h)))

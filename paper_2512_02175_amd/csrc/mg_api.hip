@@ -86,6 +86,7 @@ struct mg_graph {
 
 struct mg_particles {
   const mg_graph *g = nullptr;
+  int32_t schedule = MG_SCHED_AUTO;
   int64_t n = 0;
   mg_precision prec = MG_FP64;
   int32_t max_splits = 8;
@@ -374,6 +375,8 @@ mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
   if (o.max_splits < 0) return fail(MG_EINVAL, "max_splits must be >= 0 (0: default)");
   if (o.max_splits == 0) o.max_splits = 8;
   if (o.steps_per_launch < 0) return fail(MG_EINVAL, "steps_per_launch must be >= 0");
+  if (o.schedule < MG_SCHED_AUTO || o.schedule > MG_SCHED_POOLS)
+    return fail(MG_EINVAL, "unknown schedule");
   if (mode == MG_INIT_EXPLICIT) {
     if (!edge || !pos) return fail(MG_EINVAL, "explicit init needs edge and pos");
     for (int64_t i = 0; i < n; ++i) {
@@ -397,6 +400,7 @@ mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
   p->tag = o.graph_tag;
   p->trace = o.trace != 0;
   p->steps_per_launch = o.steps_per_launch;
+  p->schedule = o.schedule;
   p->stream = (hipStream_t)o.hip_stream;
   if (o.arena) {
     if (o.arena_bytes < (int64_t)L.total) {
@@ -483,14 +487,10 @@ static mg_status check_steps(const mg_particles *p, int64_t n_steps, double dt) 
   return MG_OK;
 }
 
-// FP32 step schedule: wave pools (default) or one particle per lane for the
-// whole launch (MG_FP32_KERNEL=lanes), kept for comparison runs.
-static int32_t fp32_kernel() {
-  static const int32_t v = [] {
-    const char *e = std::getenv("MG_FP32_KERNEL");
-    return (e && std::strcmp(e, "lanes") == 0) ? 0 : 1;
-  }();
-  return v;
+// FP32 step schedule of a set: 1 = wave pools, 0 = one particle per lane.
+// Automatic selection takes the pools.
+static int32_t fp32_kernel(const mg_particles *p) {
+  return p->schedule == MG_SCHED_LANES ? 0 : 1;
 }
 
 static uint32_t chunk_steps(int32_t spl) {
@@ -510,7 +510,7 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   a.dt = dt;
-  a.kernel = fp32_kernel();
+  a.kernel = fp32_kernel(p);
   const uint32_t chunk = chunk_steps(p->steps_per_launch);
   int64_t left = n_steps;
   while (left > 0) {
@@ -622,6 +622,8 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
     if (sets[i]->prec != sets[0]->prec) return fail(MG_EINVAL, "sets differ in precision");
     if (sets[i]->max_splits != sets[0]->max_splits) return fail(MG_EINVAL, "sets differ in max_splits");
     if (sets[i]->trace != sets[0]->trace) return fail(MG_EINVAL, "sets differ in trace");
+    if (fp32_kernel(sets[i]) != fp32_kernel(sets[0]))
+      return fail(MG_EINVAL, "sets differ in schedule");
     for (int32_t j = 0; j < i; ++j)
       if (sets[j] == sets[i]) return fail(MG_EINVAL, "set %d appears twice", i);
   }
@@ -629,7 +631,7 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
   b->sets.assign(sets, sets + n_sets);
   std::vector<BatchItem> items;
   bool all_stage = true;
-  const int32_t tile = batch_tile(sets[0]->prec == MG_FP64, fp32_kernel());
+  const int32_t tile = batch_tile(sets[0]->prec == MG_FP64, fp32_kernel(sets[0]));
   for (int32_t i = 0; i < n_sets; ++i) {
     for (int64_t f = 0; f < sets[i]->n; f += tile) items.push_back({i, (uint32_t)f});
     b->max_nnz = std::max(b->max_nnz, sets[i]->g->nnz);
@@ -684,7 +686,7 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   a.dt = dt;
-  a.kernel = fp32_kernel();
+  a.kernel = fp32_kernel(p0);
   const uint32_t chunk = chunk_steps(p0->steps_per_launch);
   const int32_t n_sets = (int32_t)b->sets.size();
   std::vector<SetDev> sds(n_sets);

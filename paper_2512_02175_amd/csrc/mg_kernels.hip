@@ -40,8 +40,15 @@ struct U4 {
   uint32_t x, y, z, w;
 };
 
-// Philox4x32-10: ten rounds of two 32x32->64 products and xors, the key
-// bumped by the Weyl increments before every round but the first.
+// Three-input exclusive or in one gfx950 instruction (v_bitop3_b32 with
+// truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// Philox4x32-10: ten rounds of two 32x32->64 products (v_mad_u64_u32) and
+// three-way xors, the key bumped by the Weyl increments before every round
+// but the first.
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
                                      uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -52,8 +59,8 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
     }
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-    const uint32_t t0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t t2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t t0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t t2 = xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = t0;
@@ -455,6 +462,22 @@ struct Particle32 {
     return false;
   }
 
+  // First sub-step as straight-line code: applied only where `active`;
+  // returns whether the proposal stays inside the edge.
+  __device__ __forceinline__ bool fast_pred(float w, bool active) {
+    const float we = (y == 0.0f) ? fabsf(w) : (side ? -w : w);
+    const float mu = fmaf(R.c, y, as);
+    const float yt = fmaf(g0, we, fmaf(mu, dt, y));
+    const bool in = (yt > 0.0f) & (yt < R.L);
+    const bool upd = active & in;
+    const bool flip = yt > 0.5f * R.L;
+    const float ys = flip ? R.L - yt : yt;
+    y = upd ? ys : y;
+    side = upd ? (side ^ (flip ? 1u : 0u)) : side;
+    as = side ? -R.aL : R.a;
+    return in;
+  }
+
   __device__ void resolve(uint32_t step, float w, uint32_t pid, const SetDev &S,
                           const StepArgs &A, Tally &t) {
     float hh = dt, hl = 0.0f;
@@ -682,9 +705,10 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ void wave_lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
+// A wave's LDS instructions execute in issue order, so lanes of one wave
+// may exchange data through LDS without waiting; only the compiler must not
+// move the accesses across each other.
+__device__ __forceinline__ void wave_lds_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
 template <bool TRACE, bool LDS>
 __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolLds32 &P,
@@ -830,11 +854,11 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         int32_t pj = -1;
 #pragma unroll
         for (uint32_t j = 0; j < 4; ++j) {
-          if (j < jb || j >= je || pj >= 0) continue;
-          if (!q.fast(W[j])) {
-            pj = (int32_t)j;
-            wp = W[j];
-          }
+          const bool act = (j >= jb) & (j < je) & (pj < 0);
+          const bool in = q.fast_pred(W[j], act);
+          const bool hit = act & !in;
+          pj = hit ? (int32_t)j : pj;
+          wp = hit ? W[j] : wp;
         }
         if (pj >= 0) {
           parked = true;
@@ -861,13 +885,17 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       do_split = split_cnt >= 64u || (split_cnt > 0u && idle >= (uint32_t)kIdleTrigger);
     }
     if (do_split) {
-      // resolve up to 64 parked particles, one per lane
+      // The lanes' own particles wait in their home slots during the pass.
+      if (has) pool_store(q, P, slot, n);
+      // Resolve up to 64 parked particles, one per lane: crossing time,
+      // edge draw, continuation sub-steps to the end of the parked step.
       const uint32_t B = min(split_cnt, 64u);
-      const bool mine = lane < B;
+      split_cnt -= B;
+      wave_lds_fence();
       bool back = false;
       uint32_t s2 = 0;
-      if (mine) {
-        s2 = P.split[split_cnt - 1u - lane];
+      if (lane < B) {
+        s2 = P.split[split_cnt + lane];
         Particle32<TRACE, LDS> q2{G, s_exit, 0, 0u, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
                                   true, 0ull, 0u, 0u};
         pool_load(q2, P, s2);
@@ -881,11 +909,14 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
           back = true;
         }
       }
-      split_cnt -= B;
       const uint64_t m_back = __ballot(back);
       if (back) P.ready[ready_cnt + lane_rank(m_back)] = (uint8_t)s2;
       ready_cnt += (uint32_t)__popcll(m_back);
       wave_lds_fence();
+      if (has) {
+        n = P.n[slot];
+        pool_load(q, P, slot);
+      }
     }
   }
 }
@@ -910,15 +941,21 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
 }
 
+#ifndef MG_POOL_WAVES_PER_EU
+#define MG_POOL_WAVES_PER_EU 7
+#endif
+
 template <bool TRACE, bool LDS, bool STAGED>
-__global__ __launch_bounds__(kBlock) void k_pool32(GraphDev G, SetDev S, StepArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
+void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
   pool_block<TRACE, LDS, STAGED>(G, S, A, blockIdx.x * kPoolPerBlock, s_tot, (char *)smem4);
 }
 
 template <bool TRACE, bool LDS, bool STAGED>
-__global__ __launch_bounds__(kBlock) void k_pool32_batch(const GraphDev *graphs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
+void k_pool32_batch(const GraphDev *graphs,
                                                          const SetDev *sets,
                                                          const BatchItem *items,
                                                          StepArgs A) {

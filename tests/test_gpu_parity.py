@@ -277,3 +277,41 @@ def test_full_size_config2_sampled(B, orc):
         else:
             assert (r["seqhash"][rows] == st.seqhash).mean() >= 0.9
             assert _tv(h, h64) <= 2e-3
+
+
+def _absorbing_star():
+    g = workloads.star_graph(5, [0.3, 0.5, 0.2, 0.8, 0.4], [-30.0, 5.0, -60.0, 0.0, -10.0],
+                             [0, -2.0, 0, 0, 0], 1.0, b_center=[0.3, 0.1, 0.3, 0.2, 0.1])
+    g.vtx_kind[2] = 1
+    g.vtx_kind[5] = 1
+    return g
+
+
+@pytest.mark.parametrize("case", ["config2", "absorbing", "config1", "path"])
+def test_fp32_pool_schedule_equals_lane_schedule(B, case):
+    """The wave-pool schedule (particles cycled through lanes, vertex hits
+    resolved in full-width passes) gives the same bits as one particle per
+    lane, for ragged set sizes, unaligned step counts, absorption and the
+    split cap."""
+    if case == "config2":
+        g, M, mode, dt = workloads.config2()[0], 8, 2, 1e-2
+    elif case == "absorbing":
+        g, M, mode, dt = _absorbing_star(), 3, 1, 5e-3
+    elif case == "config1":
+        g, M, mode, dt = workloads.config1()[0], 8, 1, 1e-3
+    else:
+        g, M, mode, dt = workloads.from_edges(3, [0, 2], [1, 1], [0.6, 0.4], sigma=1.0), 8, 2, 1e-3
+    G = B.mg_graph_create(g)
+    for n in (1, 63, 65, 511, 513, 5000):
+        res = []
+        for sched in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS):
+            p = B.mg_particles_init(G, n, mode, vertex=0, init_seed=n, precision=B.MG_FP32,
+                                    max_splits=M, trace=True, schedule=sched)
+            for k in (3, 254, 1, 342):
+                B.mg_simulate(p, k, dt, 77)
+            res.append((B.mg_particles_read(p, trace=True), B.mg_exit_counts(p)))
+        (ra, ca), (rb, cb) = res
+        for f in ("edge", "x", "alive", "seqhash", "hits"):
+            assert np.array_equal(ra[f], rb[f]), (case, n, f)
+        for x, y in zip(ca, cb):
+            assert np.array_equal(x, y), (case, n)
