@@ -84,19 +84,149 @@ def run_pass(B, G, g, run, prec, dt, torch, kernel_times):
                 trunc=int(tot[0]), exit=ex, hist=hist)
 
 
-def cpu_baseline(g, run, n_sample: int):
+def cpu_baseline(g, run, n_sample: int, dt: float = 1e-3):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     st = oracle.init(g, run["n_particles"], oracle.INIT_UNIFORM_LENGTH, seed=0,
                      pids=__import__("numpy").arange(n_sample))
     t0 = time.perf_counter()
-    c = oracle.simulate(g, st, 0, run["n_steps"], 1e-3, run["seed"], threads=threads,
+    c = oracle.simulate(g, st, 0, run["n_steps"], dt, run["seed"], threads=threads,
                         max_splits=run["max_splits"])
-    dt = time.perf_counter() - t0
-    return {"value": c.substeps / dt, "unit": "particle-substeps/s", "cores": threads,
+    el = time.perf_counter() - t0
+    return {"value": c.substeps / el, "unit": "particle-substeps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"particle ids 0..{n_sample - 1} of the same workload at dt=1e-3, "
-                      f"{run['n_steps']} steps, FP64 ({c.substeps} sub-steps in {dt:.2f} s)"}
+            "sample": f"particle ids 0..{n_sample - 1} of the same workload at dt={dt:.3g}, "
+                      f"{run['n_steps']} steps, FP64 ({c.substeps} sub-steps in {el:.2f} s)"}
+
+
+def _tv(a, b):
+    import numpy as np
+    return 0.5 * float(np.abs(a.astype(float) - b.astype(float)).sum()) / max(float(b.sum()), 1.0)
+
+
+def run_vascular(args, B, torch):
+    """Synthetic vascular network (20k vertices, 26k edges, advective drift,
+    absorbing outlets): 1e8 FP32 particles uniform by length, 1e4 steps at
+    ten times the upwind finite-volume CFL limit, 64 bins per edge; FP64
+    beside it under common random numbers."""
+    import numpy as np
+    import workloads
+    g, run = workloads.config3()
+    G = B.mg_graph_create(g)
+    n = run["n_particles"]
+
+    def one(prec, ktimes):
+        p = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=0, precision=prec,
+                                max_splits=run["max_splits"])
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        B.mg_simulate(p, run["n_steps"], run["dt"], run["seed"])
+        e1.record()
+        ex, ab, tot = B.mg_exit_counts(p)
+        h = B.mg_histogram(p, run["bins"])
+        ktimes.append(e0.elapsed_time(e1) * 1e-3)
+        out = dict(substeps=int(tot[1]), hits=int(tot[2]), steps=int(tot[3]), exit=ex,
+                   absorbed=int(ab.sum()), hist=h)
+        del p
+        return out
+
+    for _ in range(args.warmup):
+        one(1, [])
+    torch.cuda.synchronize()
+    kt = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r32 = one(1, kt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = r32["substeps"] * args.steps / wall
+    line = {"metric": METRIC, "value": value, "unit": "particle-substeps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "vascular20k: synthetic microvascular network, 20k vertices, "
+                                   "26k edges, Poiseuille drift, absorbing outlets, 1e8 particles, "
+                                   "1e4 steps of 10x the FVM CFL dt, 64 bins/edge",
+                       "dt": run["dt"], "n_particles": n, "n_steps": run["n_steps"]},
+            "hits_per_step": r32["hits"] / r32["steps"], "absorbed_fraction": r32["absorbed"] / n,
+            "kernel_substeps_per_s": r32["substeps"] / float(np.mean(kt))}
+    if not args.no_fp64:
+        k64 = []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r64 = one(0, k64)
+        torch.cuda.synchronize()
+        w64 = time.perf_counter() - t1
+        line["fp64"] = {"value": r64["substeps"] / w64, "unit": "particle-substeps/s",
+                        "fp32_speedup": value / (r64["substeps"] / w64)}
+        line["tv_fp32_vs_fp64"] = _tv(r32["hist"], r64["hist"])
+        line["exit_prob_err_fp32_vs_fp64"] = float(np.abs(
+            exit_probs(r32["exit"], g.vtx_offsets) - exit_probs(r64["exit"], g.vtx_offsets)).max())
+    achieved = alg_work(1, r32["steps"], r32["hits"]) / float(np.mean(kt))
+    line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                        "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
+                        "traffic": None, "kernel": "k_pool32"}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(g, run, args.cpu_sample, dt=run["dt"])
+    return line
+
+
+def run_batch(args, B, torch):
+    """512 independent uneven graphs (stars and random trees, edges
+    loguniform 3..4096, particles loguniform 1e4..1e6, half with quadratic
+    potentials): one batched launch per call against one launch per graph."""
+    import numpy as np
+    import workloads
+    graphs, counts, run = workloads.config4()
+    Gs = [B.mg_graph_create(g) for g in graphs]
+
+    def make():
+        return [B.mg_particles_init(G, c, B.MG_INIT_UNIFORM_LENGTH, init_seed=i, graph_tag=i,
+                                    precision=B.MG_FP32, max_splits=run["max_splits"])
+                for i, (G, c) in enumerate(zip(Gs, counts))]
+
+    def totals(sets):
+        t = np.zeros(4, np.uint64)
+        for s in sets:
+            t += B.mg_exit_counts(s)[2]
+        return t
+
+    sets = make()
+    batch = B.mg_batch_create(sets)
+    B.mg_batch_simulate(batch, 8, run["dt"], run["seed"])      # warm-up
+    torch.cuda.synchronize()
+    t_before = totals(sets)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.mg_batch_simulate(batch, run["n_steps"], run["dt"], run["seed"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tot = totals(sets) - t_before
+    value = float(tot[1]) / wall
+    # the same work launched graph by graph
+    solo = make()
+    for s in solo:
+        B.mg_simulate(s, 8, run["dt"], run["seed"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in solo:
+        B.mg_simulate(s, run["n_steps"], run["dt"], run["seed"])
+    torch.cuda.synchronize()
+    wall_solo = time.perf_counter() - t1
+    line = {"metric": METRIC, "value": value, "unit": "particle-substeps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": wall / args.steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "batch512: 512 stars/random trees, 3..4096 edges, 1e4..1e6 "
+                                   "particles each, zero drift or quadratic potentials, dt=1e-3, "
+                                   "1000 steps per call, one batched launch",
+                       "n_graphs": len(graphs), "n_particles": int(sum(counts)),
+                       "n_edges": int(sum(g.n_edges for g in graphs))},
+            "unbatched_value": float(tot[1]) / args.steps / wall_solo,
+            "batch_speedup": wall_solo * args.steps / wall,
+            "hits_per_step": float(tot[2]) / float(tot[3])}
+    return line
 
 
 def main():
@@ -107,6 +237,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
     ap.add_argument("--cpu-sample", type=int, default=40_000)
+    ap.add_argument("--workload", default="langevin_star64",
+                    choices=["langevin_star64", "vascular20k", "batch512"],
+                    help="the metric's configuration (default) or another workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -122,6 +255,12 @@ def main():
     from paper_2512_02175_amd import binding as B
 
     torch.cuda.set_device(0)
+    if args.workload == "vascular20k":
+        print(json.dumps(run_vascular(args, B, torch)), flush=True)
+        return
+    if args.workload == "batch512":
+        print(json.dumps(run_batch(args, B, torch)), flush=True)
+        return
     g, run = workloads.config2()
     G = B.mg_graph_create(g)
     dts = run["dts"]

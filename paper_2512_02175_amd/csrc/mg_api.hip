@@ -128,7 +128,7 @@ SetLayout set_layout(int32_t V, int32_t nnz, int64_t n, mg_precision prec, bool 
     return o;
   };
   L.ef = take((size_t)n * 4);
-  L.pos = take((size_t)n * (prec == MG_FP64 ? 8 : 4));
+  L.pos = take((size_t)n * 8);  // double x, or float2 (y, compensation)
   L.hash = trace ? take((size_t)n * 8) : 0;
   L.hits = trace ? take((size_t)n * 4) : 0;
   L.exitc = take((size_t)std::max(nnz, 1) * 8);
@@ -425,7 +425,7 @@ mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
   SetDev &s = p->sd;
   s.ef = (uint32_t *)(base + L.ef);
   s.x64 = o.precision == MG_FP64 ? (double *)(base + L.pos) : nullptr;
-  s.y32 = o.precision == MG_FP32 ? (float *)(base + L.pos) : nullptr;
+  s.y32 = o.precision == MG_FP32 ? (float2 *)(base + L.pos) : nullptr;
   s.seqhash = p->trace ? (uint64_t *)(base + L.hash) : nullptr;
   s.hits = p->trace ? (uint32_t *)(base + L.hits) : nullptr;
   s.exit_cnt = (uint64_t *)(base + L.exitc);
@@ -577,7 +577,7 @@ mg_status mg_particles_read(const mg_particles *p, int64_t first, int64_t count,
   MG_HIP(hipMemcpyAsync(ef.data(), p->sd.ef + first, (size_t)count * 4, hipMemcpyDeviceToHost,
                         p->stream), "copying states");
   std::vector<double> x64;
-  std::vector<float> y32;
+  std::vector<float2> y32;
   if (pos) {
     if (p->prec == MG_FP64) {
       x64.resize(count);
@@ -585,7 +585,7 @@ mg_status mg_particles_read(const mg_particles *p, int64_t first, int64_t count,
                             hipMemcpyDeviceToHost, p->stream), "copying positions");
     } else {
       y32.resize(count);
-      MG_HIP(hipMemcpyAsync(y32.data(), p->sd.y32 + first, (size_t)count * 4,
+      MG_HIP(hipMemcpyAsync(y32.data(), p->sd.y32 + first, (size_t)count * 8,
                             hipMemcpyDeviceToHost, p->stream), "copying positions");
     }
   }
@@ -604,7 +604,7 @@ mg_status mg_particles_read(const mg_particles *p, int64_t first, int64_t count,
       if (p->prec == MG_FP64) {
         pos[i] = x64[i];
       } else {
-        const double y = (double)y32[i];
+        const double y = (double)y32[i].x + (double)y32[i].y;
         pos[i] = (ef[i] & kSideBit) ? p->g->length[e] - y : y;
       }
     }

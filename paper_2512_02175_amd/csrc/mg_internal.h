@@ -80,7 +80,8 @@ struct GraphDev {
 struct SetDev {
   uint32_t *ef;        // [n] state word
   double *x64;         // [n] FP64 position from the initial vertex
-  float *y32;          // [n] FP32 distance from the reference end
+  float2 *y32;         // [n] FP32 distance from the reference end and its
+                       //     compensation term (value = x + y)
   uint64_t *seqhash;   // [n] or null
   uint32_t *hits;      // [n] or null
   uint64_t *exit_cnt;  // [nnz]
@@ -109,7 +110,10 @@ struct BatchItem {
 };
 
 constexpr int kBlock = 256;
-constexpr int kPoolPerWave = 128;                       // FP32 wave pools
+#ifndef MG_POOL_PER_WAVE
+#define MG_POOL_PER_WAVE 128
+#endif
+constexpr int kPoolPerWave = MG_POOL_PER_WAVE;          // FP32 wave pools (<= 256)
 constexpr int kPoolPerBlock = kPoolPerWave * (kBlock / 64);
 constexpr int kLdsExitMax = 16384;  // slots counted in LDS (64 KiB of u32)
 constexpr int kLdsStageMax = 24576; // graph tables staged in LDS up to this size

@@ -264,17 +264,22 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
 #pragma unroll
     for (uint32_t j = 0; j < NW; ++j) {
       if (j < jb || j >= je || pj >= 0) continue;
-      if (!q.fast(W[j])) pj = (int32_t)j;
+      if (!q.fast(W[j]))
+        pj = (int32_t)j;
+      else if ((j & 3u) == 3u)
+        q.reanchor();
     }
     while (pj >= 0) {
       const uint32_t j0 = (uint32_t)pj;
       q.resolve(base + j0, pickw(W, j0), pid, S, A, t);
+      if ((j0 & 3u) == 3u && q.alive) q.reanchor();
       pj = -1;
       for (uint32_t j = j0 + 1; j < je && q.alive; ++j) {
         if (!q.fast(pickw(W, j))) {
           pj = (int32_t)j;
           break;
         }
+        if ((j & 3u) == 3u) q.reanchor();
       }
     }
     n = base + je;
@@ -303,6 +308,9 @@ struct Particle64 {
   __device__ static void box_muller(uint32_t a, uint32_t b, double &c, double &s) {
     box_muller64(a, b, c, s);
   }
+
+  // FP64 positions are always measured from the initial vertex.
+  __device__ __forceinline__ void reanchor() {}
 
   __device__ __forceinline__ bool fast(double w) {
     if (x == 0.0)
@@ -406,12 +414,18 @@ __device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const St
 
 // ------------------------------------------------------------ FP32 path --
 // Same step; the position is y = distance from the reference end (bit 30
-// of the state word), re-anchored to the nearer end after every interior
-// move, so points near a vertex keep full relative precision.  In that
+// of the state word).  The reference end is re-chosen as the nearer end
+// after every step that closes a Philox group (step index = 3 mod 4, in
+// every schedule alike), so points near a vertex keep full relative
+// precision.  In that
 // frame the drift is as + c y with as = a (from the initial end) or
 // -(a + c L) (from the terminal end), and the normal's sign flips with the
-// end.  The remaining time is a compensated pair (hh, hl); the crossing
-// solve runs in FP64 within 1e-6 L of a vertex.
+// end.  The position is a compensated pair (y, yl): each move adds its
+// increment, computed at the increment's own magnitude, with the rounding
+// error of the sum carried in yl (Fast2Sum, Dekker), so positions do not
+// collect one rounding of y per step.  The remaining time is a compensated
+// pair (hh, hl) too; the crossing solve runs in FP64 within 1e-6 L of a
+// vertex.
 struct Edge32 {
   float L, a, c, sigma, aL;
   int32_t vinit, vterm;
@@ -429,7 +443,7 @@ struct Particle32 {
   uint32_t *s_exit;
   int32_t e;
   uint32_t side;
-  float y;
+  float y, yl;    // distance from the reference end, compensation term
   Edge32 R;
   float as, g0;   // drift constant in the local frame, sigma sqrt(dt)
   float dt, sqdt;
@@ -442,11 +456,21 @@ struct Particle32 {
     box_muller32(a, b, c, s);
   }
 
-  // Re-anchor to the nearer end: L - yt is exact for yt in [L/2, L)
-  // (Sterbenz), so the move loses nothing.
-  __device__ __forceinline__ void settle(float yt) {
-    const bool flip = yt > 0.5f * R.L;
-    y = flip ? R.L - yt : yt;
+  // y + s as a compensated sum (Fast2Sum: exact error when |y| >= |s|,
+  // a bounded one otherwise, which happens only within one step of the
+  // reference end): returns the rounded sum, err its error.
+  __device__ __forceinline__ float add_comp(float s, float &err) const {
+    const float yt = y + s;
+    err = s - (yt - y);
+    return yt;
+  }
+
+  // Re-anchor to the nearer end: L - y is exact for y in [L/2, L)
+  // (Sterbenz), so the move loses nothing; the compensation flips sign.
+  __device__ __forceinline__ void reanchor() {
+    const bool flip = y > 0.5f * R.L;
+    y = flip ? R.L - y : y;
+    yl = flip ? -yl : yl;
     side ^= flip ? 1u : 0u;
     as = side ? -R.aL : R.a;
   }
@@ -454,9 +478,11 @@ struct Particle32 {
   __device__ __forceinline__ bool fast(float w) {
     const float we = (y == 0.0f) ? fabsf(w) : (side ? -w : w);
     const float mu = fmaf(R.c, y, as);
-    const float yt = fmaf(g0, we, fmaf(mu, dt, y));
+    float err;
+    const float yt = add_comp(fmaf(g0, we, mu * dt) + yl, err);
     if (yt > 0.0f && yt < R.L) {
-      settle(yt);
+      y = yt;
+      yl = err;
       return true;
     }
     return false;
@@ -467,14 +493,12 @@ struct Particle32 {
   __device__ __forceinline__ bool fast_pred(float w, bool active) {
     const float we = (y == 0.0f) ? fabsf(w) : (side ? -w : w);
     const float mu = fmaf(R.c, y, as);
-    const float yt = fmaf(g0, we, fmaf(mu, dt, y));
+    float err;
+    const float yt = add_comp(fmaf(g0, we, mu * dt) + yl, err);
     const bool in = (yt > 0.0f) & (yt < R.L);
     const bool upd = active & in;
-    const bool flip = yt > 0.5f * R.L;
-    const float ys = flip ? R.L - yt : yt;
-    y = upd ? ys : y;
-    side = upd ? (side ^ (flip ? 1u : 0u)) : side;
-    as = side ? -R.aL : R.a;
+    y = upd ? yt : y;
+    yl = upd ? err : yl;
     return in;
   }
 
@@ -487,17 +511,20 @@ struct Particle32 {
       const float we = (y == 0.0f) ? fabsf(w) : (side ? -w : w);
       const float mu = fmaf(R.c, y, as);
       const float g = first ? g0 : R.sigma * __builtin_amdgcn_sqrtf(hh);
-      const float yt = fmaf(g, we, fmaf(mu, hh, y));
+      float err;
+      const float yt = add_comp(fmaf(g, we, mu * hh) + yl, err);
       if (!first) t.sub++;
       first = false;
       if (yt > 0.0f && yt < R.L) {
-        settle(yt);
+        y = yt;
+        yl = err;
         break;
       }
       const bool near = yt <= 0.0f;
       const bool at_term = near == (side != 0u);
       const int32_t v = at_term ? R.vterm : R.vinit;
-      const float d = near ? y : R.L - y;
+      const float dn = y + yl;
+      const float d = fmaxf(near ? dn : (R.L - y) - yl, 0.0f);
       float u;
       if (d < 1e-6f * R.L) {
         // crossing solve in FP64 next to the vertex
@@ -506,7 +533,8 @@ struct Particle32 {
         const double gd = (double)R.sigma * sqrt(hd);
         const double qa = near ? mud * hd : -(mud * hd);
         const double qb = near ? gd * (double)we : -(gd * (double)we);
-        const double dd = near ? (double)y : (double)R.L - (double)y;
+        const double yd = (double)y + (double)yl;
+        const double dd = fmax(near ? yd : (double)R.L - yd, 0.0);
         u = (float)first_root64(qa, qb, dd);
       } else {
         const float mh = mu * hh, gw = g * we;
@@ -543,6 +571,7 @@ struct Particle32 {
       R = load_edge32(G.e32, e);
       side = sp.eo & 1u;
       y = 0.0f;
+      yl = 0.0f;
       as = side ? -R.aL : R.a;
       g0 = R.sigma * sqdt;
       last = s;
@@ -571,7 +600,8 @@ __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const St
   const float sqdt = (float)sqrt(A.dt);
   const Edge32 R = load_edge32(G.e32, e);
   const uint32_t side = (ef & kSideBit) ? 1u : 0u;
-  Particle32<TRACE, LDS> q{G, s_exit, e, side, S.y32[pid], R,
+  const float2 yy = S.y32[pid];
+  Particle32<TRACE, LDS> q{G, s_exit, e, side, yy.x, yy.y, R,
                            side ? -R.aL : R.a, R.sigma * sqdt, (float)A.dt, sqdt, true,
                            TRACE ? S.seqhash[pid] : 0ull, TRACE ? S.hits[pid] : 0u, 0u};
   if (!(q.y >= 0.0f && q.y <= R.L)) {
@@ -580,7 +610,7 @@ __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const St
   }
   step_loop<NG>(q, S, A, pid, t);
   S.ef[pid] = (uint32_t)q.e | (q.side ? kSideBit : 0u) | (q.alive ? 0u : kDeadBit);
-  S.y32[pid] = q.y;
+  S.y32[pid] = make_float2(q.y, q.yl);
   if (TRACE) {
     S.seqhash[pid] = q.hash;
     S.hits[pid] = q.nhit;
@@ -687,11 +717,14 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
 // results equal the plain per-particle order bit for bit.  Waves never wait
 // for one another: the stacks and their counts are private to a wave.
 constexpr int kWavesPerBlock = kBlock / 64;
+static_assert(kPoolPerWave % 64 == 0 && kPoolPerWave >= 128 && kPoolPerWave <= 256,
+              "a wave pool holds 2 to 4 particles per lane");
 constexpr int kIdleTrigger = 8;  // idle lanes that trigger a partial split pass
 
 struct PoolLds32 {
   uint32_t ef[kPoolPerWave];
   float y[kPoolPerWave];
+  float yl[kPoolPerWave];
   uint32_t n[kPoolPerWave];   // next step (ready) or the step to resolve (parked)
   float w[kPoolPerWave];      // first sub-step normal of a parked step
   uint32_t hits[kPoolPerWave];
@@ -717,6 +750,7 @@ __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolL
   q.e = (int32_t)(ef & kEdgeMask);
   q.side = (ef & kSideBit) ? 1u : 0u;
   q.y = P.y[s];
+  q.yl = P.yl[s];
   q.R = load_edge32(q.G.e32, q.e);
   q.as = q.side ? -q.R.aL : q.R.a;
   q.g0 = q.R.sigma * q.sqdt;
@@ -732,6 +766,7 @@ __device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS> &q, Pool
                                            uint32_t s, uint32_t n) {
   P.ef[s] = (uint32_t)q.e | (q.side ? kSideBit : 0u);
   P.y[s] = q.y;
+  P.yl[s] = q.yl;
   P.n[s] = n;
   if (TRACE) {
     P.hits[s] = q.nhit;
@@ -743,7 +778,7 @@ template <bool TRACE, bool LDS>
 __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS> &q, const SetDev &S,
                                             const StepArgs &A, uint32_t pid, Tally &t) {
   S.ef[pid] = (uint32_t)q.e | (q.side ? kSideBit : 0u) | (q.alive ? 0u : kDeadBit);
-  S.y32[pid] = q.y;
+  S.y32[pid] = make_float2(q.y, q.yl);
   if (TRACE) {
     S.seqhash[pid] = q.hash;
     S.hits[pid] = q.nhit;
@@ -761,23 +796,25 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   const float dt = (float)A.dt;
   const float sqdt = (float)sqrt(A.dt);
   const uint32_t n_end = S.n0 + A.nsteps;
-  Particle32<TRACE, LDS> q{G, s_exit, 0, 0u, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
+  Particle32<TRACE, LDS> q{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
                            true, 0ull, 0u, 0u};
   bool has = false;
   uint32_t slot = 0, n = 0;
   uint32_t ready_cnt = 0, split_cnt = 0;
 
-  // Initial placement: slot `lane` rides in the lane, slot 64 + lane waits.
+  // Initial placement: slot `lane` rides in the lane, slots 64k + lane wait.
 #pragma unroll
-  for (uint32_t half = 0; half < 2; ++half) {
+  for (uint32_t half = 0; half < (uint32_t)kPoolPerWave / 64u; ++half) {
     const uint32_t s = lane + 64u * half;
     const uint32_t pid = base + s;
     bool ok = false;
     uint32_t ef = 0;
-    float y = 0.0f;
+    float y = 0.0f, yl = 0.0f;
     if (pid < S.n) {
       ef = S.ef[pid];
-      y = S.y32[pid];
+      const float2 yy = S.y32[pid];
+      y = yy.x;
+      yl = yy.y;
       const int32_t e = (int32_t)(ef & kEdgeMask);
       if (!(ef & kDeadBit)) {
         if (e >= n_edges) {
@@ -793,6 +830,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       if (ok) {
         P.ef[s] = ef;
         P.y[s] = y;
+        P.yl[s] = yl;
         if (TRACE) {
           P.hits[s] = S.hits[pid];
           P.hash[s] = S.seqhash[pid];
@@ -808,6 +846,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       if (ok) {
         P.ef[s] = ef;
         P.y[s] = y;
+        P.yl[s] = yl;
         P.n[s] = S.n0;
         if (TRACE) {
           P.hits[s] = S.hits[pid];
@@ -864,6 +903,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
           parked = true;
           n = (m << 2) + (uint32_t)pj;
         } else {
+          if (je == 4u) q.reanchor();  // the group's last step completed
           n = (m << 2) + je;
         }
         if (!parked && n == n_end) {
@@ -896,11 +936,12 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       uint32_t s2 = 0;
       if (lane < B) {
         s2 = P.split[split_cnt + lane];
-        Particle32<TRACE, LDS> q2{G, s_exit, 0, 0u, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
-                                  true, 0ull, 0u, 0u};
+        Particle32<TRACE, LDS> q2{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt,
+                                  sqdt, true, 0ull, 0u, 0u};
         pool_load(q2, P, s2);
         const uint32_t step = P.n[s2];
         q2.resolve(step, P.w[s2], base + s2, S, A, t);
+        if ((step & 3u) == 3u && q2.alive) q2.reanchor();
         const uint32_t n2 = step + 1u;
         if (!q2.alive || n2 == n_end) {
           pool_finish(q2, S, A, base + s2, t);
@@ -1006,8 +1047,10 @@ __global__ __launch_bounds__(kBlock) void k_init(GraphDev G, SetDev S, int mode,
     S.x64[pid] = x;
   } else {
     const bool side = x > 0.5 * L;
+    const double yd = side ? L - x : x;
+    const float yh = (float)yd;
     S.ef[pid] = (uint32_t)e | (side ? kSideBit : 0u);
-    S.y32[pid] = (float)(side ? L - x : x);
+    S.y32[pid] = make_float2(yh, (float)(yd - (double)yh));
   }
   if (S.seqhash) S.seqhash[pid] = 0xcbf29ce484222325ull;
   if (S.hits) S.hits[pid] = 0;
@@ -1033,7 +1076,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(GraphDev G, SetDev S, int32_t n
     if (FP64) {
       x = S.x64[pid];
     } else {
-      const double y = (double)S.y32[pid];
+      const float2 yy = S.y32[pid];
+      const double y = (double)yy.x + (double)yy.y;
       x = (ef & kSideBit) ? L - y : y;
     }
     const double inv = (double)nb / L;

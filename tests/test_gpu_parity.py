@@ -315,3 +315,46 @@ def test_fp32_pool_schedule_equals_lane_schedule(B, case):
             assert np.array_equal(ra[f], rb[f]), (case, n, f)
         for x, y in zip(ca, cb):
             assert np.array_equal(x, y), (case, n)
+
+
+def test_vascular_network_fp64_parity_and_fp32(B, orc):
+    """Config 3's synthetic vascular network (cycles, advective drift,
+    absorbing outlets): FP64 element by element against the oracle on 20k
+    particles, FP32 against FP64 under common random numbers.  No closed form
+    exists for this network; the oracle's arithmetic is pinned elsewhere."""
+    g, run = workloads.config3()
+    dt = 10 * run["dt"]        # more vertex traffic per step than the benchmark
+    n, steps = 20_000, 1500
+    st, c = _oracle_run(orc, g, n, 2, steps, dt, 13, init_seed=3)
+    assert c.absorbed.sum() > 0 and c.hits > 0
+    G, p = _gpu_run(B, g, n, 2, steps, dt, 13, init_seed=3)
+    r = B.mg_particles_read(p, trace=True)
+    diff = _compare_fp64(st, r)
+    ex, ab, tot = B.mg_exit_counts(p)
+    nd = int(diff.sum())
+    assert np.abs(ab.astype(np.int64) - c.absorbed.astype(np.int64)).sum() <= nd
+    G, p32 = _gpu_run(B, g, n, 2, steps, dt, 13, init_seed=3, precision=1, G=G)
+    r32 = B.mg_particles_read(p32, trace=True)
+    assert (r32["seqhash"] == st.seqhash).mean() > 0.99
+    assert _tv(B.mg_histogram(p32, 64), orc.histogram(g, st, 64)) <= 2e-3
+
+
+def test_config4_batch_sample_against_oracle(B, orc):
+    """A slice of config 4's 512 uneven graphs (stars and random trees, with
+    and without quadratic potentials) advanced in one batched launch per
+    chunk; sampled particles of several members against the oracle, FP64."""
+    graphs, counts, run = workloads.config4()
+    pick = [0, 1, 2, 3, 100, 101, 510, 511]
+    sets = []
+    for i in pick:
+        G = B.mg_graph_create(graphs[i])
+        sets.append(B.mg_particles_init(G, min(counts[i], 3000), 2, init_seed=i, graph_tag=i,
+                                        trace=True))
+    b = B.mg_batch_create(sets)
+    B.mg_batch_simulate(b, 300, run["dt"], 5)
+    for i, s in zip(pick, sets):
+        n = s.n
+        rows = np.arange(0, n, max(1, n // 200))
+        st = orc.init(graphs[i], n, 2, seed=i, tag=i, pids=rows)
+        orc.simulate(graphs[i], st, 0, 300, run["dt"], 5, tag=i)
+        _compare_fp64(st, B.mg_particles_read(s, trace=True), rows=rows, min_frac=1.0)
