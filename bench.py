@@ -31,7 +31,7 @@ PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 
 # Algorithmic VALU operations of the method per unit of work: the minimal
 # gfx950 instruction sequence, counted once per operation whatever its rate.
-# Derivation in DESIGN.md ("Roofline").
+# The counts are per operation of the step, whatever the instruction's rate.
 ALG_FP32_STEP = 32.5     # per particle-step: 1/4 Philox + 1/2 Box-Muller pair + EM
 ALG_FP32_HIT = 80.0      # per vertex hit: Philox, one normal, root, time, slot, edge
 ALG_FP64_STEP = 62.5
@@ -229,6 +229,133 @@ def run_batch(args, B, torch):
     return line
 
 
+def run_sweep(args, B, torch):
+    """Batched FP32 vs FP64 over dt: the vascular network and 128 Langevin
+    stars in one batch per precision and dt, over fixed horizons.  Reports
+    per dt the throughput of both precisions, the largest histogram TV
+    between them (same random integers), and how far the exit probabilities
+    are from the jump probabilities b (Corollary 1: they converge as dt -> 0),
+    weighted by the exits each vertex records."""
+    import numpy as np
+    import workloads
+    graphs, counts, run = workloads.config5()
+    Gs = [B.mg_graph_create(g) for g in graphs]
+    rows = []
+    sub32_total = wall32_total = 0.0
+    for dt in run["dts"]:
+        res = {}
+        for prec in (B.MG_FP32, B.MG_FP64):
+            sets = [B.mg_particles_init(G, c, B.MG_INIT_UNIFORM_LENGTH, init_seed=i,
+                                        graph_tag=i, precision=prec,
+                                        max_splits=run["max_splits"])
+                    for i, (G, c) in enumerate(zip(Gs, counts))]
+            steps = [max(1, int(round(T / dt))) for T in run["horizons"]]
+            batch_net = B.mg_batch_create(sets[:1])
+            batch_st = B.mg_batch_create(sets[1:])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.mg_batch_simulate(batch_net, steps[0], dt, run["seed"])
+            B.mg_batch_simulate(batch_st, steps[1], dt, run["seed"])
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            sub = 0
+            hists, exits = [], []
+            for s_, nb in zip(sets, run["bins"]):
+                ex, ab, tot = B.mg_exit_counts(s_)
+                sub += int(tot[1])
+                exits.append(ex)
+                hists.append(B.mg_histogram(s_, nb))
+            res[prec] = dict(wall=wall, sub=sub, hists=hists, exits=exits)
+            del batch_net, batch_st, sets
+        tv = max(_tv(a, b) for a, b in zip(res[B.MG_FP32]["hists"], res[B.MG_FP64]["hists"]))
+        ee = max(float(np.abs(exit_probs(a, g.vtx_offsets) - exit_probs(b, g.vtx_offsets)).max())
+                 for a, b, g in zip(res[B.MG_FP32]["exits"], res[B.MG_FP64]["exits"], graphs))
+        # distance of the FP64 exit law from b, per vertex weighted by exits
+        dev = {}
+        for name, idx in (("network", [0]), ("stars", list(range(1, len(graphs))))):
+            num = den = 0.0
+            for i in idx:
+                g, ex = graphs[i], res[B.MG_FP64]["exits"][i]
+                pr = exit_probs(ex, g.vtx_offsets)
+                for v in range(g.n_vertices):
+                    s0, s1 = g.vtx_offsets[v], g.vtx_offsets[v + 1]
+                    tot_v = float(ex[s0:s1].sum())
+                    if s1 - s0 < 2 or tot_v == 0:
+                        continue
+                    num += tot_v * 0.5 * float(np.abs(pr[s0:s1] - g.slot_jump_prob[s0:s1]).sum())
+                    den += tot_v
+            dev[name] = num / den if den else None
+        r32, r64 = res[B.MG_FP32], res[B.MG_FP64]
+        sub32_total += r32["sub"]
+        wall32_total += r32["wall"]
+        rows.append({"dt": dt, "fp32_substeps_per_s": r32["sub"] / r32["wall"],
+                     "fp64_substeps_per_s": r64["sub"] / r64["wall"],
+                     "tv_fp32_vs_fp64_max": tv, "exit_prob_err_fp32_vs_fp64_max": ee,
+                     "exit_law_tv_from_b_network": dev["network"],
+                     "exit_law_tv_from_b_stars": dev["stars"]})
+    return {"metric": METRIC, "value": sub32_total / wall32_total, "unit": "particle-substeps/s",
+            "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": wall32_total * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "accuracy_sweep: vascular20k + 128 Langevin stars, one batch "
+                                   "per precision and dt, dt in {1e-2,3e-3,1e-3,3e-4}, horizons "
+                                   "0.05 (network) and 2 (stars), 1e8 + 1e8 particles per dt"},
+            "per_dt": rows}
+
+
+def run_density(args, B, torch):
+    """The paper's accuracy experiment (Sec. 4.1, Fig. "error"): the 5-edge
+    star with the linear (mu_i = -10 i) and quadratic (mu_i = -10 i x)
+    potentials, b = 1/5, sigma = 1, edges truncated to length 2 with
+    reflecting leaves.  Particles start on the vertex, burn in for 0.5 time
+    units, then the streamed histogram takes a snapshot every 0.01 time units
+    for 2 time units (inside the step kernels).  Reported per potential, dt
+    and particle count: the empirical L2 error of the time-averaged density
+    against the closed-form stationary density (100 bins per edge) and the
+    FP32 throughput of the whole run."""
+    import numpy as np
+    import workloads
+    from workloads import stationary
+    bins, burn_t, obs_t, gap_t = 100, 0.5, 2.0, 0.01
+    rows = []
+    sub_total = wall_total = 0.0
+    for pot in ("linear", "quadratic"):
+        g = workloads.paper_star5(pot)
+        G = B.mg_graph_create(g)
+        ref = stationary.star_bin_means(g, bins)
+        for dt in (1e-2, 1e-3, 1e-4):
+            for n in (10_000, 100_000, 1_000_000, 10_000_000):
+                p = B.mg_particles_init(G, n, B.MG_INIT_AT_VERTEX, vertex=0, init_seed=1,
+                                        precision=B.MG_FP32)
+                burn = int(round(burn_t / dt))
+                every = max(1, int(round(gap_t / dt)))
+                steps = int(round(obs_t / dt))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                B.mg_simulate(p, burn, dt, 11)
+                B.mg_observe_histogram(p, bins, every)
+                B.mg_simulate(p, steps, dt, 12)
+                h, snaps = B.mg_observed_histogram(p)
+                wall = time.perf_counter() - t0
+                tot = B.mg_exit_counts(p)[2]
+                l2 = B.mg_density_l2(G, bins, h, ref)
+                sub_total += float(tot[1])
+                wall_total += wall
+                rows.append({"potential": pot, "dt": dt, "particles": n, "snapshots": snaps,
+                             "l2_error": l2, "substeps_per_s": float(tot[1]) / wall,
+                             "hits_per_step": float(tot[2]) / float(tot[3])})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+                del p
+    return {"metric": METRIC, "value": sub_total / wall_total, "unit": "particle-substeps/s",
+            "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": wall_total * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "paper_star5 density error: linear and quadratic "
+                                   "potentials, dt in {1e-2,1e-3,1e-4}, 1e4..1e7 particles, "
+                                   "burn-in 0.5, snapshots every 0.01 for 2.0, 100 bins/edge"},
+            "runs": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,7 +365,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
     ap.add_argument("--cpu-sample", type=int, default=40_000)
     ap.add_argument("--workload", default="langevin_star64",
-                    choices=["langevin_star64", "vascular20k", "batch512"],
+                    choices=["langevin_star64", "vascular20k", "batch512", "accuracy_sweep",
+                             "density_error"],
                     help="the metric's configuration (default) or another workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -260,6 +388,12 @@ def main():
         return
     if args.workload == "batch512":
         print(json.dumps(run_batch(args, B, torch)), flush=True)
+        return
+    if args.workload == "accuracy_sweep":
+        print(json.dumps(run_sweep(args, B, torch)), flush=True)
+        return
+    if args.workload == "density_error":
+        print(json.dumps(run_density(args, B, torch)), flush=True)
         return
     g, run = workloads.config2()
     G = B.mg_graph_create(g)

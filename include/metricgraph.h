@@ -171,6 +171,42 @@ mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge,
                        uint64_t *out, int64_t out_len);
 
 /*
+ * Streamed (time-averaged) histogram, accumulated inside the step kernels.
+ * After this call, whenever a step brings the set's step counter to a
+ * multiple of `every` (1 <= every <= 2^30), every alive particle adds one
+ * count to its bin (binning as in mg_histogram, bins_per_edge per edge) in
+ * an accumulator of E * bins_per_edge u64 counters owned by the set.  The
+ * sum over a run approximates the time integral of the density (the
+ * stationary density after burn-in, Sec. 4.1's error measurement).  The
+ * accumulator starts at zero; calling again discards it and starts a new
+ * one; every = 0 turns streaming off.  Allocates device memory for the
+ * accumulator (outside any arena); synchronises the stream.  Batched sets
+ * stream too.
+ */
+mg_status mg_observe_histogram(mg_particles *p, int32_t bins_per_edge, int32_t every);
+
+/*
+ * Reads the accumulator into out[E * bins_per_edge] (out may be NULL) and
+ * the number of snapshots taken so far into *n_snapshots (may be NULL).
+ * MG_ESTATE if streaming is off.  Synchronises the stream.
+ */
+mg_status mg_observed_histogram(const mg_particles *p, uint64_t *out, int64_t out_len,
+                                int64_t *n_snapshots);
+
+/*
+ * Empirical L2 distance between the density a histogram estimates and a
+ * reference density (the error measure of Sec. 4.1, Fig. "error"):
+ *   l2 = sqrt( sum_e sum_k w_e (c_ek / (mass w_e) - ref_ek)^2 ),
+ * with w_e = L_e / bins_per_edge the bin width on edge e, c the counts
+ * (E * bins_per_edge, edge-major) and ref the reference density averaged
+ * over each bin.  mass = 0 takes mass = sum of the counts (the estimate then
+ * has total mass 1).  counts and ref_density may be host or device memory.
+ * Runs on the host in FP64 with compensated summation.
+ */
+mg_status mg_density_l2(const mg_graph *g, int32_t bins_per_edge, const uint64_t *counts,
+                        double mass, const double *ref_density, double *l2);
+
+/*
  * Accumulated counters (Corollary 1 exit edges): slot_counts[nnz] counts,
  * per slot, the steps whose last vertex hit drew that slot (alive
  * particles); absorbed[V] the particles removed at each vertex;
@@ -205,6 +241,29 @@ int64_t mg_particles_step(const mg_particles *p);
 mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **out);
 mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t seed);
 void mg_batch_destroy(mg_batch *b);
+
+/*
+ * Autotuning of an FP32 set's kernel schedule.  The candidates (one
+ * particle per lane; wave pools with partial split passes at 4, 8, 16 or 32
+ * idle lanes) all give identical results, so tuning changes only speed.
+ * Each candidate advances a scratch copy of the set's first
+ * min(n, 2^21) particles by probe_steps steps (<= 0: 32) of size dt with
+ * Philox key seed, timed with HIP events on the set's stream; the set
+ * keeps the fastest for its later mg_simulate calls at this dt.  Sets
+ * created with schedule MG_SCHED_AUTO are tuned this way on their first
+ * mg_simulate at each dt.  FP64 sets have nothing to tune (schedule lanes).
+ * `out` (may be NULL) receives the choice and the probe times.  Allocates
+ * scratch device memory for the probe; synchronises the stream.
+ */
+typedef struct {
+  int32_t schedule;      /* MG_SCHED_LANES or MG_SCHED_POOLS */
+  int32_t idle_trigger;  /* pools: idle lanes that start a partial split pass */
+  int32_t n_probes;      /* entries used in probe_ms */
+  float probe_ms[8];     /* lanes, pools@4, pools@8, pools@16, pools@32 */
+} mg_tuning;
+
+mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_steps,
+                      mg_tuning *out);
 
 /* Description of the calling thread's last error ("" if none). */
 const char *mg_last_error(void);

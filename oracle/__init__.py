@@ -278,3 +278,43 @@ def histogram(g, st: State, bins: int) -> np.ndarray:
     lib().or_histogram(g.ref, st.pid.size, _ptr(st.edge), _ptr(st.x), _ptr(st.alive),
                        bins, _ptr(out))
     return out.reshape(g.E, bins)
+
+
+def observed_histogram(g, st: State, n0: int, n_steps: int, dt: float, seed: int,
+                       every: int, bins: int, *, tag: int = 0, max_splits: int = 8,
+                       counts: Counts | None = None):
+    """Streamed (time-summed) histogram, by its definition: advance the rows
+    of ``st`` through steps [n0, n0+n_steps) and, each time the step counter
+    reaches a multiple of ``every``, add the snapshot histogram of the alive
+    particles (the binning of ``histogram``).  The time average of these
+    snapshots estimates the stationary density after burn-in (Sec. 4.1's
+    density measurement).  Returns (sum of snapshots [E, bins], number of
+    snapshots, counts)."""
+    g = as_graph(g)
+    if counts is None:
+        counts = new_counts(g)
+    acc = np.zeros((g.E, bins), np.uint64)
+    snaps = 0
+    n, end = n0, n0 + n_steps
+    while n < end:
+        nxt = min(end, (n // every + 1) * every)
+        simulate(g, st, n, nxt - n, dt, seed, tag=tag, max_splits=max_splits, counts=counts)
+        n = nxt
+        if n % every == 0:
+            acc += histogram(g, st, bins)
+            snaps += 1
+    return acc, snaps, counts
+
+
+def density_l2(lengths, bins: int, counts, ref_density, mass: float = 0.0) -> float:
+    """Empirical L2 distance between the density that binned counts estimate
+    and a reference density given as bin averages (Sec. 4.1, Fig. "error"):
+    the estimate on bin k of edge e is c_ek / (mass w_e) with bin width
+    w_e = L_e / bins (mass 0: the total count), and the distance is
+    sqrt(sum_e sum_k w_e (estimate - reference)^2)."""
+    L = np.asarray(lengths, np.float64)
+    c = np.asarray(counts, np.float64).reshape(L.size, bins)
+    r = np.asarray(ref_density, np.float64).reshape(L.size, bins)
+    total = float(mass) if mass > 0 else float(np.asarray(counts, np.uint64).sum())
+    w = (L / bins)[:, None]
+    return float(np.sqrt(np.sum(w * (c / (total * w) - r) ** 2)))

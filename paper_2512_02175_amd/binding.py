@@ -26,7 +26,8 @@ EXPORTED = (
     "mg_graph_create", "mg_graph_destroy", "mg_particles_arena_bytes",
     "mg_particles_init", "mg_particles_destroy", "mg_simulate", "mg_histogram",
     "mg_exit_counts", "mg_particles_read", "mg_particles_step", "mg_batch_create",
-    "mg_batch_simulate", "mg_batch_destroy", "mg_last_error",
+    "mg_batch_simulate", "mg_batch_destroy", "mg_autotune", "mg_observe_histogram",
+    "mg_observed_histogram", "mg_density_l2", "mg_last_error",
 )
 
 
@@ -52,6 +53,11 @@ class mg_options(C.Structure):
                 ("steps_per_launch", C.c_int32), ("hip_stream", C.c_void_p),
                 ("arena", C.c_void_p), ("arena_bytes", C.c_int64),
                 ("schedule", C.c_int32)]
+
+
+class mg_tuning(C.Structure):
+    _fields_ = [("schedule", C.c_int32), ("idle_trigger", C.c_int32),
+                ("n_probes", C.c_int32), ("probe_ms", C.c_float * 8)]
 
 
 _lib = None
@@ -84,6 +90,10 @@ def lib() -> C.CDLL:
         L.mg_batch_simulate.argtypes = [vp, i64, C.c_double, u64]
         L.mg_batch_destroy.argtypes = [vp]
         L.mg_batch_destroy.restype = None
+        L.mg_autotune.argtypes = [vp, C.c_double, u64, i32, vp]
+        L.mg_observe_histogram.argtypes = [vp, i32, i32]
+        L.mg_observed_histogram.argtypes = [vp, vp, i64, vp]
+        L.mg_density_l2.argtypes = [vp, i32, vp, C.c_double, vp, vp]
         L.mg_last_error.restype = C.c_char_p
         for name in EXPORTED:
             if name not in ("mg_graph_destroy", "mg_particles_destroy",
@@ -254,6 +264,39 @@ def mg_histogram(p: Particles, bins_per_edge: int, out=None):
     return out
 
 
+def mg_observe_histogram(p: Particles, bins_per_edge: int, every: int) -> None:
+    """Starts (or restarts, or with every=0 stops) the streamed histogram:
+    a snapshot of the alive particles' bins whenever the step counter
+    reaches a multiple of ``every``."""
+    _check(lib().mg_observe_histogram(p.handle, int(bins_per_edge), int(every)))
+    p.obs_bins = int(bins_per_edge) if every else 0
+
+
+def mg_observed_histogram(p: Particles):
+    """(counts as a [E, bins] uint64 array, number of snapshots)."""
+    nb = getattr(p, "obs_bins", 0)
+    E = p.graph.n_edges
+    out = np.zeros(max(E * nb, 1), np.uint64)
+    ns = C.c_int64()
+    _check(lib().mg_observed_histogram(p.handle, _p(out) if nb else None, out.size,
+                                       C.byref(ns)))
+    return out[: E * nb].reshape(E, nb), int(ns.value)
+
+
+def mg_density_l2(g: Graph, bins_per_edge: int, counts, ref_density, mass: float = 0.0) -> float:
+    """Empirical L2 distance between the density the counts estimate and the
+    bin-averaged reference density (both [E, bins] or flat, edge-major)."""
+    c = np.ascontiguousarray(np.asarray(counts, np.uint64).ravel())
+    r = np.ascontiguousarray(np.asarray(ref_density, np.float64).ravel())
+    n = g.n_edges * int(bins_per_edge)
+    if c.size != n or r.size != n:
+        raise ValueError(f"need {n} counts and reference values")
+    out = C.c_double()
+    _check(lib().mg_density_l2(g.handle, int(bins_per_edge), _p(c), float(mass), _p(r),
+                               C.byref(out)))
+    return float(out.value)
+
+
 def mg_exit_counts(p: Particles):
     """(slot_counts[nnz], absorbed[V], totals[4]) with totals =
     (truncations, sub-steps, vertex hits, particle-steps)."""
@@ -298,3 +341,13 @@ def mg_batch_destroy(b: Batch) -> None:
     if b.handle:
         lib().mg_batch_destroy(b.handle)
         b.handle = None
+
+
+def mg_autotune(p: Particles, dt: float, seed: int = 0, probe_steps: int = 0) -> dict:
+    """Times the FP32 schedules on a scratch copy of the set and keeps the
+    fastest; returns the choice and the probe times (ms)."""
+    t = mg_tuning()
+    _check(lib().mg_autotune(p.handle, float(dt), C.c_uint64(seed), int(probe_steps),
+                             C.byref(t)))
+    return dict(schedule=int(t.schedule), idle_trigger=int(t.idle_trigger),
+                n_probes=int(t.n_probes), probe_ms=[float(t.probe_ms[i]) for i in range(t.n_probes)])

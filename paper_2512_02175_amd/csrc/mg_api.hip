@@ -87,6 +87,11 @@ struct mg_graph {
 struct mg_particles {
   const mg_graph *g = nullptr;
   int32_t schedule = MG_SCHED_AUTO;
+  // autotuned choice (schedule AUTO): valid for dt == tuned_dt
+  bool tuned = false;
+  double tuned_dt = 0.0;
+  int32_t tuned_kernel = 1;
+  int32_t tuned_idle = 8;
   int64_t n = 0;
   mg_precision prec = MG_FP64;
   int32_t max_splits = 8;
@@ -98,6 +103,7 @@ struct mg_particles {
   void *mem = nullptr;
   SetDev sd{};
   uint64_t step = 0;
+  uint64_t obs_start = 0;  // step counter when the streamed histogram started
 };
 
 struct mg_batch {
@@ -109,6 +115,20 @@ struct mg_batch {
   int32_t n_items = 0;
   int32_t max_nnz = 0;
   int32_t max_stage = 0;  // staged table bytes if every set's graph fits, else 0
+  int32_t kernel = 1;     // FP32 schedule fixed at creation (tile size follows it)
+  // Per-call set descriptors go up from pinned memory; the launch chain of a
+  // call is a HIP graph of kernel nodes, re-instantiated only when the
+  // call's shape (steps, dt, seed, schedule) changes.
+  SetDev *h_sets = nullptr;
+  hipEvent_t uploaded = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t key_steps = -1;
+  double key_dt = 0.0;
+  uint64_t key_seed = 0;
+  int32_t key_idle = -1;
+  uint32_t key_chunk = 0;
+  bool key_obs = false;
 };
 
 namespace {
@@ -470,10 +490,9 @@ mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
 
 void mg_particles_destroy(mg_particles *p) {
   if (!p) return;
-  if (p->owns && p->mem) {
-    (void)hipStreamSynchronize(p->stream);
-    (void)hipFree(p->mem);
-  }
+  if ((p->owns && p->mem) || p->sd.obs) (void)hipStreamSynchronize(p->stream);
+  if (p->owns && p->mem) (void)hipFree(p->mem);
+  if (p->sd.obs) (void)hipFree(p->sd.obs);
   delete p;
 }
 
@@ -488,9 +507,15 @@ static mg_status check_steps(const mg_particles *p, int64_t n_steps, double dt) 
 }
 
 // FP32 step schedule of a set: 1 = wave pools, 0 = one particle per lane.
-// Automatic selection takes the pools.
+// Automatic selection takes the autotuned choice, or the pools until tuned.
 static int32_t fp32_kernel(const mg_particles *p) {
-  return p->schedule == MG_SCHED_LANES ? 0 : 1;
+  if (p->schedule == MG_SCHED_LANES) return 0;
+  if (p->schedule == MG_SCHED_POOLS) return 1;
+  return p->tuned ? p->tuned_kernel : 1;
+}
+
+static int32_t pool_idle(const mg_particles *p) {
+  return (p->schedule == MG_SCHED_AUTO && p->tuned) ? p->tuned_idle : 8;
 }
 
 static uint32_t chunk_steps(int32_t spl) {
@@ -505,12 +530,19 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
   if (!p) return fail(MG_EINVAL, "particles is NULL");
   mg_status st = check_steps(p, n_steps, dt);
   if (st != MG_OK) return st;
+  if (n_steps > 0 && p->prec == MG_FP32 && p->schedule == MG_SCHED_AUTO &&
+      !(p->tuned && p->tuned_dt == dt)) {
+    st = mg_autotune(p, dt, seed, 0, nullptr);
+    if (st != MG_OK) return st;
+    g_err.clear();
+  }
   StepArgs a{};
   a.max_splits = p->max_splits;
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   a.dt = dt;
   a.kernel = fp32_kernel(p);
+  a.idle = pool_idle(p);
   const uint32_t chunk = chunk_steps(p->steps_per_launch);
   int64_t left = n_steps;
   while (left > 0) {
@@ -546,6 +578,103 @@ mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge, uint64_t *o
   if (!dev_out) (void)hipFree(d_out);
   if (he != hipSuccess) return hip_fail(he, "computing the histogram");
   return check_device_error(p);
+}
+
+mg_status mg_observe_histogram(mg_particles *p, int32_t bins_per_edge, int32_t every) {
+  g_err.clear();
+  if (!p) return fail(MG_EINVAL, "particles is NULL");
+  if (every < 0 || every > (1 << 30)) return fail(MG_EINVAL, "every must be in [0, 2^30]");
+  if (every > 0) {
+    if (bins_per_edge < 1) return fail(MG_EINVAL, "bins_per_edge must be >= 1");
+    if ((int64_t)p->g->E * bins_per_edge > 0x7FFFFFFF)
+      return fail(MG_EINVAL, "E * bins_per_edge too large");
+  }
+  // kernels already queued may still add to the old counters
+  MG_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+  if (p->sd.obs) (void)hipFree(p->sd.obs);
+  p->sd.obs = nullptr;
+  p->sd.obs_nb = 0;
+  p->sd.obs_every = 0;
+  if (every == 0) return MG_OK;
+  const size_t bytes = (size_t)p->g->E * (size_t)bins_per_edge * 8;
+  uint64_t *mem = nullptr;
+  hipError_t he = hipMalloc(&mem, bytes);
+  if (he != hipSuccess)
+    return fail(MG_ENOMEM, "hipMalloc for the streamed histogram: %s", hipGetErrorString(he));
+  he = hipMemsetAsync(mem, 0, bytes, p->stream);
+  if (he != hipSuccess) {
+    (void)hipFree(mem);
+    return hip_fail(he, "clearing the streamed histogram");
+  }
+  p->sd.obs = mem;
+  p->sd.obs_nb = bins_per_edge;
+  p->sd.obs_every = (uint32_t)every;
+  p->obs_start = p->step;
+  return MG_OK;
+}
+
+mg_status mg_observed_histogram(const mg_particles *p, uint64_t *out, int64_t out_len,
+                                int64_t *n_snapshots) {
+  g_err.clear();
+  if (!p) return fail(MG_EINVAL, "particles is NULL");
+  if (!p->sd.obs) return fail(MG_ESTATE, "the streamed histogram is off");
+  const int64_t need = (int64_t)p->g->E * p->sd.obs_nb;
+  if (out) {
+    if (out_len < need)
+      return fail(MG_EINVAL, "out_len %lld < E * bins_per_edge = %lld", (long long)out_len,
+                  (long long)need);
+    MG_HIP(hipMemcpyAsync(out, p->sd.obs, (size_t)need * 8, hipMemcpyDefault, p->stream),
+           "copying the streamed histogram");
+  }
+  MG_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+  if (n_snapshots)
+    *n_snapshots = (int64_t)(p->step / p->sd.obs_every - p->obs_start / p->sd.obs_every);
+  return check_device_error(p);
+}
+
+mg_status mg_density_l2(const mg_graph *g, int32_t bins_per_edge, const uint64_t *counts,
+                        double mass, const double *ref_density, double *l2) {
+  g_err.clear();
+  if (!g || !counts || !ref_density || !l2) return fail(MG_EINVAL, "NULL argument");
+  if (bins_per_edge < 1) return fail(MG_EINVAL, "bins_per_edge must be >= 1");
+  const int64_t nbins = (int64_t)g->E * bins_per_edge;
+  if (nbins > 0x7FFFFFFF) return fail(MG_EINVAL, "E * bins_per_edge too large");
+  if (!(mass >= 0.0) || !is_finite(mass)) return fail(MG_EINVAL, "mass must be finite, >= 0");
+  std::vector<uint64_t> c((size_t)nbins);
+  std::vector<double> ref((size_t)nbins);
+  if (is_device_pointer(counts))
+    MG_HIP(hipMemcpy(c.data(), counts, (size_t)nbins * 8, hipMemcpyDeviceToHost),
+           "copying the counts");
+  else
+    std::memcpy(c.data(), counts, (size_t)nbins * 8);
+  if (is_device_pointer(ref_density))
+    MG_HIP(hipMemcpy(ref.data(), ref_density, (size_t)nbins * 8, hipMemcpyDeviceToHost),
+           "copying the reference density");
+  else
+    std::memcpy(ref.data(), ref_density, (size_t)nbins * 8);
+  double total = mass;
+  if (total == 0.0) {
+    uint64_t sum = 0;
+    for (uint64_t v : c) sum += v;
+    total = (double)sum;
+  }
+  if (!(total > 0.0)) return fail(MG_EINVAL, "the histogram is empty");
+  // Neumaier-compensated sum of w (rho_hat - rho_ref)^2 over all bins
+  double acc = 0.0, comp = 0.0;
+  for (int32_t e = 0; e < g->E; ++e) {
+    const double w = g->length[e] / bins_per_edge;
+    for (int32_t k = 0; k < bins_per_edge; ++k) {
+      const size_t i = (size_t)e * bins_per_edge + k;
+      if (!is_finite(ref[i])) return fail(MG_EINVAL, "reference density %zu not finite", i);
+      const double d = (double)c[i] / (total * w) - ref[i];
+      const double term = w * d * d;
+      const double t = acc + term;
+      comp += std::fabs(acc) >= std::fabs(term) ? (acc - t) + term : (term - t) + acc;
+      acc = t;
+    }
+  }
+  *l2 = std::sqrt(acc + comp);
+  return MG_OK;
 }
 
 mg_status mg_exit_counts(const mg_particles *p, uint64_t *slot_counts, uint64_t *absorbed,
@@ -629,6 +758,7 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
   }
   mg_batch *b = new mg_batch();
   b->sets.assign(sets, sets + n_sets);
+  b->kernel = fp32_kernel(sets[0]);
   std::vector<BatchItem> items;
   bool all_stage = true;
   const int32_t tile = batch_tile(sets[0]->prec == MG_FP64, fp32_kernel(sets[0]));
@@ -664,12 +794,59 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
   if (he == hipSuccess)
     he = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(),
                    hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipHostMalloc((void **)&b->h_sets, sizeof(SetDev) * n_sets, 0);
+  if (he == hipSuccess) he = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+  if (he == hipSuccess) he = hipEventRecord(b->uploaded, sets[0]->stream);
   if (he != hipSuccess) {
     mg_batch_destroy(b);
-    return hip_fail(he, "copying the batch tables");
+    return hip_fail(he, "setting up the batch");
   }
   *out = b;
   return MG_OK;
+}
+
+static void drop_graph(mg_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->key_steps = -1;
+}
+
+// Kernel nodes of one call: one launch per chunk of steps, chained.
+static hipError_t build_graph(mg_batch *b, int64_t n_steps, const StepArgs &base,
+                              uint32_t chunk) {
+  hipError_t he = hipGraphCreate(&b->graph, 0);
+  if (he != hipSuccess) return he;
+  mg_particles *p0 = b->sets[0];
+  hipGraphNode_t prev = nullptr;
+  uint32_t done = 0;
+  int64_t left = n_steps;
+  while (left > 0 && he == hipSuccess) {
+    StepArgs a = base;
+    a.nsteps = (uint32_t)std::min<int64_t>(left, chunk);
+    a.n0_offset = done;
+    const KernelLaunch k = batch_launch(b->n_items, b->max_nnz, b->max_stage, a,
+                                        p0->prec == MG_FP64, p0->trace, b->key_obs);
+    const GraphDev *g = b->d_graphs;
+    const SetDev *sd = b->d_sets;
+    const BatchItem *it = b->d_items;
+    void *args[] = {(void *)&g, (void *)&sd, (void *)&it, (void *)&a};
+    hipKernelNodeParams np{};
+    np.func = (void *)k.func;
+    np.gridDim = k.grid;
+    np.blockDim = k.block;
+    np.sharedMemBytes = (unsigned)k.shm;
+    np.kernelParams = args;
+    np.extra = nullptr;
+    hipGraphNode_t node;
+    he = hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+    prev = node;
+    done += a.nsteps;
+    left -= a.nsteps;
+  }
+  if (he == hipSuccess) he = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  return he;
 }
 
 mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t seed) {
@@ -679,6 +856,7 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
     mg_status st = check_steps(p, n_steps, dt);
     if (st != MG_OK) return st;
   }
+  if (n_steps == 0) return MG_OK;
   mg_particles *p0 = b->sets[0];
   hipStream_t stream = p0->stream;
   StepArgs a{};
@@ -686,33 +864,125 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   a.dt = dt;
-  a.kernel = fp32_kernel(p0);
+  a.kernel = b->kernel;
+  a.idle = pool_idle(p0);
   const uint32_t chunk = chunk_steps(p0->steps_per_launch);
   const int32_t n_sets = (int32_t)b->sets.size();
-  std::vector<SetDev> sds(n_sets);
-  int64_t left = n_steps;
-  while (left > 0) {
-    const uint32_t now = (uint32_t)std::min<int64_t>(left, chunk);
-    a.nsteps = now;
-    for (int32_t i = 0; i < n_sets; ++i) {
-      sds[i] = b->sets[i]->sd;
-      sds[i].n0 = (uint32_t)b->sets[i]->step;
-    }
-    MG_HIP(hipMemcpyAsync(b->d_sets, sds.data(), sizeof(SetDev) * n_sets,
-                          hipMemcpyHostToDevice, stream), "copying set descriptors");
-    MG_HIP(launch_batch(b->d_graphs, b->d_sets, b->d_items, b->n_items, b->max_nnz,
-                        b->max_stage, a, p0->prec == MG_FP64, p0->trace, stream),
-           "launching the batch kernel");
-    // the descriptor copy above reads pageable host memory: keep it alive
-    MG_HIP(hipStreamSynchronize(stream), "synchronising the batch");
-    for (mg_particles *p : b->sets) p->step += now;
-    left -= now;
+  // the previous call's upload must have left the pinned buffer
+  MG_HIP(hipEventSynchronize(b->uploaded), "waiting for the previous upload");
+  for (int32_t i = 0; i < n_sets; ++i) {
+    b->h_sets[i] = b->sets[i]->sd;
+    b->h_sets[i].n0 = (uint32_t)b->sets[i]->step;
   }
+  MG_HIP(hipMemcpyAsync(b->d_sets, b->h_sets, sizeof(SetDev) * n_sets, hipMemcpyHostToDevice,
+                        stream), "copying set descriptors");
+  MG_HIP(hipEventRecord(b->uploaded, stream), "recording the upload");
+  bool obs = false;
+  for (mg_particles *p : b->sets) obs = obs || p->sd.obs != nullptr;
+  if (!(b->exec && b->key_steps == n_steps && b->key_dt == dt && b->key_seed == seed &&
+        b->key_idle == a.idle && b->key_chunk == chunk && b->key_obs == obs)) {
+    drop_graph(b);
+    b->key_obs = obs;
+    hipError_t he = build_graph(b, n_steps, a, chunk);
+    if (he != hipSuccess) {
+      drop_graph(b);
+      return hip_fail(he, "building the batch launch graph");
+    }
+    b->key_steps = n_steps;
+    b->key_dt = dt;
+    b->key_seed = seed;
+    b->key_idle = a.idle;
+    b->key_chunk = chunk;
+  }
+  MG_HIP(hipGraphLaunch(b->exec, stream), "launching the batch graph");
+  for (mg_particles *p : b->sets) p->step += (uint64_t)n_steps;
+  return MG_OK;
+}
+
+mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_steps,
+                      mg_tuning *out) {
+  g_err.clear();
+  if (!p) return fail(MG_EINVAL, "particles is NULL");
+  if (!is_finite(dt) || !(dt > 0.0)) return fail(MG_EINVAL, "dt must be finite and > 0");
+  mg_tuning res{};
+  if (p->prec == MG_FP64) {
+    res.schedule = MG_SCHED_LANES;
+    res.idle_trigger = 0;
+    if (out) *out = res;
+    return MG_OK;
+  }
+  const int64_t n = std::min<int64_t>(p->n, 1 << 21);
+  const uint32_t steps = (uint32_t)(probe_steps > 0 ? probe_steps : 32);
+  if ((uint64_t)p->step + steps > 0xFFFFFFFFull)
+    return fail(MG_EINVAL, "the probe would pass step 2^32");
+  const SetLayout L = set_layout(p->g->V, p->g->nnz, n, MG_FP32, false);
+  void *mem = nullptr;
+  MG_HIP(hipMalloc(&mem, L.total), "allocating the tuning probe");
+  char *base = (char *)mem;
+  SetDev sd{};
+  sd.ef = (uint32_t *)(base + L.ef);
+  sd.y32 = (float2 *)(base + L.pos);
+  sd.exit_cnt = (uint64_t *)(base + L.exitc);
+  sd.absorbed = (uint64_t *)(base + L.absorbed);
+  sd.totals = (uint64_t *)(base + L.totals);
+  sd.err = (uint32_t *)(base + L.err);
+  sd.n = (uint32_t)n;
+  sd.n0 = (uint32_t)p->step;
+  sd.tag = p->tag;
+  StepArgs a{};
+  a.nsteps = steps;
+  a.max_splits = p->max_splits;
+  a.key0 = (uint32_t)seed;
+  a.key1 = (uint32_t)(seed >> 32);
+  a.dt = dt;
+  const int32_t cand_kernel[5] = {0, 1, 1, 1, 1};
+  const int32_t cand_idle[5] = {8, 4, 8, 16, 32};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  float best = 0.0f;
+  int best_i = -1;
+  for (int i = 0; i < 5 && he == hipSuccess; ++i) {
+    he = hipMemcpyAsync(sd.ef, p->sd.ef, (size_t)n * 4, hipMemcpyDeviceToDevice, p->stream);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(sd.y32, p->sd.y32, (size_t)n * 8, hipMemcpyDeviceToDevice, p->stream);
+    if (he == hipSuccess) he = hipEventRecord(e0, p->stream);
+    a.kernel = cand_kernel[i];
+    a.idle = cand_idle[i];
+    if (he == hipSuccess) he = launch_step(p->g->gd, sd, a, false, false, p->stream);
+    if (he == hipSuccess) he = hipEventRecord(e1, p->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) break;
+    res.probe_ms[i] = ms;
+    if (best_i < 0 || ms < best) {
+      best = ms;
+      best_i = i;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(mem);
+  if (he != hipSuccess) return hip_fail(he, "running the tuning probe");
+  res.n_probes = 5;
+  res.schedule = cand_kernel[best_i] ? MG_SCHED_POOLS : MG_SCHED_LANES;
+  res.idle_trigger = cand_idle[best_i];
+  p->tuned = true;
+  p->tuned_dt = dt;
+  p->tuned_kernel = cand_kernel[best_i];
+  p->tuned_idle = cand_idle[best_i];
+  if (out) *out = res;
   return MG_OK;
 }
 
 void mg_batch_destroy(mg_batch *b) {
   if (!b) return;
+  if (b->uploaded) (void)hipEventSynchronize(b->uploaded);
+  if (!b->sets.empty()) (void)hipStreamSynchronize(b->sets[0]->stream);
+  drop_graph(b);
+  if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+  if (b->h_sets) (void)hipHostFree(b->h_sets);
   if (b->dev) (void)hipFree(b->dev);
   delete b;
 }

@@ -88,6 +88,10 @@ struct SetDev {
   uint64_t *absorbed;  // [V]
   uint64_t *totals;    // [4]
   uint32_t *err;       // [1]
+  uint64_t *obs;       // [E * obs_nb] streamed histogram, or null (off)
+  int32_t obs_nb;      // its bins per edge
+  uint32_t obs_every;  // a snapshot each time the step counter reaches a
+                       // multiple of obs_every
   uint32_t n;
   uint32_t n0;         // first step of this launch (set's step counter)
   uint32_t tag;
@@ -101,6 +105,9 @@ struct StepArgs {
   uint32_t key0, key1;
   double dt;
   int32_t kernel;  // FP32 schedule: 0 lane-per-particle windows, 1 wave pools
+  int32_t idle;    // wave pools: idle lanes that trigger a partial split pass
+  uint32_t n0_offset;  // batched launches: steps taken earlier in the call
+  int32_t obs_lds;     // streamed-histogram bins privatised in LDS (0: global)
 };
 
 // Batched form: one work item per (set, tile of particles).
@@ -115,8 +122,13 @@ constexpr int kBlock = 256;
 #endif
 constexpr int kPoolPerWave = MG_POOL_PER_WAVE;          // FP32 wave pools (<= 256)
 constexpr int kPoolPerBlock = kPoolPerWave * (kBlock / 64);
-constexpr int kLdsExitMax = 16384;  // slots counted in LDS (64 KiB of u32)
+constexpr int kLdsExitMax = 4096;   // slots counted in LDS (16 KiB of u32); with
+                                    // staged tables and pools a block stays
+                                    // within 64 KiB of LDS
 constexpr int kLdsStageMax = 24576; // graph tables staged in LDS up to this size
+constexpr int kLdsHistMax = 16384;  // histogram bins privatised in LDS (64 KiB)
+constexpr int kLdsObsMax = 4096;    // streamed-histogram bins privatised in LDS
+constexpr int kLdsBlockMax = 65536; // LDS bytes a step block may take
 
 hipError_t launch_init(const GraphDev &g, const SetDev &s, int mode,
                        int32_t vertex, uint32_t key0, uint32_t key1,
@@ -127,10 +139,17 @@ hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
 // Particles per batch work item: a pool block for the FP32 wave-pool
 // kernel, a plain block otherwise.
 int32_t batch_tile(bool fp64, int32_t kernel);
-hipError_t launch_batch(const GraphDev *graphs, const SetDev *sets,
-                        const BatchItem *items, int32_t n_items,
-                        int32_t max_nnz, int32_t max_stage, const StepArgs &a,
-                        bool fp64, bool trace, hipStream_t st);
+
+// A kernel and its launch shape, for stream launches and graph nodes.  The
+// batch kernels take (const GraphDev*, const SetDev*, const BatchItem*,
+// StepArgs).
+struct KernelLaunch {
+  const void *func;
+  dim3 grid, block;
+  size_t shm;
+};
+KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
+                          const StepArgs &a, bool fp64, bool trace, bool obs);
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,
                             uint64_t *out, bool fp64, hipStream_t st);
 

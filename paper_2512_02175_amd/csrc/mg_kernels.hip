@@ -17,6 +17,8 @@
 // The FP32 path consumes the same integers as the FP64 path.
 //
 // Compiled with -ffp-contract=off: every fused multiply-add is explicit.
+#include <type_traits>
+
 #include "mg_internal.h"
 
 namespace mg {
@@ -221,6 +223,44 @@ __device__ __forceinline__ void count_exit(uint32_t *s_exit, uint64_t *g_exit,
     atomicAdd((unsigned long long *)&g_exit[slot], 1ull);
 }
 
+// Bin of position x on an edge of length L, nb bins per edge: x times the
+// FP64 inverse bin width nb / L, rounded down, clamped to [0, nb - 1] (the
+// appendix histogram kernel, with x = L in the last bin).
+__device__ __forceinline__ int32_t bin_of(double x, double L, int32_t nb) {
+  const double inv = (double)nb / L;
+  const double f = floor(x * inv);
+  return f < 0.0 ? 0 : (f > (double)(nb - 1) ? nb - 1 : (int32_t)f);
+}
+
+// Streamed histogram.  A snapshot adds every alive particle's bin at each
+// step counter value that is a multiple of S.obs_every (the state after
+// that many steps).  next_snapshot(n) is the first such value after n; 0
+// (never reached: counters after a step are >= 1) when there is none below
+// 2^32 or streaming is off.
+__device__ __forceinline__ uint32_t next_snapshot(uint32_t n, const SetDev &S) {
+  if (!S.obs) return 0u;
+  const uint64_t v = ((uint64_t)(n / S.obs_every) + 1u) * S.obs_every;
+  return v > 0xFFFFFFFFull ? 0u : (uint32_t)v;
+}
+
+// Where snapshots go: LDS bins of the block (lds != null) or the set's
+// global counters; e64 is the global FP64 edge table (bins are taken in
+// FP64 from the lengths, as the histogram kernel does).
+struct ObsSink {
+  uint32_t *lds;
+  const EdgeRec64 *e64;
+};
+
+template <typename P>
+__device__ __forceinline__ void observe(const P &q, const SetDev &S, const ObsSink &o) {
+  const double L = o.e64[q.e].L;
+  const int32_t idx = q.e * S.obs_nb + bin_of(q.pos64(L), L, S.obs_nb);
+  if (o.lds)
+    atomicAdd(&o.lds[idx], 1u);
+  else
+    atomicAdd((unsigned long long *)&S.obs[idx], 1ull);
+}
+
 template <typename T, int N>
 __device__ __forceinline__ T pickw(const T (&W)[N], uint32_t j) {
   T w = W[0];
@@ -243,12 +283,20 @@ __device__ __forceinline__ T pickw(const T (&W)[N], uint32_t j) {
 // particle's arithmetic and random numbers are those of the plain order;
 // the split code runs once per round for all parked lanes instead of once
 // per step for any lane that hit.
-template <int NG, typename P>
+template <int NG, bool OBS, typename P>
 __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs &A,
-                                          uint32_t pid, Tally &t) {
+                                          uint32_t pid, Tally &t, const ObsSink &o) {
   constexpr uint32_t NW = 4 * NG;  // steps per window
   const uint32_t n_end = S.n0 + A.nsteps;
   uint32_t n = S.n0;
+  uint32_t snap = OBS ? next_snapshot(n, S) : 0u;
+  // after each completed step (and the group-end re-anchoring)
+  auto snapshot = [&](uint32_t done) {
+    if (OBS && done == snap) {
+      observe(q, S, o);
+      snap = next_snapshot(done, S);
+    }
+  };
   while (n < n_end && q.alive) {
     const uint32_t base = n & ~(NW - 1);
     typename P::real W[NW];
@@ -264,15 +312,20 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
 #pragma unroll
     for (uint32_t j = 0; j < NW; ++j) {
       if (j < jb || j >= je || pj >= 0) continue;
-      if (!q.fast(W[j]))
+      if (!q.fast(W[j])) {
         pj = (int32_t)j;
-      else if ((j & 3u) == 3u)
-        q.reanchor();
+      } else {
+        if ((j & 3u) == 3u) q.reanchor();
+        snapshot(base + j + 1u);
+      }
     }
     while (pj >= 0) {
       const uint32_t j0 = (uint32_t)pj;
       q.resolve(base + j0, pickw(W, j0), pid, S, A, t);
-      if ((j0 & 3u) == 3u && q.alive) q.reanchor();
+      if (q.alive) {
+        if ((j0 & 3u) == 3u) q.reanchor();
+        snapshot(base + j0 + 1u);
+      }
       pj = -1;
       for (uint32_t j = j0 + 1; j < je && q.alive; ++j) {
         if (!q.fast(pickw(W, j))) {
@@ -280,6 +333,7 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
           break;
         }
         if ((j & 3u) == 3u) q.reanchor();
+        snapshot(base + j + 1u);
       }
     }
     n = base + je;
@@ -311,6 +365,7 @@ struct Particle64 {
 
   // FP64 positions are always measured from the initial vertex.
   __device__ __forceinline__ void reanchor() {}
+  __device__ __forceinline__ double pos64(double) const { return x; }
 
   __device__ __forceinline__ bool fast(double w) {
     if (x == 0.0)
@@ -386,9 +441,9 @@ struct Particle64 {
   }
 };
 
-template <bool TRACE, bool LDS, int NG>
+template <bool TRACE, bool LDS, bool OBS, int NG>
 __device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const StepArgs &A,
-                      uint32_t pid, uint32_t *s_exit, Tally &t) {
+                      uint32_t pid, uint32_t *s_exit, Tally &t, const ObsSink &o) {
   const uint32_t ef = S.ef[pid];
   if (ef & kDeadBit) return;
   const int32_t e = (int32_t)(ef & kEdgeMask);
@@ -403,7 +458,7 @@ __device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const St
     atomicOr(S.err, kErrPos);
     return;
   }
-  step_loop<NG>(q, S, A, pid, t);
+  step_loop<NG, OBS>(q, S, A, pid, t, o);
   S.ef[pid] = (uint32_t)q.e | (q.alive ? 0u : kDeadBit);
   S.x64[pid] = q.x;
   if (TRACE) {
@@ -463,6 +518,12 @@ struct Particle32 {
     const float yt = y + s;
     err = s - (yt - y);
     return yt;
+  }
+
+  // Position from the initial vertex in FP64, as the histogram reads it.
+  __device__ __forceinline__ double pos64(double L) const {
+    const double v = (double)y + (double)yl;
+    return side ? L - v : v;
   }
 
   // Re-anchor to the nearer end: L - y is exact for y in [L/2, L)
@@ -587,9 +648,9 @@ struct Particle32 {
   }
 };
 
-template <bool TRACE, bool LDS, int NG>
+template <bool TRACE, bool LDS, bool OBS, int NG>
 __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const StepArgs &A,
-                      uint32_t pid, uint32_t *s_exit, Tally &t) {
+                      uint32_t pid, uint32_t *s_exit, Tally &t, const ObsSink &o) {
   const uint32_t ef = S.ef[pid];
   if (ef & kDeadBit) return;
   const int32_t e = (int32_t)(ef & kEdgeMask);
@@ -608,7 +669,7 @@ __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const St
     atomicOr(S.err, kErrPos);
     return;
   }
-  step_loop<NG>(q, S, A, pid, t);
+  step_loop<NG, OBS>(q, S, A, pid, t, o);
   S.ef[pid] = (uint32_t)q.e | (q.side ? kSideBit : 0u) | (q.alive ? 0u : kDeadBit);
   S.y32[pid] = make_float2(q.y, q.yl);
   if (TRACE) {
@@ -636,7 +697,18 @@ __device__ __forceinline__ void flush(const SetDev &S, const Tally &t,
   }
 }
 
-// Shared memory of a step block: [exit counters (LDS)][staged tables].
+// Adds a block's LDS snapshot bins to the set's counters (after the
+// barrier in flush()).
+__device__ __forceinline__ void flush_obs(const SetDev &S, const uint32_t *s_obs,
+                                          int32_t nbins) {
+  for (int32_t b = threadIdx.x; b < nbins; b += blockDim.x)
+    if (s_obs[b]) atomicAdd((unsigned long long *)&S.obs[b], (unsigned long long)s_obs[b]);
+}
+
+__device__ __forceinline__ int32_t align16(int32_t v) { return (v + 15) & ~15; }
+
+// Shared memory of a step block: [exit counters (LDS)][staged tables]
+// [snapshot bins (LDS)].
 // Staged tables keep their relative layout: vertex blocks, slot table and
 // guide tables, then the edge records of the kernel's precision.
 template <bool FP64, bool STAGED>
@@ -661,7 +733,7 @@ __device__ __forceinline__ GView block_view(const GraphDev &G, char *smem) {
 
 __device__ __forceinline__ int32_t exit_bytes(int32_t nnz) { return ((nnz * 4) + 15) & ~15; }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS>
 __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t pid,
                                            uint32_t *s_tot, char *smem) {
@@ -669,27 +741,35 @@ __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
   if (threadIdx.x < 4) s_tot[threadIdx.x] = 0;
   if (LDS)
     for (int32_t s = threadIdx.x; s < G.nnz; s += blockDim.x) s_exit[s] = 0;
-  const GView view = block_view<FP64, STAGED>(G, smem + (LDS ? exit_bytes(G.nnz) : 0));
+  const int32_t ex = LDS ? exit_bytes(G.nnz) : 0;
+  const GView view = block_view<FP64, STAGED>(G, smem + ex);
+  ObsSink o{nullptr, G.e64};
+  if (OBS && A.obs_lds) {
+    o.lds = (uint32_t *)(smem + align16(ex + (STAGED ? (FP64 ? G.stage_bytes64
+                                                             : G.stage_bytes32) : 0)));
+    for (int32_t b = threadIdx.x; b < A.obs_lds; b += blockDim.x) o.lds[b] = 0;
+  }
   __syncthreads();
   Tally t{0, 0, 0, 0};
   if (pid < S.n) {
     if (FP64)
-      run64<TRACE, LDS, kWindowGroups64>(view, G.E, S, A, pid, s_exit, t);
+      run64<TRACE, LDS, OBS, kWindowGroups64>(view, G.E, S, A, pid, s_exit, t, o);
     else
-      run32<TRACE, LDS, kWindowGroups32>(view, G.E, S, A, pid, s_exit, t);
+      run32<TRACE, LDS, OBS, kWindowGroups32>(view, G.E, S, A, pid, s_exit, t, o);
   }
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
+  if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
 }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS>
 __global__ __launch_bounds__(kBlock) void k_step(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  step_block<FP64, TRACE, LDS, STAGED>(G, S, A, blockIdx.x * kBlock + threadIdx.x, s_tot,
-                                       (char *)smem4);
+  step_block<FP64, TRACE, LDS, STAGED, OBS>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
+                                            s_tot, (char *)smem4);
 }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS>
 __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
                                                   const SetDev *sets,
                                                   const BatchItem *items,
@@ -697,10 +777,11 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
   const BatchItem it = items[blockIdx.x];
-  const SetDev S = sets[it.set];
+  SetDev S = sets[it.set];
+  S.n0 += A.n0_offset;  // steps already taken by earlier launches of this call
   const GraphDev G = graphs[it.set];
-  step_block<FP64, TRACE, LDS, STAGED>(G, S, A, it.first + threadIdx.x, s_tot,
-                                       (char *)smem4);
+  step_block<FP64, TRACE, LDS, STAGED, OBS>(G, S, A, it.first + threadIdx.x, s_tot,
+                                            (char *)smem4);
 }
 
 // ------------------------------------------------ FP32 wave-pool kernel --
@@ -719,7 +800,6 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
 constexpr int kWavesPerBlock = kBlock / 64;
 static_assert(kPoolPerWave % 64 == 0 && kPoolPerWave >= 128 && kPoolPerWave <= 256,
               "a wave pool holds 2 to 4 particles per lane");
-constexpr int kIdleTrigger = 8;  // idle lanes that trigger a partial split pass
 
 struct PoolLds32 {
   uint32_t ef[kPoolPerWave];
@@ -788,10 +868,10 @@ __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS> &q, con
   t.sub += taken;
 }
 
-template <bool TRACE, bool LDS>
+template <bool TRACE, bool LDS, bool OBS>
 __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
                            const StepArgs &A, uint32_t base, PoolLds32 &P,
-                           uint32_t *s_exit, Tally &t) {
+                           uint32_t *s_exit, Tally &t, const ObsSink &sink) {
   const uint32_t lane = threadIdx.x & 63u;
   const float dt = (float)A.dt;
   const float sqdt = (float)sqrt(A.dt);
@@ -800,6 +880,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
                            true, 0ull, 0u, 0u};
   bool has = false;
   uint32_t slot = 0, n = 0;
+  uint32_t snap = 0;  // next snapshot count of the lane's particle
   uint32_t ready_cnt = 0, split_cnt = 0;
 
   // Initial placement: slot `lane` rides in the lane, slots 64k + lane wait.
@@ -840,6 +921,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         has = true;
         slot = s;
         n = S.n0;
+        if (OBS) snap = next_snapshot(n, S);
       }
     } else {
       const uint64_t m = __ballot(ok);
@@ -870,6 +952,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
           n = P.n[slot];
           pool_load(q, P, slot);
           has = true;
+          if (OBS) snap = next_snapshot(n, S);
         }
       }
       ready_cnt -= min((uint32_t)__popcll(m_empty), ready_cnt);
@@ -898,12 +981,21 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
           const bool hit = act & !in;
           pj = hit ? (int32_t)j : pj;
           wp = hit ? W[j] : wp;
+          if (OBS && (act & in)) {
+            if (j == 3u) q.reanchor();
+            const uint32_t done = (m << 2) + j + 1u;
+            if (done == snap) {
+              observe(q, S, sink);
+              snap = next_snapshot(done, S);
+            }
+          }
         }
         if (pj >= 0) {
           parked = true;
           n = (m << 2) + (uint32_t)pj;
         } else {
-          if (je == 4u) q.reanchor();  // the group's last step completed
+          // the group's last step completed
+          if (!OBS && je == 4u) q.reanchor();
           n = (m << 2) + je;
         }
         if (!parked && n == n_end) {
@@ -922,7 +1014,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       wave_lds_fence();
       const uint32_t empty = (uint32_t)__popcll(__ballot(!has));
       const uint32_t idle = empty > ready_cnt ? empty - ready_cnt : 0u;
-      do_split = split_cnt >= 64u || (split_cnt > 0u && idle >= (uint32_t)kIdleTrigger);
+      do_split = split_cnt >= 64u || (split_cnt > 0u && idle >= (uint32_t)A.idle);
     }
     if (do_split) {
       // The lanes' own particles wait in their home slots during the pass.
@@ -941,7 +1033,10 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         pool_load(q2, P, s2);
         const uint32_t step = P.n[s2];
         q2.resolve(step, P.w[s2], base + s2, S, A, t);
-        if ((step & 3u) == 3u && q2.alive) q2.reanchor();
+        if (q2.alive) {
+          if ((step & 3u) == 3u) q2.reanchor();
+          if (OBS && step + 1u == next_snapshot(step, S)) observe(q2, S, sink);
+        }
         const uint32_t n2 = step + 1u;
         if (!q2.alive || n2 == n_end) {
           pool_finish(q2, S, A, base + s2, t);
@@ -962,7 +1057,9 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   }
 }
 
-template <bool TRACE, bool LDS, bool STAGED>
+// Shared memory of a pool block: [exit counters][staged tables][pools]
+// [snapshot bins].
+template <bool TRACE, bool LDS, bool STAGED, bool OBS>
 __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t block_first,
                                            uint32_t *s_tot, char *smem) {
@@ -972,29 +1069,36 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
     for (int32_t s = threadIdx.x; s < G.nnz; s += blockDim.x) s_exit[s] = 0;
   const int32_t ex = LDS ? exit_bytes(G.nnz) : 0;
   const GView view = block_view<false, STAGED>(G, smem + ex);
-  PoolLds32 *pools =
-      (PoolLds32 *)(smem + ((ex + (STAGED ? G.stage_bytes32 : 0) + 15) & ~15));
+  const int32_t o_pools = align16(ex + (STAGED ? G.stage_bytes32 : 0));
+  PoolLds32 *pools = (PoolLds32 *)(smem + o_pools);
+  ObsSink o{nullptr, G.e64};
+  if (OBS && A.obs_lds) {
+    o.lds = (uint32_t *)(smem + o_pools + (int32_t)sizeof(PoolLds32) * kWavesPerBlock);
+    for (int32_t b = threadIdx.x; b < A.obs_lds; b += blockDim.x) o.lds[b] = 0;
+  }
   __syncthreads();
   Tally t{0, 0, 0, 0};
   const uint32_t wave = threadIdx.x >> 6;
-  run_pool32<TRACE, LDS>(view, G.E, S, A, block_first + wave * kPoolPerWave, pools[wave],
-                         s_exit, t);
+  run_pool32<TRACE, LDS, OBS>(view, G.E, S, A, block_first + wave * kPoolPerWave,
+                              pools[wave], s_exit, t, o);
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
+  if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
 }
 
 #ifndef MG_POOL_WAVES_PER_EU
 #define MG_POOL_WAVES_PER_EU 7
 #endif
 
-template <bool TRACE, bool LDS, bool STAGED>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  pool_block<TRACE, LDS, STAGED>(G, S, A, blockIdx.x * kPoolPerBlock, s_tot, (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS>(G, S, A, blockIdx.x * kPoolPerBlock, s_tot,
+                                      (char *)smem4);
 }
 
-template <bool TRACE, bool LDS, bool STAGED>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32_batch(const GraphDev *graphs,
                                                          const SetDev *sets,
@@ -1003,9 +1107,10 @@ void k_pool32_batch(const GraphDev *graphs,
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
   const BatchItem it = items[blockIdx.x];
-  const SetDev S = sets[it.set];
+  SetDev S = sets[it.set];
+  S.n0 += A.n0_offset;
   const GraphDev G = graphs[it.set];
-  pool_block<TRACE, LDS, STAGED>(G, S, A, it.first, s_tot, (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS>(G, S, A, it.first, s_tot, (char *)smem4);
 }
 
 // ---------------------------------------------------------------- init --
@@ -1080,10 +1185,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(GraphDev G, SetDev S, int32_t n
       const double y = (double)yy.x + (double)yy.y;
       x = (ef & kSideBit) ? L - y : y;
     }
-    const double inv = (double)nb / L;
-    const double f = floor(x * inv);
-    int32_t b = f < 0.0 ? 0 : (f > (double)(nb - 1) ? nb - 1 : (int32_t)f);
-    const int32_t idx = e * nb + b;
+    const int32_t idx = e * nb + bin_of(x, L, nb);
     if (LDS)
       atomicAdd(&s_bin[idx], 1u);
     else
@@ -1096,85 +1198,95 @@ __global__ __launch_bounds__(kBlock) void k_hist(GraphDev G, SetDev S, int32_t n
   }
 }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED>
-void launch_step_k(const GraphDev &g, const SetDev &s, const StepArgs &a, size_t shm,
-                   hipStream_t st) {
-  const uint32_t blocks = (s.n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL((k_step<FP64, TRACE, LDS, STAGED>), dim3(blocks), dim3(kBlock), shm, st,
-                     g, s, a);
+// Calls f(std::bool_constant<x>...) for the run-time flags, so one launch
+// site covers every compiled variant.
+template <typename F>
+void with_flags(F &&f) {
+  f();
+}
+template <typename F, typename... Rest>
+void with_flags(F &&f, bool x, Rest... rest) {
+  if (x)
+    with_flags([&](auto... v) { f(std::true_type{}, v...); }, rest...);
+  else
+    with_flags([&](auto... v) { f(std::false_type{}, v...); }, rest...);
 }
 
-template <bool TRACE, bool LDS, bool STAGED>
-void launch_pool_k(const GraphDev &g, const SetDev &s, const StepArgs &a, size_t shm,
-                   hipStream_t st) {
-  const uint32_t blocks = (s.n + kPoolPerBlock - 1) / kPoolPerBlock;
-  hipLaunchKernelGGL((k_pool32<TRACE, LDS, STAGED>), dim3(blocks), dim3(kBlock), shm, st,
-                     g, s, a);
-}
+// LDS layout sizes shared by the host launchers and the kernels' offsets.
+struct LdsPlan {
+  bool lds_exit;
+  int32_t obs_lds;  // snapshot bins in LDS, 0: global counters
+  size_t shm;
+};
 
-template <bool TRACE>
-hipError_t launch_pool_t(const GraphDev &g, const SetDev &s, const StepArgs &a,
-                         hipStream_t st) {
-  const bool lds = g.nnz <= kLdsExitMax;
-  const int32_t stage = g.stage_bytes32;
-  const int32_t ex = lds ? ((g.nnz * 4 + 15) & ~15) : 0;
-  const size_t shm = (size_t)(((ex + stage) + 15) & ~15) + sizeof(PoolLds32) * kWavesPerBlock;
-  if (lds && stage) launch_pool_k<TRACE, true, true>(g, s, a, shm, st);
-  else if (lds) launch_pool_k<TRACE, true, false>(g, s, a, shm, st);
-  else if (stage) launch_pool_k<TRACE, false, true>(g, s, a, shm, st);
-  else launch_pool_k<TRACE, false, false>(g, s, a, shm, st);
-  return hipGetLastError();
-}
-
-template <bool FP64, bool TRACE>
-hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a,
-                         hipStream_t st) {
-  if (!FP64 && a.kernel == 1) return launch_pool_t<TRACE>(g, s, a, st);
-  const bool lds = g.nnz <= kLdsExitMax;
-  const int32_t stage = FP64 ? g.stage_bytes64 : g.stage_bytes32;
-  const size_t shm = (lds ? (size_t)((g.nnz * 4 + 15) & ~15) : 0) + (size_t)stage;
-  if (lds && stage) launch_step_k<FP64, TRACE, true, true>(g, s, a, shm, st);
-  else if (lds) launch_step_k<FP64, TRACE, true, false>(g, s, a, shm, st);
-  else if (stage) launch_step_k<FP64, TRACE, false, true>(g, s, a, shm, st);
-  else launch_step_k<FP64, TRACE, false, false>(g, s, a, shm, st);
-  return hipGetLastError();
-}
-
-template <bool FP64, bool TRACE, bool LDS, bool STAGED>
-void launch_batch_k(const GraphDev *graphs, const SetDev *sets, const BatchItem *items,
-                    int32_t n_items, const StepArgs &a, size_t shm, hipStream_t st) {
-  hipLaunchKernelGGL((k_batch<FP64, TRACE, LDS, STAGED>), dim3(n_items), dim3(kBlock), shm,
-                     st, graphs, sets, items, a);
-}
-
-template <bool TRACE, bool LDS, bool STAGED>
-void launch_pool_batch_k(const GraphDev *graphs, const SetDev *sets, const BatchItem *items,
-                         int32_t n_items, const StepArgs &a, size_t shm, hipStream_t st) {
-  hipLaunchKernelGGL((k_pool32_batch<TRACE, LDS, STAGED>), dim3(n_items), dim3(kBlock), shm,
-                     st, graphs, sets, items, a);
+LdsPlan plan_lds(int32_t nnz, int32_t stage, size_t pools, const SetDev *obs_set,
+                 int32_t n_edges) {
+  LdsPlan p{};
+  p.lds_exit = nnz <= kLdsExitMax;
+  const int32_t ex = p.lds_exit ? ((nnz * 4 + 15) & ~15) : 0;
+  size_t base = (size_t)((ex + stage + 15) & ~15) + pools;
+  base = (base + 15) & ~(size_t)15;
+  p.shm = base;
+  if (obs_set && obs_set->obs) {
+    const int64_t nbins = (int64_t)n_edges * obs_set->obs_nb;
+    if (nbins <= kLdsObsMax && base + (size_t)nbins * 4 <= (size_t)kLdsBlockMax) {
+      p.obs_lds = (int32_t)nbins;
+      p.shm = base + (size_t)nbins * 4;
+    }
+  }
+  return p;
 }
 
 template <bool FP64, bool TRACE>
-hipError_t launch_batch_t(const GraphDev *graphs, const SetDev *sets,
-                          const BatchItem *items, int32_t n_items, int32_t max_nnz,
-                          int32_t max_stage, const StepArgs &a, hipStream_t st) {
-  const bool lds = max_nnz <= kLdsExitMax;
+hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
+                         hipStream_t st) {
+  StepArgs a = a0;
+  const bool obs = s.obs != nullptr;
   if (!FP64 && a.kernel == 1) {
-    const int32_t ex = lds ? ((max_nnz * 4 + 15) & ~15) : 0;
-    const size_t shm =
-        (size_t)(((ex + max_stage) + 15) & ~15) + sizeof(PoolLds32) * kWavesPerBlock;
-    if (lds && max_stage) launch_pool_batch_k<TRACE, true, true>(graphs, sets, items, n_items, a, shm, st);
-    else if (lds) launch_pool_batch_k<TRACE, true, false>(graphs, sets, items, n_items, a, shm, st);
-    else if (max_stage) launch_pool_batch_k<TRACE, false, true>(graphs, sets, items, n_items, a, shm, st);
-    else launch_pool_batch_k<TRACE, false, false>(graphs, sets, items, n_items, a, shm, st);
+    const int32_t stage = g.stage_bytes32;
+    const LdsPlan lp = plan_lds(g.nnz, stage, sizeof(PoolLds32) * kWavesPerBlock, &s, g.E);
+    a.obs_lds = lp.obs_lds;
+    const uint32_t blocks = (s.n + kPoolPerBlock - 1) / kPoolPerBlock;
+    with_flags([&](auto L, auto T, auto O) {
+      hipLaunchKernelGGL((k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
+                                   decltype(O)::value>),
+                         dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+    }, lp.lds_exit, stage > 0, obs);
     return hipGetLastError();
   }
-  const size_t shm = (lds ? (size_t)((max_nnz * 4 + 15) & ~15) : 0) + (size_t)max_stage;
-  if (lds && max_stage) launch_batch_k<FP64, TRACE, true, true>(graphs, sets, items, n_items, a, shm, st);
-  else if (lds) launch_batch_k<FP64, TRACE, true, false>(graphs, sets, items, n_items, a, shm, st);
-  else if (max_stage) launch_batch_k<FP64, TRACE, false, true>(graphs, sets, items, n_items, a, shm, st);
-  else launch_batch_k<FP64, TRACE, false, false>(graphs, sets, items, n_items, a, shm, st);
+  const int32_t stage = FP64 ? g.stage_bytes64 : g.stage_bytes32;
+  const LdsPlan lp = plan_lds(g.nnz, stage, 0, &s, g.E);
+  a.obs_lds = lp.obs_lds;
+  const uint32_t blocks = (s.n + kBlock - 1) / kBlock;
+  with_flags([&](auto L, auto T, auto O) {
+    hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
+                               decltype(O)::value>),
+                       dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+  }, lp.lds_exit, stage > 0, obs);
   return hipGetLastError();
+}
+
+// Batched launches keep snapshot bins in global memory (the sets differ).
+template <bool FP64, bool TRACE>
+KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
+                            const StepArgs &a, bool obs) {
+  KernelLaunch k{};
+  k.grid = dim3(n_items);
+  k.block = dim3(kBlock);
+  const bool pools = !FP64 && a.kernel == 1;
+  const LdsPlan lp = plan_lds(max_nnz, max_stage,
+                              pools ? sizeof(PoolLds32) * kWavesPerBlock : 0, nullptr, 0);
+  k.shm = lp.shm;
+  with_flags([&](auto L, auto T, auto O) {
+    constexpr bool l = decltype(L)::value, t = decltype(T)::value, o = decltype(O)::value;
+    if constexpr (!FP64)
+      if (pools) {
+        k.func = (const void *)k_pool32_batch<TRACE, l, t, o>;
+        return;
+      }
+    k.func = (const void *)k_batch<FP64, TRACE, l, t, o>;
+  }, lp.lds_exit, max_stage > 0, obs);
+  return k;
 }
 
 }  // namespace
@@ -1204,21 +1316,19 @@ int32_t batch_tile(bool fp64, int32_t kernel) {
   return (!fp64 && kernel == 1) ? kPoolPerBlock : kBlock;
 }
 
-hipError_t launch_batch(const GraphDev *graphs, const SetDev *sets,
-                        const BatchItem *items, int32_t n_items, int32_t max_nnz,
-                        int32_t max_stage, const StepArgs &a, bool fp64, bool trace,
-                        hipStream_t st) {
+KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
+                          const StepArgs &a, bool fp64, bool trace, bool obs) {
   if (fp64)
-    return trace ? launch_batch_t<true, true>(graphs, sets, items, n_items, max_nnz, max_stage, a, st)
-                 : launch_batch_t<true, false>(graphs, sets, items, n_items, max_nnz, max_stage, a, st);
-  return trace ? launch_batch_t<false, true>(graphs, sets, items, n_items, max_nnz, max_stage, a, st)
-               : launch_batch_t<false, false>(graphs, sets, items, n_items, max_nnz, max_stage, a, st);
+    return trace ? batch_launch_t<true, true>(n_items, max_nnz, max_stage, a, obs)
+                 : batch_launch_t<true, false>(n_items, max_nnz, max_stage, a, obs);
+  return trace ? batch_launch_t<false, true>(n_items, max_nnz, max_stage, a, obs)
+               : batch_launch_t<false, false>(n_items, max_nnz, max_stage, a, obs);
 }
 
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,
                             uint64_t *out, bool fp64, hipStream_t st) {
   const int64_t nbins = (int64_t)g.E * nb;
-  const bool lds = nbins <= kLdsExitMax;
+  const bool lds = nbins <= kLdsHistMax;
   uint32_t blocks = (s.n + kBlock - 1) / kBlock;
   if (lds && blocks > 1024) blocks = 1024;  // amortise the LDS merge
   if (!lds && blocks > 8192) blocks = 8192;

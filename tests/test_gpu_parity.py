@@ -358,3 +358,67 @@ def test_config4_batch_sample_against_oracle(B, orc):
         st = orc.init(graphs[i], n, 2, seed=i, tag=i, pids=rows)
         orc.simulate(graphs[i], st, 0, 300, run["dt"], 5, tag=i)
         _compare_fp64(st, B.mg_particles_read(s, trace=True), rows=rows, min_frac=1.0)
+
+
+def test_batch_graph_replays_equal_individual_runs(B):
+    """The batch's launch chain is a HIP graph kept across calls of the same
+    shape: replayed several times, with other eager work and reads between
+    the replays, and rebuilt when the shape changes, every call leaves the
+    sets bit-identical to the same sets advanced one by one."""
+    rng = np.random.default_rng(8)
+    graphs = [workloads.config2()[0], workloads.random_tree(30, rng, quadratic=True),
+              _absorbing_star()]
+    counts = [3000, 517, 129]
+    for prec in (B.MG_FP64, B.MG_FP32):
+        sets_b, sets_a = [], []
+        for i, (g, n) in enumerate(zip(graphs, counts)):
+            G = B.mg_graph_create(g)
+            kw = dict(init_seed=i + 1, precision=prec, graph_tag=10 + i, trace=True,
+                      max_splits=4, steps_per_launch=37)
+            sets_b.append(B.mg_particles_init(G, n, 2, **kw))
+            sets_a.append(B.mg_particles_init(G, n, 2, **kw))
+        b = B.mg_batch_create(sets_b)
+        other = B.mg_particles_init(B.mg_graph_create(graphs[1]), 777, 2, precision=prec)
+        for k, (steps, dt) in enumerate([(100, 1e-2), (100, 1e-2), (100, 1e-2), (41, 3e-3),
+                                         (100, 1e-2)]):
+            B.mg_batch_simulate(b, steps, dt, 21)
+            B.mg_simulate(other, 13, 1e-2, k)          # eager work between replays
+            for pa in sets_a:
+                B.mg_simulate(pa, steps, dt, 21)
+            for pa, pb in zip(sets_a, sets_b):
+                ra, rb = (B.mg_particles_read(pa, trace=True),
+                          B.mg_particles_read(pb, trace=True))
+                for f in ("edge", "x", "alive", "seqhash", "hits"):
+                    assert np.array_equal(ra[f], rb[f]), (prec, k, f)
+                for x, y in zip(B.mg_exit_counts(pa), B.mg_exit_counts(pb)):
+                    assert np.array_equal(x, y), (prec, k)
+                assert B.mg_particles_step(pa) == B.mg_particles_step(pb)
+
+
+def test_autotune_choice_and_auto_schedule_bitwise(B):
+    """Autotuning times the candidate schedules on a scratch copy: it leaves
+    the set untouched, reports a valid choice, and a set on the automatic
+    schedule gives the same bits as one on the fixed lane schedule."""
+    g, _ = workloads.config2()
+    G = B.mg_graph_create(g)
+    kw = dict(init_seed=4, precision=B.MG_FP32, trace=True)
+    auto = B.mg_particles_init(G, 70_000, 2, schedule=B.MG_SCHED_AUTO, **kw)
+    lanes = B.mg_particles_init(G, 70_000, 2, schedule=B.MG_SCHED_LANES, **kw)
+    before = B.mg_particles_read(auto, trace=True)
+    t = B.mg_autotune(auto, 1e-2, 3, 8)
+    after = B.mg_particles_read(auto, trace=True)
+    for f in before:
+        assert np.array_equal(before[f], after[f]), f
+    assert B.mg_particles_step(auto) == 0
+    assert t["schedule"] in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS)
+    assert t["n_probes"] == 5 and all(ms > 0 for ms in t["probe_ms"][:5])
+    if t["schedule"] == B.MG_SCHED_POOLS:
+        assert t["idle_trigger"] in (4, 8, 16, 32)
+    for dt in (1e-2, 1e-3):              # 1e-3 is tuned on its first call
+        B.mg_simulate(auto, 150, dt, 9)
+        B.mg_simulate(lanes, 150, dt, 9)
+    ra, rl = B.mg_particles_read(auto, trace=True), B.mg_particles_read(lanes, trace=True)
+    for f in ra:
+        assert np.array_equal(ra[f], rl[f]), f
+    for x, y in zip(B.mg_exit_counts(auto), B.mg_exit_counts(lanes)):
+        assert np.array_equal(x, y)

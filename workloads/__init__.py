@@ -27,7 +27,7 @@ import numpy as np
 
 __all__ = [
     "GraphDesc", "from_edges", "star_graph", "segment", "random_tree",
-    "config1", "config2", "config3", "config4", "paper_star5",
+    "config1", "config2", "config3", "config4", "config5", "paper_star5",
 ]
 
 
@@ -382,4 +382,19 @@ def config4(seed: int = 4) -> tuple[list, list, dict]:
         counts.append(int(np.rint(np.exp(rng.uniform(np.log(1e4), np.log(1e6))))))
     run = dict(init="uniform", dt=1e-3, n_steps=1000, max_splits=8, seed=0,
                bins=64)
+    return graphs, counts, run
+
+
+def config5() -> tuple[list, list, dict]:
+    """Accuracy sweep: config 3's network plus 128 config-2-style stars
+    (seeds 5000..5127), advanced together as one batch at each dt in
+    {1e-2, 3e-3, 1e-3, 3e-4} over a fixed horizon (stars T = 2, network
+    T = 0.05 in its diffusive time unit); 1e8 particles on the network and
+    1e8 split evenly over the stars per dt."""
+    net, run3 = config3()
+    stars = [config2(seed)[0] for seed in range(5000, 5128)]
+    graphs = [net] + stars
+    counts = [100_000_000] + [100_000_000 // 128] * 128
+    run = dict(dts=(1e-2, 3e-3, 1e-3, 3e-4), horizons=[0.05] + [2.0] * 128,
+               init="uniform", max_splits=8, seed=0, bins=[64] + [256] * 128)
     return graphs, counts, run
