@@ -68,10 +68,17 @@ def exit_probs(ex, offsets):
     return p
 
 
-def run_pass(B, G, g, run, prec, dt, torch, kernel_times):
-    """One pass of the path at one dt: init, simulate, exit counts, histogram."""
+def run_pass(B, G, g, run, prec, dt, torch, kernel_times, schedules=None):
+    """One pass of the path at one dt: init, schedule tuning (FP32), simulate,
+    exit counts, histogram.  kernel_times gets the HIP-event time of the
+    step launches alone."""
     p = B.mg_particles_init(G, run["n_particles"], B.MG_INIT_UNIFORM_LENGTH, init_seed=0,
                             precision=prec, max_splits=run["max_splits"])
+    if prec == B.MG_FP32:
+        t = B.mg_autotune(p, dt, run["seed"])
+        if schedules is not None:
+            schedules.append("k_pool32" if t["schedule"] == B.MG_SCHED_POOLS
+                             else "k_step<fp32>")
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -356,6 +363,62 @@ def run_density(args, B, torch):
             "runs": rows}
 
 
+def run_nohit(args, B, torch):
+    """The step kernel's no-hit ceiling: 1e7 FP32 particles in the middle of
+    one edge of length 1e9 (sigma = sqrt(2)), 2000 steps at dt = 1e-3, so no
+    move reaches a vertex; the same launch path as the metric's workload."""
+    import numpy as np
+    import workloads
+    g = workloads.segment(1e9, 0.0, 0.0, np.sqrt(2.0))
+    G = B.mg_graph_create(g)
+    n, steps, dt = 10_000_000, 2000, 1e-3
+    ktimes, walls, res = [], [], None
+    for it in range(args.warmup + args.steps):
+        p = B.mg_particles_init(G, n, B.MG_INIT_EXPLICIT, edge=np.zeros(n, np.int32),
+                                pos=np.full(n, 5e8), precision=B.MG_FP32)
+        t = B.mg_autotune(p, dt, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        B.mg_simulate(p, steps, dt, 0)
+        e1.record()
+        tot = B.mg_exit_counts(p)[2]
+        wall = time.perf_counter() - t0
+        if it >= args.warmup:
+            ktimes.append(e0.elapsed_time(e1) * 1e-3)
+            walls.append(wall)
+            res = tot
+        del p
+    k = float(np.mean(ktimes))
+    achieved = ALG_FP32_STEP * float(res[3]) / k
+    kern = "k_pool32" if t["schedule"] == B.MG_SCHED_POOLS else "k_step<fp32>"
+    return {"metric": METRIC, "value": float(res[1]) / float(np.mean(walls)),
+            "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": float(np.mean(walls)) * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "nohit_segment: 1e7 particles mid-edge of a 1e9-long "
+                                   "segment, 2000 steps at dt=1e-3, no vertex hits"},
+            "hits": int(res[2]),
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                         "peak": PEAK_LANE_OPS / 1e12, "unit": "T VALU lane-ops/s",
+                         "frac": achieved / PEAK_LANE_OPS, "traffic": None, "kernel": kern,
+                         "kernel_ms_per_launch": k * 1e3}}
+
+
+def calibrate_copy(torch):
+    """A 1 GiB device-to-device copy: the kernel of known size that HBM
+    counter readings (FETCH_SIZE, WRITE_SIZE) are scaled by."""
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -364,9 +427,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
     ap.add_argument("--cpu-sample", type=int, default=40_000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB on the device (scale for HBM counters)")
     ap.add_argument("--workload", default="langevin_star64",
                     choices=["langevin_star64", "vascular20k", "batch512", "accuracy_sweep",
-                             "density_error"],
+                             "density_error", "nohit_segment"],
                     help="the metric's configuration (default) or another workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -383,6 +448,11 @@ def main():
     from paper_2512_02175_amd import binding as B
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+    if args.workload == "nohit_segment":
+        print(json.dumps(run_nohit(args, B, torch)), flush=True)
+        return
     if args.workload == "vascular20k":
         print(json.dumps(run_vascular(args, B, torch)), flush=True)
         return
@@ -399,8 +469,10 @@ def main():
     G = B.mg_graph_create(g)
     dts = run["dts"]
 
+    scheds = []
+
     def step(prec, ktimes):
-        return [run_pass(B, G, g, run, prec, dt, torch, ktimes) for dt in dts]
+        return [run_pass(B, G, g, run, prec, dt, torch, ktimes, scheds) for dt in dts]
 
     # FP32: the headline path
     for _ in range(args.warmup):
@@ -445,7 +517,7 @@ def main():
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
             "traffic": kernel_traffic(),
-            "kernel": "k_step<fp32>", "kernel_ms_per_launch": k32 * 1e3,
+            "kernel": "/".join(sorted(set(scheds))), "kernel_ms_per_launch": k32 * 1e3,
             "alg_lane_ops_per_particle_step": ALG_FP32_STEP,
             "alg_lane_ops_per_hit": ALG_FP32_HIT}
 

@@ -95,8 +95,9 @@ void mg_graph_destroy(mg_graph *g);
  * Options of a particle set.
  *   precision     MG_FP64 (reference arithmetic) or MG_FP32 (positions held
  *                 relative to the nearer edge end, compensated remaining
- *                 time, FP64 crossing solve within 1e-6 L of a vertex).
- *   max_splits    M >= 1, the most vertex hits per step (0: default 8).
+ *                 time, FP64 crossing solve within 1e-6 L of a vertex,
+ *                 off the vertex itself).
+ *   max_splits    M in [1, 255], the most vertex hits per step (0: default 8).
  *   graph_tag     fourth Philox counter word; independent streams for sets
  *                 that share seeds (e.g. the members of a batch).
  *   trace         nonzero: keep a per-particle hit-sequence hash and hit
@@ -169,6 +170,21 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
  */
 mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge,
                        uint64_t *out, int64_t out_len);
+
+/*
+ * Histogram over per-edge bins of any count and widths (appendix kernels,
+ * the general histogram): edge e owns bins bin_offsets[e] ..
+ * bin_offsets[e+1] - 1 (bin_offsets[E+1], bin_offsets[0] = 0, at least one
+ * bin per edge), whose upper boundaries bin_upper[] (FP64, measured from the
+ * edge's initial vertex) increase strictly from 0 along the edge; the last
+ * one is normally L_e.  An alive particle at x goes to the first bin of its
+ * edge whose upper boundary is >= x, or to the edge's last bin if x exceeds
+ * them all.  bin_offsets and bin_upper are host arrays, copied per call;
+ * out[bin_offsets[E]] (host or device).  Allocates device memory for the
+ * bin tables; synchronises the stream.
+ */
+mg_status mg_histogram_csr(const mg_particles *p, const int32_t *bin_offsets,
+                           const double *bin_upper, uint64_t *out, int64_t out_len);
 
 /*
  * Streamed (time-averaged) histogram, accumulated inside the step kernels.

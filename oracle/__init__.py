@@ -318,3 +318,30 @@ def density_l2(lengths, bins: int, counts, ref_density, mass: float = 0.0) -> fl
     total = float(mass) if mass > 0 else float(np.asarray(counts, np.uint64).sum())
     w = (L / bins)[:, None]
     return float(np.sqrt(np.sum(w * (c / (total * w) - r) ** 2)))
+
+
+def histogram_csr(g, st: State, bin_offsets, bin_upper) -> np.ndarray:
+    """Histogram over per-edge bins of any widths and counts (the appendix's
+    general histogram kernel): the bins of edge e are bin_offsets[e] ..
+    bin_offsets[e+1]-1, with upper boundaries bin_upper (nondecreasing along
+    the edge, the last one L_e).  A particle at x goes to the first bin of its
+    edge whose upper boundary is >= x, or to the edge's last bin if none is
+    (bins have positive widths, so this is the listing's scan over
+    accumulated bin lengths).  Written as that scan, one particle at a
+    time."""
+    g = as_graph(g)
+    off = np.asarray(bin_offsets, np.int64)
+    up = np.asarray(bin_upper, np.float64)
+    out = np.zeros(int(off[-1]), np.uint64)
+    for i in range(st.pid.size):
+        if not st.alive[i]:
+            continue
+        e = int(st.edge[i])
+        x = float(st.x[i])
+        b = int(off[e + 1]) - 1
+        for k in range(int(off[e]), int(off[e + 1])):
+            if x <= up[k]:
+                b = k
+                break
+        out[b] += 1
+    return out

@@ -26,7 +26,8 @@ EXPORTED = (
     "mg_graph_create", "mg_graph_destroy", "mg_particles_arena_bytes",
     "mg_particles_init", "mg_particles_destroy", "mg_simulate", "mg_histogram",
     "mg_exit_counts", "mg_particles_read", "mg_particles_step", "mg_batch_create",
-    "mg_batch_simulate", "mg_batch_destroy", "mg_autotune", "mg_observe_histogram",
+    "mg_batch_simulate", "mg_batch_destroy", "mg_autotune", "mg_histogram_csr",
+    "mg_observe_histogram",
     "mg_observed_histogram", "mg_density_l2", "mg_last_error",
 )
 
@@ -91,6 +92,7 @@ def lib() -> C.CDLL:
         L.mg_batch_destroy.argtypes = [vp]
         L.mg_batch_destroy.restype = None
         L.mg_autotune.argtypes = [vp, C.c_double, u64, i32, vp]
+        L.mg_histogram_csr.argtypes = [vp, vp, vp, vp, i64]
         L.mg_observe_histogram.argtypes = [vp, i32, i32]
         L.mg_observed_histogram.argtypes = [vp, vp, i64, vp]
         L.mg_density_l2.argtypes = [vp, i32, vp, C.c_double, vp, vp]
@@ -262,6 +264,16 @@ def mg_histogram(p: Particles, bins_per_edge: int, out=None):
         _check(lib().mg_histogram(p.handle, int(bins_per_edge), C.c_void_p(out.data_ptr()),
                                   out.numel()))
     return out
+
+
+def mg_histogram_csr(p: Particles, bin_offsets, bin_upper) -> np.ndarray:
+    """Histogram over per-edge bins of any widths: bin_offsets[E+1] (CSR) and
+    the bins' upper boundaries; returns counts[bin_offsets[E]]."""
+    off = np.ascontiguousarray(np.asarray(bin_offsets, np.int32))
+    up = np.ascontiguousarray(np.asarray(bin_upper, np.float64))
+    out = np.zeros(max(int(off[-1]), 1), np.uint64)
+    _check(lib().mg_histogram_csr(p.handle, _p(off), _p(up), _p(out), out.size))
+    return out[: int(off[-1])]
 
 
 def mg_observe_histogram(p: Particles, bins_per_edge: int, every: int) -> None:

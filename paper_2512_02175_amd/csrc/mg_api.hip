@@ -392,7 +392,8 @@ mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
   o.precision = MG_FP64;
   if (opt) o = *opt;
   if (o.precision != MG_FP64 && o.precision != MG_FP32) return fail(MG_EINVAL, "unknown precision");
-  if (o.max_splits < 0) return fail(MG_EINVAL, "max_splits must be >= 0 (0: default)");
+  if (o.max_splits < 0 || o.max_splits > 255)
+    return fail(MG_EINVAL, "max_splits must be in [0, 255] (0: default)");
   if (o.max_splits == 0) o.max_splits = 8;
   if (o.steps_per_launch < 0) return fail(MG_EINVAL, "steps_per_launch must be >= 0");
   if (o.schedule < MG_SCHED_AUTO || o.schedule > MG_SCHED_POOLS)
@@ -576,6 +577,54 @@ mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge, uint64_t *o
     he = hipMemcpyAsync(out, d_out, (size_t)need * 8, hipMemcpyDeviceToHost, p->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
   if (!dev_out) (void)hipFree(d_out);
+  if (he != hipSuccess) return hip_fail(he, "computing the histogram");
+  return check_device_error(p);
+}
+
+mg_status mg_histogram_csr(const mg_particles *p, const int32_t *bin_offsets,
+                           const double *bin_upper, uint64_t *out, int64_t out_len) {
+  g_err.clear();
+  if (!p || !bin_offsets || !bin_upper || !out) return fail(MG_EINVAL, "NULL argument");
+  const int32_t E = p->g->E;
+  if (bin_offsets[0] != 0) return fail(MG_EINVAL, "bin_offsets[0] must be 0");
+  for (int32_t e = 0; e < E; ++e) {
+    if (bin_offsets[e + 1] <= bin_offsets[e])
+      return fail(MG_EINVAL, "edge %d has no bins (offsets must increase)", e);
+    double prev = 0.0;
+    for (int32_t k = bin_offsets[e]; k < bin_offsets[e + 1]; ++k) {
+      if (!is_finite(bin_upper[k]) || !(bin_upper[k] > prev))
+        return fail(MG_EINVAL, "bin %d of edge %d: upper boundaries must be finite and "
+                    "strictly increasing from 0", k - bin_offsets[e], e);
+      prev = bin_upper[k];
+    }
+  }
+  const int64_t nbins = bin_offsets[E];
+  if (out_len < nbins)
+    return fail(MG_EINVAL, "out_len %lld < bin_offsets[E] = %lld", (long long)out_len,
+                (long long)nbins);
+  const bool dev_out = is_device_pointer(out);
+  const size_t o_off = 0, o_up = align_up(sizeof(int32_t) * (E + 1), 256),
+               o_out = align_up(o_up + sizeof(double) * nbins, 256),
+               total = o_out + (dev_out ? 0 : sizeof(uint64_t) * nbins);
+  char *mem = nullptr;
+  MG_HIP(hipMalloc(&mem, total), "allocating the bin tables");
+  int32_t *d_off = (int32_t *)(mem + o_off);
+  double *d_up = (double *)(mem + o_up);
+  uint64_t *d_out = dev_out ? out : (uint64_t *)(mem + o_out);
+  hipError_t he = hipMemcpyAsync(d_off, bin_offsets, sizeof(int32_t) * (E + 1),
+                                 hipMemcpyHostToDevice, p->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(d_up, bin_upper, sizeof(double) * nbins, hipMemcpyHostToDevice,
+                        p->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(d_out, 0, sizeof(uint64_t) * nbins, p->stream);
+  if (he == hipSuccess)
+    he = launch_histogram_csr(p->g->gd, p->sd, d_off, d_up, (int32_t)nbins, d_out,
+                              p->prec == MG_FP64, p->stream);
+  if (he == hipSuccess && !dev_out)
+    he = hipMemcpyAsync(out, d_out, sizeof(uint64_t) * nbins, hipMemcpyDeviceToHost,
+                        p->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
+  (void)hipFree(mem);
   if (he != hipSuccess) return hip_fail(he, "computing the histogram");
   return check_device_error(p);
 }

@@ -152,5 +152,8 @@ KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
                           const StepArgs &a, bool fp64, bool trace, bool obs);
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,
                             uint64_t *out, bool fp64, hipStream_t st);
+hipError_t launch_histogram_csr(const GraphDev &g, const SetDev &s, const int32_t *off,
+                                const double *up, int32_t nbins, uint64_t *out, bool fp64,
+                                hipStream_t st);
 
 }  // namespace mg

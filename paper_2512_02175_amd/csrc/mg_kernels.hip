@@ -261,14 +261,6 @@ __device__ __forceinline__ void observe(const P &q, const SetDev &S, const ObsSi
     atomicAdd((unsigned long long *)&S.obs[idx], 1ull);
 }
 
-template <typename T, int N>
-__device__ __forceinline__ T pickw(const T (&W)[N], uint32_t j) {
-  T w = W[0];
-#pragma unroll
-  for (int i = 1; i < N; ++i) w = (j == (uint32_t)i) ? W[i] : w;
-  return w;
-}
-
 // Step loop shared by both precisions.  P is a per-lane particle (FP64 or
 // FP32) with
 //   bool fast(W)                    first sub-step of a step (h = dt); true if
@@ -308,12 +300,16 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
     }
     const uint32_t jb = n - base;
     const uint32_t je = min(NW, n_end - base);
+    // The window's normals stay in registers: every access below has a
+    // compile-time index, and the normal of a parked step travels in wp.
     int32_t pj = -1;
+    typename P::real wp = 0;
 #pragma unroll
     for (uint32_t j = 0; j < NW; ++j) {
       if (j < jb || j >= je || pj >= 0) continue;
       if (!q.fast(W[j])) {
         pj = (int32_t)j;
+        wp = W[j];
       } else {
         if ((j & 3u) == 3u) q.reanchor();
         snapshot(base + j + 1u);
@@ -321,19 +317,22 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
     }
     while (pj >= 0) {
       const uint32_t j0 = (uint32_t)pj;
-      q.resolve(base + j0, pickw(W, j0), pid, S, A, t);
+      q.resolve(base + j0, wp, pid, S, A, t);
       if (q.alive) {
         if ((j0 & 3u) == 3u) q.reanchor();
         snapshot(base + j0 + 1u);
       }
       pj = -1;
-      for (uint32_t j = j0 + 1; j < je && q.alive; ++j) {
-        if (!q.fast(pickw(W, j))) {
+#pragma unroll
+      for (uint32_t j = 1; j < NW; ++j) {
+        if (j <= j0 || j >= je || !q.alive || pj >= 0) continue;
+        if (!q.fast(W[j])) {
           pj = (int32_t)j;
-          break;
+          wp = W[j];
+        } else {
+          if ((j & 3u) == 3u) q.reanchor();
+          snapshot(base + j + 1u);
         }
-        if ((j & 3u) == 3u) q.reanchor();
-        snapshot(base + j + 1u);
       }
     }
     n = base + je;
@@ -479,8 +478,9 @@ __device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const St
 // increment, computed at the increment's own magnitude, with the rounding
 // error of the sum carried in yl (Fast2Sum, Dekker), so positions do not
 // collect one rounding of y per step.  The remaining time is a compensated
-// pair (hh, hl) too; the crossing solve runs in FP64 within 1e-6 L of a
-// vertex.
+// pair (hh, hl) too; the crossing solve runs in FP64 when the particle is
+// within 1e-6 L of the vertex but not on it (on it the root is one
+// division).
 struct Edge32 {
   float L, a, c, sigma, aL;
   int32_t vinit, vterm;
@@ -490,6 +490,14 @@ __device__ __forceinline__ Edge32 load_edge32(const EdgeRec32 *e32, int32_t e) {
   const EdgeRec32 r = e32[e];
   return {r.L, r.a, r.c, r.sigma, r.aL, r.vinit, r.vterm};
 }
+
+// Resolution state of an FP32 step whose sub-step reached a vertex:
+// remaining time (compensated pair), the pending sub-step's normal, the
+// crossings so far and the last slot drawn.
+struct Hit32 {
+  float hh, hl, w;
+  int32_t k, last;
+};
 
 template <bool TRACE, bool LDS>
 struct Particle32 {
@@ -563,88 +571,108 @@ struct Particle32 {
     return in;
   }
 
+  // One vertex crossing of a step whose current sub-step proposal (normal
+  // h.w over the remaining time h.hh + h.hl; the step's first sub-step when
+  // h.k == 0) reached a vertex: crossing time, edge draw, and the next
+  // sub-step's proposal.  Returns true when the step is complete (inside an
+  // edge, absorbed, out of time or at the split cap), false when the next
+  // proposal reaches a vertex again.  resolve() loops over it; the wave
+  // pools run one crossing per lane per pass.
+  __device__ bool cross(uint32_t step, Hit32 &h, uint32_t pid, const SetDev &S,
+                        const StepArgs &A, Tally &t) {
+    float hh = h.hh, hl = h.hl;
+    // the pending proposal, recomputed as it was made
+    const float we = (y == 0.0f) ? fabsf(h.w) : (side ? -h.w : h.w);
+    const float mu = fmaf(R.c, y, as);
+    const float g = h.k == 0 ? g0 : R.sigma * __builtin_amdgcn_sqrtf(hh);
+    float err;
+    const float yt = add_comp(fmaf(g, we, mu * hh) + yl, err);
+    const bool near = yt <= 0.0f;
+    const bool at_term = near == (side != 0u);
+    const int32_t v = at_term ? R.vterm : R.vinit;
+    const float dn = y + yl;
+    const float d = fmaxf(near ? dn : (R.L - y) - yl, 0.0f);
+    float u;
+    if (d > 0.0f && d < 1e-6f * R.L) {
+      // crossing solve in FP64 next to the vertex (on the vertex itself,
+      // d = 0, the root is -B/A: one division, no cancellation)
+      const double hd = (double)hh + (double)hl;
+      const double mud = fma((double)R.c, (double)y, (double)as);
+      const double gd = (double)R.sigma * sqrt(hd);
+      const double qa = near ? mud * hd : -(mud * hd);
+      const double qb = near ? gd * (double)we : -(gd * (double)we);
+      const double yd = (double)y + (double)yl;
+      const double dd = fmax(near ? yd : (double)R.L - yd, 0.0);
+      u = (float)first_root64(qa, qb, dd);
+    } else {
+      const float mh = mu * hh, gw = g * we;
+      u = first_root32(near ? mh : -mh, near ? gw : -gw, d);
+    }
+    // remaining time (1 - u^2)(hh + hl), compensated (TwoProduct by fma,
+    // TwoSum, renormalised)
+    {
+      const float al = u * u;
+      const float p = al * hh;
+      const float pe = fmaf(al, hh, -p);
+      const float s = hh - p;
+      const float bb = s - hh;
+      const float se = (hh - (s - bb)) + (-p - bb);
+      const float lo = ((se - pe) + hl) - al * hl;
+      hh = s + lo;
+      hl = lo - (hh - s);
+    }
+    h.hh = hh;
+    h.hl = hl;
+    ++h.k;
+    ++nhit;
+    t.hits++;
+    const VtxBlk vb = G.vtx[v];
+    if (vb.deg < 0) {
+      alive = false;
+      death_step = step;
+      atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
+      if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
+      return true;
+    }
+    const U4 hd = philox(pid, step, (uint32_t)h.k, S.tag, A.key0, A.key1);
+    const SlotPick sp = pick_slot(G, vb, hd.x);
+    e = eo_edge(sp.eo);
+    R = load_edge32(G.e32, e);
+    side = sp.eo & 1u;
+    y = 0.0f;
+    yl = 0.0f;
+    as = side ? -R.aL : R.a;
+    g0 = R.sigma * sqdt;
+    h.last = sp.s;
+    if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)sp.s);
+    bool done = hh == 0.0f;
+    if (!done && h.k == A.max_splits) {
+      t.trunc++;
+      done = true;
+    }
+    if (!done) {
+      // the next sub-step, from the vertex (normal folded into the edge)
+      h.w = box_muller32_cos(hd.y, hd.z);
+      const float mu2 = fmaf(R.c, y, as);
+      const float g2 = R.sigma * __builtin_amdgcn_sqrtf(hh);
+      float err2;
+      const float yt2 = add_comp(fmaf(g2, fabsf(h.w), mu2 * hh) + yl, err2);
+      t.sub++;
+      if (yt2 > 0.0f && yt2 < R.L) {
+        y = yt2;
+        yl = err2;
+        done = true;
+      }
+    }
+    if (done) count_exit<LDS>(s_exit, S.exit_cnt, h.last);
+    return done;
+  }
+
   __device__ void resolve(uint32_t step, float w, uint32_t pid, const SetDev &S,
                           const StepArgs &A, Tally &t) {
-    float hh = dt, hl = 0.0f;
-    int32_t k = 0, last = -1;
-    bool first = true;
-    for (;;) {
-      const float we = (y == 0.0f) ? fabsf(w) : (side ? -w : w);
-      const float mu = fmaf(R.c, y, as);
-      const float g = first ? g0 : R.sigma * __builtin_amdgcn_sqrtf(hh);
-      float err;
-      const float yt = add_comp(fmaf(g, we, mu * hh) + yl, err);
-      if (!first) t.sub++;
-      first = false;
-      if (yt > 0.0f && yt < R.L) {
-        y = yt;
-        yl = err;
-        break;
-      }
-      const bool near = yt <= 0.0f;
-      const bool at_term = near == (side != 0u);
-      const int32_t v = at_term ? R.vterm : R.vinit;
-      const float dn = y + yl;
-      const float d = fmaxf(near ? dn : (R.L - y) - yl, 0.0f);
-      float u;
-      if (d < 1e-6f * R.L) {
-        // crossing solve in FP64 next to the vertex
-        const double hd = (double)hh + (double)hl;
-        const double mud = fma((double)R.c, (double)y, (double)as);
-        const double gd = (double)R.sigma * sqrt(hd);
-        const double qa = near ? mud * hd : -(mud * hd);
-        const double qb = near ? gd * (double)we : -(gd * (double)we);
-        const double yd = (double)y + (double)yl;
-        const double dd = fmax(near ? yd : (double)R.L - yd, 0.0);
-        u = (float)first_root64(qa, qb, dd);
-      } else {
-        const float mh = mu * hh, gw = g * we;
-        u = first_root32(near ? mh : -mh, near ? gw : -gw, d);
-      }
-      // remaining time (1 - u^2)(hh + hl), compensated (TwoProduct by fma,
-      // TwoSum, renormalised)
-      {
-        const float al = u * u;
-        const float p = al * hh;
-        const float pe = fmaf(al, hh, -p);
-        const float s = hh - p;
-        const float bb = s - hh;
-        const float se = (hh - (s - bb)) + (-p - bb);
-        const float lo = ((se - pe) + hl) - al * hl;
-        hh = s + lo;
-        hl = lo - (hh - s);
-      }
-      ++k;
-      ++nhit;
-      t.hits++;
-      const VtxBlk vb = G.vtx[v];
-      if (vb.deg < 0) {
-        alive = false;
-        death_step = step;
-        atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
-        if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
-        break;
-      }
-      const U4 hd = philox(pid, step, (uint32_t)k, S.tag, A.key0, A.key1);
-      const SlotPick sp = pick_slot(G, vb, hd.x);
-      const int32_t s = sp.s;
-      e = eo_edge(sp.eo);
-      R = load_edge32(G.e32, e);
-      side = sp.eo & 1u;
-      y = 0.0f;
-      yl = 0.0f;
-      as = side ? -R.aL : R.a;
-      g0 = R.sigma * sqdt;
-      last = s;
-      if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)s);
-      if (hh == 0.0f) break;
-      if (k == A.max_splits) {
-        t.trunc++;
-        break;
-      }
-      w = box_muller32_cos(hd.y, hd.z);
+    Hit32 h{dt, 0.0f, w, 0, -1};
+    while (!cross(step, h, pid, S, A, t)) {
     }
-    if (k >= 1 && alive) count_exit<LDS>(s_exit, S.exit_cnt, last);
   }
 };
 
@@ -791,9 +819,12 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
 // iteration; a particle whose sub-step reaches a vertex is parked: its state
 // goes to its home slot and its slot id onto the wave's split stack, and the
 // lane takes a ready particle instead.  When 64 particles are parked (or
-// lanes would idle), one split pass resolves them with every lane busy:
-// crossing time, Philox hit stream, slot draw, continuation sub-steps, exit
-// record, and puts them back on the ready stack.  Each particle still
+// lanes would idle), one split pass takes them with every lane busy and
+// resolves one vertex crossing each: crossing time, Philox hit stream, slot
+// draw and the next sub-step's proposal.  A particle whose step is then
+// complete goes back on the ready stack (with its exit record); one whose
+// proposal reaches a vertex again goes back on the split stack, so a pass
+// never waits for the lane with the most crossings.  Each particle still
 // consumes exactly the random numbers of its own (step, hit) counters, so the
 // results equal the plain per-particle order bit for bit.  Waves never wait
 // for one another: the stacks and their counts are private to a wave.
@@ -801,14 +832,27 @@ constexpr int kWavesPerBlock = kBlock / 64;
 static_assert(kPoolPerWave % 64 == 0 && kPoolPerWave >= 128 && kPoolPerWave <= 256,
               "a wave pool holds 2 to 4 particles per lane");
 
-struct PoolLds32 {
+template <bool TRACE>
+struct PoolTrace {
+  uint32_t hits[kPoolPerWave];
+  uint64_t hash[kPoolPerWave];
+};
+template <>
+struct PoolTrace<false> {};
+
+// A wave's pool in LDS: home slots of its particles, the resolution state
+// of parked steps, and the ready and split stacks (slot ids).
+template <bool TRACE>
+struct PoolLds32 : PoolTrace<TRACE> {
   uint32_t ef[kPoolPerWave];
   float y[kPoolPerWave];
   float yl[kPoolPerWave];
   uint32_t n[kPoolPerWave];   // next step (ready) or the step to resolve (parked)
-  float w[kPoolPerWave];      // first sub-step normal of a parked step
-  uint32_t hits[kPoolPerWave];
-  uint64_t hash[kPoolPerWave];
+  float w[kPoolPerWave];      // normal of a parked step's pending sub-step
+  float hh[kPoolPerWave];     // remaining time of a parked step (when k > 0)
+  float hl[kPoolPerWave];
+  int32_t last[kPoolPerWave]; // last slot drawn in the parked step
+  uint8_t k[kPoolPerWave];    // crossings so far in the parked step
   uint8_t ready[kPoolPerWave];
   uint8_t split[kPoolPerWave];
 };
@@ -824,7 +868,7 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 __device__ __forceinline__ void wave_lds_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
 template <bool TRACE, bool LDS>
-__device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolLds32 &P,
+__device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolLds32<TRACE> &P,
                                           uint32_t s) {
   const uint32_t ef = P.ef[s];
   q.e = (int32_t)(ef & kEdgeMask);
@@ -835,20 +879,20 @@ __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolL
   q.as = q.side ? -q.R.aL : q.R.a;
   q.g0 = q.R.sigma * q.sqdt;
   q.alive = true;
-  if (TRACE) {
+  if constexpr (TRACE) {
     q.nhit = P.hits[s];
     q.hash = P.hash[s];
   }
 }
 
 template <bool TRACE, bool LDS>
-__device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS> &q, PoolLds32 &P,
+__device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS> &q, PoolLds32<TRACE> &P,
                                            uint32_t s, uint32_t n) {
   P.ef[s] = (uint32_t)q.e | (q.side ? kSideBit : 0u);
   P.y[s] = q.y;
   P.yl[s] = q.yl;
   P.n[s] = n;
-  if (TRACE) {
+  if constexpr (TRACE) {
     P.hits[s] = q.nhit;
     P.hash[s] = q.hash;
   }
@@ -870,7 +914,7 @@ __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS> &q, con
 
 template <bool TRACE, bool LDS, bool OBS>
 __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
-                           const StepArgs &A, uint32_t base, PoolLds32 &P,
+                           const StepArgs &A, uint32_t base, PoolLds32<TRACE> &P,
                            uint32_t *s_exit, Tally &t, const ObsSink &sink) {
   const uint32_t lane = threadIdx.x & 63u;
   const float dt = (float)A.dt;
@@ -912,7 +956,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         P.ef[s] = ef;
         P.y[s] = y;
         P.yl[s] = yl;
-        if (TRACE) {
+        if constexpr (TRACE) {
           P.hits[s] = S.hits[pid];
           P.hash[s] = S.seqhash[pid];
         }
@@ -930,7 +974,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         P.y[s] = y;
         P.yl[s] = yl;
         P.n[s] = S.n0;
-        if (TRACE) {
+        if constexpr (TRACE) {
           P.hits[s] = S.hits[pid];
           P.hash[s] = S.seqhash[pid];
         }
@@ -1007,6 +1051,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       if (parked) {
         pool_store(q, P, slot, n);
         P.w[slot] = wp;
+        P.k[slot] = 0;  // fresh: hh = dt, hl = 0, no slot drawn yet
         P.split[split_cnt + lane_rank(m_park)] = (uint8_t)slot;
         has = false;
       }
@@ -1019,12 +1064,11 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
     if (do_split) {
       // The lanes' own particles wait in their home slots during the pass.
       if (has) pool_store(q, P, slot, n);
-      // Resolve up to 64 parked particles, one per lane: crossing time,
-      // edge draw, continuation sub-steps to the end of the parked step.
+      // Up to 64 parked particles, one per lane, one crossing each.
       const uint32_t B = min(split_cnt, 64u);
       split_cnt -= B;
       wave_lds_fence();
-      bool back = false;
+      bool back = false, again = false;
       uint32_t s2 = 0;
       if (lane < B) {
         s2 = P.split[split_cnt + lane];
@@ -1032,19 +1076,38 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
                                   sqdt, true, 0ull, 0u, 0u};
         pool_load(q2, P, s2);
         const uint32_t step = P.n[s2];
-        q2.resolve(step, P.w[s2], base + s2, S, A, t);
-        if (q2.alive) {
-          if ((step & 3u) == 3u) q2.reanchor();
-          if (OBS && step + 1u == next_snapshot(step, S)) observe(q2, S, sink);
+        Hit32 h{dt, 0.0f, P.w[s2], (int32_t)P.k[s2], -1};
+        if (h.k > 0) {
+          h.hh = P.hh[s2];
+          h.hl = P.hl[s2];
+          h.last = P.last[s2];
         }
-        const uint32_t n2 = step + 1u;
-        if (!q2.alive || n2 == n_end) {
-          pool_finish(q2, S, A, base + s2, t);
+        if (!q2.cross(step, h, base + s2, S, A, t)) {
+          // reached a vertex again: back on the split stack for the next pass
+          pool_store(q2, P, s2, step);
+          P.w[s2] = h.w;
+          P.hh[s2] = h.hh;
+          P.hl[s2] = h.hl;
+          P.last[s2] = h.last;
+          P.k[s2] = (uint8_t)h.k;
+          again = true;
         } else {
-          pool_store(q2, P, s2, n2);
-          back = true;
+          if (q2.alive) {
+            if ((step & 3u) == 3u) q2.reanchor();
+            if (OBS && step + 1u == next_snapshot(step, S)) observe(q2, S, sink);
+          }
+          const uint32_t n2 = step + 1u;
+          if (!q2.alive || n2 == n_end) {
+            pool_finish(q2, S, A, base + s2, t);
+          } else {
+            pool_store(q2, P, s2, n2);
+            back = true;
+          }
         }
       }
+      const uint64_t m_again = __ballot(again);
+      if (again) P.split[split_cnt + lane_rank(m_again)] = (uint8_t)s2;
+      split_cnt += (uint32_t)__popcll(m_again);
       const uint64_t m_back = __ballot(back);
       if (back) P.ready[ready_cnt + lane_rank(m_back)] = (uint8_t)s2;
       ready_cnt += (uint32_t)__popcll(m_back);
@@ -1070,10 +1133,10 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
   const int32_t ex = LDS ? exit_bytes(G.nnz) : 0;
   const GView view = block_view<false, STAGED>(G, smem + ex);
   const int32_t o_pools = align16(ex + (STAGED ? G.stage_bytes32 : 0));
-  PoolLds32 *pools = (PoolLds32 *)(smem + o_pools);
+  PoolLds32<TRACE> *pools = (PoolLds32<TRACE> *)(smem + o_pools);
   ObsSink o{nullptr, G.e64};
   if (OBS && A.obs_lds) {
-    o.lds = (uint32_t *)(smem + o_pools + (int32_t)sizeof(PoolLds32) * kWavesPerBlock);
+    o.lds = (uint32_t *)(smem + o_pools + (int32_t)sizeof(PoolLds32<TRACE>) * kWavesPerBlock);
     for (int32_t b = threadIdx.x; b < A.obs_lds; b += blockDim.x) o.lds[b] = 0;
   }
   __syncthreads();
@@ -1198,6 +1261,53 @@ __global__ __launch_bounds__(kBlock) void k_hist(GraphDev G, SetDev S, int32_t n
   }
 }
 
+// Histogram over per-edge bins of any widths (the appendix's general
+// histogram kernel): the bins of edge e are off[e] .. off[e+1]-1 with upper
+// boundaries up[] (FP64, strictly increasing along the edge).  A particle at
+// x takes the first bin whose upper boundary is >= x (binary search), or the
+// edge's last bin.
+template <bool FP64, bool LDS>
+__global__ __launch_bounds__(kBlock) void k_hist_csr(GraphDev G, SetDev S, const int32_t *off,
+                                                     const double *up, int32_t nbins,
+                                                     uint64_t *out) {
+  extern __shared__ uint32_t s_bin[];
+  if (LDS) {
+    for (int32_t b = threadIdx.x; b < nbins; b += blockDim.x) s_bin[b] = 0;
+    __syncthreads();
+  }
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t pid = blockIdx.x * kBlock + threadIdx.x; pid < S.n; pid += stride) {
+    const uint32_t ef = S.ef[pid];
+    if (ef & kDeadBit) continue;
+    const int32_t e = (int32_t)(ef & kEdgeMask);
+    double x;
+    if (FP64) {
+      x = S.x64[pid];
+    } else {
+      const float2 yy = S.y32[pid];
+      const double y = (double)yy.x + (double)yy.y;
+      x = (ef & kSideBit) ? G.e64[e].L - y : y;
+    }
+    int32_t lo = off[e], hi = off[e + 1] - 1;  // the answer lies in [lo, hi]
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (x <= up[mid])
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    if (LDS)
+      atomicAdd(&s_bin[lo], 1u);
+    else
+      atomicAdd((unsigned long long *)&out[lo], 1ull);
+  }
+  if (LDS) {
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b < nbins; b += blockDim.x)
+      if (s_bin[b]) atomicAdd((unsigned long long *)&out[b], (unsigned long long)s_bin[b]);
+  }
+}
+
 // Calls f(std::bool_constant<x>...) for the run-time flags, so one launch
 // site covers every compiled variant.
 template <typename F>
@@ -1244,7 +1354,8 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
   const bool obs = s.obs != nullptr;
   if (!FP64 && a.kernel == 1) {
     const int32_t stage = g.stage_bytes32;
-    const LdsPlan lp = plan_lds(g.nnz, stage, sizeof(PoolLds32) * kWavesPerBlock, &s, g.E);
+    const LdsPlan lp = plan_lds(g.nnz, stage, sizeof(PoolLds32<TRACE>) * kWavesPerBlock, &s,
+                                g.E);
     a.obs_lds = lp.obs_lds;
     const uint32_t blocks = (s.n + kPoolPerBlock - 1) / kPoolPerBlock;
     with_flags([&](auto L, auto T, auto O) {
@@ -1275,7 +1386,8 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
   k.block = dim3(kBlock);
   const bool pools = !FP64 && a.kernel == 1;
   const LdsPlan lp = plan_lds(max_nnz, max_stage,
-                              pools ? sizeof(PoolLds32) * kWavesPerBlock : 0, nullptr, 0);
+                              pools ? sizeof(PoolLds32<TRACE>) * kWavesPerBlock : 0, nullptr,
+                              0);
   k.shm = lp.shm;
   with_flags([&](auto L, auto T, auto O) {
     constexpr bool l = decltype(L)::value, t = decltype(T)::value, o = decltype(O)::value;
@@ -1323,6 +1435,21 @@ KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
                  : batch_launch_t<true, false>(n_items, max_nnz, max_stage, a, obs);
   return trace ? batch_launch_t<false, true>(n_items, max_nnz, max_stage, a, obs)
                : batch_launch_t<false, false>(n_items, max_nnz, max_stage, a, obs);
+}
+
+hipError_t launch_histogram_csr(const GraphDev &g, const SetDev &s, const int32_t *off,
+                                const double *up, int32_t nbins, uint64_t *out, bool fp64,
+                                hipStream_t st) {
+  const bool lds = nbins <= kLdsHistMax;
+  uint32_t blocks = (s.n + kBlock - 1) / kBlock;
+  if (lds && blocks > 1024) blocks = 1024;
+  if (!lds && blocks > 8192) blocks = 8192;
+  const size_t shm = lds ? (size_t)nbins * 4 : 0;
+  with_flags([&](auto F, auto L) {
+    hipLaunchKernelGGL((k_hist_csr<decltype(F)::value, decltype(L)::value>), dim3(blocks),
+                       dim3(kBlock), shm, st, g, s, off, up, nbins, out);
+  }, fp64, lds);
+  return hipGetLastError();
 }
 
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,

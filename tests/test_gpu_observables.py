@@ -167,3 +167,44 @@ def test_paper_star_density_error_falls_with_dt(B):
         errs[dt] = B.mg_density_l2(G, bins, h, ref)
     flat = B.mg_density_l2(G, bins, np.ones((5, bins), np.uint64), ref)
     assert errs[1e-4] < 0.5 * errs[1e-3] and errs[1e-3] < 0.4 * flat, (errs, flat)
+
+
+def test_histogram_csr_parity_and_errors(B, orc):
+    """Per-edge bins of uneven counts and widths: FP64 counts against the
+    oracle on the same paths (up to the particles whose paths differ), FP32
+    close to them, device output, and invalid bin tables rejected."""
+    import torch
+    g, _ = workloads.config2()
+    n, steps, dt = 20_000, 200, 1e-2
+    st = orc.init(g, n, 2, seed=6)
+    orc.simulate(g, st, 0, steps, dt, 8)
+    rng = np.random.default_rng(9)
+    counts = rng.integers(1, 40, size=g.n_edges)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    up = np.concatenate([np.sort(rng.uniform(0, L, c - 1)).tolist() + [L]
+                         for L, c in zip(g.length, counts)])
+    want = orc.histogram_csr(g, st, off, up)
+    G = B.mg_graph_create(g)
+    p = B.mg_particles_init(G, n, 2, init_seed=6, trace=True)
+    B.mg_simulate(p, steps, dt, 8)
+    nd = int((B.mg_particles_read(p, trace=True)["seqhash"] != st.seqhash).sum())
+    h = B.mg_histogram_csr(p, off, up)
+    assert np.abs(h.astype(np.int64) - want.astype(np.int64)).sum() <= 2 * nd
+    p32 = B.mg_particles_init(G, n, 2, init_seed=6, precision=B.MG_FP32)
+    B.mg_simulate(p32, steps, dt, 8)
+    assert _tv(B.mg_histogram_csr(p32, off, up), h) <= 2e-3
+    out = torch.zeros(int(off[-1]), dtype=torch.int64, device="cuda")
+    import ctypes as C
+    rc = B.lib().mg_histogram_csr(p.handle, off.ctypes.data_as(C.c_void_p),
+                                  up.ctypes.data_as(C.c_void_p), C.c_void_p(out.data_ptr()),
+                                  out.numel())
+    assert rc == 0 and np.array_equal(out.cpu().numpy().astype(np.uint64), h)
+    bad = up.copy()
+    e2 = int(np.argmax(counts >= 2))
+    bad[off[e2] + 1] = bad[off[e2]]       # a zero-width bin
+    with pytest.raises(B.MgError):
+        B.mg_histogram_csr(p, off, bad)
+    bad_off = off.copy()
+    bad_off[3] = bad_off[2]               # an edge without bins
+    with pytest.raises(B.MgError):
+        B.mg_histogram_csr(p, bad_off, up)

@@ -123,3 +123,38 @@ def test_stationary_bin_means_match_quadrature(which):
     quad = np.array([cf.binned(xs[e], ds[e], np.linspace(0, g.length[e], bins + 1))
                      for e in range(g.n_edges)]) / w
     np.testing.assert_allclose(ref, quad, rtol=1e-6, atol=1e-9 * ref.max())
+
+
+def test_histogram_csr_hand_example(orc):
+    """Uneven bins on two edges: upper boundaries (0.1, 0.5, 2.0) on edge 0
+    and (1.0,) on edge 1; a particle on a boundary goes to the bin below it,
+    the edge's ends to its first and last bins, dead particles nowhere."""
+    g = workloads.from_edges(3, [0, 0], [1, 2], [2.0, 1.0], sigma=1.0)
+    st = orc.init(g, 7, orc.INIT_EXPLICIT, edge=np.array([0, 0, 0, 0, 0, 1, 1]),
+                  pos=np.array([0.0, 0.1, 0.3, 0.5, 2.0, 0.0, 1.0]))
+    st.alive[6] = 0
+    h = orc.histogram_csr(g, st, [0, 3, 4], [0.1, 0.5, 2.0, 1.0])
+    assert h.tolist() == [2, 2, 1, 1]
+
+
+def test_histogram_csr_matches_uniform_and_search(orc):
+    """With uniform bins it is the uniform histogram (positions off the
+    interior boundaries), and in general a binary search for the first
+    upper boundary >= x."""
+    g, _ = workloads.config2()
+    st = orc.init(g, 20_000, orc.INIT_UNIFORM_LENGTH, seed=3)
+    nb = 16
+    off = np.arange(g.n_edges + 1) * nb
+    up = np.concatenate([np.arange(1, nb + 1) * (L / nb) for L in g.length])
+    assert np.array_equal(orc.histogram_csr(g, st, off, up), orc.histogram(g, st, nb).ravel())
+    rng = np.random.default_rng(4)
+    counts = rng.integers(1, 9, size=g.n_edges)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    up = np.concatenate([np.sort(rng.uniform(0, L, c - 1)).tolist() + [L]
+                         for L, c in zip(g.length, counts)])
+    h = orc.histogram_csr(g, st, off, up)
+    want = np.zeros(off[-1], np.uint64)
+    for e, x in zip(st.edge, st.x):
+        k = np.searchsorted(up[off[e]:off[e + 1]], x, side="left")
+        want[off[e] + min(k, counts[e] - 1)] += 1
+    assert np.array_equal(h, want) and int(h.sum()) == st.pid.size
