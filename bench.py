@@ -408,6 +408,49 @@ def run_nohit(args, B, torch):
                          "kernel_ms_per_launch": k * 1e3}}
 
 
+def run_tracer(args, B, torch):
+    """Tracer transport on the vascular network (Sec. 4.2): a pulse of 1e8
+    FP32 particles injected at the inlets in proportion to their inflow,
+    advanced 1e4 steps at config 3's dt with the streamed histogram taking a
+    snapshot every step (64 bins per edge).  By linearity the time-summed
+    histogram of a pulse is the steady state of a constant injection, the
+    tracer density the paper visualises.  Reported: substeps/s of the whole
+    run (init, stepping with snapshots, readout), the absorbed fraction and
+    the mean residence time the occupation gives."""
+    import numpy as np
+    import workloads
+    g, run = workloads.config3()
+    G = B.mg_graph_create(g)
+    n, steps, dt, bins = run["n_particles"], run["n_steps"], run["dt"], run["bins"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = B.mg_particles_init_sources(G, n, g.meta["inlets"], g.meta["inflow"], init_seed=0,
+                                    precision=B.MG_FP32)
+    B.mg_autotune(p, dt, run["seed"])
+    B.mg_observe_histogram(p, bins, 1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    B.mg_simulate(p, steps, dt, run["seed"])
+    e1.record()
+    h, snaps = B.mg_observed_histogram(p)
+    ex, ab, tot = B.mg_exit_counts(p)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k = e0.elapsed_time(e1) * 1e-3
+    return {"metric": METRIC, "value": float(tot[1]) / wall, "unit": "particle-substeps/s",
+            "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "vascular20k tracer pulse: 1e8 particles injected at the "
+                                   "inlets by inflow, 1e4 steps at 10x CFL dt, snapshot "
+                                   "every step, 64 bins/edge"},
+            "kernel_substeps_per_s": float(tot[1]) / k,
+            "absorbed_fraction": float(ab.sum()) / n,
+            "mean_residence_time_T0": float(h.sum()) * dt / n,
+            "snapshots": snaps, "hits_per_step": float(tot[2]) / float(tot[3])}
+
+
 def calibrate_copy(torch):
     """A 1 GiB device-to-device copy: the kernel of known size that HBM
     counter readings (FETCH_SIZE, WRITE_SIZE) are scaled by."""
@@ -431,7 +474,7 @@ def main():
                     help="first copy 1 GiB on the device (scale for HBM counters)")
     ap.add_argument("--workload", default="langevin_star64",
                     choices=["langevin_star64", "vascular20k", "batch512", "accuracy_sweep",
-                             "density_error", "nohit_segment"],
+                             "density_error", "nohit_segment", "vascular_tracer"],
                     help="the metric's configuration (default) or another workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -450,6 +493,9 @@ def main():
     torch.cuda.set_device(0)
     if args.calibrate_copy:
         calibrate_copy(torch)
+    if args.workload == "vascular_tracer":
+        print(json.dumps(run_tracer(args, B, torch)), flush=True)
+        return
     if args.workload == "nohit_segment":
         print(json.dumps(run_nohit(args, B, torch)), flush=True)
         return

@@ -151,6 +151,22 @@ mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
                             const int32_t *edge, const double *pos,
                             int32_t vertex, uint64_t init_seed,
                             const mg_options *opt, mg_particles **out);
+/*
+ * Creates n particles injected at source vertices (the inlets of the
+ * tracer problem, Sec. 4.2): particle i starts on source j with probability
+ * rates[j] / sum(rates), on an incident edge drawn from that vertex's b
+ * (Alg. 1's vertex rule, as in MG_INIT_AT_VERTEX).  Init-stream word 0
+ * draws the source (thresholds built like the slot thresholds: normalised
+ * running sum, floor(C 2^32), 2^32 for the last source of positive rate),
+ * word 1 the slot.  vertices[n_sources] must be standard vertices and
+ * rates[n_sources] finite, >= 0, with a positive sum (host arrays).  A
+ * continuous injection at these rates has as its steady state the time
+ * integral of one such pulse, which the streamed histogram accumulates.
+ */
+mg_status mg_particles_init_sources(const mg_graph *g, int64_t n, int32_t n_sources,
+                                    const int32_t *vertices, const double *rates,
+                                    uint64_t init_seed, const mg_options *opt,
+                                    mg_particles **out);
 void mg_particles_destroy(mg_particles *p);
 
 /*

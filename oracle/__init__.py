@@ -72,6 +72,8 @@ def lib():
         L.or_simulate_traced.restype = C.c_int
         L.or_init.argtypes = [vp, i64, vp, i32, i32, u64, u32, vp, vp, vp, vp, vp]
         L.or_init.restype = C.c_int
+        L.or_init_sources.argtypes = [vp, i64, vp, i32, vp, vp, u64, u32, vp, vp, vp, vp, vp]
+        L.or_init_sources.restype = C.c_int
         L.or_histogram.argtypes = [vp, i64, vp, vp, vp, i32, vp]
         L.or_fnv_offset.restype = u64
         _lib = L
@@ -212,6 +214,26 @@ def init(g, n: int, mode: int, *, vertex: int = 0, seed: int = 0, tag: int = 0,
                        _ptr(st.hits))
     if rc != 0:
         raise ValueError(f"or_init failed ({rc})")
+    return st
+
+
+def init_sources(g, n: int, vertices, rates, *, seed: int = 0, tag: int = 0,
+                 pids=None) -> State:
+    """Particles injected at source vertices (inlets) chosen with probability
+    proportional to their rates, each on an incident edge drawn from the
+    vertex's b."""
+    g = as_graph(g)
+    pid = np.arange(n, dtype=np.uint32) if pids is None else np.ascontiguousarray(pids, np.uint32)
+    m = pid.size
+    st = State(pid, np.zeros(m, np.int32), np.zeros(m, np.float64), np.ones(m, np.uint8),
+               np.full(m, fnv_offset(), np.uint64), np.zeros(m, np.uint32))
+    v = np.ascontiguousarray(vertices, np.int32)
+    r = np.ascontiguousarray(rates, np.float64)
+    rc = lib().or_init_sources(g.ref, m, _ptr(pid), int(v.size), _ptr(v), _ptr(r),
+                               C.c_uint64(seed), tag, _ptr(st.edge), _ptr(st.x),
+                               _ptr(st.alive), _ptr(st.seqhash), _ptr(st.hits))
+    if rc != 0:
+        raise ValueError(f"or_init_sources failed ({rc})")
     return st
 
 

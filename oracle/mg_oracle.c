@@ -485,6 +485,65 @@ int or_init(const or_graph *g, int64_t count, const uint32_t *pid, int32_t mode,
   return 0;
 }
 
+/*
+ * Injection at source vertices (the tracer problem's inlets, Sec. 4.2):
+ * particle i starts on a source vertex drawn with probability proportional
+ * to its rate, on an incident edge drawn from that vertex's b (the vertex
+ * rule of Alg. 1, as for a particle started on one vertex).  Init-stream
+ * word 0 draws the source (cumulative rate thresholds built like the slot
+ * thresholds: normalised running sum, floor(C 2^32), 2^32 for the last
+ * source of positive rate), word 1 the slot.
+ */
+int or_init_sources(const or_graph *g, int64_t count, const uint32_t *pid,
+                    int32_t n_src, const int32_t *src_v, const double *src_rate,
+                    uint64_t seed, uint32_t tag, int32_t *edge, double *x,
+                    uint8_t *alive, uint64_t *hash, uint32_t *hits) {
+  const int32_t nnz = g->vtx_offsets[g->n_vertices];
+  if (n_src < 1) return -1;
+  double total = 0.0;
+  int32_t last_pos = -1;
+  for (int32_t j = 0; j < n_src; ++j) {
+    if (src_v[j] < 0 || src_v[j] >= g->n_vertices) return -1;
+    if (!(src_rate[j] >= 0.0)) return -1;
+    total += src_rate[j];
+    if (src_rate[j] > 0.0) last_pos = j;
+  }
+  if (last_pos < 0) return -1;
+  uint64_t *sthr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n_src);
+  uint64_t *thr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nnz > 0 ? nnz : 1));
+  if (!sthr || !thr) { free(sthr); free(thr); return -2; }
+  double cum = 0.0;
+  for (int32_t j = 0; j < n_src; ++j) {
+    cum += src_rate[j] / total;
+    if (j >= last_pos) {
+      sthr[j] = (uint64_t)1 << 32;
+    } else {
+      double t = floor(cum * 4294967296.0);
+      sthr[j] = t >= 4294967296.0 ? ((uint64_t)1 << 32) : (uint64_t)t;
+    }
+  }
+  if (or_thresholds(g, thr) != 0) { free(sthr); free(thr); return -1; }
+  for (int64_t i = 0; i < count; ++i) {
+    uint32_t ctr[4] = {pid[i], 0xFFFFFFFFu, 0xFFFFFFFFu, tag};
+    uint32_t o[4];
+    philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), o);
+    int32_t j = n_src - 1;
+    for (int32_t k = 0; k < n_src; ++k)
+      if ((uint64_t)o[0] < sthr[k]) { j = k; break; }
+    const int32_t v = src_v[j];
+    const int32_t s = pick_slot(g, thr, v, o[1]);
+    const int32_t e = g->slot_edge[s];
+    edge[i] = e;
+    x[i] = g->slot_orient[s] ? g->length[e] : 0.0;
+    alive[i] = 1;
+    hash[i] = OR_FNV_OFFSET;
+    hits[i] = 0;
+  }
+  free(sthr);
+  free(thr);
+  return 0;
+}
+
 /* ------------------------------------------------------------ histogram */
 /*
  * Uniform-bin histogram of alive particles (appendix kernel; reading A13):

@@ -24,7 +24,8 @@ MG_SCHED_AUTO, MG_SCHED_LANES, MG_SCHED_POOLS = 0, 1, 2
 
 EXPORTED = (
     "mg_graph_create", "mg_graph_destroy", "mg_particles_arena_bytes",
-    "mg_particles_init", "mg_particles_destroy", "mg_simulate", "mg_histogram",
+    "mg_particles_init", "mg_particles_init_sources", "mg_particles_destroy", "mg_simulate",
+    "mg_histogram",
     "mg_exit_counts", "mg_particles_read", "mg_particles_step", "mg_batch_create",
     "mg_batch_simulate", "mg_batch_destroy", "mg_autotune", "mg_histogram_csr",
     "mg_observe_histogram",
@@ -79,6 +80,7 @@ def lib() -> C.CDLL:
         L.mg_particles_arena_bytes.argtypes = [vp, i64, vp]
         L.mg_particles_arena_bytes.restype = i64
         L.mg_particles_init.argtypes = [vp, i64, C.c_int, vp, vp, i32, u64, vp, vp]
+        L.mg_particles_init_sources.argtypes = [vp, i64, i32, vp, vp, u64, vp, vp]
         L.mg_particles_destroy.argtypes = [vp]
         L.mg_particles_destroy.restype = None
         L.mg_simulate.argtypes = [vp, i64, C.c_double, u64]
@@ -238,6 +240,25 @@ def mg_particles_init(g: Graph, n: int, mode: int, *, edge=None, pos=None, verte
     _check(lib().mg_particles_init(g.handle, int(n), int(mode), _p(e), _p(x), int(vertex),
                                    C.c_uint64(init_seed), C.byref(o), C.byref(h)))
     return Particles(h, g, int(n), int(precision), arena_obj)
+
+
+def mg_particles_init_sources(g: Graph, n: int, vertices, rates, *, init_seed: int = 0,
+                              precision: int = MG_FP64, max_splits: int = 8,
+                              graph_tag: int = 0, trace: bool = False,
+                              steps_per_launch: int = 0, stream=None,
+                              schedule: int = MG_SCHED_AUTO) -> Particles:
+    """Particles injected at source vertices with probabilities proportional
+    to ``rates``."""
+    v = np.ascontiguousarray(vertices, np.int32)
+    r = np.ascontiguousarray(rates, np.float64)
+    if v.size != r.size:
+        raise ValueError("vertices and rates differ in length")
+    o = _options(precision, max_splits, graph_tag, trace, steps_per_launch, stream,
+                 schedule=schedule)
+    h = C.c_void_p()
+    _check(lib().mg_particles_init_sources(g.handle, int(n), int(v.size), _p(v), _p(r),
+                                           C.c_uint64(init_seed), C.byref(o), C.byref(h)))
+    return Particles(h, g, int(n), int(precision))
 
 
 def mg_particles_destroy(p: Particles) -> None:

@@ -379,11 +379,11 @@ int64_t mg_particles_arena_bytes(const mg_graph *g, int64_t n, const mg_options 
   return (int64_t)set_layout(g->V, g->nnz, n, prec, trace).total;
 }
 
-mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
-                            const int32_t *edge, const double *pos, int32_t vertex,
-                            uint64_t init_seed, const mg_options *opt,
-                            mg_particles **out) {
-  g_err.clear();
+// Mode 3 (internal): injection at source vertices.
+static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t *edge,
+                           const double *pos, int32_t vertex, int32_t n_src,
+                           const int32_t *src_v, const double *src_rate,
+                           uint64_t init_seed, const mg_options *opt, mg_particles **out) {
   if (!out) return fail(MG_EINVAL, "out is NULL");
   *out = nullptr;
   if (!g) return fail(MG_EINVAL, "graph is NULL");
@@ -409,6 +409,19 @@ mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
     if (vertex < 0 || vertex >= g->V) return fail(MG_EINVAL, "vertex out of range");
     if (g->vtx_host[vertex].deg <= 0)
       return fail(MG_EINVAL, "vertex %d is absorbing or isolated", vertex);
+  } else if (mode == 3) {
+    if (n_src < 1 || !src_v || !src_rate) return fail(MG_EINVAL, "need at least one source");
+    double total = 0.0;
+    for (int32_t j = 0; j < n_src; ++j) {
+      const int32_t v = src_v[j];
+      if (v < 0 || v >= g->V) return fail(MG_EINVAL, "source %d: vertex out of range", j);
+      if (g->vtx_host[v].deg <= 0)
+        return fail(MG_EINVAL, "source %d: vertex %d is absorbing or isolated", j, v);
+      if (!is_finite(src_rate[j]) || src_rate[j] < 0.0)
+        return fail(MG_EINVAL, "source %d: rate must be finite and >= 0", j);
+      total += src_rate[j];
+    }
+    if (!(total > 0.0)) return fail(MG_EINVAL, "the source rates sum to 0");
   } else if (mode != MG_INIT_UNIFORM_LENGTH) {
     return fail(MG_EINVAL, "unknown init mode");
   }
@@ -466,6 +479,24 @@ mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
   int32_t *d_edge = nullptr;
   double *d_pos = nullptr;
   void *tmp = nullptr;
+  InitSources src{nullptr, nullptr, 0};
+  if (mode == 3) {
+    std::vector<uint64_t> thr;
+    const int32_t off[2] = {0, n_src};
+    slot_thresholds(1, off, src_rate, thr);
+    he = hipMalloc(&tmp, align_up((size_t)n_src * 8, 256) + (size_t)n_src * 4);
+    if (he != hipSuccess)
+      return bail(fail(MG_ENOMEM, "staging the sources: %s", hipGetErrorString(he)));
+    uint64_t *d_thr = (uint64_t *)tmp;
+    int32_t *d_v = (int32_t *)((char *)tmp + align_up((size_t)n_src * 8, 256));
+    he = hipMemcpy(d_thr, thr.data(), (size_t)n_src * 8, hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(d_v, src_v, (size_t)n_src * 4, hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+      (void)hipFree(tmp);
+      return bail(hip_fail(he, "copying the sources"));
+    }
+    src = InitSources{d_thr, d_v, n_src};
+  }
   if (mode == MG_INIT_EXPLICIT) {
     he = hipMalloc(&tmp, (size_t)n * 12 + 256);
     if (he != hipSuccess) return bail(fail(MG_ENOMEM, "staging explicit positions: %s", hipGetErrorString(he)));
@@ -480,13 +511,35 @@ mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
     }
   }
   he = launch_init(g->gd, s, (int)mode, vertex, (uint32_t)init_seed,
-                   (uint32_t)(init_seed >> 32), d_edge, d_pos, o.precision == MG_FP64,
+                   (uint32_t)(init_seed >> 32), d_edge, d_pos, src, o.precision == MG_FP64,
                    p->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
   if (tmp) (void)hipFree(tmp);
   if (he != hipSuccess) return bail(hip_fail(he, "initialising particles"));
   *out = p;
   return MG_OK;
+}
+
+mg_status mg_particles_init(const mg_graph *g, int64_t n, mg_init_mode mode,
+                            const int32_t *edge, const double *pos, int32_t vertex,
+                            uint64_t init_seed, const mg_options *opt,
+                            mg_particles **out) {
+  g_err.clear();
+  if (mode != MG_INIT_EXPLICIT && mode != MG_INIT_AT_VERTEX && mode != MG_INIT_UNIFORM_LENGTH) {
+    if (out) *out = nullptr;
+    return fail(MG_EINVAL, "unknown init mode");
+  }
+  return init_impl(g, n, (int)mode, edge, pos, vertex, 0, nullptr, nullptr, init_seed, opt,
+                   out);
+}
+
+mg_status mg_particles_init_sources(const mg_graph *g, int64_t n, int32_t n_sources,
+                                    const int32_t *vertices, const double *rates,
+                                    uint64_t init_seed, const mg_options *opt,
+                                    mg_particles **out) {
+  g_err.clear();
+  return init_impl(g, n, 3, nullptr, nullptr, 0, n_sources, vertices, rates, init_seed, opt,
+                   out);
 }
 
 void mg_particles_destroy(mg_particles *p) {

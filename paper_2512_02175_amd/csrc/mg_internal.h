@@ -130,10 +130,18 @@ constexpr int kLdsHistMax = 16384;  // histogram bins privatised in LDS (64 KiB)
 constexpr int kLdsObsMax = 4096;    // streamed-histogram bins privatised in LDS
 constexpr int kLdsBlockMax = 65536; // LDS bytes a step block may take
 
+// Injection sources of init mode 3: vertex ids and cumulative rate
+// thresholds (device arrays of n entries).
+struct InitSources {
+  const uint64_t *thr;
+  const int32_t *vtx;
+  int32_t n;
+};
+
 hipError_t launch_init(const GraphDev &g, const SetDev &s, int mode,
                        int32_t vertex, uint32_t key0, uint32_t key1,
                        const int32_t *edge_in, const double *pos_in,
-                       bool fp64, hipStream_t st);
+                       const InitSources &src, bool fp64, hipStream_t st);
 hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
                        bool fp64, bool trace, hipStream_t st);
 // Particles per batch work item: a pool block for the FP32 wave-pool

@@ -1181,7 +1181,7 @@ template <bool FP64>
 __global__ __launch_bounds__(kBlock) void k_init(GraphDev G, SetDev S, int mode,
                                                  int32_t vertex, uint32_t k0,
                                                  uint32_t k1, const int32_t *edge_in,
-                                                 const double *pos_in) {
+                                                 const double *pos_in, InitSources src) {
   const uint32_t pid = blockIdx.x * kBlock + threadIdx.x;
   if (pid >= S.n) return;
   int32_t e;
@@ -1191,8 +1191,22 @@ __global__ __launch_bounds__(kBlock) void k_init(GraphDev G, SetDev S, int mode,
     x = pos_in[pid];
   } else {
     const U4 o = philox(pid, 0xFFFFFFFFu, 0xFFFFFFFFu, S.tag, k0, k1);
-    if (mode == 1) {
-      const SlotPick sp = pick_slot(global_view(G), G.vtx[vertex], o.x);
+    if (mode == 1 || mode == 3) {
+      uint32_t r = o.x;
+      if (mode == 3) {
+        // source: first j with word 0 < T_j (T nondecreasing, last 2^32)
+        int32_t lo = 0, hi = src.n - 1;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if ((uint64_t)o.x < src.thr[mid])
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        vertex = src.vtx[lo];
+        r = o.y;
+      }
+      const SlotPick sp = pick_slot(global_view(G), G.vtx[vertex], r);
       e = eo_edge(sp.eo);
       x = (sp.eo & 1u) ? G.e64[e].L : 0.0;
     } else {
@@ -1405,14 +1419,15 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
 
 hipError_t launch_init(const GraphDev &g, const SetDev &s, int mode, int32_t vertex,
                        uint32_t key0, uint32_t key1, const int32_t *edge_in,
-                       const double *pos_in, bool fp64, hipStream_t st) {
+                       const double *pos_in, const InitSources &src, bool fp64,
+                       hipStream_t st) {
   const uint32_t blocks = (s.n + kBlock - 1) / kBlock;
   if (fp64)
     hipLaunchKernelGGL(k_init<true>, dim3(blocks), dim3(kBlock), 0, st, g, s, mode,
-                       vertex, key0, key1, edge_in, pos_in);
+                       vertex, key0, key1, edge_in, pos_in, src);
   else
     hipLaunchKernelGGL(k_init<false>, dim3(blocks), dim3(kBlock), 0, st, g, s, mode,
-                       vertex, key0, key1, edge_in, pos_in);
+                       vertex, key0, key1, edge_in, pos_in, src);
   return hipGetLastError();
 }
 

@@ -208,3 +208,34 @@ def test_histogram_csr_parity_and_errors(B, orc):
     bad_off[3] = bad_off[2]               # an edge without bins
     with pytest.raises(B.MgError):
         B.mg_histogram_csr(p, bad_off, up)
+
+
+def test_sources_init_and_tracer_pulse(B, orc):
+    """Injection at the vascular network's inlets in proportion to their
+    inflow (the tracer problem, Sec. 4.2): initial states equal the oracle's
+    in both precisions, and a pulse advanced with the streamed histogram
+    (FP64) matches the oracle's sum of snapshots and absorbed counts up to
+    the particles whose paths differ."""
+    g, run = workloads.config3()
+    v, r = g.meta["inlets"], g.meta["inflow"]
+    n = 20_000
+    st = orc.init_sources(g, n, v, r, seed=5)
+    G = B.mg_graph_create(g)
+    for prec in (B.MG_FP64, B.MG_FP32):
+        p = B.mg_particles_init_sources(G, n, v, r, init_seed=5, precision=prec, trace=True)
+        rr = B.mg_particles_read(p, trace=True)
+        assert np.array_equal(rr["edge"], st.edge) and np.array_equal(rr["x"], st.x)
+    p = B.mg_particles_init_sources(G, n, v, r, init_seed=5, trace=True)
+    dt, steps, every, bins = 10 * run["dt"], 1500, 10, 8
+    acc, snaps, c = orc.observed_histogram(g, st, 0, steps, dt, 7, every, bins)
+    B.mg_observe_histogram(p, bins, every)
+    B.mg_simulate(p, steps, dt, 7)
+    h, ns = B.mg_observed_histogram(p)
+    assert ns == snaps and c.absorbed.sum() > 0
+    nd = int((B.mg_particles_read(p, trace=True)["seqhash"] != st.seqhash).sum())
+    assert nd <= n // 10_000 + 1
+    assert np.abs(h.astype(np.int64) - acc.astype(np.int64)).sum() <= 2 * nd * snaps
+    ab = B.mg_exit_counts(p)[1]
+    assert np.abs(ab.astype(np.int64) - c.absorbed.astype(np.int64)).sum() <= nd
+    with pytest.raises(B.MgError):
+        B.mg_particles_init_sources(G, 10, [int(np.flatnonzero(g.vtx_kind)[0])], [1.0])

@@ -348,10 +348,18 @@ def config3(seed: int = 3) -> tuple[GraphDesc, dict]:
     sig = np.sqrt(2.0)
     dx = Lh / 64.0
     dt_cfl = np.min(1.0 / (np.abs(mu) / dx + 2.0 * (0.5 * sig * sig) / (dx * dx)))
+    # inlets: inflow boundary vertices, with the inflow rate |Q| of their edge
+    inlets, inflow = [], []
+    for lf in bnd:
+        if kind[lf] == 0:
+            e = int(np.flatnonzero((ei == lf) | (et == lf))[0])
+            inlets.append(int(lf))
+            inflow.append(float(abs(Q[e])))
     g = from_edges(V, ei, et, Lh, mu, None, sig, weight_init=area,
                    weight_term=area, vtx_kind=kind,
                    meta={"name": "vascular20k", "T0": T0, "L0": L0,
-                         "dt_cfl": float(dt_cfl)})
+                         "dt_cfl": float(dt_cfl), "inlets": np.array(inlets, np.int32),
+                         "inflow": np.array(inflow)})
     run = dict(n_particles=100_000_000, init="uniform", dt=10.0 * float(dt_cfl),
                n_steps=10_000, max_splits=8, seed=0, bins=64)
     return g, run
