@@ -47,6 +47,7 @@ mg_status hip_fail(hipError_t e, const char *what) {
 // T_s = 2^32 from the last slot with b > 0 onward.
 void slot_thresholds(int32_t V, const int32_t *off, const double *b,
                      std::vector<uint64_t> &thr) {
+  thr.assign((size_t)off[V], 0);
   for (int32_t v = 0; v < V; ++v) {
     const int32_t s0 = off[v], s1 = off[v + 1];
     double total = 0.0;
@@ -481,7 +482,7 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
   void *tmp = nullptr;
   InitSources src{nullptr, nullptr, 0};
   if (mode == 3) {
-    std::vector<uint64_t> thr;
+    std::vector<uint64_t> thr((size_t)n_src);
     const int32_t off[2] = {0, n_src};
     slot_thresholds(1, off, src_rate, thr);
     he = hipMalloc(&tmp, align_up((size_t)n_src * 8, 256) + (size_t)n_src * 4);

@@ -122,9 +122,8 @@ constexpr int kBlock = 256;
 #endif
 constexpr int kPoolPerWave = MG_POOL_PER_WAVE;          // FP32 wave pools (<= 256)
 constexpr int kPoolPerBlock = kPoolPerWave * (kBlock / 64);
-constexpr int kLdsExitMax = 4096;   // slots counted in LDS (16 KiB of u32); with
-                                    // staged tables and pools a block stays
-                                    // within 64 KiB of LDS
+constexpr int kLdsExitMax = 16384;  // slots counted in LDS (64 KiB of u32) when
+                                    // the block's LDS budget allows
 constexpr int kLdsStageMax = 24576; // graph tables staged in LDS up to this size
 constexpr int kLdsHistMax = 16384;  // histogram bins privatised in LDS (64 KiB)
 constexpr int kLdsObsMax = 4096;    // streamed-histogram bins privatised in LDS

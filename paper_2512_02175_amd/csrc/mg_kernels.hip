@@ -261,6 +261,14 @@ __device__ __forceinline__ void observe(const P &q, const SetDev &S, const ObsSi
     atomicAdd((unsigned long long *)&S.obs[idx], 1ull);
 }
 
+template <typename T, int N>
+__device__ __forceinline__ T pickw(const T (&W)[N], uint32_t j) {
+  T w = W[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) w = (j == (uint32_t)i) ? W[i] : w;
+  return w;
+}
+
 // Step loop shared by both precisions.  P is a per-lane particle (FP64 or
 // FP32) with
 //   bool fast(W)                    first sub-step of a step (h = dt); true if
@@ -300,8 +308,11 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
     }
     const uint32_t jb = n - base;
     const uint32_t je = min(NW, n_end - base);
-    // The window's normals stay in registers: every access below has a
-    // compile-time index, and the normal of a parked step travels in wp.
+    // FP32: the window's normals stay in registers (every access has a
+    // compile-time index; the normal of a parked step travels in wp).
+    // FP64: the continuation after a hit indexes them at run time, which
+    // keeps the eight doubles out of registers (measured faster: one more
+    // wave per SIMD).
     int32_t pj = -1;
     typename P::real wp = 0;
 #pragma unroll
@@ -323,15 +334,28 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
         snapshot(base + j0 + 1u);
       }
       pj = -1;
-#pragma unroll
-      for (uint32_t j = 1; j < NW; ++j) {
-        if (j <= j0 || j >= je || !q.alive || pj >= 0) continue;
-        if (!q.fast(W[j])) {
-          pj = (int32_t)j;
-          wp = W[j];
-        } else {
+      if constexpr (sizeof(typename P::real) == 8) {
+        for (uint32_t j = j0 + 1; j < je && q.alive; ++j) {
+          const typename P::real wj = pickw(W, j);
+          if (!q.fast(wj)) {
+            pj = (int32_t)j;
+            wp = wj;
+            break;
+          }
           if ((j & 3u) == 3u) q.reanchor();
           snapshot(base + j + 1u);
+        }
+      } else {
+#pragma unroll
+        for (uint32_t j = 1; j < NW; ++j) {
+          if (j <= j0 || j >= je || !q.alive || pj >= 0) continue;
+          if (!q.fast(W[j])) {
+            pj = (int32_t)j;
+            wp = W[j];
+          } else {
+            if ((j & 3u) == 3u) q.reanchor();
+            snapshot(base + j + 1u);
+          }
         }
       }
     }
@@ -1336,9 +1360,13 @@ void with_flags(F &&f, bool x, Rest... rest) {
     with_flags([&](auto... v) { f(std::false_type{}, v...); }, rest...);
 }
 
-// LDS layout sizes shared by the host launchers and the kernels' offsets.
+// LDS layout of a step block, shared by the host launchers and the
+// kernels' offsets: [exit counters][staged tables][pools][snapshot bins].
+// Within kLdsBlockMax bytes, exit counters come first (they take an atomic
+// per hit-step), staged tables next, snapshot bins last.
 struct LdsPlan {
   bool lds_exit;
+  bool staged;
   int32_t obs_lds;  // snapshot bins in LDS, 0: global counters
   size_t shm;
 };
@@ -1347,9 +1375,15 @@ LdsPlan plan_lds(int32_t nnz, int32_t stage, size_t pools, const SetDev *obs_set
                  int32_t n_edges) {
   LdsPlan p{};
   p.lds_exit = nnz <= kLdsExitMax;
-  const int32_t ex = p.lds_exit ? ((nnz * 4 + 15) & ~15) : 0;
-  size_t base = (size_t)((ex + stage + 15) & ~15) + pools;
-  base = (base + 15) & ~(size_t)15;
+  p.staged = stage > 0;
+  auto size = [&]() {
+    const int32_t ex = p.lds_exit ? ((nnz * 4 + 15) & ~15) : 0;
+    const size_t b = (size_t)((ex + (p.staged ? stage : 0) + 15) & ~15) + pools;
+    return (b + 15) & ~(size_t)15;
+  };
+  if (size() > (size_t)kLdsBlockMax) p.staged = false;
+  if (size() > (size_t)kLdsBlockMax) p.lds_exit = false;
+  const size_t base = size();
   p.shm = base;
   if (obs_set && obs_set->obs) {
     const int64_t nbins = (int64_t)n_edges * obs_set->obs_nb;
@@ -1376,7 +1410,7 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
       hipLaunchKernelGGL((k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
                                    decltype(O)::value>),
                          dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
-    }, lp.lds_exit, stage > 0, obs);
+    }, lp.lds_exit, lp.staged, obs);
     return hipGetLastError();
   }
   const int32_t stage = FP64 ? g.stage_bytes64 : g.stage_bytes32;
@@ -1387,7 +1421,7 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
     hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
                                decltype(O)::value>),
                        dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
-  }, lp.lds_exit, stage > 0, obs);
+  }, lp.lds_exit, lp.staged, obs);
   return hipGetLastError();
 }
 
@@ -1411,7 +1445,7 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
         return;
       }
     k.func = (const void *)k_batch<FP64, TRACE, l, t, o>;
-  }, lp.lds_exit, max_stage > 0, obs);
+  }, lp.lds_exit, lp.staged, obs);
   return k;
 }
 
