@@ -1038,6 +1038,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   a.dt = dt;
+  a.probe = 1;
   const int32_t cand_kernel[5] = {0, 1, 1, 1, 1};
   const int32_t cand_idle[5] = {8, 4, 8, 16, 32};
   hipEvent_t e0 = nullptr, e1 = nullptr;

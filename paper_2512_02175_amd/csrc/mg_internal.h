@@ -108,6 +108,7 @@ struct StepArgs {
   int32_t idle;    // wave pools: idle lanes that trigger a partial split pass
   uint32_t n0_offset;  // batched launches: steps taken earlier in the call
   int32_t obs_lds;     // streamed-histogram bins privatised in LDS (0: global)
+  int32_t probe;       // autotuning probe: the same kernels under probe names
 };
 
 // Batched form: one work item per (set, tile of particles).

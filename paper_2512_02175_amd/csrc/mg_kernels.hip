@@ -841,17 +841,17 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
 // wait in the wave's private LDS home slots.  A lane runs its particle's
 // first sub-steps for one main-stream Philox group (four steps) per
 // iteration; a particle whose sub-step reaches a vertex is parked: its state
-// goes to its home slot and its slot id onto the wave's split stack, and the
+// goes to its home slot and its slot id onto the wave's split queue, and the
 // lane takes a ready particle instead.  When 64 particles are parked (or
 // lanes would idle), one split pass takes them with every lane busy and
 // resolves one vertex crossing each: crossing time, Philox hit stream, slot
 // draw and the next sub-step's proposal.  A particle whose step is then
-// complete goes back on the ready stack (with its exit record); one whose
-// proposal reaches a vertex again goes back on the split stack, so a pass
+// complete goes back on the ready queue (with its exit record); one whose
+// proposal reaches a vertex again goes back on the split queue, so a pass
 // never waits for the lane with the most crossings.  Each particle still
 // consumes exactly the random numbers of its own (step, hit) counters, so the
 // results equal the plain per-particle order bit for bit.  Waves never wait
-// for one another: the stacks and their counts are private to a wave.
+// for one another: the queues and their counters are private to a wave.
 constexpr int kWavesPerBlock = kBlock / 64;
 static_assert(kPoolPerWave % 64 == 0 && kPoolPerWave >= 128 && kPoolPerWave <= 256,
               "a wave pool holds 2 to 4 particles per lane");
@@ -865,7 +865,7 @@ template <>
 struct PoolTrace<false> {};
 
 // A wave's pool in LDS: home slots of its particles, the resolution state
-// of parked steps, and the ready and split stacks (slot ids).
+// of parked steps, and the ready and split queues (slot ids).
 template <bool TRACE>
 struct PoolLds32 : PoolTrace<TRACE> {
   uint32_t ef[kPoolPerWave];
@@ -949,7 +949,11 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   bool has = false;
   uint32_t slot = 0, n = 0;
   uint32_t snap = 0;  // next snapshot count of the lane's particle
-  uint32_t ready_cnt = 0, split_cnt = 0;
+  // Ready and split queues: FIFO rings over the pool's slot ids, with
+  // wave-uniform head and tail counters.  FIFO keeps the particles of a pool
+  // advancing together, so a launch ends without a long tail of stragglers.
+  constexpr uint32_t K = (uint32_t)kPoolPerWave;
+  uint32_t r_head = 0, r_tail = 0, s_head = 0, s_tail = 0;
 
   // Initial placement: slot `lane` rides in the lane, slots 64k + lane wait.
 #pragma unroll
@@ -1002,9 +1006,9 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
           P.hits[s] = S.hits[pid];
           P.hash[s] = S.seqhash[pid];
         }
-        P.ready[ready_cnt + lane_rank(m)] = (uint8_t)s;
+        P.ready[(r_tail + lane_rank(m)) % K] = (uint8_t)s;
       }
-      ready_cnt += (uint32_t)__popcll(m);
+      r_tail += (uint32_t)__popcll(m);
     }
   }
   wave_lds_fence();
@@ -1015,19 +1019,19 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       const uint64_t m_empty = __ballot(!has);
       if (!has) {
         const uint32_t r = lane_rank(m_empty);
-        if (r < ready_cnt) {
-          slot = P.ready[ready_cnt - 1u - r];
+        if (r < r_tail - r_head) {
+          slot = P.ready[(r_head + r) % K];
           n = P.n[slot];
           pool_load(q, P, slot);
           has = true;
           if (OBS) snap = next_snapshot(n, S);
         }
       }
-      ready_cnt -= min((uint32_t)__popcll(m_empty), ready_cnt);
+      r_head += min((uint32_t)__popcll(m_empty), r_tail - r_head);
     }
     bool do_split = false;
     if (__ballot(has) == 0ull) {
-      if (split_cnt == 0) break;
+      if (s_tail == s_head) break;
       do_split = true;
     } else {
       // one Philox group of first sub-steps for every lane with a particle
@@ -1076,12 +1080,13 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         pool_store(q, P, slot, n);
         P.w[slot] = wp;
         P.k[slot] = 0;  // fresh: hh = dt, hl = 0, no slot drawn yet
-        P.split[split_cnt + lane_rank(m_park)] = (uint8_t)slot;
+        P.split[(s_tail + lane_rank(m_park)) % K] = (uint8_t)slot;
         has = false;
       }
-      split_cnt += (uint32_t)__popcll(m_park);
+      s_tail += (uint32_t)__popcll(m_park);
       wave_lds_fence();
       const uint32_t empty = (uint32_t)__popcll(__ballot(!has));
+      const uint32_t ready_cnt = r_tail - r_head, split_cnt = s_tail - s_head;
       const uint32_t idle = empty > ready_cnt ? empty - ready_cnt : 0u;
       do_split = split_cnt >= 64u || (split_cnt > 0u && idle >= (uint32_t)A.idle);
     }
@@ -1089,13 +1094,14 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       // The lanes' own particles wait in their home slots during the pass.
       if (has) pool_store(q, P, slot, n);
       // Up to 64 parked particles, one per lane, one crossing each.
-      const uint32_t B = min(split_cnt, 64u);
-      split_cnt -= B;
+      const uint32_t B = min(s_tail - s_head, 64u);
+      const uint32_t s_base = s_head;
+      s_head += B;
       wave_lds_fence();
       bool back = false, again = false;
       uint32_t s2 = 0;
       if (lane < B) {
-        s2 = P.split[split_cnt + lane];
+        s2 = P.split[(s_base + lane) % K];
         Particle32<TRACE, LDS> q2{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt,
                                   sqdt, true, 0ull, 0u, 0u};
         pool_load(q2, P, s2);
@@ -1107,7 +1113,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
           h.last = P.last[s2];
         }
         if (!q2.cross(step, h, base + s2, S, A, t)) {
-          // reached a vertex again: back on the split stack for the next pass
+          // reached a vertex again: back on the split queue for a later pass
           pool_store(q2, P, s2, step);
           P.w[s2] = h.w;
           P.hh[s2] = h.hh;
@@ -1130,11 +1136,11 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         }
       }
       const uint64_t m_again = __ballot(again);
-      if (again) P.split[split_cnt + lane_rank(m_again)] = (uint8_t)s2;
-      split_cnt += (uint32_t)__popcll(m_again);
+      if (again) P.split[(s_tail + lane_rank(m_again)) % K] = (uint8_t)s2;
+      s_tail += (uint32_t)__popcll(m_again);
       const uint64_t m_back = __ballot(back);
-      if (back) P.ready[ready_cnt + lane_rank(m_back)] = (uint8_t)s2;
-      ready_cnt += (uint32_t)__popcll(m_back);
+      if (back) P.ready[(r_tail + lane_rank(m_back)) % K] = (uint8_t)s2;
+      r_tail += (uint32_t)__popcll(m_back);
       wave_lds_fence();
       if (has) {
         n = P.n[slot];
@@ -1198,6 +1204,25 @@ void k_pool32_batch(const GraphDev *graphs,
   S.n0 += A.n0_offset;
   const GraphDev G = graphs[it.set];
   pool_block<TRACE, LDS, STAGED, OBS>(G, S, A, it.first, s_tot, (char *)smem4);
+}
+
+// Autotuning probes: the FP32 step kernels under names of their own, so a
+// profile tells the probes apart from the launches they tune.
+template <bool LDS, bool STAGED>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
+void k_pool32_probe(GraphDev G, SetDev S, StepArgs A) {
+  extern __shared__ uint4 smem4[];
+  __shared__ uint32_t s_tot[4];
+  pool_block<false, LDS, STAGED, false>(G, S, A, blockIdx.x * kPoolPerBlock, s_tot,
+                                        (char *)smem4);
+}
+
+template <bool LDS, bool STAGED>
+__global__ __launch_bounds__(kBlock) void k_step32_probe(GraphDev G, SetDev S, StepArgs A) {
+  extern __shared__ uint4 smem4[];
+  __shared__ uint32_t s_tot[4];
+  step_block<false, false, LDS, STAGED, false>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
+                                               s_tot, (char *)smem4);
 }
 
 // ---------------------------------------------------------------- init --
@@ -1406,6 +1431,13 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
                                 g.E);
     a.obs_lds = lp.obs_lds;
     const uint32_t blocks = (s.n + kPoolPerBlock - 1) / kPoolPerBlock;
+    if (!TRACE && !obs && a.probe) {
+      with_flags([&](auto L, auto T) {
+        hipLaunchKernelGGL((k_pool32_probe<decltype(L)::value, decltype(T)::value>),
+                           dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+      }, lp.lds_exit, lp.staged);
+      return hipGetLastError();
+    }
     with_flags([&](auto L, auto T, auto O) {
       hipLaunchKernelGGL((k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
                                    decltype(O)::value>),
@@ -1417,6 +1449,13 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
   const LdsPlan lp = plan_lds(g.nnz, stage, 0, &s, g.E);
   a.obs_lds = lp.obs_lds;
   const uint32_t blocks = (s.n + kBlock - 1) / kBlock;
+  if (!FP64 && !TRACE && !obs && a.probe) {
+    with_flags([&](auto L, auto T) {
+      hipLaunchKernelGGL((k_step32_probe<decltype(L)::value, decltype(T)::value>),
+                         dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+    }, lp.lds_exit, lp.staged);
+    return hipGetLastError();
+  }
   with_flags([&](auto L, auto T, auto O) {
     hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
                                decltype(O)::value>),
