@@ -68,6 +68,30 @@ def exit_probs(ex, offsets):
     return p
 
 
+MIN_EXITS = 10_000
+
+
+def exit_err(ex_a, ex_b, offsets, min_exits=MIN_EXITS):
+    """Exit-probability error of one run against another: the largest
+    |p_a - p_b| over the slots of vertices that record at least min_exits
+    exits in run b (below that a single differing path moves a probability
+    by more than 1e-4), and the exit-weighted mean over all vertices."""
+    import numpy as np
+    pa, pb = exit_probs(ex_a, offsets), exit_probs(ex_b, offsets)
+    worst, num, den = 0.0, 0.0, 0.0
+    for v in range(offsets.size - 1):
+        s0, s1 = offsets[v], offsets[v + 1]
+        tot = float(ex_b[s0:s1].sum())
+        if tot == 0.0:
+            continue
+        d = float(np.abs(pa[s0:s1] - pb[s0:s1]).max())
+        num += tot * d
+        den += tot
+        if tot >= min_exits:
+            worst = max(worst, d)
+    return worst, (num / den if den else 0.0)
+
+
 def run_pass(B, G, g, run, prec, dt, torch, kernel_times, schedules=None):
     """One pass of the path at one dt: init, schedule tuning (FP32), simulate,
     exit counts, histogram.  kernel_times gets the HIP-event time of the
@@ -173,8 +197,9 @@ def run_vascular(args, B, torch):
         line["fp64"] = {"value": r64["substeps"] / w64, "unit": "particle-substeps/s",
                         "fp32_speedup": value / (r64["substeps"] / w64)}
         line["tv_fp32_vs_fp64"] = _tv(r32["hist"], r64["hist"])
-        line["exit_prob_err_fp32_vs_fp64"] = float(np.abs(
-            exit_probs(r32["exit"], g.vtx_offsets) - exit_probs(r64["exit"], g.vtx_offsets)).max())
+        w, m = exit_err(r32["exit"], r64["exit"], g.vtx_offsets)
+        line["exit_prob_err_fp32_vs_fp64"] = w
+        line["exit_prob_err_weighted_mean"] = m
     achieved = alg_work(1, r32["steps"], r32["hits"]) / float(np.mean(kt))
     line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                         "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
@@ -193,9 +218,9 @@ def run_batch(args, B, torch):
     graphs, counts, run = workloads.config4()
     Gs = [B.mg_graph_create(g) for g in graphs]
 
-    def make():
+    def make(prec=B.MG_FP32):
         return [B.mg_particles_init(G, c, B.MG_INIT_UNIFORM_LENGTH, init_seed=i, graph_tag=i,
-                                    precision=B.MG_FP32, max_splits=run["max_splits"])
+                                    precision=prec, max_splits=run["max_splits"])
                 for i, (G, c) in enumerate(zip(Gs, counts))]
 
     def totals(sets):
@@ -216,6 +241,24 @@ def run_batch(args, B, torch):
     wall = time.perf_counter() - t0
     tot = totals(sets) - t_before
     value = float(tot[1]) / wall
+    acc = {}
+    if not args.no_fp64:
+        # FP64 batch from the same initial states and counters (common random
+        # numbers): histogram TV and exit-probability error, worst member
+        s64 = make(B.MG_FP64)
+        b64 = B.mg_batch_create(s64)
+        B.mg_batch_simulate(b64, 8, run["dt"], run["seed"])
+        for _ in range(args.steps):
+            B.mg_batch_simulate(b64, run["n_steps"], run["dt"], run["seed"])
+        tv = ee = em = 0.0
+        for g, a, c in zip(graphs, sets, s64):
+            tv = max(tv, _tv(B.mg_histogram(a, run["bins"]), B.mg_histogram(c, run["bins"])))
+            w, m = exit_err(B.mg_exit_counts(a)[0], B.mg_exit_counts(c)[0], g.vtx_offsets)
+            ee, em = max(ee, w), max(em, m)
+        acc = {"tv_fp32_vs_fp64_max": tv, "exit_prob_err_fp32_vs_fp64_max": ee,
+               "exit_prob_err_weighted_mean_max": em,
+               "exit_err_min_exits_per_vertex": MIN_EXITS}
+        del b64, s64
     # the same work launched graph by graph
     solo = make()
     for s in solo:
@@ -238,6 +281,7 @@ def run_batch(args, B, torch):
             "unbatched_value": float(tot[1]) / args.steps / wall_solo,
             "batch_speedup": wall_solo * args.steps / wall,
             "hits_per_step": float(tot[2]) / float(tot[3])}
+    line.update(acc)
     return line
 
 
@@ -280,7 +324,7 @@ def run_sweep(args, B, torch):
             res[prec] = dict(wall=wall, sub=sub, hists=hists, exits=exits)
             del batch_net, batch_st, sets
         tv = max(_tv(a, b) for a, b in zip(res[B.MG_FP32]["hists"], res[B.MG_FP64]["hists"]))
-        ee = max(float(np.abs(exit_probs(a, g.vtx_offsets) - exit_probs(b, g.vtx_offsets)).max())
+        ee = max(exit_err(a, b, g.vtx_offsets)[0]
                  for a, b, g in zip(res[B.MG_FP32]["exits"], res[B.MG_FP64]["exits"], graphs))
         # distance of the FP64 exit law from b, per vertex weighted by exits
         dev = {}
@@ -542,7 +586,7 @@ def main():
     value = sub32 / wall32
 
     out_fp64 = None
-    tv = exit_err = None
+    tv = exit_e = None
     if not args.no_fp64:
         ktimes64 = []
         torch.cuda.synchronize()
@@ -553,9 +597,8 @@ def main():
         sub64 = sum(r["substeps"] for r in res64)
         tv = [0.5 * float(np.abs(a["hist"].astype(float) - b["hist"].astype(float)).sum())
               / float(b["hist"].sum()) for a, b in zip(res32, res64)]
-        exit_err = [float(np.abs(exit_probs(a["exit"], g.vtx_offsets)
-                                 - exit_probs(b["exit"], g.vtx_offsets)).max())
-                    for a, b in zip(res32, res64)]
+        exit_e = [exit_err(a["exit"], b["exit"], g.vtx_offsets)[0]
+                  for a, b in zip(res32, res64)]
         k64 = sum(ktimes64)
         w64 = sum(alg_work(0, r["steps"], r["hits"]) for r in res64)
         out_fp64 = {"value": sub64 / wall64, "unit": "particle-substeps/s",
@@ -590,7 +633,7 @@ def main():
         "truncations": [r["trunc"] for r in res32],
         "fp64": out_fp64,
         "tv_fp32_vs_fp64": tv,
-        "exit_prob_err_fp32_vs_fp64": exit_err,
+        "exit_prob_err_fp32_vs_fp64": exit_e,
         "roofline": roof,
     }
     if not args.no_cpu:

@@ -422,3 +422,67 @@ def test_autotune_choice_and_auto_schedule_bitwise(B):
         assert np.array_equal(ra[f], rl[f]), f
     for x, y in zip(B.mg_exit_counts(auto), B.mg_exit_counts(lanes)):
         assert np.array_equal(x, y)
+
+
+def _read_rows(B, p, rows):
+    out = {k: [] for k in ("edge", "x", "alive", "seqhash", "hits")}
+    for r in rows:
+        d = B.mg_particles_read(p, int(r), 1, trace=True)
+        for k in out:
+            out[k].append(d[k][0])
+    return {k: np.array(v) for k, v in out.items()}
+
+
+def test_full_size_config3_sampled(B, orc):
+    """Config 3 at its full size (1e8 particles, 1e4 steps at 10x the CFL dt)
+    in the launch configuration the benchmark times: sampled particle ids
+    against the oracle one by one in FP64, FP32 under common random numbers,
+    and the totals that hold at any size."""
+    g, run = workloads.config3()
+    n, steps, dt = run["n_particles"], run["n_steps"], run["dt"]
+    G = B.mg_graph_create(g)
+    rows = np.sort(np.random.default_rng(3).choice(n, 48, replace=False))
+    st = orc.init(g, n, 2, seed=0, pids=rows)
+    orc.simulate(g, st, 0, steps, dt, 0)
+    for prec in (B.MG_FP64, B.MG_FP32):
+        p = B.mg_particles_init(G, n, 2, init_seed=0, precision=prec, trace=True)
+        B.mg_simulate(p, steps, dt, 0)
+        r = _read_rows(B, p, rows)
+        ex, ab, tot = B.mg_exit_counts(p)
+        h = B.mg_histogram(p, run["bins"])
+        assert int(h.sum()) + int(ab.sum()) == n
+        assert int(tot[1]) >= int(tot[3])
+        if prec == B.MG_FP64:
+            _compare_fp64(st, r, rows=np.arange(rows.size), min_frac=1.0)
+            h64 = h
+        else:
+            assert (r["seqhash"] == st.seqhash).mean() >= 0.9
+            assert _tv(h, h64) <= 2e-3
+        del p
+
+
+def test_full_size_config4_batch_sampled(B, orc):
+    """Config 4's full batch (512 graphs, 1.18e8 particles, 1000 steps) in
+    one batched launch, FP64: sampled particles of 24 members against the
+    oracle one by one; FP32 batch within TV 2e-3 of it on every member."""
+    graphs, counts, run = workloads.config4()
+    Gs = [B.mg_graph_create(g) for g in graphs]
+    pick = np.random.default_rng(4).choice(len(graphs), 24, replace=False)
+    res = {}
+    for prec in (B.MG_FP64, B.MG_FP32):
+        sets = [B.mg_particles_init(G, c, 2, init_seed=i, graph_tag=i, precision=prec,
+                                    trace=(prec == B.MG_FP64))
+                for i, (G, c) in enumerate(zip(Gs, counts))]
+        b = B.mg_batch_create(sets)
+        B.mg_batch_simulate(b, run["n_steps"], run["dt"], run["seed"])
+        res[prec] = [B.mg_histogram(sets[i], 16) for i in pick]
+        if prec == B.MG_FP64:
+            for i in pick:
+                rows = np.array([0, counts[i] // 2, counts[i] - 1])
+                st = orc.init(graphs[i], counts[i], 2, seed=int(i), tag=int(i), pids=rows)
+                orc.simulate(graphs[i], st, 0, run["n_steps"], run["dt"], run["seed"], tag=int(i))
+                _compare_fp64(st, _read_rows(B, sets[i], rows), rows=np.arange(rows.size),
+                              min_frac=1.0)
+        del b, sets
+    for h32, h64 in zip(res[B.MG_FP32], res[B.MG_FP64]):
+        assert _tv(h32, h64) <= 2e-3
