@@ -105,6 +105,9 @@ struct mg_particles {
   SetDev sd{};
   uint64_t step = 0;
   uint64_t obs_start = 0;  // step counter when the streamed histogram started
+  // histogram kernel choice for large E * nb (timed on the first call)
+  mutable int32_t hist_nb = 0;
+  mutable bool hist_tiled = false;
 };
 
 struct mg_batch {
@@ -624,9 +627,40 @@ mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge, uint64_t *o
   const bool dev_out = is_device_pointer(out);
   uint64_t *d_out = out;
   if (!dev_out) MG_HIP(hipMalloc(&d_out, (size_t)need * 8), "allocating the histogram");
-  hipError_t he = hipMemsetAsync(d_out, 0, (size_t)need * 8, p->stream);
-  if (he == hipSuccess)
-    he = launch_histogram(p->g->gd, p->sd, bins_per_edge, d_out, p->prec == MG_FP64, p->stream);
+  const bool fp64 = p->prec == MG_FP64;
+  hipError_t he = hipSuccess;
+  if (need > kLdsHistMax && bins_per_edge <= kLdsHistMax && p->hist_nb != bins_per_edge) {
+    // Too large for one LDS copy: time 64-bit global atomics against
+    // edge-range LDS tiles once for this bin count and keep the faster.
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (hipEvent_t &e : ev)
+      if (he == hipSuccess) he = hipEventCreate(&e);
+    float t_glob = 0.0f, t_tile = 0.0f;
+    if (he == hipSuccess) he = hipMemsetAsync(d_out, 0, (size_t)need * 8, p->stream);
+    if (he == hipSuccess) he = hipEventRecord(ev[0], p->stream);
+    if (he == hipSuccess)
+      he = launch_histogram(p->g->gd, p->sd, bins_per_edge, d_out, fp64, false, p->stream);
+    if (he == hipSuccess) he = hipEventRecord(ev[1], p->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(d_out, 0, (size_t)need * 8, p->stream);
+    if (he == hipSuccess) he = hipEventRecord(ev[2], p->stream);
+    if (he == hipSuccess)
+      he = launch_histogram(p->g->gd, p->sd, bins_per_edge, d_out, fp64, true, p->stream);
+    if (he == hipSuccess) he = hipEventRecord(ev[3], p->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(ev[3]);
+    if (he == hipSuccess) he = hipEventElapsedTime(&t_glob, ev[0], ev[1]);
+    if (he == hipSuccess) he = hipEventElapsedTime(&t_tile, ev[2], ev[3]);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (he == hipSuccess) {
+      p->hist_nb = bins_per_edge;
+      p->hist_tiled = t_tile < t_glob;
+    }
+  } else {
+    he = hipMemsetAsync(d_out, 0, (size_t)need * 8, p->stream);
+    if (he == hipSuccess)
+      he = launch_histogram(p->g->gd, p->sd, bins_per_edge, d_out, fp64,
+                            p->hist_nb == bins_per_edge && p->hist_tiled, p->stream);
+  }
   if (he == hipSuccess && !dev_out)
     he = hipMemcpyAsync(out, d_out, (size_t)need * 8, hipMemcpyDeviceToHost, p->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(p->stream);

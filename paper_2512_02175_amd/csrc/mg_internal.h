@@ -158,8 +158,10 @@ struct KernelLaunch {
 };
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
                           const StepArgs &a, bool fp64, bool trace, bool obs);
+// tiled: edge-range LDS tiles when E * nb exceeds one LDS copy (else 64-bit
+// global atomics); below that size both take the single LDS copy.
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,
-                            uint64_t *out, bool fp64, hipStream_t st);
+                            uint64_t *out, bool fp64, bool tiled, hipStream_t st);
 hipError_t launch_histogram_csr(const GraphDev &g, const SetDev &s, const int32_t *off,
                                 const double *up, int32_t nbins, uint64_t *out, bool fp64,
                                 hipStream_t st);

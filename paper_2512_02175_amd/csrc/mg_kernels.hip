@@ -17,6 +17,7 @@
 // The FP32 path consumes the same integers as the FP64 path.
 //
 // Compiled with -ffp-contract=off: every fused multiply-add is explicit.
+#include <algorithm>
 #include <type_traits>
 
 #include "mg_internal.h"
@@ -1324,6 +1325,42 @@ __global__ __launch_bounds__(kBlock) void k_hist(GraphDev G, SetDev S, int32_t n
   }
 }
 
+// Histogram too large for one LDS copy, in edge-range tiles: blockIdx.y
+// picks a range of whole edges whose bins fit in LDS, and the block counts
+// only the particles on those edges (the state word decides; the position
+// is read only for them), then merges its u32 counts into the u64 bins.
+template <bool FP64>
+__global__ __launch_bounds__(kBlock) void k_hist_tiled(GraphDev G, SetDev S, int32_t nb,
+                                                       int32_t edges_per_tile, uint64_t *out) {
+  extern __shared__ uint32_t s_bin[];
+  const int32_t e0 = (int32_t)blockIdx.y * edges_per_tile;
+  const int32_t e1 = min(G.E, e0 + edges_per_tile);
+  const int32_t nbins = (e1 - e0) * nb;
+  for (int32_t b = threadIdx.x; b < nbins; b += blockDim.x) s_bin[b] = 0;
+  __syncthreads();
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t pid = blockIdx.x * kBlock + threadIdx.x; pid < S.n; pid += stride) {
+    const uint32_t ef = S.ef[pid];
+    if (ef & kDeadBit) continue;
+    const int32_t e = (int32_t)(ef & kEdgeMask);
+    if (e < e0 || e >= e1) continue;
+    const double L = G.e64[e].L;
+    double x;
+    if (FP64) {
+      x = S.x64[pid];
+    } else {
+      const float2 yy = S.y32[pid];
+      const double y = (double)yy.x + (double)yy.y;
+      x = (ef & kSideBit) ? L - y : y;
+    }
+    atomicAdd(&s_bin[(e - e0) * nb + bin_of(x, L, nb)], 1u);
+  }
+  __syncthreads();
+  uint64_t *o = out + (int64_t)e0 * nb;
+  for (int32_t b = threadIdx.x; b < nbins; b += blockDim.x)
+    if (s_bin[b]) atomicAdd((unsigned long long *)&o[b], (unsigned long long)s_bin[b]);
+}
+
 // Histogram over per-edge bins of any widths (the appendix's general
 // histogram kernel): the bins of edge e are off[e] .. off[e+1]-1 with upper
 // boundaries up[] (FP64, strictly increasing along the edge).  A particle at
@@ -1541,8 +1578,23 @@ hipError_t launch_histogram_csr(const GraphDev &g, const SetDev &s, const int32_
 }
 
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,
-                            uint64_t *out, bool fp64, hipStream_t st) {
+                            uint64_t *out, bool fp64, bool tiled, hipStream_t st) {
   const int64_t nbins = (int64_t)g.E * nb;
+  if (tiled && nbins > kLdsHistMax && nb <= kLdsHistMax) {
+    const int32_t ept = kLdsHistMax / nb;
+    const uint32_t tiles = (uint32_t)((g.E + ept - 1) / ept);
+    uint32_t bx = (s.n + kBlock - 1) / kBlock;
+    const uint32_t want = std::max<uint32_t>(1u, 4096u / tiles);  // ~4096 blocks in all
+    if (bx > want) bx = want;
+    const size_t shm = (size_t)ept * nb * 4;
+    if (fp64)
+      hipLaunchKernelGGL((k_hist_tiled<true>), dim3(bx, tiles), dim3(kBlock), shm, st, g, s, nb,
+                         ept, out);
+    else
+      hipLaunchKernelGGL((k_hist_tiled<false>), dim3(bx, tiles), dim3(kBlock), shm, st, g, s, nb,
+                         ept, out);
+    return hipGetLastError();
+  }
   const bool lds = nbins <= kLdsHistMax;
   uint32_t blocks = (s.n + kBlock - 1) / kBlock;
   if (lds && blocks > 1024) blocks = 1024;  // amortise the LDS merge

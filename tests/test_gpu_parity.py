@@ -333,6 +333,17 @@ def test_vascular_network_fp64_parity_and_fp32(B, orc):
     ex, ab, tot = B.mg_exit_counts(p)
     nd = int(diff.sum())
     assert np.abs(ab.astype(np.int64) - c.absorbed.astype(np.int64)).sum() <= nd
+    # 1.66e6 bins: the first call times global atomics against edge-range
+    # LDS tiles, later calls use the faster; both agree with the oracle and
+    # with the binary-search kernel over the same (uniform) bins
+    h1 = B.mg_histogram(p, 64)
+    h2 = B.mg_histogram(p, 64)
+    assert np.array_equal(h1, h2)
+    ho = orc.histogram(g, st, 64)
+    assert np.abs(h1.astype(np.int64) - ho.astype(np.int64)).sum() <= 2 * nd
+    off = np.arange(g.n_edges + 1, dtype=np.int32) * 64
+    up = np.concatenate([np.arange(1, 65) * (L / 64) for L in g.length])
+    assert np.array_equal(B.mg_histogram_csr(p, off, up), h1.ravel())
     G, p32 = _gpu_run(B, g, n, 2, steps, dt, 13, init_seed=3, precision=1, G=G)
     r32 = B.mg_particles_read(p32, trace=True)
     assert (r32["seqhash"] == st.seqhash).mean() > 0.99
