@@ -101,8 +101,8 @@ def run_pass(B, G, g, run, prec, dt, torch, kernel_times, schedules=None):
     if prec == B.MG_FP32:
         t = B.mg_autotune(p, dt, run["seed"])
         if schedules is not None:
-            schedules.append("k_pool32" if t["schedule"] == B.MG_SCHED_POOLS
-                             else "k_step<fp32>")
+            schedules.append(f"k_pool32 ({t['pool_size']} per wave, idle {t['idle_trigger']})"
+                             if t["schedule"] == B.MG_SCHED_POOLS else "k_step<fp32>")
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()

@@ -111,11 +111,14 @@ void mg_graph_destroy(mg_graph *g);
  *   schedule      FP32 kernel schedule: MG_SCHED_AUTO (0), MG_SCHED_LANES
  *                 (1: one particle per lane for a whole launch) or
  *                 MG_SCHED_POOLS (2: each wave cycles 128 particles through
- *                 its lanes and resolves vertex hits in full-width passes).
+ *                 its lanes and resolves vertex hits in full-width passes)
+ *                 or MG_SCHED_POOLS256 (3: the same with 256 particles).
  *                 Results are identical; only the speed differs.  FP64 sets
  *                 always use the lane schedule.
  */
-typedef enum { MG_SCHED_AUTO = 0, MG_SCHED_LANES = 1, MG_SCHED_POOLS = 2 } mg_schedule;
+typedef enum {
+  MG_SCHED_AUTO = 0, MG_SCHED_LANES = 1, MG_SCHED_POOLS = 2, MG_SCHED_POOLS256 = 3
+} mg_schedule;
 
 typedef struct {
   mg_precision precision;
@@ -276,22 +279,26 @@ void mg_batch_destroy(mg_batch *b);
 
 /*
  * Autotuning of an FP32 set's kernel schedule.  The candidates (one
- * particle per lane; wave pools with partial split passes at 4, 8, 16 or 32
- * idle lanes) all give identical results, so tuning changes only speed.
- * Each candidate advances a scratch copy of the set's first
- * min(n, 2^21) particles by probe_steps steps (<= 0: 32) of size dt with
+ * particle per lane; wave pools of 128 particles (2 per lane) that start a
+ * partial split pass at 4, 8, 16 or 32 idle lanes; pools of 256 (4 per
+ * lane) at 8 or 16) all give identical results, so tuning changes only
+ * speed.  Each candidate advances a scratch copy of the set's first
+ * min(n, 2^22) particles by probe_steps steps (<= 0: 1024) of size dt with
  * Philox key seed, timed with HIP events on the set's stream; the set
- * keeps the fastest for its later mg_simulate calls at this dt.  Sets
- * created with schedule MG_SCHED_AUTO are tuned this way on their first
- * mg_simulate at each dt.  FP64 sets have nothing to tune (schedule lanes).
- * `out` (may be NULL) receives the choice and the probe times.  Allocates
- * scratch device memory for the probe; synchronises the stream.
+ * keeps the fastest for its later mg_simulate calls at this dt.  The
+ * result is also kept with the graph: later calls for any set on the same
+ * graph at the same dt take it without probing.  Sets created with
+ * schedule MG_SCHED_AUTO are tuned this way on their first mg_simulate at
+ * each dt.  FP64 sets have nothing to tune (schedule lanes).  `out` (may be
+ * NULL) receives the choice and the probe times.  A probe allocates scratch
+ * device memory and synchronises the stream.
  */
 typedef struct {
   int32_t schedule;      /* MG_SCHED_LANES or MG_SCHED_POOLS */
   int32_t idle_trigger;  /* pools: idle lanes that start a partial split pass */
+  int32_t pool_size;     /* pools: particles per wave (128 or 256), else 0 */
   int32_t n_probes;      /* entries used in probe_ms */
-  float probe_ms[8];     /* lanes, pools@4, pools@8, pools@16, pools@32 */
+  float probe_ms[8];     /* lanes, pools128@4, @8, @16, @32, pools256@8, @16 */
 } mg_tuning;
 
 mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_steps,

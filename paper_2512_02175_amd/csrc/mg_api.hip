@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -79,6 +80,9 @@ bool is_finite(double v) { return std::isfinite(v); }
 
 struct mg_graph {
   int32_t V, E, nnz;
+  // FP32 schedule tuning results per dt, shared by the sets on this graph
+  mutable std::mutex tune_mu;
+  mutable std::vector<std::pair<double, mg_tuning>> tune_cache;
   std::vector<double> length;  // host copy for readback conversion
   std::vector<VtxBlk> vtx_host;
   void *dev = nullptr;         // one allocation holding every table
@@ -400,7 +404,7 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
     return fail(MG_EINVAL, "max_splits must be in [0, 255] (0: default)");
   if (o.max_splits == 0) o.max_splits = 8;
   if (o.steps_per_launch < 0) return fail(MG_EINVAL, "steps_per_launch must be >= 0");
-  if (o.schedule < MG_SCHED_AUTO || o.schedule > MG_SCHED_POOLS)
+  if (o.schedule < MG_SCHED_AUTO || o.schedule > MG_SCHED_POOLS256)
     return fail(MG_EINVAL, "unknown schedule");
   if (mode == MG_INIT_EXPLICIT) {
     if (!edge || !pos) return fail(MG_EINVAL, "explicit init needs edge and pos");
@@ -569,6 +573,7 @@ static mg_status check_steps(const mg_particles *p, int64_t n_steps, double dt) 
 static int32_t fp32_kernel(const mg_particles *p) {
   if (p->schedule == MG_SCHED_LANES) return 0;
   if (p->schedule == MG_SCHED_POOLS) return 1;
+  if (p->schedule == MG_SCHED_POOLS256) return 2;
   return p->tuned ? p->tuned_kernel : 1;
 }
 
@@ -1048,8 +1053,21 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
     if (out) *out = res;
     return MG_OK;
   }
-  const int64_t n = std::min<int64_t>(p->n, 1 << 21);
-  const uint32_t steps = (uint32_t)(probe_steps > 0 ? probe_steps : 32);
+  {
+    std::lock_guard<std::mutex> lock(p->g->tune_mu);
+    for (const auto &c : p->g->tune_cache)
+      if (c.first == dt) {
+        res = c.second;
+        p->tuned = true;
+        p->tuned_dt = dt;
+        p->tuned_kernel = res.schedule == MG_SCHED_LANES ? 0 : (res.pool_size == kPoolLarge ? 2 : 1);
+        p->tuned_idle = res.idle_trigger;
+        if (out) *out = res;
+        return MG_OK;
+      }
+  }
+  const int64_t n = std::min<int64_t>(p->n, 1 << 22);
+  const uint32_t steps = (uint32_t)(probe_steps > 0 ? probe_steps : 1024);
   if ((uint64_t)p->step + steps > 0xFFFFFFFFull)
     return fail(MG_EINVAL, "the probe would pass step 2^32");
   const SetLayout L = set_layout(p->g->V, p->g->nnz, n, MG_FP32, false);
@@ -1073,14 +1091,17 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   a.key1 = (uint32_t)(seed >> 32);
   a.dt = dt;
   a.probe = 1;
-  const int32_t cand_kernel[5] = {0, 1, 1, 1, 1};
-  const int32_t cand_idle[5] = {8, 4, 8, 16, 32};
+  // one particle per lane; pools of 128 (2 per lane) at four idle triggers;
+  // pools of 256 (4 per lane) at two
+  constexpr int kCand = 7;
+  const int32_t cand_kernel[kCand] = {0, 1, 1, 1, 1, 2, 2};
+  const int32_t cand_idle[kCand] = {8, 4, 8, 16, 32, 8, 16};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
   float best = 0.0f;
   int best_i = -1;
-  for (int i = 0; i < 5 && he == hipSuccess; ++i) {
+  for (int i = 0; i < kCand && he == hipSuccess; ++i) {
     he = hipMemcpyAsync(sd.ef, p->sd.ef, (size_t)n * 4, hipMemcpyDeviceToDevice, p->stream);
     if (he == hipSuccess)
       he = hipMemcpyAsync(sd.y32, p->sd.y32, (size_t)n * 8, hipMemcpyDeviceToDevice, p->stream);
@@ -1103,13 +1124,18 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(mem);
   if (he != hipSuccess) return hip_fail(he, "running the tuning probe");
-  res.n_probes = 5;
+  res.n_probes = kCand;
   res.schedule = cand_kernel[best_i] ? MG_SCHED_POOLS : MG_SCHED_LANES;
-  res.idle_trigger = cand_idle[best_i];
+  res.idle_trigger = cand_kernel[best_i] ? cand_idle[best_i] : 0;
+  res.pool_size = cand_kernel[best_i] ? pool_per_wave(cand_kernel[best_i]) : 0;
   p->tuned = true;
   p->tuned_dt = dt;
   p->tuned_kernel = cand_kernel[best_i];
   p->tuned_idle = cand_idle[best_i];
+  {
+    std::lock_guard<std::mutex> lock(p->g->tune_mu);
+    p->g->tune_cache.emplace_back(dt, res);
+  }
   if (out) *out = res;
   return MG_OK;
 }

@@ -104,7 +104,8 @@ struct StepArgs {
   int32_t max_splits;
   uint32_t key0, key1;
   double dt;
-  int32_t kernel;  // FP32 schedule: 0 lane-per-particle windows, 1 wave pools
+  int32_t kernel;  // FP32 schedule: 0 lane-per-particle windows, 1 / 2 wave
+                   // pools of 128 / 256 particles
   int32_t idle;    // wave pools: idle lanes that trigger a partial split pass
   uint32_t n0_offset;  // batched launches: steps taken earlier in the call
   int32_t obs_lds;     // streamed-histogram bins privatised in LDS (0: global)
@@ -118,11 +119,11 @@ struct BatchItem {
 };
 
 constexpr int kBlock = 256;
-#ifndef MG_POOL_PER_WAVE
-#define MG_POOL_PER_WAVE 128
-#endif
-constexpr int kPoolPerWave = MG_POOL_PER_WAVE;          // FP32 wave pools (<= 256)
-constexpr int kPoolPerBlock = kPoolPerWave * (kBlock / 64);
+// FP32 wave pools hold 128 or 256 particles per wave (2 or 4 per lane); the
+// step schedule (StepArgs::kernel) picks: 0 one particle per lane, 1 pools
+// of 128, 2 pools of 256.
+constexpr int kPoolSmall = 128, kPoolLarge = 256;
+inline int pool_per_wave(int32_t kernel) { return kernel == 2 ? kPoolLarge : kPoolSmall; }
 constexpr int kLdsExitMax = 16384;  // slots counted in LDS (64 KiB of u32) when
                                     // the block's LDS budget allows
 constexpr int kLdsStageMax = 24576; // graph tables staged in LDS up to this size

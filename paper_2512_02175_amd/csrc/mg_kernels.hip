@@ -838,7 +838,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
 }
 
 // ------------------------------------------------ FP32 wave-pool kernel --
-// Each wave owns kPoolPerWave particles: 64 ride in the lanes, the others
+// Each wave owns PW particles (128 or 256): 64 ride in the lanes, the others
 // wait in the wave's private LDS home slots.  A lane runs its particle's
 // first sub-steps for one main-stream Philox group (four steps) per
 // iteration; a particle whose sub-step reaches a vertex is parked: its state
@@ -854,32 +854,31 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
 // results equal the plain per-particle order bit for bit.  Waves never wait
 // for one another: the queues and their counters are private to a wave.
 constexpr int kWavesPerBlock = kBlock / 64;
-static_assert(kPoolPerWave % 64 == 0 && kPoolPerWave >= 128 && kPoolPerWave <= 256,
-              "a wave pool holds 2 to 4 particles per lane");
 
-template <bool TRACE>
+template <bool TRACE, int PW>
 struct PoolTrace {
-  uint32_t hits[kPoolPerWave];
-  uint64_t hash[kPoolPerWave];
+  uint32_t hits[PW];
+  uint64_t hash[PW];
 };
-template <>
-struct PoolTrace<false> {};
+template <int PW>
+struct PoolTrace<false, PW> {};
 
 // A wave's pool in LDS: home slots of its particles, the resolution state
 // of parked steps, and the ready and split queues (slot ids).
-template <bool TRACE>
-struct PoolLds32 : PoolTrace<TRACE> {
-  uint32_t ef[kPoolPerWave];
-  float y[kPoolPerWave];
-  float yl[kPoolPerWave];
-  uint32_t n[kPoolPerWave];   // next step (ready) or the step to resolve (parked)
-  float w[kPoolPerWave];      // normal of a parked step's pending sub-step
-  float hh[kPoolPerWave];     // remaining time of a parked step (when k > 0)
-  float hl[kPoolPerWave];
-  int32_t last[kPoolPerWave]; // last slot drawn in the parked step
-  uint8_t k[kPoolPerWave];    // crossings so far in the parked step
-  uint8_t ready[kPoolPerWave];
-  uint8_t split[kPoolPerWave];
+template <bool TRACE, int PW>
+struct PoolLds32 : PoolTrace<TRACE, PW> {
+  static_assert(PW % 64 == 0 && PW <= 256, "slot ids are bytes");
+  uint32_t ef[PW];
+  float y[PW];
+  float yl[PW];
+  uint32_t n[PW];   // next step (ready) or the step to resolve (parked)
+  float w[PW];      // normal of a parked step's pending sub-step
+  float hh[PW];     // remaining time of a parked step (when k > 0)
+  float hl[PW];
+  int32_t last[PW]; // last slot drawn in the parked step
+  uint8_t k[PW];    // crossings so far in the parked step
+  uint8_t ready[PW];
+  uint8_t split[PW];
 };
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
@@ -892,8 +891,8 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 // move the accesses across each other.
 __device__ __forceinline__ void wave_lds_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
-template <bool TRACE, bool LDS>
-__device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolLds32<TRACE> &P,
+template <bool TRACE, bool LDS, int PW>
+__device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolLds32<TRACE, PW> &P,
                                           uint32_t s) {
   const uint32_t ef = P.ef[s];
   q.e = (int32_t)(ef & kEdgeMask);
@@ -910,8 +909,8 @@ __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolL
   }
 }
 
-template <bool TRACE, bool LDS>
-__device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS> &q, PoolLds32<TRACE> &P,
+template <bool TRACE, bool LDS, int PW>
+__device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS> &q, PoolLds32<TRACE, PW> &P,
                                            uint32_t s, uint32_t n) {
   P.ef[s] = (uint32_t)q.e | (q.side ? kSideBit : 0u);
   P.y[s] = q.y;
@@ -937,9 +936,9 @@ __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS> &q, con
   t.sub += taken;
 }
 
-template <bool TRACE, bool LDS, bool OBS>
+template <bool TRACE, bool LDS, bool OBS, int PW>
 __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
-                           const StepArgs &A, uint32_t base, PoolLds32<TRACE> &P,
+                           const StepArgs &A, uint32_t base, PoolLds32<TRACE, PW> &P,
                            uint32_t *s_exit, Tally &t, const ObsSink &sink) {
   const uint32_t lane = threadIdx.x & 63u;
   const float dt = (float)A.dt;
@@ -953,12 +952,12 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   // Ready and split queues: FIFO rings over the pool's slot ids, with
   // wave-uniform head and tail counters.  FIFO keeps the particles of a pool
   // advancing together, so a launch ends without a long tail of stragglers.
-  constexpr uint32_t K = (uint32_t)kPoolPerWave;
+  constexpr uint32_t K = (uint32_t)PW;
   uint32_t r_head = 0, r_tail = 0, s_head = 0, s_tail = 0;
 
   // Initial placement: slot `lane` rides in the lane, slots 64k + lane wait.
 #pragma unroll
-  for (uint32_t half = 0; half < (uint32_t)kPoolPerWave / 64u; ++half) {
+  for (uint32_t half = 0; half < (uint32_t)PW / 64u; ++half) {
     const uint32_t s = lane + 64u * half;
     const uint32_t pid = base + s;
     bool ok = false;
@@ -1153,7 +1152,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
 
 // Shared memory of a pool block: [exit counters][staged tables][pools]
 // [snapshot bins].
-template <bool TRACE, bool LDS, bool STAGED, bool OBS>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW>
 __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t block_first,
                                            uint32_t *s_tot, char *smem) {
@@ -1164,16 +1163,16 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
   const int32_t ex = LDS ? exit_bytes(G.nnz) : 0;
   const GView view = block_view<false, STAGED>(G, smem + ex);
   const int32_t o_pools = align16(ex + (STAGED ? G.stage_bytes32 : 0));
-  PoolLds32<TRACE> *pools = (PoolLds32<TRACE> *)(smem + o_pools);
+  PoolLds32<TRACE, PW> *pools = (PoolLds32<TRACE, PW> *)(smem + o_pools);
   ObsSink o{nullptr, G.e64};
   if (OBS && A.obs_lds) {
-    o.lds = (uint32_t *)(smem + o_pools + (int32_t)sizeof(PoolLds32<TRACE>) * kWavesPerBlock);
+    o.lds = (uint32_t *)(smem + o_pools + (int32_t)sizeof(PoolLds32<TRACE, PW>) * kWavesPerBlock);
     for (int32_t b = threadIdx.x; b < A.obs_lds; b += blockDim.x) o.lds[b] = 0;
   }
   __syncthreads();
   Tally t{0, 0, 0, 0};
   const uint32_t wave = threadIdx.x >> 6;
-  run_pool32<TRACE, LDS, OBS>(view, G.E, S, A, block_first + wave * kPoolPerWave,
+  run_pool32<TRACE, LDS, OBS, PW>(view, G.E, S, A, block_first + wave * PW,
                               pools[wave], s_exit, t, o);
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
   if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
@@ -1183,16 +1182,16 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
 #define MG_POOL_WAVES_PER_EU 7
 #endif
 
-template <bool TRACE, bool LDS, bool STAGED, bool OBS>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  pool_block<TRACE, LDS, STAGED, OBS>(G, S, A, blockIdx.x * kPoolPerBlock, s_tot,
-                                      (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS, PW>(G, S, A, blockIdx.x * (PW * kWavesPerBlock), s_tot,
+                                          (char *)smem4);
 }
 
-template <bool TRACE, bool LDS, bool STAGED, bool OBS>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32_batch(const GraphDev *graphs,
                                                          const SetDev *sets,
@@ -1204,18 +1203,18 @@ void k_pool32_batch(const GraphDev *graphs,
   SetDev S = sets[it.set];
   S.n0 += A.n0_offset;
   const GraphDev G = graphs[it.set];
-  pool_block<TRACE, LDS, STAGED, OBS>(G, S, A, it.first, s_tot, (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS, PW>(G, S, A, it.first, s_tot, (char *)smem4);
 }
 
 // Autotuning probes: the FP32 step kernels under names of their own, so a
 // profile tells the probes apart from the launches they tune.
-template <bool LDS, bool STAGED>
+template <bool LDS, bool STAGED, int PW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32_probe(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  pool_block<false, LDS, STAGED, false>(G, S, A, blockIdx.x * kPoolPerBlock, s_tot,
-                                        (char *)smem4);
+  pool_block<false, LDS, STAGED, false, PW>(G, S, A, blockIdx.x * (PW * kWavesPerBlock), s_tot,
+                                            (char *)smem4);
 }
 
 template <bool LDS, bool STAGED>
@@ -1462,24 +1461,27 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
                          hipStream_t st) {
   StepArgs a = a0;
   const bool obs = s.obs != nullptr;
-  if (!FP64 && a.kernel == 1) {
-    const int32_t stage = g.stage_bytes32;
-    const LdsPlan lp = plan_lds(g.nnz, stage, sizeof(PoolLds32<TRACE>) * kWavesPerBlock, &s,
-                                g.E);
-    a.obs_lds = lp.obs_lds;
-    const uint32_t blocks = (s.n + kPoolPerBlock - 1) / kPoolPerBlock;
-    if (!TRACE && !obs && a.probe) {
-      with_flags([&](auto L, auto T) {
-        hipLaunchKernelGGL((k_pool32_probe<decltype(L)::value, decltype(T)::value>),
+  if (!FP64 && a.kernel >= 1) {
+    with_flags([&](auto Big) {
+      constexpr int PW = decltype(Big)::value ? kPoolLarge : kPoolSmall;
+      const int32_t stage = g.stage_bytes32;
+      const LdsPlan lp = plan_lds(g.nnz, stage, sizeof(PoolLds32<TRACE, PW>) * kWavesPerBlock,
+                                  &s, g.E);
+      a.obs_lds = lp.obs_lds;
+      const uint32_t blocks = (s.n + PW * kWavesPerBlock - 1) / (PW * kWavesPerBlock);
+      if (!TRACE && !obs && a.probe) {
+        with_flags([&](auto L, auto T) {
+          hipLaunchKernelGGL((k_pool32_probe<decltype(L)::value, decltype(T)::value, PW>),
+                             dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+        }, lp.lds_exit, lp.staged);
+        return;
+      }
+      with_flags([&](auto L, auto T, auto O) {
+        hipLaunchKernelGGL((k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
+                                     decltype(O)::value, PW>),
                            dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
-      }, lp.lds_exit, lp.staged);
-      return hipGetLastError();
-    }
-    with_flags([&](auto L, auto T, auto O) {
-      hipLaunchKernelGGL((k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
-                                   decltype(O)::value>),
-                         dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
-    }, lp.lds_exit, lp.staged, obs);
+      }, lp.lds_exit, lp.staged, obs);
+    }, a.kernel == 2);
     return hipGetLastError();
   }
   const int32_t stage = FP64 ? g.stage_bytes64 : g.stage_bytes32;
@@ -1508,20 +1510,23 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
   KernelLaunch k{};
   k.grid = dim3(n_items);
   k.block = dim3(kBlock);
-  const bool pools = !FP64 && a.kernel == 1;
-  const LdsPlan lp = plan_lds(max_nnz, max_stage,
-                              pools ? sizeof(PoolLds32<TRACE>) * kWavesPerBlock : 0, nullptr,
-                              0);
-  k.shm = lp.shm;
-  with_flags([&](auto L, auto T, auto O) {
-    constexpr bool l = decltype(L)::value, t = decltype(T)::value, o = decltype(O)::value;
-    if constexpr (!FP64)
-      if (pools) {
-        k.func = (const void *)k_pool32_batch<TRACE, l, t, o>;
-        return;
-      }
-    k.func = (const void *)k_batch<FP64, TRACE, l, t, o>;
-  }, lp.lds_exit, lp.staged, obs);
+  const bool pools = !FP64 && a.kernel >= 1;
+  with_flags([&](auto Big) {
+    constexpr int PW = decltype(Big)::value ? kPoolLarge : kPoolSmall;
+    const LdsPlan lp = plan_lds(max_nnz, max_stage,
+                                pools ? sizeof(PoolLds32<TRACE, PW>) * kWavesPerBlock : 0,
+                                nullptr, 0);
+    k.shm = lp.shm;
+    with_flags([&](auto L, auto T, auto O) {
+      constexpr bool l = decltype(L)::value, t = decltype(T)::value, o = decltype(O)::value;
+      if constexpr (!FP64)
+        if (pools) {
+          k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW>;
+          return;
+        }
+      k.func = (const void *)k_batch<FP64, TRACE, l, t, o>;
+    }, lp.lds_exit, lp.staged, obs);
+  }, a.kernel == 2);
   return k;
 }
 
@@ -1550,7 +1555,7 @@ hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
 }
 
 int32_t batch_tile(bool fp64, int32_t kernel) {
-  return (!fp64 && kernel == 1) ? kPoolPerBlock : kBlock;
+  return (!fp64 && kernel >= 1) ? pool_per_wave(kernel) * kWavesPerBlock : kBlock;
 }
 
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,

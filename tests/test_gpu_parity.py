@@ -302,19 +302,20 @@ def test_fp32_pool_schedule_equals_lane_schedule(B, case):
     else:
         g, M, mode, dt = workloads.from_edges(3, [0, 2], [1, 1], [0.6, 0.4], sigma=1.0), 8, 2, 1e-3
     G = B.mg_graph_create(g)
-    for n in (1, 63, 65, 511, 513, 5000):
+    for n in (1, 63, 65, 511, 513, 1025, 5000):
         res = []
-        for sched in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS):
+        for sched in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS, B.MG_SCHED_POOLS256):
             p = B.mg_particles_init(G, n, mode, vertex=0, init_seed=n, precision=B.MG_FP32,
                                     max_splits=M, trace=True, schedule=sched)
             for k in (3, 254, 1, 342):
                 B.mg_simulate(p, k, dt, 77)
             res.append((B.mg_particles_read(p, trace=True), B.mg_exit_counts(p)))
-        (ra, ca), (rb, cb) = res
-        for f in ("edge", "x", "alive", "seqhash", "hits"):
-            assert np.array_equal(ra[f], rb[f]), (case, n, f)
-        for x, y in zip(ca, cb):
-            assert np.array_equal(x, y), (case, n)
+        (ra, ca) = res[0]
+        for rb, cb in res[1:]:
+            for f in ("edge", "x", "alive", "seqhash", "hits"):
+                assert np.array_equal(ra[f], rb[f]), (case, n, f)
+            for x, y in zip(ca, cb):
+                assert np.array_equal(x, y), (case, n)
 
 
 def test_vascular_network_fp64_parity_and_fp32(B, orc):
@@ -385,7 +386,8 @@ def test_batch_graph_replays_equal_individual_runs(B):
         for i, (g, n) in enumerate(zip(graphs, counts)):
             G = B.mg_graph_create(g)
             kw = dict(init_seed=i + 1, precision=prec, graph_tag=10 + i, trace=True,
-                      max_splits=4, steps_per_launch=37)
+                      max_splits=4, steps_per_launch=37,
+                      schedule=B.MG_SCHED_POOLS256 if prec == B.MG_FP32 else B.MG_SCHED_AUTO)
             sets_b.append(B.mg_particles_init(G, n, 2, **kw))
             sets_a.append(B.mg_particles_init(G, n, 2, **kw))
         b = B.mg_batch_create(sets_b)
@@ -422,9 +424,9 @@ def test_autotune_choice_and_auto_schedule_bitwise(B):
         assert np.array_equal(before[f], after[f]), f
     assert B.mg_particles_step(auto) == 0
     assert t["schedule"] in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS)
-    assert t["n_probes"] == 5 and all(ms > 0 for ms in t["probe_ms"][:5])
+    assert t["n_probes"] == 7 and all(ms > 0 for ms in t["probe_ms"][:7])
     if t["schedule"] == B.MG_SCHED_POOLS:
-        assert t["idle_trigger"] in (4, 8, 16, 32)
+        assert t["idle_trigger"] in (4, 8, 16, 32) and t["pool_size"] in (128, 256)
     for dt in (1e-2, 1e-3):              # 1e-3 is tuned on its first call
         B.mg_simulate(auto, 150, dt, 9)
         B.mg_simulate(lanes, 150, dt, 9)
