@@ -20,6 +20,8 @@ CF = "tests/test_oracle_closed_forms.py::"
 RNG = "tests/test_oracle_rng.py::"
 RS = "tests/test_oracle_root_slots.py::"
 INV = "tests/test_oracle_invariants.py::"
+SEQ = "tests/test_oracle_split_sequences.py::"
+SRCS = "tests/test_oracle_sources.py::"
 
 MUTANTS = {
     "drift_sign": (
@@ -86,6 +88,13 @@ MUTANTS = {
     "vertex_normal_not_folded": (
         [("if (x == 0.0) w = fabs(w);", "if (0) w = fabs(w);")],
         CF + "test_first_vertex_substep_closed_form"),
+    "remaining_time_kept": (
+        [("h = fma(-alpha, h, h);", "h = h;")],
+        SEQ + "test_split_sequences_match_exact_law"),
+    "source_slot_from_source_word": (
+        [("const int32_t s = pick_slot(g, thr, v, o[1]);",
+          "const int32_t s = pick_slot(g, thr, v, o[0]);")],
+        SRCS + "test_sources_law"),
     "far_end_not_checked": (
         [("if (xt > 0.0 && xt < L) {", "if (xt > 0.0) {")],
         CF + "test_radial_reflected_heat_kernel_converges"),
