@@ -144,7 +144,7 @@ namespace {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct SetLayout {
-  size_t ef, pos, hash, hits, exitc, absorbed, totals, err, total;
+  size_t ef, pos, hash, hits, exitc, absorbed, totals, err, work, total;
 };
 
 SetLayout set_layout(int32_t V, int32_t nnz, int64_t n, mg_precision prec, bool trace) {
@@ -163,6 +163,7 @@ SetLayout set_layout(int32_t V, int32_t nnz, int64_t n, mg_precision prec, bool 
   L.absorbed = take((size_t)std::max(V, 1) * 8);
   L.totals = take(4 * 8);
   L.err = take(4);
+  L.work = take(4);
   L.total = off;
   return L;
 }
@@ -474,6 +475,7 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
   s.absorbed = (uint64_t *)(base + L.absorbed);
   s.totals = (uint64_t *)(base + L.totals);
   s.err = (uint32_t *)(base + L.err);
+  s.work = (uint32_t *)(base + L.work);
   s.n = (uint32_t)n;
   s.n0 = 0;
   s.tag = p->tag;
@@ -1081,6 +1083,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   sd.absorbed = (uint64_t *)(base + L.absorbed);
   sd.totals = (uint64_t *)(base + L.totals);
   sd.err = (uint32_t *)(base + L.err);
+  sd.work = (uint32_t *)(base + L.work);
   sd.n = (uint32_t)n;
   sd.n0 = (uint32_t)p->step;
   sd.tag = p->tag;

@@ -88,6 +88,7 @@ struct SetDev {
   uint64_t *absorbed;  // [V]
   uint64_t *totals;    // [4]
   uint32_t *err;       // [1]
+  uint32_t *work;      // [1] next particle id a persistent pool launch hands out
   uint64_t *obs;       // [E * obs_nb] streamed histogram, or null (off)
   int32_t obs_nb;      // its bins per edge
   uint32_t obs_every;  // a snapshot each time the step counter reaches a

@@ -876,9 +876,11 @@ struct PoolLds32 : PoolTrace<TRACE, PW> {
   float hh[PW];     // remaining time of a parked step (when k > 0)
   float hl[PW];
   int32_t last[PW]; // last slot drawn in the parked step
+  uint32_t pid[PW];   // particle held by each home slot
   uint8_t k[PW];    // crossings so far in the parked step
   uint8_t ready[PW];
   uint8_t split[PW];
+  uint8_t freeq[PW];  // home slots without a particle
 };
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
@@ -936,10 +938,16 @@ __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS> &q, con
   t.sub += taken;
 }
 
-template <bool TRACE, bool LDS, bool OBS, int PW>
+// Where a wave's particles come from.  PERSIST: a single set advanced by a
+// grid that stays resident; every wave claims the next 64 particle ids from
+// the set's counter whenever 64 of its home slots are free, so pools stay
+// full until the set runs out and a launch ends with one short tail instead
+// of one per block.  Otherwise (batched launches): the ids [first, last).
+template <bool TRACE, bool LDS, bool OBS, int PW, bool PERSIST>
 __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
-                           const StepArgs &A, uint32_t base, PoolLds32<TRACE, PW> &P,
-                           uint32_t *s_exit, Tally &t, const ObsSink &sink) {
+                           const StepArgs &A, uint32_t first, uint32_t last,
+                           PoolLds32<TRACE, PW> &P, uint32_t *s_exit, Tally &t,
+                           const ObsSink &sink) {
   const uint32_t lane = threadIdx.x & 63u;
   const float dt = (float)A.dt;
   const float sqdt = (float)sqrt(A.dt);
@@ -949,71 +957,74 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   bool has = false;
   uint32_t slot = 0, n = 0;
   uint32_t snap = 0;  // next snapshot count of the lane's particle
-  // Ready and split queues: FIFO rings over the pool's slot ids, with
+  // Ready, split and free queues: FIFO rings over the pool's slot ids, with
   // wave-uniform head and tail counters.  FIFO keeps the particles of a pool
   // advancing together, so a launch ends without a long tail of stragglers.
   constexpr uint32_t K = (uint32_t)PW;
   uint32_t r_head = 0, r_tail = 0, s_head = 0, s_tail = 0;
-
-  // Initial placement: slot `lane` rides in the lane, slots 64k + lane wait.
-#pragma unroll
-  for (uint32_t half = 0; half < (uint32_t)PW / 64u; ++half) {
-    const uint32_t s = lane + 64u * half;
-    const uint32_t pid = base + s;
-    bool ok = false;
-    uint32_t ef = 0;
-    float y = 0.0f, yl = 0.0f;
-    if (pid < S.n) {
-      ef = S.ef[pid];
-      const float2 yy = S.y32[pid];
-      y = yy.x;
-      yl = yy.y;
-      const int32_t e = (int32_t)(ef & kEdgeMask);
-      if (!(ef & kDeadBit)) {
-        if (e >= n_edges) {
-          atomicOr(S.err, kErrEdge);
-        } else if (!(y >= 0.0f && y <= G.e32[e].L)) {
-          atomicOr(S.err, kErrPos);
-        } else {
-          ok = true;
-        }
-      }
-    }
-    if (half == 0) {
-      if (ok) {
-        P.ef[s] = ef;
-        P.y[s] = y;
-        P.yl[s] = yl;
-        if constexpr (TRACE) {
-          P.hits[s] = S.hits[pid];
-          P.hash[s] = S.seqhash[pid];
-        }
-        wave_lds_fence();
-        pool_load(q, P, s);
-        has = true;
-        slot = s;
-        n = S.n0;
-        if (OBS) snap = next_snapshot(n, S);
-      }
-    } else {
-      const uint64_t m = __ballot(ok);
-      if (ok) {
-        P.ef[s] = ef;
-        P.y[s] = y;
-        P.yl[s] = yl;
-        P.n[s] = S.n0;
-        if constexpr (TRACE) {
-          P.hits[s] = S.hits[pid];
-          P.hash[s] = S.seqhash[pid];
-        }
-        P.ready[(r_tail + lane_rank(m)) % K] = (uint8_t)s;
-      }
-      r_tail += (uint32_t)__popcll(m);
-    }
-  }
+  uint32_t f_head = 0, f_tail = K;
+  for (uint32_t i = lane; i < K; i += 64u) P.freeq[i] = (uint8_t)i;
+  uint32_t next = first;
+  const uint32_t lim = PERSIST ? S.n : last;
+  bool exhausted = false;
   wave_lds_fence();
 
   for (;;) {
+    // claim 64 more particles while 64 home slots are free
+    while (!exhausted && f_tail - f_head >= 64u) {
+      uint32_t b;
+      if (PERSIST) {
+        uint32_t v = 0u;
+        if (lane == 0u) v = atomicAdd(S.work, 64u);
+        b = __builtin_amdgcn_readfirstlane(v);
+      } else {
+        b = next;
+        next += 64u;
+      }
+      if (b >= lim) {
+        exhausted = true;
+        break;
+      }
+      if (b + 64u >= lim) exhausted = true;
+      const uint32_t id = b + lane;
+      bool ok = false;
+      uint32_t ef = 0;
+      float2 yy = make_float2(0.0f, 0.0f);
+      if (id < lim) {
+        ef = S.ef[id];
+        yy = S.y32[id];
+        const int32_t e = (int32_t)(ef & kEdgeMask);
+        if (!(ef & kDeadBit)) {
+          if (e >= n_edges) {
+            atomicOr(S.err, kErrEdge);
+          } else if (!(yy.x >= 0.0f && yy.x <= G.e32[e].L)) {
+            atomicOr(S.err, kErrPos);
+          } else {
+            ok = true;
+          }
+        }
+      }
+      const uint32_t hs = P.freeq[(f_head + lane) % K];
+      f_head += 64u;
+      const uint64_t m_ok = __ballot(ok);
+      if (ok) {
+        P.ef[hs] = ef;
+        P.y[hs] = yy.x;
+        P.yl[hs] = yy.y;
+        P.n[hs] = S.n0;
+        P.pid[hs] = id;
+        if constexpr (TRACE) {
+          P.hits[hs] = S.hits[id];
+          P.hash[hs] = S.seqhash[id];
+        }
+        P.ready[(r_tail + lane_rank(m_ok)) % K] = (uint8_t)hs;
+      } else {
+        P.freeq[(f_tail + lane_rank(~m_ok)) % K] = (uint8_t)hs;
+      }
+      r_tail += (uint32_t)__popcll(m_ok);
+      f_tail += 64u - (uint32_t)__popcll(m_ok);
+      wave_lds_fence();
+    }
     // lanes without a particle take ready ones
     {
       const uint64_t m_empty = __ballot(!has);
@@ -1031,15 +1042,19 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
     }
     bool do_split = false;
     if (__ballot(has) == 0ull) {
-      if (s_tail == s_head) break;
+      if (s_tail == s_head) {
+        if (exhausted) break;
+        continue;  // every particle claimed so far was dead: claim more
+      }
       do_split = true;
     } else {
       // one Philox group of first sub-steps for every lane with a particle
-      bool parked = false;
+      bool parked = false, done_now = false;
       float wp = 0.0f;
       if (has) {
         const uint32_t m = n >> 2;
-        const U4 o = philox(base + slot, m, 0u, S.tag, A.key0, A.key1);
+        const uint32_t pid = P.pid[slot];
+        const U4 o = philox(pid, m, 0u, S.tag, A.key0, A.key1);
         float W[4];
         box_muller32(o.x, o.y, W[0], W[1]);
         box_muller32(o.z, o.w, W[2], W[3]);
@@ -1071,10 +1086,14 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
           n = (m << 2) + je;
         }
         if (!parked && n == n_end) {
-          pool_finish(q, S, A, base + slot, t);
+          pool_finish(q, S, A, pid, t);
           has = false;
+          done_now = true;
         }
       }
+      const uint64_t m_done = __ballot(done_now);
+      if (done_now) P.freeq[(f_tail + lane_rank(m_done)) % K] = (uint8_t)slot;
+      f_tail += (uint32_t)__popcll(m_done);
       const uint64_t m_park = __ballot(parked);
       if (parked) {
         pool_store(q, P, slot, n);
@@ -1098,7 +1117,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       const uint32_t s_base = s_head;
       s_head += B;
       wave_lds_fence();
-      bool back = false, again = false;
+      bool back = false, again = false, freed = false;
       uint32_t s2 = 0;
       if (lane < B) {
         s2 = P.split[(s_base + lane) % K];
@@ -1106,13 +1125,14 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
                                   sqdt, true, 0ull, 0u, 0u};
         pool_load(q2, P, s2);
         const uint32_t step = P.n[s2];
+        const uint32_t pid2 = P.pid[s2];
         Hit32 h{dt, 0.0f, P.w[s2], (int32_t)P.k[s2], -1};
         if (h.k > 0) {
           h.hh = P.hh[s2];
           h.hl = P.hl[s2];
           h.last = P.last[s2];
         }
-        if (!q2.cross(step, h, base + s2, S, A, t)) {
+        if (!q2.cross(step, h, pid2, S, A, t)) {
           // reached a vertex again: back on the split queue for a later pass
           pool_store(q2, P, s2, step);
           P.w[s2] = h.w;
@@ -1128,13 +1148,17 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
           }
           const uint32_t n2 = step + 1u;
           if (!q2.alive || n2 == n_end) {
-            pool_finish(q2, S, A, base + s2, t);
+            pool_finish(q2, S, A, pid2, t);
+            freed = true;
           } else {
             pool_store(q2, P, s2, n2);
             back = true;
           }
         }
       }
+      const uint64_t m_freed = __ballot(freed);
+      if (freed) P.freeq[(f_tail + lane_rank(m_freed)) % K] = (uint8_t)s2;
+      f_tail += (uint32_t)__popcll(m_freed);
       const uint64_t m_again = __ballot(again);
       if (again) P.split[(s_tail + lane_rank(m_again)) % K] = (uint8_t)s2;
       s_tail += (uint32_t)__popcll(m_again);
@@ -1152,7 +1176,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
 
 // Shared memory of a pool block: [exit counters][staged tables][pools]
 // [snapshot bins].
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, bool PERSIST>
 __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t block_first,
                                            uint32_t *s_tot, char *smem) {
@@ -1172,8 +1196,9 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
   __syncthreads();
   Tally t{0, 0, 0, 0};
   const uint32_t wave = threadIdx.x >> 6;
-  run_pool32<TRACE, LDS, OBS, PW>(view, G.E, S, A, block_first + wave * PW,
-                              pools[wave], s_exit, t, o);
+  const uint32_t first = block_first + wave * PW;
+  run_pool32<TRACE, LDS, OBS, PW, PERSIST>(view, G.E, S, A, first, min(first + PW, S.n),
+                                           pools[wave], s_exit, t, o);
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
   if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
 }
@@ -1187,8 +1212,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_
 void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  pool_block<TRACE, LDS, STAGED, OBS, PW>(G, S, A, blockIdx.x * (PW * kWavesPerBlock), s_tot,
-                                          (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS, PW, true>(G, S, A, 0u, s_tot, (char *)smem4);
 }
 
 template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW>
@@ -1203,7 +1227,7 @@ void k_pool32_batch(const GraphDev *graphs,
   SetDev S = sets[it.set];
   S.n0 += A.n0_offset;
   const GraphDev G = graphs[it.set];
-  pool_block<TRACE, LDS, STAGED, OBS, PW>(G, S, A, it.first, s_tot, (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS, PW, false>(G, S, A, it.first, s_tot, (char *)smem4);
 }
 
 // Autotuning probes: the FP32 step kernels under names of their own, so a
@@ -1213,8 +1237,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_
 void k_pool32_probe(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  pool_block<false, LDS, STAGED, false, PW>(G, S, A, blockIdx.x * (PW * kWavesPerBlock), s_tot,
-                                            (char *)smem4);
+  pool_block<false, LDS, STAGED, false, PW, true>(G, S, A, 0u, s_tot, (char *)smem4);
 }
 
 template <bool LDS, bool STAGED>
@@ -1223,6 +1246,31 @@ __global__ __launch_bounds__(kBlock) void k_step32_probe(GraphDev G, SetDev S, S
   __shared__ uint32_t s_tot[4];
   step_block<false, false, LDS, STAGED, false>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
                                                s_tot, (char *)smem4);
+}
+
+// Clears the particle counter of a persistent pool launch (a kernel rather
+// than a memset, so that launch chains can be captured in HIP graphs).
+__global__ void k_clear_word(uint32_t *w) {
+  if (threadIdx.x == 0) *w = 0u;
+}
+
+// Blocks of a persistent launch: as many as stay resident at once (CUs x
+// blocks per CU for this kernel and LDS size), fewer if the set is small.
+uint32_t resident_blocks(const void *func, size_t shm, uint32_t need) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kBlock, shm) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  const uint32_t r = (uint32_t)cus * (uint32_t)per_cu;
+  return need < r ? need : r;
 }
 
 // ---------------------------------------------------------------- init --
@@ -1468,18 +1516,25 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
       const LdsPlan lp = plan_lds(g.nnz, stage, sizeof(PoolLds32<TRACE, PW>) * kWavesPerBlock,
                                   &s, g.E);
       a.obs_lds = lp.obs_lds;
-      const uint32_t blocks = (s.n + PW * kWavesPerBlock - 1) / (PW * kWavesPerBlock);
+      const uint32_t need = (s.n + PW * kWavesPerBlock - 1) / (PW * kWavesPerBlock);
+      hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, st, s.work);
       if (!TRACE && !obs && a.probe) {
         with_flags([&](auto L, auto T) {
+          const void *f =
+              (const void *)k_pool32_probe<decltype(L)::value, decltype(T)::value, PW>;
           hipLaunchKernelGGL((k_pool32_probe<decltype(L)::value, decltype(T)::value, PW>),
-                             dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+                             dim3(resident_blocks(f, lp.shm, need)), dim3(kBlock), lp.shm, st,
+                             g, s, a);
         }, lp.lds_exit, lp.staged);
         return;
       }
       with_flags([&](auto L, auto T, auto O) {
+        const void *f = (const void *)k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
+                                               decltype(O)::value, PW>;
         hipLaunchKernelGGL((k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
                                      decltype(O)::value, PW>),
-                           dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+                           dim3(resident_blocks(f, lp.shm, need)), dim3(kBlock), lp.shm, st,
+                           g, s, a);
       }, lp.lds_exit, lp.staged, obs);
     }, a.kernel == 2);
     return hipGetLastError();
