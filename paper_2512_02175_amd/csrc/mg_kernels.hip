@@ -316,10 +316,11 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
     // wave per SIMD).
     int32_t pj = -1;
     typename P::real wp = 0;
+    q.prep_window(W, jb);
 #pragma unroll
     for (uint32_t j = 0; j < NW; ++j) {
       if (j < jb || j >= je || pj >= 0) continue;
-      if (!q.fast(W[j])) {
+      if (!q.fast_first(W[j])) {
         pj = (int32_t)j;
         wp = W[j];
       } else {
@@ -389,6 +390,9 @@ struct Particle64 {
 
   // FP64 positions are always measured from the initial vertex.
   __device__ __forceinline__ void reanchor() {}
+  template <int N>
+  __device__ __forceinline__ void prep_window(double (&)[N], uint32_t, bool = true) const {}
+  __device__ __forceinline__ bool fast_first(double w) { return fast(w); }
   __device__ __forceinline__ double pos64(double) const { return x; }
 
   __device__ __forceinline__ bool fast(double w) {
@@ -539,6 +543,20 @@ struct Particle32 {
   uint64_t hash;
   uint32_t nhit;
   uint32_t death_step;
+  // First sub-step constants of the current edge and frame: c dt, as dt and
+  // g0 with the frame's sign, so that a first sub-step is
+  // y + fma(gs, w, fma(cd, y, ad)) with no per-step sign select.
+  float cd = 0.0f, ad = 0.0f, gs = 0.0f;
+
+  // Sets as, g0 and the first sub-step constants for the current edge R and
+  // side (after an edge load or a change of reference end).
+  __device__ __forceinline__ void frame() {
+    as = side ? -R.aL : R.a;
+    g0 = R.sigma * sqdt;
+    cd = R.c * dt;
+    ad = as * dt;
+    gs = side ? -g0 : g0;
+  }
 
   __device__ static void box_muller(uint32_t a, uint32_t b, float &c, float &s) {
     box_muller32(a, b, c, s);
@@ -562,18 +580,54 @@ struct Particle32 {
   // Re-anchor to the nearer end: L - y is exact for y in [L/2, L)
   // (Sterbenz), so the move loses nothing; the compensation flips sign.
   __device__ __forceinline__ void reanchor() {
-    const bool flip = y > 0.5f * R.L;
+    reanchor_if(true);
+  }
+  __device__ __forceinline__ void reanchor_if(bool cond) {
+    const bool flip = cond & (y > 0.5f * R.L);
     y = flip ? R.L - y : y;
     yl = flip ? -yl : yl;
     side ^= flip ? 1u : 0u;
-    as = side ? -R.aL : R.a;
+    as = flip ? (side ? -R.aL : R.a) : as;
+    ad = flip ? as * dt : ad;
+    gs = flip ? -gs : gs;
+  }
+
+  // The normal a first sub-step from y = 0 uses: a particle on a vertex
+  // moves into its edge, so the noise term is g0 |w| (gs carries the frame's
+  // sign, hence |w| with that sign).
+  __device__ __forceinline__ float at_vertex(float w) const {
+    return copysignf(fabsf(w), gs);
+  }
+  // A step's first sub-step over dt with normal w; w must already be
+  // at_vertex(w) when y = 0.  Returns the proposal and its compensation.
+  __device__ __forceinline__ float propose(float w, float &err) const {
+    return add_comp(fmaf(gs, w, fmaf(cd, y, ad)) + yl, err);
+  }
+
+  // Window preparation of the step loop: the first active step of a window
+  // is the only one that can start on a vertex.
+  template <int N>
+  __device__ __forceinline__ void prep_window(float (&W)[N], uint32_t jb, bool on = true) const {
+    if (on && y == 0.0f) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) W[i] = (jb == (uint32_t)i) ? at_vertex(W[i]) : W[i];
+    }
+  }
+  // First sub-step of a window's first active step after prep_window.
+  __device__ __forceinline__ bool fast_first(float w) {
+    float err;
+    const float yt = propose(w, err);
+    if (yt > 0.0f && yt < R.L) {
+      y = yt;
+      yl = err;
+      return true;
+    }
+    return false;
   }
 
   __device__ __forceinline__ bool fast(float w) {
-    const float we = (y == 0.0f) ? fabsf(w) : (side ? -w : w);
-    const float mu = fmaf(R.c, y, as);
     float err;
-    const float yt = add_comp(fmaf(g0, we, mu * dt) + yl, err);
+    const float yt = propose((y == 0.0f) ? at_vertex(w) : w, err);
     if (yt > 0.0f && yt < R.L) {
       y = yt;
       yl = err;
@@ -583,12 +637,13 @@ struct Particle32 {
   }
 
   // First sub-step as straight-line code: applied only where `active`;
-  // returns whether the proposal stays inside the edge.
+  // returns whether the proposal stays inside the edge.  No y = 0 check:
+  // y is positive after every step that stays inside an edge, so only a
+  // group's first active step can start on a vertex, and the caller passes
+  // at_vertex(w) for it.
   __device__ __forceinline__ bool fast_pred(float w, bool active) {
-    const float we = (y == 0.0f) ? fabsf(w) : (side ? -w : w);
-    const float mu = fmaf(R.c, y, as);
     float err;
-    const float yt = add_comp(fmaf(g0, we, mu * dt) + yl, err);
+    const float yt = propose(w, err);
     const bool in = (yt > 0.0f) & (yt < R.L);
     const bool upd = active & in;
     y = upd ? yt : y;
@@ -607,11 +662,13 @@ struct Particle32 {
                         const StepArgs &A, Tally &t) {
     float hh = h.hh, hl = h.hl;
     // the pending proposal, recomputed as it was made
+    // (the first sub-step's exactly as propose() made it: g0 we = gs w)
     const float we = (y == 0.0f) ? fabsf(h.w) : (side ? -h.w : h.w);
     const float mu = fmaf(R.c, y, as);
     const float g = h.k == 0 ? g0 : R.sigma * __builtin_amdgcn_sqrtf(hh);
+    const float mdt = h.k == 0 ? fmaf(cd, y, ad) : mu * hh;
     float err;
-    const float yt = add_comp(fmaf(g, we, mu * hh) + yl, err);
+    const float yt = add_comp(fmaf(g, we, mdt) + yl, err);
     const bool near = yt <= 0.0f;
     const bool at_term = near == (side != 0u);
     const int32_t v = at_term ? R.vterm : R.vinit;
@@ -630,8 +687,8 @@ struct Particle32 {
       const double dd = fmax(near ? yd : (double)R.L - yd, 0.0);
       u = (float)first_root64(qa, qb, dd);
     } else {
-      const float mh = mu * hh, gw = g * we;
-      u = first_root32(near ? mh : -mh, near ? gw : -gw, d);
+      const float gw = g * we;
+      u = first_root32(near ? mdt : -mdt, near ? gw : -gw, d);
     }
     // remaining time (1 - u^2)(hh + hl), compensated (TwoProduct by fma,
     // TwoSum, renormalised)
@@ -666,8 +723,7 @@ struct Particle32 {
     side = sp.eo & 1u;
     y = 0.0f;
     yl = 0.0f;
-    as = side ? -R.aL : R.a;
-    g0 = R.sigma * sqdt;
+    frame();
     h.last = sp.s;
     if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)sp.s);
     bool done = hh == 0.0f;
@@ -718,6 +774,7 @@ __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const St
   Particle32<TRACE, LDS> q{G, s_exit, e, side, yy.x, yy.y, R,
                            side ? -R.aL : R.a, R.sigma * sqdt, (float)A.dt, sqdt, true,
                            TRACE ? S.seqhash[pid] : 0ull, TRACE ? S.hits[pid] : 0u, 0u};
+  q.frame();
   if (!(q.y >= 0.0f && q.y <= R.L)) {
     atomicOr(S.err, kErrPos);
     return;
@@ -902,8 +959,7 @@ __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolL
   q.y = P.y[s];
   q.yl = P.yl[s];
   q.R = load_edge32(q.G.e32, q.e);
-  q.as = q.side ? -q.R.aL : q.R.a;
-  q.g0 = q.R.sigma * q.sqdt;
+  q.frame();
   q.alive = true;
   if constexpr (TRACE) {
     q.nhit = P.hits[s];
@@ -955,7 +1011,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   Particle32<TRACE, LDS> q{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
                            true, 0ull, 0u, 0u};
   bool has = false;
-  uint32_t slot = 0, n = 0;
+  uint32_t slot = 0, n = 0, pid = 0;  // the lane's home slot, next step, particle
   uint32_t snap = 0;  // next snapshot count of the lane's particle
   // Ready, split and free queues: FIFO rings over the pool's slot ids, with
   // wave-uniform head and tail counters.  FIFO keeps the particles of a pool
@@ -1028,17 +1084,19 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
     // lanes without a particle take ready ones
     {
       const uint64_t m_empty = __ballot(!has);
+      const uint32_t ready_cnt = r_tail - r_head;
       if (!has) {
         const uint32_t r = lane_rank(m_empty);
-        if (r < r_tail - r_head) {
+        if (r < ready_cnt) {
           slot = P.ready[(r_head + r) % K];
           n = P.n[slot];
+          pid = P.pid[slot];
           pool_load(q, P, slot);
           has = true;
           if (OBS) snap = next_snapshot(n, S);
         }
       }
-      r_head += min((uint32_t)__popcll(m_empty), r_tail - r_head);
+      r_head += min((uint32_t)__popcll(m_empty), ready_cnt);
     }
     bool do_split = false;
     if (__ballot(has) == 0ull) {
@@ -1048,49 +1106,40 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       }
       do_split = true;
     } else {
-      // one Philox group of first sub-steps for every lane with a particle
-      bool parked = false, done_now = false;
+      // One Philox group of first sub-steps.  Every lane runs the same
+      // straight-line code; a lane without a particle has no active step.
+      const uint32_t m = n >> 2;
+      const U4 o = philox(pid, m, 0u, S.tag, A.key0, A.key1);
+      float W[4];
+      box_muller32(o.x, o.y, W[0], W[1]);
+      box_muller32(o.z, o.w, W[2], W[3]);
+      const uint32_t jb = n & 3u;
+      const uint32_t je = has ? min(4u, n_end - (m << 2)) : 0u;
+      q.prep_window(W, jb, has);
+      int32_t pj = -1;
       float wp = 0.0f;
-      if (has) {
-        const uint32_t m = n >> 2;
-        const uint32_t pid = P.pid[slot];
-        const U4 o = philox(pid, m, 0u, S.tag, A.key0, A.key1);
-        float W[4];
-        box_muller32(o.x, o.y, W[0], W[1]);
-        box_muller32(o.z, o.w, W[2], W[3]);
-        const uint32_t jb = n & 3u;
-        const uint32_t je = min(4u, n_end - (m << 2));
-        int32_t pj = -1;
 #pragma unroll
-        for (uint32_t j = 0; j < 4; ++j) {
-          const bool act = (j >= jb) & (j < je) & (pj < 0);
-          const bool in = q.fast_pred(W[j], act);
-          const bool hit = act & !in;
-          pj = hit ? (int32_t)j : pj;
-          wp = hit ? W[j] : wp;
-          if (OBS && (act & in)) {
-            if (j == 3u) q.reanchor();
-            const uint32_t done = (m << 2) + j + 1u;
-            if (done == snap) {
-              observe(q, S, sink);
-              snap = next_snapshot(done, S);
-            }
+      for (uint32_t j = 0; j < 4; ++j) {
+        const bool act = (j >= jb) & (j < je) & (pj < 0);
+        const bool in = q.fast_pred(W[j], act);
+        const bool hit = act & !in;
+        pj = hit ? (int32_t)j : pj;
+        wp = hit ? W[j] : wp;
+        if (OBS && (act & in)) {
+          if (j == 3u) q.reanchor();
+          const uint32_t done = (m << 2) + j + 1u;
+          if (done == snap) {
+            observe(q, S, sink);
+            snap = next_snapshot(done, S);
           }
         }
-        if (pj >= 0) {
-          parked = true;
-          n = (m << 2) + (uint32_t)pj;
-        } else {
-          // the group's last step completed
-          if (!OBS && je == 4u) q.reanchor();
-          n = (m << 2) + je;
-        }
-        if (!parked && n == n_end) {
-          pool_finish(q, S, A, pid, t);
-          has = false;
-          done_now = true;
-        }
       }
+      const bool parked = pj >= 0;
+      // a completed group's last step re-anchors (with snapshots: in the loop)
+      if (!OBS) q.reanchor_if(!parked & (je == 4u));
+      n = parked ? (m << 2) + (uint32_t)pj : (has ? (m << 2) + je : n);
+      const bool done_now = has & !parked & (n == n_end);
+      if (done_now) pool_finish(q, S, A, pid, t);
       const uint64_t m_done = __ballot(done_now);
       if (done_now) P.freeq[(f_tail + lane_rank(m_done)) % K] = (uint8_t)slot;
       f_tail += (uint32_t)__popcll(m_done);
@@ -1100,9 +1149,9 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         P.w[slot] = wp;
         P.k[slot] = 0;  // fresh: hh = dt, hl = 0, no slot drawn yet
         P.split[(s_tail + lane_rank(m_park)) % K] = (uint8_t)slot;
-        has = false;
       }
       s_tail += (uint32_t)__popcll(m_park);
+      has = has & !parked & !done_now;
       wave_lds_fence();
       const uint32_t empty = (uint32_t)__popcll(__ballot(!has));
       const uint32_t ready_cnt = r_tail - r_head, split_cnt = s_tail - s_head;
