@@ -101,8 +101,9 @@ def run_pass(B, G, g, run, prec, dt, torch, kernel_times, schedules=None):
     if prec == B.MG_FP32:
         t = B.mg_autotune(p, dt, run["seed"])
         if schedules is not None:
-            schedules.append(f"k_pool32 ({t['pool_size']} per wave, idle {t['idle_trigger']})"
-                             if t["schedule"] == B.MG_SCHED_POOLS else "k_step<fp32>")
+            schedules.append(f"k_pool32 ({t['pool_size']} per wave, {t['window']}-step windows, "
+                             f"idle {t['idle_trigger']})"
+                             if t["schedule"] != B.MG_SCHED_LANES else "k_step<fp32>")
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -153,7 +154,7 @@ def run_vascular(args, B, torch):
                                 max_splits=run["max_splits"])
         if prec == B.MG_FP32:
             t = B.mg_autotune(p, run["dt"], run["seed"])
-            scheds.append("k_pool32" if t["schedule"] == B.MG_SCHED_POOLS else "k_step<fp32>")
+            scheds.append("k_pool32" if t["schedule"] != B.MG_SCHED_LANES else "k_step<fp32>")
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -442,7 +443,7 @@ def run_nohit(args, B, torch):
         del p
     k = float(np.mean(ktimes))
     achieved = ALG_FP32_STEP * float(res[3]) / k
-    kern = "k_pool32" if t["schedule"] == B.MG_SCHED_POOLS else "k_step<fp32>"
+    kern = "k_pool32" if t["schedule"] != B.MG_SCHED_LANES else "k_step<fp32>"
     return {"metric": METRIC, "value": float(res[1]) / float(np.mean(walls)),
             "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": float(np.mean(walls)) * 1e3,

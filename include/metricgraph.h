@@ -111,13 +111,17 @@ void mg_graph_destroy(mg_graph *g);
  *   schedule      FP32 kernel schedule: MG_SCHED_AUTO (0), MG_SCHED_LANES
  *                 (1: one particle per lane for a whole launch) or
  *                 MG_SCHED_POOLS (2: each wave cycles 128 particles through
- *                 its lanes and resolves vertex hits in full-width passes)
- *                 or MG_SCHED_POOLS256 (3: the same with 256 particles).
+ *                 its lanes and resolves vertex hits in full-width passes),
+ *                 MG_SCHED_POOLS256 (3: the same with 256 particles) or
+ *                 MG_SCHED_POOLS_W8 (4: pools of 128 whose lanes take
+ *                 windows of 8 first sub-steps, two Philox groups, per
+ *                 pass instead of 4).
  *                 Results are identical; only the speed differs.  FP64 sets
  *                 always use the lane schedule.
  */
 typedef enum {
-  MG_SCHED_AUTO = 0, MG_SCHED_LANES = 1, MG_SCHED_POOLS = 2, MG_SCHED_POOLS256 = 3
+  MG_SCHED_AUTO = 0, MG_SCHED_LANES = 1, MG_SCHED_POOLS = 2, MG_SCHED_POOLS256 = 3,
+  MG_SCHED_POOLS_W8 = 4
 } mg_schedule;
 
 typedef struct {
@@ -281,7 +285,8 @@ void mg_batch_destroy(mg_batch *b);
  * Autotuning of an FP32 set's kernel schedule.  The candidates (one
  * particle per lane; wave pools of 128 particles (2 per lane) that start a
  * partial split pass at 4, 8, 16 or 32 idle lanes; pools of 256 (4 per
- * lane) at 8 or 16) all give identical results, so tuning changes only
+ * lane) at 8 or 16; pools of 128 with 8-step windows at 8, 16 or 32) all
+ * give identical results, so tuning changes only
  * speed.  Each candidate advances a scratch copy of the set's first
  * min(n, 2^22) particles by probe_steps steps (<= 0: 1024) of size dt with
  * Philox key seed, timed with HIP events on the set's stream; the set
@@ -294,11 +299,13 @@ void mg_batch_destroy(mg_batch *b);
  * device memory and synchronises the stream.
  */
 typedef struct {
-  int32_t schedule;      /* MG_SCHED_LANES or MG_SCHED_POOLS */
+  int32_t schedule;      /* MG_SCHED_LANES, _POOLS, _POOLS256 or _POOLS_W8 */
   int32_t idle_trigger;  /* pools: idle lanes that start a partial split pass */
   int32_t pool_size;     /* pools: particles per wave (128 or 256), else 0 */
+  int32_t window;        /* first sub-steps per lane and pass (4 or 8) */
   int32_t n_probes;      /* entries used in probe_ms */
-  float probe_ms[8];     /* lanes, pools128@4, @8, @16, @32, pools256@8, @16 */
+  float probe_ms[12];    /* lanes, pools128@4, @8, @16, @32, pools256@8, @16,
+                            pools128 8-step windows@8, @16, @32 */
 } mg_tuning;
 
 mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_steps,

@@ -20,7 +20,7 @@ MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ESTATE = 0, 1, 2, 3, 4
 MG_FP64, MG_FP32 = 0, 1
 MG_VTX_STANDARD, MG_VTX_ABSORBING = 0, 1
 MG_INIT_EXPLICIT, MG_INIT_AT_VERTEX, MG_INIT_UNIFORM_LENGTH = 0, 1, 2
-MG_SCHED_AUTO, MG_SCHED_LANES, MG_SCHED_POOLS, MG_SCHED_POOLS256 = 0, 1, 2, 3
+MG_SCHED_AUTO, MG_SCHED_LANES, MG_SCHED_POOLS, MG_SCHED_POOLS256, MG_SCHED_POOLS_W8 = 0, 1, 2, 3, 4
 
 EXPORTED = (
     "mg_graph_create", "mg_graph_destroy", "mg_particles_arena_bytes",
@@ -59,7 +59,8 @@ class mg_options(C.Structure):
 
 class mg_tuning(C.Structure):
     _fields_ = [("schedule", C.c_int32), ("idle_trigger", C.c_int32),
-                ("pool_size", C.c_int32), ("n_probes", C.c_int32), ("probe_ms", C.c_float * 8)]
+                ("pool_size", C.c_int32), ("window", C.c_int32), ("n_probes", C.c_int32),
+                ("probe_ms", C.c_float * 12)]
 
 
 _lib = None
@@ -383,4 +384,5 @@ def mg_autotune(p: Particles, dt: float, seed: int = 0, probe_steps: int = 0) ->
     _check(lib().mg_autotune(p.handle, float(dt), C.c_uint64(seed), int(probe_steps),
                              C.byref(t)))
     return dict(schedule=int(t.schedule), idle_trigger=int(t.idle_trigger),
-                pool_size=int(t.pool_size), n_probes=int(t.n_probes), probe_ms=[float(t.probe_ms[i]) for i in range(t.n_probes)])
+                pool_size=int(t.pool_size), window=int(t.window), n_probes=int(t.n_probes),
+                probe_ms=[float(t.probe_ms[i]) for i in range(t.n_probes)])

@@ -405,7 +405,7 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
     return fail(MG_EINVAL, "max_splits must be in [0, 255] (0: default)");
   if (o.max_splits == 0) o.max_splits = 8;
   if (o.steps_per_launch < 0) return fail(MG_EINVAL, "steps_per_launch must be >= 0");
-  if (o.schedule < MG_SCHED_AUTO || o.schedule > MG_SCHED_POOLS256)
+  if (o.schedule < MG_SCHED_AUTO || o.schedule > MG_SCHED_POOLS_W8)
     return fail(MG_EINVAL, "unknown schedule");
   if (mode == MG_INIT_EXPLICIT) {
     if (!edge || !pos) return fail(MG_EINVAL, "explicit init needs edge and pos");
@@ -570,12 +570,27 @@ static mg_status check_steps(const mg_particles *p, int64_t n_steps, double dt) 
   return MG_OK;
 }
 
-// FP32 step schedule of a set: 1 = wave pools, 0 = one particle per lane.
-// Automatic selection takes the autotuned choice, or the pools until tuned.
+// Step kernel (StepArgs::kernel) of an FP32 schedule: 0 one particle per
+// lane, 1 / 2 wave pools of 128 / 256 particles, 3 pools of 128 with
+// 8-step windows; and back.
+static int32_t kernel_of(int32_t schedule) {
+  switch (schedule) {
+    case MG_SCHED_LANES: return 0;
+    case MG_SCHED_POOLS256: return 2;
+    case MG_SCHED_POOLS_W8: return 3;
+    default: return 1;
+  }
+}
+static int32_t schedule_of(int32_t kernel) {
+  static const int32_t s[4] = {MG_SCHED_LANES, MG_SCHED_POOLS, MG_SCHED_POOLS256,
+                               MG_SCHED_POOLS_W8};
+  return s[kernel];
+}
+
+// FP32 step kernel of a set.  Automatic selection takes the autotuned
+// choice, or the pools of 128 until tuned.
 static int32_t fp32_kernel(const mg_particles *p) {
-  if (p->schedule == MG_SCHED_LANES) return 0;
-  if (p->schedule == MG_SCHED_POOLS) return 1;
-  if (p->schedule == MG_SCHED_POOLS256) return 2;
+  if (p->schedule != MG_SCHED_AUTO) return kernel_of(p->schedule);
   return p->tuned ? p->tuned_kernel : 1;
 }
 
@@ -1062,7 +1077,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
         res = c.second;
         p->tuned = true;
         p->tuned_dt = dt;
-        p->tuned_kernel = res.schedule == MG_SCHED_LANES ? 0 : (res.pool_size == kPoolLarge ? 2 : 1);
+        p->tuned_kernel = kernel_of(res.schedule);
         p->tuned_idle = res.idle_trigger;
         if (out) *out = res;
         return MG_OK;
@@ -1095,10 +1110,12 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   a.dt = dt;
   a.probe = 1;
   // one particle per lane; pools of 128 (2 per lane) at four idle triggers;
-  // pools of 256 (4 per lane) at two
-  constexpr int kCand = 7;
-  const int32_t cand_kernel[kCand] = {0, 1, 1, 1, 1, 2, 2};
-  const int32_t cand_idle[kCand] = {8, 4, 8, 16, 32, 8, 16};
+  // pools of 256 (4 per lane) at two; pools of 128 with 8-step windows at
+  // three
+  constexpr int kCand = 10;
+  static_assert(kCand <= (int)(sizeof(mg_tuning::probe_ms) / sizeof(float)), "probe_ms");
+  const int32_t cand_kernel[kCand] = {0, 1, 1, 1, 1, 2, 2, 3, 3, 3};
+  const int32_t cand_idle[kCand] = {8, 4, 8, 16, 32, 8, 16, 8, 16, 32};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
@@ -1128,9 +1145,10 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   (void)hipFree(mem);
   if (he != hipSuccess) return hip_fail(he, "running the tuning probe");
   res.n_probes = kCand;
-  res.schedule = cand_kernel[best_i] ? MG_SCHED_POOLS : MG_SCHED_LANES;
+  res.schedule = schedule_of(cand_kernel[best_i]);
   res.idle_trigger = cand_kernel[best_i] ? cand_idle[best_i] : 0;
   res.pool_size = cand_kernel[best_i] ? pool_per_wave(cand_kernel[best_i]) : 0;
+  res.window = cand_kernel[best_i] == 3 ? 8 : 4;
   p->tuned = true;
   p->tuned_dt = dt;
   p->tuned_kernel = cand_kernel[best_i];

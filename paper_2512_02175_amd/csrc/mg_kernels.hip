@@ -999,7 +999,7 @@ __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS> &q, con
 // the set's counter whenever 64 of its home slots are free, so pools stay
 // full until the set runs out and a launch ends with one short tail instead
 // of one per block.  Otherwise (batched launches): the ids [first, last).
-template <bool TRACE, bool LDS, bool OBS, int PW, bool PERSIST>
+template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool PERSIST>
 __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
                            const StepArgs &A, uint32_t first, uint32_t last,
                            PoolLds32<TRACE, PW> &P, uint32_t *s_exit, Tally &t,
@@ -1106,28 +1106,34 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       }
       do_split = true;
     } else {
-      // One Philox group of first sub-steps.  Every lane runs the same
-      // straight-line code; a lane without a particle has no active step.
-      const uint32_t m = n >> 2;
-      const U4 o = philox(pid, m, 0u, S.tag, A.key0, A.key1);
-      float W[4];
-      box_muller32(o.x, o.y, W[0], W[1]);
-      box_muller32(o.z, o.w, W[2], W[3]);
-      const uint32_t jb = n & 3u;
-      const uint32_t je = has ? min(4u, n_end - (m << 2)) : 0u;
+      // A window of NG Philox groups of first sub-steps.  Every lane runs
+      // the same straight-line code; a lane without a particle has no
+      // active step.
+      constexpr uint32_t NW = 4u * NG;
+      const uint32_t base = n & ~(NW - 1u);
+      float W[NW];
+#pragma unroll
+      for (uint32_t g = 0; g < (uint32_t)NG; ++g) {
+        const U4 o = philox(pid, (base >> 2) + g, 0u, S.tag, A.key0, A.key1);
+        box_muller32(o.x, o.y, W[4 * g + 0], W[4 * g + 1]);
+        box_muller32(o.z, o.w, W[4 * g + 2], W[4 * g + 3]);
+      }
+      const uint32_t jb = n - base;
+      const uint32_t je = has ? min(NW, n_end - base) : 0u;
       q.prep_window(W, jb, has);
       int32_t pj = -1;
       float wp = 0.0f;
 #pragma unroll
-      for (uint32_t j = 0; j < 4; ++j) {
+      for (uint32_t j = 0; j < NW; ++j) {
         const bool act = (j >= jb) & (j < je) & (pj < 0);
         const bool in = q.fast_pred(W[j], act);
         const bool hit = act & !in;
         pj = hit ? (int32_t)j : pj;
         wp = hit ? W[j] : wp;
+        // a completed group's last step re-anchors
+        if ((j & 3u) == 3u) q.reanchor_if(act & in);
         if (OBS && (act & in)) {
-          if (j == 3u) q.reanchor();
-          const uint32_t done = (m << 2) + j + 1u;
+          const uint32_t done = base + j + 1u;
           if (done == snap) {
             observe(q, S, sink);
             snap = next_snapshot(done, S);
@@ -1135,9 +1141,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         }
       }
       const bool parked = pj >= 0;
-      // a completed group's last step re-anchors (with snapshots: in the loop)
-      if (!OBS) q.reanchor_if(!parked & (je == 4u));
-      n = parked ? (m << 2) + (uint32_t)pj : (has ? (m << 2) + je : n);
+      n = parked ? base + (uint32_t)pj : (has ? base + je : n);
       const bool done_now = has & !parked & (n == n_end);
       if (done_now) pool_finish(q, S, A, pid, t);
       const uint64_t m_done = __ballot(done_now);
@@ -1225,7 +1229,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
 
 // Shared memory of a pool block: [exit counters][staged tables][pools]
 // [snapshot bins].
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, bool PERSIST>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool PERSIST>
 __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t block_first,
                                            uint32_t *s_tot, char *smem) {
@@ -1246,7 +1250,7 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
   Tally t{0, 0, 0, 0};
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t first = block_first + wave * PW;
-  run_pool32<TRACE, LDS, OBS, PW, PERSIST>(view, G.E, S, A, first, min(first + PW, S.n),
+  run_pool32<TRACE, LDS, OBS, PW, NG, PERSIST>(view, G.E, S, A, first, min(first + PW, S.n),
                                            pools[wave], s_exit, t, o);
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
   if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
@@ -1256,15 +1260,15 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
 #define MG_POOL_WAVES_PER_EU 7
 #endif
 
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  pool_block<TRACE, LDS, STAGED, OBS, PW, true>(G, S, A, 0u, s_tot, (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, true>(G, S, A, 0u, s_tot, (char *)smem4);
 }
 
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32_batch(const GraphDev *graphs,
                                                          const SetDev *sets,
@@ -1276,17 +1280,17 @@ void k_pool32_batch(const GraphDev *graphs,
   SetDev S = sets[it.set];
   S.n0 += A.n0_offset;
   const GraphDev G = graphs[it.set];
-  pool_block<TRACE, LDS, STAGED, OBS, PW, false>(G, S, A, it.first, s_tot, (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, false>(G, S, A, it.first, s_tot, (char *)smem4);
 }
 
 // Autotuning probes: the FP32 step kernels under names of their own, so a
 // profile tells the probes apart from the launches they tune.
-template <bool LDS, bool STAGED, int PW>
+template <bool LDS, bool STAGED, int PW, int NG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32_probe(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  pool_block<false, LDS, STAGED, false, PW, true>(G, S, A, 0u, s_tot, (char *)smem4);
+  pool_block<false, LDS, STAGED, false, PW, NG, true>(G, S, A, 0u, s_tot, (char *)smem4);
 }
 
 template <bool LDS, bool STAGED>
@@ -1518,6 +1522,19 @@ void with_flags(F &&f, bool x, Rest... rest) {
     with_flags([&](auto... v) { f(std::false_type{}, v...); }, rest...);
 }
 
+// Shape of an FP32 wave-pool schedule (StepArgs::kernel 1, 2, 3): particles
+// per wave and Philox groups per phase-A window.
+template <typename F>
+void with_pool(int32_t kernel, F &&f) {
+  using I = std::integral_constant<int, 1>;
+  if (kernel == 2)
+    f(std::integral_constant<int, kPoolLarge>{}, I{});
+  else if (kernel == 3)
+    f(std::integral_constant<int, kPoolSmall>{}, std::integral_constant<int, 2>{});
+  else
+    f(std::integral_constant<int, kPoolSmall>{}, I{});
+}
+
 // LDS layout of a step block, shared by the host launchers and the
 // kernels' offsets: [exit counters][staged tables][pools][snapshot bins].
 // Within kLdsBlockMax bytes, exit counters come first (they take an atomic
@@ -1559,8 +1576,8 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
   StepArgs a = a0;
   const bool obs = s.obs != nullptr;
   if (!FP64 && a.kernel >= 1) {
-    with_flags([&](auto Big) {
-      constexpr int PW = decltype(Big)::value ? kPoolLarge : kPoolSmall;
+    with_pool(a.kernel, [&](auto PWc, auto NGc) {
+      constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
       const int32_t stage = g.stage_bytes32;
       const LdsPlan lp = plan_lds(g.nnz, stage, sizeof(PoolLds32<TRACE, PW>) * kWavesPerBlock,
                                   &s, g.E);
@@ -1570,8 +1587,8 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
       if (!TRACE && !obs && a.probe) {
         with_flags([&](auto L, auto T) {
           const void *f =
-              (const void *)k_pool32_probe<decltype(L)::value, decltype(T)::value, PW>;
-          hipLaunchKernelGGL((k_pool32_probe<decltype(L)::value, decltype(T)::value, PW>),
+              (const void *)k_pool32_probe<decltype(L)::value, decltype(T)::value, PW, NG>;
+          hipLaunchKernelGGL((k_pool32_probe<decltype(L)::value, decltype(T)::value, PW, NG>),
                              dim3(resident_blocks(f, lp.shm, need)), dim3(kBlock), lp.shm, st,
                              g, s, a);
         }, lp.lds_exit, lp.staged);
@@ -1579,13 +1596,13 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
       }
       with_flags([&](auto L, auto T, auto O) {
         const void *f = (const void *)k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
-                                               decltype(O)::value, PW>;
+                                               decltype(O)::value, PW, NG>;
         hipLaunchKernelGGL((k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
-                                     decltype(O)::value, PW>),
+                                     decltype(O)::value, PW, NG>),
                            dim3(resident_blocks(f, lp.shm, need)), dim3(kBlock), lp.shm, st,
                            g, s, a);
       }, lp.lds_exit, lp.staged, obs);
-    }, a.kernel == 2);
+    });
     return hipGetLastError();
   }
   const int32_t stage = FP64 ? g.stage_bytes64 : g.stage_bytes32;
@@ -1615,8 +1632,8 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
   k.grid = dim3(n_items);
   k.block = dim3(kBlock);
   const bool pools = !FP64 && a.kernel >= 1;
-  with_flags([&](auto Big) {
-    constexpr int PW = decltype(Big)::value ? kPoolLarge : kPoolSmall;
+  with_pool(a.kernel, [&](auto PWc, auto NGc) {
+    constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
     const LdsPlan lp = plan_lds(max_nnz, max_stage,
                                 pools ? sizeof(PoolLds32<TRACE, PW>) * kWavesPerBlock : 0,
                                 nullptr, 0);
@@ -1625,12 +1642,12 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
       constexpr bool l = decltype(L)::value, t = decltype(T)::value, o = decltype(O)::value;
       if constexpr (!FP64)
         if (pools) {
-          k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW>;
+          k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG>;
           return;
         }
       k.func = (const void *)k_batch<FP64, TRACE, l, t, o>;
     }, lp.lds_exit, lp.staged, obs);
-  }, a.kernel == 2);
+  });
   return k;
 }
 

@@ -75,7 +75,8 @@ def test_streamed_histogram_schedules_and_fp32(B, orc):
     for name, prec, sched in (("fp64", B.MG_FP64, B.MG_SCHED_LANES),
                               ("lanes", B.MG_FP32, B.MG_SCHED_LANES),
                               ("pools", B.MG_FP32, B.MG_SCHED_POOLS),
-                              ("pools256", B.MG_FP32, B.MG_SCHED_POOLS256)):
+                              ("pools256", B.MG_FP32, B.MG_SCHED_POOLS256),
+                              ("pools_w8", B.MG_FP32, B.MG_SCHED_POOLS_W8)):
         p = B.mg_particles_init(G, n, 2, init_seed=2, precision=prec, schedule=sched)
         B.mg_observe_histogram(p, bins, 5)
         for k in (3, 254, 1, 342):
@@ -84,6 +85,7 @@ def test_streamed_histogram_schedules_and_fp32(B, orc):
     assert res["lanes"][1] == res["pools"][1] == res["fp64"][1] == 120
     assert np.array_equal(res["lanes"][0], res["pools"][0])
     assert np.array_equal(res["lanes"][0], res["pools256"][0])
+    assert np.array_equal(res["lanes"][0], res["pools_w8"][0])
     assert _tv(res["lanes"][0], res["fp64"][0]) <= 2e-3
 
 

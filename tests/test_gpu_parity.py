@@ -304,7 +304,8 @@ def test_fp32_pool_schedule_equals_lane_schedule(B, case):
     G = B.mg_graph_create(g)
     for n in (1, 63, 65, 511, 513, 1025, 5000):
         res = []
-        for sched in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS, B.MG_SCHED_POOLS256):
+        for sched in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS, B.MG_SCHED_POOLS256,
+                      B.MG_SCHED_POOLS_W8):
             p = B.mg_particles_init(G, n, mode, vertex=0, init_seed=n, precision=B.MG_FP32,
                                     max_splits=M, trace=True, schedule=sched)
             for k in (3, 254, 1, 342):
@@ -423,10 +424,12 @@ def test_autotune_choice_and_auto_schedule_bitwise(B):
     for f in before:
         assert np.array_equal(before[f], after[f]), f
     assert B.mg_particles_step(auto) == 0
-    assert t["schedule"] in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS)
-    assert t["n_probes"] == 7 and all(ms > 0 for ms in t["probe_ms"][:7])
-    if t["schedule"] == B.MG_SCHED_POOLS:
+    assert t["schedule"] in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS, B.MG_SCHED_POOLS256,
+                             B.MG_SCHED_POOLS_W8)
+    assert t["n_probes"] == 10 and all(ms > 0 for ms in t["probe_ms"][:10])
+    if t["schedule"] != B.MG_SCHED_LANES:
         assert t["idle_trigger"] in (4, 8, 16, 32) and t["pool_size"] in (128, 256)
+        assert t["window"] == (8 if t["schedule"] == B.MG_SCHED_POOLS_W8 else 4)
     for dt in (1e-2, 1e-3):              # 1e-3 is tuned on its first call
         B.mg_simulate(auto, 150, dt, 9)
         B.mg_simulate(lanes, 150, dt, 9)
