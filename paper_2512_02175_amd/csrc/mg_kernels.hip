@@ -1163,9 +1163,8 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       do_split = split_cnt >= 64u || (split_cnt > 0u && idle >= (uint32_t)A.idle);
     }
     if (do_split) {
-      // The lanes' own particles wait in their home slots during the pass.
-      if (has) pool_store(q, P, slot, n);
-      // Up to 64 parked particles, one per lane, one crossing each.
+      // Up to 64 parked particles, one per lane, one crossing each.  The
+      // lanes' own particles stay in registers meanwhile.
       const uint32_t B = min(s_tail - s_head, 64u);
       const uint32_t s_base = s_head;
       s_head += B;
@@ -1219,10 +1218,6 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       if (back) P.ready[(r_tail + lane_rank(m_back)) % K] = (uint8_t)s2;
       r_tail += (uint32_t)__popcll(m_back);
       wave_lds_fence();
-      if (has) {
-        n = P.n[slot];
-        pool_load(q, P, slot);
-      }
     }
   }
 }
