@@ -1123,13 +1123,15 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       q.prep_window(W, jb, has);
       int32_t pj = -1;
       float wp = 0.0f;
+      bool go = true;  // no vertex reached yet in this window
 #pragma unroll
       for (uint32_t j = 0; j < NW; ++j) {
-        const bool act = (j >= jb) & (j < je) & (pj < 0);
+        const bool act = (j >= jb) & (j < je) & go;
         const bool in = q.fast_pred(W[j], act);
         const bool hit = act & !in;
         pj = hit ? (int32_t)j : pj;
         wp = hit ? W[j] : wp;
+        go = go & !hit;
         // a completed group's last step re-anchors
         if ((j & 3u) == 3u) q.reanchor_if(act & in);
         if (OBS && (act & in)) {
