@@ -1106,11 +1106,12 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       }
       do_split = true;
     } else {
-      // A window of NG Philox groups of first sub-steps.  Every lane runs
-      // the same straight-line code; a lane without a particle has no
-      // active step.
+      // A window of NG Philox groups of first sub-steps, starting at the
+      // group that holds the lane's next step (so a particle resumed after
+      // a split skips at most three steps of it).  Every lane runs the same
+      // straight-line code; a lane without a particle has no active step.
       constexpr uint32_t NW = 4u * NG;
-      const uint32_t base = n & ~(NW - 1u);
+      const uint32_t base = n & ~3u;
       float W[NW];
 #pragma unroll
       for (uint32_t g = 0; g < (uint32_t)NG; ++g) {
@@ -1118,7 +1119,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         box_muller32(o.x, o.y, W[4 * g + 0], W[4 * g + 1]);
         box_muller32(o.z, o.w, W[4 * g + 2], W[4 * g + 3]);
       }
-      const uint32_t jb = n - base;
+      const uint32_t jb = n & 3u;  // = n - base
       const uint32_t je = has ? min(NW, n_end - base) : 0u;
       q.prep_window(W, jb, has);
       int32_t pj = -1;
