@@ -139,21 +139,28 @@ __device__ __forceinline__ double first_root64(double A, double B, double Cc) {
   return u > 1.0 ? 1.0 : u;
 }
 
-// The same in FP32 with hardware reciprocals (about one ulp).
+// The same in FP32 with one hardware reciprocal (about one ulp).  In the
+// general case the sign of B tells which root is the smallest positive one,
+// so only that division is made: with C > 0 and real roots, B < 0 gives
+// q > 0 and the root C/q, which is the smaller of two positive roots (A > 0;
+// q^2 >= AC) or the positive one (A < 0); B >= 0 gives q <= 0, so C/q <= 0
+// and q/A is positive exactly when A < 0.  A negative discriminant (only
+// after rounding, next to a double root) is clamped to 0 and gives the
+// double root q/A.  No positive root gives the whole sub-step, u = 1.  The
+// result equals that of taking both divisions and the smallest positive.
 __device__ __forceinline__ float first_root32(float A, float B, float Cc) {
-  float disc = fmaf(B, B, -4.0f * A * Cc);
-  disc = disc < 0.0f ? 0.0f : disc;
-  const float sq = __builtin_amdgcn_sqrtf(disc);
-  const float q = -0.5f * (B >= 0.0f ? B + sq : B - sq);
+  const float disc0 = fmaf(B, B, -4.0f * A * Cc);
+  const bool real2 = disc0 > 0.0f;
+  const float sq = __builtin_amdgcn_sqrtf(real2 ? disc0 : 0.0f);
+  const bool bneg = B < 0.0f;
+  const float q = -0.5f * (bneg ? B - sq : B + sq);
   const bool c0 = Cc == 0.0f, a0 = A == 0.0f;
-  const float n1 = c0 ? -B : (a0 ? -Cc : q);
-  const float d1 = a0 ? B : A;
-  const float r1 = n1 * __builtin_amdgcn_rcpf(d1);
-  const float r2 = Cc * __builtin_amdgcn_rcpf(q);
-  const float lo = fminf(r1, r2), hi = fmaxf(r1, r2);
-  float ug = lo > 0.0f ? lo : hi;
-  ug = ug > 0.0f ? ug : 1.0f;
-  float u = (c0 || a0) ? r1 : ug;
+  const bool cq = bneg & real2;
+  // C = 0: -B / A;  A = 0: -C / B;  else C / q or q / A
+  const float num = c0 ? -B : (a0 ? -Cc : (cq ? Cc : q));
+  const float den = c0 ? A : (a0 ? B : (cq ? q : A));
+  const float r = num * __builtin_amdgcn_rcpf(den);
+  float u = (c0 || a0) ? r : (r > 0.0f ? r : 1.0f);
   u = (c0 && a0) ? 0.0f : u;
   u = u >= 0.0f ? u : 0.0f;
   return u > 1.0f ? 1.0f : u;
