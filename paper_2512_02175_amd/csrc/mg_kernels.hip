@@ -918,6 +918,10 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
 // results equal the plain per-particle order bit for bit.  Waves never wait
 // for one another: the queues and their counters are private to a wave.
 constexpr int kWavesPerBlock = kBlock / 64;
+#ifndef MG_POOL_CLAIM_MIN
+#define MG_POOL_CLAIM_MIN 16
+#endif
+constexpr int kClaimMin = MG_POOL_CLAIM_MIN;  // free home slots that start a claim
 
 template <bool TRACE, int PW>
 struct PoolTrace {
@@ -1033,12 +1037,16 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   wave_lds_fence();
 
   for (;;) {
-    // claim 64 more particles while 64 home slots are free
-    while (!exhausted && f_tail - f_head >= 64u) {
+    // Claim more particles: a persistent wave takes as many ids as it has
+    // free home slots (up to 64) once kClaimMin are free, so a pool refills
+    // while its first particles finish rather than after half of them have;
+    // a batched tile takes 64 at a time.
+    while (!exhausted && f_tail - f_head >= (PERSIST ? (uint32_t)kClaimMin : 64u)) {
+      const uint32_t want = PERSIST ? min(64u, f_tail - f_head) : 64u;
       uint32_t b;
       if (PERSIST) {
         uint32_t v = 0u;
-        if (lane == 0u) v = atomicAdd(S.work, 64u);
+        if (lane == 0u) v = atomicAdd(S.work, want);
         b = __builtin_amdgcn_readfirstlane(v);
       } else {
         b = next;
@@ -1048,12 +1056,13 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         exhausted = true;
         break;
       }
-      if (b + 64u >= lim) exhausted = true;
+      if (b + want >= lim) exhausted = true;
       const uint32_t id = b + lane;
+      const bool mine = lane < want;
       bool ok = false;
       uint32_t ef = 0;
       float2 yy = make_float2(0.0f, 0.0f);
-      if (id < lim) {
+      if (mine && id < lim) {
         ef = S.ef[id];
         yy = S.y32[id];
         const int32_t e = (int32_t)(ef & kEdgeMask);
@@ -1067,9 +1076,10 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
           }
         }
       }
-      const uint32_t hs = P.freeq[(f_head + lane) % K];
-      f_head += 64u;
+      const uint32_t hs = mine ? P.freeq[(f_head + lane) % K] : 0u;
+      f_head += want;
       const uint64_t m_ok = __ballot(ok);
+      const uint64_t m_back = __ballot(mine & !ok);
       if (ok) {
         P.ef[hs] = ef;
         P.y[hs] = yy.x;
@@ -1081,11 +1091,11 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
           P.hash[hs] = S.seqhash[id];
         }
         P.ready[(r_tail + lane_rank(m_ok)) % K] = (uint8_t)hs;
-      } else {
-        P.freeq[(f_tail + lane_rank(~m_ok)) % K] = (uint8_t)hs;
+      } else if (mine) {
+        P.freeq[(f_tail + lane_rank(m_back)) % K] = (uint8_t)hs;
       }
       r_tail += (uint32_t)__popcll(m_ok);
-      f_tail += 64u - (uint32_t)__popcll(m_ok);
+      f_tail += (uint32_t)__popcll(m_back);
       wave_lds_fence();
     }
     // lanes without a particle take ready ones
