@@ -30,9 +30,14 @@ METRIC = "particle-substeps/s at 1 GPU, FP32 vs FP64, + % VALU peak at TV≤2e-3
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 
 # Algorithmic VALU operations of the method per unit of work: the minimal
-# gfx950 instruction sequence, counted once per operation whatever its rate.
-# The counts are per operation of the step, whatever the instruction's rate.
-ALG_FP32_STEP = 32.5     # per particle-step: 1/4 Philox + 1/2 Box-Muller pair + EM
+# gfx950 instruction sequence, counted once per instruction whatever its rate.
+# FP32 particle-step: 1/4 Philox4x32-10 (10 rounds x 2 multiplies + 2
+# three-input xors) = 10; 1/2 Box-Muller pair (2 converts, 2 fma, log, mul,
+# sqrt, cos, sin, 2 mul) = 5.5; the first sub-step from per-frame constants
+# (2 fma, 2 adds and 2 subtractions of the compensated sum, 2 compares,
+# 2 selects) = 10; 1/4 re-anchor (compare, subtraction, 3 selects, xor,
+# multiply, select) = 2.
+ALG_FP32_STEP = 27.5
 ALG_FP32_HIT = 80.0      # per vertex hit: Philox, one normal, root, time, slot, edge
 ALG_FP64_STEP = 62.5
 ALG_FP64_HIT = 130.0

@@ -294,7 +294,9 @@ void mg_batch_destroy(mg_batch *b);
  * result is also kept with the graph: later calls for any set on the same
  * graph at the same dt take it without probing.  Sets created with
  * schedule MG_SCHED_AUTO are tuned this way on their first mg_simulate at
- * each dt.  FP64 sets have nothing to tune (schedule lanes).  `out` (may be
+ * each dt; until then (and in a batch built from untuned sets) they use
+ * pools of 128 with 8-step windows.  Fixed pool schedules start a partial
+ * pass at 16 idle lanes.  FP64 sets have nothing to tune (schedule lanes).  `out` (may be
  * NULL) receives the choice and the probe times.  A probe allocates scratch
  * device memory and synchronises the stream.
  */
