@@ -922,6 +922,7 @@ constexpr int kWavesPerBlock = kBlock / 64;
 #define MG_POOL_CLAIM_MIN 16
 #endif
 constexpr int kClaimMin = MG_POOL_CLAIM_MIN;  // free home slots that start a claim
+static_assert((kClaimMin & (kClaimMin - 1)) == 0 && kClaimMin <= 64, "claim granularity");
 
 template <bool TRACE, int PW>
 struct PoolTrace {
@@ -1038,11 +1039,13 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
 
   for (;;) {
     // Claim more particles: a persistent wave takes as many ids as it has
-    // free home slots (up to 64) once kClaimMin are free, so a pool refills
+    // free home slots, in multiples of kClaimMin up to 64, so a pool refills
     // while its first particles finish rather than after half of them have;
-    // a batched tile takes 64 at a time.
+    // a batched tile takes 64 at a time.  Claims stay multiples of
+    // kClaimMin, so every claim starts at a multiple of it and the state
+    // lines a wave reads and writes belong to that wave alone.
     while (!exhausted && f_tail - f_head >= (PERSIST ? (uint32_t)kClaimMin : 64u)) {
-      const uint32_t want = PERSIST ? min(64u, f_tail - f_head) : 64u;
+      const uint32_t want = PERSIST ? min(64u, f_tail - f_head) & ~((uint32_t)kClaimMin - 1u) : 64u;
       uint32_t b;
       if (PERSIST) {
         uint32_t v = 0u;
