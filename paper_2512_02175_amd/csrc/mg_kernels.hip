@@ -904,8 +904,9 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
 // ------------------------------------------------ FP32 wave-pool kernel --
 // Each wave owns PW particles (128 or 256): 64 ride in the lanes, the others
 // wait in the wave's private LDS home slots.  A lane runs its particle's
-// first sub-steps for one main-stream Philox group (four steps) per
-// iteration; a particle whose sub-step reaches a vertex is parked: its state
+// first sub-steps for one window (one or two main-stream Philox groups,
+// four or eight steps) per iteration; a particle whose sub-step reaches a
+// vertex is parked: its state
 // goes to its home slot and its slot id onto the wave's split queue, and the
 // lane takes a ready particle instead.  When 64 particles are parked (or
 // lanes would idle), one split pass takes them with every lane busy and
@@ -923,6 +924,9 @@ constexpr int kWavesPerBlock = kBlock / 64;
 #endif
 constexpr int kClaimMin = MG_POOL_CLAIM_MIN;  // free home slots that start a claim
 static_assert((kClaimMin & (kClaimMin - 1)) == 0 && kClaimMin <= 64, "claim granularity");
+// A batched pool wave owns kBatchGens pools' worth of particles of its tile
+// and refills its pool from them as particles finish.
+constexpr int kBatchGens = 4;
 
 template <bool TRACE, int PW>
 struct PoolTrace {
@@ -1007,10 +1011,10 @@ __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS> &q, con
 }
 
 // Where a wave's particles come from.  PERSIST: a single set advanced by a
-// grid that stays resident; every wave claims the next 64 particle ids from
-// the set's counter whenever 64 of its home slots are free, so pools stay
-// full until the set runs out and a launch ends with one short tail instead
-// of one per block.  Otherwise (batched launches): the ids [first, last).
+// grid that stays resident; every wave claims the next particle ids from
+// the set's counter as its home slots free up, so pools stay nearly full
+// until the set runs out and a launch ends with one short tail instead of
+// one per block.  Otherwise (batched launches): the ids [first, last).
 template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool PERSIST>
 __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
                            const StepArgs &A, uint32_t first, uint32_t last,
@@ -1038,14 +1042,16 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   wave_lds_fence();
 
   for (;;) {
-    // Claim more particles: a persistent wave takes as many ids as it has
-    // free home slots, in multiples of kClaimMin up to 64, so a pool refills
-    // while its first particles finish rather than after half of them have;
-    // a batched tile takes 64 at a time.  Claims stay multiples of
-    // kClaimMin, so every claim starts at a multiple of it and the state
-    // lines a wave reads and writes belong to that wave alone.
-    while (!exhausted && f_tail - f_head >= (PERSIST ? (uint32_t)kClaimMin : 64u)) {
-      const uint32_t want = PERSIST ? min(64u, f_tail - f_head) & ~((uint32_t)kClaimMin - 1u) : 64u;
+    // Claim more particles: a wave takes as many ids as it has free home
+    // slots, in multiples of kClaimMin up to 64, so a pool refills while its
+    // first particles finish rather than after half of them have.  A
+    // persistent wave takes them from the set's counter, a batched wave
+    // from its own range.  Claims stay multiples of kClaimMin, so every
+    // claim starts at a multiple of it: a claim's 128-byte lines of
+    // positions belong to one wave (its state words share a line with one
+    // neighbouring claim).
+    while (!exhausted && f_tail - f_head >= (uint32_t)kClaimMin) {
+      const uint32_t want = min(64u, f_tail - f_head) & ~((uint32_t)kClaimMin - 1u);
       uint32_t b;
       if (PERSIST) {
         uint32_t v = 0u;
@@ -1053,7 +1059,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         b = __builtin_amdgcn_readfirstlane(v);
       } else {
         b = next;
-        next += 64u;
+        next += want;
       }
       if (b >= lim) {
         exhausted = true;
@@ -1267,8 +1273,9 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
   __syncthreads();
   Tally t{0, 0, 0, 0};
   const uint32_t wave = threadIdx.x >> 6;
-  const uint32_t first = block_first + wave * PW;
-  run_pool32<TRACE, LDS, OBS, PW, NG, PERSIST>(view, G.E, S, A, first, min(first + PW, S.n),
+  const uint32_t first = block_first + wave * PW * kBatchGens;
+  run_pool32<TRACE, LDS, OBS, PW, NG, PERSIST>(view, G.E, S, A, first,
+                                               min(first + PW * kBatchGens, S.n),
                                            pools[wave], s_exit, t, o);
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
   if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
@@ -1694,7 +1701,7 @@ hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
 }
 
 int32_t batch_tile(bool fp64, int32_t kernel) {
-  return (!fp64 && kernel >= 1) ? pool_per_wave(kernel) * kWavesPerBlock : kBlock;
+  return (!fp64 && kernel >= 1) ? pool_per_wave(kernel) * kWavesPerBlock * kBatchGens : kBlock;
 }
 
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
