@@ -146,7 +146,7 @@ hipError_t launch_init(const GraphDev &g, const SetDev &s, int mode,
                        const InitSources &src, bool fp64, hipStream_t st);
 hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
                        bool fp64, bool trace, hipStream_t st);
-// Particles per batch work item: four pools per wave for the FP32
+// Particles per batch work item: eight pools per wave for the FP32
 // wave-pool kernel (a wave refills its pool from them), a plain block
 // otherwise.
 int32_t batch_tile(bool fp64, int32_t kernel);

@@ -926,7 +926,7 @@ constexpr int kClaimMin = MG_POOL_CLAIM_MIN;  // free home slots that start a cl
 static_assert((kClaimMin & (kClaimMin - 1)) == 0 && kClaimMin <= 64, "claim granularity");
 // A batched pool wave owns kBatchGens pools' worth of particles of its tile
 // and refills its pool from them as particles finish.
-constexpr int kBatchGens = 4;
+constexpr int kBatchGens = 8;
 
 template <bool TRACE, int PW>
 struct PoolTrace {
