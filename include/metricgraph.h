@@ -56,7 +56,18 @@ typedef struct mg_batch mg_batch;          /* opaque */
  * Alg. 2's vertex tables).  All pointers are host memory.
  *   n_vertices, n_edges  V >= 1, E >= 1.
  *   edge_init/edge_term  [E] vertex ids; x = 0 at edge_init, x = L at edge_term.
- *   length               [E] finite, > 0.
+ *   length               [E] > 0: finite, or +infinity for a semi-infinite
+ *                        edge [0, infinity) (Def. 1 allows l_e = infinity;
+ *                        its terminal vertex is a vertex at infinity).  Give
+ *                        that vertex an id of its own holding only this
+ *                        edge's terminal slot (absorbing, or standard with
+ *                        b = 1); no particle reaches it, and it may not be a
+ *                        starting or source vertex.  Graphs with such edges
+ *                        reject MG_INIT_UNIFORM_LENGTH, mg_histogram,
+ *                        mg_observe_histogram and mg_density_l2 (uniform
+ *                        bins need finite edges): bin them with
+ *                        mg_histogram_csr, whose last bin on an edge takes
+ *                        every position beyond its last boundary.
  *   drift_a, drift_c     [E] drift mu_e(x) = a_e + c_e x (NULL: 0); finite.
  *   sigma                [E] finite, > 0 (the paper takes sigma continuous
  *                        at vertices; that is the caller's responsibility).

@@ -205,6 +205,8 @@ def init(g, n: int, mode: int, *, vertex: int = 0, seed: int = 0, tag: int = 0,
     m = pid.size
     st = State(pid, np.zeros(m, np.int32), np.zeros(m, np.float64), np.ones(m, np.uint8),
                np.full(m, fnv_offset(), np.uint64), np.zeros(m, np.uint32))
+    if mode == INIT_UNIFORM_LENGTH and not np.all(np.isfinite(g._keep["length"])):
+        raise ValueError("uniform-by-length init needs finite edges")
     if mode == INIT_EXPLICIT:
         st.edge[:] = np.asarray(edge, np.int32)[pid] if pids is not None else np.asarray(edge, np.int32)
         st.x[:] = np.asarray(pos, np.float64)[pid] if pids is not None else np.asarray(pos, np.float64)
@@ -296,6 +298,8 @@ def simulate_traced(g, st: State, row: int, n0: int, n_steps: int, dt: float,
 
 def histogram(g, st: State, bins: int) -> np.ndarray:
     g = as_graph(g)
+    if not np.all(np.isfinite(g._keep["length"])):
+        raise ValueError("uniform bins need finite edges (histogram_csr bins semi-infinite ones)")
     out = np.zeros(g.E * bins, np.uint64)
     lib().or_histogram(g.ref, st.pid.size, _ptr(st.edge), _ptr(st.x), _ptr(st.alive),
                        bins, _ptr(out))

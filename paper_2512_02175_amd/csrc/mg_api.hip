@@ -85,6 +85,10 @@ struct mg_graph {
   mutable std::vector<std::pair<double, mg_tuning>> tune_cache;
   std::vector<double> length;  // host copy for readback conversion
   std::vector<VtxBlk> vtx_host;
+  // semi-infinite edges (length +infinity): their terminal vertices are
+  // the vertices at infinity, which no particle reaches
+  bool infinite = false;
+  std::vector<uint8_t> at_infinity;  // [V]
   void *dev = nullptr;         // one allocation holding every table
   GraphDev gd{};
 };
@@ -216,8 +220,8 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
     if (d->edge_init[e] < 0 || d->edge_init[e] >= V || d->edge_term[e] < 0 ||
         d->edge_term[e] >= V)
       return fail(MG_EINVAL, "edge %d has a vertex out of range", e);
-    if (!is_finite(d->length[e]) || !(d->length[e] > 0.0))
-      return fail(MG_EINVAL, "edge %d: length must be finite and > 0", e);
+    if (std::isnan(d->length[e]) || !(d->length[e] > 0.0))
+      return fail(MG_EINVAL, "edge %d: length must be > 0 (finite, or +infinity)", e);
     if (!is_finite(d->sigma[e]) || !(d->sigma[e] > 0.0))
       return fail(MG_EINVAL, "edge %d: sigma must be finite and > 0", e);
     if (d->drift_a && !is_finite(d->drift_a[e])) return fail(MG_EINVAL, "edge %d: drift_a not finite", e);
@@ -252,6 +256,19 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   }
   for (size_t i = 0; i < seen.size(); ++i)
     if (!seen[i]) return fail(MG_EINVAL, "edge %zu end %zu is missing from the slot table", i / 2, i % 2);
+  // a semi-infinite edge ends at a vertex at infinity: one that holds only
+  // that edge's terminal slot
+  std::vector<uint8_t> at_inf(V, 0);
+  bool infinite = false;
+  for (int32_t e = 0; e < E; ++e) {
+    if (!std::isinf(d->length[e])) continue;
+    infinite = true;
+    const int32_t v = d->edge_term[e];
+    if (v == d->edge_init[e] || off[v + 1] - off[v] != 1)
+      return fail(MG_EINVAL,
+                  "edge %d is semi-infinite: its terminal vertex %d must hold only its own end", e, v);
+    at_inf[v] = 1;
+  }
 
   // pack
   std::vector<EdgeRec64> e64(E);
@@ -260,8 +277,10 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
     const double a = d->drift_a ? d->drift_a[e] : 0.0;
     const double c = d->drift_c ? d->drift_c[e] : 0.0;
     e64[e] = {d->length[e], a, c, d->sigma[e], d->edge_init[e], d->edge_term[e], 0, 0};
-    e32[e] = {(float)d->length[e], (float)a, (float)c, (float)d->sigma[e],
-              (float)std::fma(c, d->length[e], a), d->edge_init[e], d->edge_term[e], 0.0f};
+    // (a particle never measures from the far end of a semi-infinite edge)
+    const double aL = std::isinf(d->length[e]) ? 0.0 : std::fma(c, d->length[e], a);
+    e32[e] = {(float)d->length[e], (float)a, (float)c, (float)d->sigma[e], (float)aL,
+              d->edge_init[e], d->edge_term[e], 0.0f};
   }
   std::vector<uint64_t> thr(nnz);
   slot_thresholds(V, off, d->slot_jump_prob, thr);
@@ -303,8 +322,9 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
     vtx[v] = b;
   }
   // length-proportional init thresholds, built like the slot thresholds
+  // (unused on graphs with semi-infinite edges)
   std::vector<uint64_t> lthr(E);
-  {
+  if (!infinite) {
     double total = 0.0;
     for (int32_t e = 0; e < E; ++e) total += d->length[e];
     double cum = 0.0;
@@ -324,6 +344,8 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   g->nnz = nnz;
   g->length.assign(d->length, d->length + E);
   g->vtx_host = vtx;
+  g->infinite = infinite;
+  g->at_infinity = at_inf;
   const size_t ng = guide.size();
   const size_t o_vtx = 0;
   const size_t o_sl = align_up(o_vtx + sizeof(VtxBlk) * V, 16);
@@ -418,6 +440,7 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
     if (vertex < 0 || vertex >= g->V) return fail(MG_EINVAL, "vertex out of range");
     if (g->vtx_host[vertex].deg <= 0)
       return fail(MG_EINVAL, "vertex %d is absorbing or isolated", vertex);
+    if (g->at_infinity[vertex]) return fail(MG_EINVAL, "vertex %d is at infinity", vertex);
   } else if (mode == 3) {
     if (n_src < 1 || !src_v || !src_rate) return fail(MG_EINVAL, "need at least one source");
     double total = 0.0;
@@ -426,6 +449,7 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
       if (v < 0 || v >= g->V) return fail(MG_EINVAL, "source %d: vertex out of range", j);
       if (g->vtx_host[v].deg <= 0)
         return fail(MG_EINVAL, "source %d: vertex %d is absorbing or isolated", j, v);
+      if (g->at_infinity[v]) return fail(MG_EINVAL, "source %d: vertex %d is at infinity", j, v);
       if (!is_finite(src_rate[j]) || src_rate[j] < 0.0)
         return fail(MG_EINVAL, "source %d: rate must be finite and >= 0", j);
       total += src_rate[j];
@@ -433,6 +457,8 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
     if (!(total > 0.0)) return fail(MG_EINVAL, "the source rates sum to 0");
   } else if (mode != MG_INIT_UNIFORM_LENGTH) {
     return fail(MG_EINVAL, "unknown init mode");
+  } else if (g->infinite) {
+    return fail(MG_EINVAL, "uniform-by-length init needs finite edges");
   }
   const SetLayout L = set_layout(g->V, g->nnz, n, o.precision, o.trace != 0);
   mg_particles *p = new mg_particles();
@@ -644,6 +670,8 @@ mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge, uint64_t *o
   g_err.clear();
   if (!p || !out) return fail(MG_EINVAL, "NULL argument");
   if (bins_per_edge < 1) return fail(MG_EINVAL, "bins_per_edge must be >= 1");
+  if (p->g->infinite)
+    return fail(MG_EINVAL, "uniform bins need finite edges (mg_histogram_csr bins semi-infinite ones)");
   const int64_t need = (int64_t)p->g->E * bins_per_edge;
   if (need > 0x7FFFFFFF) return fail(MG_EINVAL, "E * bins_per_edge too large");
   if (out_len < need) return fail(MG_EINVAL, "out_len %lld < E * bins_per_edge = %lld",
@@ -747,6 +775,7 @@ mg_status mg_observe_histogram(mg_particles *p, int32_t bins_per_edge, int32_t e
   if (every < 0 || every > (1 << 30)) return fail(MG_EINVAL, "every must be in [0, 2^30]");
   if (every > 0) {
     if (bins_per_edge < 1) return fail(MG_EINVAL, "bins_per_edge must be >= 1");
+    if (p->g->infinite) return fail(MG_EINVAL, "uniform bins need finite edges");
     if ((int64_t)p->g->E * bins_per_edge > 0x7FFFFFFF)
       return fail(MG_EINVAL, "E * bins_per_edge too large");
   }
@@ -798,6 +827,7 @@ mg_status mg_density_l2(const mg_graph *g, int32_t bins_per_edge, const uint64_t
   g_err.clear();
   if (!g || !counts || !ref_density || !l2) return fail(MG_EINVAL, "NULL argument");
   if (bins_per_edge < 1) return fail(MG_EINVAL, "bins_per_edge must be >= 1");
+  if (g->infinite) return fail(MG_EINVAL, "uniform bins need finite edges");
   const int64_t nbins = (int64_t)g->E * bins_per_edge;
   if (nbins > 0x7FFFFFFF) return fail(MG_EINVAL, "E * bins_per_edge too large");
   if (!(mass >= 0.0) || !is_finite(mass)) return fail(MG_EINVAL, "mass must be finite, >= 0");

@@ -18,6 +18,8 @@ Graph description (same fields as the C-ABI ``mg_graph_desc``):
   at x = 0), 1 means its terminal vertex (enters at x = L).  The jump
   probabilities b_{v,e} of the standard gluing conditions sum to 1 per vertex.
 * ``vtx_kind[v]``: 0 standard vertex, 1 absorbing vertex.
+* A semi-infinite edge has ``length`` = inf; its terminal vertex is a vertex
+  at infinity of its own (one slot, never reached).
 """
 from __future__ import annotations
 
@@ -28,6 +30,7 @@ import numpy as np
 __all__ = [
     "GraphDesc", "from_edges", "star_graph", "segment", "random_tree",
     "config1", "config2", "config3", "config4", "config5", "paper_star5",
+    "csr_bins",
 ]
 
 
@@ -166,9 +169,12 @@ def config2(seed: int = 2) -> tuple[GraphDesc, dict]:
 
 def paper_star5(potential: str = "linear", length: float = 2.0,
                 sigma: float = 1.0) -> GraphDesc:
-    """The 5-edge star of the paper's experiments (Sec. 4), edges truncated to
-    a finite length with reflecting leaves: mu_i = -10 i (linear potential) or
-    mu_i = -10 i x (quadratic potential), uniform b = 1/5."""
+    """The 5-edge star of the paper's experiments (Sec. 4): mu_i = -10 i
+    (linear potential) or mu_i = -10 i x (quadratic potential), uniform
+    b = 1/5.  ``length`` = inf gives the paper's star metric graph (Def. 3:
+    one vertex, semi-infinite edges; here each edge's far end is a vertex at
+    infinity of its own); a finite length truncates the edges with
+    reflecting leaves."""
     i = np.arange(1, 6, dtype=np.float64)
     if potential == "linear":
         a, c = -10.0 * i, np.zeros(5)
@@ -178,6 +184,39 @@ def paper_star5(potential: str = "linear", length: float = 2.0,
         raise ValueError(potential)
     return star_graph(5, length, a, c, sigma,
                       meta={"name": f"paper_star5_{potential}"})
+
+
+def csr_bins(g: GraphDesc, width: float, n_finite: int):
+    """Per-edge bins for ``histogram_csr``: on each edge ``n_finite`` bins of
+    ``width`` from x = 0 (clipped to the edge's length), then, on an edge
+    longer than that, one more bin whose upper boundary is the edge's length
+    (or, on a semi-infinite edge, that takes every position beyond).
+    Returns (bin_offsets [E+1], bin_upper [nnz bins], true upper bounds
+    including inf)."""
+    off = [0]
+    up, true_up = [], []
+    for e in range(int(g.n_edges)):
+        L = float(g.length[e])
+        k = 0
+        for k in range(1, n_finite + 1):
+            u = k * width
+            if u >= L:
+                break
+            up.append(u)
+            true_up.append(u)
+        else:
+            k = n_finite + 1
+        if np.isinf(L):
+            # the tail bin: its stored boundary is any finite value above the
+            # previous one; positions beyond it land there as well
+            up.append((n_finite + 1) * width)
+            true_up.append(np.inf)
+        else:
+            up.append(L)
+            true_up.append(L)
+        off.append(len(up))
+    return (np.asarray(off, np.int32), np.asarray(up, np.float64),
+            np.asarray(true_up, np.float64))
 
 
 def _vascular_topology(rng, n_vertices, n_edges, n_leaves, side):

@@ -43,6 +43,31 @@ def _bin_integrals(a: float, c: float, D: float, edges: np.ndarray) -> np.ndarra
     raise ValueError("c > 0 (a confining-free potential) is not supported")
 
 
+def star_csr_masses(g, bin_offsets, true_upper) -> np.ndarray:
+    """Stationary mass of each bin of a ``csr_bins`` table on a star (finite
+    or semi-infinite edges; every edge starts at vertex 0), total mass 1.
+    ``true_upper`` holds the real upper bounds (inf for a semi-infinite
+    edge's tail bin)."""
+    E = int(g.n_edges)
+    if not np.all(np.asarray(g.edge_init) == 0):
+        raise ValueError("not a star centred at vertex 0")
+    sig = np.asarray(g.sigma, np.float64)
+    if not np.all(sig == sig[0]):
+        raise ValueError("sigma must be constant")
+    D = 0.5 * float(sig[0]) ** 2
+    b = np.zeros(E)
+    for s in range(int(g.vtx_offsets[0]), int(g.vtx_offsets[1])):
+        b[int(g.slot_edge[s])] += float(g.slot_jump_prob[s])
+    off = np.asarray(bin_offsets, np.int64)
+    up = np.asarray(true_upper, np.float64)
+    out = np.zeros(int(off[-1]))
+    for e in range(E):
+        edges = np.concatenate([[0.0], up[off[e]:off[e + 1]]])
+        out[off[e]:off[e + 1]] = b[e] / D * _bin_integrals(
+            float(g.drift_a[e]), float(g.drift_c[e]), D, edges)
+    return out / out.sum()
+
+
 def star_bin_means(g, bins: int) -> np.ndarray:
     """Bin averages [E, bins] of the stationary density of a star built like
     ``workloads.star_graph`` (every edge starts at vertex 0), normalised to
