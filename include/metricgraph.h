@@ -63,11 +63,7 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *                        edge's terminal slot (absorbing, or standard with
  *                        b = 1); no particle reaches it, and it may not be a
  *                        starting or source vertex.  Graphs with such edges
- *                        reject MG_INIT_UNIFORM_LENGTH, mg_histogram,
- *                        mg_observe_histogram and mg_density_l2 (uniform
- *                        bins need finite edges): bin them with
- *                        mg_histogram_csr, whose last bin on an edge takes
- *                        every position beyond its last boundary.
+ *                        reject MG_INIT_UNIFORM_LENGTH.
  *   drift_a, drift_c     [E] drift mu_e(x) = a_e + c_e x (NULL: 0); finite.
  *   sigma                [E] finite, > 0 (the paper takes sigma continuous
  *                        at vertices; that is the caller's responsibility).
@@ -80,6 +76,12 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *   vtx_kind             [V] mg_vertex_kind, or NULL for all standard.  An
  *                        absorbing vertex removes a particle that hits it
  *                        (Wentzell killing term a_v = 1, Sec. 2.2).
+ *   bin_span             [E] the length of edge e that the uniform histograms
+ *                        (mg_histogram, mg_observe_histogram, mg_density_l2)
+ *                        divide into their bins: bin width bin_span[e] / nb,
+ *                        positions beyond bin_span[e] counted in the last
+ *                        bin.  Finite, > 0.  NULL: the edge lengths (then
+ *                        every edge must be finite).
  * Every edge must appear exactly once at its initial vertex with orient 0
  * and once at its terminal vertex with orient 1 (a self-loop twice at its
  * vertex).  A standard vertex needs at least one slot with b > 0.
@@ -95,6 +97,7 @@ typedef struct {
   const uint8_t *slot_orient;
   const double *slot_jump_prob;
   const uint8_t *vtx_kind;
+  const double *bin_span;
 } mg_graph_desc;
 
 /* Validates and packs the graph into device tables (edge records, slot

@@ -44,7 +44,7 @@ class _Graph(C.Structure):
                 ("drift_c", C.c_void_p), ("sigma", C.c_void_p),
                 ("vtx_offsets", C.c_void_p), ("slot_edge", C.c_void_p),
                 ("slot_orient", C.c_void_p), ("slot_jump_prob", C.c_void_p),
-                ("vtx_kind", C.c_void_p)]
+                ("vtx_kind", C.c_void_p), ("bin_span", C.c_void_p)]
 
 
 def lib():
@@ -102,12 +102,17 @@ class OracleGraph:
             slot_jump_prob=np.ascontiguousarray(desc.slot_jump_prob, np.float64),
             vtx_kind=np.ascontiguousarray(desc.vtx_kind, np.uint8),
         )
+        span = getattr(desc, "bin_span", None)
+        self._keep["bin_span"] = np.ascontiguousarray(
+            self._keep["length"] if span is None else span, np.float64)
+        if not np.all(np.isfinite(self._keep["bin_span"])):
+            raise ValueError("a semi-infinite edge needs a finite bin_span")
         k = self._keep
         self.c = _Graph(int(desc.n_vertices), int(desc.n_edges),
                         *[k[n].ctypes.data for n in (
                             "edge_init", "edge_term", "length", "drift_a",
                             "drift_c", "sigma", "vtx_offsets", "slot_edge",
-                            "slot_orient", "slot_jump_prob", "vtx_kind")])
+                            "slot_orient", "slot_jump_prob", "vtx_kind", "bin_span")])
         self.V = int(desc.n_vertices)
         self.E = int(desc.n_edges)
         self.nnz = int(k["vtx_offsets"][-1])
@@ -298,8 +303,6 @@ def simulate_traced(g, st: State, row: int, n0: int, n_steps: int, dt: float,
 
 def histogram(g, st: State, bins: int) -> np.ndarray:
     g = as_graph(g)
-    if not np.all(np.isfinite(g._keep["length"])):
-        raise ValueError("uniform bins need finite edges (histogram_csr bins semi-infinite ones)")
     out = np.zeros(g.E * bins, np.uint64)
     lib().or_histogram(g.ref, st.pid.size, _ptr(st.edge), _ptr(st.x), _ptr(st.alive),
                        bins, _ptr(out))

@@ -142,6 +142,7 @@ typedef struct {
   const uint8_t *slot_orient;             /* [nnz] 0: enter at x=0, 1: at x=L */
   const double *slot_jump_prob;           /* [nnz] b_{v,e} */
   const uint8_t *vtx_kind;                /* [V] 0 standard, 1 absorbing */
+  const double *bin_span;                 /* [E] length the uniform bins cover */
 } or_graph;
 
 /*
@@ -547,7 +548,10 @@ int or_init_sources(const or_graph *g, int64_t count, const uint32_t *pid,
 /* ------------------------------------------------------------ histogram */
 /*
  * Uniform-bin histogram of alive particles (appendix kernel; reading A13):
- * bin = min(nb - 1, floor(x * (nb / L_e))), counted into out[e * nb + bin].
+ * bin = min(nb - 1, floor(x * (nb / S_e))), counted into out[e * nb + bin],
+ * with S_e the binned length (the edge length unless given otherwise; a
+ * semi-infinite edge needs one), so positions beyond S_e land in the last
+ * bin.
  */
 void or_histogram(const or_graph *g, int64_t count, const int32_t *edge,
                   const double *x, const uint8_t *alive, int32_t nb,
@@ -555,7 +559,7 @@ void or_histogram(const or_graph *g, int64_t count, const int32_t *edge,
   for (int64_t i = 0; i < count; ++i) {
     if (!alive[i]) continue;
     const int32_t e = edge[i];
-    const double inv = (double)nb / g->length[e];
+    const double inv = (double)nb / g->bin_span[e];
     double f = floor(x[i] * inv);
     int64_t b = f < 0.0 ? 0 : (int64_t)f;
     if (b > nb - 1) b = nb - 1;

@@ -46,7 +46,7 @@ class mg_graph_desc(C.Structure):
                 ("drift_c", C.c_void_p), ("sigma", C.c_void_p),
                 ("vtx_offsets", C.c_void_p), ("slot_edge", C.c_void_p),
                 ("slot_orient", C.c_void_p), ("slot_jump_prob", C.c_void_p),
-                ("vtx_kind", C.c_void_p)]
+                ("vtx_kind", C.c_void_p), ("bin_span", C.c_void_p)]
 
 
 class mg_options(C.Structure):
@@ -191,11 +191,15 @@ def mg_graph_create(desc) -> Graph:
         slot_jump_prob=np.ascontiguousarray(desc.slot_jump_prob, np.float64),
         vtx_kind=np.ascontiguousarray(desc.vtx_kind, np.uint8),
     )
+    span = getattr(desc, "bin_span", None)
+    if span is not None:
+        keep["bin_span"] = np.ascontiguousarray(span, np.float64)
     d = mg_graph_desc(int(desc.n_vertices), int(desc.n_edges),
                       *[keep[k].ctypes.data for k in (
                           "edge_init", "edge_term", "length", "drift_a", "drift_c",
                           "sigma", "vtx_offsets", "slot_edge", "slot_orient",
-                          "slot_jump_prob", "vtx_kind")])
+                          "slot_jump_prob", "vtx_kind")],
+                      keep["bin_span"].ctypes.data if span is not None else None)
     h = C.c_void_p()
     _check(lib().mg_graph_create(C.byref(d), C.byref(h)))
     return Graph(h, desc)

@@ -84,6 +84,7 @@ struct mg_graph {
   mutable std::mutex tune_mu;
   mutable std::vector<std::pair<double, mg_tuning>> tune_cache;
   std::vector<double> length;  // host copy for readback conversion
+  std::vector<double> span;    // length binned by the uniform histograms
   std::vector<VtxBlk> vtx_host;
   // semi-infinite edges (length +infinity): their terminal vertices are
   // the vertices at infinity, which no particle reaches
@@ -226,6 +227,10 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
       return fail(MG_EINVAL, "edge %d: sigma must be finite and > 0", e);
     if (d->drift_a && !is_finite(d->drift_a[e])) return fail(MG_EINVAL, "edge %d: drift_a not finite", e);
     if (d->drift_c && !is_finite(d->drift_c[e])) return fail(MG_EINVAL, "edge %d: drift_c not finite", e);
+    if (d->bin_span ? !(is_finite(d->bin_span[e]) && d->bin_span[e] > 0.0)
+                    : std::isinf(d->length[e]))
+      return fail(MG_EINVAL, "edge %d: bin_span must be finite and > 0 (and given for a "
+                  "semi-infinite edge)", e);
   }
   // every edge exactly once at each end with the right orientation
   std::vector<uint8_t> seen((size_t)E * 2, 0);
@@ -276,7 +281,8 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   for (int32_t e = 0; e < E; ++e) {
     const double a = d->drift_a ? d->drift_a[e] : 0.0;
     const double c = d->drift_c ? d->drift_c[e] : 0.0;
-    e64[e] = {d->length[e], a, c, d->sigma[e], d->edge_init[e], d->edge_term[e], 0, 0};
+    e64[e] = {d->length[e], a, c, d->sigma[e], d->edge_init[e], d->edge_term[e],
+              d->bin_span ? d->bin_span[e] : d->length[e]};
     // (a particle never measures from the far end of a semi-infinite edge)
     const double aL = std::isinf(d->length[e]) ? 0.0 : std::fma(c, d->length[e], a);
     e32[e] = {(float)d->length[e], (float)a, (float)c, (float)d->sigma[e], (float)aL,
@@ -343,6 +349,7 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   g->E = E;
   g->nnz = nnz;
   g->length.assign(d->length, d->length + E);
+  g->span = d->bin_span ? std::vector<double>(d->bin_span, d->bin_span + E) : g->length;
   g->vtx_host = vtx;
   g->infinite = infinite;
   g->at_infinity = at_inf;
@@ -670,8 +677,6 @@ mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge, uint64_t *o
   g_err.clear();
   if (!p || !out) return fail(MG_EINVAL, "NULL argument");
   if (bins_per_edge < 1) return fail(MG_EINVAL, "bins_per_edge must be >= 1");
-  if (p->g->infinite)
-    return fail(MG_EINVAL, "uniform bins need finite edges (mg_histogram_csr bins semi-infinite ones)");
   const int64_t need = (int64_t)p->g->E * bins_per_edge;
   if (need > 0x7FFFFFFF) return fail(MG_EINVAL, "E * bins_per_edge too large");
   if (out_len < need) return fail(MG_EINVAL, "out_len %lld < E * bins_per_edge = %lld",
@@ -775,7 +780,6 @@ mg_status mg_observe_histogram(mg_particles *p, int32_t bins_per_edge, int32_t e
   if (every < 0 || every > (1 << 30)) return fail(MG_EINVAL, "every must be in [0, 2^30]");
   if (every > 0) {
     if (bins_per_edge < 1) return fail(MG_EINVAL, "bins_per_edge must be >= 1");
-    if (p->g->infinite) return fail(MG_EINVAL, "uniform bins need finite edges");
     if ((int64_t)p->g->E * bins_per_edge > 0x7FFFFFFF)
       return fail(MG_EINVAL, "E * bins_per_edge too large");
   }
@@ -827,7 +831,6 @@ mg_status mg_density_l2(const mg_graph *g, int32_t bins_per_edge, const uint64_t
   g_err.clear();
   if (!g || !counts || !ref_density || !l2) return fail(MG_EINVAL, "NULL argument");
   if (bins_per_edge < 1) return fail(MG_EINVAL, "bins_per_edge must be >= 1");
-  if (g->infinite) return fail(MG_EINVAL, "uniform bins need finite edges");
   const int64_t nbins = (int64_t)g->E * bins_per_edge;
   if (nbins > 0x7FFFFFFF) return fail(MG_EINVAL, "E * bins_per_edge too large");
   if (!(mass >= 0.0) || !is_finite(mass)) return fail(MG_EINVAL, "mass must be finite, >= 0");
@@ -853,7 +856,7 @@ mg_status mg_density_l2(const mg_graph *g, int32_t bins_per_edge, const uint64_t
   // Neumaier-compensated sum of w (rho_hat - rho_ref)^2 over all bins
   double acc = 0.0, comp = 0.0;
   for (int32_t e = 0; e < g->E; ++e) {
-    const double w = g->length[e] / bins_per_edge;
+    const double w = g->span[e] / bins_per_edge;
     for (int32_t k = 0; k < bins_per_edge; ++k) {
       const size_t i = (size_t)e * bins_per_edge + k;
       if (!is_finite(ref[i])) return fail(MG_EINVAL, "reference density %zu not finite", i);

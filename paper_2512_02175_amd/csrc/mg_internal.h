@@ -15,11 +15,13 @@ constexpr uint32_t kSideBit = 0x40000000u;
 constexpr uint32_t kDeadBit = 0x80000000u;
 constexpr int32_t kMaxEdges = 0x3FFFFFFF;
 
-// Edge record for the FP64 path: 48 bytes, one per edge.
+// Edge record for the FP64 path: 48 bytes, one per edge.  span is the
+// length the uniform histograms bin (the edge length unless the caller gave
+// another; finite on a semi-infinite edge).
 struct alignas(16) EdgeRec64 {
   double L, a, c, sigma;  // length, drift a + c x, diffusion
   int32_t vinit, vterm;   // end vertices
-  int32_t pad0, pad1;
+  double span;
 };
 
 // Edge record for the FP32 path: 32 bytes.  aL = a + c L is the drift at

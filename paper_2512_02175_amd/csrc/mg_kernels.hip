@@ -231,11 +231,12 @@ __device__ __forceinline__ void count_exit(uint32_t *s_exit, uint64_t *g_exit,
     atomicAdd((unsigned long long *)&g_exit[slot], 1ull);
 }
 
-// Bin of position x on an edge of length L, nb bins per edge: x times the
-// FP64 inverse bin width nb / L, rounded down, clamped to [0, nb - 1] (the
-// appendix histogram kernel, with x = L in the last bin).
-__device__ __forceinline__ int32_t bin_of(double x, double L, int32_t nb) {
-  const double inv = (double)nb / L;
+// Bin of position x on an edge binned over [0, span], nb bins per edge: x
+// times the FP64 inverse bin width nb / span, rounded down, clamped to
+// [0, nb - 1] (the appendix histogram kernel, with x = span and anything
+// beyond in the last bin).
+__device__ __forceinline__ int32_t bin_of(double x, double span, int32_t nb) {
+  const double inv = (double)nb / span;
   const double f = floor(x * inv);
   return f < 0.0 ? 0 : (f > (double)(nb - 1) ? nb - 1 : (int32_t)f);
 }
@@ -261,8 +262,8 @@ struct ObsSink {
 
 template <typename P>
 __device__ __forceinline__ void observe(const P &q, const SetDev &S, const ObsSink &o) {
-  const double L = o.e64[q.e].L;
-  const int32_t idx = q.e * S.obs_nb + bin_of(q.pos64(L), L, S.obs_nb);
+  const EdgeRec64 &r = o.e64[q.e];
+  const int32_t idx = q.e * S.obs_nb + bin_of(q.pos64(r.L), r.span, S.obs_nb);
   if (o.lds)
     atomicAdd(&o.lds[idx], 1u);
   else
@@ -1428,16 +1429,16 @@ __global__ __launch_bounds__(kBlock) void k_hist(GraphDev G, SetDev S, int32_t n
     const uint32_t ef = S.ef[pid];
     if (ef & kDeadBit) continue;
     const int32_t e = (int32_t)(ef & kEdgeMask);
-    const double L = G.e64[e].L;
+    const EdgeRec64 &r = G.e64[e];
     double x;
     if (FP64) {
       x = S.x64[pid];
     } else {
       const float2 yy = S.y32[pid];
       const double y = (double)yy.x + (double)yy.y;
-      x = (ef & kSideBit) ? L - y : y;
+      x = (ef & kSideBit) ? r.L - y : y;
     }
-    const int32_t idx = e * nb + bin_of(x, L, nb);
+    const int32_t idx = e * nb + bin_of(x, r.span, nb);
     if (LDS)
       atomicAdd(&s_bin[idx], 1u);
     else
@@ -1469,16 +1470,16 @@ __global__ __launch_bounds__(kBlock) void k_hist_tiled(GraphDev G, SetDev S, int
     if (ef & kDeadBit) continue;
     const int32_t e = (int32_t)(ef & kEdgeMask);
     if (e < e0 || e >= e1) continue;
-    const double L = G.e64[e].L;
+    const EdgeRec64 &r = G.e64[e];
     double x;
     if (FP64) {
       x = S.x64[pid];
     } else {
       const float2 yy = S.y32[pid];
       const double y = (double)yy.x + (double)yy.y;
-      x = (ef & kSideBit) ? L - y : y;
+      x = (ef & kSideBit) ? r.L - y : y;
     }
-    atomicAdd(&s_bin[(e - e0) * nb + bin_of(x, L, nb)], 1u);
+    atomicAdd(&s_bin[(e - e0) * nb + bin_of(x, r.span, nb)], 1u);
   }
   __syncthreads();
   uint64_t *o = out + (int64_t)e0 * nb;

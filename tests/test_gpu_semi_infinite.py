@@ -92,32 +92,49 @@ def test_semi_infinite_star_fp32_against_fp64(B):
             assert np.array_equal(r[f], r32[f]), (name, f)
 
 
-def test_calls_that_need_finite_edges(B):
+def test_init_rules_and_uniform_bins_on_a_span(B, orc):
+    """Uniform-by-length init and a start on a vertex at infinity are
+    rejected; uniform bins (one-off and streamed) cover each edge's bin span
+    with everything beyond in the last bin, as the oracle counts them."""
     g = _graph("linear")
     G = B.mg_graph_create(g)
     with pytest.raises(B.MgError):
         B.mg_particles_init(G, 100, B.MG_INIT_UNIFORM_LENGTH)
     with pytest.raises(B.MgError):           # a vertex at infinity
         B.mg_particles_init(G, 100, B.MG_INIT_AT_VERTEX, vertex=1)
-    p = B.mg_particles_init(G, 100, B.MG_INIT_AT_VERTEX, vertex=0)
+    edge, pos = [0, 0, 1, 4, 2], [0.0, 1.99, 2.0, 1e6, 0.5]
+    st = orc.init(g, 5, orc.INIT_EXPLICIT, edge=edge, pos=pos)
+    for prec in (B.MG_FP64, B.MG_FP32):
+        q = B.mg_particles_init(G, 5, B.MG_INIT_EXPLICIT, edge=edge, pos=pos, precision=prec)
+        assert np.array_equal(B.mg_histogram(q, 8), orc.histogram(g, st, 8))
+    # streamed snapshots on the semi-infinite star against the oracle's
+    n, dt, bins = 20_000, 1e-3, 50
+    p = B.mg_particles_init(G, n, B.MG_INIT_AT_VERTEX, vertex=0, init_seed=2,
+                            precision=B.MG_FP64, trace=True)
+    B.mg_observe_histogram(p, bins, 25)
+    for k in (7, 293, 200):
+        B.mg_simulate(p, k, dt, 5)
+    h, snaps = B.mg_observed_histogram(p)
+    st = orc.init(g, n, orc.INIT_AT_VERTEX, vertex=0, seed=2)
+    acc, osnaps, _ = orc.observed_histogram(g, st, 0, 500, dt, 5, 25, bins)
+    r = B.mg_particles_read(p, trace=True)
+    nd = int((r["seqhash"] != st.seqhash).sum())
+    assert snaps == osnaps == 20
+    assert np.abs(h.astype(np.int64).ravel() - acc.astype(np.int64).ravel()).sum() <= 2 * snaps * nd
+    # a semi-infinite edge needs a bin span
+    g.bin_span = None
     with pytest.raises(B.MgError):
-        B.mg_histogram(p, 16)
-    with pytest.raises(B.MgError):
-        B.mg_observe_histogram(p, 16, 10)
-    # explicit positions far out on a semi-infinite edge are fine
-    q = B.mg_particles_init(G, 2, B.MG_INIT_EXPLICIT, edge=[0, 4], pos=[1e6, 0.5])
-    B.mg_simulate(q, 10, 1e-3, 0)
-    assert np.all(np.isfinite(B.mg_particles_read(q)["x"]))
+        B.mg_graph_create(g)
 
 
 def test_semi_infinite_graph_validation(B):
     """A semi-infinite edge's terminal vertex must hold only that edge's end;
     NaN and non-positive lengths are rejected."""
-    bad = workloads.from_edges(3, [0, 1], [1, 2], [np.inf, 1.0])  # vertex 1 also starts edge 1
+    bad = workloads.from_edges(3, [0, 1], [1, 2], [np.inf, 1.0], bin_span=1.0)  # vertex 1 also starts edge 1
     with pytest.raises(B.MgError):
         B.mg_graph_create(bad)
     for L in (np.nan, -np.inf, 0.0):
         with pytest.raises(B.MgError):
             B.mg_graph_create(workloads.from_edges(2, [0], [1], [L]))
-    ok = workloads.from_edges(3, [0, 1], [1, 2], [1.0, np.inf])   # a segment then a half-line
+    ok = workloads.from_edges(3, [0, 1], [1, 2], [1.0, np.inf], bin_span=[1.0, 5.0])  # a segment then a half-line
     B.mg_graph_create(ok)

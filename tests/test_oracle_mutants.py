@@ -76,8 +76,8 @@ MUTANTS = {
     "philox_key_schedule": (
         [("if (round > 0) {", "if (round > 1) {")],
         RNG + "test_philox_matches_rocrand"),
-    "histogram_ignores_length": (
-        [("const double inv = (double)nb / g->length[e];", "const double inv = (double)nb;")],
+    "histogram_ignores_span": (
+        [("const double inv = (double)nb / g->bin_span[e];", "const double inv = (double)nb;")],
         INV + "test_mass_histogram_and_hits_consistency"),
     "root_takes_larger": (
         [("u = lo > 0.0 ? lo : hi;", "u = hi;")],

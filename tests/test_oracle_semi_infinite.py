@@ -70,7 +70,7 @@ def test_far_start_moves_as_plain_euler_maruyama(orc):
     reaches the vertex within a short run: its moves are plain EM increments,
     so its mean and variance over many particles follow x0 + a t and
     sigma^2 t exactly (normal law, any dt)."""
-    g = workloads.from_edges(2, [0], [1], [np.inf], [1.5], [0.0], 0.8)
+    g = workloads.from_edges(2, [0], [1], [np.inf], [1.5], [0.0], 0.8, bin_span=100.0)
     N, dt, steps, x0 = 40_000, 0.01, 50, 40.0
     st = orc.init(g, N, orc.INIT_EXPLICIT, edge=np.zeros(N), pos=np.full(N, x0))
     c = orc.simulate(g, st, 0, steps, dt, 7)
@@ -82,10 +82,17 @@ def test_far_start_moves_as_plain_euler_maruyama(orc):
     assert stats.kstest(z, "norm").pvalue > 1e-4
 
 
-def test_uniform_init_and_bins_need_finite_edges(orc):
-    g = workloads.paper_star5("linear", length=np.inf)
+def test_uniform_init_needs_finite_edges_and_bins_a_span(orc):
+    """Uniform-by-length init is undefined with an infinite edge; uniform
+    bins cover the edge's bin span, the last bin taking everything beyond,
+    and a semi-infinite edge must have a span."""
+    g = workloads.paper_star5("linear", length=np.inf, bin_span=2.0)
     with pytest.raises(ValueError):
         orc.init(g, 10, orc.INIT_UNIFORM_LENGTH)
-    st = orc.init(g, 10, orc.INIT_AT_VERTEX, vertex=0)
+    st = orc.init(g, 4, orc.INIT_EXPLICIT, edge=[0, 0, 1, 4], pos=[0.0, 1.99, 2.0, 1e9])
+    h = orc.histogram(g, st, 8)
+    assert h[0, 0] == 1 and h[0, 7] == 1 and h[1, 7] == 1 and h[4, 7] == 1
+    assert h.sum() == 4
+    g.bin_span = None
     with pytest.raises(ValueError):
-        orc.histogram(g, st, 8)
+        orc.init(g, 10, orc.INIT_AT_VERTEX, vertex=0)

@@ -20,6 +20,8 @@ Graph description (same fields as the C-ABI ``mg_graph_desc``):
 * ``vtx_kind[v]``: 0 standard vertex, 1 absorbing vertex.
 * A semi-infinite edge has ``length`` = inf; its terminal vertex is a vertex
   at infinity of its own (one slot, never reached).
+* ``bin_span[e]`` (optional): the length of e the uniform histograms cover
+  (default the edge length; required for a semi-infinite edge).
 """
 from __future__ import annotations
 
@@ -49,6 +51,7 @@ class GraphDesc:
     slot_orient: np.ndarray
     slot_jump_prob: np.ndarray
     vtx_kind: np.ndarray
+    bin_span: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
 
     @property
@@ -58,7 +61,7 @@ class GraphDesc:
 
 def from_edges(n_vertices, edge_init, edge_term, length, drift_a=None,
                drift_c=None, sigma=1.0, weight_init=None, weight_term=None,
-               vtx_kind=None, meta=None) -> GraphDesc:
+               vtx_kind=None, meta=None, bin_span=None) -> GraphDesc:
     """Build the CSR slot table from an edge list.
 
     ``weight_init[e]``/``weight_term[e]`` are nonnegative weights of edge e at
@@ -91,13 +94,15 @@ def from_edges(n_vertices, edge_init, edge_term, length, drift_a=None,
     np.cumsum(counts, out=offsets[1:])
     tot = np.bincount(verts, weights=w, minlength=V)
     b = np.where(tot[verts] > 0, w / np.where(tot[verts] > 0, tot[verts], 1.0), 0.0)
+    span = None if bin_span is None else np.broadcast_to(
+        np.asarray(bin_span, np.float64), (E,)).copy()
     return GraphDesc(V, E, ei, et, L, a, c, s, offsets, edges.astype(np.int32),
-                     ends.astype(np.uint8), b.astype(np.float64), kind,
+                     ends.astype(np.uint8), b.astype(np.float64), kind, span,
                      dict(meta or {}))
 
 
 def star_graph(n_edges, length=1.0, drift_a=None, drift_c=None, sigma=1.0,
-               b_center=None, meta=None) -> GraphDesc:
+               b_center=None, meta=None, bin_span=None) -> GraphDesc:
     """Finite star: centre vertex 0, leaf vertex i+1 at the far end of edge i.
 
     Edge i runs from the centre (x = 0) to leaf i+1 (x = L_i); each leaf is a
@@ -107,7 +112,7 @@ def star_graph(n_edges, length=1.0, drift_a=None, drift_c=None, sigma=1.0,
     et = np.arange(1, E + 1, dtype=np.int32)
     wi = np.ones(E) if b_center is None else np.asarray(b_center, np.float64)
     return from_edges(E + 1, ei, et, length, drift_a, drift_c, sigma,
-                      weight_init=wi, meta=meta)
+                      weight_init=wi, meta=meta, bin_span=bin_span)
 
 
 def segment(length=1.0, drift_a=0.0, drift_c=0.0, sigma=1.0) -> GraphDesc:
@@ -168,13 +173,14 @@ def config2(seed: int = 2) -> tuple[GraphDesc, dict]:
 
 
 def paper_star5(potential: str = "linear", length: float = 2.0,
-                sigma: float = 1.0) -> GraphDesc:
+                sigma: float = 1.0, bin_span: float = 2.0) -> GraphDesc:
     """The 5-edge star of the paper's experiments (Sec. 4): mu_i = -10 i
     (linear potential) or mu_i = -10 i x (quadratic potential), uniform
     b = 1/5.  ``length`` = inf gives the paper's star metric graph (Def. 3:
     one vertex, semi-infinite edges; here each edge's far end is a vertex at
     infinity of its own); a finite length truncates the edges with
-    reflecting leaves."""
+    reflecting leaves.  Uniform histograms cover [0, min(length, bin_span)]
+    of every edge."""
     i = np.arange(1, 6, dtype=np.float64)
     if potential == "linear":
         a, c = -10.0 * i, np.zeros(5)
@@ -183,7 +189,8 @@ def paper_star5(potential: str = "linear", length: float = 2.0,
     else:
         raise ValueError(potential)
     return star_graph(5, length, a, c, sigma,
-                      meta={"name": f"paper_star5_{potential}"})
+                      meta={"name": f"paper_star5_{potential}"},
+                      bin_span=min(float(length), float(bin_span)))
 
 
 def csr_bins(g: GraphDesc, width: float, n_finite: int):

@@ -71,7 +71,9 @@ def star_csr_masses(g, bin_offsets, true_upper) -> np.ndarray:
 def star_bin_means(g, bins: int) -> np.ndarray:
     """Bin averages [E, bins] of the stationary density of a star built like
     ``workloads.star_graph`` (every edge starts at vertex 0), normalised to
-    total mass 1 over the graph."""
+    total mass 1 over the graph.  The bins of edge e cover its binned length
+    (``bin_span``, default the length); the last one also holds the mass
+    beyond, as the histograms count it."""
     E = int(g.n_edges)
     if not np.all(np.asarray(g.edge_init) == 0):
         raise ValueError("not a star centred at vertex 0")
@@ -82,11 +84,13 @@ def star_bin_means(g, bins: int) -> np.ndarray:
     b = np.zeros(E)
     for s in range(int(g.vtx_offsets[0]), int(g.vtx_offsets[1])):
         b[int(g.slot_edge[s])] += float(g.slot_jump_prob[s])
+    span = np.asarray(g.length if getattr(g, "bin_span", None) is None else g.bin_span,
+                      np.float64)
     out = np.zeros((E, bins))
     for e in range(E):
-        L = float(g.length[e])
-        edges = np.linspace(0.0, L, bins + 1)
+        edges = np.linspace(0.0, float(span[e]), bins + 1)
+        edges[-1] = float(g.length[e])  # the last bin runs to the edge's end
         out[e] = b[e] / D * _bin_integrals(float(g.drift_a[e]), float(g.drift_c[e]), D, edges)
     out /= out.sum()
-    width = np.asarray(g.length, np.float64)[:, None] / bins
+    width = span[:, None] / bins
     return out / width
