@@ -285,8 +285,9 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
               d->bin_span ? d->bin_span[e] : d->length[e]};
     // (a particle never measures from the far end of a semi-infinite edge)
     const double aL = std::isinf(d->length[e]) ? 0.0 : std::fma(c, d->length[e], a);
+    const float scale = (float)(std::isinf(d->length[e]) ? d->bin_span[e] : d->length[e]);
     e32[e] = {(float)d->length[e], (float)a, (float)c, (float)d->sigma[e], (float)aL,
-              d->edge_init[e], d->edge_term[e], 0.0f};
+              d->edge_init[e], d->edge_term[e], 1e-6f * scale};
   }
   std::vector<uint64_t> thr(nnz);
   slot_thresholds(V, off, d->slot_jump_prob, thr);

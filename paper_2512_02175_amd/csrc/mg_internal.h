@@ -25,12 +25,14 @@ struct alignas(16) EdgeRec64 {
 };
 
 // Edge record for the FP32 path: 32 bytes.  aL = a + c L is the drift at
-// the terminal end (the constant term of the drift seen from that end).
+// the terminal end (the constant term of the drift seen from that end);
+// near = 1e-6 L (1e-6 times the binned length on a semi-infinite edge): a
+// crossing from closer to the vertex than that is solved in FP64.
 struct alignas(16) EdgeRec32 {
   float L, a, c, sigma;
   float aL;
   int32_t vinit, vterm;
-  float pad;
+  float near;
 };
 
 // Vertex block, 32 bytes: everything a vertex hit needs in one load.

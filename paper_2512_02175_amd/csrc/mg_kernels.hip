@@ -683,7 +683,7 @@ struct Particle32 {
     const float dn = y + yl;
     const float d = fmaxf(near ? dn : (R.L - y) - yl, 0.0f);
     float u;
-    if (d > 0.0f && d < 1e-6f * R.L) {
+    if (d > 0.0f && d < G.e32[e].near) {
       // crossing solve in FP64 next to the vertex (on the vertex itself,
       // d = 0, the root is -B/A: one division, no cancellation)
       const double hd = (double)hh + (double)hl;
