@@ -1336,14 +1336,13 @@ __global__ void k_clear_word(uint32_t *w) {
 // Blocks of a persistent launch: as many as stay resident at once (CUs x
 // blocks per CU for this kernel and LDS size), fewer if the set is small.
 uint32_t resident_blocks(const void *func, size_t shm, uint32_t need) {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-  }
+  // the current device's CU count (queried per launch: a host-side call of
+  // microseconds, and correct whichever device the caller has made current)
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kBlock, shm) != hipSuccess ||
       per_cu <= 0)
