@@ -125,6 +125,13 @@ def test_init_rules_and_uniform_bins_on_a_span(B, orc):
     g.bin_span = None
     with pytest.raises(B.MgError):
         B.mg_graph_create(g)
+    # a span shorter than a finite edge: the last bin takes the rest
+    f = workloads.star_graph(3, [1.0, 2.0, 3.0], sigma=1.0, bin_span=[1.0, 0.5, 3.0])
+    Gf = B.mg_graph_create(f)
+    st = orc.init(f, 20_000, orc.INIT_UNIFORM_LENGTH, seed=8)
+    for prec in (B.MG_FP64, B.MG_FP32):
+        q = B.mg_particles_init(Gf, 20_000, B.MG_INIT_UNIFORM_LENGTH, init_seed=8, precision=prec)
+        assert np.array_equal(B.mg_histogram(q, 10), orc.histogram(f, st, 10))
 
 
 def test_semi_infinite_graph_validation(B):
