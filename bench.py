@@ -46,7 +46,7 @@ ALG_FP64_HIT = 130.0
 # HBM bytes per k_pool32 launch on this workload from the FETCH_SIZE and
 # WRITE_SIZE counter passes (scaled by a 1 GiB copy), valid for the kernel
 # source whose sha256 prefix is given; reported as null for any other build.
-TRAFFIC = {"kernel_sha256": "387c521cc8696aaa", "bytes_per_launch": 321.1e6}
+TRAFFIC = {"kernel_sha256": "c3d97039749a9fce", "bytes_per_launch": 321.4e6}
 
 
 def kernel_traffic():
@@ -532,8 +532,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB on the device (scale for HBM counters)")
     ap.add_argument("--workload", default="langevin_star64",
-                    choices=["langevin_star64", "vascular20k", "batch512", "accuracy_sweep",
-                             "density_error", "nohit_segment", "vascular_tracer"],
+                    choices=["langevin_star64", "langevin_star64_mirror", "vascular20k",
+                             "batch512", "accuracy_sweep", "density_error", "nohit_segment",
+                             "vascular_tracer"],
                     help="the metric's configuration (default) or another workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -571,6 +572,11 @@ def main():
         print(json.dumps(run_density(args, B, torch)), flush=True)
         return
     g, run = workloads.config2()
+    mirror = args.workload == "langevin_star64_mirror"
+    if mirror:
+        # the same star with mirror leaves (reflection by the mirror image)
+        g = workloads.star_graph(g.n_edges, g.length, g.drift_a, g.drift_c, g.sigma,
+                                 b_center=np.ones(g.n_edges), meta=g.meta, leaf_kind=2)
     G = B.mg_graph_create(g)
     dts = run["dts"]
 
@@ -620,7 +626,7 @@ def main():
     achieved = float(np.mean(per_launch)) / k32
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
-            "traffic": kernel_traffic(),
+            "traffic": None if mirror else kernel_traffic(),
             "kernel": "/".join(sorted(set(scheds))), "kernel_ms_per_launch": k32 * 1e3,
             "alg_lane_ops_per_particle_step": ALG_FP32_STEP,
             "alg_lane_ops_per_hit": ALG_FP32_HIT}
@@ -630,9 +636,11 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall32 / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "langevin_star64: 64-edge star, V_e=k(x-m)^2, sigma=sqrt(2), "
+        "config": {"workload": ("langevin_star64_mirror" if mirror else "langevin_star64")
+                               + ": 64-edge star, V_e=k(x-m)^2, sigma=sqrt(2), "
                                "b=1/64, 1e7 particles uniform by length, 1e4 steps at "
-                               "dt=1e-2 and dt=1e-3, M=8, 256 bins/edge",
+                               "dt=1e-2 and dt=1e-3, M=8, 256 bins/edge"
+                               + (", mirror leaves" if mirror else ""),
                    "n_particles": run["n_particles"], "n_steps": run["n_steps"],
                    "dts": list(dts), "bins_per_edge": run["bins"]},
         "particle_steps_per_s": sum(r["steps"] for r in res32) * args.steps / wall32,

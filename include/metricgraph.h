@@ -45,7 +45,7 @@ typedef enum {
 
 typedef enum { MG_FP64 = 0, MG_FP32 = 1 } mg_precision;
 
-typedef enum { MG_VTX_STANDARD = 0, MG_VTX_ABSORBING = 1 } mg_vertex_kind;
+typedef enum { MG_VTX_STANDARD = 0, MG_VTX_ABSORBING = 1, MG_VTX_MIRROR = 2 } mg_vertex_kind;
 
 typedef struct mg_graph mg_graph;          /* opaque */
 typedef struct mg_particles mg_particles;  /* opaque */
@@ -75,7 +75,18 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *                        1e-9 (the library divides by the sum).
  *   vtx_kind             [V] mg_vertex_kind, or NULL for all standard.  An
  *                        absorbing vertex removes a particle that hits it
- *                        (Wentzell killing term a_v = 1, Sec. 2.2).
+ *                        (Wentzell killing term a_v = 1, Sec. 2.2).  A
+ *                        mirror vertex is a leaf (exactly one slot, b = 1)
+ *                        that reflects: a sub-step proposal that leaves the
+ *                        edge through it is replaced by its mirror image
+ *                        (-x~ at an initial end, 2L - x~ at a terminal end;
+ *                        the far-end reflection of the paper's star-graph
+ *                        kernel, Sec. 4) when that image lies strictly
+ *                        inside the edge, which ends the step with no vertex
+ *                        hit: no split, no hit-stream draw, no exit record of
+ *                        its own.  Otherwise (a move longer than the edge, or
+ *                        an image on a vertex) the sub-step splits there as at
+ *                        a standard leaf.
  *   bin_span             [E] the length of edge e that the uniform histograms
  *                        (mg_histogram, mg_observe_histogram, mg_density_l2)
  *                        divide into their bins: bin width bin_span[e] / nb,

@@ -107,6 +107,11 @@ class OracleGraph:
             self._keep["length"] if span is None else span, np.float64)
         if not np.all(np.isfinite(self._keep["bin_span"])):
             raise ValueError("a semi-infinite edge needs a finite bin_span")
+        kind, off = self._keep["vtx_kind"], self._keep["vtx_offsets"]
+        if np.any(kind > 2):
+            raise ValueError("unknown vertex kind")
+        if np.any((kind == 2) & (np.diff(off) != 1)):
+            raise ValueError("a mirror vertex must be a leaf (exactly one slot)")
         k = self._keep
         self.c = _Graph(int(desc.n_vertices), int(desc.n_edges),
                         *[k[n].ctypes.data for n in (

@@ -141,7 +141,8 @@ typedef struct {
   const int32_t *slot_edge;               /* [nnz] */
   const uint8_t *slot_orient;             /* [nnz] 0: enter at x=0, 1: at x=L */
   const double *slot_jump_prob;           /* [nnz] b_{v,e} */
-  const uint8_t *vtx_kind;                /* [V] 0 standard, 1 absorbing */
+  const uint8_t *vtx_kind;                /* [V] 0 standard, 1 absorbing,
+                                             2 mirror (a reflecting leaf) */
   const double *bin_span;                 /* [E] length the uniform bins cover */
 } or_graph;
 
@@ -164,7 +165,7 @@ int or_thresholds(const or_graph *g, uint64_t *thr) {
     }
     if (last_pos < 0) {
       for (int32_t s = s0; s < s1; ++s) thr[s] = 0;
-      if (s1 > s0 && (!g->vtx_kind || g->vtx_kind[v] == 0)) return -1;
+      if (s1 > s0 && (!g->vtx_kind || g->vtx_kind[v] != 1)) return -1;
       continue;
     }
     double cum = 0.0;
@@ -299,6 +300,16 @@ static void run_particle(const or_graph *g, const uint64_t *thr, uint32_t p,
       /* Vertex hit: the end is init if the proposal is <= 0 (reading A8). */
       const int hit_init = xt <= 0.0;
       const int32_t v = hit_init ? g->edge_init[e] : g->edge_term[e];
+      /* Mirror leaf (reading A25; the far-end reflection of the star-graph
+         kernel, Sec. 4): the proposal's mirror image in the vertex ends the
+         step when it lies inside the edge; no vertex hit is recorded. */
+      if (g->vtx_kind && g->vtx_kind[v] == 2) {
+        const double xr = hit_init ? -xt : 2.0 * L - xt;
+        if (xr > 0.0 && xr < L) {
+          x = xr;
+          break;
+        }
+      }
       const double d = hit_init ? x : L - x;
       const double A = hit_init ? mu * h : -(mu * h);
       const double B = hit_init ? gsd * w : -(gsd * w);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmetricgraph.so")
 
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ESTATE = 0, 1, 2, 3, 4
 MG_FP64, MG_FP32 = 0, 1
-MG_VTX_STANDARD, MG_VTX_ABSORBING = 0, 1
+MG_VTX_STANDARD, MG_VTX_ABSORBING, MG_VTX_MIRROR = 0, 1, 2
 MG_INIT_EXPLICIT, MG_INIT_AT_VERTEX, MG_INIT_UNIFORM_LENGTH = 0, 1, 2
 MG_SCHED_AUTO, MG_SCHED_LANES, MG_SCHED_POOLS, MG_SCHED_POOLS256, MG_SCHED_POOLS_W8 = 0, 1, 2, 3, 4
 

@@ -252,7 +252,10 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
       any_pos |= b > 0.0;
     }
     const bool absorbing = d->vtx_kind && d->vtx_kind[v] == MG_VTX_ABSORBING;
-    if (d->vtx_kind && d->vtx_kind[v] > 1) return fail(MG_EINVAL, "vertex %d: unknown kind", v);
+    if (d->vtx_kind && d->vtx_kind[v] > MG_VTX_MIRROR)
+      return fail(MG_EINVAL, "vertex %d: unknown kind", v);
+    if (d->vtx_kind && d->vtx_kind[v] == MG_VTX_MIRROR && off[v + 1] - off[v] != 1)
+      return fail(MG_EINVAL, "mirror vertex %d must be a leaf (exactly one slot)", v);
     if (!absorbing) {
       if (!any_pos) return fail(MG_EINVAL, "standard vertex %d has no positive jump probability", v);
       if (std::fabs(sum - 1.0) > 1e-9)
@@ -278,16 +281,21 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   // pack
   std::vector<EdgeRec64> e64(E);
   std::vector<EdgeRec32> e32(E);
+  auto end_id = [&](int32_t v) {
+    const bool mirror = d->vtx_kind && d->vtx_kind[v] == MG_VTX_MIRROR;
+    return (int32_t)((uint32_t)v | (mirror ? kMirrorEnd : 0u));
+  };
   for (int32_t e = 0; e < E; ++e) {
     const double a = d->drift_a ? d->drift_a[e] : 0.0;
     const double c = d->drift_c ? d->drift_c[e] : 0.0;
-    e64[e] = {d->length[e], a, c, d->sigma[e], d->edge_init[e], d->edge_term[e],
+    const int32_t vi = end_id(d->edge_init[e]), vt = end_id(d->edge_term[e]);
+    e64[e] = {d->length[e], a, c, d->sigma[e], vi, vt,
               d->bin_span ? d->bin_span[e] : d->length[e]};
     // (a particle never measures from the far end of a semi-infinite edge)
     const double aL = std::isinf(d->length[e]) ? 0.0 : std::fma(c, d->length[e], a);
     const float scale = (float)(std::isinf(d->length[e]) ? d->bin_span[e] : d->length[e]);
     e32[e] = {(float)d->length[e], (float)a, (float)c, (float)d->sigma[e], (float)aL,
-              d->edge_init[e], d->edge_term[e], 1e-6f * scale};
+              vi, vt, 1e-6f * scale};
   }
   std::vector<uint64_t> thr(nnz);
   slot_thresholds(V, off, d->slot_jump_prob, thr);

@@ -17,10 +17,15 @@ constexpr int32_t kMaxEdges = 0x3FFFFFFF;
 
 // Edge record for the FP64 path: 48 bytes, one per edge.  span is the
 // length the uniform histograms bin (the edge length unless the caller gave
-// another; finite on a semi-infinite edge).
+// another; finite on a semi-infinite edge).  The end vertex ids of both
+// records carry kMirrorEnd when that end is a mirror vertex (a reflecting
+// leaf: a proposal leaving the edge there takes its mirror image when that
+// lies inside the edge), so the step reads the flag with the edge.
+constexpr uint32_t kMirrorEnd = 0x80000000u;
+constexpr int32_t kVertexMask = 0x7FFFFFFF;
 struct alignas(16) EdgeRec64 {
   double L, a, c, sigma;  // length, drift a + c x, diffusion
-  int32_t vinit, vterm;   // end vertices
+  int32_t vinit, vterm;   // end vertices (| kMirrorEnd at a mirror vertex)
   double span;
 };
 

@@ -440,7 +440,17 @@ struct Particle64 {
         break;
       }
       const bool at_init = xt <= 0.0;
-      const int32_t v = at_init ? R.vinit : R.vterm;
+      const int32_t vr = at_init ? R.vinit : R.vterm;
+      if (vr < 0) {
+        // reflecting leaf: the mirror image ends the step if it lies
+        // inside the edge
+        const double xr = at_init ? -xt : 2.0 * R.L - xt;
+        if (xr > 0.0 && xr < R.L) {
+          x = xr;
+          break;
+        }
+      }
+      const int32_t v = vr & kVertexMask;
       const double d = at_init ? x : R.L - x;
       const double qa = at_init ? mu * h : -(mu * h);
       const double qb = at_init ? g * w : -(g * w);
@@ -679,81 +689,102 @@ struct Particle32 {
     const float yt = add_comp(fmaf(g, we, mdt) + yl, err);
     const bool near = yt <= 0.0f;
     const bool at_term = near == (side != 0u);
-    const int32_t v = at_term ? R.vterm : R.vinit;
-    const float dn = y + yl;
-    const float d = fmaxf(near ? dn : (R.L - y) - yl, 0.0f);
-    float u;
-    if (d > 0.0f && d < G.e32[e].near) {
-      // crossing solve in FP64 next to the vertex (on the vertex itself,
-      // d = 0, the root is -B/A: one division, no cancellation)
-      const double hd = (double)hh + (double)hl;
-      const double mud = fma((double)R.c, (double)y, (double)as);
-      const double gd = (double)R.sigma * sqrt(hd);
-      const double qa = near ? mud * hd : -(mud * hd);
-      const double qb = near ? gd * (double)we : -(gd * (double)we);
-      const double yd = (double)y + (double)yl;
-      const double dd = fmax(near ? yd : (double)R.L - yd, 0.0);
-      u = (float)first_root64(qa, qb, dd);
-    } else {
-      const float gw = g * we;
-      u = first_root32(near ? mdt : -mdt, near ? gw : -gw, d);
-    }
-    // remaining time (1 - u^2)(hh + hl), compensated (TwoProduct by fma,
-    // TwoSum, renormalised)
-    {
-      const float al = u * u;
-      const float p = al * hh;
-      const float pe = fmaf(al, hh, -p);
-      const float s = hh - p;
-      const float bb = s - hh;
-      const float se = (hh - (s - bb)) + (-p - bb);
-      const float lo = ((se - pe) + hl) - al * hl;
-      hh = s + lo;
-      hl = lo - (hh - s);
-    }
-    h.hh = hh;
-    h.hl = hl;
-    ++h.k;
-    ++nhit;
-    t.hits++;
-    const VtxBlk vb = G.vtx[v];
-    if (vb.deg < 0) {
-      alive = false;
-      death_step = step;
-      atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
-      if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
-      return true;
-    }
-    const U4 hd = philox(pid, step, (uint32_t)h.k, S.tag, A.key0, A.key1);
-    const SlotPick sp = pick_slot(G, vb, hd.x);
-    e = eo_edge(sp.eo);
-    R = load_edge32(G.e32, e);
-    side = sp.eo & 1u;
-    y = 0.0f;
-    yl = 0.0f;
-    frame();
-    h.last = sp.s;
-    if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)sp.s);
-    bool done = hh == 0.0f;
-    if (!done && h.k == A.max_splits) {
-      t.trunc++;
+    const int32_t vr = at_term ? R.vterm : R.vinit;
+    // reflecting leaf: the mirror image, as a distance from the hit end
+    // (-(yt + err) at the reference end; (yt - L) + err at the other, where
+    // yt - L is exact for yt <= 2L), renormalised by TwoSum; it ends the
+    // step when it lies inside the edge
+    const float r0 = near ? -yt : yt - R.L;
+    const float r1 = near ? -err : err;
+    const float rs = r0 + r1;
+    const float rb = rs - r0;
+    const float re = (r0 - (rs - rb)) + (r1 - rb);
+    bool done;
+    if (vr < 0 && rs > 0.0f && rs < R.L) {
+      y = rs;
+      yl = re;
+      if (!near) {
+        side ^= 1u;
+        frame();
+      }
       done = true;
-    }
-    if (!done) {
-      // the next sub-step, from the vertex (normal folded into the edge)
-      h.w = box_muller32_cos(hd.y, hd.z);
-      const float mu2 = fmaf(R.c, y, as);
-      const float g2 = R.sigma * __builtin_amdgcn_sqrtf(hh);
-      float err2;
-      const float yt2 = add_comp(fmaf(g2, fabsf(h.w), mu2 * hh) + yl, err2);
-      t.sub++;
-      if (yt2 > 0.0f && yt2 < R.L) {
-        y = yt2;
-        yl = err2;
+    } else {
+      const int32_t v = vr & kVertexMask;
+      const float dn = y + yl;
+      const float d = fmaxf(near ? dn : (R.L - y) - yl, 0.0f);
+      float u;
+      if (d > 0.0f && d < G.e32[e].near) {
+        // crossing solve in FP64 next to the vertex (on the vertex itself,
+        // d = 0, the root is -B/A: one division, no cancellation)
+        const double hd = (double)hh + (double)hl;
+        const double mud = fma((double)R.c, (double)y, (double)as);
+        const double gd = (double)R.sigma * sqrt(hd);
+        const double qa = near ? mud * hd : -(mud * hd);
+        const double qb = near ? gd * (double)we : -(gd * (double)we);
+        const double yd = (double)y + (double)yl;
+        const double dd = fmax(near ? yd : (double)R.L - yd, 0.0);
+        u = (float)first_root64(qa, qb, dd);
+      } else {
+        const float gw = g * we;
+        u = first_root32(near ? mdt : -mdt, near ? gw : -gw, d);
+      }
+      // remaining time (1 - u^2)(hh + hl), compensated (TwoProduct by fma,
+      // TwoSum, renormalised)
+      {
+        const float al = u * u;
+        const float p = al * hh;
+        const float pe = fmaf(al, hh, -p);
+        const float s = hh - p;
+        const float bb = s - hh;
+        const float se = (hh - (s - bb)) + (-p - bb);
+        const float lo = ((se - pe) + hl) - al * hl;
+        hh = s + lo;
+        hl = lo - (hh - s);
+      }
+      h.hh = hh;
+      h.hl = hl;
+      ++h.k;
+      ++nhit;
+      t.hits++;
+      const VtxBlk vb = G.vtx[v];
+      if (vb.deg < 0) {
+        alive = false;
+        death_step = step;
+        atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
+        if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
+        return true;
+      }
+      const U4 hd = philox(pid, step, (uint32_t)h.k, S.tag, A.key0, A.key1);
+      const SlotPick sp = pick_slot(G, vb, hd.x);
+      e = eo_edge(sp.eo);
+      R = load_edge32(G.e32, e);
+      side = sp.eo & 1u;
+      y = 0.0f;
+      yl = 0.0f;
+      frame();
+      h.last = sp.s;
+      if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)sp.s);
+      done = hh == 0.0f;
+      if (!done && h.k == A.max_splits) {
+        t.trunc++;
         done = true;
       }
+      if (!done) {
+        // the next sub-step, from the vertex (normal folded into the edge)
+        h.w = box_muller32_cos(hd.y, hd.z);
+        const float mu2 = fmaf(R.c, y, as);
+        const float g2 = R.sigma * __builtin_amdgcn_sqrtf(hh);
+        float err2;
+        const float yt2 = add_comp(fmaf(g2, fabsf(h.w), mu2 * hh) + yl, err2);
+        t.sub++;
+        if (yt2 > 0.0f && yt2 < R.L) {
+          y = yt2;
+          yl = err2;
+          done = true;
+        }
+      }
     }
-    if (done) count_exit<LDS>(s_exit, S.exit_cnt, h.last);
+    if (done && h.k > 0) count_exit<LDS>(s_exit, S.exit_cnt, h.last);
     return done;
   }
 

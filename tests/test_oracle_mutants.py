@@ -22,6 +22,7 @@ RS = "tests/test_oracle_root_slots.py::"
 INV = "tests/test_oracle_invariants.py::"
 SEQ = "tests/test_oracle_split_sequences.py::"
 SRCS = "tests/test_oracle_sources.py::"
+MIR = "tests/test_oracle_mirror.py::"
 
 MUTANTS = {
     "drift_sign": (
@@ -95,6 +96,16 @@ MUTANTS = {
         [("const int32_t s = pick_slot(g, thr, v, o[1]);",
           "const int32_t s = pick_slot(g, thr, v, o[0]);")],
         SRCS + "test_sources_law"),
+    "mirror_skipped": (
+        [("if (g->vtx_kind && g->vtx_kind[v] == 2) {", "if (0) {")],
+        MIR + "test_one_step_is_the_folded_normal"),
+    "mirror_far_image_wrong": (
+        [("const double xr = hit_init ? -xt : 2.0 * L - xt;",
+          "const double xr = hit_init ? -xt : L - xt;")],
+        MIR + "test_one_step_is_the_folded_normal"),
+    "mirror_image_not_checked": (
+        [("if (xr > 0.0 && xr < L) {", "if (xr > 0.0) {")],
+        MIR + "test_image_outside_the_edge_splits"),
     "far_end_not_checked": (
         [("if (xt > 0.0 && xt < L) {", "if (xt > 0.0) {")],
         CF + "test_radial_reflected_heat_kernel_converges"),

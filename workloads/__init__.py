@@ -17,7 +17,8 @@ Graph description (same fields as the C-ABI ``mg_graph_desc``):
   edge ends; orient 0 means v is the edge's initial vertex (a particle enters
   at x = 0), 1 means its terminal vertex (enters at x = L).  The jump
   probabilities b_{v,e} of the standard gluing conditions sum to 1 per vertex.
-* ``vtx_kind[v]``: 0 standard vertex, 1 absorbing vertex.
+* ``vtx_kind[v]``: 0 standard vertex, 1 absorbing vertex, 2 mirror vertex
+  (a leaf that reflects a proposal leaving through it into the edge).
 * A semi-infinite edge has ``length`` = inf; its terminal vertex is a vertex
   at infinity of its own (one slot, never reached).
 * ``bin_span[e]`` (optional): the length of e the uniform histograms cover
@@ -102,22 +103,27 @@ def from_edges(n_vertices, edge_init, edge_term, length, drift_a=None,
 
 
 def star_graph(n_edges, length=1.0, drift_a=None, drift_c=None, sigma=1.0,
-               b_center=None, meta=None, bin_span=None) -> GraphDesc:
+               b_center=None, meta=None, bin_span=None, leaf_kind=0) -> GraphDesc:
     """Finite star: centre vertex 0, leaf vertex i+1 at the far end of edge i.
 
     Edge i runs from the centre (x = 0) to leaf i+1 (x = L_i); each leaf is a
-    degree-1 vertex (jump probability 1, i.e. reflecting)."""
+    degree-1 vertex (jump probability 1, i.e. reflecting by a split there), or
+    with ``leaf_kind`` = 2 a mirror vertex (reflecting by the mirror image)."""
     E = int(n_edges)
     ei = np.zeros(E, np.int32)
     et = np.arange(1, E + 1, dtype=np.int32)
     wi = np.ones(E) if b_center is None else np.asarray(b_center, np.float64)
+    kind = np.zeros(E + 1, np.uint8)
+    kind[1:] = leaf_kind
     return from_edges(E + 1, ei, et, length, drift_a, drift_c, sigma,
-                      weight_init=wi, meta=meta, bin_span=bin_span)
+                      weight_init=wi, meta=meta, bin_span=bin_span, vtx_kind=kind)
 
 
-def segment(length=1.0, drift_a=0.0, drift_c=0.0, sigma=1.0) -> GraphDesc:
-    """One edge between two degree-1 (reflecting) vertices."""
-    return from_edges(2, [0], [1], [length], [drift_a], [drift_c], sigma)
+def segment(length=1.0, drift_a=0.0, drift_c=0.0, sigma=1.0, end_kind=0) -> GraphDesc:
+    """One edge between two degree-1 vertices: reflecting by a split there,
+    or with ``end_kind`` = 2 mirror vertices."""
+    return from_edges(2, [0], [1], [length], [drift_a], [drift_c], sigma,
+                      vtx_kind=[end_kind, end_kind])
 
 
 def random_tree(n_edges, rng, length_range=(0.2, 3.0), sigma=np.sqrt(2.0),
@@ -173,14 +179,16 @@ def config2(seed: int = 2) -> tuple[GraphDesc, dict]:
 
 
 def paper_star5(potential: str = "linear", length: float = 2.0,
-                sigma: float = 1.0, bin_span: float = 2.0) -> GraphDesc:
+                sigma: float = 1.0, bin_span: float = 2.0,
+                leaf_kind: int = 0) -> GraphDesc:
     """The 5-edge star of the paper's experiments (Sec. 4): mu_i = -10 i
     (linear potential) or mu_i = -10 i x (quadratic potential), uniform
     b = 1/5.  ``length`` = inf gives the paper's star metric graph (Def. 3:
     one vertex, semi-infinite edges; here each edge's far end is a vertex at
     infinity of its own); a finite length truncates the edges with
     reflecting leaves.  Uniform histograms cover [0, min(length, bin_span)]
-    of every edge."""
+    of every edge.  ``leaf_kind`` = 2 makes the leaves of a finite star
+    mirror vertices, as the paper's star kernel reflects at far ends."""
     i = np.arange(1, 6, dtype=np.float64)
     if potential == "linear":
         a, c = -10.0 * i, np.zeros(5)
@@ -190,7 +198,8 @@ def paper_star5(potential: str = "linear", length: float = 2.0,
         raise ValueError(potential)
     return star_graph(5, length, a, c, sigma,
                       meta={"name": f"paper_star5_{potential}"},
-                      bin_span=min(float(length), float(bin_span)))
+                      bin_span=min(float(length), float(bin_span)),
+                      leaf_kind=leaf_kind)
 
 
 def csr_bins(g: GraphDesc, width: float, n_finite: int):
