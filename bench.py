@@ -41,12 +41,15 @@ ALG_FP32_STEP = 27.5
 ALG_FP32_HIT = 80.0      # per vertex hit: Philox, one normal, root, time, slot, edge
 ALG_FP64_STEP = 62.5
 ALG_FP64_HIT = 130.0
+# cubic drift and diffusion: two Horner steps more for mu and three for
+# sigma at every sub-step start (a step, or a restart from a vertex)
+ALG_FP64_CUBIC = 5.0
 
 
 # HBM bytes per k_pool32 launch on this workload from the FETCH_SIZE and
 # WRITE_SIZE counter passes (scaled by a 1 GiB copy), valid for the kernel
 # source whose sha256 prefix is given; reported as null for any other build.
-TRAFFIC = {"kernel_sha256": "c3d97039749a9fce", "bytes_per_launch": 321.4e6}
+TRAFFIC = {"kernel_sha256": "5192e2c355655e81", "bytes_per_launch": 321.1e6}
 
 
 def kernel_traffic():
@@ -465,6 +468,55 @@ def run_nohit(args, B, torch):
                          "kernel_ms_per_launch": k * 1e3}}
 
 
+def run_double_well(args, B, torch):
+    """General coefficients on the FP64 path: the 64-edge double-well star
+    (cubic drift, graded diffusion), 1e7 particles uniform by length, 1e4
+    steps at dt = 1e-3."""
+    import numpy as np
+    import workloads
+    g = workloads.double_well_star(64)
+    G = B.mg_graph_create(g)
+    n, steps, dt = 10_000_000, 10_000, 1e-3
+    ktimes, walls, res = [], [], None
+    for it in range(args.warmup + args.steps):
+        p = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=0,
+                                precision=B.MG_FP64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        B.mg_simulate(p, steps, dt, 0)
+        e1.record()
+        tot = B.mg_exit_counts(p)[2]
+        hist = B.mg_histogram(p, 64)
+        wall = time.perf_counter() - t0
+        if it >= args.warmup:
+            ktimes.append(e0.elapsed_time(e1) * 1e-3)
+            walls.append(wall)
+            res = tot
+        del p
+    k = float(np.mean(ktimes))
+    work = ((ALG_FP64_STEP + ALG_FP64_CUBIC) * float(res[3])
+            + (ALG_FP64_HIT + ALG_FP64_CUBIC) * float(res[2]))
+    achieved = work / k
+    return {"metric": METRIC, "value": float(res[1]) / float(np.mean(walls)),
+            "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": float(np.mean(walls)) * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "double_well_star64: 64-edge star, cubic drift -V' of a "
+                                   "double-well potential per edge, graded sigma(x), 1e7 "
+                                   "particles uniform by length, 1e4 steps at dt=1e-3, FP64"},
+            "hits_per_step": float(res[2]) / float(res[3]),
+            "histogram_mass": int(hist.sum()),
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                         "peak": PEAK_LANE_OPS / 1e12, "unit": "T VALU lane-ops/s",
+                         "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                         "kernel": "k_step<fp64, cubic coefficients>",
+                         "kernel_ms_per_call": k * 1e3}}
+
+
 def run_tracer(args, B, torch):
     """Tracer transport on the vascular network (Sec. 4.2): a pulse of 1e8
     FP32 particles injected at the inlets in proportion to their inflow,
@@ -534,7 +586,7 @@ def main():
     ap.add_argument("--workload", default="langevin_star64",
                     choices=["langevin_star64", "langevin_star64_mirror", "vascular20k",
                              "batch512", "accuracy_sweep", "density_error", "nohit_segment",
-                             "vascular_tracer"],
+                             "vascular_tracer", "double_well_star64"],
                     help="the metric's configuration (default) or another workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -558,6 +610,9 @@ def main():
         return
     if args.workload == "nohit_segment":
         print(json.dumps(run_nohit(args, B, torch)), flush=True)
+        return
+    if args.workload == "double_well_star64":
+        print(json.dumps(run_double_well(args, B, torch)), flush=True)
         return
     if args.workload == "vascular20k":
         print(json.dumps(run_vascular(args, B, torch)), flush=True)

@@ -93,6 +93,16 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *                        positions beyond bin_span[e] counted in the last
  *                        bin.  Finite, > 0.  NULL: the edge lengths (then
  *                        every edge must be finite).
+ *   drift_c2, drift_c3   [E] higher drift terms: mu_e(x) = a_e + c_e x +
+ *                        c2_e x^2 + c3_e x^3 (NULL: 0); finite.
+ *   sigma_c1..sigma_c3   [E] position-dependent diffusion: sigma_e(x) =
+ *                        sigma_e + s1_e x + s2_e x^2 + s3_e x^3 (NULL: 0),
+ *                        > 0 on all of [0, L_e].  The paper allows any C^1
+ *                        coefficients (Sec. 2.2); cubics cover double-well
+ *                        potentials and graded diffusivities.  Each sub-step
+ *                        freezes both at its starting point (Euler-Maruyama,
+ *                        Alg. 2).  Nonzero higher terms need finite edges and
+ *                        FP64 sets: an FP32 set on such a graph is refused.
  * Every edge must appear exactly once at its initial vertex with orient 0
  * and once at its terminal vertex with orient 1 (a self-loop twice at its
  * vertex).  A standard vertex needs at least one slot with b > 0.
@@ -109,6 +119,8 @@ typedef struct {
   const double *slot_jump_prob;
   const uint8_t *vtx_kind;
   const double *bin_span;
+  const double *drift_c2, *drift_c3;
+  const double *sigma_c1, *sigma_c2, *sigma_c3;
 } mg_graph_desc;
 
 /* Validates and packs the graph into device tables (edge records, slot

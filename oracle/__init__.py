@@ -44,7 +44,12 @@ class _Graph(C.Structure):
                 ("drift_c", C.c_void_p), ("sigma", C.c_void_p),
                 ("vtx_offsets", C.c_void_p), ("slot_edge", C.c_void_p),
                 ("slot_orient", C.c_void_p), ("slot_jump_prob", C.c_void_p),
-                ("vtx_kind", C.c_void_p), ("bin_span", C.c_void_p)]
+                ("vtx_kind", C.c_void_p), ("bin_span", C.c_void_p),
+                ("drift_c2", C.c_void_p), ("drift_c3", C.c_void_p),
+                ("sigma_c1", C.c_void_p), ("sigma_c2", C.c_void_p),
+                ("sigma_c3", C.c_void_p)]
+
+HIGHER = ("drift_c2", "drift_c3", "sigma_c1", "sigma_c2", "sigma_c3")
 
 
 def lib():
@@ -112,12 +117,23 @@ class OracleGraph:
             raise ValueError("unknown vertex kind")
         if np.any((kind == 2) & (np.diff(off) != 1)):
             raise ValueError("a mirror vertex must be a leaf (exactly one slot)")
+        # higher coefficient terms: absent arrays are passed as NULL (zero)
+        hi = []
+        for n in HIGHER:
+            v = getattr(desc, n, None)
+            if v is None:
+                hi.append(None)
+                continue
+            self._keep[n] = np.ascontiguousarray(
+                np.broadcast_to(np.asarray(v, np.float64), (int(desc.n_edges),)))
+            hi.append(self._keep[n].ctypes.data)
         k = self._keep
         self.c = _Graph(int(desc.n_vertices), int(desc.n_edges),
                         *[k[n].ctypes.data for n in (
                             "edge_init", "edge_term", "length", "drift_a",
                             "drift_c", "sigma", "vtx_offsets", "slot_edge",
-                            "slot_orient", "slot_jump_prob", "vtx_kind", "bin_span")])
+                            "slot_orient", "slot_jump_prob", "vtx_kind", "bin_span")],
+                        *hi)
         self.V = int(desc.n_vertices)
         self.E = int(desc.n_edges)
         self.nnz = int(k["vtx_offsets"][-1])

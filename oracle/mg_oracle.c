@@ -144,7 +144,27 @@ typedef struct {
   const uint8_t *vtx_kind;                /* [V] 0 standard, 1 absorbing,
                                              2 mirror (a reflecting leaf) */
   const double *bin_span;                 /* [E] length the uniform bins cover */
+  /* [E] each, or NULL (zero): higher terms of the coefficient functions,
+     mu_e(x) = a + c x + c2 x^2 + c3 x^3, sigma_e(x) = sigma + s1 x + s2 x^2
+     + s3 x^3 (Sec. 2.2 allows any C^1 coefficients) */
+  const double *drift_c2, *drift_c3;
+  const double *sigma_c1, *sigma_c2, *sigma_c3;
 } or_graph;
+
+/* Cubic p0 + p1 x + p2 x^2 + p3 x^3 by Horner's rule; NULL higher arrays
+   count as zero, which leaves exactly fma(p1, x, p0). */
+static double coef(const double *p2, const double *p3, int32_t e, double p0, double p1,
+                   double x) {
+  const double c2 = p2 ? p2[e] : 0.0, c3 = p3 ? p3[e] : 0.0;
+  return fma(fma(fma(c3, x, c2), x, p1), x, p0);
+}
+static double drift_at(const or_graph *g, int32_t e, double x) {
+  return coef(g->drift_c2, g->drift_c3, e, g->drift_a[e], g->drift_c[e], x);
+}
+static double sigma_at(const or_graph *g, int32_t e, double x) {
+  const double s1 = g->sigma_c1 ? g->sigma_c1[e] : 0.0;
+  return coef(g->sigma_c2, g->sigma_c3, e, g->sigma[e], s1, x);
+}
 
 /*
  * Integer slot thresholds (reading: slot draw, A10 in the design doc).  Per
@@ -288,9 +308,10 @@ static void run_particle(const or_graph *g, const uint64_t *thr, uint32_t p,
          (Alg. 1; reading A3). */
       if (x == 0.0) w = fabs(w);
       else if (x == L) w = -fabs(w);
-      /* EM proposal (Alg. 2): x + mu(x) h + sigma sqrt(h) W. */
-      const double mu = fma(g->drift_c[e], x, g->drift_a[e]);
-      const double gsd = g->sigma[e] * sqrt(h);
+      /* EM proposal (Alg. 2): x + mu(x) h + sigma(x) sqrt(h) W, both
+         coefficients frozen at the sub-step's starting point. */
+      const double mu = drift_at(g, e, x);
+      const double gsd = sigma_at(g, e, x) * sqrt(h);
       const double xt = fma(gsd, w, fma(mu, h, x));
       cnt->substeps++;
       if (xt > 0.0 && xt < L) { /* strict interior test (reading A6) */

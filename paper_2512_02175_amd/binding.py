@@ -46,7 +46,10 @@ class mg_graph_desc(C.Structure):
                 ("drift_c", C.c_void_p), ("sigma", C.c_void_p),
                 ("vtx_offsets", C.c_void_p), ("slot_edge", C.c_void_p),
                 ("slot_orient", C.c_void_p), ("slot_jump_prob", C.c_void_p),
-                ("vtx_kind", C.c_void_p), ("bin_span", C.c_void_p)]
+                ("vtx_kind", C.c_void_p), ("bin_span", C.c_void_p),
+                ("drift_c2", C.c_void_p), ("drift_c3", C.c_void_p),
+                ("sigma_c1", C.c_void_p), ("sigma_c2", C.c_void_p),
+                ("sigma_c3", C.c_void_p)]
 
 
 class mg_options(C.Structure):
@@ -191,15 +194,21 @@ def mg_graph_create(desc) -> Graph:
         slot_jump_prob=np.ascontiguousarray(desc.slot_jump_prob, np.float64),
         vtx_kind=np.ascontiguousarray(desc.vtx_kind, np.uint8),
     )
-    span = getattr(desc, "bin_span", None)
-    if span is not None:
-        keep["bin_span"] = np.ascontiguousarray(span, np.float64)
+    opt = []
+    for k in ("bin_span", "drift_c2", "drift_c3", "sigma_c1", "sigma_c2", "sigma_c3"):
+        v = getattr(desc, k, None)
+        if v is None:
+            opt.append(None)
+        else:
+            keep[k] = np.ascontiguousarray(
+                np.broadcast_to(np.asarray(v, np.float64), (int(desc.n_edges),)))
+            opt.append(keep[k].ctypes.data)
     d = mg_graph_desc(int(desc.n_vertices), int(desc.n_edges),
                       *[keep[k].ctypes.data for k in (
                           "edge_init", "edge_term", "length", "drift_a", "drift_c",
                           "sigma", "vtx_offsets", "slot_edge", "slot_orient",
                           "slot_jump_prob", "vtx_kind")],
-                      keep["bin_span"].ctypes.data if span is not None else None)
+                      *opt)
     h = C.c_void_p()
     _check(lib().mg_graph_create(C.byref(d), C.byref(h)))
     return Graph(h, desc)

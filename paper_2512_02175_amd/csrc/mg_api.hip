@@ -75,6 +75,8 @@ void slot_thresholds(int32_t V, const int32_t *off, const double *b,
 }
 
 bool is_finite(double v) { return std::isfinite(v); }
+// an optional per-edge coefficient array: its entry, or 0 when absent
+double higher(const double *p, int32_t e) { return p ? p[e] : 0.0; }
 
 }  // namespace
 
@@ -90,6 +92,9 @@ struct mg_graph {
   // the vertices at infinity, which no particle reaches
   bool infinite = false;
   std::vector<uint8_t> at_infinity;  // [V]
+  // some edge has higher coefficients (mu beyond affine or sigma(x) not
+  // constant): FP64 sets only
+  bool poly = false;
   void *dev = nullptr;         // one allocation holding every table
   GraphDev gd{};
 };
@@ -128,6 +133,7 @@ struct mg_batch {
   int32_t n_items = 0;
   int32_t max_nnz = 0;
   int32_t max_stage = 0;  // staged table bytes if every set's graph fits, else 0
+  bool poly = false;      // some set's graph has higher coefficients (FP64 only)
   int32_t kernel = 1;     // FP32 schedule fixed at creation (tile size follows it)
   // Per-call set descriptors go up from pinned memory; the launch chain of a
   // call is a HIP graph of kernel nodes, re-instantiated only when the
@@ -217,6 +223,7 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   const int32_t nnz = off[V];
   if ((int64_t)nnz != 2 * (int64_t)E)
     return fail(MG_EINVAL, "nnz = %d, but every edge needs two slots (2E = %d)", nnz, 2 * E);
+  bool poly = false;  // some edge has a higher coefficient
   for (int32_t e = 0; e < E; ++e) {
     if (d->edge_init[e] < 0 || d->edge_init[e] >= V || d->edge_term[e] < 0 ||
         d->edge_term[e] >= V)
@@ -231,6 +238,38 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
                     : std::isinf(d->length[e]))
       return fail(MG_EINVAL, "edge %d: bin_span must be finite and > 0 (and given for a "
                   "semi-infinite edge)", e);
+    const double hi[5] = {higher(d->drift_c2, e), higher(d->drift_c3, e),
+                          higher(d->sigma_c1, e), higher(d->sigma_c2, e),
+                          higher(d->sigma_c3, e)};
+    bool any = false;
+    for (double h : hi) {
+      if (!is_finite(h)) return fail(MG_EINVAL, "edge %d: higher coefficient not finite", e);
+      any |= h != 0.0;
+    }
+    if (!any) continue;
+    poly = true;
+    if (std::isinf(d->length[e]))
+      return fail(MG_EINVAL, "edge %d: higher coefficients need a finite edge", e);
+    // sigma_e(x) > 0 on [0, L]: its minimum is at an end or where
+    // s1 + 2 s2 x + 3 s3 x^2 = 0
+    const double L = d->length[e], s0 = d->sigma[e], s1 = hi[2], s2 = hi[3], s3 = hi[4];
+    auto sig = [&](double x) { return ((s3 * x + s2) * x + s1) * x + s0; };
+    double crit[4] = {0.0, L, 0.0, 0.0};
+    int nc = 2;
+    if (s3 != 0.0) {
+      const double disc = 4.0 * s2 * s2 - 12.0 * s3 * s1;
+      if (disc >= 0.0) {
+        crit[nc++] = (-2.0 * s2 + std::sqrt(disc)) / (6.0 * s3);
+        crit[nc++] = (-2.0 * s2 - std::sqrt(disc)) / (6.0 * s3);
+      }
+    } else if (s2 != 0.0) {
+      crit[nc++] = -s1 / (2.0 * s2);
+    }
+    for (int i = 0; i < nc; ++i) {
+      const double x = crit[i];
+      if (x >= 0.0 && x <= L && !(sig(x) > 0.0))
+        return fail(MG_EINVAL, "edge %d: sigma(x) must be > 0 on [0, L]", e);
+    }
   }
   // every edge exactly once at each end with the right orientation
   std::vector<uint8_t> seen((size_t)E * 2, 0);
@@ -290,7 +329,9 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
     const double c = d->drift_c ? d->drift_c[e] : 0.0;
     const int32_t vi = end_id(d->edge_init[e]), vt = end_id(d->edge_term[e]);
     e64[e] = {d->length[e], a, c, d->sigma[e], vi, vt,
-              d->bin_span ? d->bin_span[e] : d->length[e]};
+              d->bin_span ? d->bin_span[e] : d->length[e],
+              higher(d->drift_c2, e), higher(d->drift_c3, e), higher(d->sigma_c1, e),
+              higher(d->sigma_c2, e), higher(d->sigma_c3, e), 0.0};
     // (a particle never measures from the far end of a semi-infinite edge)
     const double aL = std::isinf(d->length[e]) ? 0.0 : std::fma(c, d->length[e], a);
     const float scale = (float)(std::isinf(d->length[e]) ? d->bin_span[e] : d->length[e]);
@@ -362,6 +403,8 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   g->vtx_host = vtx;
   g->infinite = infinite;
   g->at_infinity = at_inf;
+  g->poly = poly;
+  g->gd.poly = poly ? 1 : 0;
   const size_t ng = guide.size();
   const size_t o_vtx = 0;
   const size_t o_sl = align_up(o_vtx + sizeof(VtxBlk) * V, 16);
@@ -445,6 +488,9 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
   if (o.steps_per_launch < 0) return fail(MG_EINVAL, "steps_per_launch must be >= 0");
   if (o.schedule < MG_SCHED_AUTO || o.schedule > MG_SCHED_POOLS_W8)
     return fail(MG_EINVAL, "unknown schedule");
+  if (g->poly && o.precision == MG_FP32)
+    return fail(MG_EINVAL, "the FP32 path takes affine drift and constant sigma: graphs "
+                "with higher coefficients need FP64 sets");
   if (mode == MG_INIT_EXPLICIT) {
     if (!edge || !pos) return fail(MG_EINVAL, "explicit init needs edge and pos");
     for (int64_t i = 0; i < n; ++i) {
@@ -972,6 +1018,7 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
     const int32_t st = sets[i]->prec == MG_FP64 ? gd.stage_bytes64 : gd.stage_bytes32;
     all_stage = all_stage && st > 0;
     b->max_stage = std::max(b->max_stage, st);
+    b->poly = b->poly || sets[i]->g->poly;
   }
   if (!all_stage) b->max_stage = 0;
   // Largest sets first so the tail of the launch is made of small tiles.
@@ -1030,7 +1077,7 @@ static hipError_t build_graph(mg_batch *b, int64_t n_steps, const StepArgs &base
     a.nsteps = (uint32_t)std::min<int64_t>(left, chunk);
     a.n0_offset = done;
     const KernelLaunch k = batch_launch(b->n_items, b->max_nnz, b->max_stage, a,
-                                        p0->prec == MG_FP64, p0->trace, b->key_obs);
+                                        p0->prec == MG_FP64, p0->trace, b->key_obs, b->poly);
     const GraphDev *g = b->d_graphs;
     const SetDev *sd = b->d_sets;
     const BatchItem *it = b->d_items;

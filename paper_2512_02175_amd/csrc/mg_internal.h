@@ -15,7 +15,7 @@ constexpr uint32_t kSideBit = 0x40000000u;
 constexpr uint32_t kDeadBit = 0x80000000u;
 constexpr int32_t kMaxEdges = 0x3FFFFFFF;
 
-// Edge record for the FP64 path: 48 bytes, one per edge.  span is the
+// Edge record for the FP64 path: 96 bytes, one per edge.  span is the
 // length the uniform histograms bin (the edge length unless the caller gave
 // another; finite on a semi-infinite edge).  The end vertex ids of both
 // records carry kMirrorEnd when that end is a mirror vertex (a reflecting
@@ -27,6 +27,10 @@ struct alignas(16) EdgeRec64 {
   double L, a, c, sigma;  // length, drift a + c x, diffusion
   int32_t vinit, vterm;   // end vertices (| kMirrorEnd at a mirror vertex)
   double span;
+  // higher terms: drift + c2 x^2 + c3 x^3, diffusion + s1 x + s2 x^2 + s3 x^3
+  // (all zero for affine drift and constant diffusion, which then evaluate
+  // to exactly the affine values)
+  double c2, c3, s1, s2, s3, pad;
 };
 
 // Edge record for the FP32 path: 32 bytes.  aL = a + c L is the drift at
@@ -82,6 +86,7 @@ struct GraphDev {
   int32_t o_vtx, o_slots, o_guide, o_e32, o_e64;
   int32_t stage_bytes32;  // vtx..e32 (FP32 kernels stage this range)
   int32_t stage_bytes64;  // vtx..guide + e64 (FP64 kernels)
+  int32_t poly;           // some edge has higher drift or diffusion terms
 };
 
 // Counters of one particle set: exit[nnz], absorbed[V], totals[4]
@@ -169,7 +174,7 @@ struct KernelLaunch {
   size_t shm;
 };
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
-                          const StepArgs &a, bool fp64, bool trace, bool obs);
+                          const StepArgs &a, bool fp64, bool trace, bool obs, bool poly);
 // tiled: edge-range LDS tiles when E * nb exceeds one LDS copy (else 64-bit
 // global atomics); below that size both take the single LDS copy.
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,

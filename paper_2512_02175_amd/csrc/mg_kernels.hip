@@ -379,7 +379,7 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
 
 // ------------------------------------------------------------ FP64 path --
 // The canonical step in FP64, operation for operation.
-template <bool TRACE, bool LDS>
+template <bool TRACE, bool LDS, bool POLY>
 struct Particle64 {
   using real = double;
   GView G;
@@ -403,13 +403,25 @@ struct Particle64 {
   __device__ __forceinline__ bool fast_first(double w) { return fast(w); }
   __device__ __forceinline__ double pos64(double) const { return x; }
 
+  // Drift and diffusion at x: affine and constant, or with POLY the cubics
+  // by Horner's rule (with zero higher terms these equal the affine values
+  // exactly).
+  __device__ __forceinline__ double drift(double at) const {
+    if (!POLY) return fma(R.c, at, R.a);
+    return fma(fma(fma(R.c3, at, R.c2), at, R.c), at, R.a);
+  }
+  __device__ __forceinline__ double diffusion(double at) const {
+    if (!POLY) return R.sigma;
+    return fma(fma(fma(R.s3, at, R.s2), at, R.s1), at, R.sigma);
+  }
+
   __device__ __forceinline__ bool fast(double w) {
     if (x == 0.0)
       w = fabs(w);
     else if (x == R.L)
       w = -fabs(w);
-    const double mu = fma(R.c, x, R.a);
-    const double g = R.sigma * sqrt(dtv);
+    const double mu = drift(x);
+    const double g = diffusion(x) * sqrt(dtv);
     const double xt = fma(g, w, fma(mu, dtv, x));
     if (xt > 0.0 && xt < R.L) {
       x = xt;
@@ -430,8 +442,8 @@ struct Particle64 {
         w = fabs(w);
       else if (x == R.L)
         w = -fabs(w);
-      const double mu = fma(R.c, x, R.a);
-      const double g = R.sigma * sqrt(h);
+      const double mu = drift(x);
+      const double g = diffusion(x) * sqrt(h);
       const double xt = fma(g, w, fma(mu, h, x));
       if (!first) t.sub++;
       first = false;
@@ -487,7 +499,7 @@ struct Particle64 {
   }
 };
 
-template <bool TRACE, bool LDS, bool OBS, int NG>
+template <bool TRACE, bool LDS, bool OBS, int NG, bool POLY>
 __device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const StepArgs &A,
                       uint32_t pid, uint32_t *s_exit, Tally &t, const ObsSink &o) {
   const uint32_t ef = S.ef[pid];
@@ -497,7 +509,7 @@ __device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const St
     atomicOr(S.err, kErrEdge);
     return;
   }
-  Particle64<TRACE, LDS> q{G, s_exit, e, S.x64[pid], G.e64[e], true,
+  Particle64<TRACE, LDS, POLY> q{G, s_exit, e, S.x64[pid], G.e64[e], true,
                            TRACE ? S.seqhash[pid] : 0ull, TRACE ? S.hits[pid] : 0u,
                            0u, A.dt};
   if (!(q.x >= 0.0 && q.x <= q.R.L)) {
@@ -882,7 +894,7 @@ __device__ __forceinline__ GView block_view(const GraphDev &G, char *smem) {
 
 __device__ __forceinline__ int32_t exit_bytes(int32_t nnz) { return ((nnz * 4) + 15) & ~15; }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool POLY>
 __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t pid,
                                            uint32_t *s_tot, char *smem) {
@@ -902,7 +914,7 @@ __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
   Tally t{0, 0, 0, 0};
   if (pid < S.n) {
     if (FP64)
-      run64<TRACE, LDS, OBS, kWindowGroups64>(view, G.E, S, A, pid, s_exit, t, o);
+      run64<TRACE, LDS, OBS, kWindowGroups64, POLY>(view, G.E, S, A, pid, s_exit, t, o);
     else
       run32<TRACE, LDS, OBS, kWindowGroups32>(view, G.E, S, A, pid, s_exit, t, o);
   }
@@ -910,15 +922,16 @@ __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
   if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
 }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS>
+// POLY (FP64 only): some edge has higher drift or diffusion terms.
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool POLY>
 __global__ __launch_bounds__(kBlock) void k_step(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  step_block<FP64, TRACE, LDS, STAGED, OBS>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
-                                            s_tot, (char *)smem4);
+  step_block<FP64, TRACE, LDS, STAGED, OBS, POLY>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
+                                                  s_tot, (char *)smem4);
 }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool POLY>
 __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
                                                   const SetDev *sets,
                                                   const BatchItem *items,
@@ -929,8 +942,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
   SetDev S = sets[it.set];
   S.n0 += A.n0_offset;  // steps already taken by earlier launches of this call
   const GraphDev G = graphs[it.set];
-  step_block<FP64, TRACE, LDS, STAGED, OBS>(G, S, A, it.first + threadIdx.x, s_tot,
-                                            (char *)smem4);
+  step_block<FP64, TRACE, LDS, STAGED, OBS, POLY>(G, S, A, it.first + threadIdx.x, s_tot,
+                                                  (char *)smem4);
 }
 
 // ------------------------------------------------ FP32 wave-pool kernel --
@@ -1354,7 +1367,7 @@ template <bool LDS, bool STAGED>
 __global__ __launch_bounds__(kBlock) void k_step32_probe(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  step_block<false, false, LDS, STAGED, false>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
+  step_block<false, false, LDS, STAGED, false, false>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
                                                s_tot, (char *)smem4);
 }
 
@@ -1672,18 +1685,26 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
     }, lp.lds_exit, lp.staged);
     return hipGetLastError();
   }
-  with_flags([&](auto L, auto T, auto O) {
-    hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
-                               decltype(O)::value>),
-                       dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
-  }, lp.lds_exit, lp.staged, obs);
+  if constexpr (FP64) {
+    with_flags([&](auto L, auto T, auto O, auto P) {
+      hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
+                                 decltype(O)::value, decltype(P)::value>),
+                         dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+    }, lp.lds_exit, lp.staged, obs, g.poly != 0);
+  } else {
+    with_flags([&](auto L, auto T, auto O) {
+      hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
+                                 decltype(O)::value, false>),
+                         dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+    }, lp.lds_exit, lp.staged, obs);
+  }
   return hipGetLastError();
 }
 
 // Batched launches keep snapshot bins in global memory (the sets differ).
 template <bool FP64, bool TRACE>
 KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
-                            const StepArgs &a, bool obs) {
+                            const StepArgs &a, bool obs, bool poly) {
   KernelLaunch k{};
   k.grid = dim3(n_items);
   k.block = dim3(kBlock);
@@ -1701,7 +1722,12 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
           k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG>;
           return;
         }
-      k.func = (const void *)k_batch<FP64, TRACE, l, t, o>;
+      if constexpr (FP64)
+        if (poly) {
+          k.func = (const void *)k_batch<FP64, TRACE, l, t, o, true>;
+          return;
+        }
+      k.func = (const void *)k_batch<FP64, TRACE, l, t, o, false>;
     }, lp.lds_exit, lp.staged, obs);
   });
   return k;
@@ -1736,12 +1762,12 @@ int32_t batch_tile(bool fp64, int32_t kernel) {
 }
 
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
-                          const StepArgs &a, bool fp64, bool trace, bool obs) {
+                          const StepArgs &a, bool fp64, bool trace, bool obs, bool poly) {
   if (fp64)
-    return trace ? batch_launch_t<true, true>(n_items, max_nnz, max_stage, a, obs)
-                 : batch_launch_t<true, false>(n_items, max_nnz, max_stage, a, obs);
-  return trace ? batch_launch_t<false, true>(n_items, max_nnz, max_stage, a, obs)
-               : batch_launch_t<false, false>(n_items, max_nnz, max_stage, a, obs);
+    return trace ? batch_launch_t<true, true>(n_items, max_nnz, max_stage, a, obs, poly)
+                 : batch_launch_t<true, false>(n_items, max_nnz, max_stage, a, obs, poly);
+  return trace ? batch_launch_t<false, true>(n_items, max_nnz, max_stage, a, obs, false)
+               : batch_launch_t<false, false>(n_items, max_nnz, max_stage, a, obs, false);
 }
 
 hipError_t launch_histogram_csr(const GraphDev &g, const SetDev &s, const int32_t *off,

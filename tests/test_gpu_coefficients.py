@@ -1,0 +1,117 @@
+"""General coefficient functions (cubic drift and diffusion, Sec. 2.2)
+through the C ABI: the FP64 path against the oracle element by element on a
+star and in the batched form, FP32 sets refused, and graph validation."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_02175_amd import binding
+    binding.lib()
+    return binding
+
+
+def _check_against_oracle(B, orc, g, p, n, steps, dt, seed, st, c):
+    r = B.mg_particles_read(p, trace=True)
+    same = r["seqhash"] == st.seqhash
+    assert same.mean() >= 0.9999, same.mean()
+    assert np.array_equal(r["edge"][same], st.edge[same])
+    assert np.array_equal(r["hits"][same], st.hits[same])
+    assert np.abs(r["x"][same] - st.x[same]).max() <= 1e-12
+    nd = int((~same).sum())
+    ex, _, tot = B.mg_exit_counts(p)
+    assert np.abs(ex.astype(np.int64) - c.exit_slot.astype(np.int64)).sum() <= 2 * steps * nd
+    if nd == 0:
+        assert int(tot[1]) == c.substeps and int(tot[2]) == c.hits
+    h = B.mg_histogram(p, 32)
+    assert np.abs(h.astype(np.int64) - orc.histogram(g, st, 32).astype(np.int64)).sum() <= 2 * nd
+
+
+def test_double_well_star_fp64_parity(B, orc):
+    """The 64-edge double-well star (cubic drift, graded diffusion), 20k
+    particles uniform by length, 1000 steps of 1e-2 in three calls: hit
+    sequences, edges, positions, counters and bins against the oracle."""
+    g = workloads.double_well_star()
+    n, steps, dt = 20_000, 1000, 1e-2
+    st = orc.init(g, n, orc.INIT_UNIFORM_LENGTH, seed=3)
+    c = orc.simulate(g, st, 0, steps, dt, 14)
+    G = B.mg_graph_create(g)
+    p = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=3,
+                            precision=B.MG_FP64, trace=True)
+    for k in (1, 499, 500):
+        B.mg_simulate(p, k, dt, 14)
+    _check_against_oracle(B, orc, g, p, n, steps, dt, 14, st, c)
+
+
+def test_cubic_segment_and_batch_fp64(B, orc):
+    """A segment with cubic drift and diffusion (the oracle's stationary
+    pin's coefficients) against the oracle, and a batch of it with an affine
+    star equal to the sets run alone."""
+    g = workloads.segment(2.0, 12.0, -44.0, 1.0)
+    g.drift_c2, g.drift_c3 = [48.0], [-16.0]
+    g.sigma_c1, g.sigma_c2, g.sigma_c3 = [0.3], [-0.1], [0.02]
+    n, steps, dt = 20_000, 600, 1e-3
+    st = orc.init(g, n, orc.INIT_UNIFORM_LENGTH, seed=7)
+    c = orc.simulate(g, st, 0, steps, dt, 5)
+    G = B.mg_graph_create(g)
+    p = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=7,
+                            precision=B.MG_FP64, trace=True)
+    B.mg_simulate(p, steps, dt, 5)
+    _check_against_oracle(B, orc, g, p, n, steps, dt, 5, st, c)
+    star = workloads.star_graph(3, [1.0, 2.0, 0.5], [0.5, -1.0, 0.0], [-2.0, 0.3, 1.0], 1.2)
+    Gs = B.mg_graph_create(star)
+    pa = [B.mg_particles_init(G, 3000, B.MG_INIT_UNIFORM_LENGTH, init_seed=1,
+                              precision=B.MG_FP64, trace=True),
+          B.mg_particles_init(Gs, 2000, B.MG_INIT_UNIFORM_LENGTH, init_seed=2,
+                              precision=B.MG_FP64, trace=True, graph_tag=1)]
+    pb = [B.mg_particles_init(G, 3000, B.MG_INIT_UNIFORM_LENGTH, init_seed=1,
+                              precision=B.MG_FP64, trace=True),
+          B.mg_particles_init(Gs, 2000, B.MG_INIT_UNIFORM_LENGTH, init_seed=2,
+                              precision=B.MG_FP64, trace=True, graph_tag=1)]
+    b = B.mg_batch_create(pb)
+    B.mg_batch_simulate(b, 200, 1e-3, 9)
+    for q in pa:
+        B.mg_simulate(q, 200, 1e-3, 9)
+    for qa, qb in zip(pa, pb):
+        ra, rb = B.mg_particles_read(qa, trace=True), B.mg_particles_read(qb, trace=True)
+        for f in ("edge", "x", "seqhash", "hits"):
+            assert np.array_equal(ra[f], rb[f]), f
+        for x, y in zip(B.mg_exit_counts(qa), B.mg_exit_counts(qb)):
+            assert np.array_equal(x, y)
+
+
+def test_coefficient_validation(B):
+    """FP32 sets are refused on graphs with higher terms; sigma(x) must stay
+    positive on the whole edge (an interior zero is caught); higher terms
+    need finite edges and finite values; zero higher terms are affine."""
+    g = workloads.double_well_star(8)
+    G = B.mg_graph_create(g)
+    with pytest.raises(B.MgError):
+        B.mg_particles_init(G, 100, B.MG_INIT_UNIFORM_LENGTH, precision=B.MG_FP32)
+    bad = workloads.segment(2.0, 0.0, 0.0, 1.0)
+    bad.sigma_c1, bad.sigma_c2 = [-4.0], [4.0]  # (1 - 2x)^2, zero at 0.5
+    with pytest.raises(B.MgError):
+        B.mg_graph_create(bad)
+    bad.sigma_c1, bad.sigma_c2, bad.sigma_c3 = [0.0], [-3.0], [1.0]  # 1 - 3x^2 + x^3 < 0 at 1
+    with pytest.raises(B.MgError):
+        B.mg_graph_create(bad)
+    inf = workloads.from_edges(2, [0], [1], [np.inf], [0.0], [0.0], 1.0, bin_span=2.0)
+    inf.drift_c2 = [0.1]
+    with pytest.raises(B.MgError):
+        B.mg_graph_create(inf)
+    nan = workloads.segment(1.0)
+    nan.drift_c3 = [np.nan]
+    with pytest.raises(B.MgError):
+        B.mg_graph_create(nan)
+    ok = workloads.segment(1.0)
+    ok.drift_c2 = ok.drift_c3 = ok.sigma_c1 = ok.sigma_c2 = ok.sigma_c3 = [0.0]
+    B.mg_particles_init(B.mg_graph_create(ok), 100, B.MG_INIT_UNIFORM_LENGTH,
+                        precision=B.MG_FP32)

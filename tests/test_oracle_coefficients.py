@@ -1,0 +1,100 @@
+"""Pins of the oracle's general coefficient functions (Sec. 2.2 allows any
+C^1 drift and diffusion; the scheme freezes both at each sub-step's start,
+Alg. 2): cubic drift mu_e(x) and cubic diffusion sigma_e(x)."""
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+import workloads
+
+# mu(x) = -V'(x) for V = 4 ((x - 0.5)(x - 1.5))^2, wells at 0.5 and 1.5
+MU = (12.0, -44.0, 48.0, -16.0)
+# sigma(x) = 1 + 0.3 x - 0.1 x^2 + 0.02 x^3 (>= 1 on [0, 2])
+SIG = (1.0, 0.3, -0.1, 0.02)
+TV_TOL = 0.02
+
+
+def _power(coef, x):
+    """sum_j coef[j] x^j written out as powers (not Horner's rule)."""
+    return sum(c * x ** j for j, c in enumerate(coef))
+
+
+def _segment(L, mu, sig):
+    g = workloads.segment(L, mu[0], mu[1], sig[0])
+    g.drift_c2, g.drift_c3 = [mu[2]], [mu[3]]
+    g.sigma_c1, g.sigma_c2, g.sigma_c3 = [sig[1]], [sig[2]], [sig[3]]
+    return g
+
+
+@pytest.mark.parametrize("x0", [2.0, 5.0])
+def test_one_step_gaussian_with_frozen_coefficients(orc, x0):
+    """Far from the vertices one step is x0 + mu(x0) dt + sigma(x0) sqrt(dt)
+    Z exactly: KS against that normal law, with mu and sigma summed as plain
+    powers.  Every term moves the law by several KS critical values."""
+    mu = (0.3, -0.5, 0.2, -0.05)
+    sig = (1.0, 0.1, 0.05, -0.004)
+    g = _segment(100.0, mu, sig)
+    N, dt = 200_000, 0.05
+    st = orc.init(g, N, orc.INIT_EXPLICIT, edge=np.zeros(N), pos=np.full(N, x0))
+    c = orc.simulate(g, st, 0, 1, dt, 3)
+    assert c.hits == 0
+    m = x0 + _power(mu, x0) * dt
+    s = _power(sig, x0) * np.sqrt(dt)
+    ks = stats.kstest(st.x, stats.norm(m, s).cdf)
+    assert ks.pvalue > 1e-4, ks
+    # the pinned moments, as a sharper check of the same law
+    assert abs(st.x.mean() - m) < 5 * s / np.sqrt(N)
+    assert abs(st.x.std() / s - 1.0) < 5 / np.sqrt(2 * N)
+
+
+def test_stationary_law_with_cubic_drift_and_diffusion(orc):
+    """A segment [0, 2] with plain reflecting leaves, double-well drift and
+    a cubic diffusion: the Ito diffusion's stationary density is
+    exp(int_0^x 2 mu / sigma^2) / sigma^2 (zero flux), integrated here by
+    quadrature.  Started from that law, time-averaged bin masses stay
+    within the Monte-Carlo and time-step error (total variation)."""
+    L, nb = 2.0, 40
+    g = _segment(L, MU, SIG)
+
+    def dens(x):
+        phi = integrate.quad(lambda y: 2 * _power(MU, y) / _power(SIG, y) ** 2, 0, x)[0]
+        return np.exp(phi) / _power(SIG, x) ** 2
+    edges = np.linspace(0, L, nb + 1)
+    mass = np.array([integrate.quad(dens, a, b)[0] for a, b in zip(edges[:-1], edges[1:])])
+    mass /= mass.sum()
+    # initial positions drawn from that law (inverse CDF on a fine grid)
+    grid = np.linspace(0, L, 4001)
+    pdf = np.array([dens(x) for x in grid])
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (pdf[1:] + pdf[:-1]) * np.diff(grid))])
+    cdf /= cdf[-1]
+    N = 20_000
+    u = np.random.default_rng(4).uniform(size=N)
+    x0 = np.interp(u, cdf, grid)
+    st = orc.init(g, N, orc.INIT_EXPLICIT, edge=np.zeros(N), pos=x0)
+    dt, n0 = 1e-3, 0
+    acc = np.zeros(nb)
+    for _ in range(6):
+        orc.simulate(g, st, n0, 300, dt, 8)
+        n0 += 300
+        acc += orc.histogram(g, st, nb).astype(np.float64).ravel()
+    emp = acc / acc.sum()
+    tv = 0.5 * np.abs(emp - mass).sum()
+    # (dropping sigma's linear term moves the law by TV 0.14, a constant
+    # sigma by 0.066; the cubic terms are pinned by the one-step law)
+    assert tv < TV_TOL, tv
+
+
+def test_zero_higher_terms_are_the_affine_step(orc):
+    """Explicit zero higher terms give bit for bit the run without them
+    (the cubics collapse to fma(c, x, a) and sigma)."""
+    g0 = workloads.star_graph(3, [1.0, 2.0, 0.5], [0.5, -1.0, 0.0], [-2.0, 0.3, 1.0], 1.2)
+    g1 = workloads.star_graph(3, [1.0, 2.0, 0.5], [0.5, -1.0, 0.0], [-2.0, 0.3, 1.0], 1.2)
+    z = np.zeros(3)
+    g1.drift_c2 = g1.drift_c3 = g1.sigma_c1 = g1.sigma_c2 = g1.sigma_c3 = z
+    out = []
+    for g in (g0, g1):
+        st = orc.init(g, 5000, orc.INIT_UNIFORM_LENGTH, seed=1)
+        orc.simulate(g, st, 0, 300, 1e-2, 2)
+        out.append(st)
+    assert np.array_equal(out[0].x, out[1].x)
+    assert np.array_equal(out[0].seqhash, out[1].seqhash)

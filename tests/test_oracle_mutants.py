@@ -23,19 +23,20 @@ INV = "tests/test_oracle_invariants.py::"
 SEQ = "tests/test_oracle_split_sequences.py::"
 SRCS = "tests/test_oracle_sources.py::"
 MIR = "tests/test_oracle_mirror.py::"
+COEF = "tests/test_oracle_coefficients.py::"
 
 MUTANTS = {
     "drift_sign": (
-        [("const double mu = fma(g->drift_c[e], x, g->drift_a[e]);",
-          "const double mu = -fma(g->drift_c[e], x, g->drift_a[e]);")],
+        [("const double mu = drift_at(g, e, x);",
+          "const double mu = -drift_at(g, e, x);")],
         CF + "test_linear_drift_ar1_law"),
     "drift_uses_full_dt": (
         [("const double xt = fma(gsd, w, fma(mu, h, x));",
           "const double xt = fma(gsd, w, fma(mu, dt, x));")],
         CF + "test_exit_law_matches_renewal_equation"),
     "diffusion_uses_full_dt": (
-        [("const double gsd = g->sigma[e] * sqrt(h);",
-          "const double gsd = g->sigma[e] * sqrt(dt);")],
+        [("const double gsd = sigma_at(g, e, x) * sqrt(h);",
+          "const double gsd = sigma_at(g, e, x) * sqrt(dt);")],
         CF + "test_exit_law_matches_renewal_equation"),
     "remaining_time_uses_u": (
         [("h = fma(-alpha, h, h);", "h = fma(-u, h, h);")],
@@ -96,6 +97,17 @@ MUTANTS = {
         [("const int32_t s = pick_slot(g, thr, v, o[1]);",
           "const int32_t s = pick_slot(g, thr, v, o[0]);")],
         SRCS + "test_sources_law"),
+    "drift_cubic_term_dropped": (
+        [("return coef(g->drift_c2, g->drift_c3, e, g->drift_a[e], g->drift_c[e], x);",
+          "return coef(g->drift_c2, NULL, e, g->drift_a[e], g->drift_c[e], x);")],
+        COEF + "test_one_step_gaussian_with_frozen_coefficients"),
+    "sigma_frozen_at_edge_start": (
+        [("const double gsd = sigma_at(g, e, x) * sqrt(h);",
+          "const double gsd = sigma_at(g, e, 0.0) * sqrt(h);")],
+        COEF + "test_one_step_gaussian_with_frozen_coefficients"),
+    "sigma_linear_term_dropped": (
+        [("const double s1 = g->sigma_c1 ? g->sigma_c1[e] : 0.0;", "const double s1 = 0.0;")],
+        COEF + "test_stationary_law_with_cubic_drift_and_diffusion"),
     "mirror_skipped": (
         [("if (g->vtx_kind && g->vtx_kind[v] == 2) {", "if (0) {")],
         MIR + "test_one_step_is_the_folded_normal"),

@@ -23,6 +23,9 @@ Graph description (same fields as the C-ABI ``mg_graph_desc``):
   at infinity of its own (one slot, never reached).
 * ``bin_span[e]`` (optional): the length of e the uniform histograms cover
   (default the edge length; required for a semi-infinite edge).
+* ``drift_c2``, ``drift_c3``, ``sigma_c1``, ``sigma_c2``, ``sigma_c3``
+  (optional): higher terms of the coefficient functions, mu_e(x) = a + c x +
+  c2 x^2 + c3 x^3 and sigma_e(x) = sigma + s1 x + s2 x^2 + s3 x^3.
 """
 from __future__ import annotations
 
@@ -54,6 +57,13 @@ class GraphDesc:
     vtx_kind: np.ndarray
     bin_span: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
+    # higher coefficient terms (None: zero): mu = a + c x + c2 x^2 + c3 x^3,
+    # sigma(x) = sigma + s1 x + s2 x^2 + s3 x^3
+    drift_c2: np.ndarray | None = None
+    drift_c3: np.ndarray | None = None
+    sigma_c1: np.ndarray | None = None
+    sigma_c2: np.ndarray | None = None
+    sigma_c3: np.ndarray | None = None
 
     @property
     def nnz(self) -> int:
@@ -200,6 +210,33 @@ def paper_star5(potential: str = "linear", length: float = 2.0,
                       meta={"name": f"paper_star5_{potential}"},
                       bin_span=min(float(length), float(bin_span)),
                       leaf_kind=leaf_kind)
+
+
+def double_well_star(n_edges: int = 64, seed: int = 6) -> GraphDesc:
+    """Star with non-affine coefficients on every edge: L ~ U[0.5, 2], a
+    double-well potential V_e(x) = h_e ((x - p_e)(x - q_e))^2 / L_e^4 with
+    wells at p_e = L/4 and q_e = 3L/4 and h_e ~ U[1, 4], drift mu_e = -V_e'
+    (a cubic), and a graded diffusion sigma_e(x) = sqrt(2) (1 + g_e x / L_e)
+    with g_e ~ U[-0.3, 0.5]; uniform jump probabilities at the centre."""
+    rng = np.random.default_rng(seed)
+    E = int(n_edges)
+    L = rng.uniform(0.5, 2.0, size=E)
+    h = rng.uniform(1.0, 4.0, size=E)
+    gr = rng.uniform(-0.3, 0.5, size=E)
+    p, q = 0.25 * L, 0.75 * L
+    # V = h/L^4 (x^2 - s x + t)^2 with s = p + q, t = p q, so
+    # -V' = -(2h/L^4)(x^2 - s x + t)(2x - s)
+    k = 2.0 * h / L ** 4
+    sm, t = p + q, p * q
+    c3 = -k * 2.0
+    c2 = -k * (-3.0 * sm)
+    c1 = -k * (2.0 * t + sm * sm)
+    c0 = -k * (-sm * t)
+    sig = np.sqrt(2.0)
+    g = star_graph(E, L, c0, c1, sig, meta={"name": f"double_well_star{E}"})
+    g.drift_c2, g.drift_c3 = c2, c3
+    g.sigma_c1 = sig * gr / L
+    return g
 
 
 def csr_bins(g: GraphDesc, width: float, n_finite: int):
