@@ -44,12 +44,16 @@ ALG_FP64_HIT = 130.0
 # cubic drift and diffusion: two Horner steps more for mu and three for
 # sigma at every sub-step start (a step, or a restart from a vertex)
 ALG_FP64_CUBIC = 5.0
+# FP32 with cubic coefficients: the frame position (select, subtraction),
+# both cubics (6 fma), the frame sign (2 selects), sigma sqrt(dt) and the
+# drift times dt (2 multiplies), against the per-frame constants' 2 fma
+ALG_FP32_CUBIC = 10.0
 
 
 # HBM bytes per k_pool32 launch on this workload from the FETCH_SIZE and
 # WRITE_SIZE counter passes (scaled by a 1 GiB copy), valid for the kernel
 # source whose sha256 prefix is given; reported as null for any other build.
-TRAFFIC = {"kernel_sha256": "5192e2c355655e81", "bytes_per_launch": 321.1e6}
+TRAFFIC = {"kernel_sha256": "f4a45f4a09b7a08e", "bytes_per_launch": 321.3e6}
 
 
 def kernel_traffic():
@@ -469,18 +473,18 @@ def run_nohit(args, B, torch):
 
 
 def run_double_well(args, B, torch):
-    """General coefficients on the FP64 path: the 64-edge double-well star
-    (cubic drift, graded diffusion), 1e7 particles uniform by length, 1e4
-    steps at dt = 1e-3."""
+    """General coefficients: the 64-edge double-well star (cubic drift,
+    graded diffusion), 1e7 particles uniform by length, 1e4 steps at
+    dt = 1e-3.  FP32 (lane schedule) is the value; FP64 is timed beside it
+    and compared under common random numbers."""
     import numpy as np
     import workloads
     g = workloads.double_well_star(64)
     G = B.mg_graph_create(g)
-    n, steps, dt = 10_000_000, 10_000, 1e-3
-    ktimes, walls, res = [], [], None
-    for it in range(args.warmup + args.steps):
-        p = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=0,
-                                precision=B.MG_FP64)
+    n, steps, dt, bins = 10_000_000, 10_000, 1e-3, 64
+
+    def one(prec):
+        p = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=0, precision=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -488,33 +492,46 @@ def run_double_well(args, B, torch):
         e0.record()
         B.mg_simulate(p, steps, dt, 0)
         e1.record()
-        tot = B.mg_exit_counts(p)[2]
-        hist = B.mg_histogram(p, 64)
+        ex, _, tot = B.mg_exit_counts(p)
+        hist = B.mg_histogram(p, bins)
         wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) * 1e-3, wall, tot, ex, hist
+
+    ktimes, walls, res = [], [], None
+    for it in range(args.warmup + args.steps):
+        k, w, tot, ex, hist = one(B.MG_FP32)
         if it >= args.warmup:
-            ktimes.append(e0.elapsed_time(e1) * 1e-3)
-            walls.append(wall)
-            res = tot
-        del p
+            ktimes.append(k)
+            walls.append(w)
+            res = (tot, ex, hist)
+    k64, w64, tot64, ex64, hist64 = one(B.MG_FP64)
+    tot, ex, hist = res
     k = float(np.mean(ktimes))
-    work = ((ALG_FP64_STEP + ALG_FP64_CUBIC) * float(res[3])
-            + (ALG_FP64_HIT + ALG_FP64_CUBIC) * float(res[2]))
+    per_step = ALG_FP32_STEP + ALG_FP32_CUBIC
+    work = per_step * float(tot[3]) + (ALG_FP32_HIT + ALG_FP32_CUBIC) * float(tot[2])
     achieved = work / k
-    return {"metric": METRIC, "value": float(res[1]) / float(np.mean(walls)),
+    value = float(tot[1]) / float(np.mean(walls))
+    tv = 0.5 * float(np.abs(hist.astype(float) - hist64.astype(float)).sum()) / float(hist64.sum())
+    return {"metric": METRIC, "value": value,
             "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": float(np.mean(walls)) * 1e3,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": "double_well_star64: 64-edge star, cubic drift -V' of a "
                                    "double-well potential per edge, graded sigma(x), 1e7 "
-                                   "particles uniform by length, 1e4 steps at dt=1e-3, FP64"},
-            "hits_per_step": float(res[2]) / float(res[3]),
-            "histogram_mass": int(hist.sum()),
+                                   "particles uniform by length, 1e4 steps at dt=1e-3"},
+            "hits_per_step": float(tot[2]) / float(tot[3]),
+            "fp64": {"value": float(tot64[1]) / w64, "unit": "particle-substeps/s",
+                     "fp32_speedup": value / (float(tot64[1]) / w64),
+                     "kernel_ms_per_call": k64 * 1e3},
+            "tv_fp32_vs_fp64": tv,
+            "exit_prob_err_fp32_vs_fp64": exit_err(ex, ex64, g.vtx_offsets)[0],
             "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                          "peak": PEAK_LANE_OPS / 1e12, "unit": "T VALU lane-ops/s",
                          "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                         "kernel": "k_step<fp64, cubic coefficients>",
-                         "kernel_ms_per_call": k * 1e3}}
+                         "kernel": "k_step<fp32, cubic coefficients>",
+                         "kernel_ms_per_call": k * 1e3,
+                         "alg_lane_ops_per_particle_step": per_step}}
 
 
 def run_tracer(args, B, torch):

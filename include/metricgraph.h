@@ -101,8 +101,11 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *                        coefficients (Sec. 2.2); cubics cover double-well
  *                        potentials and graded diffusivities.  Each sub-step
  *                        freezes both at its starting point (Euler-Maruyama,
- *                        Alg. 2).  Nonzero higher terms need finite edges and
- *                        FP64 sets: an FP32 set on such a graph is refused.
+ *                        Alg. 2).  Nonzero higher terms need finite edges;
+ *                        FP32 sets on such a graph run the lane schedule
+ *                        (MG_SCHED_AUTO or MG_SCHED_LANES; a pool schedule is
+ *                        refused), and a batch cannot mix them with sets on
+ *                        affine graphs unless those ask for MG_SCHED_LANES.
  * Every edge must appear exactly once at its initial vertex with orient 0
  * and once at its terminal vertex with orient 1 (a self-loop twice at its
  * vertex).  A standard vertex needs at least one slot with b > 0.

@@ -178,10 +178,12 @@ struct GView {
   const int32_t *guide;
   const EdgeRec32 *e32;
   const EdgeRec64 *e64;
+  const EdgeRec64 *hi64;  // global FP64 records: the FP32 path reads the
+                          // higher coefficient terms from them
 };
 
 __device__ __forceinline__ GView global_view(const GraphDev &G) {
-  return {G.vtx, G.slots, G.guide, G.e32, G.e64};
+  return {G.vtx, G.slots, G.guide, G.e32, G.e64, G.e64};
 }
 
 struct SlotPick {
@@ -558,7 +560,10 @@ struct Hit32 {
   int32_t k, last;
 };
 
-template <bool TRACE, bool LDS>
+// POLY: the graph has higher coefficient terms (cubic drift or diffusion);
+// the first sub-step then evaluates them at the particle's position instead
+// of using the per-frame affine constants.
+template <bool TRACE, bool LDS, bool POLY = false>
 struct Particle32 {
   using real = float;
   GView G;
@@ -577,6 +582,9 @@ struct Particle32 {
   // g0 with the frame's sign, so that a first sub-step is
   // y + fma(gs, w, fma(cd, y, ad)) with no per-step sign select.
   float cd = 0.0f, ad = 0.0f, gs = 0.0f;
+  // Higher terms of the current edge (POLY), x from the initial vertex:
+  // drift + c2 x^2 + c3 x^3, diffusion + s1 x + s2 x^2 + s3 x^3.
+  float c2 = 0.0f, c3 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 
   // Sets as, g0 and the first sub-step constants for the current edge R and
   // side (after an edge load or a change of reference end).
@@ -586,6 +594,34 @@ struct Particle32 {
     cd = R.c * dt;
     ad = as * dt;
     gs = side ? -g0 : g0;
+    if constexpr (POLY) {
+      const EdgeRec64 &P = G.hi64[e];
+      c2 = (float)P.c2;
+      c3 = (float)P.c3;
+      s1 = (float)P.s1;
+      s2 = (float)P.s2;
+      s3 = (float)P.s3;
+    }
+  }
+
+  // Drift in the frame (sign of the reference end) and diffusion at
+  // distance yy from the reference end.
+  __device__ __forceinline__ float fdrift(float yy) const {
+    if constexpr (!POLY) {
+      return fmaf(R.c, yy, as);
+    } else {
+      const float x = side ? R.L - yy : yy;
+      const float m = fmaf(fmaf(fmaf(c3, x, c2), x, R.c), x, R.a);
+      return side ? -m : m;
+    }
+  }
+  __device__ __forceinline__ float fsigma(float yy) const {
+    if constexpr (!POLY) {
+      return R.sigma;
+    } else {
+      const float x = side ? R.L - yy : yy;
+      return fmaf(fmaf(fmaf(s3, x, s2), x, s1), x, R.sigma);
+    }
   }
 
   __device__ static void box_muller(uint32_t a, uint32_t b, float &c, float &s) {
@@ -631,7 +667,12 @@ struct Particle32 {
   // A step's first sub-step over dt with normal w; w must already be
   // at_vertex(w) when y = 0.  Returns the proposal and its compensation.
   __device__ __forceinline__ float propose(float w, float &err) const {
-    return add_comp(fmaf(gs, w, fmaf(cd, y, ad)) + yl, err);
+    if constexpr (!POLY) {
+      return add_comp(fmaf(gs, w, fmaf(cd, y, ad)) + yl, err);
+    } else {
+      const float sg = fsigma(y) * sqdt;
+      return add_comp(fmaf(side ? -sg : sg, w, fdrift(y) * dt) + yl, err);
+    }
   }
 
   // Window preparation of the step loop: the first active step of a window
@@ -694,9 +735,10 @@ struct Particle32 {
     // the pending proposal, recomputed as it was made
     // (the first sub-step's exactly as propose() made it: g0 we = gs w)
     const float we = (y == 0.0f) ? fabsf(h.w) : (side ? -h.w : h.w);
-    const float mu = fmaf(R.c, y, as);
-    const float g = h.k == 0 ? g0 : R.sigma * __builtin_amdgcn_sqrtf(hh);
-    const float mdt = h.k == 0 ? fmaf(cd, y, ad) : mu * hh;
+    const float mu = fdrift(y);
+    const float g = h.k == 0 ? (POLY ? fsigma(y) * sqdt : g0)
+                             : fsigma(y) * __builtin_amdgcn_sqrtf(hh);
+    const float mdt = h.k == 0 ? (POLY ? mu * dt : fmaf(cd, y, ad)) : mu * hh;
     float err;
     const float yt = add_comp(fmaf(g, we, mdt) + yl, err);
     const bool near = yt <= 0.0f;
@@ -729,8 +771,8 @@ struct Particle32 {
         // crossing solve in FP64 next to the vertex (on the vertex itself,
         // d = 0, the root is -B/A: one division, no cancellation)
         const double hd = (double)hh + (double)hl;
-        const double mud = fma((double)R.c, (double)y, (double)as);
-        const double gd = (double)R.sigma * sqrt(hd);
+        const double mud = POLY ? (double)mu : fma((double)R.c, (double)y, (double)as);
+        const double gd = (double)fsigma(y) * sqrt(hd);
         const double qa = near ? mud * hd : -(mud * hd);
         const double qb = near ? gd * (double)we : -(gd * (double)we);
         const double yd = (double)y + (double)yl;
@@ -784,8 +826,8 @@ struct Particle32 {
       if (!done) {
         // the next sub-step, from the vertex (normal folded into the edge)
         h.w = box_muller32_cos(hd.y, hd.z);
-        const float mu2 = fmaf(R.c, y, as);
-        const float g2 = R.sigma * __builtin_amdgcn_sqrtf(hh);
+        const float mu2 = fdrift(y);
+        const float g2 = fsigma(y) * __builtin_amdgcn_sqrtf(hh);
         float err2;
         const float yt2 = add_comp(fmaf(g2, fabsf(h.w), mu2 * hh) + yl, err2);
         t.sub++;
@@ -808,7 +850,7 @@ struct Particle32 {
   }
 };
 
-template <bool TRACE, bool LDS, bool OBS, int NG>
+template <bool TRACE, bool LDS, bool OBS, int NG, bool POLY>
 __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const StepArgs &A,
                       uint32_t pid, uint32_t *s_exit, Tally &t, const ObsSink &o) {
   const uint32_t ef = S.ef[pid];
@@ -822,7 +864,7 @@ __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const St
   const Edge32 R = load_edge32(G.e32, e);
   const uint32_t side = (ef & kSideBit) ? 1u : 0u;
   const float2 yy = S.y32[pid];
-  Particle32<TRACE, LDS> q{G, s_exit, e, side, yy.x, yy.y, R,
+  Particle32<TRACE, LDS, POLY> q{G, s_exit, e, side, yy.x, yy.y, R,
                            side ? -R.aL : R.a, R.sigma * sqdt, (float)A.dt, sqdt, true,
                            TRACE ? S.seqhash[pid] : 0ull, TRACE ? S.hits[pid] : 0u, 0u};
   q.frame();
@@ -889,6 +931,7 @@ __device__ __forceinline__ GView block_view(const GraphDev &G, char *smem) {
   v.guide = (const int32_t *)(smem + G.o_guide);
   v.e32 = (const EdgeRec32 *)(smem + head);
   v.e64 = (const EdgeRec64 *)(smem + head);
+  v.hi64 = G.e64;
   return v;
 }
 
@@ -916,13 +959,13 @@ __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
     if (FP64)
       run64<TRACE, LDS, OBS, kWindowGroups64, POLY>(view, G.E, S, A, pid, s_exit, t, o);
     else
-      run32<TRACE, LDS, OBS, kWindowGroups32>(view, G.E, S, A, pid, s_exit, t, o);
+      run32<TRACE, LDS, OBS, kWindowGroups32, POLY>(view, G.E, S, A, pid, s_exit, t, o);
   }
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
   if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
 }
 
-// POLY (FP64 only): some edge has higher drift or diffusion terms.
+// POLY: some edge has higher drift or diffusion terms (FP32: lane schedule only).
 template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool POLY>
 __global__ __launch_bounds__(kBlock) void k_step(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
@@ -1644,7 +1687,7 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
                          hipStream_t st) {
   StepArgs a = a0;
   const bool obs = s.obs != nullptr;
-  if (!FP64 && a.kernel >= 1) {
+  if (!FP64 && a.kernel >= 1 && !g.poly) {
     with_pool(a.kernel, [&](auto PWc, auto NGc) {
       constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
       const int32_t stage = g.stage_bytes32;
@@ -1685,19 +1728,11 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
     }, lp.lds_exit, lp.staged);
     return hipGetLastError();
   }
-  if constexpr (FP64) {
-    with_flags([&](auto L, auto T, auto O, auto P) {
-      hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
-                                 decltype(O)::value, decltype(P)::value>),
-                         dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
-    }, lp.lds_exit, lp.staged, obs, g.poly != 0);
-  } else {
-    with_flags([&](auto L, auto T, auto O) {
-      hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
-                                 decltype(O)::value, false>),
-                         dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
-    }, lp.lds_exit, lp.staged, obs);
-  }
+  with_flags([&](auto L, auto T, auto O, auto P) {
+    hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
+                               decltype(O)::value, decltype(P)::value>),
+                       dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+  }, lp.lds_exit, lp.staged, obs, g.poly != 0);
   return hipGetLastError();
 }
 
@@ -1708,7 +1743,7 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
   KernelLaunch k{};
   k.grid = dim3(n_items);
   k.block = dim3(kBlock);
-  const bool pools = !FP64 && a.kernel >= 1;
+  const bool pools = !FP64 && a.kernel >= 1 && !poly;
   with_pool(a.kernel, [&](auto PWc, auto NGc) {
     constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
     const LdsPlan lp = plan_lds(max_nnz, max_stage,
@@ -1722,11 +1757,10 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
           k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG>;
           return;
         }
-      if constexpr (FP64)
-        if (poly) {
-          k.func = (const void *)k_batch<FP64, TRACE, l, t, o, true>;
-          return;
-        }
+      if (poly) {
+        k.func = (const void *)k_batch<FP64, TRACE, l, t, o, true>;
+        return;
+      }
       k.func = (const void *)k_batch<FP64, TRACE, l, t, o, false>;
     }, lp.lds_exit, lp.staged, obs);
   });
@@ -1766,8 +1800,8 @@ KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
   if (fp64)
     return trace ? batch_launch_t<true, true>(n_items, max_nnz, max_stage, a, obs, poly)
                  : batch_launch_t<true, false>(n_items, max_nnz, max_stage, a, obs, poly);
-  return trace ? batch_launch_t<false, true>(n_items, max_nnz, max_stage, a, obs, false)
-               : batch_launch_t<false, false>(n_items, max_nnz, max_stage, a, obs, false);
+  return trace ? batch_launch_t<false, true>(n_items, max_nnz, max_stage, a, obs, poly)
+               : batch_launch_t<false, false>(n_items, max_nnz, max_stage, a, obs, poly);
 }
 
 hipError_t launch_histogram_csr(const GraphDev &g, const SetDev &s, const int32_t *off,
