@@ -102,10 +102,11 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *                        potentials and graded diffusivities.  Each sub-step
  *                        freezes both at its starting point (Euler-Maruyama,
  *                        Alg. 2).  Nonzero higher terms need finite edges;
- *                        FP32 sets on such a graph run the lane schedule
- *                        (MG_SCHED_AUTO or MG_SCHED_LANES; a pool schedule is
- *                        refused), and a batch cannot mix them with sets on
- *                        affine graphs unless those ask for MG_SCHED_LANES.
+ *                        FP32 sets on such a graph run MG_SCHED_POOLS_W8
+ *                        (MG_SCHED_AUTO's choice, no probing) or
+ *                        MG_SCHED_LANES; the other pool schedules are
+ *                        refused, and a batch mixes them with sets on affine
+ *                        graphs only on a schedule all of them take.
  * Every edge must appear exactly once at its initial vertex with orient 0
  * and once at its terminal vertex with orient 1 (a self-loop twice at its
  * vertex).  A standard vertex needs at least one slot with b > 0.

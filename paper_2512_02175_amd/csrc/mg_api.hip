@@ -488,9 +488,10 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
   if (o.steps_per_launch < 0) return fail(MG_EINVAL, "steps_per_launch must be >= 0");
   if (o.schedule < MG_SCHED_AUTO || o.schedule > MG_SCHED_POOLS_W8)
     return fail(MG_EINVAL, "unknown schedule");
-  if (g->poly && o.precision == MG_FP32 && o.schedule != MG_SCHED_AUTO &&
-      o.schedule != MG_SCHED_LANES)
-    return fail(MG_EINVAL, "graphs with higher coefficients run the FP32 lane schedule only");
+  if (g->poly && o.precision == MG_FP32 &&
+      (o.schedule == MG_SCHED_POOLS || o.schedule == MG_SCHED_POOLS256))
+    return fail(MG_EINVAL, "graphs with higher coefficients run the FP32 lane schedule or "
+                "MG_SCHED_POOLS_W8 only");
   if (mode == MG_INIT_EXPLICIT) {
     if (!edge || !pos) return fail(MG_EINVAL, "explicit init needs edge and pos");
     for (int64_t i = 0; i < n; ++i) {
@@ -680,8 +681,9 @@ static int32_t schedule_of(int32_t kernel) {
 // schedule at the hit rates of config 2, the vascular network and the
 // batch of config 4).
 static int32_t fp32_kernel(const mg_particles *p) {
-  // the wave pools take affine coefficients only (FP64 sets ignore this)
-  if (p->g->poly && p->prec == MG_FP32) return 0;
+  // cubic coefficients: the lane schedule or pools of 128 with 8-step
+  // windows (FP64 sets ignore this)
+  if (p->g->poly && p->prec == MG_FP32) return p->schedule == MG_SCHED_LANES ? 0 : 3;
   if (p->schedule != MG_SCHED_AUTO) return kernel_of(p->schedule);
   return p->tuned ? p->tuned_kernel : 3;
 }
@@ -1157,7 +1159,16 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   if (!p) return fail(MG_EINVAL, "particles is NULL");
   if (!is_finite(dt) || !(dt > 0.0)) return fail(MG_EINVAL, "dt must be finite and > 0");
   mg_tuning res{};
-  if (p->prec == MG_FP64 || p->g->poly) {
+  if (p->prec == MG_FP32 && p->g->poly) {
+    // one pool schedule is built for cubic coefficients: nothing to probe
+    res.schedule = MG_SCHED_POOLS_W8;
+    res.idle_trigger = pool_idle(p);
+    res.pool_size = kPoolSmall;
+    res.window = 8;
+    if (out) *out = res;
+    return MG_OK;
+  }
+  if (p->prec == MG_FP64) {
     res.schedule = MG_SCHED_LANES;
     res.idle_trigger = 0;
     if (out) *out = res;

@@ -1054,8 +1054,9 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 // move the accesses across each other.
 __device__ __forceinline__ void wave_lds_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
-template <bool TRACE, bool LDS, int PW>
-__device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolLds32<TRACE, PW> &P,
+template <bool TRACE, bool LDS, bool POLY, int PW>
+__device__ __forceinline__ void pool_load(Particle32<TRACE, LDS, POLY> &q,
+                                          const PoolLds32<TRACE, PW> &P,
                                           uint32_t s) {
   const uint32_t ef = P.ef[s];
   q.e = (int32_t)(ef & kEdgeMask);
@@ -1071,8 +1072,9 @@ __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS> &q, const PoolL
   }
 }
 
-template <bool TRACE, bool LDS, int PW>
-__device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS> &q, PoolLds32<TRACE, PW> &P,
+template <bool TRACE, bool LDS, bool POLY, int PW>
+__device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS, POLY> &q,
+                                           PoolLds32<TRACE, PW> &P,
                                            uint32_t s, uint32_t n) {
   P.ef[s] = (uint32_t)q.e | (q.side ? kSideBit : 0u);
   P.y[s] = q.y;
@@ -1084,8 +1086,8 @@ __device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS> &q, Pool
   }
 }
 
-template <bool TRACE, bool LDS>
-__device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS> &q, const SetDev &S,
+template <bool TRACE, bool LDS, bool POLY>
+__device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS, POLY> &q, const SetDev &S,
                                             const StepArgs &A, uint32_t pid, Tally &t) {
   S.ef[pid] = (uint32_t)q.e | (q.side ? kSideBit : 0u) | (q.alive ? 0u : kDeadBit);
   S.y32[pid] = make_float2(q.y, q.yl);
@@ -1103,7 +1105,7 @@ __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS> &q, con
 // the set's counter as its home slots free up, so pools stay nearly full
 // until the set runs out and a launch ends with one short tail instead of
 // one per block.  Otherwise (batched launches): the ids [first, last).
-template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool PERSIST>
+template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool PERSIST, bool POLY>
 __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
                            const StepArgs &A, uint32_t first, uint32_t last,
                            PoolLds32<TRACE, PW> &P, uint32_t *s_exit, Tally &t,
@@ -1112,8 +1114,8 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   const float dt = (float)A.dt;
   const float sqdt = (float)sqrt(A.dt);
   const uint32_t n_end = S.n0 + A.nsteps;
-  Particle32<TRACE, LDS> q{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
-                           true, 0ull, 0u, 0u};
+  Particle32<TRACE, LDS, POLY> q{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
+                                 true, 0ull, 0u, 0u};
   bool has = false;
   uint32_t slot = 0, n = 0, pid = 0;  // the lane's home slot, next step, particle
   uint32_t snap = 0;  // next snapshot count of the lane's particle
@@ -1290,7 +1292,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       uint32_t s2 = 0;
       if (lane < B) {
         s2 = P.split[(s_base + lane) % K];
-        Particle32<TRACE, LDS> q2{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt,
+        Particle32<TRACE, LDS, POLY> q2{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt,
                                   sqdt, true, 0ull, 0u, 0u};
         pool_load(q2, P, s2);
         const uint32_t step = P.n[s2];
@@ -1341,7 +1343,8 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
 
 // Shared memory of a pool block: [exit counters][staged tables][pools]
 // [snapshot bins].
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool PERSIST>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool PERSIST,
+          bool POLY>
 __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t block_first,
                                            uint32_t *s_tot, char *smem) {
@@ -1362,7 +1365,7 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
   Tally t{0, 0, 0, 0};
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t first = block_first + wave * PW * kBatchGens;
-  run_pool32<TRACE, LDS, OBS, PW, NG, PERSIST>(view, G.E, S, A, first,
+  run_pool32<TRACE, LDS, OBS, PW, NG, PERSIST, POLY>(view, G.E, S, A, first,
                                                min(first + PW * kBatchGens, S.n),
                                            pools[wave], s_exit, t, o);
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
@@ -1373,15 +1376,17 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
 #define MG_POOL_WAVES_PER_EU 7
 #endif
 
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG>
+// POLY (cubic coefficients) is instantiated for pools of 128 with two
+// Philox groups per window only.
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool POLY = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, true>(G, S, A, 0u, s_tot, (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, true, POLY>(G, S, A, 0u, s_tot, (char *)smem4);
 }
 
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool POLY = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32_batch(const GraphDev *graphs,
                                                          const SetDev *sets,
@@ -1393,7 +1398,8 @@ void k_pool32_batch(const GraphDev *graphs,
   SetDev S = sets[it.set];
   S.n0 += A.n0_offset;
   const GraphDev G = graphs[it.set];
-  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, false>(G, S, A, it.first, s_tot, (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, false, POLY>(G, S, A, it.first, s_tot,
+                                                          (char *)smem4);
 }
 
 // Autotuning probes: the FP32 step kernels under names of their own, so a
@@ -1403,7 +1409,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_
 void k_pool32_probe(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ uint32_t s_tot[4];
-  pool_block<false, LDS, STAGED, false, PW, NG, true>(G, S, A, 0u, s_tot, (char *)smem4);
+  pool_block<false, LDS, STAGED, false, PW, NG, true, false>(G, S, A, 0u, s_tot, (char *)smem4);
 }
 
 template <bool LDS, bool STAGED>
@@ -1687,7 +1693,7 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
                          hipStream_t st) {
   StepArgs a = a0;
   const bool obs = s.obs != nullptr;
-  if (!FP64 && a.kernel >= 1 && !g.poly) {
+  if (!FP64 && a.kernel >= 1 && (!g.poly || a.kernel == 3)) {
     with_pool(a.kernel, [&](auto PWc, auto NGc) {
       constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
       const int32_t stage = g.stage_bytes32;
@@ -1705,6 +1711,19 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
                              g, s, a);
         }, lp.lds_exit, lp.staged);
         return;
+      }
+      if constexpr (PW == kPoolSmall && NG == 2) {
+        if (g.poly) {
+          with_flags([&](auto L, auto T, auto O) {
+            const void *f = (const void *)k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
+                                                   decltype(O)::value, PW, NG, true>;
+            hipLaunchKernelGGL((k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
+                                         decltype(O)::value, PW, NG, true>),
+                               dim3(resident_blocks(f, lp.shm, need)), dim3(kBlock), lp.shm,
+                               st, g, s, a);
+          }, lp.lds_exit, lp.staged, obs);
+          return;
+        }
       }
       with_flags([&](auto L, auto T, auto O) {
         const void *f = (const void *)k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
@@ -1743,7 +1762,7 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
   KernelLaunch k{};
   k.grid = dim3(n_items);
   k.block = dim3(kBlock);
-  const bool pools = !FP64 && a.kernel >= 1 && !poly;
+  const bool pools = !FP64 && a.kernel >= 1 && (!poly || a.kernel == 3);
   with_pool(a.kernel, [&](auto PWc, auto NGc) {
     constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
     const LdsPlan lp = plan_lds(max_nnz, max_stage,
@@ -1754,6 +1773,11 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
       constexpr bool l = decltype(L)::value, t = decltype(T)::value, o = decltype(O)::value;
       if constexpr (!FP64)
         if (pools) {
+          if constexpr (PW == kPoolSmall && NG == 2)
+            if (poly) {
+              k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG, true>;
+              return;
+            }
           k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG>;
           return;
         }

@@ -1,7 +1,7 @@
 """General coefficient functions (cubic drift and diffusion, Sec. 2.2)
 through the C ABI: the FP64 path against the oracle element by element on a
 star and in the batched form, FP32 against FP64 under common random numbers
-(lane schedule, alone and batched), and graph validation."""
+(lane and pool schedules, alone and batched), and graph validation."""
 import numpy as np
 import pytest
 
@@ -90,21 +90,23 @@ def test_cubic_segment_and_batch_fp64(B, orc):
 
 
 def test_double_well_star_fp32_against_fp64(B):
-    """FP32 (lane schedule, chosen by AUTO and by LANES alike, and in a
-    batch) against FP64 on the double-well star under common random numbers:
+    """FP32 against FP64 on the double-well star under common random numbers:
     binned total variation <= 2e-3, exit probabilities at the centre within
-    1e-3, most hit sequences equal."""
+    1e-3, most hit sequences equal; the lane schedule, the pools of 128 with
+    8-step windows (AUTO's choice and asked for) and the batched form equal
+    each other bit for bit."""
     g = workloads.double_well_star()
     G = B.mg_graph_create(g)
     n, dt, bins = 200_000, 1e-2, 64
     res = {}
     for name, prec, sched in (("fp64", B.MG_FP64, B.MG_SCHED_AUTO),
                               ("auto", B.MG_FP32, B.MG_SCHED_AUTO),
+                              ("pools_w8", B.MG_FP32, B.MG_SCHED_POOLS_W8),
                               ("lanes", B.MG_FP32, B.MG_SCHED_LANES)):
         p = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=6,
                                 precision=prec, trace=True, schedule=sched)
         if name == "auto":
-            assert B.mg_autotune(p, dt)["schedule"] == B.MG_SCHED_LANES
+            assert B.mg_autotune(p, dt)["schedule"] == B.MG_SCHED_POOLS_W8
         for k in (3, 997, 1000):
             B.mg_simulate(p, k, dt, 21)
         res[name] = (B.mg_histogram(p, bins), B.mg_exit_counts(p),
@@ -127,7 +129,7 @@ def test_double_well_star_fp32_against_fp64(B):
     c = slice(g.vtx_offsets[0], g.vtx_offsets[1])
     assert np.abs(e64[c] / e64[c].sum() - e32[c] / e32[c].sum()).max() <= 1e-3
     assert (r32["seqhash"] == r64["seqhash"]).mean() > 0.9
-    for name in ("auto", "batch"):
+    for name in ("auto", "pools_w8", "batch"):
         h, (e, _, t), r = res[name]
         assert np.array_equal(h, h32) and np.array_equal(e, e32) and np.array_equal(t, t32)
         for f in ("edge", "x", "seqhash", "hits"):
@@ -135,16 +137,20 @@ def test_double_well_star_fp32_against_fp64(B):
 
 
 def test_coefficient_validation(B):
-    """FP32 sets on graphs with higher terms refuse the pool schedules;
+    """FP32 sets on graphs with higher terms refuse the pool schedules other
+    than pools of 128 with 8-step windows;
     sigma(x) must stay positive on the whole edge (an interior zero is
     caught); higher terms need finite edges and finite values; zero higher
     terms are affine."""
     g = workloads.double_well_star(8)
     G = B.mg_graph_create(g)
-    for sched in (B.MG_SCHED_POOLS, B.MG_SCHED_POOLS256, B.MG_SCHED_POOLS_W8):
+    for sched in (B.MG_SCHED_POOLS, B.MG_SCHED_POOLS256):
         with pytest.raises(B.MgError):
             B.mg_particles_init(G, 100, B.MG_INIT_UNIFORM_LENGTH, precision=B.MG_FP32,
                                 schedule=sched)
+    for sched in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS_W8, B.MG_SCHED_AUTO):
+        B.mg_particles_init(G, 100, B.MG_INIT_UNIFORM_LENGTH, precision=B.MG_FP32,
+                            schedule=sched)
     bad = workloads.segment(2.0, 0.0, 0.0, 1.0)
     bad.sigma_c1, bad.sigma_c2 = [-4.0], [4.0]  # (1 - 2x)^2, zero at 0.5
     with pytest.raises(B.MgError):
