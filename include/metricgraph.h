@@ -158,7 +158,9 @@ void mg_graph_destroy(mg_graph *g);
  *                 windows of 8 first sub-steps, two Philox groups, per
  *                 pass instead of 4).
  *                 Results are identical; only the speed differs.  FP64 sets
- *                 always use the lane schedule.
+ *                 always use the lane schedule.  On a graph with higher
+ *                 coefficient terms (mg_graph_desc) only MG_SCHED_AUTO,
+ *                 MG_SCHED_LANES and MG_SCHED_POOLS_W8 are accepted.
  */
 typedef enum {
   MG_SCHED_AUTO = 0, MG_SCHED_LANES = 1, MG_SCHED_POOLS = 2, MG_SCHED_POOLS256 = 3,
