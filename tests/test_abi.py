@@ -98,3 +98,64 @@ def test_null_arguments(B):
     L.mg_particles_destroy(None)
     L.mg_batch_destroy(None)
     assert "batch" in B.mg_last_error() or B.mg_last_error() != ""
+
+
+def _cubic(**hi):
+    g = workloads.segment(2.0, 0.0, 0.0, 1.0)
+    for k, v in hi.items():
+        setattr(g, k, np.asarray(v, np.float64))
+    return g
+
+
+@pytest.mark.parametrize("make,msg", [
+    # a mirror vertex must be a leaf (the centre of a star has three slots)
+    (lambda: workloads.from_edges(4, [0, 0, 0], [1, 2, 3], 1.0, vtx_kind=[2, 0, 0, 0]),
+     "leaf"),
+    # sigma(x) = (1 - 2x)^2 vanishes inside the edge; its ends are positive
+    (lambda: _cubic(sigma_c1=[-4.0], sigma_c2=[4.0]), "sigma(x)"),
+    # sigma(x) = 1 - 3x^2 + x^3 turns negative at x = 1
+    (lambda: _cubic(sigma_c2=[-3.0], sigma_c3=[1.0]), "sigma(x)"),
+    (lambda: _cubic(drift_c3=[np.nan]), "not finite"),
+    (lambda: workloads.from_edges(2, [0], [1], [np.inf], bin_span=2.0), None),
+])
+def test_method_variant_graphs_checked(B, make, msg):
+    """Mirror vertices and cubic coefficients are validated on the host: the
+    bad cases are refused with the reason, the good ones pass validation
+    (which is all that runs here; building the device tables needs a GPU)."""
+    g = make()
+    if msg is None:
+        g.drift_c2 = np.array([0.1])  # higher terms need a finite edge
+        msg = "finite edge"
+    with pytest.raises(B.MgError) as ei:
+        B.mg_graph_create(g)
+    assert ei.value.status == B.MG_EINVAL
+    assert msg in str(ei.value), str(ei.value)
+
+
+def test_struct_layouts_match_the_header(B, tmp_path):
+    """The binding's ctypes structs have the header's field offsets and
+    sizes (compiled with the host C compiler from include/metricgraph.h)."""
+    structs = {"mg_graph_desc": B.mg_graph_desc, "mg_options": B.mg_options,
+               "mg_tuning": B.mg_tuning}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "metricgraph.h"',
+             "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                    str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for f in cls._fields_:
+            assert got[(name, f[0])] == getattr(cls, f[0]).offset, (name, f[0])
