@@ -105,8 +105,8 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *                        FP32 sets on such a graph run MG_SCHED_POOLS_W8
  *                        (MG_SCHED_AUTO's choice, no probing) or
  *                        MG_SCHED_LANES; the other pool schedules are
- *                        refused, and a batch mixes them with sets on affine
- *                        graphs only on a schedule all of them take.
+ *                        refused, and an FP32 batch does not mix them with
+ *                        sets on affine graphs (FP64 batches may).
  * Every edge must appear exactly once at its initial vertex with orient 0
  * and once at its terminal vertex with orient 1 (a self-loop twice at its
  * vertex).  A standard vertex needs at least one slot with b > 0.

@@ -133,7 +133,7 @@ struct mg_batch {
   int32_t n_items = 0;
   int32_t max_nnz = 0;
   int32_t max_stage = 0;  // staged table bytes if every set's graph fits, else 0
-  bool poly = false;      // some set's graph has higher coefficients (FP64 only)
+  bool poly = false;      // some set's graph has higher coefficients
   int32_t kernel = 1;     // FP32 schedule fixed at creation (tile size follows it)
   // Per-call set descriptors go up from pinned memory; the launch chain of a
   // call is a HIP graph of kernel nodes, re-instantiated only when the
@@ -1006,6 +1006,11 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
     if (sets[i]->trace != sets[0]->trace) return fail(MG_EINVAL, "sets differ in trace");
     if (fp32_kernel(sets[i]) != fp32_kernel(sets[0]))
       return fail(MG_EINVAL, "sets differ in schedule");
+    // the FP32 cubic step evaluates the coefficients at the position, the
+    // affine one uses per-frame constants: one launch cannot give both sets
+    // their own bits
+    if (sets[0]->prec == MG_FP32 && sets[i]->g->poly != sets[0]->g->poly)
+      return fail(MG_EINVAL, "FP32 sets differ in coefficient form (cubic and affine)");
     for (int32_t j = 0; j < i; ++j)
       if (sets[j] == sets[i]) return fail(MG_EINVAL, "set %d appears twice", i);
   }

@@ -129,6 +129,12 @@ def test_double_well_star_fp32_against_fp64(B):
     c = slice(g.vtx_offsets[0], g.vtx_offsets[1])
     assert np.abs(e64[c] / e64[c].sum() - e32[c] / e32[c].sum()).max() <= 1e-3
     assert (r32["seqhash"] == r64["seqhash"]).mean() > 0.9
+    # an FP32 batch cannot mix cubic and affine graphs
+    aff = B.mg_particles_init(B.mg_graph_create(workloads.star_graph(3, 1.0)), 100,
+                              B.MG_INIT_UNIFORM_LENGTH, precision=B.MG_FP32, trace=True,
+                              graph_tag=2)
+    with pytest.raises(B.MgError):
+        B.mg_batch_create([pb, aff])
     for name in ("auto", "pools_w8", "batch"):
         h, (e, _, t), r = res[name]
         assert np.array_equal(h, h32) and np.array_equal(e, e32) and np.array_equal(t, t32)
