@@ -81,7 +81,7 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *                        edge through it is replaced by its mirror image
  *                        (-x~ at an initial end, 2L - x~ at a terminal end;
  *                        the far-end reflection of the paper's star-graph
- *                        kernel, Sec. 4) when that image lies strictly
+ *                        kernel in the appendix) when that image lies strictly
  *                        inside the edge, which ends the step with no vertex
  *                        hit: no split, no hit-stream draw, no exit record of
  *                        its own.  Otherwise (a move longer than the edge, or

@@ -322,7 +322,7 @@ static void run_particle(const or_graph *g, const uint64_t *thr, uint32_t p,
       const int hit_init = xt <= 0.0;
       const int32_t v = hit_init ? g->edge_init[e] : g->edge_term[e];
       /* Mirror leaf (reading A25; the far-end reflection of the star-graph
-         kernel, Sec. 4): the proposal's mirror image in the vertex ends the
+         kernel in the appendix): the mirror image in the vertex ends the
          step when it lies inside the edge; no vertex hit is recorded. */
       if (g->vtx_kind && g->vtx_kind[v] == 2) {
         const double xr = hit_init ? -xt : 2.0 * L - xt;

@@ -1,6 +1,6 @@
 """Mirror vertices (reflecting leaves: a proposal that leaves the edge
 through one takes its mirror image when that lies inside the edge, the
-far-end reflection of the paper's star-graph kernel, Sec. 4) through the C
+far-end reflection of the paper's star-graph kernel in the appendix) through the C
 ABI: the FP64 path against the oracle element by element, FP32 against FP64
 under common random numbers, the FP32 schedules and the batched form against
 each other bit for bit, the folded-normal law of one FP32 step at full

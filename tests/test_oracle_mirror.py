@@ -1,6 +1,6 @@
 """Pins of the oracle's mirror vertices: leaves that reflect a proposal
 leaving the edge through them by its mirror image (the far-end reflection of
-the paper's star-graph kernel, Sec. 4), against what the mathematics fixes."""
+the paper's star-graph kernel in the appendix), against what the mathematics fixes."""
 import numpy as np
 import pytest
 from scipy import stats
