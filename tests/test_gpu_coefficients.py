@@ -89,6 +89,36 @@ def test_cubic_segment_and_batch_fp64(B, orc):
             assert np.array_equal(x, y)
 
 
+def test_cubic_segment_with_mirror_ends(B, orc):
+    """Cubic coefficients and mirror vertices together (the mirror branch
+    of the cubic step): FP64 against the oracle element by element, FP32
+    against FP64 in distribution, FP32 pools equal to FP32 lanes."""
+    g = workloads.segment(2.0, 12.0, -44.0, 1.0, end_kind=2)
+    g.drift_c2, g.drift_c3 = [48.0], [-16.0]
+    g.sigma_c1, g.sigma_c2, g.sigma_c3 = [0.3], [-0.1], [0.02]
+    n, steps, dt = 20_000, 600, 1e-3
+    st = orc.init(g, n, orc.INIT_UNIFORM_LENGTH, seed=5)
+    c = orc.simulate(g, st, 0, steps, dt, 6)
+    G = B.mg_graph_create(g)
+    p = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=5,
+                            precision=B.MG_FP64, trace=True)
+    B.mg_simulate(p, steps, dt, 6)
+    _check_against_oracle(B, orc, g, p, n, steps, dt, 6, st, c)
+    h64 = B.mg_histogram(p, 40)
+    res = {}
+    for name, sched in (("lanes", B.MG_SCHED_LANES), ("pools_w8", B.MG_SCHED_POOLS_W8)):
+        q = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=5,
+                                precision=B.MG_FP32, trace=True, schedule=sched)
+        B.mg_simulate(q, steps, dt, 6)
+        res[name] = (B.mg_histogram(q, 40), B.mg_particles_read(q, trace=True))
+    h32, r32 = res["lanes"]
+    assert 0.5 * np.abs(h32 / h32.sum() - h64 / h64.sum()).sum() <= 2e-3
+    hp, rp = res["pools_w8"]
+    assert np.array_equal(hp, h32)
+    for f in ("edge", "x", "seqhash", "hits"):
+        assert np.array_equal(rp[f], r32[f]), f
+
+
 def test_double_well_star_fp32_against_fp64(B):
     """FP32 against FP64 on the double-well star under common random numbers:
     binned total variation <= 2e-3, exit probabilities at the centre within

@@ -19,8 +19,8 @@ def _power(coef, x):
     return sum(c * x ** j for j, c in enumerate(coef))
 
 
-def _segment(L, mu, sig):
-    g = workloads.segment(L, mu[0], mu[1], sig[0])
+def _segment(L, mu, sig, end_kind=0):
+    g = workloads.segment(L, mu[0], mu[1], sig[0], end_kind=end_kind)
     g.drift_c2, g.drift_c3 = [mu[2]], [mu[3]]
     g.sigma_c1, g.sigma_c2, g.sigma_c3 = [sig[1]], [sig[2]], [sig[3]]
     return g
@@ -47,14 +47,16 @@ def test_one_step_gaussian_with_frozen_coefficients(orc, x0):
     assert abs(st.x.std() / s - 1.0) < 5 / np.sqrt(2 * N)
 
 
-def test_stationary_law_with_cubic_drift_and_diffusion(orc):
-    """A segment [0, 2] with plain reflecting leaves, double-well drift and
-    a cubic diffusion: the Ito diffusion's stationary density is
-    exp(int_0^x 2 mu / sigma^2) / sigma^2 (zero flux), integrated here by
-    quadrature.  Started from that law, time-averaged bin masses stay
-    within the Monte-Carlo and time-step error (total variation)."""
+@pytest.mark.parametrize("end_kind", [0, 2])
+def test_stationary_law_with_cubic_drift_and_diffusion(orc, end_kind):
+    """A segment [0, 2] with reflecting ends (plain leaves, or mirror
+    vertices), double-well drift and a cubic diffusion: the Ito diffusion's
+    stationary density is exp(int_0^x 2 mu / sigma^2) / sigma^2 (zero flux),
+    integrated here by quadrature.  Started from that law, time-averaged bin
+    masses stay within the Monte-Carlo and time-step error (total
+    variation)."""
     L, nb = 2.0, 40
-    g = _segment(L, MU, SIG)
+    g = _segment(L, MU, SIG, end_kind)
 
     def dens(x):
         phi = integrate.quad(lambda y: 2 * _power(MU, y) / _power(SIG, y) ** 2, 0, x)[0]
