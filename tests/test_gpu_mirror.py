@@ -37,12 +37,21 @@ def _mixed_tree():
     return g
 
 
+def _mixed_tree_cubic():
+    """The mixed tree with a cubic drift term and a graded diffusion."""
+    g = _mixed_tree()
+    g.drift_c3 = np.full(g.n_edges, -0.2)
+    g.sigma_c1 = np.full(g.n_edges, 0.1)
+    return g
+
+
 def _graphs():
     return {
         "brownian_star": workloads.star_graph(3, [0.5, 1.0, 1.5], sigma=1.0, leaf_kind=2),
         "langevin_star64": workloads.star_graph(
             **_config2_kwargs(), leaf_kind=2),
         "mixed_tree": _mixed_tree(),
+        "mixed_tree_cubic": _mixed_tree_cubic(),
     }
 
 
@@ -52,7 +61,8 @@ def _config2_kwargs():
                 sigma=g.sigma, b_center=np.ones(g.n_edges))
 
 
-@pytest.mark.parametrize("name", ["brownian_star", "langevin_star64", "mixed_tree"])
+@pytest.mark.parametrize("name", ["brownian_star", "langevin_star64", "mixed_tree",
+                                  "mixed_tree_cubic"])
 def test_mirror_fp64_parity(B, orc, name):
     """20k particles uniform by length, 1000 steps of 1e-2 (leaves reached
     many times): hit sequences, edges, positions, exit and absorbed counts,
@@ -77,7 +87,7 @@ def test_mirror_fp64_parity(B, orc, name):
     ex, ab, tot = B.mg_exit_counts(p)
     assert np.abs(ex.astype(np.int64) - c.exit_slot.astype(np.int64)).sum() <= 2 * steps * nd
     assert np.abs(ab.astype(np.int64) - c.absorbed.astype(np.int64)).sum() <= nd
-    if name != "mixed_tree":
+    if not name.startswith("mixed_tree"):
         # on the stars no move is longer than an edge: a mirror leaf never
         # splits, so it records no exit (the tree's short edges do split
         # there now and then, as the oracle does)
