@@ -206,3 +206,35 @@ def test_coefficient_validation(B):
     ok.drift_c2 = ok.drift_c3 = ok.sigma_c1 = ok.sigma_c2 = ok.sigma_c3 = [0.0]
     B.mg_particles_init(B.mg_graph_create(ok), 100, B.MG_INIT_UNIFORM_LENGTH,
                         precision=B.MG_FP32)
+
+
+def test_streamed_histogram_with_cubic_coefficients(B, orc):
+    """Streamed snapshots on the double-well star: FP64 against the oracle's
+    streamed histogram, FP32 pools against FP32 lanes bit for bit."""
+    g = workloads.double_well_star(16)
+    G = B.mg_graph_create(g)
+    n, dt, bins, every = 20_000, 1e-2, 32, 25
+    p = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=2,
+                            precision=B.MG_FP64, trace=True)
+    B.mg_observe_histogram(p, bins, every)
+    for k in (7, 293, 200):
+        B.mg_simulate(p, k, dt, 5)
+    h, snaps = B.mg_observed_histogram(p)
+    st = orc.init(g, n, orc.INIT_UNIFORM_LENGTH, seed=2)
+    acc, osnaps, _ = orc.observed_histogram(g, st, 0, 500, dt, 5, every, bins)
+    r = B.mg_particles_read(p, trace=True)
+    nd = int((r["seqhash"] != st.seqhash).sum())
+    assert snaps == osnaps == 20
+    assert np.abs(h.astype(np.int64).ravel() - acc.astype(np.int64).ravel()).sum() <= 2 * snaps * nd
+    out = {}
+    for name, sched in (("lanes", B.MG_SCHED_LANES), ("pools_w8", B.MG_SCHED_POOLS_W8)):
+        q = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=2,
+                                precision=B.MG_FP32, schedule=sched)
+        B.mg_observe_histogram(q, bins, every)
+        for k in (7, 293, 200):
+            B.mg_simulate(q, k, dt, 5)
+        out[name] = B.mg_observed_histogram(q)
+    assert out["lanes"][1] == out["pools_w8"][1] == 20
+    assert np.array_equal(out["lanes"][0], out["pools_w8"][0])
+    tv = 0.5 * np.abs(out["lanes"][0] / out["lanes"][0].sum() - h / h.sum()).sum()
+    assert tv <= 2e-3, tv
