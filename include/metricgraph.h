@@ -190,7 +190,7 @@ int64_t mg_particles_arena_bytes(const mg_graph *g, int64_t n,
                                  const mg_options *opt);
 
 /*
- * Creates n particles (1 <= n <= 2^32 - 1) on graph g.  Random draws of
+ * Creates n particles (1 <= n <= 2^32 - 2^20) on graph g.  Random draws of
  * the non-explicit modes use the init stream of Philox keyed by init_seed.
  * EXPLICIT needs 0 <= pos[i] <= L_{edge[i]}; a position on an end means the
  * particle sits on that vertex.  AT_VERTEX needs a standard vertex.  The set
@@ -231,7 +231,10 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
 /*
  * Uniform-bin histogram of the alive particles (appendix kernels):
  * out[e * bins_per_edge + b] = number of particles on e with
- * min(bins_per_edge - 1, floor(x * bins_per_edge / L_e)) = b.
+ * min(bins_per_edge - 1, floor(x * (bins_per_edge / S_e))) = b, where S_e is
+ * the edge's binned length (mg_graph_desc.bin_span; the edge length when
+ * none was given), so bins have width S_e / bins_per_edge and positions at
+ * or beyond S_e count in the last bin.  The inverse width is formed in FP64.
  * out_len must be >= E * bins_per_edge.  Synchronises the stream.
  */
 mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge,

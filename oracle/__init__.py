@@ -85,6 +85,18 @@ def lib():
     return _lib
 
 
+def default_threads() -> int:
+    """OpenMP threads of a run: OMP_NUM_THREADS when set (a machine's share
+    of its cores), else every core the process may use."""
+    v = os.environ.get("OMP_NUM_THREADS", "")
+    if v.isdigit() and int(v) > 0:
+        return int(v)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
@@ -278,7 +290,7 @@ def simulate(g, st: State, n0: int, n_steps: int, dt: float, seed: int, *,
     if counts is None:
         counts = new_counts(g)
     sc = np.zeros(3, np.uint64)
-    nth = threads if threads is not None else (os.cpu_count() or 1)
+    nth = threads if threads is not None else default_threads()
     rc = lib().or_simulate(g.ref, st.pid.size, _ptr(st.pid), _ptr(st.edge), _ptr(st.x),
                            _ptr(st.alive), _ptr(st.seqhash), _ptr(st.hits),
                            C.c_uint64(n0), C.c_uint64(n_steps), C.c_double(dt),

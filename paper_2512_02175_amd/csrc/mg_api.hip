@@ -75,6 +75,18 @@ void slot_thresholds(int32_t V, const int32_t *off, const double *b,
 }
 
 bool is_finite(double v) { return std::isfinite(v); }
+
+// Iterations of a wave-pool loop between moves of the 32-bit lane tallies
+// and LDS counters into 64-bit ones: 1024, or MG_POOL_DRAIN (1 .. 1024)
+// from the environment, read at each launch.  Tests lower it to run the
+// moves often; the results are the same at any value.
+uint32_t pool_drain() {
+  const char *v = std::getenv("MG_POOL_DRAIN");
+  if (!v || !*v) return kDrainMax;
+  char *end = nullptr;
+  const unsigned long long x = std::strtoull(v, &end, 10);
+  return (end && *end == 0 && x >= 1 && x <= kDrainMax) ? (uint32_t)x : kDrainMax;
+}
 // an optional per-edge coefficient array: its entry, or 0 when absent
 double higher(const double *p, int32_t e) { return p ? p[e] : 0.0; }
 
@@ -147,6 +159,7 @@ struct mg_batch {
   uint64_t key_seed = 0;
   int32_t key_idle = -1;
   uint32_t key_chunk = 0;
+  uint32_t key_drain = 0;
   bool key_obs = false;
 };
 
@@ -250,20 +263,34 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
     poly = true;
     if (std::isinf(d->length[e]))
       return fail(MG_EINVAL, "edge %d: higher coefficients need a finite edge", e);
-    // sigma_e(x) > 0 on [0, L]: its minimum is at an end or where
-    // s1 + 2 s2 x + 3 s3 x^2 = 0
+    // sigma_e(x) > 0 on [0, L]: its minimum is at an end or at a real root
+    // of sigma' = s1 + 2 s2 x + 3 s3 x^2, found with the cancellation-free
+    // quadratic formula (q = -(b + sgn(b) sqrt(b^2 - 4ac)) / 2, roots q/a
+    // and c/q) and refined by one Newton step; sigma is evaluated there in
+    // FP64 (a minimum within rounding of zero may pass either way)
     const double L = d->length[e], s0 = d->sigma[e], s1 = hi[2], s2 = hi[3], s3 = hi[4];
     auto sig = [&](double x) { return ((s3 * x + s2) * x + s1) * x + s0; };
+    auto dsig = [&](double x) { return (3.0 * s3 * x + 2.0 * s2) * x + s1; };
+    auto newton = [&](double x) {
+      const double dd = 6.0 * s3 * x + 2.0 * s2;
+      return dd != 0.0 ? x - dsig(x) / dd : x;
+    };
     double crit[4] = {0.0, L, 0.0, 0.0};
     int nc = 2;
-    if (s3 != 0.0) {
-      const double disc = 4.0 * s2 * s2 - 12.0 * s3 * s1;
+    const double qa = 3.0 * s3, qb = 2.0 * s2, qc = s1;
+    if (qa != 0.0) {
+      const double disc = qb * qb - 4.0 * qa * qc;
       if (disc >= 0.0) {
-        crit[nc++] = (-2.0 * s2 + std::sqrt(disc)) / (6.0 * s3);
-        crit[nc++] = (-2.0 * s2 - std::sqrt(disc)) / (6.0 * s3);
+        const double q = -0.5 * (qb + std::copysign(std::sqrt(disc), qb));
+        if (q != 0.0) {
+          crit[nc++] = newton(q / qa);
+          crit[nc++] = newton(qc / q);
+        } else {
+          crit[nc++] = 0.0;  // b = c = 0: a double root at 0
+        }
       }
-    } else if (s2 != 0.0) {
-      crit[nc++] = -s1 / (2.0 * s2);
+    } else if (qb != 0.0) {
+      crit[nc++] = -qc / qb;
     }
     for (int i = 0; i < nc; ++i) {
       const double x = crit[i];
@@ -476,8 +503,8 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
                            uint64_t init_seed, const mg_options *opt, mg_particles **out) {
   if (!out) return fail(MG_EINVAL, "out is NULL");
   *out = nullptr;
+  if (n < 1 || n > kMaxParticles) return fail(MG_EINVAL, "n must be in [1, 2^32 - 2^20]");
   if (!g) return fail(MG_EINVAL, "graph is NULL");
-  if (n < 1 || n > 0xFFFFFFFFll) return fail(MG_EINVAL, "n must be in [1, 2^32 - 1]");
   mg_options o{};
   o.precision = MG_FP64;
   if (opt) o = *opt;
@@ -693,8 +720,11 @@ static int32_t pool_idle(const mg_particles *p) {
 }
 
 static uint32_t chunk_steps(int32_t spl) {
-  // Steps fused per launch.  Per-lane tallies are 32-bit and a launch may
-  // not run forever, so cap a chunk at 2^20 steps.
+  // Steps fused per launch, capped at 2^20: a lane of the lane schedule
+  // keeps 32-bit tallies of one particle's launch (at most 2^20 (M + 1)
+  // sub-steps, M <= 255), the wave pools' drain bound assumes it, and a
+  // launch should not run forever.  Block totals are 64-bit and the pools
+  // drain their u32 counters, so no count limits a launch otherwise.
   const uint32_t cap = 1u << 20;
   return spl > 0 ? std::min<uint32_t>((uint32_t)spl, cap) : cap;
 }
@@ -711,6 +741,7 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
     g_err.clear();
   }
   StepArgs a{};
+  a.drain = pool_drain();
   a.max_splits = p->max_splits;
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
@@ -1119,6 +1150,7 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
   mg_particles *p0 = b->sets[0];
   hipStream_t stream = p0->stream;
   StepArgs a{};
+  a.drain = pool_drain();
   a.max_splits = p0->max_splits;
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
@@ -1139,7 +1171,8 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
   bool obs = false;
   for (mg_particles *p : b->sets) obs = obs || p->sd.obs != nullptr;
   if (!(b->exec && b->key_steps == n_steps && b->key_dt == dt && b->key_seed == seed &&
-        b->key_idle == a.idle && b->key_chunk == chunk && b->key_obs == obs)) {
+        b->key_idle == a.idle && b->key_chunk == chunk && b->key_obs == obs &&
+        b->key_drain == a.drain)) {
     drop_graph(b);
     b->key_obs = obs;
     hipError_t he = build_graph(b, n_steps, a, chunk);
@@ -1152,6 +1185,7 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
     b->key_seed = seed;
     b->key_idle = a.idle;
     b->key_chunk = chunk;
+    b->key_drain = a.drain;
   }
   MG_HIP(hipGraphLaunch(b->exec, stream), "launching the batch graph");
   for (mg_particles *p : b->sets) p->step += (uint64_t)n_steps;
@@ -1212,6 +1246,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   sd.n0 = (uint32_t)p->step;
   sd.tag = p->tag;
   StepArgs a{};
+  a.drain = pool_drain();
   a.nsteps = steps;
   a.max_splits = p->max_splits;
   a.key0 = (uint32_t)seed;

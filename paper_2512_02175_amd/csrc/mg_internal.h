@@ -125,7 +125,18 @@ struct StepArgs {
   uint32_t n0_offset;  // batched launches: steps taken earlier in the call
   int32_t obs_lds;     // streamed-histogram bins privatised in LDS (0: global)
   int32_t probe;       // autotuning probe: the same kernels under probe names
+  uint32_t drain;      // wave pools: iterations between moves of the lanes'
+                       // u32 tallies and the block's u32 LDS counters into
+                       // 64-bit ones (1 .. 1024; tests lower it)
 };
+
+// Largest particle set.  A persistent pool launch hands out particle ids
+// from a 32-bit counter; every wave overshoots it by at most one claim of
+// 64 ids, and a persistent grid has at most kMaxPersistBlocks blocks of four
+// waves, so the counter stays below n + 2^19 < 2^32 and ids below 2^32.
+constexpr int64_t kMaxParticles = 0xFFFFFFFFll - 0xFFFFFll;  // 2^32 - 2^20
+constexpr uint32_t kMaxPersistBlocks = 2048;
+constexpr uint32_t kDrainMax = 1024;
 
 // Batched form: one work item per (set, tile of particles).
 struct BatchItem {

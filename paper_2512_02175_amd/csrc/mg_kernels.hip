@@ -219,7 +219,12 @@ __device__ __forceinline__ SlotPick pick_slot(const GView &g, const VtxBlk &vb, 
   return {vb.first + k, sr.eo};
 }
 
-// Per-lane tallies reduced once per block.
+// Per-lane tallies reduced once per block.  A lane of the lane schedule
+// holds one particle for a launch of at most 2^20 steps and M <= 255, so
+// each field stays below 2^20 (M + 1) = 2^28; the block adds them into
+// 64-bit LDS totals.  A lane of the wave pools serves any number of
+// particles, so the pools drain their lanes' tallies into the block totals
+// periodically (drain_tally).
 struct Tally {
   uint32_t trunc, sub, hits, steps;
 };
@@ -881,18 +886,19 @@ __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const St
   }
 }
 
-// Block-level reduction of the lane tallies and the LDS exit counters.
+// Block-level reduction of the lane tallies (into the 64-bit LDS totals,
+// to which the wave pools' periodic drains have already added) and the LDS
+// exit counters.
 __device__ __forceinline__ void flush(const SetDev &S, const Tally &t,
-                                      uint32_t *s_tot, uint32_t *s_exit,
+                                      unsigned long long *s_tot, uint32_t *s_exit,
                                       int32_t nnz, bool lds) {
-  atomicAdd(&s_tot[0], t.trunc);
-  atomicAdd(&s_tot[1], t.sub);
-  atomicAdd(&s_tot[2], t.hits);
-  atomicAdd(&s_tot[3], t.steps);
+  if (t.trunc) atomicAdd(&s_tot[0], (unsigned long long)t.trunc);
+  if (t.sub) atomicAdd(&s_tot[1], (unsigned long long)t.sub);
+  if (t.hits) atomicAdd(&s_tot[2], (unsigned long long)t.hits);
+  if (t.steps) atomicAdd(&s_tot[3], (unsigned long long)t.steps);
   __syncthreads();
   if (threadIdx.x < 4 && s_tot[threadIdx.x])
-    atomicAdd((unsigned long long *)&S.totals[threadIdx.x],
-              (unsigned long long)s_tot[threadIdx.x]);
+    atomicAdd((unsigned long long *)&S.totals[threadIdx.x], s_tot[threadIdx.x]);
   if (lds) {
     for (int32_t s = threadIdx.x; s < nnz; s += blockDim.x)
       if (s_exit[s]) atomicAdd((unsigned long long *)&S.exit_cnt[s],
@@ -940,7 +946,7 @@ __device__ __forceinline__ int32_t exit_bytes(int32_t nnz) { return ((nnz * 4) +
 template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool POLY>
 __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t pid,
-                                           uint32_t *s_tot, char *smem) {
+                                           unsigned long long *s_tot, char *smem) {
   uint32_t *s_exit = (uint32_t *)smem;
   if (threadIdx.x < 4) s_tot[threadIdx.x] = 0;
   if (LDS)
@@ -969,7 +975,7 @@ __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
 template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool POLY>
 __global__ __launch_bounds__(kBlock) void k_step(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
-  __shared__ uint32_t s_tot[4];
+  __shared__ unsigned long long s_tot[4];
   step_block<FP64, TRACE, LDS, STAGED, OBS, POLY>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
                                                   s_tot, (char *)smem4);
 }
@@ -980,7 +986,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
                                                   const BatchItem *items,
                                                   StepArgs A) {
   extern __shared__ uint4 smem4[];
-  __shared__ uint32_t s_tot[4];
+  __shared__ unsigned long long s_tot[4];
   const BatchItem it = items[blockIdx.x];
   SetDev S = sets[it.set];
   S.n0 += A.n0_offset;  // steps already taken by earlier launches of this call
@@ -1086,6 +1092,8 @@ __device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS, POLY> &q
   }
 }
 
+// Writes a particle back at the end of its launch and counts the steps it
+// took (each has one first sub-step; resolve() counts the others).
 template <bool TRACE, bool LDS, bool POLY>
 __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS, POLY> &q, const SetDev &S,
                                             const StepArgs &A, uint32_t pid, Tally &t) {
@@ -1100,6 +1108,38 @@ __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS, POLY> &
   t.sub += taken;
 }
 
+// Adds a lane's tallies to the block's 64-bit totals and clears them.
+__device__ __forceinline__ void drain_tally(Tally &t, unsigned long long *s_tot) {
+  if (t.trunc) atomicAdd(&s_tot[0], (unsigned long long)t.trunc);
+  if (t.sub) atomicAdd(&s_tot[1], (unsigned long long)t.sub);
+  if (t.hits) atomicAdd(&s_tot[2], (unsigned long long)t.hits);
+  if (t.steps) atomicAdd(&s_tot[3], (unsigned long long)t.steps);
+  t = Tally{0, 0, 0, 0};
+}
+
+// Moves a block's u32 LDS counters into their 64-bit counters in the set
+// (the lanes of one wave, each counter taken and cleared atomically, so
+// counts other waves add meanwhile are kept).
+__device__ __forceinline__ void drain_lds(uint32_t *lds, uint64_t *glob, int32_t n) {
+  for (int32_t i = (int32_t)(threadIdx.x & 63u); i < n; i += 64) {
+    const uint32_t v = atomicExch(&lds[i], 0u);
+    if (v) atomicAdd((unsigned long long *)&glob[i], (unsigned long long)v);
+  }
+}
+
+// A lane of a pool serves any number of particles in a launch, and a
+// persistent block any number of particle-steps, so every wave drains its
+// lanes' 32-bit tallies and the block's u32 LDS exit and snapshot counters
+// into 64-bit ones every A.drain (at most kDrainMax = 1024) iterations of its
+// pool loop.  Bounds: one iteration finishes at most two particles on a
+// lane (its own, and the one of its split-pass slot), each adding at most
+// 2^20 steps (a launch's cap), plus at most one crossing, so 1024
+// iterations add at most 2^31 + 1024 to a tally.  Between two drains of an
+// LDS counter (by any wave), each of the block's four waves runs fewer than
+// A.drain iterations, each adding at most 64 exit records and 64 x 9
+// snapshots (one per step of a window of at most 8 steps, and one per
+// split-pass lane): below 2^22 per counter.
+
 // Where a wave's particles come from.  PERSIST: a single set advanced by a
 // grid that stays resident; every wave claims the next particle ids from
 // the set's counter as its home slots free up, so pools stay nearly full
@@ -1109,7 +1149,7 @@ template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool PERSIST, bool POL
 __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
                            const StepArgs &A, uint32_t first, uint32_t last,
                            PoolLds32<TRACE, PW> &P, uint32_t *s_exit, Tally &t,
-                           const ObsSink &sink) {
+                           unsigned long long *s_tot, int32_t nnz, const ObsSink &sink) {
   const uint32_t lane = threadIdx.x & 63u;
   const float dt = (float)A.dt;
   const float sqdt = (float)sqrt(A.dt);
@@ -1129,9 +1169,16 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   uint32_t next = first;
   const uint32_t lim = PERSIST ? S.n : last;
   bool exhausted = false;
+  uint32_t iter = 0;
   wave_lds_fence();
 
   for (;;) {
+    if (++iter >= A.drain) {
+      iter = 0;
+      drain_tally(t, s_tot);
+      if (LDS) drain_lds(s_exit, S.exit_cnt, nnz);
+      if (OBS && sink.lds) drain_lds(sink.lds, S.obs, A.obs_lds);
+    }
     // Claim more particles: a wave takes as many ids as it has free home
     // slots, in multiples of kClaimMin up to 64, so a pool refills while its
     // first particles finish rather than after half of them have.  A
@@ -1347,7 +1394,7 @@ template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool PERS
           bool POLY>
 __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t block_first,
-                                           uint32_t *s_tot, char *smem) {
+                                           unsigned long long *s_tot, char *smem) {
   uint32_t *s_exit = (uint32_t *)smem;
   if (threadIdx.x < 4) s_tot[threadIdx.x] = 0;
   if (LDS)
@@ -1367,7 +1414,7 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
   const uint32_t first = block_first + wave * PW * kBatchGens;
   run_pool32<TRACE, LDS, OBS, PW, NG, PERSIST, POLY>(view, G.E, S, A, first,
                                                min(first + PW * kBatchGens, S.n),
-                                           pools[wave], s_exit, t, o);
+                                           pools[wave], s_exit, t, s_tot, G.nnz, o);
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
   if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
 }
@@ -1382,7 +1429,7 @@ template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool POLY
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
-  __shared__ uint32_t s_tot[4];
+  __shared__ unsigned long long s_tot[4];
   pool_block<TRACE, LDS, STAGED, OBS, PW, NG, true, POLY>(G, S, A, 0u, s_tot, (char *)smem4);
 }
 
@@ -1393,7 +1440,7 @@ void k_pool32_batch(const GraphDev *graphs,
                                                          const BatchItem *items,
                                                          StepArgs A) {
   extern __shared__ uint4 smem4[];
-  __shared__ uint32_t s_tot[4];
+  __shared__ unsigned long long s_tot[4];
   const BatchItem it = items[blockIdx.x];
   SetDev S = sets[it.set];
   S.n0 += A.n0_offset;
@@ -1408,14 +1455,14 @@ template <bool LDS, bool STAGED, int PW, int NG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32_probe(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
-  __shared__ uint32_t s_tot[4];
+  __shared__ unsigned long long s_tot[4];
   pool_block<false, LDS, STAGED, false, PW, NG, true, false>(G, S, A, 0u, s_tot, (char *)smem4);
 }
 
 template <bool LDS, bool STAGED>
 __global__ __launch_bounds__(kBlock) void k_step32_probe(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
-  __shared__ uint32_t s_tot[4];
+  __shared__ unsigned long long s_tot[4];
   step_block<false, false, LDS, STAGED, false, false>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
                                                s_tot, (char *)smem4);
 }
@@ -1440,7 +1487,8 @@ uint32_t resident_blocks(const void *func, size_t shm, uint32_t need) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kBlock, shm) != hipSuccess ||
       per_cu <= 0)
     per_cu = 1;
-  const uint32_t r = (uint32_t)cus * (uint32_t)per_cu;
+  uint32_t r = (uint32_t)cus * (uint32_t)per_cu;
+  if (r > kMaxPersistBlocks) r = kMaxPersistBlocks;  // bounds the claim counter
   return need < r ? need : r;
 }
 

@@ -100,6 +100,20 @@ def test_null_arguments(B):
     assert "batch" in B.mg_last_error() or B.mg_last_error() != ""
 
 
+def test_particle_count_limit(B):
+    """A set holds at most 2^32 - 2^20 particles (the persistent launch's
+    32-bit claim counter then cannot wrap); the count is checked before
+    anything touches the device."""
+    L = B.lib()
+    h = C.c_void_p()
+    for n in (0, -1, 2**32 - 2**20 + 1, 2**32 - 1, 2**40):
+        assert L.mg_particles_init(None, n, 2, None, None, 0, 0, None, C.byref(h)) == B.MG_EINVAL
+        assert "2^32 - 2^20" in B.mg_last_error()
+    assert L.mg_particles_init(None, 2**32 - 2**20, 2, None, None, 0, 0, None,
+                               C.byref(h)) == B.MG_EINVAL
+    assert "graph is NULL" in B.mg_last_error()
+
+
 def _cubic(**hi):
     g = workloads.segment(2.0, 0.0, 0.0, 1.0)
     for k, v in hi.items():
@@ -115,6 +129,10 @@ def _cubic(**hi):
     (lambda: _cubic(sigma_c1=[-4.0], sigma_c2=[4.0]), "sigma(x)"),
     # sigma(x) = 1 - 3x^2 + x^3 turns negative at x = 1
     (lambda: _cubic(sigma_c2=[-3.0], sigma_c3=[1.0]), "sigma(x)"),
+    # sigma(x) = (1 - 2x)^2 - 1e-12 x^3 is -1.25e-13 at x = 1/2: the
+    # critical point must come from the cancellation-free formula (the
+    # textbook form puts it at 0.50004, where sigma is 7.9e-9)
+    (lambda: _cubic(sigma_c1=[-4.0], sigma_c2=[4.0], sigma_c3=[-1e-12]), "sigma(x)"),
     (lambda: _cubic(drift_c3=[np.nan]), "not finite"),
     (lambda: workloads.from_edges(2, [0], [1], [np.inf], bin_span=2.0), None),
 ])

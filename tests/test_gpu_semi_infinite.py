@@ -119,6 +119,7 @@ def test_init_rules_and_uniform_bins_on_a_span(B, orc):
     acc, osnaps, _ = orc.observed_histogram(g, st, 0, 500, dt, 5, 25, bins)
     r = B.mg_particles_read(p, trace=True)
     nd = int((r["seqhash"] != st.seqhash).sum())
+    assert nd <= n // 10_000 + 1, nd          # the bound below uses nd
     assert snaps == osnaps == 20
     assert np.abs(h.astype(np.int64).ravel() - acc.astype(np.int64).ravel()).sum() <= 2 * snaps * nd
     # a semi-infinite edge needs a bin span
