@@ -47,7 +47,8 @@ class _Graph(C.Structure):
                 ("vtx_kind", C.c_void_p), ("bin_span", C.c_void_p),
                 ("drift_c2", C.c_void_p), ("drift_c3", C.c_void_p),
                 ("sigma_c1", C.c_void_p), ("sigma_c2", C.c_void_p),
-                ("sigma_c3", C.c_void_p)]
+                ("sigma_c3", C.c_void_p), ("vtx_kill", C.c_void_p),
+                ("vtx_sticky", C.c_void_p)]
 
 HIGHER = ("drift_c2", "drift_c3", "sigma_c1", "sigma_c2", "sigma_c3")
 
@@ -125,7 +126,7 @@ class OracleGraph:
         if not np.all(np.isfinite(self._keep["bin_span"])):
             raise ValueError("a semi-infinite edge needs a finite bin_span")
         kind, off = self._keep["vtx_kind"], self._keep["vtx_offsets"]
-        if np.any(kind > 2):
+        if np.any(kind > 3):
             raise ValueError("unknown vertex kind")
         if np.any((kind == 2) & (np.diff(off) != 1)):
             raise ValueError("a mirror vertex must be a leaf (exactly one slot)")
@@ -138,6 +139,15 @@ class OracleGraph:
                 continue
             self._keep[n] = np.ascontiguousarray(
                 np.broadcast_to(np.asarray(v, np.float64), (int(desc.n_edges),)))
+            hi.append(self._keep[n].ctypes.data)
+        # Wentzell vertices (kind 3): a_v and c_v, read only at such vertices
+        for n in ("vtx_kill", "vtx_sticky"):
+            v = getattr(desc, n, None)
+            if v is None:
+                hi.append(None)
+                continue
+            self._keep[n] = np.ascontiguousarray(
+                np.broadcast_to(np.asarray(v, np.float64), (int(desc.n_vertices),)))
             hi.append(self._keep[n].ctypes.data)
         k = self._keep
         self.c = _Graph(int(desc.n_vertices), int(desc.n_edges),

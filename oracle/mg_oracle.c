@@ -36,6 +36,10 @@
  *                 Box-Muller pair (o1,o2) drives the sub-step after it.
  *   init stream   ctr = (p, 0xFFFFFFFF, 0xFFFFFFFF, tag): o0 picks the edge,
  *                 o1 the position.
+ *   vertex stream ctr = (p, n, 0x100 + k, tag) at a Wentzell vertex: for the
+ *                 k-th hit of step n (k >= 1), or for a step that starts on
+ *                 a sticky vertex (k = 0); o0 decides the killing, o1 the
+ *                 holding time.
  */
 #include <math.h>
 #include <stdint.h>
@@ -149,6 +153,9 @@ typedef struct {
      + s3 x^3 (Sec. 2.2 allows any C^1 coefficients) */
   const double *drift_c2, *drift_c3;
   const double *sigma_c1, *sigma_c2, *sigma_c3;
+  /* [V] each, or NULL: a_v and c_v of a Wentzell vertex (kind 3), read
+     only at such vertices (Sec. 2.2, the general gluing condition) */
+  const double *vtx_kill, *vtx_sticky;
 } or_graph;
 
 /* Cubic p0 + p1 x + p2 x^2 + p3 x^3 by Horner's rule; NULL higher arrays
@@ -208,6 +215,117 @@ static int32_t pick_slot(const or_graph *g, const uint64_t *thr, int32_t v,
   for (int32_t s = s0; s < s1; ++s)
     if ((uint64_t)r < thr[s]) return s;
   return s1 - 1;
+}
+
+/* -------------------------------------------------- Wentzell vertices */
+/*
+ * Reading A27 (Sec. 2.2, the Wentzell gluing condition
+ * a_v f(v) - sum_e b_ve f'_e(v) + c_v (L f)(v) = 0 with a_v + sum b + c_v = 1;
+ * the paper writes the last term as c_v f''(v)/2, the generator of its
+ * standard Brownian motion).  With beta_v = sum_e b_ve the process leaves v
+ * into edge e with probability b_ve / beta_v, is killed at rate
+ * kappa_v = a_v / beta_v per unit of its local time at v, and spends
+ * gamma_v = c_v / beta_v units of time on v per unit of that local time
+ * (local time in units of length: the reflection term of the distance to v).
+ *
+ * In the split scheme a visit of v is a hit (or a step that starts on v)
+ * followed by the sub-step that leaves v.  The local time of a visit is its
+ * share of the reflection term of the distance to v: the overshoot o of the
+ * proposal that crossed v (how far past v the free move would have gone)
+ * plus the mean local time sigma_v sqrt(2 h'' / pi) of the reflected move
+ * of length h'' that leaves v (Levy: the local time of reflected Brownian
+ * motion has the law of |B|).  Over many visits these add up to the local
+ * time whatever the density next to v looks like.  Per visit:
+ *   - the particle first stays on v for gamma_v l, then moves for h'',
+ *     with h'' + gamma_v (o + sigma_v sqrt(2 h'' / pi)) = h (the time left
+ *     in the step); when gamma_v o >= h it stays on v for all of h and
+ *     owes the rest of its stay, which it works off at the start of the
+ *     next steps and then leaves v with a visit of its own (o = 0);
+ *   - it is killed with probability 1 - exp(-kappa_v l) (o alone while it
+ *     stays on v for the rest of the step; the move's part when it leaves).
+ * sigma_v is the b-weighted mean of the incident edges' diffusion at v
+ * (sigma is continuous at vertices in the paper; then this is its value).
+ * A particle owing a stay sits on v; its position field holds the time it
+ * still owes as a signed offset beyond the end it sits on (-t at the
+ * initial end, L + t at the terminal end).
+ */
+typedef struct {
+  double *kappa;    /* [V] a_v / beta_v (0: no killing) */
+  double *gamma;    /* [V] c_v / beta_v (0: not sticky) */
+  double *sigma_v;  /* [V] diffusion at v */
+} or_wentzell;
+
+static const double OR_PI = 3.14159265358979323846264338327950288;
+
+static int wentzell_params(const or_graph *g, or_wentzell *wz) {
+  const int32_t V = g->n_vertices;
+  const size_t nv = (size_t)(V > 0 ? V : 1);
+  wz->kappa = (double *)calloc(nv, sizeof(double));
+  wz->gamma = (double *)calloc(nv, sizeof(double));
+  wz->sigma_v = (double *)calloc(nv, sizeof(double));
+  if (!wz->kappa || !wz->gamma || !wz->sigma_v) return -2;
+  for (int32_t v = 0; v < V; ++v) {
+    if (!g->vtx_kind || g->vtx_kind[v] != 3) continue;
+    const int32_t s0 = g->vtx_offsets[v], s1 = g->vtx_offsets[v + 1];
+    double beta = 0.0, sig = 0.0;
+    for (int32_t s = s0; s < s1; ++s) beta += g->slot_jump_prob[s];
+    if (!(beta > 0.0)) return -1;
+    for (int32_t s = s0; s < s1; ++s) {
+      const int32_t e = g->slot_edge[s];
+      const double at = g->slot_orient[s] ? g->length[e] : 0.0;
+      sig += (g->slot_jump_prob[s] / beta) * sigma_at(g, e, at);
+    }
+    wz->kappa[v] = (g->vtx_kill ? g->vtx_kill[v] : 0.0) / beta;
+    wz->gamma[v] = (g->vtx_sticky ? g->vtx_sticky[v] : 0.0) / beta;
+    wz->sigma_v[v] = sig;
+  }
+  return 0;
+}
+
+static void wentzell_free(or_wentzell *wz) {
+  free(wz->kappa);
+  free(wz->gamma);
+  free(wz->sigma_v);
+}
+
+/* Vertex-stream draw for visit k (k-th hit, or 0 for a step start). */
+static uint32_t vertex_draw(uint32_t p, uint64_t n, uint32_t k, uint32_t tag,
+                            uint64_t seed) {
+  uint32_t ctr[4] = {p, (uint32_t)n, 0x100u + k, tag};
+  uint32_t o[4];
+  philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), o);
+  return o[0];
+}
+
+/*
+ * One visit of Wentzell vertex v with overshoot o and time h left in the
+ * step.  Returns 1 if the particle is killed.  Otherwise *h_move is the
+ * length of the move that leaves v (0: the particle stays on v for the
+ * rest of the step) and *owed the stay it still owes after this step.
+ */
+static int wentzell_visit(const or_wentzell *wz, int32_t v, double o, double h,
+                          uint32_t kill_bits, double *h_move, double *owed) {
+  const double gam = wz->gamma[v], sig = wz->sigma_v[v];
+  const double c = sig * sqrt(2.0 / OR_PI);  /* mean local time of a move: c sqrt(h'') */
+  double hm, lt;
+  *owed = 0.0;
+  if (gam == 0.0) {
+    hm = h;
+    lt = o + c * sqrt(h);
+  } else if (gam * o >= h) {
+    hm = 0.0;
+    lt = o;
+    *owed = gam * o - h;
+  } else {
+    /* s = sqrt(h'') solves s^2 + gam c s - (h - gam o) = 0 (s >= 0), in the
+       cancellation-free form 2 r / (b + sqrt(b^2 + 4 r)) */
+    const double b = gam * c, r = h - gam * o;
+    const double sq = 2.0 * r / (b + sqrt(b * b + 4.0 * r));
+    hm = sq * sq;
+    lt = o + c * sq;
+  }
+  *h_move = hm;
+  return wz->kappa[v] > 0.0 && unit_open(kill_bits) < -expm1(-wz->kappa[v] * lt);
 }
 
 /* --------------------------------------------------------- crossing time */
@@ -285,7 +403,8 @@ typedef struct {
  * measured from e's initial vertex, alive flag.  A position equal to 0 or to
  * L_e means the particle sits on that vertex.
  */
-static void run_particle(const or_graph *g, const uint64_t *thr, uint32_t p,
+static void run_particle(const or_graph *g, const uint64_t *thr,
+                         const or_wentzell *wz, uint32_t p,
                          int32_t *e_io, double *x_io, uint8_t *alive_io,
                          uint64_t *hash_io, uint32_t *hits_io, uint64_t n0,
                          uint64_t n_steps, double dt, uint64_t seed,
@@ -302,6 +421,49 @@ static void run_particle(const or_graph *g, const uint64_t *thr, uint32_t p,
     int32_t k = 0;           /* vertex hits in this step */
     int32_t last_slot = -1;  /* slot of the last hit */
     double w = main_normal(p, n, tag, seed);
+    /* A step that starts on a Wentzell vertex (reading A27): a particle that
+       owes a stay there works it off first; one that sits on the vertex, or
+       has just finished its stay, leaves it with a visit of its own.  A step
+       that ends where it started (on the vertex, or killed at the visit)
+       counts its one sub-step without a move. */
+    {
+      const double L0 = g->length[e];
+      int32_t v0 = -1;
+      int init0 = 0;
+      double owe = 0.0;
+      if (x <= 0.0) {
+        v0 = g->edge_init[e];
+        init0 = 1;
+        owe = -x;
+      } else if (x >= L0) {
+        v0 = g->edge_term[e];
+        owe = x - L0;
+      }
+      if (v0 >= 0 && g->vtx_kind && g->vtx_kind[v0] == 3) {
+        if (owe >= h) {
+          owe = owe - h;
+          x = init0 ? -owe : L0 + owe;
+          cnt->substeps++;
+          continue;
+        }
+        h = h - owe;
+        x = init0 ? 0.0 : L0;
+        double hm, owed;
+        if (wentzell_visit(wz, v0, 0.0, h, vertex_draw(p, n, 0u, tag, seed), &hm, &owed)) {
+          alive = 0;
+          cnt->absorbed[v0]++;
+          cnt->substeps++;
+          hash = fnv_word(fnv_word(hash, (uint32_t)n), 0x80000000u | (uint32_t)v0);
+          continue;
+        }
+        if (hm == 0.0) {
+          x = init0 ? -owed : L0 + owed;
+          cnt->substeps++;
+          continue;
+        }
+        h = hm;
+      }
+    }
     for (;;) {
       const double L = g->length[e];
       /* At a vertex the normal is used by magnitude, pointing into the edge
@@ -340,7 +502,17 @@ static void run_particle(const or_graph *g, const uint64_t *thr, uint32_t p,
       k++;
       hits++;
       cnt->hits++;
-      if (g->vtx_kind && g->vtx_kind[v] == 1) { /* absorbing (reading A17) */
+      /* Wentzell vertex (reading A27): the visit that starts with this hit,
+         its overshoot being how far past v the proposal went. */
+      const int wentzell = g->vtx_kind && g->vtx_kind[v] == 3;
+      double h_move = h, owed = 0.0;
+      int killed = 0;
+      if (wentzell) {
+        const double o = hit_init ? -xt : xt - L;
+        killed = wentzell_visit(wz, v, o, h, vertex_draw(p, n, (uint32_t)k, tag, seed),
+                                &h_move, &owed);
+      }
+      if (killed || (g->vtx_kind && g->vtx_kind[v] == 1)) { /* absorbing (reading A17) */
         alive = 0;
         cnt->absorbed[v]++;
         hash = fnv_word(fnv_word(hash, (uint32_t)n), 0x80000000u | (uint32_t)v);
@@ -363,6 +535,13 @@ static void run_particle(const or_graph *g, const uint64_t *thr, uint32_t p,
         tr->step[tr->len] = n; tr->k[tr->len] = k; tr->vertex[tr->len] = v;
         tr->slot[tr->len] = s; tr->u[tr->len] = u; tr->h_after[tr->len] = h;
         tr->len++;
+      }
+      if (wentzell) {
+        h = h_move;
+        if (h == 0.0) {        /* stays on v for the rest of the step */
+          x = g->slot_orient[s] ? g->length[e] + owed : -owed;
+          break;
+        }
       }
       if (h == 0.0) break;     /* the step ended exactly on the vertex */
       if (k == max_splits) {   /* split cap reached: drop the rest (A9) */
@@ -396,10 +575,13 @@ int or_simulate(const or_graph *g, int64_t count, const uint32_t *pid,
   uint64_t *thr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nnz > 0 ? nnz : 1));
   if (!thr) return -2;
   if (or_thresholds(g, thr) != 0) { free(thr); return -1; }
+  or_wentzell wz;
+  const int wrc = wentzell_params(g, &wz);
+  if (wrc != 0) { wentzell_free(&wz); free(thr); return wrc; }
   if (n_threads < 1) n_threads = 1;
   int64_t nth = n_threads;
   uint64_t *priv = (uint64_t *)calloc((size_t)nth * (size_t)(nnz + V + 3), sizeof(uint64_t));
-  if (!priv) { free(thr); return -2; }
+  if (!priv) { wentzell_free(&wz); free(thr); return -2; }
 #pragma omp parallel for schedule(dynamic, 64) num_threads(n_threads)
   for (int64_t i = 0; i < count; ++i) {
     int tid = 0;
@@ -411,7 +593,7 @@ int or_simulate(const or_graph *g, int64_t count, const uint32_t *pid,
     c.exit_slot = base;
     c.absorbed = base + nnz;
     c.truncations = 0; c.substeps = 0; c.hits = 0;
-    run_particle(g, thr, pid[i], &edge[i], &x[i], &alive[i], &hash[i], &hits[i],
+    run_particle(g, thr, &wz, pid[i], &edge[i], &x[i], &alive[i], &hash[i], &hits[i],
                  n0, n_steps, dt, seed, tag, max_splits, &c, NULL);
     base[nnz + V] += c.truncations;
     base[nnz + V + 1] += c.substeps;
@@ -426,6 +608,7 @@ int or_simulate(const or_graph *g, int64_t count, const uint32_t *pid,
     scalars[2] += base[nnz + V + 2];
   }
   free(priv);
+  wentzell_free(&wz);
   free(thr);
   return 0;
 }
@@ -446,9 +629,13 @@ int or_simulate_traced(const or_graph *g, uint32_t pid, int32_t *edge, double *x
   or_counts c;
   c.exit_slot = exit_slot; c.absorbed = absorbed;
   c.truncations = 0; c.substeps = 0; c.hits = 0;
+  or_wentzell wz;
+  const int wrc = wentzell_params(g, &wz);
+  if (wrc != 0) { wentzell_free(&wz); free(thr); return wrc; }
   or_trace tr = {cap, 0, t_step, t_k, t_vertex, t_slot, t_u, t_h};
-  run_particle(g, thr, pid, edge, x, alive, hash, hits, n0, n_steps, dt, seed,
+  run_particle(g, thr, &wz, pid, edge, x, alive, hash, hits, n0, n_steps, dt, seed,
                tag, max_splits, &c, &tr);
+  wentzell_free(&wz);
   scalars[0] += c.truncations;
   scalars[1] += c.substeps;
   scalars[2] += c.hits;

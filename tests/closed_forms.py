@@ -127,3 +127,89 @@ def theorem2_bound(k, gamma):
 
 def norm_sf(x):
     return 0.5 * special.erfc(x / np.sqrt(2))
+
+
+# ------------------------------------------------------- Wentzell vertices
+# A vertex with the general gluing condition a f(v) - sum_e b_e f'_e(v) +
+# c (L f)(v) = 0 (beta = sum_e b_e): killing at rate kappa = a / beta per
+# unit of local time at v (local time in units of length, the reflection
+# term of the distance to v), and gamma = c / beta units of time spent on v
+# per unit of local time.  For zero drift and diffusion sigma the density u
+# on an edge then satisfies u_x(v) = kappa u(v) (mass is lost at the rate
+# kappa times the local-time rate sigma^2 u(v) / 2), and the resolvent of
+# the process started on v follows from excursion theory: the inverse local
+# time of reflected Brownian motion has Laplace exponent sqrt(2 lambda) /
+# sigma, so E_v int e^{-lambda t} 1{X_t = v} dt =
+# gamma / (sqrt(2 lambda) / sigma + gamma lambda + kappa).
+
+
+def robin_segment_survival(t, length, sigma, kappa, n_terms=400):
+    """P(alive at t) on [0, length] from the uniform law, killing rate kappa
+    per unit local time at 0 (u_x(0) = kappa u(0)), reflecting at length.
+    Eigenfunctions cos(k (length - x)) with k tan(k length) = kappa."""
+    from scipy import optimize
+    D = 0.5 * sigma * sigma
+    ks = []
+    for n in range(n_terms):
+        lo, hi = n * np.pi / length, (n + 0.5) * np.pi / length
+        ks.append(optimize.brentq(lambda k: k * np.tan(k * length) - kappa,
+                                  lo + 1e-12 / length, hi - 1e-12 / length))
+    k = np.array(ks)
+    integral = np.sin(k * length) / k
+    norm = length / 2 + np.sin(2 * k * length) / (4 * k)
+    return float((integral ** 2 / norm / length * np.exp(-D * k * k * t)).sum())
+
+
+def _sticky_roots(sigma, gamma, kappa):
+    """Roots r of s^2 + a s + kappa / gamma, a = sqrt(2) / (gamma sigma):
+    the atom's resolvent is 1 / ((sqrt(lambda) - r1)(sqrt(lambda) - r2))."""
+    a = np.sqrt(2.0) / (gamma * sigma)
+    disc = np.sqrt(complex(a * a - 4.0 * kappa / gamma))
+    return (-a + disc) / 2.0, (-a - disc) / 2.0
+
+
+def sticky_halfline_at_vertex(t, sigma, gamma, kappa=0.0):
+    """P(X_t = v, alive) for the process started on v on a half-line [0, inf)
+    (one edge, zero drift).  The inverse Laplace transform of
+    1 / ((sqrt(l) - r1)(sqrt(l) - r2)) is
+    (r1 erfcx(-r1 sqrt t) - r2 erfcx(-r2 sqrt t)) / (r1 - r2); with kappa = 0
+    it is erfcx(sqrt(2 t) / (gamma sigma))."""
+    from scipy import special
+    if kappa == 0.0:
+        return float(special.erfcx(np.sqrt(2.0 * t) / (gamma * sigma)))
+    r1, r2 = _sticky_roots(sigma, gamma, kappa)
+    st = np.sqrt(t)
+    v = (r1 * special.erfcx(-r1 * st) - r2 * special.erfcx(-r2 * st)) / (r1 - r2)
+    return float(np.real(v))
+
+
+def sticky_halfline_alive(t, sigma, gamma, kappa):
+    """P(alive at t) from v on the half-line: mass is lost at kappa times the
+    local-time rate, and the time on v is gamma times the local time, so
+    d/dt P(alive) = -(kappa / gamma) P(X_t = v)."""
+    from scipy import integrate
+    if kappa == 0.0:
+        return 1.0
+    val, _ = integrate.quad(lambda u: sticky_halfline_at_vertex(u, sigma, gamma, kappa),
+                            0.0, t, limit=200)
+    return 1.0 - kappa / gamma * val
+
+
+def killing_halfline_alive(t, sigma, kappa):
+    """P(alive at t) from v on a half-line with killing only: E exp(-kappa l_t)
+    with l_t distributed as |sigma B_t| (Levy), i.e. erfcx(kappa sigma
+    sqrt(t / 2))."""
+    from scipy import special
+    return float(special.erfcx(kappa * sigma * np.sqrt(t / 2.0)))
+
+
+def sticky_star_stationary(lengths, b_hat, sigma, gamma):
+    """Stationary law on a finite star with zero drift, constant sigma,
+    reflecting leaves and a sticky centre: density C b_e / D on edge e
+    (D = sigma^2 / 2) and an atom gamma C on the centre (gamma times the
+    local-time rate D sum_e pi_e(0) = C).  Returns (atom, per-edge masses)."""
+    lengths = np.asarray(lengths, np.float64)
+    b_hat = np.asarray(b_hat, np.float64)
+    D = 0.5 * sigma * sigma
+    C = 1.0 / (float((b_hat * lengths).sum()) / D + gamma)
+    return gamma * C, C * b_hat * lengths / D

@@ -24,6 +24,7 @@ SEQ = "tests/test_oracle_split_sequences.py::"
 SRCS = "tests/test_oracle_sources.py::"
 MIR = "tests/test_oracle_mirror.py::"
 COEF = "tests/test_oracle_coefficients.py::"
+WZ = "tests/test_oracle_wentzell.py::"
 
 MUTANTS = {
     "drift_sign": (
@@ -70,7 +71,7 @@ MUTANTS = {
          ("last_slot = s;\n", "last_slot = s;\n      cnt->exit_slot[s]++;\n")],
         CF + "test_exit_law_matches_renewal_equation"),
     "absorption_ignored": (
-        [("if (g->vtx_kind && g->vtx_kind[v] == 1) {", "if (0) {")],
+        [("if (killed || (g->vtx_kind && g->vtx_kind[v] == 1)) {", "if (killed) {")],
         CF + "test_absorbing_vertex_survival"),
     "philox_multiplier": (
         [("#define OR_PHILOX_M1 0xCD9E8D57u", "#define OR_PHILOX_M1 0xCD9E8D59u")],
@@ -118,6 +119,26 @@ MUTANTS = {
     "mirror_image_not_checked": (
         [("if (xr > 0.0 && xr < L) {", "if (xr > 0.0) {")],
         MIR + "test_image_outside_the_edge_splits"),
+    "wentzell_gamma_unnormalised": (
+        [("wz->gamma[v] = (g->vtx_sticky ? g->vtx_sticky[v] : 0.0) / beta;",
+          "wz->gamma[v] = (g->vtx_sticky ? g->vtx_sticky[v] : 0.0);")],
+        WZ + "test_sticky_halfline_from_vertex"),
+    "wentzell_kill_ignores_move": (
+        [("lt = o + c * sqrt(h);", "lt = o;")],
+        WZ + "test_robin_segment_survival"),
+    "wentzell_overshoot_dropped": (
+        [("const double o = hit_init ? -xt : xt - L;", "const double o = 0.0;")],
+        WZ + "test_robin_segment_survival"),
+    "wentzell_sigma_v_ignored": (
+        [("sig += (g->slot_jump_prob[s] / beta) * sigma_at(g, e, at);",
+          "sig += g->slot_jump_prob[s] / beta;")],
+        WZ + "test_killing_halfline_from_vertex"),
+    "wentzell_owed_dropped": (
+        [("*owed = gam * o - h;", "*owed = 0.0;")],
+        WZ + "test_sticky_halfline_from_vertex"),
+    "wentzell_move_stay_dropped": (
+        [("const double b = gam * c, r = h - gam * o;", "const double b = 0.0, r = h - gam * o;")],
+        WZ + "test_sticky_star_stationary_atom"),
     "far_end_not_checked": (
         [("if (xt > 0.0 && xt < L) {", "if (xt > 0.0) {")],
         CF + "test_radial_reflected_heat_kernel_converges"),

@@ -18,7 +18,9 @@ Graph description (same fields as the C-ABI ``mg_graph_desc``):
   at x = 0), 1 means its terminal vertex (enters at x = L).  The jump
   probabilities b_{v,e} of the standard gluing conditions sum to 1 per vertex.
 * ``vtx_kind[v]``: 0 standard vertex, 1 absorbing vertex, 2 mirror vertex
-  (a leaf that reflects a proposal leaving through it into the edge).
+  (a leaf that reflects a proposal leaving through it into the edge), 3
+  Wentzell vertex with ``vtx_kill[v]`` = a_v and ``vtx_sticky[v]`` = c_v; its
+  jump probabilities then sum to 1 - a_v - c_v.
 * A semi-infinite edge has ``length`` = inf; its terminal vertex is a vertex
   at infinity of its own (one slot, never reached).
 * ``bin_span[e]`` (optional): the length of e the uniform histograms cover
@@ -64,6 +66,10 @@ class GraphDesc:
     sigma_c1: np.ndarray | None = None
     sigma_c2: np.ndarray | None = None
     sigma_c3: np.ndarray | None = None
+    # Wentzell vertices (vtx_kind 3): a_v (killing) and c_v (stickiness) per
+    # vertex, with a_v + sum_e b_ve + c_v = 1 (None: zero)
+    vtx_kill: np.ndarray | None = None
+    vtx_sticky: np.ndarray | None = None
 
     @property
     def nnz(self) -> int:
