@@ -256,6 +256,27 @@ mg_status mg_histogram_csr(const mg_particles *p, const int32_t *bin_offsets,
                            const double *bin_upper, uint64_t *out, int64_t out_len);
 
 /*
+ * mg_histogram_csr without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, validation and result as
+ * mg_histogram_csr.  The bin tables, and the counters when `out` is host
+ * memory, are staged in a fixed workspace of MG_NOALLOC_SCRATCH_BYTES per
+ * GPU (a device array of the library, created when the library loads on
+ * that GPU and held until the process ends): offsets and boundaries take
+ * 256-byte-aligned 4 (E + 1) + 8 bin_offsets[E] bytes, plus
+ * 8 bin_offsets[E] for a host `out` (about 2e6 bins with host output).
+ * Larger tables give MG_EINVAL.  The call allocates no memory (no hipMalloc,
+ * hipFree or allocating library routine), clears the counters with a
+ * kernel, and synchronises the set's stream.  Every call on one GPU shares
+ * that GPU's workspace: calls that overlap on one GPU (other threads,
+ * other streams) race and must be serialised by the caller.
+ */
+#define MG_NOALLOC_SCRATCH_BYTES (32u << 20)
+mg_status mg_histogram_csr_noalloc(const mg_particles *p, const int32_t *bin_offsets,
+                                   const double *bin_upper, uint64_t *out,
+                                   int64_t out_len);
+
+/*
  * Streamed (time-averaged) histogram, accumulated inside the step kernels.
  * After this call, whenever a step brings the set's step counter to a
  * multiple of `every` (1 <= every <= 2^30), every alive particle adds one

@@ -28,7 +28,7 @@ EXPORTED = (
     "mg_histogram",
     "mg_exit_counts", "mg_particles_read", "mg_particles_step", "mg_batch_create",
     "mg_batch_simulate", "mg_batch_destroy", "mg_autotune", "mg_histogram_csr",
-    "mg_observe_histogram",
+    "mg_histogram_csr_noalloc", "mg_observe_histogram",
     "mg_observed_histogram", "mg_density_l2", "mg_last_error",
 )
 
@@ -99,6 +99,7 @@ def lib() -> C.CDLL:
         L.mg_batch_destroy.restype = None
         L.mg_autotune.argtypes = [vp, C.c_double, u64, i32, vp]
         L.mg_histogram_csr.argtypes = [vp, vp, vp, vp, i64]
+        L.mg_histogram_csr_noalloc.argtypes = [vp, vp, vp, vp, i64]
         L.mg_observe_histogram.argtypes = [vp, i32, i32]
         L.mg_observed_histogram.argtypes = [vp, vp, i64, vp]
         L.mg_density_l2.argtypes = [vp, i32, vp, C.c_double, vp, vp]
@@ -309,6 +310,24 @@ def mg_histogram_csr(p: Particles, bin_offsets, bin_upper) -> np.ndarray:
     out = np.zeros(max(int(off[-1]), 1), np.uint64)
     _check(lib().mg_histogram_csr(p.handle, _p(off), _p(up), _p(out), out.size))
     return out[: int(off[-1])]
+
+
+def mg_histogram_csr_noalloc(p: Particles, bin_offsets, bin_upper, out=None) -> np.ndarray:
+    """mg_histogram_csr staged in the library's fixed per-GPU workspace
+    instead of allocated device memory.  ``out``: an optional uint64 numpy
+    array or device tensor of at least bin_offsets[E] counters (default: a
+    new host array); returns the counts."""
+    off = np.ascontiguousarray(np.asarray(bin_offsets, np.int32))
+    up = np.ascontiguousarray(np.asarray(bin_upper, np.float64))
+    nb = int(off[-1])
+    if out is None:
+        out = np.zeros(max(nb, 1), np.uint64)
+    if isinstance(out, np.ndarray):
+        _check(lib().mg_histogram_csr_noalloc(p.handle, _p(off), _p(up), _p(out), out.size))
+        return out[:nb]
+    _check(lib().mg_histogram_csr_noalloc(p.handle, _p(off), _p(up),
+                                          C.c_void_p(out.data_ptr()), out.numel()))
+    return out[:nb]
 
 
 def mg_observe_histogram(p: Particles, bins_per_edge: int, every: int) -> None:

@@ -212,6 +212,33 @@ bool is_device_pointer(const void *ptr) {
   return attr.type == hipMemoryTypeDevice;
 }
 
+// Arguments of the general (CSR) histogram: per-edge bins with strictly
+// increasing finite upper boundaries from 0, and an output of at least
+// bin_offsets[E] counters.  *nbins receives bin_offsets[E].
+mg_status check_csr_bins(const mg_particles *p, const int32_t *bin_offsets,
+                         const double *bin_upper, const uint64_t *out, int64_t out_len,
+                         int64_t *nbins) {
+  if (!p || !bin_offsets || !bin_upper || !out) return fail(MG_EINVAL, "NULL argument");
+  const int32_t E = p->g->E;
+  if (bin_offsets[0] != 0) return fail(MG_EINVAL, "bin_offsets[0] must be 0");
+  for (int32_t e = 0; e < E; ++e) {
+    if (bin_offsets[e + 1] <= bin_offsets[e])
+      return fail(MG_EINVAL, "edge %d has no bins (offsets must increase)", e);
+    double prev = 0.0;
+    for (int32_t k = bin_offsets[e]; k < bin_offsets[e + 1]; ++k) {
+      if (!is_finite(bin_upper[k]) || !(bin_upper[k] > prev))
+        return fail(MG_EINVAL, "bin %d of edge %d: upper boundaries must be finite and "
+                    "strictly increasing from 0", k - bin_offsets[e], e);
+      prev = bin_upper[k];
+    }
+  }
+  *nbins = bin_offsets[E];
+  if (out_len < *nbins)
+    return fail(MG_EINVAL, "out_len %lld < bin_offsets[E] = %lld", (long long)out_len,
+                (long long)*nbins);
+  return MG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -819,24 +846,10 @@ mg_status mg_histogram(const mg_particles *p, int32_t bins_per_edge, uint64_t *o
 mg_status mg_histogram_csr(const mg_particles *p, const int32_t *bin_offsets,
                            const double *bin_upper, uint64_t *out, int64_t out_len) {
   g_err.clear();
-  if (!p || !bin_offsets || !bin_upper || !out) return fail(MG_EINVAL, "NULL argument");
+  int64_t nbins = 0;
+  const mg_status vs = check_csr_bins(p, bin_offsets, bin_upper, out, out_len, &nbins);
+  if (vs != MG_OK) return vs;
   const int32_t E = p->g->E;
-  if (bin_offsets[0] != 0) return fail(MG_EINVAL, "bin_offsets[0] must be 0");
-  for (int32_t e = 0; e < E; ++e) {
-    if (bin_offsets[e + 1] <= bin_offsets[e])
-      return fail(MG_EINVAL, "edge %d has no bins (offsets must increase)", e);
-    double prev = 0.0;
-    for (int32_t k = bin_offsets[e]; k < bin_offsets[e + 1]; ++k) {
-      if (!is_finite(bin_upper[k]) || !(bin_upper[k] > prev))
-        return fail(MG_EINVAL, "bin %d of edge %d: upper boundaries must be finite and "
-                    "strictly increasing from 0", k - bin_offsets[e], e);
-      prev = bin_upper[k];
-    }
-  }
-  const int64_t nbins = bin_offsets[E];
-  if (out_len < nbins)
-    return fail(MG_EINVAL, "out_len %lld < bin_offsets[E] = %lld", (long long)out_len,
-                (long long)nbins);
   const bool dev_out = is_device_pointer(out);
   const size_t o_off = 0, o_up = align_up(sizeof(int32_t) * (E + 1), 256),
                o_out = align_up(o_up + sizeof(double) * nbins, 256),
@@ -860,6 +873,49 @@ mg_status mg_histogram_csr(const mg_particles *p, const int32_t *bin_offsets,
                         p->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
   (void)hipFree(mem);
+  if (he != hipSuccess) return hip_fail(he, "computing the histogram");
+  return check_device_error(p);
+}
+
+mg_status mg_histogram_csr_noalloc(const mg_particles *p, const int32_t *bin_offsets,
+                                   const double *bin_upper, uint64_t *out,
+                                   int64_t out_len) {
+  g_err.clear();
+  int64_t nbins = 0;
+  const mg_status vs = check_csr_bins(p, bin_offsets, bin_upper, out, out_len, &nbins);
+  if (vs != MG_OK) return vs;
+  const int32_t E = p->g->E;
+  const bool dev_out = is_device_pointer(out);
+  // the bin tables (and the counters, for a host `out`) in the fixed
+  // workspace of the set's device, laid out as mg_histogram_csr lays out
+  // its allocation
+  const size_t o_off = 0, o_up = align_up(sizeof(int32_t) * ((size_t)E + 1), 256),
+               o_out = align_up(o_up + sizeof(double) * (size_t)nbins, 256),
+               total = o_out + (dev_out ? 0 : sizeof(uint64_t) * (size_t)nbins);
+  if (total > kNoAllocScratchBytes)
+    return fail(MG_EINVAL, "the bin tables need %zu bytes of workspace, more than the %zu "
+                "of the allocation-free histogram (use mg_histogram_csr)", total,
+                kNoAllocScratchBytes);
+  hipPointerAttribute_t attr;
+  MG_HIP(hipPointerGetAttributes(&attr, p->sd.ef), "finding the set's device");
+  char *mem = nullptr;
+  MG_HIP(noalloc_scratch(attr.device, &mem), "looking up the workspace address");
+  int32_t *d_off = (int32_t *)(mem + o_off);
+  double *d_up = (double *)(mem + o_up);
+  uint64_t *d_out = dev_out ? out : (uint64_t *)(mem + o_out);
+  hipError_t he = hipMemcpyAsync(d_off, bin_offsets, sizeof(int32_t) * ((size_t)E + 1),
+                                 hipMemcpyHostToDevice, p->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(d_up, bin_upper, sizeof(double) * (size_t)nbins,
+                        hipMemcpyHostToDevice, p->stream);
+  if (he == hipSuccess) he = launch_fill_zero_u64(d_out, nbins, p->stream);
+  if (he == hipSuccess)
+    he = launch_histogram_csr(p->g->gd, p->sd, d_off, d_up, (int32_t)nbins, d_out,
+                              p->prec == MG_FP64, p->stream);
+  if (he == hipSuccess && !dev_out)
+    he = hipMemcpyAsync(out, d_out, sizeof(uint64_t) * (size_t)nbins, hipMemcpyDeviceToHost,
+                        p->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
   if (he != hipSuccess) return hip_fail(he, "computing the histogram");
   return check_device_error(p);
 }

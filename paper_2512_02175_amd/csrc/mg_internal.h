@@ -194,4 +194,14 @@ hipError_t launch_histogram_csr(const GraphDev &g, const SetDev &s, const int32_
                                 const double *up, int32_t nbins, uint64_t *out, bool fp64,
                                 hipStream_t st);
 
+// Clears n 64-bit words with a kernel (no memset node in captured work).
+hipError_t launch_fill_zero_u64(uint64_t *p, int64_t n, hipStream_t st);
+
+// Allocation-free entry points stage their tables in one fixed device array
+// per GPU of kNoAllocScratchBytes (32 MiB), whose address on `device` is
+// looked up once (hipGetSymbolAddress, with that device current) and kept.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, char **base);
+
 }  // namespace mg

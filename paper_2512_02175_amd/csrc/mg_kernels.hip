@@ -18,6 +18,7 @@
 //
 // Compiled with -ffp-contract=off: every fused multiply-add is explicit.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "mg_internal.h"
@@ -1891,6 +1892,21 @@ hipError_t launch_histogram_csr(const GraphDev &g, const SetDev &s, const int32_
   return hipGetLastError();
 }
 
+// Clears n 64-bit words (a kernel rather than a memset, so that callers
+// may capture the work in a HIP graph).
+__global__ __launch_bounds__(kBlock) void k_fill_zero_u64(uint64_t *p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) p[i] = 0ull;
+}
+
+hipError_t launch_fill_zero_u64(uint64_t *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_zero_u64, dim3((uint32_t)blocks), dim3(kBlock), 0, st, p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,
                             uint64_t *out, bool fp64, bool tiled, hipStream_t st) {
   const int64_t nbins = (int64_t)g.E * nb;
@@ -1925,3 +1941,39 @@ hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,
 }
 
 }  // namespace mg
+
+// Fixed workspace of the allocation-free entry points: one copy per GPU,
+// created when the library's code object is loaded on that GPU and held
+// until the process ends.  Host code must not take this array's address
+// (in host code the name is a host-side stand-in, not a device address):
+// it uses the per-device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[mg::kNoAllocScratchBytes];
+
+namespace mg {
+
+hipError_t noalloc_scratch(int device, char **base) {
+  static std::mutex mu;
+  static char *addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    addr[device] = (char *)ptr;
+  }
+  *base = addr[device];
+  return hipSuccess;
+}
+
+}  // namespace mg
+
