@@ -128,19 +128,104 @@ def run_pass(B, G, g, run, prec, dt, torch, kernel_times, schedules=None):
                 trunc=int(tot[0]), exit=ex, hist=hist)
 
 
-def cpu_baseline(g, run, n_sample: int, dt: float = 1e-3):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, run, n_sample: int, dt: float = 1e-3, repeats: int = 3,
+                 n_single: int | None = None):
+    """The oracle timed on the host cores: the median of `repeats` runs of
+    particle ids 0..n_sample-1 with all threads (OMP_NUM_THREADS, else every
+    core this process may use), and the median of `repeats` single-thread
+    runs of the first n_single ids; the particle loop only (the initial
+    states are drawn before the clock starts)."""
+    import numpy as np
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    st = oracle.init(g, run["n_particles"], oracle.INIT_UNIFORM_LENGTH, seed=0,
-                     pids=__import__("numpy").arange(n_sample))
-    t0 = time.perf_counter()
-    c = oracle.simulate(g, st, 0, run["n_steps"], dt, run["seed"], threads=threads,
-                        max_splits=run["max_splits"])
-    el = time.perf_counter() - t0
-    return {"value": c.substeps / el, "unit": "particle-substeps/s", "cores": threads,
-            "kind": "oracle",
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    threads = int(os.environ.get("OMP_NUM_THREADS", affinity or os.cpu_count() or 1))
+    n_single = n_single or max(1, n_sample // 10)
+
+    def timed(n, th):
+        rates, subs, els = [], [], []
+        for _ in range(repeats):
+            st = oracle.init(g, run["n_particles"], oracle.INIT_UNIFORM_LENGTH, seed=0,
+                             pids=np.arange(n))
+            t0 = time.perf_counter()
+            c = oracle.simulate(g, st, 0, run["n_steps"], dt, run["seed"], threads=th,
+                                max_splits=run["max_splits"])
+            el = time.perf_counter() - t0
+            rates.append(c.substeps / el)
+            subs.append(c.substeps)
+            els.append(el)
+        k = int(np.argsort(rates)[len(rates) // 2])
+        return rates[k], subs[k], els[k], rates
+
+    v, sub, el, all_r = timed(n_sample, threads)
+    v1, sub1, el1, all_r1 = timed(n_single, 1)
+    return {"value": v, "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
             "sample": f"particle ids 0..{n_sample - 1} of the same workload at dt={dt:.3g}, "
-                      f"{run['n_steps']} steps, FP64 ({c.substeps} sub-steps in {el:.2f} s)"}
+                      f"{run['n_steps']} steps, FP64, median of {repeats} runs "
+                      f"({sub} sub-steps in {el:.2f} s)",
+            "runs": all_r,
+            "single_thread": {"value": v1, "unit": "particle-substeps/s",
+                              "sample": f"particle ids 0..{n_single - 1}, median of {repeats} "
+                                        f"runs ({sub1} sub-steps in {el1:.2f} s)",
+                              "runs": all_r1},
+            "nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": _cpu_model()}
+
+
+def at_scale(B, torch):
+    """The accuracy targets at 1e8 particles: the synthetic vascular network
+    (20k vertices, 26k edges, 1e8 particles uniform by length, 1e4 steps,
+    64 bins per edge), FP32 and FP64 from the same initial states and random
+    integers; histogram TV, exit-probability error, throughput of both
+    precisions and the FP32 kernel's roofline fraction."""
+    import numpy as np
+    import workloads
+    g, run = workloads.config3()
+    G = B.mg_graph_create(g)
+    n = run["n_particles"]
+    res = {}
+    for prec in (B.MG_FP32, B.MG_FP64):
+        p = B.mg_particles_init(G, n, B.MG_INIT_UNIFORM_LENGTH, init_seed=0, precision=prec,
+                                max_splits=run["max_splits"])
+        if prec == B.MG_FP32:
+            B.mg_autotune(p, run["dt"], run["seed"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        B.mg_simulate(p, run["n_steps"], run["dt"], run["seed"])
+        e1.record()
+        ex, ab, tot = B.mg_exit_counts(p)
+        wall = time.perf_counter() - t0
+        res[prec] = dict(k=e0.elapsed_time(e1) * 1e-3, wall=wall, ex=ex, ab=int(ab.sum()),
+                         sub=int(tot[1]), hits=int(tot[2]), steps=int(tot[3]),
+                         hist=B.mg_histogram(p, run["bins"]))
+        del p
+    r32, r64 = res[B.MG_FP32], res[B.MG_FP64]
+    w, m = exit_err(r32["ex"], r64["ex"], g.vtx_offsets)
+    frac = alg_work(1, r32["steps"], r32["hits"]) / r32["k"] / PEAK_LANE_OPS
+    return {"workload": "vascular20k: 20k vertices, 26k edges, Poiseuille drift, absorbing "
+                        "outlets, 1e8 particles uniform by length, 1e4 steps at 10x the FVM "
+                        "CFL dt, 64 bins/edge, M=8",
+            "n_particles": n, "n_steps": run["n_steps"], "dt": run["dt"],
+            "fp32_substeps_per_s": r32["sub"] / r32["wall"],
+            "fp32_kernel_substeps_per_s": r32["sub"] / r32["k"],
+            "fp64_substeps_per_s": r64["sub"] / r64["wall"],
+            "fp64_kernel_substeps_per_s": r64["sub"] / r64["k"],
+            "tv_fp32_vs_fp64": _tv(r32["hist"], r64["hist"]),
+            "exit_prob_err_fp32_vs_fp64": w, "exit_prob_err_weighted_mean": m,
+            "absorbed_fraction": [r32["ab"] / n, r64["ab"] / n],
+            "roofline_frac": frac, "hits_per_step": r32["hits"] / r32["steps"]}
 
 
 def _tv(a, b):
@@ -598,6 +683,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
+    ap.add_argument("--no-1e8", action="store_true",
+                    help="skip the 1e8-particle accuracy leg of the default workload")
     ap.add_argument("--cpu-sample", type=int, default=40_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB on the device (scale for HBM counters)")
@@ -725,6 +812,8 @@ def main():
         "exit_prob_err_fp32_vs_fp64": exit_e,
         "roofline": roof,
     }
+    if not args.no_1e8:
+        line["at_1e8"] = at_scale(B, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, run, args.cpu_sample)
     print(json.dumps(line), flush=True)
