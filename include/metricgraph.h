@@ -45,7 +45,9 @@ typedef enum {
 
 typedef enum { MG_FP64 = 0, MG_FP32 = 1 } mg_precision;
 
-typedef enum { MG_VTX_STANDARD = 0, MG_VTX_ABSORBING = 1, MG_VTX_MIRROR = 2 } mg_vertex_kind;
+typedef enum {
+  MG_VTX_STANDARD = 0, MG_VTX_ABSORBING = 1, MG_VTX_MIRROR = 2, MG_VTX_WENTZELL = 3
+} mg_vertex_kind;
 
 typedef struct mg_graph mg_graph;          /* opaque */
 typedef struct mg_particles mg_particles;  /* opaque */
@@ -54,7 +56,7 @@ typedef struct mg_batch mg_batch;          /* opaque */
 /*
  * Graph description (Def. 1 metric graph; Def. 4 jump probabilities;
  * Alg. 2's vertex tables).  All pointers are host memory.
- *   n_vertices, n_edges  V >= 1, E >= 1.
+ *   n_vertices, n_edges  1 <= V <= 2^30 - 1, E >= 1.
  *   edge_init/edge_term  [E] vertex ids; x = 0 at edge_init, x = L at edge_term.
  *   length               [E] > 0: finite, or +infinity for a semi-infinite
  *                        edge [0, infinity) (Def. 1 allows l_e = infinity;
@@ -86,7 +88,28 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *                        hit: no split, no hit-stream draw, no exit record of
  *                        its own.  Otherwise (a move longer than the edge, or
  *                        an image on a vertex) the sub-step splits there as at
- *                        a standard leaf.
+ *                        a standard leaf.  A Wentzell vertex has the general
+ *                        gluing condition of Sec. 2.2, a_v f(v) - sum_e b_ve
+ *                        f'_e(v) + c_v (L f)(v) = 0 with a_v + sum_e b_ve +
+ *                        c_v = 1 (a_v = vtx_kill[v], c_v = vtx_sticky[v]):
+ *                        with beta = sum_e b_ve, a particle leaves it into e
+ *                        with probability b_ve / beta, is killed at rate
+ *                        a_v / beta per unit of its local time at v and is
+ *                        held on v for c_v / beta units of time per unit of
+ *                        local time.  The step charges each visit (a hit, or
+ *                        a step that starts on v) its local time: the
+ *                        overshoot of the proposal that crossed v plus
+ *                        sigma_v sqrt(2 h''/pi) for the move of length h''
+ *                        that leaves v (sigma_v the b-weighted mean of the
+ *                        incident edges' diffusion at v); the visit first
+ *                        holds the particle on v, kills it with probability
+ *                        1 - exp(-kappa l), and a stay longer than the rest of
+ *                        the step carries into the next steps.  A killed
+ *                        particle counts in absorbed[v].  Its killing draw is
+ *                        word 0 of Philox (p, n, 0x100 + k, tag) for the visit
+ *                        of hit k of step n (k = 0: the visit at a step's
+ *                        start).  FP32 sets on such a graph run as on graphs
+ *                        with higher coefficient terms (below).
  *   bin_span             [E] the length of edge e that the uniform histograms
  *                        (mg_histogram, mg_observe_histogram, mg_density_l2)
  *                        divide into their bins: bin width bin_span[e] / nb,
@@ -107,6 +130,8 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *                        MG_SCHED_LANES; the other pool schedules are
  *                        refused, and an FP32 batch does not mix them with
  *                        sets on affine graphs (FP64 batches may).
+ *   vtx_kill, vtx_sticky [V] a_v and c_v of Wentzell vertices (finite, >= 0;
+ *                        read only there; NULL: 0).
  * Every edge must appear exactly once at its initial vertex with orient 0
  * and once at its terminal vertex with orient 1 (a self-loop twice at its
  * vertex).  A standard vertex needs at least one slot with b > 0.
@@ -125,6 +150,7 @@ typedef struct {
   const double *bin_span;
   const double *drift_c2, *drift_c3;
   const double *sigma_c1, *sigma_c2, *sigma_c3;
+  const double *vtx_kill, *vtx_sticky;
 } mg_graph_desc;
 
 /* Validates and packs the graph into device tables (edge records, slot
@@ -324,7 +350,9 @@ mg_status mg_exit_counts(const mg_particles *p, uint64_t *slot_counts,
 
 /*
  * Copies particles [first, first + count): edge id, position from the
- * edge's initial vertex (FP64; FP32 sets are converted), alive flag, and,
+ * edge's initial vertex (FP64; FP32 sets are converted; a particle held on
+ * a Wentzell vertex that still owes a stay of t there reads -t at the
+ * edge's initial end, L + t at its terminal end), alive flag, and,
  * for traced sets, the hit-sequence hash (FNV-1a over 32-bit words
  * (step, slot) per hit, (step, 0x80000000 | vertex) for an absorption) and
  * the hit count.  Any pointer may be NULL.  Synchronises the stream.

@@ -38,8 +38,9 @@
  *                 o1 the position.
  *   vertex stream ctr = (p, n, 0x100 + k, tag) at a Wentzell vertex: for the
  *                 k-th hit of step n (k >= 1), or for a step that starts on
- *                 a sticky vertex (k = 0); o0 decides the killing, o1 the
- *                 holding time.
+ *                 a sticky vertex (k = 0); o0 decides the killing (the
+ *                 holding time is not random: gamma_v times the visit's
+ *                 local time).
  */
 #include <math.h>
 #include <stdint.h>

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmetricgraph.so")
 
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ESTATE = 0, 1, 2, 3, 4
 MG_FP64, MG_FP32 = 0, 1
-MG_VTX_STANDARD, MG_VTX_ABSORBING, MG_VTX_MIRROR = 0, 1, 2
+MG_VTX_STANDARD, MG_VTX_ABSORBING, MG_VTX_MIRROR, MG_VTX_WENTZELL = 0, 1, 2, 3
 MG_INIT_EXPLICIT, MG_INIT_AT_VERTEX, MG_INIT_UNIFORM_LENGTH = 0, 1, 2
 MG_SCHED_AUTO, MG_SCHED_LANES, MG_SCHED_POOLS, MG_SCHED_POOLS256, MG_SCHED_POOLS_W8 = 0, 1, 2, 3, 4
 
@@ -49,7 +49,8 @@ class mg_graph_desc(C.Structure):
                 ("vtx_kind", C.c_void_p), ("bin_span", C.c_void_p),
                 ("drift_c2", C.c_void_p), ("drift_c3", C.c_void_p),
                 ("sigma_c1", C.c_void_p), ("sigma_c2", C.c_void_p),
-                ("sigma_c3", C.c_void_p)]
+                ("sigma_c3", C.c_void_p), ("vtx_kill", C.c_void_p),
+                ("vtx_sticky", C.c_void_p)]
 
 
 class mg_options(C.Structure):
@@ -203,6 +204,14 @@ def mg_graph_create(desc) -> Graph:
         else:
             keep[k] = np.ascontiguousarray(
                 np.broadcast_to(np.asarray(v, np.float64), (int(desc.n_edges),)))
+            opt.append(keep[k].ctypes.data)
+    for k in ("vtx_kill", "vtx_sticky"):     # per vertex
+        v = getattr(desc, k, None)
+        if v is None:
+            opt.append(None)
+        else:
+            keep[k] = np.ascontiguousarray(
+                np.broadcast_to(np.asarray(v, np.float64), (int(desc.n_vertices),)))
             opt.append(keep[k].ctypes.data)
     d = mg_graph_desc(int(desc.n_vertices), int(desc.n_edges),
                       *[keep[k].ctypes.data for k in (

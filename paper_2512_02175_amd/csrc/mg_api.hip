@@ -105,8 +105,12 @@ struct mg_graph {
   bool infinite = false;
   std::vector<uint8_t> at_infinity;  // [V]
   // some edge has higher coefficients (mu beyond affine or sigma(x) not
-  // constant): FP64 sets only
+  // constant), some vertex is a Wentzell vertex; gen: either (the kernels'
+  // general instantiation; FP32 sets run the lane schedule or pools of 128
+  // with 8-step windows)
   bool poly = false;
+  bool wentzell = false;
+  bool gen = false;
   void *dev = nullptr;         // one allocation holding every table
   GraphDev gd{};
 };
@@ -145,7 +149,7 @@ struct mg_batch {
   int32_t n_items = 0;
   int32_t max_nnz = 0;
   int32_t max_stage = 0;  // staged table bytes if every set's graph fits, else 0
-  bool poly = false;      // some set's graph has higher coefficients
+  bool gen = false;       // some set's graph has a general method variant
   int32_t kernel = 1;     // FP32 schedule fixed at creation (tile size follows it)
   // Per-call set descriptors go up from pinned memory; the launch chain of a
   // call is a HIP graph of kernel nodes, re-instantiated only when the
@@ -253,6 +257,7 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   const int32_t V = d->n_vertices, E = d->n_edges;
   if (V < 1 || E < 1) return fail(MG_EINVAL, "need at least one vertex and one edge");
   if (E > kMaxEdges) return fail(MG_EINVAL, "too many edges");
+  if (V > kMaxVertices) return fail(MG_EINVAL, "too many vertices (at most 2^30 - 1)");
   if (!d->edge_init || !d->edge_term || !d->length || !d->sigma || !d->vtx_offsets ||
       !d->slot_edge || !d->slot_orient || !d->slot_jump_prob)
     return fail(MG_EINVAL, "a required array is NULL");
@@ -345,11 +350,24 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
       any_pos |= b > 0.0;
     }
     const bool absorbing = d->vtx_kind && d->vtx_kind[v] == MG_VTX_ABSORBING;
-    if (d->vtx_kind && d->vtx_kind[v] > MG_VTX_MIRROR)
+    const bool wz = d->vtx_kind && d->vtx_kind[v] == MG_VTX_WENTZELL;
+    if (d->vtx_kind && d->vtx_kind[v] > MG_VTX_WENTZELL)
       return fail(MG_EINVAL, "vertex %d: unknown kind", v);
     if (d->vtx_kind && d->vtx_kind[v] == MG_VTX_MIRROR && off[v + 1] - off[v] != 1)
       return fail(MG_EINVAL, "mirror vertex %d must be a leaf (exactly one slot)", v);
-    if (!absorbing) {
+    if (wz) {
+      // a_v + sum_e b_ve + c_v = 1 (Sec. 2.2) with a_v, c_v >= 0
+      const double a = d->vtx_kill ? d->vtx_kill[v] : 0.0;
+      const double c = d->vtx_sticky ? d->vtx_sticky[v] : 0.0;
+      if (!is_finite(a) || a < 0.0 || !is_finite(c) || c < 0.0)
+        return fail(MG_EINVAL, "Wentzell vertex %d: vtx_kill and vtx_sticky must be finite "
+                    "and >= 0", v);
+      if (!any_pos)
+        return fail(MG_EINVAL, "Wentzell vertex %d has no positive jump probability", v);
+      if (std::fabs(a + sum + c - 1.0) > 1e-9)
+        return fail(MG_EINVAL, "Wentzell vertex %d: a_v + sum b + c_v = %.17g, not 1", v,
+                    a + sum + c);
+    } else if (!absorbing) {
       if (!any_pos) return fail(MG_EINVAL, "standard vertex %d has no positive jump probability", v);
       if (std::fabs(sum - 1.0) > 1e-9)
         return fail(MG_EINVAL, "vertex %d: jump probabilities sum to %.17g, not 1", v, sum);
@@ -376,7 +394,8 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   std::vector<EdgeRec32> e32(E);
   auto end_id = [&](int32_t v) {
     const bool mirror = d->vtx_kind && d->vtx_kind[v] == MG_VTX_MIRROR;
-    return (int32_t)((uint32_t)v | (mirror ? kMirrorEnd : 0u));
+    const bool wz = d->vtx_kind && d->vtx_kind[v] == MG_VTX_WENTZELL;
+    return (int32_t)((uint32_t)v | (mirror ? kMirrorEnd : 0u) | (wz ? kWentzellEnd : 0u));
   };
   for (int32_t e = 0; e < E; ++e) {
     const double a = d->drift_a ? d->drift_a[e] : 0.0;
@@ -431,6 +450,30 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
     }
     vtx[v] = b;
   }
+  // Wentzell table: per such vertex, beta = sum_e b_ve, kappa = a_v / beta,
+  // gamma = c_v / beta and sigma_v = sum_e (b_ve / beta) sigma_e(v) over
+  // its slots in order, sigma_e(v) the cubic by Horner's rule at the edge's
+  // end (x = 0 or L)
+  std::vector<WzRec> wzt;
+  for (int32_t v = 0; v < V; ++v) {
+    if (!(d->vtx_kind && d->vtx_kind[v] == MG_VTX_WENTZELL)) continue;
+    double beta = 0.0, sig = 0.0;
+    for (int32_t s = off[v]; s < off[v + 1]; ++s) beta += d->slot_jump_prob[s];
+    for (int32_t s = off[v]; s < off[v + 1]; ++s) {
+      const int32_t e = d->slot_edge[s];
+      const double at = d->slot_orient[s] ? d->length[e] : 0.0;
+      const double sv = std::fma(std::fma(std::fma(higher(d->sigma_c3, e), at,
+                                                   higher(d->sigma_c2, e)), at,
+                                          higher(d->sigma_c1, e)), at, d->sigma[e]);
+      sig += (d->slot_jump_prob[s] / beta) * sv;
+    }
+    WzRec r{};
+    r.kappa = (d->vtx_kill ? d->vtx_kill[v] : 0.0) / beta;
+    r.gamma = (d->vtx_sticky ? d->vtx_sticky[v] : 0.0) / beta;
+    r.lt_per_sqrt = sig * std::sqrt(2.0 / 3.14159265358979323846264338327950288);
+    wzt.push_back(r);
+    vtx[v].wz = (uint32_t)wzt.size();
+  }
   // length-proportional init thresholds, built like the slot thresholds
   // (unused on graphs with semi-infinite edges)
   std::vector<uint64_t> lthr(E);
@@ -458,7 +501,9 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   g->infinite = infinite;
   g->at_infinity = at_inf;
   g->poly = poly;
-  g->gd.poly = poly ? 1 : 0;
+  g->wentzell = !wzt.empty();
+  g->gen = g->poly || g->wentzell;
+  g->gd.gen = g->gen ? 1 : 0;
   const size_t ng = guide.size();
   const size_t o_vtx = 0;
   const size_t o_sl = align_up(o_vtx + sizeof(VtxBlk) * V, 16);
@@ -466,7 +511,8 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   const size_t o_32 = align_up(o_gd + 4 * ng, 16);
   const size_t o_64 = align_up(o_32 + sizeof(EdgeRec32) * E, 16);
   const size_t o_lt = align_up(o_64 + sizeof(EdgeRec64) * E, 256);
-  const size_t total = align_up(o_lt + 8 * (size_t)E, 256);
+  const size_t o_wz = align_up(o_lt + 8 * (size_t)E, 256);
+  const size_t total = align_up(o_wz + sizeof(WzRec) * wzt.size(), 256);
   hipError_t he = hipMalloc(&g->dev, total);
   if (he != hipSuccess) {
     delete g;
@@ -480,6 +526,7 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   std::memcpy(host.data() + o_32, e32.data(), sizeof(EdgeRec32) * E);
   std::memcpy(host.data() + o_64, e64.data(), sizeof(EdgeRec64) * E);
   std::memcpy(host.data() + o_lt, lthr.data(), 8 * (size_t)E);
+  if (!wzt.empty()) std::memcpy(host.data() + o_wz, wzt.data(), sizeof(WzRec) * wzt.size());
   he = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
   if (he != hipSuccess) {
     (void)hipFree(g->dev);
@@ -493,6 +540,7 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   g->gd.e32 = (const EdgeRec32 *)(base + o_32);
   g->gd.e64 = (const EdgeRec64 *)(base + o_64);
   g->gd.len_thr = (const uint64_t *)(base + o_lt);
+  g->gd.wz = wzt.empty() ? nullptr : (const WzRec *)(base + o_wz);
   g->gd.n_guide = (int32_t)ng;
   g->gd.o_vtx = (int32_t)o_vtx;
   g->gd.o_slots = (int32_t)o_sl;
@@ -542,10 +590,10 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
   if (o.steps_per_launch < 0) return fail(MG_EINVAL, "steps_per_launch must be >= 0");
   if (o.schedule < MG_SCHED_AUTO || o.schedule > MG_SCHED_POOLS_W8)
     return fail(MG_EINVAL, "unknown schedule");
-  if (g->poly && o.precision == MG_FP32 &&
+  if (g->gen && o.precision == MG_FP32 &&
       (o.schedule == MG_SCHED_POOLS || o.schedule == MG_SCHED_POOLS256))
-    return fail(MG_EINVAL, "graphs with higher coefficients run the FP32 lane schedule or "
-                "MG_SCHED_POOLS_W8 only");
+    return fail(MG_EINVAL, "graphs with higher coefficients or Wentzell vertices run the "
+                "FP32 lane schedule or MG_SCHED_POOLS_W8 only");
   if (mode == MG_INIT_EXPLICIT) {
     if (!edge || !pos) return fail(MG_EINVAL, "explicit init needs edge and pos");
     for (int64_t i = 0; i < n; ++i) {
@@ -737,7 +785,7 @@ static int32_t schedule_of(int32_t kernel) {
 static int32_t fp32_kernel(const mg_particles *p) {
   // cubic coefficients: the lane schedule or pools of 128 with 8-step
   // windows (FP64 sets ignore this)
-  if (p->g->poly && p->prec == MG_FP32) return p->schedule == MG_SCHED_LANES ? 0 : 3;
+  if (p->g->gen && p->prec == MG_FP32) return p->schedule == MG_SCHED_LANES ? 0 : 3;
   if (p->schedule != MG_SCHED_AUTO) return kernel_of(p->schedule);
   return p->tuned ? p->tuned_kernel : 3;
 }
@@ -1093,11 +1141,12 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
     if (sets[i]->trace != sets[0]->trace) return fail(MG_EINVAL, "sets differ in trace");
     if (fp32_kernel(sets[i]) != fp32_kernel(sets[0]))
       return fail(MG_EINVAL, "sets differ in schedule");
-    // the FP32 cubic step evaluates the coefficients at the position, the
-    // affine one uses per-frame constants: one launch cannot give both sets
-    // their own bits
-    if (sets[0]->prec == MG_FP32 && sets[i]->g->poly != sets[0]->g->poly)
-      return fail(MG_EINVAL, "FP32 sets differ in coefficient form (cubic and affine)");
+    // the FP32 general step (cubic coefficients, Wentzell vertices)
+    // evaluates the coefficients at the position, the affine one uses
+    // per-frame constants: one launch cannot give both sets their own bits
+    if (sets[0]->prec == MG_FP32 && sets[i]->g->gen != sets[0]->g->gen)
+      return fail(MG_EINVAL, "FP32 sets differ in coefficient form (general variants: cubic "
+                  "coefficients or Wentzell vertices, and affine)");
     for (int32_t j = 0; j < i; ++j)
       if (sets[j] == sets[i]) return fail(MG_EINVAL, "set %d appears twice", i);
   }
@@ -1114,7 +1163,7 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
     const int32_t st = sets[i]->prec == MG_FP64 ? gd.stage_bytes64 : gd.stage_bytes32;
     all_stage = all_stage && st > 0;
     b->max_stage = std::max(b->max_stage, st);
-    b->poly = b->poly || sets[i]->g->poly;
+    b->gen = b->gen || sets[i]->g->gen;
   }
   if (!all_stage) b->max_stage = 0;
   // Largest sets first so the tail of the launch is made of small tiles.
@@ -1173,7 +1222,7 @@ static hipError_t build_graph(mg_batch *b, int64_t n_steps, const StepArgs &base
     a.nsteps = (uint32_t)std::min<int64_t>(left, chunk);
     a.n0_offset = done;
     const KernelLaunch k = batch_launch(b->n_items, b->max_nnz, b->max_stage, a,
-                                        p0->prec == MG_FP64, p0->trace, b->key_obs, b->poly);
+                                        p0->prec == MG_FP64, p0->trace, b->key_obs, b->gen);
     const GraphDev *g = b->d_graphs;
     const SetDev *sd = b->d_sets;
     const BatchItem *it = b->d_items;
@@ -1254,8 +1303,8 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   if (!p) return fail(MG_EINVAL, "particles is NULL");
   if (!is_finite(dt) || !(dt > 0.0)) return fail(MG_EINVAL, "dt must be finite and > 0");
   mg_tuning res{};
-  if (p->prec == MG_FP32 && p->g->poly) {
-    // one pool schedule is built for cubic coefficients: nothing to probe
+  if (p->prec == MG_FP32 && p->g->gen) {
+    // one pool schedule is built for the general variants: nothing to probe
     res.schedule = MG_SCHED_POOLS_W8;
     res.idle_trigger = pool_idle(p);
     res.pool_size = kPoolSmall;

@@ -20,9 +20,14 @@ constexpr int32_t kMaxEdges = 0x3FFFFFFF;
 // another; finite on a semi-infinite edge).  The end vertex ids of both
 // records carry kMirrorEnd when that end is a mirror vertex (a reflecting
 // leaf: a proposal leaving the edge there takes its mirror image when that
-// lies inside the edge), so the step reads the flag with the edge.
+// lies inside the edge), so the step reads the flag with the edge, and
+// kWentzellEnd when it is a Wentzell vertex (killing and stickiness), so a
+// step that starts on a vertex knows without a table load whether it first
+// visits that vertex.
 constexpr uint32_t kMirrorEnd = 0x80000000u;
-constexpr int32_t kVertexMask = 0x7FFFFFFF;
+constexpr uint32_t kWentzellEnd = 0x40000000u;
+constexpr int32_t kVertexMask = 0x3FFFFFFF;
+constexpr int32_t kMaxVertices = 0x3FFFFFFF;
 struct alignas(16) EdgeRec64 {
   double L, a, c, sigma;  // length, drift a + c x, diffusion
   int32_t vinit, vterm;   // end vertices (| kMirrorEnd at a mirror vertex)
@@ -52,12 +57,28 @@ struct alignas(16) EdgeRec32 {
 //   threshold every 32-bit draw lies below).  The last slot needs none.
 // deg > 3: t0 = offset of the vertex's guide table, t1 = the shift that maps
 //   a draw to its guide bucket; slots are read from the slot table.
+//   wz     Wentzell vertex: 1 + its row in the Wentzell table; else 0.
 struct alignas(16) VtxBlk {
   int32_t first;
   int32_t deg;
   uint32_t t0, t1;
   uint32_t eo0, eo1, eo2;
-  uint32_t pad;
+  uint32_t wz;
+};
+
+// Wentzell vertex v (the general gluing condition a_v f(v) - sum_e b_ve
+// f'_e(v) + c_v (L f)(v) = 0, a_v + sum_e b_ve + c_v = 1), with
+// beta = sum_e b_ve: a visit of v with local time l kills with probability
+// 1 - exp(-kappa l) and holds the particle on v for gamma l.  The local time
+// of a visit is its overshoot o plus lt_per_sqrt sqrt(h'') for a move of
+// length h'' away from v (the mean local time of a reflected move:
+// sigma_v sqrt(2/pi), sigma_v the b-weighted mean of the incident edges'
+// diffusion at v).
+struct alignas(16) WzRec {
+  double kappa;        // a_v / beta
+  double gamma;        // c_v / beta
+  double lt_per_sqrt;  // sigma_v sqrt(2 / pi)
+  double pad;
 };
 
 // Slot table entry for vertices of degree > 3 (same encoding as above).
@@ -86,7 +107,11 @@ struct GraphDev {
   int32_t o_vtx, o_slots, o_guide, o_e32, o_e64;
   int32_t stage_bytes32;  // vtx..e32 (FP32 kernels stage this range)
   int32_t stage_bytes64;  // vtx..guide + e64 (FP64 kernels)
-  int32_t poly;           // some edge has higher drift or diffusion terms
+  // a general method variant is present (some edge has higher drift or
+  // diffusion terms, or some vertex is a Wentzell vertex): the step kernels
+  // run their GEN instantiation
+  int32_t gen;
+  const WzRec *wz;        // Wentzell table (rows named by VtxBlk::wz), or null
 };
 
 // Counters of one particle set: exit[nnz], absorbed[V], totals[4]
@@ -185,7 +210,7 @@ struct KernelLaunch {
   size_t shm;
 };
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
-                          const StepArgs &a, bool fp64, bool trace, bool obs, bool poly);
+                          const StepArgs &a, bool fp64, bool trace, bool obs, bool gen);
 // tiled: edge-range LDS tiles when E * nb exceeds one LDS copy (else 64-bit
 // global atomics); below that size both take the single LDS copy.
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,

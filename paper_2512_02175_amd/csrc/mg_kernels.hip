@@ -171,6 +171,48 @@ __device__ __forceinline__ uint64_t fnv(uint64_t h, uint32_t w) {
   return (h ^ (uint64_t)w) * kFnvPrime;
 }
 
+// Vertex stream of a Wentzell visit: word 0 of Philox (p, n, 0x100 + k, tag)
+// decides the killing at the visit of the k-th hit of step n (k = 0: the
+// visit at the start of a step that begins on the vertex).  Hit streams use
+// k <= 255 in that word, so the two never share a counter.
+__device__ __forceinline__ uint32_t vertex_draw(uint32_t pid, uint32_t step, uint32_t k,
+                                                const SetDev &S, const StepArgs &A) {
+  return philox(pid, step, 0x100u + k, S.tag, A.key0, A.key1).x;
+}
+
+// One visit of a Wentzell vertex (general gluing condition, Sec. 2.2; the
+// scheme charges each visit its local time l = o + lt_per_sqrt sqrt(h''),
+// the overshoot o of the proposal that crossed the vertex plus the mean
+// local time of the move of length h'' that leaves it).  With h left in
+// the step, the particle first stays on the vertex for gamma l and then
+// moves for h'', where h'' + gamma (o + lt_per_sqrt sqrt(h'')) = h, a
+// quadratic in sqrt(h'') solved in cancellation-free form; when gamma o >= h
+// it stays for all of h and owes gamma o - h more.  The visit kills with
+// probability 1 - exp(-kappa l), decided by the vertex-stream word `bits`
+// as a uniform (bits + 1/2) 2^-32.  Returns true if the particle is killed;
+// otherwise hm is the move's length (0: it stays for the rest of the step)
+// and owed the stay still owed after this step.  FP64 throughout (both
+// precisions; visits are rare).
+__device__ __forceinline__ bool wz_visit(const WzRec &w, double o, double h, uint32_t bits,
+                                         double &hm, double &owed) {
+  double lt;
+  owed = 0.0;
+  if (w.gamma == 0.0) {
+    hm = h;
+    lt = o + w.lt_per_sqrt * sqrt(h);
+  } else if (w.gamma * o >= h) {
+    hm = 0.0;
+    lt = o;
+    owed = w.gamma * o - h;
+  } else {
+    const double b = w.gamma * w.lt_per_sqrt, r = h - w.gamma * o;
+    const double sq = 2.0 * r / (b + sqrt(b * b + 4.0 * r));
+    hm = sq * sq;
+    lt = o + w.lt_per_sqrt * sq;
+  }
+  return w.kappa > 0.0 && ((double)bits + 0.5) * 0x1p-32 < -expm1(-w.kappa * lt);
+}
+
 // Graph tables as the step kernels see them: global memory, or LDS when the
 // block staged them.
 struct GView {
@@ -181,10 +223,11 @@ struct GView {
   const EdgeRec64 *e64;
   const EdgeRec64 *hi64;  // global FP64 records: the FP32 path reads the
                           // higher coefficient terms from them
+  const WzRec *wz;        // global Wentzell table
 };
 
 __device__ __forceinline__ GView global_view(const GraphDev &G) {
-  return {G.vtx, G.slots, G.guide, G.e32, G.e64, G.e64};
+  return {G.vtx, G.slots, G.guide, G.e32, G.e64, G.e64, G.wz};
 }
 
 struct SlotPick {
@@ -387,7 +430,7 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
 
 // ------------------------------------------------------------ FP64 path --
 // The canonical step in FP64, operation for operation.
-template <bool TRACE, bool LDS, bool POLY>
+template <bool TRACE, bool LDS, bool GEN>
 struct Particle64 {
   using real = double;
   GView G;
@@ -411,19 +454,36 @@ struct Particle64 {
   __device__ __forceinline__ bool fast_first(double w) { return fast(w); }
   __device__ __forceinline__ double pos64(double) const { return x; }
 
-  // Drift and diffusion at x: affine and constant, or with POLY the cubics
+  // Drift and diffusion at x: affine and constant, or with GEN the cubics
   // by Horner's rule (with zero higher terms these equal the affine values
   // exactly).
   __device__ __forceinline__ double drift(double at) const {
-    if (!POLY) return fma(R.c, at, R.a);
+    if (!GEN) return fma(R.c, at, R.a);
     return fma(fma(fma(R.c3, at, R.c2), at, R.c), at, R.a);
   }
   __device__ __forceinline__ double diffusion(double at) const {
-    if (!POLY) return R.sigma;
+    if (!GEN) return R.sigma;
     return fma(fma(fma(R.s3, at, R.s2), at, R.s1), at, R.sigma);
   }
 
+  // GEN: the particle sits on a Wentzell vertex (x <= 0 at the initial
+  // end, x >= L at the terminal one; a particle that owes a stay there
+  // holds -t or L + t).  Its step starts with a visit, in resolve().
+  __device__ __forceinline__ bool on_wentzell() const {
+    if constexpr (!GEN) return false;
+    return (x <= 0.0 && ((uint32_t)R.vinit & kWentzellEnd)) ||
+           (x >= R.L && ((uint32_t)R.vterm & kWentzellEnd));
+  }
+
+  __device__ __forceinline__ void die(int32_t v, uint32_t step, const SetDev &S) {
+    alive = false;
+    death_step = step;
+    atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
+    if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
+  }
+
   __device__ __forceinline__ bool fast(double w) {
+    if (on_wentzell()) return false;
     if (x == 0.0)
       w = fabs(w);
     else if (x == R.L)
@@ -445,6 +505,32 @@ struct Particle64 {
     double h = dtv;
     int32_t k = 0, last = -1;
     bool first = true;
+    if (on_wentzell()) {
+      // a step that starts on a Wentzell vertex: the stay owed there first,
+      // then the visit that leaves it (its own local time only, o = 0); a
+      // step spent on the vertex, or ended by the visit's killing, has no
+      // move (its one sub-step is counted with the step)
+      const bool init = x <= 0.0;
+      const int32_t v = (init ? R.vinit : R.vterm) & kVertexMask;
+      double owe = init ? -x : x - R.L;
+      if (owe >= h) {
+        owe = owe - h;
+        x = init ? -owe : R.L + owe;
+        return;
+      }
+      h = h - owe;
+      x = init ? 0.0 : R.L;
+      double hm, owed;
+      if (wz_visit(G.wz[G.vtx[v].wz - 1u], 0.0, h, vertex_draw(pid, step, 0u, S, A), hm, owed)) {
+        die(v, step, S);
+        return;
+      }
+      if (hm == 0.0) {
+        x = init ? -owed : R.L + owed;
+        return;
+      }
+      h = hm;
+    }
     for (;;) {
       if (x == 0.0)
         w = fabs(w);
@@ -481,11 +567,17 @@ struct Particle64 {
       ++nhit;
       t.hits++;
       const VtxBlk vb = G.vtx[v];
-      if (vb.deg < 0) {  // absorbing vertex
-        alive = false;
-        death_step = step;
-        atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
-        if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
+      // a Wentzell vertex: the visit this hit starts, its overshoot being
+      // how far past the vertex the proposal went
+      double h_move = h, owed = 0.0;
+      bool killed = false;
+      if (GEN && vb.wz) {
+        const double o = at_init ? -xt : xt - R.L;
+        killed = wz_visit(G.wz[vb.wz - 1u], o, h, vertex_draw(pid, step, (uint32_t)k, S, A),
+                          h_move, owed);
+      }
+      if (vb.deg < 0 || killed) {  // absorbing vertex, or killed at the visit
+        die(v, step, S);
         break;
       }
       const U4 hd = philox(pid, step, (uint32_t)k, S.tag, A.key0, A.key1);
@@ -496,6 +588,13 @@ struct Particle64 {
       x = (sp.eo & 1u) ? R.L : 0.0;
       last = s;
       if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)s);
+      if (GEN && vb.wz) {
+        h = h_move;
+        if (h == 0.0) {  // stays on the vertex for the rest of the step
+          x = (sp.eo & 1u) ? R.L + owed : -owed;
+          break;
+        }
+      }
       if (h == 0.0) break;
       if (k == A.max_splits) {
         t.trunc++;
@@ -507,7 +606,7 @@ struct Particle64 {
   }
 };
 
-template <bool TRACE, bool LDS, bool OBS, int NG, bool POLY>
+template <bool TRACE, bool LDS, bool OBS, int NG, bool GEN>
 __device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const StepArgs &A,
                       uint32_t pid, uint32_t *s_exit, Tally &t, const ObsSink &o) {
   const uint32_t ef = S.ef[pid];
@@ -517,10 +616,10 @@ __device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const St
     atomicOr(S.err, kErrEdge);
     return;
   }
-  Particle64<TRACE, LDS, POLY> q{G, s_exit, e, S.x64[pid], G.e64[e], true,
+  Particle64<TRACE, LDS, GEN> q{G, s_exit, e, S.x64[pid], G.e64[e], true,
                            TRACE ? S.seqhash[pid] : 0ull, TRACE ? S.hits[pid] : 0u,
                            0u, A.dt};
-  if (!(q.x >= 0.0 && q.x <= q.R.L)) {
+  if (!((q.x >= 0.0 && q.x <= q.R.L) || q.on_wentzell())) {
     atomicOr(S.err, kErrPos);
     return;
   }
@@ -566,10 +665,13 @@ struct Hit32 {
   int32_t k, last;
 };
 
-// POLY: the graph has higher coefficient terms (cubic drift or diffusion);
-// the first sub-step then evaluates them at the particle's position instead
-// of using the per-frame affine constants.
-template <bool TRACE, bool LDS, bool POLY = false>
+// GEN: the graph has a general method variant.  Higher coefficient terms
+// (cubic drift or diffusion): the first sub-step evaluates them at the
+// particle's position instead of using the per-frame affine constants.
+// Wentzell vertices: a step that starts on one begins with a visit (in
+// cross()), and a hit there is a visit too; a particle that owes a stay on
+// the vertex holds y = -t in the frame of that end.
+template <bool TRACE, bool LDS, bool GEN = false>
 struct Particle32 {
   using real = float;
   GView G;
@@ -588,7 +690,7 @@ struct Particle32 {
   // g0 with the frame's sign, so that a first sub-step is
   // y + fma(gs, w, fma(cd, y, ad)) with no per-step sign select.
   float cd = 0.0f, ad = 0.0f, gs = 0.0f;
-  // Higher terms of the current edge (POLY), x from the initial vertex:
+  // Higher terms of the current edge (GEN), x from the initial vertex:
   // drift + c2 x^2 + c3 x^3, diffusion + s1 x + s2 x^2 + s3 x^3.
   float c2 = 0.0f, c3 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 
@@ -600,7 +702,7 @@ struct Particle32 {
     cd = R.c * dt;
     ad = as * dt;
     gs = side ? -g0 : g0;
-    if constexpr (POLY) {
+    if constexpr (GEN) {
       const EdgeRec64 &P = G.hi64[e];
       c2 = (float)P.c2;
       c3 = (float)P.c3;
@@ -613,7 +715,7 @@ struct Particle32 {
   // Drift in the frame (sign of the reference end) and diffusion at
   // distance yy from the reference end.
   __device__ __forceinline__ float fdrift(float yy) const {
-    if constexpr (!POLY) {
+    if constexpr (!GEN) {
       return fmaf(R.c, yy, as);
     } else {
       const float x = side ? R.L - yy : yy;
@@ -622,7 +724,7 @@ struct Particle32 {
     }
   }
   __device__ __forceinline__ float fsigma(float yy) const {
-    if constexpr (!POLY) {
+    if constexpr (!GEN) {
       return R.sigma;
     } else {
       const float x = side ? R.L - yy : yy;
@@ -664,6 +766,26 @@ struct Particle32 {
     gs = flip ? -gs : gs;
   }
 
+  // GEN: the particle sits on a Wentzell vertex, its reference end (y <= 0:
+  // on the vertex, or owing a stay of -y there).
+  __device__ __forceinline__ bool on_wentzell() const {
+    if constexpr (!GEN) return false;
+    return y <= 0.0f && ((uint32_t)(side ? R.vterm : R.vinit) & kWentzellEnd);
+  }
+  // The particle stays on its reference end, a Wentzell vertex, owing a
+  // further stay of t there (y = -t as a compensated pair).
+  __device__ __forceinline__ void owe_stay(double t) {
+    const double yd = -t;
+    y = (float)yd;
+    yl = (float)(yd - (double)y);
+  }
+  __device__ __forceinline__ void die(int32_t v, uint32_t step, const SetDev &S) {
+    alive = false;
+    death_step = step;
+    atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
+    if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
+  }
+
   // The normal a first sub-step from y = 0 uses: a particle on a vertex
   // moves into its edge, so the noise term is g0 |w| (gs carries the frame's
   // sign, hence |w| with that sign).
@@ -673,7 +795,7 @@ struct Particle32 {
   // A step's first sub-step over dt with normal w; w must already be
   // at_vertex(w) when y = 0.  Returns the proposal and its compensation.
   __device__ __forceinline__ float propose(float w, float &err) const {
-    if constexpr (!POLY) {
+    if constexpr (!GEN) {
       return add_comp(fmaf(gs, w, fmaf(cd, y, ad)) + yl, err);
     } else {
       const float sg = fsigma(y) * sqdt;
@@ -692,6 +814,7 @@ struct Particle32 {
   }
   // First sub-step of a window's first active step after prep_window.
   __device__ __forceinline__ bool fast_first(float w) {
+    if (on_wentzell()) return false;
     float err;
     const float yt = propose(w, err);
     if (yt > 0.0f && yt < R.L) {
@@ -703,6 +826,7 @@ struct Particle32 {
   }
 
   __device__ __forceinline__ bool fast(float w) {
+    if (on_wentzell()) return false;
     float err;
     const float yt = propose((y == 0.0f) ? at_vertex(w) : w, err);
     if (yt > 0.0f && yt < R.L) {
@@ -721,7 +845,7 @@ struct Particle32 {
   __device__ __forceinline__ bool fast_pred(float w, bool active) {
     float err;
     const float yt = propose(w, err);
-    const bool in = (yt > 0.0f) & (yt < R.L);
+    const bool in = (yt > 0.0f) & (yt < R.L) & !on_wentzell();
     const bool upd = active & in;
     y = upd ? yt : y;
     yl = upd ? err : yl;
@@ -738,15 +862,53 @@ struct Particle32 {
   __device__ bool cross(uint32_t step, Hit32 &h, uint32_t pid, const SetDev &S,
                         const StepArgs &A, Tally &t) {
     float hh = h.hh, hl = h.hl;
+    // the pending sub-step is the step's first, over dt (else over hh + hl)
+    bool first = h.k == 0;
+    if (first && on_wentzell()) {
+      // a step that starts on a Wentzell vertex: the stay owed there first,
+      // then the visit that leaves it (o = 0); a step spent on the vertex,
+      // or ended by the visit's killing, has no move
+      const int32_t v = (side ? R.vterm : R.vinit) & kVertexMask;
+      double hd = (double)hh + (double)hl;
+      const double owe = -((double)y + (double)yl);
+      if (owe >= hd) {
+        owe_stay(owe - hd);
+        return true;
+      }
+      hd = hd - owe;
+      y = 0.0f;
+      yl = 0.0f;
+      double hm, owed;
+      if (wz_visit(G.wz[G.vtx[v].wz - 1u], 0.0, hd, vertex_draw(pid, step, 0u, S, A), hm,
+                   owed)) {
+        die(v, step, S);
+        return true;
+      }
+      if (hm == 0.0) {
+        owe_stay(owed);
+        return true;
+      }
+      hh = (float)hm;
+      hl = (float)(hm - (double)hh);
+      h.hh = hh;
+      h.hl = hl;
+      first = false;
+    }
     // the pending proposal, recomputed as it was made
     // (the first sub-step's exactly as propose() made it: g0 we = gs w)
     const float we = (y == 0.0f) ? fabsf(h.w) : (side ? -h.w : h.w);
     const float mu = fdrift(y);
-    const float g = h.k == 0 ? (POLY ? fsigma(y) * sqdt : g0)
-                             : fsigma(y) * __builtin_amdgcn_sqrtf(hh);
-    const float mdt = h.k == 0 ? (POLY ? mu * dt : fmaf(cd, y, ad)) : mu * hh;
+    const float g = first ? (GEN ? fsigma(y) * sqdt : g0)
+                          : fsigma(y) * __builtin_amdgcn_sqrtf(hh);
+    const float mdt = first ? (GEN ? mu * dt : fmaf(cd, y, ad)) : mu * hh;
     float err;
     const float yt = add_comp(fmaf(g, we, mdt) + yl, err);
+    // the move that leaves a start-of-step visit need not reach a vertex
+    if (GEN && h.k == 0 && !first && yt > 0.0f && yt < R.L) {
+      y = yt;
+      yl = err;
+      return true;
+    }
     const bool near = yt <= 0.0f;
     const bool at_term = near == (side != 0u);
     const int32_t vr = at_term ? R.vterm : R.vinit;
@@ -777,7 +939,7 @@ struct Particle32 {
         // crossing solve in FP64 next to the vertex (on the vertex itself,
         // d = 0, the root is -B/A: one division, no cancellation)
         const double hd = (double)hh + (double)hl;
-        const double mud = POLY ? (double)mu : fma((double)R.c, (double)y, (double)as);
+        const double mud = GEN ? (double)mu : fma((double)R.c, (double)y, (double)as);
         const double gd = (double)fsigma(y) * sqrt(hd);
         const double qa = near ? mud * hd : -(mud * hd);
         const double qb = near ? gd * (double)we : -(gd * (double)we);
@@ -807,11 +969,16 @@ struct Particle32 {
       ++nhit;
       t.hits++;
       const VtxBlk vb = G.vtx[v];
-      if (vb.deg < 0) {
-        alive = false;
-        death_step = step;
-        atomicAdd((unsigned long long *)&S.absorbed[v], 1ull);
-        if (TRACE) hash = fnv(fnv(hash, step), 0x80000000u | (uint32_t)v);
+      // a Wentzell vertex: the visit this hit starts, with the proposal's
+      // overshoot past the vertex
+      double hm = 0.0, owed = 0.0;
+      bool killed = false;
+      if (GEN && vb.wz)
+        killed = wz_visit(G.wz[vb.wz - 1u], (double)r0 + (double)r1,
+                          (double)hh + (double)hl, vertex_draw(pid, step, (uint32_t)h.k, S, A),
+                          hm, owed);
+      if (vb.deg < 0 || killed) {
+        die(v, step, S);
         return true;
       }
       const U4 hd = philox(pid, step, (uint32_t)h.k, S.tag, A.key0, A.key1);
@@ -824,7 +991,19 @@ struct Particle32 {
       frame();
       h.last = sp.s;
       if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)sp.s);
-      done = hh == 0.0f;
+      bool stays = false;
+      if (GEN && vb.wz) {
+        if (hm == 0.0) {  // stays on the vertex for the rest of the step
+          owe_stay(owed);
+          stays = true;
+        } else {
+          hh = (float)hm;
+          hl = (float)(hm - (double)hh);
+          h.hh = hh;
+          h.hl = hl;
+        }
+      }
+      done = stays || hh == 0.0f;
       if (!done && h.k == A.max_splits) {
         t.trunc++;
         done = true;
@@ -856,7 +1035,7 @@ struct Particle32 {
   }
 };
 
-template <bool TRACE, bool LDS, bool OBS, int NG, bool POLY>
+template <bool TRACE, bool LDS, bool OBS, int NG, bool GEN>
 __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const StepArgs &A,
                       uint32_t pid, uint32_t *s_exit, Tally &t, const ObsSink &o) {
   const uint32_t ef = S.ef[pid];
@@ -870,11 +1049,11 @@ __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const St
   const Edge32 R = load_edge32(G.e32, e);
   const uint32_t side = (ef & kSideBit) ? 1u : 0u;
   const float2 yy = S.y32[pid];
-  Particle32<TRACE, LDS, POLY> q{G, s_exit, e, side, yy.x, yy.y, R,
+  Particle32<TRACE, LDS, GEN> q{G, s_exit, e, side, yy.x, yy.y, R,
                            side ? -R.aL : R.a, R.sigma * sqdt, (float)A.dt, sqdt, true,
                            TRACE ? S.seqhash[pid] : 0ull, TRACE ? S.hits[pid] : 0u, 0u};
   q.frame();
-  if (!(q.y >= 0.0f && q.y <= R.L)) {
+  if (!((q.y >= 0.0f && q.y <= R.L) || q.on_wentzell())) {
     atomicOr(S.err, kErrPos);
     return;
   }
@@ -939,12 +1118,13 @@ __device__ __forceinline__ GView block_view(const GraphDev &G, char *smem) {
   v.e32 = (const EdgeRec32 *)(smem + head);
   v.e64 = (const EdgeRec64 *)(smem + head);
   v.hi64 = G.e64;
+  v.wz = G.wz;
   return v;
 }
 
 __device__ __forceinline__ int32_t exit_bytes(int32_t nnz) { return ((nnz * 4) + 15) & ~15; }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool POLY>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool GEN>
 __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t pid,
                                            unsigned long long *s_tot, char *smem) {
@@ -964,24 +1144,24 @@ __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
   Tally t{0, 0, 0, 0};
   if (pid < S.n) {
     if (FP64)
-      run64<TRACE, LDS, OBS, kWindowGroups64, POLY>(view, G.E, S, A, pid, s_exit, t, o);
+      run64<TRACE, LDS, OBS, kWindowGroups64, GEN>(view, G.E, S, A, pid, s_exit, t, o);
     else
-      run32<TRACE, LDS, OBS, kWindowGroups32, POLY>(view, G.E, S, A, pid, s_exit, t, o);
+      run32<TRACE, LDS, OBS, kWindowGroups32, GEN>(view, G.E, S, A, pid, s_exit, t, o);
   }
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
   if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
 }
 
-// POLY: some edge has higher drift or diffusion terms (FP32: lane schedule only).
-template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool POLY>
+// GEN: some edge has higher drift or diffusion terms (FP32: lane schedule only).
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_step(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ unsigned long long s_tot[4];
-  step_block<FP64, TRACE, LDS, STAGED, OBS, POLY>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
+  step_block<FP64, TRACE, LDS, STAGED, OBS, GEN>(G, S, A, blockIdx.x * kBlock + threadIdx.x,
                                                   s_tot, (char *)smem4);
 }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool POLY>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
                                                   const SetDev *sets,
                                                   const BatchItem *items,
@@ -992,7 +1172,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
   SetDev S = sets[it.set];
   S.n0 += A.n0_offset;  // steps already taken by earlier launches of this call
   const GraphDev G = graphs[it.set];
-  step_block<FP64, TRACE, LDS, STAGED, OBS, POLY>(G, S, A, it.first + threadIdx.x, s_tot,
+  step_block<FP64, TRACE, LDS, STAGED, OBS, GEN>(G, S, A, it.first + threadIdx.x, s_tot,
                                                   (char *)smem4);
 }
 
@@ -1061,8 +1241,8 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 // move the accesses across each other.
 __device__ __forceinline__ void wave_lds_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
-template <bool TRACE, bool LDS, bool POLY, int PW>
-__device__ __forceinline__ void pool_load(Particle32<TRACE, LDS, POLY> &q,
+template <bool TRACE, bool LDS, bool GEN, int PW>
+__device__ __forceinline__ void pool_load(Particle32<TRACE, LDS, GEN> &q,
                                           const PoolLds32<TRACE, PW> &P,
                                           uint32_t s) {
   const uint32_t ef = P.ef[s];
@@ -1079,8 +1259,8 @@ __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS, POLY> &q,
   }
 }
 
-template <bool TRACE, bool LDS, bool POLY, int PW>
-__device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS, POLY> &q,
+template <bool TRACE, bool LDS, bool GEN, int PW>
+__device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS, GEN> &q,
                                            PoolLds32<TRACE, PW> &P,
                                            uint32_t s, uint32_t n) {
   P.ef[s] = (uint32_t)q.e | (q.side ? kSideBit : 0u);
@@ -1095,8 +1275,8 @@ __device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS, POLY> &q
 
 // Writes a particle back at the end of its launch and counts the steps it
 // took (each has one first sub-step; resolve() counts the others).
-template <bool TRACE, bool LDS, bool POLY>
-__device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS, POLY> &q, const SetDev &S,
+template <bool TRACE, bool LDS, bool GEN>
+__device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS, GEN> &q, const SetDev &S,
                                             const StepArgs &A, uint32_t pid, Tally &t) {
   S.ef[pid] = (uint32_t)q.e | (q.side ? kSideBit : 0u) | (q.alive ? 0u : kDeadBit);
   S.y32[pid] = make_float2(q.y, q.yl);
@@ -1146,7 +1326,7 @@ __device__ __forceinline__ void drain_lds(uint32_t *lds, uint64_t *glob, int32_t
 // the set's counter as its home slots free up, so pools stay nearly full
 // until the set runs out and a launch ends with one short tail instead of
 // one per block.  Otherwise (batched launches): the ids [first, last).
-template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool PERSIST, bool POLY>
+template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool PERSIST, bool GEN>
 __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
                            const StepArgs &A, uint32_t first, uint32_t last,
                            PoolLds32<TRACE, PW> &P, uint32_t *s_exit, Tally &t,
@@ -1155,7 +1335,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   const float dt = (float)A.dt;
   const float sqdt = (float)sqrt(A.dt);
   const uint32_t n_end = S.n0 + A.nsteps;
-  Particle32<TRACE, LDS, POLY> q{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
+  Particle32<TRACE, LDS, GEN> q{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
                                  true, 0ull, 0u, 0u};
   bool has = false;
   uint32_t slot = 0, n = 0, pid = 0;  // the lane's home slot, next step, particle
@@ -1216,7 +1396,10 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
         if (!(ef & kDeadBit)) {
           if (e >= n_edges) {
             atomicOr(S.err, kErrEdge);
-          } else if (!(yy.x >= 0.0f && yy.x <= G.e32[e].L)) {
+          } else if (!((yy.x >= 0.0f && yy.x <= G.e32[e].L) ||
+                       (GEN && yy.x < 0.0f &&
+                        ((uint32_t)((ef & kSideBit) ? G.e32[e].vterm : G.e32[e].vinit) &
+                         kWentzellEnd)))) {
             atomicOr(S.err, kErrPos);
           } else {
             ok = true;
@@ -1340,7 +1523,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       uint32_t s2 = 0;
       if (lane < B) {
         s2 = P.split[(s_base + lane) % K];
-        Particle32<TRACE, LDS, POLY> q2{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt,
+        Particle32<TRACE, LDS, GEN> q2{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt,
                                   sqdt, true, 0ull, 0u, 0u};
         pool_load(q2, P, s2);
         const uint32_t step = P.n[s2];
@@ -1392,7 +1575,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
 // Shared memory of a pool block: [exit counters][staged tables][pools]
 // [snapshot bins].
 template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool PERSIST,
-          bool POLY>
+          bool GEN>
 __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t block_first,
                                            unsigned long long *s_tot, char *smem) {
@@ -1413,7 +1596,7 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
   Tally t{0, 0, 0, 0};
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t first = block_first + wave * PW * kBatchGens;
-  run_pool32<TRACE, LDS, OBS, PW, NG, PERSIST, POLY>(view, G.E, S, A, first,
+  run_pool32<TRACE, LDS, OBS, PW, NG, PERSIST, GEN>(view, G.E, S, A, first,
                                                min(first + PW * kBatchGens, S.n),
                                            pools[wave], s_exit, t, s_tot, G.nnz, o);
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
@@ -1424,17 +1607,17 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
 #define MG_POOL_WAVES_PER_EU 7
 #endif
 
-// POLY (cubic coefficients) is instantiated for pools of 128 with two
+// GEN (cubic coefficients) is instantiated for pools of 128 with two
 // Philox groups per window only.
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool POLY = false>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool GEN = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ unsigned long long s_tot[4];
-  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, true, POLY>(G, S, A, 0u, s_tot, (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, true, GEN>(G, S, A, 0u, s_tot, (char *)smem4);
 }
 
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool POLY = false>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool GEN = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32_batch(const GraphDev *graphs,
                                                          const SetDev *sets,
@@ -1446,7 +1629,7 @@ void k_pool32_batch(const GraphDev *graphs,
   SetDev S = sets[it.set];
   S.n0 += A.n0_offset;
   const GraphDev G = graphs[it.set];
-  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, false, POLY>(G, S, A, it.first, s_tot,
+  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, false, GEN>(G, S, A, it.first, s_tot,
                                                           (char *)smem4);
 }
 
@@ -1742,7 +1925,7 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
                          hipStream_t st) {
   StepArgs a = a0;
   const bool obs = s.obs != nullptr;
-  if (!FP64 && a.kernel >= 1 && (!g.poly || a.kernel == 3)) {
+  if (!FP64 && a.kernel >= 1 && (!g.gen || a.kernel == 3)) {
     with_pool(a.kernel, [&](auto PWc, auto NGc) {
       constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
       const int32_t stage = g.stage_bytes32;
@@ -1762,7 +1945,7 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
         return;
       }
       if constexpr (PW == kPoolSmall && NG == 2) {
-        if (g.poly) {
+        if (g.gen) {
           with_flags([&](auto L, auto T, auto O) {
             const void *f = (const void *)k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
                                                    decltype(O)::value, PW, NG, true>;
@@ -1800,18 +1983,18 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
     hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
                                decltype(O)::value, decltype(P)::value>),
                        dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
-  }, lp.lds_exit, lp.staged, obs, g.poly != 0);
+  }, lp.lds_exit, lp.staged, obs, g.gen != 0);
   return hipGetLastError();
 }
 
 // Batched launches keep snapshot bins in global memory (the sets differ).
 template <bool FP64, bool TRACE>
 KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
-                            const StepArgs &a, bool obs, bool poly) {
+                            const StepArgs &a, bool obs, bool gen) {
   KernelLaunch k{};
   k.grid = dim3(n_items);
   k.block = dim3(kBlock);
-  const bool pools = !FP64 && a.kernel >= 1 && (!poly || a.kernel == 3);
+  const bool pools = !FP64 && a.kernel >= 1 && (!gen || a.kernel == 3);
   with_pool(a.kernel, [&](auto PWc, auto NGc) {
     constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
     const LdsPlan lp = plan_lds(max_nnz, max_stage,
@@ -1823,14 +2006,14 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
       if constexpr (!FP64)
         if (pools) {
           if constexpr (PW == kPoolSmall && NG == 2)
-            if (poly) {
+            if (gen) {
               k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG, true>;
               return;
             }
           k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG>;
           return;
         }
-      if (poly) {
+      if (gen) {
         k.func = (const void *)k_batch<FP64, TRACE, l, t, o, true>;
         return;
       }
@@ -1869,12 +2052,12 @@ int32_t batch_tile(bool fp64, int32_t kernel) {
 }
 
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
-                          const StepArgs &a, bool fp64, bool trace, bool obs, bool poly) {
+                          const StepArgs &a, bool fp64, bool trace, bool obs, bool gen) {
   if (fp64)
-    return trace ? batch_launch_t<true, true>(n_items, max_nnz, max_stage, a, obs, poly)
-                 : batch_launch_t<true, false>(n_items, max_nnz, max_stage, a, obs, poly);
-  return trace ? batch_launch_t<false, true>(n_items, max_nnz, max_stage, a, obs, poly)
-               : batch_launch_t<false, false>(n_items, max_nnz, max_stage, a, obs, poly);
+    return trace ? batch_launch_t<true, true>(n_items, max_nnz, max_stage, a, obs, gen)
+                 : batch_launch_t<true, false>(n_items, max_nnz, max_stage, a, obs, gen);
+  return trace ? batch_launch_t<false, true>(n_items, max_nnz, max_stage, a, obs, gen)
+               : batch_launch_t<false, false>(n_items, max_nnz, max_stage, a, obs, gen);
 }
 
 hipError_t launch_histogram_csr(const GraphDev &g, const SetDev &s, const int32_t *off,

@@ -121,6 +121,17 @@ def _cubic(**hi):
     return g
 
 
+def _wentzell(a, c, b, kind=3):
+    """Segment whose vertex 0 is a Wentzell vertex with a_v = a, c_v = c and
+    jump probability b."""
+    g = workloads.segment(1.0, 0.0, 0.0, 1.0)
+    g.vtx_kind[0] = kind
+    g.slot_jump_prob[g.vtx_offsets[0]] = b
+    g.vtx_kill = np.array([a, 0.0])
+    g.vtx_sticky = np.array([c, 0.0])
+    return g
+
+
 @pytest.mark.parametrize("make,msg", [
     # a mirror vertex must be a leaf (the centre of a star has three slots)
     (lambda: workloads.from_edges(4, [0, 0, 0], [1, 2, 3], 1.0, vtx_kind=[2, 0, 0, 0]),
@@ -135,10 +146,18 @@ def _cubic(**hi):
     (lambda: _cubic(sigma_c1=[-4.0], sigma_c2=[4.0], sigma_c3=[-1e-12]), "sigma(x)"),
     (lambda: _cubic(drift_c3=[np.nan]), "not finite"),
     (lambda: workloads.from_edges(2, [0], [1], [np.inf], bin_span=2.0), None),
+    # Wentzell vertices: a_v + sum b + c_v must be 1, a_v and c_v >= 0, and
+    # some b > 0 (the particle must be able to leave)
+    (lambda: _wentzell(0.2, 0.1, 0.6), "not 1"),
+    (lambda: _wentzell(-0.1, 0.0, 1.1), ">= 0"),
+    (lambda: _wentzell(0.0, np.nan, 1.0), ">= 0"),
+    (lambda: _wentzell(0.5, 0.5, 0.0), "no positive jump probability"),
+    (lambda: _wentzell(0.2, 0.1, 0.7, kind=4), "unknown kind"),
 ])
 def test_method_variant_graphs_checked(B, make, msg):
-    """Mirror vertices and cubic coefficients are validated on the host: the
-    bad cases are refused with the reason, the good ones pass validation
+    """Mirror vertices, cubic coefficients and Wentzell vertices are validated
+    on the host: the bad cases are refused with the reason, the good ones
+    pass validation
     (which is all that runs here; building the device tables needs a GPU)."""
     g = make()
     if msg is None:

@@ -174,14 +174,17 @@ def test_mirror_fp32_one_step_law(B, a, x0):
 
 
 def test_mirror_validation(B):
-    """A mirror vertex must be a leaf; unknown kinds are rejected."""
+    """A mirror vertex must be a leaf; unknown kinds are rejected (kind 3 is a
+    Wentzell vertex, which with a_v = c_v = 0 is a valid standard one)."""
     g = workloads.star_graph(3, 1.0)
     g.vtx_kind[0] = 2
     with pytest.raises(B.MgError):
         B.mg_graph_create(g)
-    g.vtx_kind[0] = 3
+    g.vtx_kind[0] = 4
     with pytest.raises(B.MgError):
         B.mg_graph_create(g)
+    g.vtx_kind[0] = 3
+    B.mg_graph_create(g)
     g.vtx_kind[0] = 0
     g.vtx_kind[1:] = 2
     B.mg_graph_create(g)

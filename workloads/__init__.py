@@ -245,6 +245,41 @@ def double_well_star(n_edges: int = 64, seed: int = 6) -> GraphDesc:
     return g
 
 
+def wentzell_star(n_edges: int = 5, seed: int = 7, cubic: bool = False) -> GraphDesc:
+    """Star whose centre and some leaves are Wentzell vertices (Sec. 2.2's
+    general gluing condition): L ~ U[0.2, 0.8], drift a_e ~ U[-6, 2] toward
+    or away from the centre, sigma 1 (with ``cubic``: a graded diffusion
+    sigma_e(x) = 1 + g_e x / L_e, g_e ~ U[-0.3, 0.5], and a cubic drift term
+    c3_e ~ U[-4, 4]); the centre kills (a = 0.05) and is sticky (c = 0.15)
+    with b-hat ~ U[0.5, 1.5] normalised; leaf 1 kills (a = 0.3, c = 0.2),
+    leaf 2 is sticky only (c = 0.5), leaf 3 kills only (a = 0.4), the other
+    leaves are standard.  b = (1 - a - c) b-hat at each Wentzell vertex."""
+    rng = np.random.default_rng(seed)
+    E = int(n_edges)
+    L = rng.uniform(0.2, 0.8, size=E)
+    a = rng.uniform(-6.0, 2.0, size=E)
+    bh = rng.uniform(0.5, 1.5, size=E)
+    bh = bh / bh.sum()
+    g = star_graph(E, L, a, None, 1.0, b_center=bh,
+                   meta={"name": f"wentzell_star{E}{'_cubic' if cubic else ''}"})
+    if cubic:
+        gr = rng.uniform(-0.3, 0.5, size=E)
+        g.sigma_c1 = gr / L
+        g.drift_c3 = rng.uniform(-4.0, 4.0, size=E)
+    kill = np.zeros(E + 1)
+    sticky = np.zeros(E + 1)
+    kill[0], sticky[0] = 0.05, 0.15
+    kill[1], sticky[1] = 0.3, 0.2
+    sticky[2] = 0.5
+    kill[3] = 0.4
+    for v in (0, 1, 2, 3):
+        g.vtx_kind[v] = 3
+        s0, s1 = g.vtx_offsets[v], g.vtx_offsets[v + 1]
+        g.slot_jump_prob[s0:s1] *= 1.0 - kill[v] - sticky[v]
+    g.vtx_kill, g.vtx_sticky = kill, sticky
+    return g
+
+
 def csr_bins(g: GraphDesc, width: float, n_finite: int):
     """Per-edge bins for ``histogram_csr``: on each edge ``n_finite`` bins of
     ``width`` from x = 0 (clipped to the edge's length), then, on an edge
