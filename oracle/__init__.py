@@ -48,7 +48,11 @@ class _Graph(C.Structure):
                 ("drift_c2", C.c_void_p), ("drift_c3", C.c_void_p),
                 ("sigma_c1", C.c_void_p), ("sigma_c2", C.c_void_p),
                 ("sigma_c3", C.c_void_p), ("vtx_kill", C.c_void_p),
-                ("vtx_sticky", C.c_void_p)]
+                ("vtx_sticky", C.c_void_p), ("table_offsets", C.c_void_p),
+                ("table_mu", C.c_void_p), ("table_dmu", C.c_void_p),
+                ("table_sigma", C.c_void_p), ("table_dsigma", C.c_void_p)]
+
+TABLES = ("table_mu", "table_dmu", "table_sigma", "table_dsigma")
 
 HIGHER = ("drift_c2", "drift_c3", "sigma_c1", "sigma_c2", "sigma_c3")
 
@@ -149,6 +153,18 @@ class OracleGraph:
             self._keep[n] = np.ascontiguousarray(
                 np.broadcast_to(np.asarray(v, np.float64), (int(desc.n_vertices),)))
             hi.append(self._keep[n].ctypes.data)
+        # tabulated coefficients: knot offsets [E+1] and four knot arrays
+        off_t = getattr(desc, "table_offsets", None)
+        if off_t is None:
+            hi += [None] * 5
+        else:
+            self._keep["table_offsets"] = np.ascontiguousarray(off_t, np.int32)
+            if self._keep["table_offsets"].size != int(desc.n_edges) + 1:
+                raise ValueError("table_offsets needs E + 1 entries")
+            hi.append(self._keep["table_offsets"].ctypes.data)
+            for n in TABLES:
+                self._keep[n] = np.ascontiguousarray(getattr(desc, n), np.float64)
+                hi.append(self._keep[n].ctypes.data)
         k = self._keep
         self.c = _Graph(int(desc.n_vertices), int(desc.n_edges),
                         *[k[n].ctypes.data for n in (

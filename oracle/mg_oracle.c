@@ -157,6 +157,15 @@ typedef struct {
   /* [V] each, or NULL: a_v and c_v of a Wentzell vertex (kind 3), read
      only at such vertices (Sec. 2.2, the general gluing condition) */
   const double *vtx_kill, *vtx_sticky;
+  /* Tabulated coefficients (Sec. 2.2 allows any C^1 drift and diffusion):
+     [E+1] offsets, or NULL for none.  Edge e with table_offsets[e+1] -
+     table_offsets[e] = K + 1 >= 2 knots has, at x_j = j L / K, the drift
+     value and derivative table_mu/table_dmu and the diffusion value and
+     derivative table_sigma/table_dsigma (index table_offsets[e] + j); its
+     coefficient functions are the cubic Hermite interpolants of these
+     (C^1), replacing its drift_a, drift_c, sigma and higher terms. */
+  const int32_t *table_offsets;
+  const double *table_mu, *table_dmu, *table_sigma, *table_dsigma;
 } or_graph;
 
 /* Cubic p0 + p1 x + p2 x^2 + p3 x^3 by Horner's rule; NULL higher arrays
@@ -166,10 +175,42 @@ static double coef(const double *p2, const double *p3, int32_t e, double p0, dou
   const double c2 = p2 ? p2[e] : 0.0, c3 = p3 ? p3[e] : 0.0;
   return fma(fma(fma(c3, x, c2), x, p1), x, p0);
 }
+/* Cubic Hermite interpolant at x in [0, L] of values v and derivatives d
+   given at the K + 1 knots j h, h = L / K (index k0 + j): on the interval
+   j = floor(x / h) (the last one for x = L), with t = x / h - j,
+   v_j H00(t) + h d_j H10(t) + v_{j+1} H01(t) + h d_{j+1} H11(t), the
+   Hermite basis H00 = 2t^3 - 3t^2 + 1, H10 = t^3 - 2t^2 + t,
+   H01 = -2t^3 + 3t^2, H11 = t^3 - t^2.  C^1 on [0, L]. */
+static double hermite(const double *v, const double *d, int32_t k0, int32_t K, double L,
+                      double x) {
+  const double h = L / (double)K;
+  const double s = x / h;
+  int32_t j = (int32_t)floor(s);
+  if (j < 0) j = 0;
+  if (j > K - 1) j = K - 1;
+  const double t = s - (double)j;
+  const double t2 = t * t, t3 = t2 * t;
+  const double h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
+  const double h10 = t3 - 2.0 * t2 + t;
+  const double h01 = -2.0 * t3 + 3.0 * t2;
+  const double h11 = t3 - t2;
+  return h00 * v[k0 + j] + h10 * h * d[k0 + j] + h01 * v[k0 + j + 1] + h11 * h * d[k0 + j + 1];
+}
+/* Intervals of edge e's table, 0 if it has none. */
+static int32_t table_k(const or_graph *g, int32_t e) {
+  if (!g->table_offsets) return 0;
+  const int32_t n = g->table_offsets[e + 1] - g->table_offsets[e];
+  return n >= 2 ? n - 1 : 0;
+}
 static double drift_at(const or_graph *g, int32_t e, double x) {
+  const int32_t K = table_k(g, e);
+  if (K) return hermite(g->table_mu, g->table_dmu, g->table_offsets[e], K, g->length[e], x);
   return coef(g->drift_c2, g->drift_c3, e, g->drift_a[e], g->drift_c[e], x);
 }
 static double sigma_at(const or_graph *g, int32_t e, double x) {
+  const int32_t K = table_k(g, e);
+  if (K)
+    return hermite(g->table_sigma, g->table_dsigma, g->table_offsets[e], K, g->length[e], x);
   const double s1 = g->sigma_c1 ? g->sigma_c1[e] : 0.0;
   return coef(g->sigma_c2, g->sigma_c3, e, g->sigma[e], s1, x);
 }

@@ -139,6 +139,17 @@ MUTANTS = {
     "wentzell_move_stay_dropped": (
         [("const double b = gam * c, r = h - gam * o;", "const double b = 0.0, r = h - gam * o;")],
         WZ + "test_sticky_star_stationary_atom"),
+    "table_derivative_unscaled": (
+        [("return h00 * v[k0 + j] + h10 * h * d[k0 + j] + h01 * v[k0 + j + 1] + h11 * h * d[k0 + j + 1];",
+          "return h00 * v[k0 + j] + h10 * d[k0 + j] + h01 * v[k0 + j + 1] + h11 * d[k0 + j + 1];")],
+        COEF + "test_table_of_a_cubic_is_the_cubic"),
+    "table_coordinate_in_length_units": (
+        [("const double t = s - (double)j;", "const double t = x - (double)j * h;")],
+        COEF + "test_table_of_a_cubic_is_the_cubic"),
+    "table_basis_swapped": (
+        [("const double h10 = t3 - 2.0 * t2 + t;", "const double h10 = t3 - t2;"),
+         ("const double h11 = t3 - t2;", "const double h11 = t3 - 2.0 * t2 + t;")],
+        COEF + "test_table_stationary_law_of_non_polynomial_coefficients"),
     "far_end_not_checked": (
         [("if (xt > 0.0 && xt < L) {", "if (xt > 0.0) {")],
         CF + "test_radial_reflected_heat_kernel_converges"),

@@ -70,6 +70,14 @@ class GraphDesc:
     # vertex, with a_v + sum_e b_ve + c_v = 1 (None: zero)
     vtx_kill: np.ndarray | None = None
     vtx_sticky: np.ndarray | None = None
+    # tabulated coefficients (None: no tables): [E+1] knot offsets; edge e
+    # with K + 1 >= 2 knots has drift and diffusion values and derivatives
+    # at x_j = j L_e / K, interpolated by cubic Hermite polynomials
+    table_offsets: np.ndarray | None = None
+    table_mu: np.ndarray | None = None
+    table_dmu: np.ndarray | None = None
+    table_sigma: np.ndarray | None = None
+    table_dsigma: np.ndarray | None = None
 
     @property
     def nnz(self) -> int:
@@ -278,6 +286,64 @@ def wentzell_star(n_edges: int = 5, seed: int = 7, cubic: bool = False) -> Graph
         g.slot_jump_prob[s0:s1] *= 1.0 - kill[v] - sticky[v]
     g.vtx_kill, g.vtx_sticky = kill, sticky
     return g
+
+
+def tabulate(g: GraphDesc, knots, mu, dmu, sigma, dsigma, edges=None) -> GraphDesc:
+    """Give edges (all, or the listed ones) tabulated coefficients: K_e + 1
+    equally spaced knots x_j = j L_e / K_e (``knots`` per edge, or one count
+    for all), with drift and diffusion values and derivatives from the
+    functions mu(e, x), dmu(e, x), sigma(e, x), dsigma(e, x) (numpy-vectorised
+    in x).  Edges without a table keep their affine or cubic coefficients."""
+    E = g.n_edges
+    sel = set(range(E) if edges is None else edges)
+    k = np.broadcast_to(np.asarray(knots, np.int64), (E,))
+    off = np.zeros(E + 1, np.int32)
+    cols = {n: [] for n in ("table_mu", "table_dmu", "table_sigma", "table_dsigma")}
+    for e in range(E):
+        if e not in sel:
+            off[e + 1] = off[e]
+            continue
+        K = int(k[e])
+        x = np.arange(K + 1) * (g.length[e] / K)
+        for n, f in (("table_mu", mu), ("table_dmu", dmu), ("table_sigma", sigma),
+                     ("table_dsigma", dsigma)):
+            cols[n].append(np.asarray(f(e, x), np.float64) * np.ones(K + 1))
+        off[e + 1] = off[e] + K + 1
+    g.table_offsets = off
+    for n, v in cols.items():
+        setattr(g, n, np.concatenate(v) if v else np.zeros(0))
+    return g
+
+
+def periodic_star(n_edges: int = 8, seed: int = 9, knots: int = 16) -> GraphDesc:
+    """Star whose coefficients are not polynomials, given as tables: on edge
+    e (L ~ U[0.5, 1.5]) the potential V_e(x) = A_e (1 - cos(2 pi f_e x / L_e))
+    (A_e ~ U[0.5, 2], f_e in {1, 2}) gives the drift mu = -V', and the
+    diffusion is sigma_e(x) = 1 + g_e sin(pi x / L_e) (g_e ~ U[-0.3, 0.5]);
+    both tabulated at ``knots`` + 1 equally spaced points per edge (values
+    and derivatives), uniform jump probabilities at the centre."""
+    rng = np.random.default_rng(seed)
+    E = int(n_edges)
+    L = rng.uniform(0.5, 1.5, size=E)
+    A = rng.uniform(0.5, 2.0, size=E)
+    f = rng.integers(1, 3, size=E).astype(np.float64)
+    gr = rng.uniform(-0.3, 0.5, size=E)
+    g = star_graph(E, L, 0.0, 0.0, 1.0, meta={"name": f"periodic_star{E}"})
+    w = 2.0 * np.pi * f / L
+
+    def mu(e, x):
+        return -A[e] * w[e] * np.sin(w[e] * x)
+
+    def dmu(e, x):
+        return -A[e] * w[e] ** 2 * np.cos(w[e] * x)
+
+    def sig(e, x):
+        return 1.0 + gr[e] * np.sin(np.pi * x / L[e])
+
+    def dsig(e, x):
+        return gr[e] * (np.pi / L[e]) * np.cos(np.pi * x / L[e])
+    g.meta["coef"] = (mu, dmu, sig, dsig)
+    return tabulate(g, knots, mu, dmu, sig, dsig)
 
 
 def csr_bins(g: GraphDesc, width: float, n_finite: int):
