@@ -142,10 +142,11 @@ struct mg_particles {
 
 struct mg_batch {
   std::vector<mg_particles *> sets;
-  void *dev = nullptr;  // GraphDev[n] + SetDev[n] + BatchItem[items]
+  void *dev = nullptr;  // GraphDev[n] + SetDev[n] + BatchItem[items] + item counter
   GraphDev *d_graphs = nullptr;
   SetDev *d_sets = nullptr;
   BatchItem *d_items = nullptr;
+  uint32_t *d_claim = nullptr;  // item counter of the persistent pool launch
   int32_t n_items = 0;
   int32_t max_nnz = 0;
   int32_t max_stage = 0;  // staged table bytes if every set's graph fits, else 0
@@ -1174,7 +1175,8 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
   const size_t og = 0;
   const size_t os = align_up(sizeof(GraphDev) * n_sets, 256);
   const size_t oi = align_up(os + sizeof(SetDev) * n_sets, 256);
-  const size_t total = align_up(oi + sizeof(BatchItem) * items.size(), 256);
+  const size_t oc = align_up(oi + sizeof(BatchItem) * items.size(), 256);
+  const size_t total = oc + 256;
   hipError_t he = hipMalloc(&b->dev, total);
   if (he != hipSuccess) {
     delete b;
@@ -1183,6 +1185,7 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
   b->d_graphs = (GraphDev *)((char *)b->dev + og);
   b->d_sets = (SetDev *)((char *)b->dev + os);
   b->d_items = (BatchItem *)((char *)b->dev + oi);
+  b->d_claim = (uint32_t *)((char *)b->dev + oc);
   std::vector<GraphDev> gds(n_sets);
   for (int32_t i = 0; i < n_sets; ++i) gds[i] = sets[i]->g->gd;
   he = hipMemcpy(b->d_graphs, gds.data(), sizeof(GraphDev) * n_sets, hipMemcpyHostToDevice);
@@ -1221,11 +1224,30 @@ static hipError_t build_graph(mg_batch *b, int64_t n_steps, const StepArgs &base
     StepArgs a = base;
     a.nsteps = (uint32_t)std::min<int64_t>(left, chunk);
     a.n0_offset = done;
+    a.batch_items = (uint32_t)b->n_items;
+    a.batch_claim = b->d_claim;
     const KernelLaunch k = batch_launch(b->n_items, b->max_nnz, b->max_stage, a,
                                         p0->prec == MG_FP64, p0->trace, b->key_obs, b->gen);
     const GraphDev *g = b->d_graphs;
     const SetDev *sd = b->d_sets;
     const BatchItem *it = b->d_items;
+    if (k.persistent) {
+      // the sets' particle counters and the item counter start at zero
+      int32_t n_sets = (int32_t)b->sets.size();
+      uint32_t *claim = b->d_claim;
+      void *rargs[] = {(void *)&sd, (void *)&n_sets, (void *)&claim};
+      hipKernelNodeParams rp{};
+      rp.func = (void *)batch_reset_kernel();
+      rp.gridDim = dim3((unsigned)((n_sets + 255) / 256));
+      rp.blockDim = dim3(256);
+      rp.sharedMemBytes = 0;
+      rp.kernelParams = rargs;
+      rp.extra = nullptr;
+      hipGraphNode_t rnode;
+      he = hipGraphAddKernelNode(&rnode, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &rp);
+      if (he != hipSuccess) break;
+      prev = rnode;
+    }
     void *args[] = {(void *)&g, (void *)&sd, (void *)&it, (void *)&a};
     hipKernelNodeParams np{};
     np.func = (void *)k.func;

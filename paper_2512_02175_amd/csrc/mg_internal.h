@@ -153,6 +153,8 @@ struct StepArgs {
   uint32_t drain;      // wave pools: iterations between moves of the lanes'
                        // u32 tallies and the block's u32 LDS counters into
                        // 64-bit ones (1 .. 1024; tests lower it)
+  uint32_t batch_items;   // batched wave pools: work items (set indices)
+  uint32_t *batch_claim;  // and the counter their resident grid takes them from
 };
 
 // Largest particle set.  A persistent pool launch hands out particle ids
@@ -163,7 +165,9 @@ constexpr int64_t kMaxParticles = 0xFFFFFFFFll - 0xFFFFFll;  // 2^32 - 2^20
 constexpr uint32_t kMaxPersistBlocks = 2048;
 constexpr uint32_t kDrainMax = 1024;
 
-// Batched form: one work item per (set, tile of particles).
+// Batched form: one work item per (set, tile of particles).  The wave-pool
+// kernel reads only the set (its waves claim the set's particles from the
+// set's counter); the other step kernels run the tile from `first`.
 struct BatchItem {
   int32_t set;
   uint32_t first;  // first particle of the tile
@@ -208,7 +212,11 @@ struct KernelLaunch {
   const void *func;
   dim3 grid, block;
   size_t shm;
+  bool persistent;  // a resident grid over the items: k_batch_reset goes first
 };
+// k_batch_reset(const SetDev *sets, int32_t n_sets, uint32_t *claim): clears
+// the sets' particle counters and the item counter of a persistent batch.
+const void *batch_reset_kernel();
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
                           const StepArgs &a, bool fp64, bool trace, bool obs, bool gen);
 // tiled: edge-range LDS tiles when E * nb exceeds one LDS copy (else 64-bit

@@ -1199,8 +1199,9 @@ constexpr int kWavesPerBlock = kBlock / 64;
 #endif
 constexpr int kClaimMin = MG_POOL_CLAIM_MIN;  // free home slots that start a claim
 static_assert((kClaimMin & (kClaimMin - 1)) == 0 && kClaimMin <= 64, "claim granularity");
-// A batched pool wave owns kBatchGens pools' worth of particles of its tile
-// and refills its pool from them as particles finish.
+// A batch work item stands for kBatchGens pools' worth of one set's
+// particles per wave of a block: the number of items of a set, and so the
+// number of blocks that may work on it at once, grows with its size.
 constexpr int kBatchGens = 8;
 
 template <bool TRACE, int PW>
@@ -1321,15 +1322,16 @@ __device__ __forceinline__ void drain_lds(uint32_t *lds, uint64_t *glob, int32_t
 // snapshots (one per step of a window of at most 8 steps, and one per
 // split-pass lane): below 2^22 per counter.
 
-// Where a wave's particles come from.  PERSIST: a single set advanced by a
-// grid that stays resident; every wave claims the next particle ids from
-// the set's counter as its home slots free up, so pools stay nearly full
-// until the set runs out and a launch ends with one short tail instead of
-// one per block.  Otherwise (batched launches): the ids [first, last).
-template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool PERSIST, bool GEN>
+// Where a wave's particles come from: the set's counter.  The grid stays
+// resident; every wave claims the next particle ids from the counter as its
+// home slots free up, so pools stay nearly full until the set runs out and
+// a launch ends with one short tail instead of one per block.  A wave that
+// finds the set run out stops claiming, so every wave passes n by at most
+// one claim of 64 per set and launch (a batched launch lets a block join a
+// set only while its counter is below n, so this holds there too).
+template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool GEN>
 __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
-                           const StepArgs &A, uint32_t first, uint32_t last,
-                           PoolLds32<TRACE, PW> &P, uint32_t *s_exit, Tally &t,
+                           const StepArgs &A, PoolLds32<TRACE, PW> &P, uint32_t *s_exit, Tally &t,
                            unsigned long long *s_tot, int32_t nnz, const ObsSink &sink) {
   const uint32_t lane = threadIdx.x & 63u;
   const float dt = (float)A.dt;
@@ -1347,8 +1349,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
   uint32_t r_head = 0, r_tail = 0, s_head = 0, s_tail = 0;
   uint32_t f_head = 0, f_tail = K;
   for (uint32_t i = lane; i < K; i += 64u) P.freeq[i] = (uint8_t)i;
-  uint32_t next = first;
-  const uint32_t lim = PERSIST ? S.n : last;
+  const uint32_t lim = S.n;
   bool exhausted = false;
   uint32_t iter = 0;
   wave_lds_fence();
@@ -1362,23 +1363,15 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
     }
     // Claim more particles: a wave takes as many ids as it has free home
     // slots, in multiples of kClaimMin up to 64, so a pool refills while its
-    // first particles finish rather than after half of them have.  A
-    // persistent wave takes them from the set's counter, a batched wave
-    // from its own range.  Claims stay multiples of kClaimMin, so every
-    // claim starts at a multiple of it: a claim's 128-byte lines of
-    // positions belong to one wave (its state words share a line with one
-    // neighbouring claim).
+    // first particles finish rather than after half of them have.  Claims
+    // stay multiples of kClaimMin, so every claim starts at a multiple of
+    // it: a claim's 128-byte lines of positions belong to one wave (its
+    // state words share a line with one neighbouring claim).
     while (!exhausted && f_tail - f_head >= (uint32_t)kClaimMin) {
       const uint32_t want = min(64u, f_tail - f_head) & ~((uint32_t)kClaimMin - 1u);
-      uint32_t b;
-      if (PERSIST) {
-        uint32_t v = 0u;
-        if (lane == 0u) v = atomicAdd(S.work, want);
-        b = __builtin_amdgcn_readfirstlane(v);
-      } else {
-        b = next;
-        next += want;
-      }
+      uint32_t v = 0u;
+      if (lane == 0u) v = atomicAdd(S.work, want);
+      const uint32_t b = __builtin_amdgcn_readfirstlane(v);
       if (b >= lim) {
         exhausted = true;
         break;
@@ -1573,12 +1566,13 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
 }
 
 // Shared memory of a pool block: [exit counters][staged tables][pools]
-// [snapshot bins].
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool PERSIST,
-          bool GEN>
+// [snapshot bins].  Stages the set's tables, runs its particles until the
+// set's counter has run out and the block's pools are empty, and adds the
+// block's counts to the set's counters.
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool GEN>
 __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
-                                           const StepArgs &A, uint32_t block_first,
-                                           unsigned long long *s_tot, char *smem) {
+                                           const StepArgs &A, unsigned long long *s_tot,
+                                           char *smem) {
   uint32_t *s_exit = (uint32_t *)smem;
   if (threadIdx.x < 4) s_tot[threadIdx.x] = 0;
   if (LDS)
@@ -1595,10 +1589,8 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
   __syncthreads();
   Tally t{0, 0, 0, 0};
   const uint32_t wave = threadIdx.x >> 6;
-  const uint32_t first = block_first + wave * PW * kBatchGens;
-  run_pool32<TRACE, LDS, OBS, PW, NG, PERSIST, GEN>(view, G.E, S, A, first,
-                                               min(first + PW * kBatchGens, S.n),
-                                           pools[wave], s_exit, t, s_tot, G.nnz, o);
+  run_pool32<TRACE, LDS, OBS, PW, NG, GEN>(view, G.E, S, A, pools[wave], s_exit, t, s_tot,
+                                           G.nnz, o);
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
   if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
 }
@@ -1614,23 +1606,55 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_
 void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ unsigned long long s_tot[4];
-  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, true, GEN>(G, S, A, 0u, s_tot, (char *)smem4);
+  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, GEN>(G, S, A, s_tot, (char *)smem4);
 }
 
+// Batched form of the wave pools: a resident grid whose blocks take work
+// items (a set index each; A.batch_items of them, largest sets first) from
+// the counter A.batch_claim, and for each runs the set's particles with the
+// single-set pool code: the block's waves claim ids from the set's own
+// counter, alongside every other block working on that set, until it has
+// run out.  An item of a set that has run out is passed over at the cost
+// of one load.  Both counters are cleared by k_batch_reset before each
+// launch.
 template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool GEN = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
-void k_pool32_batch(const GraphDev *graphs,
-                                                         const SetDev *sets,
-                                                         const BatchItem *items,
-                                                         StepArgs A) {
+void k_pool32_batch(const GraphDev *graphs, const SetDev *sets, const BatchItem *items,
+                    StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ unsigned long long s_tot[4];
-  const BatchItem it = items[blockIdx.x];
-  SetDev S = sets[it.set];
-  S.n0 += A.n0_offset;
-  const GraphDev G = graphs[it.set];
-  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, false, GEN>(G, S, A, it.first, s_tot,
-                                                          (char *)smem4);
+  __shared__ int32_t s_set;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const uint32_t i = atomicAdd(A.batch_claim, 1u);
+      int32_t set = -1;  // -1: no items left
+      if (i < A.batch_items) {
+        set = items[i].set;
+        const SetDev &Si = sets[set];
+        if (__hip_atomic_load(Si.work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= Si.n)
+          set = -2;  // that set has run out
+      }
+      s_set = set;
+    }
+    __syncthreads();
+    const int32_t set = s_set;
+    __syncthreads();  // every thread has read s_set before thread 0 writes it again
+    if (set == -1) break;
+    if (set < 0) continue;
+    SetDev S = sets[set];
+    S.n0 += A.n0_offset;  // steps already taken by earlier launches of this call
+    const GraphDev G = graphs[set];
+    pool_block<TRACE, LDS, STAGED, OBS, PW, NG, GEN>(G, S, A, s_tot, (char *)smem4);
+  }
+}
+
+// Clears the particle counters of a batch's sets and its item counter
+// before a launch of k_pool32_batch (a kernel, so that the launch chain can
+// be a HIP graph of kernel nodes).
+__global__ void k_batch_reset(const SetDev *sets, int32_t n_sets, uint32_t *claim) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_sets) *sets[i].work = 0u;
+  if (i == 0) *claim = 0u;
 }
 
 // Autotuning probes: the FP32 step kernels under names of their own, so a
@@ -1640,7 +1664,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_
 void k_pool32_probe(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ unsigned long long s_tot[4];
-  pool_block<false, LDS, STAGED, false, PW, NG, true, false>(G, S, A, 0u, s_tot, (char *)smem4);
+  pool_block<false, LDS, STAGED, false, PW, NG, false>(G, S, A, s_tot, (char *)smem4);
 }
 
 template <bool LDS, bool STAGED>
@@ -1994,6 +2018,7 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
   KernelLaunch k{};
   k.grid = dim3(n_items);
   k.block = dim3(kBlock);
+  k.persistent = false;
   const bool pools = !FP64 && a.kernel >= 1 && (!gen || a.kernel == 3);
   with_pool(a.kernel, [&](auto PWc, auto NGc) {
     constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
@@ -2005,12 +2030,12 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
       constexpr bool l = decltype(L)::value, t = decltype(T)::value, o = decltype(O)::value;
       if constexpr (!FP64)
         if (pools) {
-          if constexpr (PW == kPoolSmall && NG == 2)
-            if (gen) {
-              k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG, true>;
-              return;
-            }
           k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG>;
+          if constexpr (PW == kPoolSmall && NG == 2)
+            if (gen) k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG, true>;
+          // a resident grid takes the items from the batch's counter
+          k.persistent = true;
+          k.grid = dim3(resident_blocks(k.func, k.shm, (uint32_t)n_items));
           return;
         }
       if (gen) {
@@ -2046,6 +2071,8 @@ hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
   return trace ? launch_step_t<false, true>(g, s, a, st)
                : launch_step_t<false, false>(g, s, a, st);
 }
+
+const void *batch_reset_kernel() { return (const void *)k_batch_reset; }
 
 int32_t batch_tile(bool fp64, int32_t kernel) {
   return (!fp64 && kernel >= 1) ? pool_per_wave(kernel) * kWavesPerBlock * kBatchGens : kBlock;
