@@ -419,3 +419,45 @@ def test_autotune_choice_and_auto_schedule_bitwise(B):
         assert np.array_equal(ra[f], rl[f]), f
     for x, y in zip(B.mg_exit_counts(auto), B.mg_exit_counts(lanes)):
         assert np.array_equal(x, y)
+
+
+def test_fp32_near_vertex_fp64_solve(B, orc):
+    """FP32 particles that start closer to a vertex than 1e-6 L (but not on
+    it), with drift toward it: their crossings are solved in FP64.  Step by
+    step for five steps, at both ends of an edge (the initial end, and the
+    terminal end seen from the near end's frame), slot sequences equal the
+    oracle's and positions stay within 1e-6 of its FP64 ones on 99.9 % of
+    the particles.  The rest are bounded by 1e-4: an FP32 normal whose first
+    uniform lies next to 1 carries the float spacing of that uniform (a
+    relative error up to about 1e-3 of a small normal), and a crossing
+    where the drift into the vertex and the noise out of it nearly cancel
+    turns it into an error of the remaining time."""
+    g = workloads.star_graph(3, [1.0, 0.7, 1.3], [-2.0, 3.0, -1.0], None, 1.0,
+                             b_center=[0.5, 0.3, 0.2])
+    rng = np.random.default_rng(17)
+    n = 30_000
+    edge = rng.integers(0, 3, size=n).astype(np.int32)
+    d = np.exp(rng.uniform(np.log(1e-10), np.log(0.99e-6), size=n)) * g.length[edge]
+    # drift toward the centre on edges 0 and 2 (start next to x = 0), toward
+    # the leaf on edge 1 (start next to x = L)
+    pos = np.where(edge == 1, g.length[edge] - d, d)
+    assert np.all((pos > 0.0) & (pos < g.length[edge]))
+    dt = 1e-4
+    G = B.mg_graph_create(g)
+    st = orc.init(g, n, orc.INIT_EXPLICIT, edge=edge, pos=pos)
+    p = B.mg_particles_init(G, n, B.MG_INIT_EXPLICIT, edge=edge, pos=pos,
+                            precision=B.MG_FP32, trace=True, schedule=B.MG_SCHED_LANES)
+    hits = 0
+    for k in range(5):
+        c = orc.simulate(g, st, k, 1, dt, 29)
+        B.mg_simulate(p, 1, dt, 29)
+        r = B.mg_particles_read(p, trace=True)
+        same = r["seqhash"] == st.seqhash
+        assert same.mean() >= 0.999, (k, same.mean())
+        assert np.array_equal(r["edge"][same], st.edge[same])
+        dx = np.abs(r["x"][same] - st.x[same])
+        assert np.quantile(dx, 0.999) <= 1e-6, (k, np.quantile(dx, 0.999))
+        assert dx.max() <= 1e-4, (k, dx.max())
+        hits += c.hits
+    # most of the first steps cross the vertex they start next to
+    assert hits > n // 3
