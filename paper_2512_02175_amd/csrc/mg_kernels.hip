@@ -73,6 +73,46 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
   return {c0, c1, c2, c3};
 }
 
+// Sine and cosine of t in [0, 2 pi) (the Box-Muller angle, t = 2 pi u with
+// u in (0, 1)): the argument is reduced by quarter turns, r = t - q pi/2
+// with pi/2 in two parts (Cody and Waite); for q <= 4 the first step
+// fma(-q, hi, t) is exact, so r carries the error of the second alone.
+// On |r| <= pi/4 the Taylor polynomials of degree 17 (sine) and 16
+// (cosine) leave a truncation below 1e-17, and Horner's rule with fused
+// multiply-adds keeps the result within one ulp of the correctly rounded
+// value (the general library routine handles any argument and costs several
+// times as much).  The quadrant then picks and signs the two.
+__device__ __forceinline__ void sincos_small(double t, double &s_out, double &c_out) {
+  const double q = rint(t * 0.6366197723675814);
+  double r = fma(-q, 1.5707963267948966, t);
+  r = fma(-q, 6.123233995736766e-17, r);
+  const double x2 = r * r;
+  double ps = -8.22063524662433e-18;  // (-1)^k / (2k+1)!, k = 8 .. 1
+  ps = fma(ps, x2, 2.8114572543455206e-15);
+  ps = fma(ps, x2, -7.647163731819816e-13);
+  ps = fma(ps, x2, 1.6059043836821613e-10);
+  ps = fma(ps, x2, -2.505210838544172e-08);
+  ps = fma(ps, x2, 2.7557319223985893e-06);
+  ps = fma(ps, x2, -0.0001984126984126984);
+  ps = fma(ps, x2, 0.008333333333333333);
+  ps = fma(ps, x2, -0.16666666666666666);
+  const double sn = fma(r * x2, ps, r);
+  double pc = 4.779477332387385e-14;  // (-1)^k / (2k)!, k = 8 .. 0
+  pc = fma(pc, x2, -1.1470745597729725e-11);
+  pc = fma(pc, x2, 2.08767569878681e-09);
+  pc = fma(pc, x2, -2.755731922398589e-07);
+  pc = fma(pc, x2, 2.48015873015873e-05);
+  pc = fma(pc, x2, -0.001388888888888889);
+  pc = fma(pc, x2, 0.041666666666666664);
+  pc = fma(pc, x2, -0.5);
+  const double cs = fma(pc, x2, 1.0);
+  const int iq = (int)q & 3;
+  const bool swap = iq & 1;
+  const double a = swap ? cs : sn, b = swap ? sn : cs;
+  s_out = (iq >= 2) ? -a : a;
+  c_out = (iq == 1 || iq == 2) ? -b : b;
+}
+
 // Box-Muller in FP64: R = sqrt(-2 ln u1), angle 2 pi u2, u = (bits + 1/2) 2^-32.
 __device__ __forceinline__ void box_muller64(uint32_t a, uint32_t b, double &wc,
                                              double &ws) {
@@ -80,7 +120,7 @@ __device__ __forceinline__ void box_muller64(uint32_t a, uint32_t b, double &wc,
   const double u2 = ((double)b + 0.5) * 0x1p-32;
   const double r = sqrt(-2.0 * log(u1));
   double s, c;
-  sincos(kTwoPi * u2, &s, &c);
+  sincos_small(kTwoPi * u2, s, c);
   wc = r * c;
   ws = r * s;
 }
@@ -88,7 +128,9 @@ __device__ __forceinline__ void box_muller64(uint32_t a, uint32_t b, double &wc,
 __device__ __forceinline__ double box_muller64_cos(uint32_t a, uint32_t b) {
   const double u1 = ((double)a + 0.5) * 0x1p-32;
   const double u2 = ((double)b + 0.5) * 0x1p-32;
-  return sqrt(-2.0 * log(u1)) * cos(kTwoPi * u2);
+  double s, c;
+  sincos_small(kTwoPi * u2, s, c);
+  return sqrt(-2.0 * log(u1)) * c;
 }
 
 // Box-Muller in FP32 on the transcendental unit: v_log_f32 is log2 and
