@@ -184,9 +184,13 @@ void mg_graph_destroy(mg_graph *g);
  *                 windows of 8 first sub-steps, two Philox groups, per
  *                 pass instead of 4).
  *                 Results are identical; only the speed differs.  FP64 sets
- *                 always use the lane schedule.  On a graph with higher
- *                 coefficient terms (mg_graph_desc) only MG_SCHED_AUTO,
- *                 MG_SCHED_LANES and MG_SCHED_POOLS_W8 are accepted.
+ *                 run MG_SCHED_LANES or MG_SCHED_POOLS_W8 (FP64 wave pools
+ *                 of 128 with 8-step windows, also the automatic choice;
+ *                 MG_SCHED_POOLS and MG_SCHED_POOLS256 are refused), with
+ *                 identical results; FP64 batches run the lane schedule.
+ *                 On a graph with higher coefficient terms (mg_graph_desc)
+ *                 FP32 sets accept only MG_SCHED_AUTO, MG_SCHED_LANES and
+ *                 MG_SCHED_POOLS_W8.
  */
 typedef enum {
   MG_SCHED_AUTO = 0, MG_SCHED_LANES = 1, MG_SCHED_POOLS = 2, MG_SCHED_POOLS256 = 3,
@@ -391,7 +395,7 @@ void mg_batch_destroy(mg_batch *b);
  * schedule MG_SCHED_AUTO are tuned this way on their first mg_simulate at
  * each dt; until then (and in a batch built from untuned sets) they use
  * pools of 128 with 8-step windows.  Fixed pool schedules start a partial
- * pass at 16 idle lanes.  FP64 sets have nothing to tune (schedule lanes).  `out` (may be
+ * pass at 16 idle lanes.  FP64 sets have nothing to probe (their set's FP64 schedule).  `out` (may be
  * NULL) receives the choice and the probe times.  A probe allocates scratch
  * device memory and synchronises the stream.
  */

@@ -595,6 +595,9 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
       (o.schedule == MG_SCHED_POOLS || o.schedule == MG_SCHED_POOLS256))
     return fail(MG_EINVAL, "graphs with higher coefficients or Wentzell vertices run the "
                 "FP32 lane schedule or MG_SCHED_POOLS_W8 only");
+  if (o.precision == MG_FP64 &&
+      (o.schedule == MG_SCHED_POOLS || o.schedule == MG_SCHED_POOLS256))
+    return fail(MG_EINVAL, "FP64 sets run MG_SCHED_LANES, MG_SCHED_POOLS_W8 or MG_SCHED_AUTO");
   if (mode == MG_INIT_EXPLICIT) {
     if (!edge || !pos) return fail(MG_EINVAL, "explicit init needs edge and pos");
     for (int64_t i = 0; i < n; ++i) {
@@ -791,6 +794,17 @@ static int32_t fp32_kernel(const mg_particles *p) {
   return p->tuned ? p->tuned_kernel : 3;
 }
 
+// FP64 step kernel of a set: the lane schedule (MG_SCHED_LANES) or wave
+// pools of 128 with 8-step windows (MG_SCHED_POOLS_W8, and the automatic
+// choice).
+static int32_t fp64_kernel(const mg_particles *p) {
+  return p->schedule == MG_SCHED_LANES ? 0 : 3;
+}
+
+static int32_t step_kernel(const mg_particles *p) {
+  return p->prec == MG_FP64 ? fp64_kernel(p) : fp32_kernel(p);
+}
+
 static int32_t pool_idle(const mg_particles *p) {
   return (p->schedule == MG_SCHED_AUTO && p->tuned) ? p->tuned_idle : 16;
 }
@@ -822,7 +836,7 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   a.dt = dt;
-  a.kernel = fp32_kernel(p);
+  a.kernel = step_kernel(p);
   a.idle = pool_idle(p);
   const uint32_t chunk = chunk_steps(p->steps_per_launch);
   int64_t left = n_steps;
@@ -1335,8 +1349,11 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
     return MG_OK;
   }
   if (p->prec == MG_FP64) {
-    res.schedule = MG_SCHED_LANES;
-    res.idle_trigger = 0;
+    // one FP64 schedule of each kind is built: nothing to probe
+    res.schedule = schedule_of(fp64_kernel(p));
+    res.idle_trigger = res.schedule == MG_SCHED_LANES ? 0 : pool_idle(p);
+    res.pool_size = res.schedule == MG_SCHED_LANES ? 0 : kPoolSmall;
+    res.window = 8;
     if (out) *out = res;
     return MG_OK;
   }

@@ -471,6 +471,15 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
 }
 
 // ------------------------------------------------------------ FP64 path --
+// Resolution state of an FP64 step whose sub-step proposal reached a vertex:
+// the remaining time, the pending sub-step's normal (as drawn; a sub-step
+// from a vertex folds it into the edge), the crossings so far and the last
+// slot drawn.
+struct Hit64 {
+  double h, w;
+  int32_t k, last;
+};
+
 // The canonical step in FP64, operation for operation.
 template <bool TRACE, bool LDS, bool GEN>
 struct Particle64 {
@@ -491,10 +500,22 @@ struct Particle64 {
 
   // FP64 positions are always measured from the initial vertex.
   __device__ __forceinline__ void reanchor() {}
-  template <int N>
-  __device__ __forceinline__ void prep_window(double (&)[N], uint32_t, bool = true) const {}
+  __device__ __forceinline__ void reanchor_if(bool) {}
   __device__ __forceinline__ bool fast_first(double w) { return fast(w); }
   __device__ __forceinline__ double pos64(double) const { return x; }
+
+  // Window preparation of the wave pools: only a window's first active step
+  // can start on a vertex (every step that stays inside an edge ends
+  // strictly inside it), where the normal points into the edge.
+  template <int N>
+  __device__ __forceinline__ void prep_window(double (&W)[N], uint32_t jb, bool on = true) const {
+    if (on && (x == 0.0 || x == R.L)) {
+      const bool init = x == 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        W[i] = (jb == (uint32_t)i) ? (init ? fabs(W[i]) : -fabs(W[i])) : W[i];
+    }
+  }
 
   // Drift and diffusion at x: affine and constant, or with GEN the cubics
   // by Horner's rule (with zero higher terms these equal the affine values
@@ -540,14 +561,36 @@ struct Particle64 {
     return false;
   }
 
-  double dtv;
+  // The same first sub-step as straight-line code (the wave pools): applied
+  // only where `active`; returns whether the proposal stays inside the edge
+  // (a step that starts on a Wentzell vertex never does: it is parked for
+  // its visit).  The normal is already folded where the step starts on a
+  // vertex (prep_window).
+  __device__ __forceinline__ bool fast_pred(double w, bool active) {
+    const double mu = drift(x);
+    const double g = diffusion(x) * sqdt;
+    const double xt = fma(g, w, fma(mu, dtv, x));
+    const bool in = (xt > 0.0) & (xt < R.L) & !on_wentzell();
+    x = (active & in) ? xt : x;
+    return in;
+  }
 
-  __device__ void resolve(uint32_t step, double w, uint32_t pid, const SetDev &S,
-                          const StepArgs &A, Tally &t) {
-    double h = dtv;
-    int32_t k = 0, last = -1;
-    bool first = true;
-    if (on_wentzell()) {
+  double dtv;
+  double sqdt;  // sqrt(dtv)
+
+  // One vertex crossing of a step whose pending sub-step proposal (normal
+  // H.w over the remaining time H.h; the step's first sub-step when
+  // H.k == 0) reached a vertex: crossing time, edge draw, and the next
+  // sub-step's proposal.  Returns true when the step is complete (inside an
+  // edge, absorbed, out of time or at the split cap), false when the next
+  // proposal reaches a vertex again.  resolve() loops over it; the wave
+  // pools run one crossing per lane per pass.  A step that starts on a
+  // Wentzell vertex begins here with its visit.
+  __device__ bool cross(uint32_t step, Hit64 &H, uint32_t pid, const SetDev &S,
+                        const StepArgs &A, Tally &t) {
+    double h = H.h;
+    bool left_visit = false;  // the move that leaves a start-of-step visit
+    if (H.k == 0 && on_wentzell()) {
       // a step that starts on a Wentzell vertex: the stay owed there first,
       // then the visit that leaves it (its own local time only, o = 0); a
       // step spent on the vertex, or ended by the visit's killing, has no
@@ -558,46 +601,46 @@ struct Particle64 {
       if (owe >= h) {
         owe = owe - h;
         x = init ? -owe : R.L + owe;
-        return;
+        return true;
       }
       h = h - owe;
       x = init ? 0.0 : R.L;
       double hm, owed;
       if (wz_visit(G.wz[G.vtx[v].wz - 1u], 0.0, h, vertex_draw(pid, step, 0u, S, A), hm, owed)) {
         die(v, step, S);
-        return;
+        return true;
       }
       if (hm == 0.0) {
         x = init ? -owed : R.L + owed;
-        return;
+        return true;
       }
       h = hm;
+      H.h = h;
+      left_visit = true;
     }
-    for (;;) {
-      if (x == 0.0)
-        w = fabs(w);
-      else if (x == R.L)
-        w = -fabs(w);
-      const double mu = drift(x);
-      const double g = diffusion(x) * sqrt(h);
-      const double xt = fma(g, w, fma(mu, h, x));
-      if (!first) t.sub++;
-      first = false;
-      if (xt > 0.0 && xt < R.L) {
-        x = xt;
-        break;
-      }
-      const bool at_init = xt <= 0.0;
-      const int32_t vr = at_init ? R.vinit : R.vterm;
-      if (vr < 0) {
-        // reflecting leaf: the mirror image ends the step if it lies
-        // inside the edge
-        const double xr = at_init ? -xt : 2.0 * R.L - xt;
-        if (xr > 0.0 && xr < R.L) {
-          x = xr;
-          break;
-        }
-      }
+    // the pending proposal, recomputed as it was made
+    double w = H.w;
+    if (x == 0.0)
+      w = fabs(w);
+    else if (x == R.L)
+      w = -fabs(w);
+    const double mu = drift(x);
+    const double g = diffusion(x) * sqrt(h);
+    const double xt = fma(g, w, fma(mu, h, x));
+    bool done = false;
+    if (left_visit && xt > 0.0 && xt < R.L) {
+      x = xt;
+      return true;
+    }
+    const bool at_init = xt <= 0.0;
+    const int32_t vr = at_init ? R.vinit : R.vterm;
+    // reflecting leaf: the mirror image ends the step if it lies inside
+    // the edge
+    const double xr = at_init ? -xt : 2.0 * R.L - xt;
+    if (vr < 0 && xr > 0.0 && xr < R.L) {
+      x = xr;
+      done = true;
+    } else {
       const int32_t v = vr & kVertexMask;
       const double d = at_init ? x : R.L - x;
       const double qa = at_init ? mu * h : -(mu * h);
@@ -605,7 +648,7 @@ struct Particle64 {
       const double u = first_root64(qa, qb, d);
       const double alpha = u * u;
       h = fma(-alpha, h, h);
-      ++k;
+      ++H.k;
       ++nhit;
       t.hits++;
       const VtxBlk vb = G.vtx[v];
@@ -615,36 +658,56 @@ struct Particle64 {
       bool killed = false;
       if (GEN && vb.wz) {
         const double o = at_init ? -xt : xt - R.L;
-        killed = wz_visit(G.wz[vb.wz - 1u], o, h, vertex_draw(pid, step, (uint32_t)k, S, A),
+        killed = wz_visit(G.wz[vb.wz - 1u], o, h, vertex_draw(pid, step, (uint32_t)H.k, S, A),
                           h_move, owed);
       }
       if (vb.deg < 0 || killed) {  // absorbing vertex, or killed at the visit
         die(v, step, S);
-        break;
+        return true;
       }
-      const U4 hd = philox(pid, step, (uint32_t)k, S.tag, A.key0, A.key1);
+      const U4 hd = philox(pid, step, (uint32_t)H.k, S.tag, A.key0, A.key1);
       const SlotPick sp = pick_slot(G, vb, hd.x);
-      const int32_t s = sp.s;
       e = eo_edge(sp.eo);
       R = G.e64[e];
       x = (sp.eo & 1u) ? R.L : 0.0;
-      last = s;
-      if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)s);
+      H.last = sp.s;
+      if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)sp.s);
       if (GEN && vb.wz) {
         h = h_move;
         if (h == 0.0) {  // stays on the vertex for the rest of the step
           x = (sp.eo & 1u) ? R.L + owed : -owed;
-          break;
+          done = true;
         }
       }
-      if (h == 0.0) break;
-      if (k == A.max_splits) {
+      if (!done) done = h == 0.0;
+      if (!done && H.k == A.max_splits) {
         t.trunc++;
-        break;
+        done = true;
       }
-      w = box_muller64_cos(hd.y, hd.z);
+      if (!done) {
+        // the next sub-step, from the vertex (normal folded into the edge)
+        H.w = box_muller64_cos(hd.y, hd.z);
+        H.h = h;
+        const double w2 = (sp.eo & 1u) ? -fabs(H.w) : fabs(H.w);
+        const double mu2 = drift(x);
+        const double g2 = diffusion(x) * sqrt(h);
+        const double xt2 = fma(g2, w2, fma(mu2, h, x));
+        t.sub++;
+        if (xt2 > 0.0 && xt2 < R.L) {
+          x = xt2;
+          done = true;
+        }
+      }
     }
-    if (k >= 1 && alive) count_exit<LDS>(s_exit, S.exit_cnt, last);
+    if (done && H.k > 0) count_exit<LDS>(s_exit, S.exit_cnt, H.last);
+    return done;
+  }
+
+  __device__ void resolve(uint32_t step, double w, uint32_t pid, const SetDev &S,
+                          const StepArgs &A, Tally &t) {
+    Hit64 H{dtv, w, 0, -1};
+    while (!cross(step, H, pid, S, A, t)) {
+    }
   }
 };
 
@@ -660,7 +723,7 @@ __device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const St
   }
   Particle64<TRACE, LDS, GEN> q{G, s_exit, e, S.x64[pid], G.e64[e], true,
                            TRACE ? S.seqhash[pid] : 0ull, TRACE ? S.hits[pid] : 0u,
-                           0u, A.dt};
+                           0u, A.dt, sqrt(A.dt)};
   if (!((q.x >= 0.0 && q.x <= q.R.L) || q.on_wentzell())) {
     atomicOr(S.err, kErrPos);
     return;
@@ -1274,6 +1337,24 @@ struct PoolLds32 : PoolTrace<TRACE, PW> {
   uint8_t freeq[PW];  // home slots without a particle
 };
 
+// The same for FP64 particles: position from the initial vertex, and the
+// parked step's normal and remaining time in FP64.
+template <bool TRACE, int PW>
+struct PoolLds64 : PoolTrace<TRACE, PW> {
+  static_assert(PW % 64 == 0 && PW <= 256, "slot ids are bytes");
+  uint32_t ef[PW];
+  uint32_t n[PW];
+  double x[PW];
+  double w[PW];
+  double h[PW];
+  int32_t last[PW];
+  uint32_t pid[PW];
+  uint8_t k[PW];
+  uint8_t ready[PW];
+  uint8_t split[PW];
+  uint8_t freeq[PW];
+};
+
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -1284,6 +1365,8 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 // move the accesses across each other.
 __device__ __forceinline__ void wave_lds_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
+// Moving particles between registers, the pool's home slots and the set:
+// one overload per precision.
 template <bool TRACE, bool LDS, bool GEN, int PW>
 __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS, GEN> &q,
                                           const PoolLds32<TRACE, PW> &P,
@@ -1295,6 +1378,19 @@ __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS, GEN> &q,
   q.yl = P.yl[s];
   q.R = load_edge32(q.G.e32, q.e);
   q.frame();
+  q.alive = true;
+  if constexpr (TRACE) {
+    q.nhit = P.hits[s];
+    q.hash = P.hash[s];
+  }
+}
+template <bool TRACE, bool LDS, bool GEN, int PW>
+__device__ __forceinline__ void pool_load(Particle64<TRACE, LDS, GEN> &q,
+                                          const PoolLds64<TRACE, PW> &P,
+                                          uint32_t s) {
+  q.e = (int32_t)(P.ef[s] & kEdgeMask);
+  q.x = P.x[s];
+  q.R = q.G.e64[q.e];
   q.alive = true;
   if constexpr (TRACE) {
     q.nhit = P.hits[s];
@@ -1315,6 +1411,124 @@ __device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS, GEN> &q,
     P.hash[s] = q.hash;
   }
 }
+template <bool TRACE, bool LDS, bool GEN, int PW>
+__device__ __forceinline__ void pool_store(const Particle64<TRACE, LDS, GEN> &q,
+                                           PoolLds64<TRACE, PW> &P,
+                                           uint32_t s, uint32_t n) {
+  P.ef[s] = (uint32_t)q.e;
+  P.x[s] = q.x;
+  P.n[s] = n;
+  if constexpr (TRACE) {
+    P.hits[s] = q.nhit;
+    P.hash[s] = q.hash;
+  }
+}
+
+// A parked step's resolution state, to and from its home slot (a fresh
+// park, k = 0, has the whole step left: dt, no slot drawn yet).
+template <bool TRACE, int PW>
+__device__ __forceinline__ Hit32 pool_hit(const PoolLds32<TRACE, PW> &P, uint32_t s,
+                                          const StepArgs &A) {
+  Hit32 h{(float)A.dt, 0.0f, P.w[s], (int32_t)P.k[s], -1};
+  if (h.k > 0) {
+    h.hh = P.hh[s];
+    h.hl = P.hl[s];
+    h.last = P.last[s];
+  }
+  return h;
+}
+template <bool TRACE, int PW>
+__device__ __forceinline__ void pool_park(PoolLds32<TRACE, PW> &P, uint32_t s, const Hit32 &h) {
+  P.w[s] = h.w;
+  P.hh[s] = h.hh;
+  P.hl[s] = h.hl;
+  P.last[s] = h.last;
+  P.k[s] = (uint8_t)h.k;
+}
+template <bool TRACE, int PW>
+__device__ __forceinline__ Hit64 pool_hit(const PoolLds64<TRACE, PW> &P, uint32_t s,
+                                          const StepArgs &A) {
+  Hit64 h{A.dt, P.w[s], (int32_t)P.k[s], -1};
+  if (h.k > 0) {
+    h.h = P.h[s];
+    h.last = P.last[s];
+  }
+  return h;
+}
+template <bool TRACE, int PW>
+__device__ __forceinline__ void pool_park(PoolLds64<TRACE, PW> &P, uint32_t s, const Hit64 &h) {
+  P.w[s] = h.w;
+  P.h[s] = h.h;
+  P.last[s] = h.last;
+  P.k[s] = (uint8_t)h.k;
+}
+
+// Reads particle id from the set when a wave claims it: the state word
+// and position go to home slot hs.  False for a removed particle, and for
+// a corrupt state (the set's error word is raised).
+template <bool TRACE, int PW, bool GEN>
+__device__ __forceinline__ bool pool_claim(const GView &G, const SetDev &S, int32_t n_edges,
+                                           uint32_t id, PoolLds32<TRACE, PW> &P, uint32_t hs,
+                                           bool mine) {
+  bool ok = false;
+  uint32_t ef = 0;
+  float2 yy = make_float2(0.0f, 0.0f);
+  if (mine) {
+    ef = S.ef[id];
+    yy = S.y32[id];
+    const int32_t e = (int32_t)(ef & kEdgeMask);
+    if (!(ef & kDeadBit)) {
+      if (e >= n_edges) {
+        atomicOr(S.err, kErrEdge);
+      } else if (!((yy.x >= 0.0f && yy.x <= G.e32[e].L) ||
+                   (GEN && yy.x < 0.0f &&
+                    ((uint32_t)((ef & kSideBit) ? G.e32[e].vterm : G.e32[e].vinit) &
+                     kWentzellEnd)))) {
+        atomicOr(S.err, kErrPos);
+      } else {
+        ok = true;
+      }
+    }
+  }
+  if (ok) {
+    P.ef[hs] = ef;
+    P.y[hs] = yy.x;
+    P.yl[hs] = yy.y;
+  }
+  return ok;
+}
+template <bool TRACE, int PW, bool GEN>
+__device__ __forceinline__ bool pool_claim(const GView &G, const SetDev &S, int32_t n_edges,
+                                           uint32_t id, PoolLds64<TRACE, PW> &P, uint32_t hs,
+                                           bool mine) {
+  bool ok = false;
+  uint32_t ef = 0;
+  double x = 0.0;
+  if (mine) {
+    ef = S.ef[id];
+    x = S.x64[id];
+    const int32_t e = (int32_t)(ef & kEdgeMask);
+    if (!(ef & kDeadBit)) {
+      if (e >= n_edges) {
+        atomicOr(S.err, kErrEdge);
+      } else {
+        const EdgeRec64 &r = G.e64[e];
+        if (!((x >= 0.0 && x <= r.L) ||
+              (GEN && ((x <= 0.0 && ((uint32_t)r.vinit & kWentzellEnd)) ||
+                       (x >= r.L && ((uint32_t)r.vterm & kWentzellEnd)))))) {
+          atomicOr(S.err, kErrPos);
+        } else {
+          ok = true;
+        }
+      }
+    }
+  }
+  if (ok) {
+    P.ef[hs] = ef;
+    P.x[hs] = x;
+  }
+  return ok;
+}
 
 // Writes a particle back at the end of its launch and counts the steps it
 // took (each has one first sub-step; resolve() counts the others).
@@ -1330,6 +1544,34 @@ __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS, GEN> &q
   const uint32_t taken = q.alive ? A.nsteps : q.death_step + 1u - S.n0;
   t.steps += taken;
   t.sub += taken;
+}
+template <bool TRACE, bool LDS, bool GEN>
+__device__ __forceinline__ void pool_finish(const Particle64<TRACE, LDS, GEN> &q, const SetDev &S,
+                                            const StepArgs &A, uint32_t pid, Tally &t) {
+  S.ef[pid] = (uint32_t)q.e | (q.alive ? 0u : kDeadBit);
+  S.x64[pid] = q.x;
+  if (TRACE) {
+    S.seqhash[pid] = q.hash;
+    S.hits[pid] = q.nhit;
+  }
+  const uint32_t taken = q.alive ? A.nsteps : q.death_step + 1u - S.n0;
+  t.steps += taken;
+  t.sub += taken;
+}
+
+// A particle of the pool loop, before its first pickup: the graph view,
+// exit counters and the launch's dt.
+template <bool TRACE, bool LDS, bool GEN>
+__device__ __forceinline__ void pool_particle(Particle32<TRACE, LDS, GEN> &q, const GView &G,
+                                              uint32_t *s_exit, const StepArgs &A) {
+  q = Particle32<TRACE, LDS, GEN>{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f,
+                                  (float)A.dt, (float)sqrt(A.dt), true, 0ull, 0u, 0u};
+}
+template <bool TRACE, bool LDS, bool GEN>
+__device__ __forceinline__ void pool_particle(Particle64<TRACE, LDS, GEN> &q, const GView &G,
+                                              uint32_t *s_exit, const StepArgs &A) {
+  q = Particle64<TRACE, LDS, GEN>{G, s_exit, 0, 0.0, EdgeRec64{}, true, 0ull, 0u, 0u,
+                                  A.dt, sqrt(A.dt)};
 }
 
 // Adds a lane's tallies to the block's 64-bit totals and clears them.
@@ -1371,16 +1613,17 @@ __device__ __forceinline__ void drain_lds(uint32_t *lds, uint64_t *glob, int32_t
 // finds the set run out stops claiming, so every wave passes n by at most
 // one claim of 64 per set and launch (a batched launch lets a block join a
 // set only while its counter is below n, so this holds there too).
-template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool GEN>
-__device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
-                           const StepArgs &A, PoolLds32<TRACE, PW> &P, uint32_t *s_exit, Tally &t,
-                           unsigned long long *s_tot, int32_t nnz, const ObsSink &sink) {
+// Q: the particle type (Particle32 or Particle64, each with its pool type
+// in LDS).
+template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool GEN, class Q, class Pool>
+__device__ void run_pool(const GView &G, int32_t n_edges, const SetDev &S,
+                         const StepArgs &A, Pool &P, uint32_t *s_exit, Tally &t,
+                         unsigned long long *s_tot, int32_t nnz, const ObsSink &sink) {
+  using real = typename Q::real;
   const uint32_t lane = threadIdx.x & 63u;
-  const float dt = (float)A.dt;
-  const float sqdt = (float)sqrt(A.dt);
   const uint32_t n_end = S.n0 + A.nsteps;
-  Particle32<TRACE, LDS, GEN> q{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt, sqdt,
-                                 true, 0ull, 0u, 0u};
+  Q q;
+  pool_particle(q, G, s_exit, A);
   bool has = false;
   uint32_t slot = 0, n = 0, pid = 0;  // the lane's home slot, next step, particle
   uint32_t snap = 0;  // next snapshot count of the lane's particle
@@ -1421,34 +1664,12 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       if (b + want >= lim) exhausted = true;
       const uint32_t id = b + lane;
       const bool mine = lane < want;
-      bool ok = false;
-      uint32_t ef = 0;
-      float2 yy = make_float2(0.0f, 0.0f);
-      if (mine && id < lim) {
-        ef = S.ef[id];
-        yy = S.y32[id];
-        const int32_t e = (int32_t)(ef & kEdgeMask);
-        if (!(ef & kDeadBit)) {
-          if (e >= n_edges) {
-            atomicOr(S.err, kErrEdge);
-          } else if (!((yy.x >= 0.0f && yy.x <= G.e32[e].L) ||
-                       (GEN && yy.x < 0.0f &&
-                        ((uint32_t)((ef & kSideBit) ? G.e32[e].vterm : G.e32[e].vinit) &
-                         kWentzellEnd)))) {
-            atomicOr(S.err, kErrPos);
-          } else {
-            ok = true;
-          }
-        }
-      }
       const uint32_t hs = mine ? P.freeq[(f_head + lane) % K] : 0u;
+      const bool ok = pool_claim<TRACE, PW, GEN>(G, S, n_edges, id, P, hs, mine && id < lim);
       f_head += want;
       const uint64_t m_ok = __ballot(ok);
       const uint64_t m_back = __ballot(mine & !ok);
       if (ok) {
-        P.ef[hs] = ef;
-        P.y[hs] = yy.x;
-        P.yl[hs] = yy.y;
         P.n[hs] = S.n0;
         P.pid[hs] = id;
         if constexpr (TRACE) {
@@ -1494,18 +1715,18 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       // straight-line code; a lane without a particle has no active step.
       constexpr uint32_t NW = 4u * NG;
       const uint32_t base = n & ~3u;
-      float W[NW];
+      real W[NW];
 #pragma unroll
       for (uint32_t g = 0; g < (uint32_t)NG; ++g) {
         const U4 o = philox(pid, (base >> 2) + g, 0u, S.tag, A.key0, A.key1);
-        box_muller32(o.x, o.y, W[4 * g + 0], W[4 * g + 1]);
-        box_muller32(o.z, o.w, W[4 * g + 2], W[4 * g + 3]);
+        Q::box_muller(o.x, o.y, W[4 * g + 0], W[4 * g + 1]);
+        Q::box_muller(o.z, o.w, W[4 * g + 2], W[4 * g + 3]);
       }
       const uint32_t jb = n & 3u;  // = n - base
       const uint32_t je = has ? min(NW, n_end - base) : 0u;
       q.prep_window(W, jb, has);
       int32_t pj = -1;
-      float wp = 0.0f;
+      real wp = 0;
       bool go = true;  // no vertex reached yet in this window
 #pragma unroll
       for (uint32_t j = 0; j < NW; ++j) {
@@ -1536,7 +1757,7 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       if (parked) {
         pool_store(q, P, slot, n);
         P.w[slot] = wp;
-        P.k[slot] = 0;  // fresh: hh = dt, hl = 0, no slot drawn yet
+        P.k[slot] = 0;  // fresh: the whole step left, no slot drawn yet
         P.split[(s_tail + lane_rank(m_park)) % K] = (uint8_t)slot;
       }
       s_tail += (uint32_t)__popcll(m_park);
@@ -1558,25 +1779,16 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
       uint32_t s2 = 0;
       if (lane < B) {
         s2 = P.split[(s_base + lane) % K];
-        Particle32<TRACE, LDS, GEN> q2{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f, dt,
-                                  sqdt, true, 0ull, 0u, 0u};
+        Q q2;
+        pool_particle(q2, G, s_exit, A);
         pool_load(q2, P, s2);
         const uint32_t step = P.n[s2];
         const uint32_t pid2 = P.pid[s2];
-        Hit32 h{dt, 0.0f, P.w[s2], (int32_t)P.k[s2], -1};
-        if (h.k > 0) {
-          h.hh = P.hh[s2];
-          h.hl = P.hl[s2];
-          h.last = P.last[s2];
-        }
+        auto h = pool_hit(P, s2, A);
         if (!q2.cross(step, h, pid2, S, A, t)) {
           // reached a vertex again: back on the split queue for a later pass
           pool_store(q2, P, s2, step);
-          P.w[s2] = h.w;
-          P.hh[s2] = h.hh;
-          P.hl[s2] = h.hl;
-          P.last[s2] = h.last;
-          P.k[s2] = (uint8_t)h.k;
+          pool_park(P, s2, h);
           again = true;
         } else {
           if (q2.alive) {
@@ -1611,28 +1823,34 @@ __device__ void run_pool32(const GView &G, int32_t n_edges, const SetDev &S,
 // [snapshot bins].  Stages the set's tables, runs its particles until the
 // set's counter has run out and the block's pools are empty, and adds the
 // block's counts to the set's counters.
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool GEN>
+template <int PW, bool FP64, bool TRACE>
+using PoolLds = std::conditional_t<FP64, PoolLds64<TRACE, PW>, PoolLds32<TRACE, PW>>;
+
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool GEN>
 __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, unsigned long long *s_tot,
                                            char *smem) {
+  using Pool = PoolLds<PW, FP64, TRACE>;
+  using Q = std::conditional_t<FP64, Particle64<TRACE, LDS, GEN>, Particle32<TRACE, LDS, GEN>>;
   uint32_t *s_exit = (uint32_t *)smem;
   if (threadIdx.x < 4) s_tot[threadIdx.x] = 0;
   if (LDS)
     for (int32_t s = threadIdx.x; s < G.nnz; s += blockDim.x) s_exit[s] = 0;
   const int32_t ex = LDS ? exit_bytes(G.nnz) : 0;
-  const GView view = block_view<false, STAGED>(G, smem + ex);
-  const int32_t o_pools = align16(ex + (STAGED ? G.stage_bytes32 : 0));
-  PoolLds32<TRACE, PW> *pools = (PoolLds32<TRACE, PW> *)(smem + o_pools);
+  const GView view = block_view<FP64, STAGED>(G, smem + ex);
+  const int32_t o_pools =
+      align16(ex + (STAGED ? (FP64 ? G.stage_bytes64 : G.stage_bytes32) : 0));
+  Pool *pools = (Pool *)(smem + o_pools);
   ObsSink o{nullptr, G.e64};
   if (OBS && A.obs_lds) {
-    o.lds = (uint32_t *)(smem + o_pools + (int32_t)sizeof(PoolLds32<TRACE, PW>) * kWavesPerBlock);
+    o.lds = (uint32_t *)(smem + o_pools + (int32_t)sizeof(Pool) * kWavesPerBlock);
     for (int32_t b = threadIdx.x; b < A.obs_lds; b += blockDim.x) o.lds[b] = 0;
   }
   __syncthreads();
   Tally t{0, 0, 0, 0};
   const uint32_t wave = threadIdx.x >> 6;
-  run_pool32<TRACE, LDS, OBS, PW, NG, GEN>(view, G.E, S, A, pools[wave], s_exit, t, s_tot,
-                                           G.nnz, o);
+  run_pool<TRACE, LDS, OBS, PW, NG, GEN, Q>(view, G.E, S, A, pools[wave], s_exit, t, s_tot,
+                                            G.nnz, o);
   flush(S, t, s_tot, s_exit, G.nnz, LDS);
   if (OBS && A.obs_lds) flush_obs(S, o.lds, A.obs_lds);
 }
@@ -1648,7 +1866,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_
 void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ unsigned long long s_tot[4];
-  pool_block<TRACE, LDS, STAGED, OBS, PW, NG, GEN>(G, S, A, s_tot, (char *)smem4);
+  pool_block<false, TRACE, LDS, STAGED, OBS, PW, NG, GEN>(G, S, A, s_tot, (char *)smem4);
+}
+
+// FP64 wave pools: the same schedule over FP64 particles (pools of 128,
+// 8-step windows).  Two FP64 particles per lane take more registers: four
+// waves per SIMD.
+#ifndef MG_POOL64_WAVES_PER_EU
+#define MG_POOL64_WAVES_PER_EU 4
+#endif
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, bool GEN>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL64_WAVES_PER_EU)))
+void k_pool64(GraphDev G, SetDev S, StepArgs A) {
+  extern __shared__ uint4 smem4[];
+  __shared__ unsigned long long s_tot[4];
+  pool_block<true, TRACE, LDS, STAGED, OBS, kPoolSmall, 2, GEN>(G, S, A, s_tot, (char *)smem4);
 }
 
 // Batched form of the wave pools: a resident grid whose blocks take work
@@ -1686,7 +1918,7 @@ void k_pool32_batch(const GraphDev *graphs, const SetDev *sets, const BatchItem 
     SetDev S = sets[set];
     S.n0 += A.n0_offset;  // steps already taken by earlier launches of this call
     const GraphDev G = graphs[set];
-    pool_block<TRACE, LDS, STAGED, OBS, PW, NG, GEN>(G, S, A, s_tot, (char *)smem4);
+    pool_block<false, TRACE, LDS, STAGED, OBS, PW, NG, GEN>(G, S, A, s_tot, (char *)smem4);
   }
 }
 
@@ -1706,7 +1938,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_
 void k_pool32_probe(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ unsigned long long s_tot[4];
-  pool_block<false, LDS, STAGED, false, PW, NG, false>(G, S, A, s_tot, (char *)smem4);
+  pool_block<false, false, LDS, STAGED, false, PW, NG, false>(G, S, A, s_tot, (char *)smem4);
 }
 
 template <bool LDS, bool STAGED>
@@ -1991,6 +2223,26 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
                          hipStream_t st) {
   StepArgs a = a0;
   const bool obs = s.obs != nullptr;
+  if constexpr (FP64) {
+    if (a.kernel == 3) {
+      // FP64 wave pools (128 per wave, 8-step windows) on a resident grid
+      const LdsPlan lp = plan_lds(g.nnz, g.stage_bytes64,
+                                  sizeof(PoolLds64<TRACE, kPoolSmall>) * kWavesPerBlock, &s,
+                                  g.E);
+      a.obs_lds = lp.obs_lds;
+      const uint32_t need = (s.n + kPoolSmall * kWavesPerBlock - 1) / (kPoolSmall * kWavesPerBlock);
+      hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, st, s.work);
+      with_flags([&](auto L, auto T, auto O, auto Gn) {
+        constexpr bool l = decltype(L)::value, t = decltype(T)::value,
+                       o = decltype(O)::value, gn = decltype(Gn)::value;
+        const void *f = (const void *)k_pool64<TRACE, l, t, o, gn>;
+        hipLaunchKernelGGL((k_pool64<TRACE, l, t, o, gn>),
+                           dim3(resident_blocks(f, lp.shm, need)), dim3(kBlock), lp.shm, st,
+                           g, s, a);
+      }, lp.lds_exit, lp.staged, obs, g.gen != 0);
+      return hipGetLastError();
+    }
+  }
   if (!FP64 && a.kernel >= 1 && (!g.gen || a.kernel == 3)) {
     with_pool(a.kernel, [&](auto PWc, auto NGc) {
       constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
