@@ -132,6 +132,21 @@ typedef struct mg_batch mg_batch;          /* opaque */
  *                        sets on affine graphs (FP64 batches may).
  *   vtx_kill, vtx_sticky [V] a_v and c_v of Wentzell vertices (finite, >= 0;
  *                        read only there; NULL: 0).
+ *   table_offsets        [E+1] or NULL: tabulated coefficient functions (any
+ *                        C^1 drift and diffusion, Sec. 2.2).  Edge e with
+ *                        K + 1 = table_offsets[e+1] - table_offsets[e] >= 2
+ *                        knots (0: no table) has, at x_j = j L_e / K,
+ *                        j = 0..K, the drift value and slope
+ *                        table_mu/table_dmu and the diffusion value and
+ *                        slope table_sigma/table_dsigma (entry
+ *                        table_offsets[e] + j, finite); its mu_e and sigma_e
+ *                        are their cubic Hermite interpolants (C^1, exact for
+ *                        cubics), which replace drift_a, drift_c, sigma (still
+ *                        validated) and require zero higher terms and a
+ *                        finite edge; the tabulated sigma must be > 0 on all
+ *                        of [0, L_e].  Graphs with tables run like graphs with
+ *                        higher terms (FP32 schedules below).
+ *   table_mu, table_dmu, table_sigma, table_dsigma  [table_offsets[E]].
  * Every edge must appear exactly once at its initial vertex with orient 0
  * and once at its terminal vertex with orient 1 (a self-loop twice at its
  * vertex).  A standard vertex needs at least one slot with b > 0.
@@ -151,6 +166,8 @@ typedef struct {
   const double *drift_c2, *drift_c3;
   const double *sigma_c1, *sigma_c2, *sigma_c3;
   const double *vtx_kill, *vtx_sticky;
+  const int32_t *table_offsets;
+  const double *table_mu, *table_dmu, *table_sigma, *table_dsigma;
 } mg_graph_desc;
 
 /* Validates and packs the graph into device tables (edge records, slot

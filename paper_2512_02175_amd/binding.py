@@ -50,7 +50,9 @@ class mg_graph_desc(C.Structure):
                 ("drift_c2", C.c_void_p), ("drift_c3", C.c_void_p),
                 ("sigma_c1", C.c_void_p), ("sigma_c2", C.c_void_p),
                 ("sigma_c3", C.c_void_p), ("vtx_kill", C.c_void_p),
-                ("vtx_sticky", C.c_void_p)]
+                ("vtx_sticky", C.c_void_p), ("table_offsets", C.c_void_p),
+                ("table_mu", C.c_void_p), ("table_dmu", C.c_void_p),
+                ("table_sigma", C.c_void_p), ("table_dsigma", C.c_void_p)]
 
 
 class mg_options(C.Structure):
@@ -212,6 +214,15 @@ def mg_graph_create(desc) -> Graph:
         else:
             keep[k] = np.ascontiguousarray(
                 np.broadcast_to(np.asarray(v, np.float64), (int(desc.n_vertices),)))
+            opt.append(keep[k].ctypes.data)
+    off_t = getattr(desc, "table_offsets", None)     # tabulated coefficients
+    if off_t is None:
+        opt += [None] * 5
+    else:
+        keep["table_offsets"] = np.ascontiguousarray(off_t, np.int32)
+        opt.append(keep["table_offsets"].ctypes.data)
+        for k in ("table_mu", "table_dmu", "table_sigma", "table_dsigma"):
+            keep[k] = np.ascontiguousarray(getattr(desc, k), np.float64)
             opt.append(keep[k].ctypes.data)
     d = mg_graph_desc(int(desc.n_vertices), int(desc.n_edges),
                       *[keep[k].ctypes.data for k in (

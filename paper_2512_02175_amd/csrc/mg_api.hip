@@ -90,6 +90,52 @@ uint32_t pool_drain() {
 // an optional per-edge coefficient array: its entry, or 0 when absent
 double higher(const double *p, int32_t e) { return p ? p[e] : 0.0; }
 
+// s0 + s1 x + s2 x^2 + s3 x^3 > 0 on [0, hi]: its minimum is at an end or at
+// a real root of the derivative s1 + 2 s2 x + 3 s3 x^2, found with the
+// cancellation-free quadratic formula (q = -(b + sgn(b) sqrt(b^2 - 4ac)) / 2,
+// roots q/a and c/q) and refined by one Newton step; the cubic is evaluated
+// there in FP64 (a minimum within rounding of zero may pass either way).
+bool cubic_positive(double s0, double s1, double s2, double s3, double hi) {
+  auto val = [&](double x) { return ((s3 * x + s2) * x + s1) * x + s0; };
+  auto der = [&](double x) { return (3.0 * s3 * x + 2.0 * s2) * x + s1; };
+  auto newton = [&](double x) {
+    const double dd = 6.0 * s3 * x + 2.0 * s2;
+    return dd != 0.0 ? x - der(x) / dd : x;
+  };
+  double crit[4] = {0.0, hi, 0.0, 0.0};
+  int nc = 2;
+  const double qa = 3.0 * s3, qb = 2.0 * s2, qc = s1;
+  if (qa != 0.0) {
+    const double disc = qb * qb - 4.0 * qa * qc;
+    if (disc >= 0.0) {
+      const double q = -0.5 * (qb + std::copysign(std::sqrt(disc), qb));
+      if (q != 0.0) {
+        crit[nc++] = newton(q / qa);
+        crit[nc++] = newton(qc / q);
+      } else {
+        crit[nc++] = 0.0;  // b = c = 0: a double root at 0
+      }
+    }
+  } else if (qb != 0.0) {
+    crit[nc++] = -qc / qb;
+  }
+  for (int i = 0; i < nc; ++i) {
+    const double x = crit[i];
+    if (x >= 0.0 && x <= hi && !(val(x) > 0.0)) return false;
+  }
+  return true;
+}
+
+// The cubic in t in [0, 1] that interpolates values p0, p1 and slopes d0, d1
+// (per unit length) at the ends of an interval of width h (cubic Hermite),
+// in powers of t: c0 + c1 t + c2 t^2 + c3 t^3.
+void hermite_power(double p0, double d0, double p1, double d1, double h, double c[4]) {
+  c[0] = p0;
+  c[1] = h * d0;
+  c[2] = 3.0 * (p1 - p0) - h * (2.0 * d0 + d1);
+  c[3] = 2.0 * (p0 - p1) + h * (d0 + d1);
+}
+
 }  // namespace
 
 struct mg_graph {
@@ -296,40 +342,58 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
     poly = true;
     if (std::isinf(d->length[e]))
       return fail(MG_EINVAL, "edge %d: higher coefficients need a finite edge", e);
-    // sigma_e(x) > 0 on [0, L]: its minimum is at an end or at a real root
-    // of sigma' = s1 + 2 s2 x + 3 s3 x^2, found with the cancellation-free
-    // quadratic formula (q = -(b + sgn(b) sqrt(b^2 - 4ac)) / 2, roots q/a
-    // and c/q) and refined by one Newton step; sigma is evaluated there in
-    // FP64 (a minimum within rounding of zero may pass either way)
-    const double L = d->length[e], s0 = d->sigma[e], s1 = hi[2], s2 = hi[3], s3 = hi[4];
-    auto sig = [&](double x) { return ((s3 * x + s2) * x + s1) * x + s0; };
-    auto dsig = [&](double x) { return (3.0 * s3 * x + 2.0 * s2) * x + s1; };
-    auto newton = [&](double x) {
-      const double dd = 6.0 * s3 * x + 2.0 * s2;
-      return dd != 0.0 ? x - dsig(x) / dd : x;
-    };
-    double crit[4] = {0.0, L, 0.0, 0.0};
-    int nc = 2;
-    const double qa = 3.0 * s3, qb = 2.0 * s2, qc = s1;
-    if (qa != 0.0) {
-      const double disc = qb * qb - 4.0 * qa * qc;
-      if (disc >= 0.0) {
-        const double q = -0.5 * (qb + std::copysign(std::sqrt(disc), qb));
-        if (q != 0.0) {
-          crit[nc++] = newton(q / qa);
-          crit[nc++] = newton(qc / q);
-        } else {
-          crit[nc++] = 0.0;  // b = c = 0: a double root at 0
+    // sigma_e(x) > 0 on [0, L]
+    if (!cubic_positive(d->sigma[e], hi[2], hi[3], hi[4], d->length[e]))
+      return fail(MG_EINVAL, "edge %d: sigma(x) must be > 0 on [0, L]", e);
+  }
+  // tabulated coefficients: knot counts, finite values, finite edges, no
+  // cubic terms beside a table, and sigma > 0 on every interval
+  std::vector<TabRec64> tab64;
+  std::vector<TabRec32> tab32;
+  std::vector<int32_t> tab0(E, 0), tab_k(E, 0);
+  if (d->table_offsets) {
+    const int32_t *to = d->table_offsets;
+    if (to[0] != 0) return fail(MG_EINVAL, "table_offsets[0] must be 0");
+    if (!d->table_mu || !d->table_dmu || !d->table_sigma || !d->table_dsigma)
+      return fail(MG_EINVAL, "table_offsets needs table_mu, table_dmu, table_sigma and "
+                  "table_dsigma");
+    for (int32_t e = 0; e < E; ++e) {
+      const int32_t n = to[e + 1] - to[e];
+      if (n < 0) return fail(MG_EINVAL, "table_offsets decreases at edge %d", e);
+      if (n == 0) continue;
+      if (n < 2) return fail(MG_EINVAL, "edge %d: a table needs at least 2 knots", e);
+      if (std::isinf(d->length[e]))
+        return fail(MG_EINVAL, "edge %d: a table needs a finite edge", e);
+      for (const double *hp : {d->drift_c2, d->drift_c3, d->sigma_c1, d->sigma_c2, d->sigma_c3})
+        if (higher(hp, e) != 0.0)
+          return fail(MG_EINVAL, "edge %d: a table replaces the cubic terms, which must be 0", e);
+      const int32_t K = n - 1;
+      const double h = d->length[e] / K;
+      tab0[e] = (int32_t)tab64.size();
+      tab_k[e] = K;
+      for (int32_t j = to[e]; j < to[e + 1]; ++j)
+        if (!is_finite(d->table_mu[j]) || !is_finite(d->table_dmu[j]) ||
+            !is_finite(d->table_sigma[j]) || !is_finite(d->table_dsigma[j]))
+          return fail(MG_EINVAL, "edge %d: table values must be finite", e);
+      for (int32_t j = 0; j < K; ++j) {
+        const int32_t k = to[e] + j;
+        TabRec64 r{};
+        hermite_power(d->table_mu[k], d->table_dmu[k], d->table_mu[k + 1],
+                      d->table_dmu[k + 1], h, r.mu);
+        hermite_power(d->table_sigma[k], d->table_dsigma[k], d->table_sigma[k + 1],
+                      d->table_dsigma[k + 1], h, r.sg);
+        if (!cubic_positive(r.sg[0], r.sg[1], r.sg[2], r.sg[3], 1.0))
+          return fail(MG_EINVAL, "edge %d: the tabulated sigma(x) must be > 0 on [0, L]", e);
+        TabRec32 r32{};
+        for (int i = 0; i < 4; ++i) {
+          r32.mu[i] = (float)r.mu[i];
+          r32.sg[i] = (float)r.sg[i];
         }
+        tab64.push_back(r);
+        tab32.push_back(r32);
       }
-    } else if (qb != 0.0) {
-      crit[nc++] = -qc / qb;
     }
-    for (int i = 0; i < nc; ++i) {
-      const double x = crit[i];
-      if (x >= 0.0 && x <= L && !(sig(x) > 0.0))
-        return fail(MG_EINVAL, "edge %d: sigma(x) must be > 0 on [0, L]", e);
-    }
+    poly = poly || !tab64.empty();
   }
   // every edge exactly once at each end with the right orientation
   std::vector<uint8_t> seen((size_t)E * 2, 0);
@@ -405,7 +469,8 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
     e64[e] = {d->length[e], a, c, d->sigma[e], vi, vt,
               d->bin_span ? d->bin_span[e] : d->length[e],
               higher(d->drift_c2, e), higher(d->drift_c3, e), higher(d->sigma_c1, e),
-              higher(d->sigma_c2, e), higher(d->sigma_c3, e), 0.0};
+              higher(d->sigma_c2, e), higher(d->sigma_c3, e),
+              tab_k[e] ? tab_k[e] / d->length[e] : 0.0, tab0[e], tab_k[e]};
     // (a particle never measures from the far end of a semi-infinite edge)
     const double aL = std::isinf(d->length[e]) ? 0.0 : std::fma(c, d->length[e], a);
     const float scale = (float)(std::isinf(d->length[e]) ? d->bin_span[e] : d->length[e]);
@@ -454,7 +519,7 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   // Wentzell table: per such vertex, beta = sum_e b_ve, kappa = a_v / beta,
   // gamma = c_v / beta and sigma_v = sum_e (b_ve / beta) sigma_e(v) over
   // its slots in order, sigma_e(v) the cubic by Horner's rule at the edge's
-  // end (x = 0 or L)
+  // end (x = 0 or L), or on a tabulated edge the table's value at that end
   std::vector<WzRec> wzt;
   for (int32_t v = 0; v < V; ++v) {
     if (!(d->vtx_kind && d->vtx_kind[v] == MG_VTX_WENTZELL)) continue;
@@ -463,9 +528,12 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
     for (int32_t s = off[v]; s < off[v + 1]; ++s) {
       const int32_t e = d->slot_edge[s];
       const double at = d->slot_orient[s] ? d->length[e] : 0.0;
-      const double sv = std::fma(std::fma(std::fma(higher(d->sigma_c3, e), at,
-                                                   higher(d->sigma_c2, e)), at,
-                                          higher(d->sigma_c1, e)), at, d->sigma[e]);
+      const double sv =
+          tab_k[e] ? d->table_sigma[d->slot_orient[s] ? d->table_offsets[e + 1] - 1
+                                                       : d->table_offsets[e]]
+                   : std::fma(std::fma(std::fma(higher(d->sigma_c3, e), at,
+                                                higher(d->sigma_c2, e)), at,
+                                       higher(d->sigma_c1, e)), at, d->sigma[e]);
       sig += (d->slot_jump_prob[s] / beta) * sv;
     }
     WzRec r{};
@@ -513,7 +581,9 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   const size_t o_64 = align_up(o_32 + sizeof(EdgeRec32) * E, 16);
   const size_t o_lt = align_up(o_64 + sizeof(EdgeRec64) * E, 256);
   const size_t o_wz = align_up(o_lt + 8 * (size_t)E, 256);
-  const size_t total = align_up(o_wz + sizeof(WzRec) * wzt.size(), 256);
+  const size_t o_t64 = align_up(o_wz + sizeof(WzRec) * wzt.size(), 256);
+  const size_t o_t32 = align_up(o_t64 + sizeof(TabRec64) * tab64.size(), 256);
+  const size_t total = align_up(o_t32 + sizeof(TabRec32) * tab32.size(), 256);
   hipError_t he = hipMalloc(&g->dev, total);
   if (he != hipSuccess) {
     delete g;
@@ -528,6 +598,10 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   std::memcpy(host.data() + o_64, e64.data(), sizeof(EdgeRec64) * E);
   std::memcpy(host.data() + o_lt, lthr.data(), 8 * (size_t)E);
   if (!wzt.empty()) std::memcpy(host.data() + o_wz, wzt.data(), sizeof(WzRec) * wzt.size());
+  if (!tab64.empty()) {
+    std::memcpy(host.data() + o_t64, tab64.data(), sizeof(TabRec64) * tab64.size());
+    std::memcpy(host.data() + o_t32, tab32.data(), sizeof(TabRec32) * tab32.size());
+  }
   he = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
   if (he != hipSuccess) {
     (void)hipFree(g->dev);
@@ -542,6 +616,8 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   g->gd.e64 = (const EdgeRec64 *)(base + o_64);
   g->gd.len_thr = (const uint64_t *)(base + o_lt);
   g->gd.wz = wzt.empty() ? nullptr : (const WzRec *)(base + o_wz);
+  g->gd.tab64 = tab64.empty() ? nullptr : (const TabRec64 *)(base + o_t64);
+  g->gd.tab32 = tab32.empty() ? nullptr : (const TabRec32 *)(base + o_t32);
   g->gd.n_guide = (int32_t)ng;
   g->gd.o_vtx = (int32_t)o_vtx;
   g->gd.o_slots = (int32_t)o_sl;

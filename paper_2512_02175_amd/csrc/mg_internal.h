@@ -35,7 +35,22 @@ struct alignas(16) EdgeRec64 {
   // higher terms: drift + c2 x^2 + c3 x^3, diffusion + s1 x + s2 x^2 + s3 x^3
   // (all zero for affine drift and constant diffusion, which then evaluate
   // to exactly the affine values)
-  double c2, c3, s1, s2, s3, pad;
+  double c2, c3, s1, s2, s3;
+  // tabulated coefficients: tab_k > 0 intervals of width L / tab_k, the
+  // first at row tab0 of the graph's table records; inv_h = tab_k / L
+  double inv_h;
+  int32_t tab0, tab_k;
+};
+
+// One interval of a tabulated edge: drift and diffusion as cubics in the
+// interval's local coordinate t in [0, 1] (c0 + c1 t + c2 t^2 + c3 t^3),
+// the cubic Hermite interpolants of the knot values and slopes, written in
+// powers of t on the host.
+struct alignas(16) TabRec64 {
+  double mu[4], sg[4];
+};
+struct alignas(16) TabRec32 {
+  float mu[4], sg[4];
 };
 
 // Edge record for the FP32 path: 32 bytes.  aL = a + c L is the drift at
@@ -112,6 +127,8 @@ struct GraphDev {
   // run their GEN instantiation
   int32_t gen;
   const WzRec *wz;        // Wentzell table (rows named by VtxBlk::wz), or null
+  const TabRec64 *tab64;  // tabulated-coefficient intervals, or null
+  const TabRec32 *tab32;
 };
 
 // Counters of one particle set: exit[nnz], absorbed[V], totals[4]

@@ -266,10 +266,12 @@ struct GView {
   const EdgeRec64 *hi64;  // global FP64 records: the FP32 path reads the
                           // higher coefficient terms from them
   const WzRec *wz;        // global Wentzell table
+  const TabRec64 *tab64;  // global tabulated-coefficient intervals
+  const TabRec32 *tab32;
 };
 
 __device__ __forceinline__ GView global_view(const GraphDev &G) {
-  return {G.vtx, G.slots, G.guide, G.e32, G.e64, G.e64, G.wz};
+  return {G.vtx, G.slots, G.guide, G.e32, G.e64, G.e64, G.wz, G.tab64, G.tab32};
 }
 
 struct SlotPick {
@@ -520,12 +522,31 @@ struct Particle64 {
   // Drift and diffusion at x: affine and constant, or with GEN the cubics
   // by Horner's rule (with zero higher terms these equal the affine values
   // exactly).
+  // A tabulated edge (GEN): its interval at x (the last one at x = L) and
+  // the local coordinate t = x K / L - j.
+  __device__ __forceinline__ const TabRec64 &interval(double at, double &t) const {
+    const double s = at * R.inv_h;
+    double j = floor(s);
+    j = j < 0.0 ? 0.0 : (j > (double)(R.tab_k - 1) ? (double)(R.tab_k - 1) : j);
+    t = s - j;
+    return G.tab64[R.tab0 + (int32_t)j];
+  }
   __device__ __forceinline__ double drift(double at) const {
     if (!GEN) return fma(R.c, at, R.a);
+    if (R.tab_k) {
+      double t;
+      const TabRec64 &T = interval(at, t);
+      return fma(fma(fma(T.mu[3], t, T.mu[2]), t, T.mu[1]), t, T.mu[0]);
+    }
     return fma(fma(fma(R.c3, at, R.c2), at, R.c), at, R.a);
   }
   __device__ __forceinline__ double diffusion(double at) const {
     if (!GEN) return R.sigma;
+    if (R.tab_k) {
+      double t;
+      const TabRec64 &T = interval(at, t);
+      return fma(fma(fma(T.sg[3], t, T.sg[2]), t, T.sg[1]), t, T.sg[0]);
+    }
     return fma(fma(fma(R.s3, at, R.s2), at, R.s1), at, R.sigma);
   }
 
@@ -798,6 +819,10 @@ struct Particle32 {
   // Higher terms of the current edge (GEN), x from the initial vertex:
   // drift + c2 x^2 + c3 x^3, diffusion + s1 x + s2 x^2 + s3 x^3.
   float c2 = 0.0f, c3 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+  // A tabulated edge (GEN): intervals per unit length and the first
+  // interval's row (tab_k = 0: no table).
+  float inv_h = 0.0f;
+  int32_t tab0 = 0, tab_k = 0;
 
   // Sets as, g0 and the first sub-step constants for the current edge R and
   // side (after an edge load or a change of reference end).
@@ -814,7 +839,20 @@ struct Particle32 {
       s1 = (float)P.s1;
       s2 = (float)P.s2;
       s3 = (float)P.s3;
+      inv_h = (float)P.inv_h;
+      tab0 = P.tab0;
+      tab_k = P.tab_k;
     }
+  }
+
+  // A tabulated edge's interval at x from the initial vertex (the last one
+  // at x = L) and the local coordinate t.
+  __device__ __forceinline__ const TabRec32 &interval(float x, float &t) const {
+    const float s = x * inv_h;
+    float j = floorf(s);
+    j = j < 0.0f ? 0.0f : (j > (float)(tab_k - 1) ? (float)(tab_k - 1) : j);
+    t = s - j;
+    return G.tab32[tab0 + (int32_t)j];
   }
 
   // Drift in the frame (sign of the reference end) and diffusion at
@@ -824,7 +862,14 @@ struct Particle32 {
       return fmaf(R.c, yy, as);
     } else {
       const float x = side ? R.L - yy : yy;
-      const float m = fmaf(fmaf(fmaf(c3, x, c2), x, R.c), x, R.a);
+      float m;
+      if (tab_k) {
+        float t;
+        const TabRec32 &T = interval(x, t);
+        m = fmaf(fmaf(fmaf(T.mu[3], t, T.mu[2]), t, T.mu[1]), t, T.mu[0]);
+      } else {
+        m = fmaf(fmaf(fmaf(c3, x, c2), x, R.c), x, R.a);
+      }
       return side ? -m : m;
     }
   }
@@ -833,6 +878,11 @@ struct Particle32 {
       return R.sigma;
     } else {
       const float x = side ? R.L - yy : yy;
+      if (tab_k) {
+        float t;
+        const TabRec32 &T = interval(x, t);
+        return fmaf(fmaf(fmaf(T.sg[3], t, T.sg[2]), t, T.sg[1]), t, T.sg[0]);
+      }
       return fmaf(fmaf(fmaf(s3, x, s2), x, s1), x, R.sigma);
     }
   }
@@ -1224,6 +1274,8 @@ __device__ __forceinline__ GView block_view(const GraphDev &G, char *smem) {
   v.e64 = (const EdgeRec64 *)(smem + head);
   v.hi64 = G.e64;
   v.wz = G.wz;
+  v.tab64 = G.tab64;
+  v.tab32 = G.tab32;
   return v;
 }
 

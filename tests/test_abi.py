@@ -132,6 +132,25 @@ def _wentzell(a, c, b, kind=3):
     return g
 
 
+def _table(knots, sig=lambda x: 1.0 + 0.0 * x, dsig=lambda x: 0.0 * x, length=1.0,
+           cubic=False):
+    """Segment with a drift and diffusion table of knots + 1 entries."""
+    g = workloads.segment(1.0, 0.0, 0.0, 1.0)
+    if knots >= 1:
+        workloads.tabulate(g, knots, lambda e, x: -x, lambda e, x: -1.0 + 0 * x,
+                           lambda e, x: sig(x), lambda e, x: dsig(x))
+    else:
+        g.table_offsets = np.array([0, 1])
+        g.table_mu = g.table_dmu = g.table_dsigma = np.zeros(1)
+        g.table_sigma = np.ones(1)
+    if not np.isfinite(length):
+        g.length[:] = length
+        g.bin_span = np.array([2.0])
+    if cubic:
+        g.drift_c2 = np.array([0.5])
+    return g
+
+
 @pytest.mark.parametrize("make,msg", [
     # a mirror vertex must be a leaf (the centre of a star has three slots)
     (lambda: workloads.from_edges(4, [0, 0, 0], [1, 2, 3], 1.0, vtx_kind=[2, 0, 0, 0]),
@@ -153,6 +172,14 @@ def _wentzell(a, c, b, kind=3):
     (lambda: _wentzell(0.0, np.nan, 1.0), ">= 0"),
     (lambda: _wentzell(0.5, 0.5, 0.0), "no positive jump probability"),
     (lambda: _wentzell(0.2, 0.1, 0.7, kind=4), "unknown kind"),
+    # tabulated coefficients: at least 2 knots, a positive sigma on the
+    # whole edge (1 - 2 sin(pi x) dips below 0 between knots 0 and 1 here),
+    # finite edges, no cubic terms beside a table
+    (lambda: _table(0), "at least 2 knots"),
+    (lambda: _table(4, sig=lambda x: 1.0 - 1.2 * np.sin(np.pi * x),
+                    dsig=lambda x: -1.2 * np.pi * np.cos(np.pi * x)), "sigma(x)"),
+    (lambda: _table(4, length=np.inf), "finite edge"),
+    (lambda: _table(4, cubic=True), "replaces the cubic terms"),
 ])
 def test_method_variant_graphs_checked(B, make, msg):
     """Mirror vertices, cubic coefficients and Wentzell vertices are validated
