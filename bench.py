@@ -104,12 +104,12 @@ def exit_err(ex_a, ex_b, offsets, min_exits=MIN_EXITS):
     return worst, (num / den if den else 0.0)
 
 
-def run_pass(B, G, g, run, prec, dt, torch, kernel_times, schedules=None):
+def run_pass(B, G, g, run, prec, dt, torch, kernel_times, schedules=None, schedule=0):
     """One pass of the path at one dt: init, schedule tuning (FP32), simulate,
     exit counts, histogram.  kernel_times gets the HIP-event time of the
     step launches alone."""
     p = B.mg_particles_init(G, run["n_particles"], B.MG_INIT_UNIFORM_LENGTH, init_seed=0,
-                            precision=prec, max_splits=run["max_splits"])
+                            precision=prec, max_splits=run["max_splits"], schedule=schedule)
     if prec == B.MG_FP32:
         t = B.mg_autotune(p, dt, run["seed"])
         if schedules is not None:
@@ -179,6 +179,61 @@ def cpu_baseline(g, run, n_sample: int, dt: float = 1e-3, repeats: int = 3,
                                         f"runs ({sub1} sub-steps in {el1:.2f} s)",
                               "runs": all_r1},
             "nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": _cpu_model()}
+
+
+def batch_leg(B, torch):
+    """The batched form on the default line: 512 independent uneven graphs
+    (stars and random recursive trees, 3..4096 edges, 1e4..1e6 particles
+    each, half with quadratic potentials), 1000 steps of dt 1e-3 in FP32,
+    one batched launch against one launch per graph; the batched kernel's
+    roofline fraction from its HIP-event time."""
+    import numpy as np
+    import workloads
+    graphs, counts, run = workloads.config4()
+    Gs = [B.mg_graph_create(g) for g in graphs]
+
+    def make():
+        return [B.mg_particles_init(G, c, B.MG_INIT_UNIFORM_LENGTH, init_seed=i, graph_tag=i,
+                                    precision=B.MG_FP32, max_splits=run["max_splits"])
+                for i, (G, c) in enumerate(zip(Gs, counts))]
+
+    def totals(sets):
+        t = np.zeros(4, np.uint64)
+        for q in sets:
+            t += B.mg_exit_counts(q)[2]
+        return t
+    sets = make()
+    batch = B.mg_batch_create(sets)
+    B.mg_batch_simulate(batch, 8, run["dt"], run["seed"])  # builds the launch graph
+    torch.cuda.synchronize()
+    t_before = totals(sets)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    B.mg_batch_simulate(batch, run["n_steps"], run["dt"], run["seed"])
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k = e0.elapsed_time(e1) * 1e-3
+    tot = totals(sets) - t_before
+    solo = make()
+    for q in solo:
+        B.mg_simulate(q, 8, run["dt"], run["seed"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for q in solo:
+        B.mg_simulate(q, run["n_steps"], run["dt"], run["seed"])
+    torch.cuda.synchronize()
+    wall_solo = time.perf_counter() - t1
+    return {"workload": "batch512: 512 stars/random trees, 3..4096 edges, 1e4..1e6 particles "
+                        "each, zero drift or quadratic potentials, dt=1e-3, 1000 steps, FP32, "
+                        "one batched launch",
+            "n_particles": int(sum(counts)), "value": float(tot[1]) / wall,
+            "kernel_substeps_per_s": float(tot[1]) / k,
+            "unbatched_value": float(tot[1]) / wall_solo, "batch_speedup": wall_solo / wall,
+            "roofline_frac": alg_work(1, int(tot[3]), int(tot[2])) / k / PEAK_LANE_OPS,
+            "hits_per_step": float(tot[2]) / float(tot[3])}
 
 
 def at_scale(B, torch):
@@ -685,6 +740,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
     ap.add_argument("--no-1e8", action="store_true",
                     help="skip the 1e8-particle accuracy leg of the default workload")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 512-graph batch leg of the default workload")
     ap.add_argument("--cpu-sample", type=int, default=40_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB on the device (scale for HBM counters)")
@@ -742,8 +799,8 @@ def main():
 
     scheds = []
 
-    def step(prec, ktimes):
-        return [run_pass(B, G, g, run, prec, dt, torch, ktimes, scheds) for dt in dts]
+    def step(prec, ktimes, schedule=0):
+        return [run_pass(B, G, g, run, prec, dt, torch, ktimes, scheds, schedule) for dt in dts]
 
     # FP32: the headline path
     for _ in range(args.warmup):
@@ -775,10 +832,25 @@ def main():
                   for a, b in zip(res32, res64)]
         k64 = sum(ktimes64)
         w64 = sum(alg_work(0, r["steps"], r["hits"]) for r in res64)
+        # the plain FP64 kernel (one particle per lane, unbatched) beside it
+        kt_plain = []
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res_plain = step(0, kt_plain, B.MG_SCHED_LANES)
+        torch.cuda.synchronize()
+        wall_plain = time.perf_counter() - t2
+        sub_plain = sum(r["substeps"] for r in res_plain)
         out_fp64 = {"value": sub64 / wall64, "unit": "particle-substeps/s",
+                    "kernel": "k_pool64 (128 per wave, 8-step windows)",
                     "kernel_substeps_per_s": sub64 / k64,
                     "alg_frac_of_alu_peak": w64 / k64 / PEAK_LANE_OPS,
-                    "fp32_speedup": value / (sub64 / wall64)}
+                    "fp32_speedup": value / (sub64 / wall64),
+                    "plain_lane_kernel": {
+                        "kernel": "k_step<fp64> (one particle per lane)",
+                        "value": sub_plain / wall_plain,
+                        "kernel_substeps_per_s": sub_plain / sum(kt_plain),
+                        "fp32_speedup": value / (sub_plain / wall_plain),
+                        "fp64_pools_speedup": (sub64 / wall64) / (sub_plain / wall_plain)}}
 
     # roofline of the dominant kernel (the fused step kernel), per launch
     k32 = float(np.mean(ktimes32))
@@ -814,6 +886,8 @@ def main():
     }
     if not args.no_1e8:
         line["at_1e8"] = at_scale(B, torch)
+    if not args.no_batch:
+        line["batch512"] = batch_leg(B, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, run, args.cpu_sample)
     print(json.dumps(line), flush=True)
