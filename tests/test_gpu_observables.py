@@ -149,28 +149,36 @@ def test_density_l2_matches_oracle(B, orc):
     assert out.value == pytest.approx(orc.density_l2(g.length, bins, c, ref), rel=1e-12)
 
 
-def test_paper_star_density_error_falls_with_dt(B):
+def test_paper_star_density_error_falls_with_dt(B, orc):
     """The paper's accuracy experiment (Sec. 4.1, Fig. "error") on its
     5-edge star with the linear potential: the time-averaged FP32 histogram
-    after burn-in against the closed-form stationary density; the L2 error
-    at dt = 1e-4 is less than half the one at dt = 1e-3 (the scheme's bias
-    falls like dt^(1/2): a factor 3.2 over a decade) and both are far below
-    the error of a flat density."""
+    of 1e6 particles after burn-in against the closed-form stationary
+    density.  The error is mostly the scheme's bias next to the vertex,
+    which the oracle reproduces: on the first 1e5 of the same particles
+    (same random numbers) its error is within 0.03 of the GPU's at each dt
+    (the Monte-Carlo part of either is below 0.02 at these counts), and the
+    error at dt = 1e-4 is less than half the one at dt = 1e-3 (the bias falls
+    like dt^(1/2): a factor 3.2 over a decade)."""
     g = workloads.paper_star5("linear")
     G = B.mg_graph_create(g)
     bins = 100
     ref = stationary.star_bin_means(g, bins)
-    errs = {}
+    errs, errs_orc = {}, {}
     for dt in (1e-3, 1e-4):
+        burn, every, steps = int(round(0.5 / dt)), max(1, int(round(0.01 / dt))), int(round(1.0 / dt))
         p = B.mg_particles_init(G, 1_000_000, 1, vertex=0, init_seed=1, precision=B.MG_FP32)
-        burn = int(round(0.5 / dt))
         B.mg_simulate(p, burn, dt, 1)
-        B.mg_observe_histogram(p, bins, max(1, int(round(0.01 / dt))))
-        B.mg_simulate(p, int(round(1.0 / dt)), dt, 2)
+        B.mg_observe_histogram(p, bins, every)
+        B.mg_simulate(p, steps, dt, 2)
         h, ns = B.mg_observed_histogram(p)
         errs[dt] = B.mg_density_l2(G, bins, h, ref)
-    flat = B.mg_density_l2(G, bins, np.ones((5, bins), np.uint64), ref)
-    assert errs[1e-4] < 0.5 * errs[1e-3] and errs[1e-3] < 0.4 * flat, (errs, flat)
+        st = orc.init(g, 100_000, orc.INIT_AT_VERTEX, vertex=0, seed=1)
+        orc.simulate(g, st, 0, burn, dt, 1)
+        acc, snaps, _ = orc.observed_histogram(g, st, burn, steps, dt, 2, every, bins)
+        assert snaps == ns
+        errs_orc[dt] = orc.density_l2(g.bin_span, bins, acc, ref)
+        assert abs(errs[dt] - errs_orc[dt]) <= 0.03, (dt, errs, errs_orc)
+    assert errs[1e-4] < 0.5 * errs[1e-3], errs
 
 
 def test_histogram_csr_parity_and_errors(B, orc):
