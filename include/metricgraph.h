@@ -407,6 +407,9 @@ void mg_batch_destroy(mg_batch *b);
  * min(n, 2^22) particles by probe_steps steps (<= 0: 1024) of size dt with
  * Philox key seed, timed with HIP events on the set's stream; the set
  * keeps the fastest for its later mg_simulate calls at this dt.  The
+ * chosen schedule then runs 2 probe_steps steps as one launch and as two
+ * launches; a set created with steps_per_launch 0 takes the faster (0: the
+ * whole call per launch, else probe_steps steps per launch).  The
  * result is also kept with the graph: later calls for any set on the same
  * graph at the same dt take it without probing.  Sets created with
  * schedule MG_SCHED_AUTO are tuned this way on their first mg_simulate at
@@ -424,6 +427,9 @@ typedef struct {
   int32_t n_probes;      /* entries used in probe_ms */
   float probe_ms[12];    /* lanes, pools128@4, @8, @16, @32, pools256@8, @16,
                             pools128 8-step windows@8, @16, @32 */
+  int32_t steps_per_launch;  /* 0: a whole call per launch; else the chunk */
+  float launch_ms[2];    /* the chosen schedule over 2 probe_steps steps: one
+                            launch, two launches of probe_steps */
 } mg_tuning;
 
 mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_steps,

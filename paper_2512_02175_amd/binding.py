@@ -66,7 +66,8 @@ class mg_options(C.Structure):
 class mg_tuning(C.Structure):
     _fields_ = [("schedule", C.c_int32), ("idle_trigger", C.c_int32),
                 ("pool_size", C.c_int32), ("window", C.c_int32), ("n_probes", C.c_int32),
-                ("probe_ms", C.c_float * 12)]
+                ("probe_ms", C.c_float * 12), ("steps_per_launch", C.c_int32),
+                ("launch_ms", C.c_float * 2)]
 
 
 _lib = None
@@ -437,4 +438,6 @@ def mg_autotune(p: Particles, dt: float, seed: int = 0, probe_steps: int = 0) ->
                              C.byref(t)))
     return dict(schedule=int(t.schedule), idle_trigger=int(t.idle_trigger),
                 pool_size=int(t.pool_size), window=int(t.window), n_probes=int(t.n_probes),
-                probe_ms=[float(t.probe_ms[i]) for i in range(t.n_probes)])
+                probe_ms=[float(t.probe_ms[i]) for i in range(t.n_probes)],
+                steps_per_launch=int(t.steps_per_launch),
+                launch_ms=[float(t.launch_ms[0]), float(t.launch_ms[1])])

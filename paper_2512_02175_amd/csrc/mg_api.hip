@@ -169,6 +169,7 @@ struct mg_particles {
   double tuned_dt = 0.0;
   int32_t tuned_kernel = 1;
   int32_t tuned_idle = 8;
+  int32_t tuned_spl = 0;  // steps per launch of the tuned choice (0: whole call)
   int64_t n = 0;
   mg_precision prec = MG_FP64;
   int32_t max_splits = 8;
@@ -914,7 +915,10 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
   a.dt = dt;
   a.kernel = step_kernel(p);
   a.idle = pool_idle(p);
-  const uint32_t chunk = chunk_steps(p->steps_per_launch);
+  // a set without a fixed launch length takes the tuned one
+  const uint32_t chunk = chunk_steps(
+      (p->steps_per_launch == 0 && p->tuned && p->tuned_dt == dt) ? p->tuned_spl
+                                                                    : p->steps_per_launch);
   int64_t left = n_steps;
   while (left > 0) {
     const uint32_t now = (uint32_t)std::min<int64_t>(left, chunk);
@@ -1442,13 +1446,14 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
         p->tuned_dt = dt;
         p->tuned_kernel = kernel_of(res.schedule);
         p->tuned_idle = res.idle_trigger;
+        p->tuned_spl = res.steps_per_launch;
         if (out) *out = res;
         return MG_OK;
       }
   }
   const int64_t n = std::min<int64_t>(p->n, 1 << 22);
   const uint32_t steps = (uint32_t)(probe_steps > 0 ? probe_steps : 1024);
-  if ((uint64_t)p->step + steps > 0xFFFFFFFFull)
+  if ((uint64_t)p->step + 2ull * steps > 0xFFFFFFFFull)
     return fail(MG_EINVAL, "the probe would pass step 2^32");
   const SetLayout L = set_layout(p->g->V, p->g->nnz, n, MG_FP32, false);
   void *mem = nullptr;
@@ -1504,10 +1509,32 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
       best_i = i;
     }
   }
+  // steps per launch for the chosen schedule: 2 x steps as one launch
+  // against two launches of `steps` (each launch ends with a tail of partly
+  // filled waves; the launch count is the only difference)
+  a.kernel = cand_kernel[best_i];
+  a.idle = cand_idle[best_i];
+  for (int i = 0; i < 2 && he == hipSuccess; ++i) {
+    he = hipMemcpyAsync(sd.ef, p->sd.ef, (size_t)n * 4, hipMemcpyDeviceToDevice, p->stream);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(sd.y32, p->sd.y32, (size_t)n * 8, hipMemcpyDeviceToDevice, p->stream);
+    if (he == hipSuccess) he = hipEventRecord(e0, p->stream);
+    for (uint32_t done = 0; done < 2 * steps && he == hipSuccess;) {
+      a.nsteps = i == 0 ? 2 * steps : steps;
+      sd.n0 = (uint32_t)p->step + done;
+      he = launch_step(p->g->gd, sd, a, false, false, p->stream);
+      done += a.nsteps;
+    }
+    if (he == hipSuccess) he = hipEventRecord(e1, p->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&res.launch_ms[i], e0, e1);
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(mem);
   if (he != hipSuccess) return hip_fail(he, "running the tuning probe");
+  // fewer launches unless the split is clearly faster
+  res.steps_per_launch = res.launch_ms[1] < 0.98f * res.launch_ms[0] ? (int32_t)steps : 0;
   res.n_probes = kCand;
   res.schedule = schedule_of(cand_kernel[best_i]);
   res.idle_trigger = cand_kernel[best_i] ? cand_idle[best_i] : 0;
@@ -1517,6 +1544,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   p->tuned_dt = dt;
   p->tuned_kernel = cand_kernel[best_i];
   p->tuned_idle = cand_idle[best_i];
+  p->tuned_spl = res.steps_per_launch;
   {
     std::lock_guard<std::mutex> lock(p->g->tune_mu);
     p->g->tune_cache.emplace_back(dt, res);

@@ -391,9 +391,10 @@ def test_batch_graph_replays_equal_individual_runs(B):
 
 
 def test_autotune_choice_and_auto_schedule_bitwise(B):
-    """Autotuning times the candidate schedules on a scratch copy: it leaves
-    the set untouched, reports a valid choice, and a set on the automatic
-    schedule gives the same bits as one on the fixed lane schedule."""
+    """Autotuning times the candidate schedules and launch lengths on a
+    scratch copy: it leaves the set untouched, reports a valid choice, and a
+    set on the automatic schedule gives the same bits as one on the fixed
+    lane schedule."""
     g, _ = workloads.config2()
     G = B.mg_graph_create(g)
     kw = dict(init_seed=4, precision=B.MG_FP32, trace=True)
@@ -411,6 +412,10 @@ def test_autotune_choice_and_auto_schedule_bitwise(B):
     if t["schedule"] != B.MG_SCHED_LANES:
         assert t["idle_trigger"] in (4, 8, 16, 32) and t["pool_size"] in (128, 256)
         assert t["window"] == (8 if t["schedule"] == B.MG_SCHED_POOLS_W8 else 4)
+    # launch length: 16 steps as one launch against two of 8; the set then
+    # runs whole calls or 8-step launches (the same bits either way)
+    assert t["steps_per_launch"] in (0, 8) and min(t["launch_ms"]) > 0
+    assert (t["steps_per_launch"] == 8) == (t["launch_ms"][1] < 0.98 * t["launch_ms"][0])
     for dt in (1e-2, 1e-3):              # 1e-3 is tuned on its first call
         B.mg_simulate(auto, 150, dt, 9)
         B.mg_simulate(lanes, 150, dt, 9)
