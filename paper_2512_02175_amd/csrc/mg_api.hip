@@ -77,15 +77,22 @@ void slot_thresholds(int32_t V, const int32_t *off, const double *b,
 bool is_finite(double v) { return std::isfinite(v); }
 
 // Iterations of a wave-pool loop between moves of the 32-bit lane tallies
-// and LDS counters into 64-bit ones: 1024, or MG_POOL_DRAIN (1 .. 1024)
-// from the environment, read at each launch.  Tests lower it to run the
-// moves often; the results are the same at any value.
-uint32_t pool_drain() {
+// into 64-bit block totals (1024) and of the block's u32 LDS counters into
+// the set's 64-bit ones (2^20; each such move is a round of device-scope
+// atomics, which travel past the XCD's L2), or MG_POOL_DRAIN (1 .. 1024) for
+// both, from the environment, read at each launch.  Tests lower it to run
+// the moves often; the results are the same at any value.
+static uint32_t drain_env() {
   const char *v = std::getenv("MG_POOL_DRAIN");
-  if (!v || !*v) return kDrainMax;
+  if (!v || !*v) return 0;
   char *end = nullptr;
   const unsigned long long x = std::strtoull(v, &end, 10);
-  return (end && *end == 0 && x >= 1 && x <= kDrainMax) ? (uint32_t)x : kDrainMax;
+  return (end && *end == 0 && x >= 1 && x <= kDrainMax) ? (uint32_t)x : 0;
+}
+void set_drain(StepArgs &a) {
+  const uint32_t d = drain_env();
+  a.drain = d ? d : kDrainMax;
+  a.drain_lds = d ? d : kLdsDrainMax;
 }
 // an optional per-edge coefficient array: its entry, or 0 when absent
 double higher(const double *p, int32_t e) { return p ? p[e] : 0.0; }
@@ -211,7 +218,7 @@ struct mg_batch {
   uint64_t key_seed = 0;
   int32_t key_idle = -1;
   uint32_t key_chunk = 0;
-  uint32_t key_drain = 0;
+  uint32_t key_drain = 0, key_drain_lds = 0;
   bool key_obs = false;
 };
 
@@ -908,7 +915,7 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
     g_err.clear();
   }
   StepArgs a{};
-  a.drain = pool_drain();
+  set_drain(a);
   a.max_splits = p->max_splits;
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
@@ -1371,7 +1378,7 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
   mg_particles *p0 = b->sets[0];
   hipStream_t stream = p0->stream;
   StepArgs a{};
-  a.drain = pool_drain();
+  set_drain(a);
   a.max_splits = p0->max_splits;
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
@@ -1393,7 +1400,7 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
   for (mg_particles *p : b->sets) obs = obs || p->sd.obs != nullptr;
   if (!(b->exec && b->key_steps == n_steps && b->key_dt == dt && b->key_seed == seed &&
         b->key_idle == a.idle && b->key_chunk == chunk && b->key_obs == obs &&
-        b->key_drain == a.drain)) {
+        b->key_drain == a.drain && b->key_drain_lds == a.drain_lds)) {
     drop_graph(b);
     b->key_obs = obs;
     hipError_t he = build_graph(b, n_steps, a, chunk);
@@ -1407,6 +1414,7 @@ mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t se
     b->key_idle = a.idle;
     b->key_chunk = chunk;
     b->key_drain = a.drain;
+    b->key_drain_lds = a.drain_lds;
   }
   MG_HIP(hipGraphLaunch(b->exec, stream), "launching the batch graph");
   for (mg_particles *p : b->sets) p->step += (uint64_t)n_steps;
@@ -1471,7 +1479,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   sd.n0 = (uint32_t)p->step;
   sd.tag = p->tag;
   StepArgs a{};
-  a.drain = pool_drain();
+  set_drain(a);
   a.nsteps = steps;
   a.max_splits = p->max_splits;
   a.key0 = (uint32_t)seed;

@@ -168,8 +168,11 @@ struct StepArgs {
   int32_t obs_lds;     // streamed-histogram bins privatised in LDS (0: global)
   int32_t probe;       // autotuning probe: the same kernels under probe names
   uint32_t drain;      // wave pools: iterations between moves of the lanes'
-                       // u32 tallies and the block's u32 LDS counters into
-                       // 64-bit ones (1 .. 1024; tests lower it)
+                       // u32 tallies into the block's 64-bit totals
+                       // (1 .. 1024; tests lower it)
+  uint32_t drain_lds;  // and between moves of the block's u32 LDS exit and
+                       // snapshot counters into the set's 64-bit ones
+                       // (1 .. 2^20; tests lower it)
   uint32_t batch_items;   // batched wave pools: work items (set indices)
   uint32_t *batch_claim;  // and the counter their resident grid takes them from
 };
@@ -181,6 +184,7 @@ struct StepArgs {
 constexpr int64_t kMaxParticles = 0xFFFFFFFFll - 0xFFFFFll;  // 2^32 - 2^20
 constexpr uint32_t kMaxPersistBlocks = 2048;
 constexpr uint32_t kDrainMax = 1024;
+constexpr uint32_t kLdsDrainMax = 1u << 20;
 
 // Batched form: one work item per (set, tile of particles).  The wave-pool
 // kernel reads only the set (its waves claim the set's particles from the

@@ -1647,16 +1647,19 @@ __device__ __forceinline__ void drain_lds(uint32_t *lds, uint64_t *glob, int32_t
 
 // A lane of a pool serves any number of particles in a launch, and a
 // persistent block any number of particle-steps, so every wave drains its
-// lanes' 32-bit tallies and the block's u32 LDS exit and snapshot counters
-// into 64-bit ones every A.drain (at most kDrainMax = 1024) iterations of its
-// pool loop.  Bounds: one iteration finishes at most two particles on a
-// lane (its own, and the one of its split-pass slot), each adding at most
-// 2^20 steps (a launch's cap), plus at most one crossing, so 1024
-// iterations add at most 2^31 + 1024 to a tally.  Between two drains of an
-// LDS counter (by any wave), each of the block's four waves runs fewer than
-// A.drain iterations, each adding at most 64 exit records and 64 x 9
-// snapshots (one per step of a window of at most 8 steps, and one per
-// split-pass lane): below 2^22 per counter.
+// lanes' 32-bit tallies into the block's 64-bit totals every A.drain (at
+// most kDrainMax = 1024) iterations of its pool loop, and the block's u32
+// LDS exit and snapshot counters into the set's 64-bit ones every
+// A.drain_lds (at most kLdsDrainMax = 2^20).  Bounds: one iteration
+// finishes at most two particles on a lane (its own, and the one of its
+// split-pass slot), each adding at most 2^20 steps (a launch's cap), plus
+// at most one crossing, so 1024 iterations add at most 2^31 + 1024 to a
+// tally.  Between two drains of an LDS counter (by any wave), each of the
+// block's four waves runs fewer than A.drain_lds iterations, each adding at
+// most 64 exit records and 64 x 9 snapshots (one per step of a window of at
+// most 8 steps, and one per split-pass lane): below 4 x 2^20 x 576 < 2^32
+// per counter.  The LDS drains are rare because each is a round of
+// device-scope atomics on the set's counters, which go past the XCD's L2.
 
 // Where a wave's particles come from: the set's counter.  The grid stays
 // resident; every wave claims the next particle ids from the counter as its
@@ -1688,13 +1691,16 @@ __device__ void run_pool(const GView &G, int32_t n_edges, const SetDev &S,
   for (uint32_t i = lane; i < K; i += 64u) P.freeq[i] = (uint8_t)i;
   const uint32_t lim = S.n;
   bool exhausted = false;
-  uint32_t iter = 0;
+  uint32_t iter = 0, iter_lds = 0;
   wave_lds_fence();
 
   for (;;) {
     if (++iter >= A.drain) {
       iter = 0;
       drain_tally(t, s_tot);
+    }
+    if (++iter_lds >= A.drain_lds) {
+      iter_lds = 0;
       if (LDS) drain_lds(s_exit, S.exit_cnt, nnz);
       if (OBS && sink.lds) drain_lds(sink.lds, S.obs, A.obs_lds);
     }
