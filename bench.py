@@ -860,6 +860,11 @@ def main():
                         "fp64_pools_speedup": (sub64 / wall64) / (sub_plain / wall_plain)}}
 
     # roofline of the dominant kernel (the fused step kernel), per launch
+    # measured VALU issue rates beside the published peak
+    rates = {name: B.mg_valu_rate(op)[0] / 1e12 for name, op in (
+        ("v_fma_f32", B.MG_VALU_FMA_F32), ("v_fma_f64", B.MG_VALU_FMA_F64),
+        ("v_mad_u64_u32", B.MG_VALU_MAD_U64_U32), ("v_bitop3_b32", B.MG_VALU_BITOP3),
+        ("v_add_u32", B.MG_VALU_ADD_U32))}
     # (a call is one launch unless the tuner split it; the rate is per call)
     k32 = float(np.mean(ktimes32))
     per_call = [alg_work(1, r["steps"], r["hits"]) for r in res32]
@@ -870,7 +875,9 @@ def main():
             "traffic": None if mirror else kernel_traffic(),
             "kernel": "/".join(sorted(set(scheds))), "kernel_ms_per_launch": k32 / n_launch * 1e3,
             "alg_lane_ops_per_particle_step": ALG_FP32_STEP,
-            "alg_lane_ops_per_hit": ALG_FP32_HIT}
+            "alg_lane_ops_per_hit": ALG_FP32_HIT,
+            "measured_issue_rates": rates,
+            "frac_of_measured_v_fma_f32": achieved / 1e12 / rates["v_fma_f32"]}
 
     line = {
         "metric": METRIC, "value": value, "unit": "particle-substeps/s", "n_gpus": 1,

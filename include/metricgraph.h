@@ -435,6 +435,30 @@ typedef struct {
 mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_steps,
                       mg_tuning *out);
 
+/*
+ * Measurement aid, not part of the method: the issue rate of one VALU
+ * instruction kind on the calling thread's current GPU, for setting the
+ * step kernels' instruction counts against a measured ceiling.  Every SIMD
+ * runs waves_per_simd (1 .. 8) waves; each lane runs 8 independent chains
+ * of `op` for 128 x iters (1 .. 2^20) rounds.  One untimed launch, then one
+ * timed with HIP events on a stream of the call's own.  *lane_ops_per_s
+ * gets lanes x rounds x chains / seconds (one lane-op = one lane of one
+ * instruction), *kernel_ms (if not NULL) the timed launch.  Allocates a
+ * device buffer of 4 bytes per lane for the chains' results and frees it;
+ * synchronises.  MG_EINVAL for an unknown op or a count out of range,
+ * MG_EDEVICE for a HIP error.
+ */
+typedef enum {
+  MG_VALU_FMA_F32 = 0,      /* v_fma_f32 (not packed) */
+  MG_VALU_FMA_F64 = 1,      /* v_fma_f64 */
+  MG_VALU_MAD_U64_U32 = 2,  /* v_mad_u64_u32: 32 x 32 -> 64-bit multiply-add */
+  MG_VALU_BITOP3 = 3,       /* v_bitop3_b32: any bitwise function of 3 words */
+  MG_VALU_ADD_U32 = 4       /* v_add_u32 */
+} mg_valu_op;
+
+mg_status mg_valu_rate(int32_t op, int32_t waves_per_simd, uint32_t iters,
+                       double *lane_ops_per_s, float *kernel_ms);
+
 /* Description of the calling thread's last error ("" if none). */
 const char *mg_last_error(void);
 

@@ -21,6 +21,7 @@ MG_FP64, MG_FP32 = 0, 1
 MG_VTX_STANDARD, MG_VTX_ABSORBING, MG_VTX_MIRROR, MG_VTX_WENTZELL = 0, 1, 2, 3
 MG_INIT_EXPLICIT, MG_INIT_AT_VERTEX, MG_INIT_UNIFORM_LENGTH = 0, 1, 2
 MG_SCHED_AUTO, MG_SCHED_LANES, MG_SCHED_POOLS, MG_SCHED_POOLS256, MG_SCHED_POOLS_W8 = 0, 1, 2, 3, 4
+MG_VALU_FMA_F32, MG_VALU_FMA_F64, MG_VALU_MAD_U64_U32, MG_VALU_BITOP3, MG_VALU_ADD_U32 = range(5)
 
 EXPORTED = (
     "mg_graph_create", "mg_graph_destroy", "mg_particles_arena_bytes",
@@ -29,7 +30,7 @@ EXPORTED = (
     "mg_exit_counts", "mg_particles_read", "mg_particles_step", "mg_batch_create",
     "mg_batch_simulate", "mg_batch_destroy", "mg_autotune", "mg_histogram_csr",
     "mg_histogram_csr_noalloc", "mg_observe_histogram",
-    "mg_observed_histogram", "mg_density_l2", "mg_last_error",
+    "mg_observed_histogram", "mg_density_l2", "mg_valu_rate", "mg_last_error",
 )
 
 
@@ -107,6 +108,7 @@ def lib() -> C.CDLL:
         L.mg_observe_histogram.argtypes = [vp, i32, i32]
         L.mg_observed_histogram.argtypes = [vp, vp, i64, vp]
         L.mg_density_l2.argtypes = [vp, i32, vp, C.c_double, vp, vp]
+        L.mg_valu_rate.argtypes = [i32, i32, C.c_uint32, vp, vp]
         L.mg_last_error.restype = C.c_char_p
         for name in EXPORTED:
             if name not in ("mg_graph_destroy", "mg_particles_destroy",
@@ -441,3 +443,13 @@ def mg_autotune(p: Particles, dt: float, seed: int = 0, probe_steps: int = 0) ->
                 probe_ms=[float(t.probe_ms[i]) for i in range(t.n_probes)],
                 steps_per_launch=int(t.steps_per_launch),
                 launch_ms=[float(t.launch_ms[0]), float(t.launch_ms[1])])
+
+
+def mg_valu_rate(op: int, waves_per_simd: int = 8, iters: int = 16384):
+    """Measured issue rate of one VALU instruction kind (lane-ops/s) and the
+    timed launch's milliseconds."""
+    rate = C.c_double()
+    ms = C.c_float()
+    _check(lib().mg_valu_rate(int(op), int(waves_per_simd), int(iters), C.byref(rate),
+                              C.byref(ms)))
+    return float(rate.value), float(ms.value)

@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("mg_api.hip", "mg_kernels.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("mg_api.hip", "mg_kernels.hip", "mg_calib.hip")]
 LIB = os.path.join(HERE, "libmetricgraph.so")
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 

@@ -1572,4 +1572,46 @@ void mg_batch_destroy(mg_batch *b) {
   delete b;
 }
 
+mg_status mg_valu_rate(int32_t op, int32_t waves_per_simd, uint32_t iters,
+                       double *lane_ops_per_s, float *kernel_ms) {
+  g_err.clear();
+  if (!lane_ops_per_s) return fail(MG_EINVAL, "lane_ops_per_s is NULL");
+  if (op < MG_VALU_FMA_F32 || op > MG_VALU_ADD_U32) return fail(MG_EINVAL, "unknown op %d", op);
+  if (waves_per_simd < 1 || waves_per_simd > 8)
+    return fail(MG_EINVAL, "waves_per_simd must be in 1 .. 8");
+  if (iters < 1 || iters > (1u << 20)) return fail(MG_EINVAL, "iters must be in 1 .. 2^20");
+  int dev = 0;
+  MG_HIP(hipGetDevice(&dev), "querying the device");
+  int cus = 0;
+  MG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+         "querying the compute units");
+  // blocks of four waves: one per CU gives each of its 4 SIMDs one wave
+  const uint32_t blocks = (uint32_t)cus * (uint32_t)waves_per_simd;
+  const size_t lanes = (size_t)blocks * valu_rate_lanes_per_block();
+  uint32_t *out = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipMalloc(&out, lanes * sizeof(uint32_t));
+  if (he == hipSuccess) he = hipStreamCreate(&st);
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  // one untimed launch (code load, clocks), then the timed one
+  if (he == hipSuccess) he = launch_valu_rate(op, blocks, iters, out, st);
+  if (he == hipSuccess) he = hipEventRecord(e0, st);
+  if (he == hipSuccess) he = launch_valu_rate(op, blocks, iters, out, st);
+  if (he == hipSuccess) he = hipEventRecord(e1, st);
+  if (he == hipSuccess) he = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) (void)hipStreamDestroy(st);
+  if (out) (void)hipFree(out);
+  if (he != hipSuccess) return hip_fail(he, "running the calibration kernel");
+  if (!(ms > 0.0f)) return fail(MG_EDEVICE, "the calibration kernel took no measurable time");
+  *lane_ops_per_s = (double)lanes * (double)valu_rate_ops_per_lane(iters) / (ms * 1e-3);
+  if (kernel_ms) *kernel_ms = ms;
+  return MG_OK;
+}
+
 }  // extern "C"

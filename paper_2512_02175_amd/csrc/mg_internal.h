@@ -251,6 +251,13 @@ hipError_t launch_histogram_csr(const GraphDev &g, const SetDev &s, const int32_
 // Clears n 64-bit words with a kernel (no memset node in captured work).
 hipError_t launch_fill_zero_u64(uint64_t *p, int64_t n, hipStream_t st);
 
+// VALU issue-rate calibration (mg_calib.hip): lanes per block, instructions
+// of the measured kind per lane, and the launch of `blocks` blocks.
+uint32_t valu_rate_lanes_per_block();
+uint64_t valu_rate_ops_per_lane(uint32_t iters);
+hipError_t launch_valu_rate(int32_t op, uint32_t blocks, uint32_t iters, uint32_t *out,
+                            hipStream_t st);
+
 // Allocation-free entry points stage their tables in one fixed device array
 // per GPU of kNoAllocScratchBytes (32 MiB), whose address on `device` is
 // looked up once (hipGetSymbolAddress, with that device current) and kept.

@@ -223,3 +223,14 @@ def test_struct_layouts_match_the_header(B, tmp_path):
         assert got[(name, "size")] == C.sizeof(cls), name
         for f in cls._fields_:
             assert got[(name, f[0])] == getattr(cls, f[0]).offset, (name, f[0])
+
+
+@pytest.mark.parametrize("args", [(5, 8, 16), (-1, 8, 16), (0, 0, 16), (0, 9, 16), (0, 8, 0),
+                                  (0, 8, (1 << 20) + 1)])
+def test_valu_rate_arguments_checked(B, args):
+    """The VALU calibration refuses an unknown instruction kind and counts out
+    of range before touching the device."""
+    rate = C.c_double()
+    st = B.lib().mg_valu_rate(*args, C.byref(rate), None)
+    assert st == B.MG_EINVAL, (args, st)
+    assert B.mg_last_error()
