@@ -205,6 +205,7 @@ struct mg_batch {
   int32_t max_nnz = 0;
   int32_t max_stage = 0;  // staged table bytes if every set's graph fits, else 0
   bool gen = false;       // some set's graph has a general method variant
+  int32_t gen_level = 0;  // the highest method-variant level of its graphs
   int32_t kernel = 1;     // FP32 schedule fixed at creation (tile size follows it)
   // Per-call set descriptors go up from pinned memory; the launch chain of a
   // call is a HIP graph of kernel nodes, re-instantiated only when the
@@ -580,7 +581,7 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   g->poly = poly;
   g->wentzell = !wzt.empty();
   g->gen = g->poly || g->wentzell;
-  g->gd.gen = g->gen ? 1 : 0;
+  g->gd.gen = (g->wentzell || !tab64.empty()) ? kGenFull : (g->poly ? kGenCubic : 0);
   const size_t ng = guide.size();
   const size_t o_vtx = 0;
   const size_t o_sl = align_up(o_vtx + sizeof(VtxBlk) * V, 16);
@@ -1266,6 +1267,7 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
     all_stage = all_stage && st > 0;
     b->max_stage = std::max(b->max_stage, st);
     b->gen = b->gen || sets[i]->g->gen;
+    b->gen_level = std::max(b->gen_level, sets[i]->g->gd.gen);
   }
   if (!all_stage) b->max_stage = 0;
   // Largest sets first so the tail of the launch is made of small tiles.
@@ -1328,7 +1330,7 @@ static hipError_t build_graph(mg_batch *b, int64_t n_steps, const StepArgs &base
     a.batch_items = (uint32_t)b->n_items;
     a.batch_claim = b->d_claim;
     const KernelLaunch k = batch_launch(b->n_items, b->max_nnz, b->max_stage, a,
-                                        p0->prec == MG_FP64, p0->trace, b->key_obs, b->gen);
+                                        p0->prec == MG_FP64, p0->trace, b->key_obs, b->gen_level);
     const GraphDev *g = b->d_graphs;
     const SetDev *sd = b->d_sets;
     const BatchItem *it = b->d_items;

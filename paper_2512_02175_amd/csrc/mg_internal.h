@@ -122,9 +122,13 @@ struct GraphDev {
   int32_t o_vtx, o_slots, o_guide, o_e32, o_e64;
   int32_t stage_bytes32;  // vtx..e32 (FP32 kernels stage this range)
   int32_t stage_bytes64;  // vtx..guide + e64 (FP64 kernels)
-  // a general method variant is present (some edge has higher drift or
-  // diffusion terms, or some vertex is a Wentzell vertex): the step kernels
-  // run their GEN instantiation
+  // method-variant level: 0 affine coefficients and standard, absorbing or
+  // mirror vertices; kGenCubic some edge has higher (cubic) drift or
+  // diffusion terms; kGenFull some edge is tabulated or some vertex is a
+  // Wentzell vertex.  The step kernels run the instantiation of this level
+  // (each level's code gives the lower levels' graphs the same bits, except
+  // that affine graphs need level 0 in FP32, whose frame constants round
+  // differently from the evaluated cubics)
   int32_t gen;
   const WzRec *wz;        // Wentzell table (rows named by VtxBlk::wz), or null
   const TabRec64 *tab64;  // tabulated-coefficient intervals, or null
@@ -199,6 +203,8 @@ constexpr int kBlock = 256;
 // step schedule (StepArgs::kernel) picks: 0 one particle per lane, 1 pools
 // of 128, 2 pools of 256.
 constexpr int kPoolSmall = 128, kPoolLarge = 256;
+// method-variant levels of the step kernels' instantiations (GraphDev::gen)
+constexpr int kGenCubic = 1, kGenFull = 2;
 inline int pool_per_wave(int32_t kernel) { return kernel == 2 ? kPoolLarge : kPoolSmall; }
 constexpr int kLdsExitMax = 16384;  // slots counted in LDS (64 KiB of u32) when
                                     // the block's LDS budget allows
@@ -239,7 +245,7 @@ struct KernelLaunch {
 // the sets' particle counters and the item counter of a persistent batch.
 const void *batch_reset_kernel();
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
-                          const StepArgs &a, bool fp64, bool trace, bool obs, bool gen);
+                          const StepArgs &a, bool fp64, bool trace, bool obs, int32_t gen);
 // tiled: edge-range LDS tiles when E * nb exceeds one LDS copy (else 64-bit
 // global atomics); below that size both take the single LDS copy.
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,

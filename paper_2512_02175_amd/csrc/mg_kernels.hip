@@ -483,7 +483,7 @@ struct Hit64 {
 };
 
 // The canonical step in FP64, operation for operation.
-template <bool TRACE, bool LDS, bool GEN>
+template <bool TRACE, bool LDS, int GEN>
 struct Particle64 {
   using real = double;
   GView G;
@@ -533,7 +533,7 @@ struct Particle64 {
   }
   __device__ __forceinline__ double drift(double at) const {
     if (!GEN) return fma(R.c, at, R.a);
-    if (R.tab_k) {
+    if (GEN == kGenFull && R.tab_k) {
       double t;
       const TabRec64 &T = interval(at, t);
       return fma(fma(fma(T.mu[3], t, T.mu[2]), t, T.mu[1]), t, T.mu[0]);
@@ -542,7 +542,7 @@ struct Particle64 {
   }
   __device__ __forceinline__ double diffusion(double at) const {
     if (!GEN) return R.sigma;
-    if (R.tab_k) {
+    if (GEN == kGenFull && R.tab_k) {
       double t;
       const TabRec64 &T = interval(at, t);
       return fma(fma(fma(T.sg[3], t, T.sg[2]), t, T.sg[1]), t, T.sg[0]);
@@ -554,7 +554,7 @@ struct Particle64 {
   // end, x >= L at the terminal one; a particle that owes a stay there
   // holds -t or L + t).  Its step starts with a visit, in resolve().
   __device__ __forceinline__ bool on_wentzell() const {
-    if constexpr (!GEN) return false;
+    if constexpr (GEN != kGenFull) return false;
     return (x <= 0.0 && ((uint32_t)R.vinit & kWentzellEnd)) ||
            (x >= R.L && ((uint32_t)R.vterm & kWentzellEnd));
   }
@@ -677,7 +677,7 @@ struct Particle64 {
       // how far past the vertex the proposal went
       double h_move = h, owed = 0.0;
       bool killed = false;
-      if (GEN && vb.wz) {
+      if (GEN == kGenFull && vb.wz) {
         const double o = at_init ? -xt : xt - R.L;
         killed = wz_visit(G.wz[vb.wz - 1u], o, h, vertex_draw(pid, step, (uint32_t)H.k, S, A),
                           h_move, owed);
@@ -693,7 +693,7 @@ struct Particle64 {
       x = (sp.eo & 1u) ? R.L : 0.0;
       H.last = sp.s;
       if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)sp.s);
-      if (GEN && vb.wz) {
+      if (GEN == kGenFull && vb.wz) {
         h = h_move;
         if (h == 0.0) {  // stays on the vertex for the rest of the step
           x = (sp.eo & 1u) ? R.L + owed : -owed;
@@ -732,7 +732,7 @@ struct Particle64 {
   }
 };
 
-template <bool TRACE, bool LDS, bool OBS, int NG, bool GEN>
+template <bool TRACE, bool LDS, bool OBS, int NG, int GEN>
 __device__ void run64(const GView &G, int32_t n_edges, const SetDev &S, const StepArgs &A,
                       uint32_t pid, uint32_t *s_exit, Tally &t, const ObsSink &o) {
   const uint32_t ef = S.ef[pid];
@@ -797,7 +797,7 @@ struct Hit32 {
 // Wentzell vertices: a step that starts on one begins with a visit (in
 // cross()), and a hit there is a visit too; a particle that owes a stay on
 // the vertex holds y = -t in the frame of that end.
-template <bool TRACE, bool LDS, bool GEN = false>
+template <bool TRACE, bool LDS, int GEN = 0>
 struct Particle32 {
   using real = float;
   GView G;
@@ -839,9 +839,11 @@ struct Particle32 {
       s1 = (float)P.s1;
       s2 = (float)P.s2;
       s3 = (float)P.s3;
-      inv_h = (float)P.inv_h;
-      tab0 = P.tab0;
-      tab_k = P.tab_k;
+      if constexpr (GEN == kGenFull) {
+        inv_h = (float)P.inv_h;
+        tab0 = P.tab0;
+        tab_k = P.tab_k;
+      }
     }
   }
 
@@ -863,7 +865,7 @@ struct Particle32 {
     } else {
       const float x = side ? R.L - yy : yy;
       float m;
-      if (tab_k) {
+      if (GEN == kGenFull && tab_k) {
         float t;
         const TabRec32 &T = interval(x, t);
         m = fmaf(fmaf(fmaf(T.mu[3], t, T.mu[2]), t, T.mu[1]), t, T.mu[0]);
@@ -878,7 +880,7 @@ struct Particle32 {
       return R.sigma;
     } else {
       const float x = side ? R.L - yy : yy;
-      if (tab_k) {
+      if (GEN == kGenFull && tab_k) {
         float t;
         const TabRec32 &T = interval(x, t);
         return fmaf(fmaf(fmaf(T.sg[3], t, T.sg[2]), t, T.sg[1]), t, T.sg[0]);
@@ -924,7 +926,7 @@ struct Particle32 {
   // GEN: the particle sits on a Wentzell vertex, its reference end (y <= 0:
   // on the vertex, or owing a stay of -y there).
   __device__ __forceinline__ bool on_wentzell() const {
-    if constexpr (!GEN) return false;
+    if constexpr (GEN != kGenFull) return false;
     return y <= 0.0f && ((uint32_t)(side ? R.vterm : R.vinit) & kWentzellEnd);
   }
   // The particle stays on its reference end, a Wentzell vertex, owing a
@@ -1059,7 +1061,7 @@ struct Particle32 {
     float err;
     const float yt = add_comp(fmaf(g, we, mdt) + yl, err);
     // the move that leaves a start-of-step visit need not reach a vertex
-    if (GEN && h.k == 0 && !first && yt > 0.0f && yt < R.L) {
+    if (GEN == kGenFull && h.k == 0 && !first && yt > 0.0f && yt < R.L) {
       y = yt;
       yl = err;
       return true;
@@ -1128,7 +1130,7 @@ struct Particle32 {
       // overshoot past the vertex
       double hm = 0.0, owed = 0.0;
       bool killed = false;
-      if (GEN && vb.wz)
+      if (GEN == kGenFull && vb.wz)
         killed = wz_visit(G.wz[vb.wz - 1u], (double)r0 + (double)r1,
                           (double)hh + (double)hl, vertex_draw(pid, step, (uint32_t)h.k, S, A),
                           hm, owed);
@@ -1147,7 +1149,7 @@ struct Particle32 {
       h.last = sp.s;
       if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)sp.s);
       bool stays = false;
-      if (GEN && vb.wz) {
+      if (GEN == kGenFull && vb.wz) {
         if (hm == 0.0) {  // stays on the vertex for the rest of the step
           owe_stay(owed);
           stays = true;
@@ -1190,7 +1192,7 @@ struct Particle32 {
   }
 };
 
-template <bool TRACE, bool LDS, bool OBS, int NG, bool GEN>
+template <bool TRACE, bool LDS, bool OBS, int NG, int GEN>
 __device__ void run32(const GView &G, int32_t n_edges, const SetDev &S, const StepArgs &A,
                       uint32_t pid, uint32_t *s_exit, Tally &t, const ObsSink &o) {
   const uint32_t ef = S.ef[pid];
@@ -1281,7 +1283,7 @@ __device__ __forceinline__ GView block_view(const GraphDev &G, char *smem) {
 
 __device__ __forceinline__ int32_t exit_bytes(int32_t nnz) { return ((nnz * 4) + 15) & ~15; }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool GEN>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, int GEN>
 __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, uint32_t pid,
                                            unsigned long long *s_tot, char *smem) {
@@ -1310,7 +1312,7 @@ __device__ __forceinline__ void step_block(const GraphDev &G, const SetDev &S,
 }
 
 // GEN: some edge has higher drift or diffusion terms (FP32: lane schedule only).
-template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool GEN>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, int GEN>
 __global__ __launch_bounds__(kBlock) void k_step(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
   __shared__ unsigned long long s_tot[4];
@@ -1318,7 +1320,7 @@ __global__ __launch_bounds__(kBlock) void k_step(GraphDev G, SetDev S, StepArgs 
                                                   s_tot, (char *)smem4);
 }
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, bool GEN>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, int GEN>
 __global__ __launch_bounds__(kBlock) void k_batch(const GraphDev *graphs,
                                                   const SetDev *sets,
                                                   const BatchItem *items,
@@ -1419,7 +1421,7 @@ __device__ __forceinline__ void wave_lds_fence() { __atomic_signal_fence(__ATOMI
 
 // Moving particles between registers, the pool's home slots and the set:
 // one overload per precision.
-template <bool TRACE, bool LDS, bool GEN, int PW>
+template <bool TRACE, bool LDS, int GEN, int PW>
 __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS, GEN> &q,
                                           const PoolLds32<TRACE, PW> &P,
                                           uint32_t s) {
@@ -1436,7 +1438,7 @@ __device__ __forceinline__ void pool_load(Particle32<TRACE, LDS, GEN> &q,
     q.hash = P.hash[s];
   }
 }
-template <bool TRACE, bool LDS, bool GEN, int PW>
+template <bool TRACE, bool LDS, int GEN, int PW>
 __device__ __forceinline__ void pool_load(Particle64<TRACE, LDS, GEN> &q,
                                           const PoolLds64<TRACE, PW> &P,
                                           uint32_t s) {
@@ -1450,7 +1452,7 @@ __device__ __forceinline__ void pool_load(Particle64<TRACE, LDS, GEN> &q,
   }
 }
 
-template <bool TRACE, bool LDS, bool GEN, int PW>
+template <bool TRACE, bool LDS, int GEN, int PW>
 __device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS, GEN> &q,
                                            PoolLds32<TRACE, PW> &P,
                                            uint32_t s, uint32_t n) {
@@ -1463,7 +1465,7 @@ __device__ __forceinline__ void pool_store(const Particle32<TRACE, LDS, GEN> &q,
     P.hash[s] = q.hash;
   }
 }
-template <bool TRACE, bool LDS, bool GEN, int PW>
+template <bool TRACE, bool LDS, int GEN, int PW>
 __device__ __forceinline__ void pool_store(const Particle64<TRACE, LDS, GEN> &q,
                                            PoolLds64<TRACE, PW> &P,
                                            uint32_t s, uint32_t n) {
@@ -1518,7 +1520,7 @@ __device__ __forceinline__ void pool_park(PoolLds64<TRACE, PW> &P, uint32_t s, c
 // Reads particle id from the set when a wave claims it: the state word
 // and position go to home slot hs.  False for a removed particle, and for
 // a corrupt state (the set's error word is raised).
-template <bool TRACE, int PW, bool GEN>
+template <bool TRACE, int PW, int GEN>
 __device__ __forceinline__ bool pool_claim(const GView &G, const SetDev &S, int32_t n_edges,
                                            uint32_t id, PoolLds32<TRACE, PW> &P, uint32_t hs,
                                            bool mine) {
@@ -1533,7 +1535,7 @@ __device__ __forceinline__ bool pool_claim(const GView &G, const SetDev &S, int3
       if (e >= n_edges) {
         atomicOr(S.err, kErrEdge);
       } else if (!((yy.x >= 0.0f && yy.x <= G.e32[e].L) ||
-                   (GEN && yy.x < 0.0f &&
+                   (GEN == kGenFull && yy.x < 0.0f &&
                     ((uint32_t)((ef & kSideBit) ? G.e32[e].vterm : G.e32[e].vinit) &
                      kWentzellEnd)))) {
         atomicOr(S.err, kErrPos);
@@ -1549,7 +1551,7 @@ __device__ __forceinline__ bool pool_claim(const GView &G, const SetDev &S, int3
   }
   return ok;
 }
-template <bool TRACE, int PW, bool GEN>
+template <bool TRACE, int PW, int GEN>
 __device__ __forceinline__ bool pool_claim(const GView &G, const SetDev &S, int32_t n_edges,
                                            uint32_t id, PoolLds64<TRACE, PW> &P, uint32_t hs,
                                            bool mine) {
@@ -1566,7 +1568,7 @@ __device__ __forceinline__ bool pool_claim(const GView &G, const SetDev &S, int3
       } else {
         const EdgeRec64 &r = G.e64[e];
         if (!((x >= 0.0 && x <= r.L) ||
-              (GEN && ((x <= 0.0 && ((uint32_t)r.vinit & kWentzellEnd)) ||
+              (GEN == kGenFull && ((x <= 0.0 && ((uint32_t)r.vinit & kWentzellEnd)) ||
                        (x >= r.L && ((uint32_t)r.vterm & kWentzellEnd)))))) {
           atomicOr(S.err, kErrPos);
         } else {
@@ -1584,7 +1586,7 @@ __device__ __forceinline__ bool pool_claim(const GView &G, const SetDev &S, int3
 
 // Writes a particle back at the end of its launch and counts the steps it
 // took (each has one first sub-step; resolve() counts the others).
-template <bool TRACE, bool LDS, bool GEN>
+template <bool TRACE, bool LDS, int GEN>
 __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS, GEN> &q, const SetDev &S,
                                             const StepArgs &A, uint32_t pid, Tally &t) {
   S.ef[pid] = (uint32_t)q.e | (q.side ? kSideBit : 0u) | (q.alive ? 0u : kDeadBit);
@@ -1597,7 +1599,7 @@ __device__ __forceinline__ void pool_finish(const Particle32<TRACE, LDS, GEN> &q
   t.steps += taken;
   t.sub += taken;
 }
-template <bool TRACE, bool LDS, bool GEN>
+template <bool TRACE, bool LDS, int GEN>
 __device__ __forceinline__ void pool_finish(const Particle64<TRACE, LDS, GEN> &q, const SetDev &S,
                                             const StepArgs &A, uint32_t pid, Tally &t) {
   S.ef[pid] = (uint32_t)q.e | (q.alive ? 0u : kDeadBit);
@@ -1613,13 +1615,13 @@ __device__ __forceinline__ void pool_finish(const Particle64<TRACE, LDS, GEN> &q
 
 // A particle of the pool loop, before its first pickup: the graph view,
 // exit counters and the launch's dt.
-template <bool TRACE, bool LDS, bool GEN>
+template <bool TRACE, bool LDS, int GEN>
 __device__ __forceinline__ void pool_particle(Particle32<TRACE, LDS, GEN> &q, const GView &G,
                                               uint32_t *s_exit, const StepArgs &A) {
   q = Particle32<TRACE, LDS, GEN>{G, s_exit, 0, 0u, 0.0f, 0.0f, Edge32{}, 0.0f, 0.0f,
                                   (float)A.dt, (float)sqrt(A.dt), true, 0ull, 0u, 0u};
 }
-template <bool TRACE, bool LDS, bool GEN>
+template <bool TRACE, bool LDS, int GEN>
 __device__ __forceinline__ void pool_particle(Particle64<TRACE, LDS, GEN> &q, const GView &G,
                                               uint32_t *s_exit, const StepArgs &A) {
   q = Particle64<TRACE, LDS, GEN>{G, s_exit, 0, 0.0, EdgeRec64{}, true, 0ull, 0u, 0u,
@@ -1670,7 +1672,7 @@ __device__ __forceinline__ void drain_lds(uint32_t *lds, uint64_t *glob, int32_t
 // set only while its counter is below n, so this holds there too).
 // Q: the particle type (Particle32 or Particle64, each with its pool type
 // in LDS).
-template <bool TRACE, bool LDS, bool OBS, int PW, int NG, bool GEN, class Q, class Pool>
+template <bool TRACE, bool LDS, bool OBS, int PW, int NG, int GEN, class Q, class Pool>
 __device__ void run_pool(const GView &G, int32_t n_edges, const SetDev &S,
                          const StepArgs &A, Pool &P, uint32_t *s_exit, Tally &t,
                          unsigned long long *s_tot, int32_t nnz, const ObsSink &sink) {
@@ -1884,7 +1886,7 @@ __device__ void run_pool(const GView &G, int32_t n_edges, const SetDev &S,
 template <int PW, bool FP64, bool TRACE>
 using PoolLds = std::conditional_t<FP64, PoolLds64<TRACE, PW>, PoolLds32<TRACE, PW>>;
 
-template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool GEN>
+template <bool FP64, bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, int GEN>
 __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
                                            const StepArgs &A, unsigned long long *s_tot,
                                            char *smem) {
@@ -1919,7 +1921,7 @@ __device__ __forceinline__ void pool_block(const GraphDev &G, const SetDev &S,
 
 // GEN (cubic coefficients) is instantiated for pools of 128 with two
 // Philox groups per window only.
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool GEN = false>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, int GEN = 0>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
@@ -1933,7 +1935,7 @@ void k_pool32(GraphDev G, SetDev S, StepArgs A) {
 #ifndef MG_POOL64_WAVES_PER_EU
 #define MG_POOL64_WAVES_PER_EU 4
 #endif
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, bool GEN>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int GEN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL64_WAVES_PER_EU)))
 void k_pool64(GraphDev G, SetDev S, StepArgs A) {
   extern __shared__ uint4 smem4[];
@@ -1949,7 +1951,7 @@ void k_pool64(GraphDev G, SetDev S, StepArgs A) {
 // run out.  An item of a set that has run out is passed over at the cost
 // of one load.  Both counters are cleared by k_batch_reset before each
 // launch.
-template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, bool GEN = false>
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int PW, int NG, int GEN = 0>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL_WAVES_PER_EU)))
 void k_pool32_batch(const GraphDev *graphs, const SetDev *sets, const BatchItem *items,
                     StepArgs A) {
@@ -2228,6 +2230,18 @@ void with_flags(F &&f, bool x, Rest... rest) {
     with_flags([&](auto... v) { f(std::false_type{}, v...); }, rest...);
 }
 
+// The graph's method-variant level as a compile-time constant: 0 affine
+// coefficients, kGenCubic cubic ones, kGenFull tables or Wentzell vertices.
+template <typename F>
+void with_gen(int32_t level, F &&f) {
+  if (level == kGenFull)
+    f(std::integral_constant<int, kGenFull>{});
+  else if (level == kGenCubic)
+    f(std::integral_constant<int, kGenCubic>{});
+  else
+    f(std::integral_constant<int, 0>{});
+}
+
 // Shape of an FP32 wave-pool schedule (StepArgs::kernel 1, 2, 3): particles
 // per wave and Philox groups per phase-A window.
 template <typename F>
@@ -2290,14 +2304,17 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
       a.obs_lds = lp.obs_lds;
       const uint32_t need = (s.n + kPoolSmall * kWavesPerBlock - 1) / (kPoolSmall * kWavesPerBlock);
       hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, st, s.work);
-      with_flags([&](auto L, auto T, auto O, auto Gn) {
-        constexpr bool l = decltype(L)::value, t = decltype(T)::value,
-                       o = decltype(O)::value, gn = decltype(Gn)::value;
-        const void *f = (const void *)k_pool64<TRACE, l, t, o, gn>;
-        hipLaunchKernelGGL((k_pool64<TRACE, l, t, o, gn>),
-                           dim3(resident_blocks(f, lp.shm, need)), dim3(kBlock), lp.shm, st,
-                           g, s, a);
-      }, lp.lds_exit, lp.staged, obs, g.gen != 0);
+      with_gen(g.gen, [&](auto Gn) {
+        constexpr int gn = decltype(Gn)::value;
+        with_flags([&](auto L, auto T, auto O) {
+          constexpr bool l = decltype(L)::value, t = decltype(T)::value,
+                         o = decltype(O)::value;
+          const void *f = (const void *)k_pool64<TRACE, l, t, o, gn>;
+          hipLaunchKernelGGL((k_pool64<TRACE, l, t, o, gn>),
+                             dim3(resident_blocks(f, lp.shm, need)), dim3(kBlock), lp.shm, st,
+                             g, s, a);
+        }, lp.lds_exit, lp.staged, obs);
+      });
       return hipGetLastError();
     }
   }
@@ -2322,14 +2339,19 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
       }
       if constexpr (PW == kPoolSmall && NG == 2) {
         if (g.gen) {
-          with_flags([&](auto L, auto T, auto O) {
-            const void *f = (const void *)k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
-                                                   decltype(O)::value, PW, NG, true>;
-            hipLaunchKernelGGL((k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
-                                         decltype(O)::value, PW, NG, true>),
-                               dim3(resident_blocks(f, lp.shm, need)), dim3(kBlock), lp.shm,
-                               st, g, s, a);
-          }, lp.lds_exit, lp.staged, obs);
+          with_gen(g.gen, [&](auto Gn) {
+            constexpr int gn = decltype(Gn)::value;
+            if constexpr (gn != 0)
+              with_flags([&](auto L, auto T, auto O) {
+                const void *f =
+                    (const void *)k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
+                                           decltype(O)::value, PW, NG, gn>;
+                hipLaunchKernelGGL((k_pool32<TRACE, decltype(L)::value, decltype(T)::value,
+                                             decltype(O)::value, PW, NG, gn>),
+                                   dim3(resident_blocks(f, lp.shm, need)), dim3(kBlock),
+                                   lp.shm, st, g, s, a);
+              }, lp.lds_exit, lp.staged, obs);
+          });
           return;
         }
       }
@@ -2355,18 +2377,21 @@ hipError_t launch_step_t(const GraphDev &g, const SetDev &s, const StepArgs &a0,
     }, lp.lds_exit, lp.staged);
     return hipGetLastError();
   }
-  with_flags([&](auto L, auto T, auto O, auto P) {
-    hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
-                               decltype(O)::value, decltype(P)::value>),
-                       dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
-  }, lp.lds_exit, lp.staged, obs, g.gen != 0);
+  with_gen(g.gen, [&](auto Gn) {
+    constexpr int gn = decltype(Gn)::value;
+    with_flags([&](auto L, auto T, auto O) {
+      hipLaunchKernelGGL((k_step<FP64, TRACE, decltype(L)::value, decltype(T)::value,
+                                 decltype(O)::value, gn>),
+                         dim3(blocks), dim3(kBlock), lp.shm, st, g, s, a);
+    }, lp.lds_exit, lp.staged, obs);
+  });
   return hipGetLastError();
 }
 
 // Batched launches keep snapshot bins in global memory (the sets differ).
 template <bool FP64, bool TRACE>
 KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
-                            const StepArgs &a, bool obs, bool gen) {
+                            const StepArgs &a, bool obs, int32_t gen) {
   KernelLaunch k{};
   k.grid = dim3(n_items);
   k.block = dim3(kBlock);
@@ -2378,24 +2403,23 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
                                 pools ? sizeof(PoolLds32<TRACE, PW>) * kWavesPerBlock : 0,
                                 nullptr, 0);
     k.shm = lp.shm;
-    with_flags([&](auto L, auto T, auto O) {
-      constexpr bool l = decltype(L)::value, t = decltype(T)::value, o = decltype(O)::value;
-      if constexpr (!FP64)
-        if (pools) {
-          k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG>;
-          if constexpr (PW == kPoolSmall && NG == 2)
-            if (gen) k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG, true>;
-          // a resident grid takes the items from the batch's counter
-          k.persistent = true;
-          k.grid = dim3(resident_blocks(k.func, k.shm, (uint32_t)n_items));
-          return;
-        }
-      if (gen) {
-        k.func = (const void *)k_batch<FP64, TRACE, l, t, o, true>;
-        return;
-      }
-      k.func = (const void *)k_batch<FP64, TRACE, l, t, o, false>;
-    }, lp.lds_exit, lp.staged, obs);
+    with_gen(gen, [&](auto Gn) {
+      constexpr int gn = decltype(Gn)::value;
+      with_flags([&](auto L, auto T, auto O) {
+        constexpr bool l = decltype(L)::value, t = decltype(T)::value, o = decltype(O)::value;
+        if constexpr (!FP64)
+          if (pools) {
+            k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG>;
+            if constexpr (PW == kPoolSmall && NG == 2 && gn != 0)
+              k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG, gn>;
+            // a resident grid takes the items from the batch's counter
+            k.persistent = true;
+            k.grid = dim3(resident_blocks(k.func, k.shm, (uint32_t)n_items));
+            return;
+          }
+        k.func = (const void *)k_batch<FP64, TRACE, l, t, o, gn>;
+      }, lp.lds_exit, lp.staged, obs);
+    });
   });
   return k;
 }
@@ -2431,7 +2455,7 @@ int32_t batch_tile(bool fp64, int32_t kernel) {
 }
 
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
-                          const StepArgs &a, bool fp64, bool trace, bool obs, bool gen) {
+                          const StepArgs &a, bool fp64, bool trace, bool obs, int32_t gen) {
   if (fp64)
     return trace ? batch_launch_t<true, true>(n_items, max_nnz, max_stage, a, obs, gen)
                  : batch_launch_t<true, false>(n_items, max_nnz, max_stage, a, obs, gen);
