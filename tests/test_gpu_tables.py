@@ -114,3 +114,34 @@ def test_table_of_a_cubic_runs_the_cubic_on_the_gpu(B):
     same = a["seqhash"] == b["seqhash"]
     assert same.mean() >= 0.999
     assert np.abs(a["x"][same] - b["x"][same]).max() < 1e-9
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_of_cubic_tabulated_and_wentzell_graphs_equals_sets_alone(B, prec):
+    """A batch runs the kernels of its most general graph: a cubic-coefficient
+    star (run alone by the cubic instantiation) batched with a tabulated star
+    and a Wentzell star (the full general one) gives each set's results as
+    when it runs alone, in both precisions."""
+    graphs = [workloads.double_well_star(16), workloads.periodic_star(),
+              workloads.wentzell_star(5, seed=7)]
+    Gs = [B.mg_graph_create(g) for g in graphs]
+    counts = [30_000, 12_000, 9_000]
+
+    def make():
+        return [B.mg_particles_init(G, c, 2, init_seed=i, precision=prec, trace=True,
+                                    graph_tag=i, max_splits=5)
+                for i, (G, c) in enumerate(zip(Gs, counts))]
+    print(f"level batch: precision={prec}", flush=True)
+    alone = make()
+    for p in alone:
+        B.mg_simulate(p, 400, 2e-3, 23)
+    batched = make()
+    b = B.mg_batch_create(batched)
+    B.mg_batch_simulate(b, 400, 2e-3, 23)
+    for pa, pb in zip(alone, batched):
+        ra, rb = B.mg_particles_read(pa, trace=True), B.mg_particles_read(pb, trace=True)
+        for f in ("edge", "x", "alive", "seqhash", "hits"):
+            assert np.array_equal(ra[f], rb[f]), f
+        for x, y in zip(B.mg_exit_counts(pa), B.mg_exit_counts(pb)):
+            assert np.array_equal(x, y)
+        assert int(B.mg_exit_counts(pa)[2][2]) > 0
