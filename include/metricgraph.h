@@ -411,7 +411,15 @@ void mg_batch_destroy(mg_batch *b);
  * launches; a set created with steps_per_launch 0 takes the faster (0: the
  * whole call per launch, else probe_steps steps per launch).  The
  * result is also kept with the graph: later calls for any set on the same
- * graph at the same dt take it without probing.  Sets created with
+ * graph at the same dt take it without probing.  With the environment
+ * variable MG_TUNE_CACHE naming a file, results also outlive the process:
+ * before probing, the call looks there for a line with the same GPU
+ * architecture name and compute-unit count, graph (a fingerprint of its
+ * packed tables), probed particle count, max_splits, dt and probe_steps,
+ * and takes that result (n_probes 0, no probe times); after probing it
+ * appends one JSON line with the key and the choice.  Lines that do not
+ * parse are skipped; a file that cannot be read or written is ignored.
+ * Sets created with
  * schedule MG_SCHED_AUTO are tuned this way on their first mg_simulate at
  * each dt; until then (and in a batch built from untuned sets) they use
  * pools of 128 with 8-step windows.  Fixed pool schedules start a partial

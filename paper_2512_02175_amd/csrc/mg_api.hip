@@ -164,6 +164,8 @@ struct mg_graph {
   bool poly = false;
   bool wentzell = false;
   bool gen = false;
+  // FNV-1a of the packed device tables: names the graph in the tuning file
+  uint64_t fingerprint = 0;
   void *dev = nullptr;         // one allocation holding every table
   GraphDev gd{};
 };
@@ -300,6 +302,94 @@ mg_status check_csr_bins(const mg_particles *p, const int32_t *bin_offsets,
 }
 
 }  // namespace
+
+// Tuning results kept across processes: with MG_TUNE_CACHE naming a file,
+// mg_autotune reads a result from it before probing and appends the result
+// of each probe, one JSON object per line.  A line's key: the GPU's
+// architecture name and compute-unit count, the graph's table fingerprint,
+// the probed particle count, the split cap, dt (its bits) and the probe
+// length.  Lines that do not parse, or have another key, are skipped.
+struct TuneKey {
+  char arch[64];
+  int32_t cus;
+  uint64_t graph;
+  long long n;
+  int32_t max_splits;
+  uint64_t dt_bits;
+  uint32_t probe_steps;
+};
+
+bool tune_key(const mg_particles *p, double dt, uint32_t steps, int64_t n, TuneKey &k) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return false;
+  std::memset(&k, 0, sizeof k);
+  // the name up to the first character the line format cannot hold
+  size_t i = 0;
+  for (; i + 1 < sizeof k.arch && prop.gcnArchName[i] && prop.gcnArchName[i] != '"' &&
+         prop.gcnArchName[i] != '\\' && (unsigned char)prop.gcnArchName[i] > ' ';
+       ++i)
+    k.arch[i] = prop.gcnArchName[i];
+  k.arch[i] = 0;
+  k.cus = prop.multiProcessorCount;
+  k.graph = p->g->fingerprint;
+  k.n = (long long)n;
+  k.max_splits = p->max_splits;
+  std::memcpy(&k.dt_bits, &dt, 8);
+  k.probe_steps = steps;
+  return true;
+}
+
+#define MG_TUNE_LINE                                                                   \
+  "{\"arch\": \"%63[^\"]\", \"cus\": %d, \"graph\": \"%16llx\", \"n\": %lld, "              \
+  "\"max_splits\": %d, \"dt_bits\": \"%16llx\", \"probe_steps\": %u, \"schedule\": %d, "      \
+  "\"idle_trigger\": %d, \"pool_size\": %d, \"window\": %d, \"steps_per_launch\": %d}"
+
+bool tune_file_read(const char *path, const TuneKey &k, mg_tuning &res) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (!found && std::fgets(line, sizeof line, f)) {
+    TuneKey r{};
+    unsigned long long gr = 0, dtb = 0;
+    mg_tuning t{};
+    const int got = std::sscanf(line, MG_TUNE_LINE, r.arch, &r.cus, &gr, &r.n, &r.max_splits,
+                                &dtb, &r.probe_steps, &t.schedule, &t.idle_trigger,
+                                &t.pool_size, &t.window, &t.steps_per_launch);
+    if (got != 12) continue;
+    if (std::strcmp(r.arch, k.arch) != 0 || r.cus != k.cus || gr != k.graph || r.n != k.n ||
+        r.max_splits != k.max_splits || dtb != k.dt_bits || r.probe_steps != k.probe_steps)
+      continue;
+    const bool pools = t.schedule == MG_SCHED_POOLS || t.schedule == MG_SCHED_POOLS256 ||
+                       t.schedule == MG_SCHED_POOLS_W8;
+    if (!(t.schedule == MG_SCHED_LANES || pools) || t.steps_per_launch < 0) continue;
+    if (pools && !(t.idle_trigger >= 1 && t.idle_trigger <= 64)) continue;
+    res = t;
+    found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_file_append(const char *path, const TuneKey &k, const mg_tuning &t) {
+  char line[512];
+  // the writer's format is the reader's with plain conversions
+  const int len = std::snprintf(
+      line, sizeof line,
+      "{\"arch\": \"%s\", \"cus\": %d, \"graph\": \"%016llx\", \"n\": %lld, "
+      "\"max_splits\": %d, \"dt_bits\": \"%016llx\", \"probe_steps\": %u, \"schedule\": %d, "
+      "\"idle_trigger\": %d, \"pool_size\": %d, \"window\": %d, \"steps_per_launch\": %d}\n",
+      k.arch, k.cus, (unsigned long long)k.graph, k.n, k.max_splits,
+      (unsigned long long)k.dt_bits, k.probe_steps, t.schedule, t.idle_trigger, t.pool_size,
+      t.window, t.steps_per_launch);
+  if (len <= 0 || len >= (int)sizeof line) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fwrite(line, 1, (size_t)len, f);
+  std::fclose(f);
+}
 
 extern "C" {
 
@@ -616,6 +706,11 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
     (void)hipFree(g->dev);
     delete g;
     return hip_fail(he, "copying the graph tables");
+  }
+  {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (char c : host) h = (h ^ (uint8_t)c) * 0x100000001b3ull;
+    g->fingerprint = h;
   }
   g->gd.tables = base;
   g->gd.vtx = (const VtxBlk *)(base + o_vtx);
@@ -1465,6 +1560,24 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   const uint32_t steps = (uint32_t)(probe_steps > 0 ? probe_steps : 1024);
   if ((uint64_t)p->step + 2ull * steps > 0xFFFFFFFFull)
     return fail(MG_EINVAL, "the probe would pass step 2^32");
+  const char *tune_path = std::getenv("MG_TUNE_CACHE");
+  if (tune_path && !*tune_path) tune_path = nullptr;
+  TuneKey key{};
+  if (tune_path && !tune_key(p, dt, steps, n, key)) tune_path = nullptr;
+  if (tune_path && tune_file_read(tune_path, key, res)) {
+    // a result of an earlier process: no probes
+    p->tuned = true;
+    p->tuned_dt = dt;
+    p->tuned_kernel = kernel_of(res.schedule);
+    p->tuned_idle = res.schedule == MG_SCHED_LANES ? 8 : res.idle_trigger;
+    p->tuned_spl = res.steps_per_launch;
+    {
+      std::lock_guard<std::mutex> lock(p->g->tune_mu);
+      p->g->tune_cache.emplace_back(dt, res);
+    }
+    if (out) *out = res;
+    return MG_OK;
+  }
   const SetLayout L = set_layout(p->g->V, p->g->nnz, n, MG_FP32, false);
   void *mem = nullptr;
   MG_HIP(hipMalloc(&mem, L.total), "allocating the tuning probe");
@@ -1559,6 +1672,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
     std::lock_guard<std::mutex> lock(p->g->tune_mu);
     p->g->tune_cache.emplace_back(dt, res);
   }
+  if (tune_path) tune_file_append(tune_path, key, res);
   if (out) *out = res;
   return MG_OK;
 }

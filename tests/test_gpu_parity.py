@@ -466,3 +466,42 @@ def test_fp32_near_vertex_fp64_solve(B, orc):
         hits += c.hits
     # most of the first steps cross the vertex they start next to
     assert hits > n // 3
+
+
+def test_tuning_file_outlives_the_graph(B, monkeypatch, tmp_path):
+    """With MG_TUNE_CACHE set, a tuning result is appended to the file as one
+    JSON line, and a new graph object with the same tables takes it from the
+    file without probing (the same choice, no probe times); a line that does
+    not parse, or has another key, is skipped."""
+    import json
+    path = tmp_path / "tune.jsonl"
+    path.write_text("not json\n{\"arch\": \"other\"}\n")
+    monkeypatch.setenv("MG_TUNE_CACHE", str(path))
+    g, _ = workloads.config2()
+    kw = dict(init_seed=4, precision=B.MG_FP32, schedule=B.MG_SCHED_AUTO)
+    p1 = B.mg_particles_init(B.mg_graph_create(g), 50_000, 2, **kw)
+    t1 = B.mg_autotune(p1, 1e-2, 3, 8)
+    assert t1["n_probes"] == 10
+    lines = path.read_text().splitlines()
+    assert len(lines) == 3
+    rec = json.loads(lines[2])
+    assert rec["schedule"] == t1["schedule"] and rec["steps_per_launch"] == t1["steps_per_launch"]
+    assert rec["n"] == 50_000 and rec["probe_steps"] == 8
+    p2 = B.mg_particles_init(B.mg_graph_create(g), 50_000, 2, **kw)
+    t2 = B.mg_autotune(p2, 1e-2, 3, 8)
+    assert t2["n_probes"] == 0
+    for f in ("schedule", "idle_trigger", "pool_size", "window", "steps_per_launch"):
+        assert t2[f] == t1[f], f
+    assert len(path.read_text().splitlines()) == 3
+    # another dt is another key: probed and appended
+    t3 = B.mg_autotune(p2, 1e-3, 3, 8)
+    assert t3["n_probes"] == 10
+    assert len(path.read_text().splitlines()) == 4
+    # the tuned sets give the lane schedule's bits
+    lanes = B.mg_particles_init(B.mg_graph_create(g), 50_000, 2, init_seed=4,
+                                precision=B.MG_FP32, schedule=B.MG_SCHED_LANES)
+    B.mg_simulate(p2, 100, 1e-2, 9)
+    B.mg_simulate(lanes, 100, 1e-2, 9)
+    ra, rb = B.mg_particles_read(p2), B.mg_particles_read(lanes)
+    for f in ra:
+        assert np.array_equal(ra[f], rb[f]), f
