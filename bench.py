@@ -864,7 +864,7 @@ def main():
     rates = {name: B.mg_valu_rate(op)[0] / 1e12 for name, op in (
         ("v_fma_f32", B.MG_VALU_FMA_F32), ("v_fma_f64", B.MG_VALU_FMA_F64),
         ("v_mad_u64_u32", B.MG_VALU_MAD_U64_U32), ("v_bitop3_b32", B.MG_VALU_BITOP3),
-        ("v_add_u32", B.MG_VALU_ADD_U32))}
+        ("v_add_u32", B.MG_VALU_ADD_U32), ("v_log_f32", B.MG_VALU_LOG_F32))}
     # (a call is one launch unless the tuner split it; the rate is per call)
     k32 = float(np.mean(ktimes32))
     per_call = [alg_work(1, r["steps"], r["hits"]) for r in res32]

@@ -461,7 +461,8 @@ typedef enum {
   MG_VALU_FMA_F64 = 1,      /* v_fma_f64 */
   MG_VALU_MAD_U64_U32 = 2,  /* v_mad_u64_u32: 32 x 32 -> 64-bit multiply-add */
   MG_VALU_BITOP3 = 3,       /* v_bitop3_b32: any bitwise function of 3 words */
-  MG_VALU_ADD_U32 = 4       /* v_add_u32 */
+  MG_VALU_ADD_U32 = 4,      /* v_add_u32 */
+  MG_VALU_LOG_F32 = 5       /* v_log_f32: the transcendental unit */
 } mg_valu_op;
 
 mg_status mg_valu_rate(int32_t op, int32_t waves_per_simd, uint32_t iters,

@@ -21,7 +21,8 @@ MG_FP64, MG_FP32 = 0, 1
 MG_VTX_STANDARD, MG_VTX_ABSORBING, MG_VTX_MIRROR, MG_VTX_WENTZELL = 0, 1, 2, 3
 MG_INIT_EXPLICIT, MG_INIT_AT_VERTEX, MG_INIT_UNIFORM_LENGTH = 0, 1, 2
 MG_SCHED_AUTO, MG_SCHED_LANES, MG_SCHED_POOLS, MG_SCHED_POOLS256, MG_SCHED_POOLS_W8 = 0, 1, 2, 3, 4
-MG_VALU_FMA_F32, MG_VALU_FMA_F64, MG_VALU_MAD_U64_U32, MG_VALU_BITOP3, MG_VALU_ADD_U32 = range(5)
+(MG_VALU_FMA_F32, MG_VALU_FMA_F64, MG_VALU_MAD_U64_U32, MG_VALU_BITOP3, MG_VALU_ADD_U32,
+ MG_VALU_LOG_F32) = range(6)
 
 EXPORTED = (
     "mg_graph_create", "mg_graph_destroy", "mg_particles_arena_bytes",

@@ -1692,7 +1692,7 @@ mg_status mg_valu_rate(int32_t op, int32_t waves_per_simd, uint32_t iters,
                        double *lane_ops_per_s, float *kernel_ms) {
   g_err.clear();
   if (!lane_ops_per_s) return fail(MG_EINVAL, "lane_ops_per_s is NULL");
-  if (op < MG_VALU_FMA_F32 || op > MG_VALU_ADD_U32) return fail(MG_EINVAL, "unknown op %d", op);
+  if (op < MG_VALU_FMA_F32 || op > MG_VALU_LOG_F32) return fail(MG_EINVAL, "unknown op %d", op);
   if (waves_per_simd < 1 || waves_per_simd > 8)
     return fail(MG_EINVAL, "waves_per_simd must be in 1 .. 8");
   if (iters < 1 || iters > (1u << 20)) return fail(MG_EINVAL, "iters must be in 1 .. 2^20");

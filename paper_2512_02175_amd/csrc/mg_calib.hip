@@ -99,6 +99,22 @@ __global__ __launch_bounds__(kBlock) void k_valu_rate(uint32_t iters, uint32_t s
 #pragma unroll
     for (int i = 0; i < kChains; ++i) r ^= a[i];
     out[tid] = r;
+  } else if constexpr (OP == MG_VALU_LOG_F32) {
+    // the transcendental unit's v_log_f32 (base 2), as Box-Muller uses it;
+    // chains that leave the positive range run on NaN at the same rate
+    float a[kChains];
+#pragma unroll
+    for (int i = 0; i < kChains; ++i) a[i] = 1.5f + (float)(s + i) * 0x1p-32f;
+    for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int i = 0; i < kChains; ++i) a[i] = __builtin_amdgcn_logf(a[i]);
+    }
+    float r = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kChains; ++i) r += a[i];
+    out[tid] = __float_as_uint(r);
   } else {
     // 32-bit integer add (of a neighbouring chain, so no loop folds)
     uint32_t a[kChains];
@@ -138,6 +154,7 @@ hipError_t launch_valu_rate(int32_t op, uint32_t blocks, uint32_t iters, uint32_
     case MG_VALU_FMA_F64: return launch<MG_VALU_FMA_F64>(blocks, iters, out, st);
     case MG_VALU_MAD_U64_U32: return launch<MG_VALU_MAD_U64_U32>(blocks, iters, out, st);
     case MG_VALU_BITOP3: return launch<MG_VALU_BITOP3>(blocks, iters, out, st);
+    case MG_VALU_LOG_F32: return launch<MG_VALU_LOG_F32>(blocks, iters, out, st);
     default: return launch<MG_VALU_ADD_U32>(blocks, iters, out, st);
   }
 }

@@ -225,7 +225,7 @@ def test_struct_layouts_match_the_header(B, tmp_path):
             assert got[(name, f[0])] == getattr(cls, f[0]).offset, (name, f[0])
 
 
-@pytest.mark.parametrize("args", [(5, 8, 16), (-1, 8, 16), (0, 0, 16), (0, 9, 16), (0, 8, 0),
+@pytest.mark.parametrize("args", [(6, 8, 16), (-1, 8, 16), (0, 0, 16), (0, 9, 16), (0, 8, 0),
                                   (0, 8, (1 << 20) + 1)])
 def test_valu_rate_arguments_checked(B, args):
     """The VALU calibration refuses an unknown instruction kind and counts out

@@ -19,7 +19,7 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("op", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("op", [0, 1, 2, 3, 4, 5])
 def test_valu_rate_runs_below_the_issue_ceiling(B, op):
     print(f"valu rate: op={op}", flush=True)
     rate, ms = B.mg_valu_rate(op, 8, 4096)
