@@ -387,11 +387,16 @@ int64_t mg_particles_step(const mg_particles *p);
 
 /*
  * Batch of independent particle sets (possibly on different graphs) that
- * mg_batch_simulate advances in one launch per steps_per_launch chunk.  All
- * sets must have the same precision and the same max_splits; each keeps its
- * own graph_tag, counters and step counter, and every set's results equal
- * those of mg_simulate on that set alone.  The batch references the sets,
- * which must outlive it; it launches on the first set's stream.
+ * mg_batch_simulate advances in one launch per steps_per_launch chunk and
+ * LDS group: mg_batch_create groups the sets by the kernel occupancy that
+ * their graphs' per-block exit counters (and staged tables) leave, so that
+ * small graphs do not run at the occupancy of the largest one; a group
+ * with under 1/32 of the particles joins the next group of larger need.
+ * All sets must have the same precision, max_splits, trace flag and
+ * schedule; each keeps its own graph_tag, counters and step counter, and
+ * every set's results equal those of mg_simulate on that set alone.  The
+ * batch references the sets, which must outlive it; it launches on the
+ * first set's stream.
  */
 mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **out);
 mg_status mg_batch_simulate(mg_batch *b, int64_t n_steps, double dt, uint64_t seed);

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -196,16 +197,25 @@ struct mg_particles {
   mutable bool hist_tiled = false;
 };
 
+// Sets of a batch whose LDS needs (exit counters, staged tables) keep the
+// same number of blocks resident: one launch per group per chunk, each with
+// the LDS plan of its own largest graph, so small graphs do not run at the
+// occupancy that the largest graph of the batch leaves.
+struct BatchGroup {
+  int32_t first = 0, count = 0;  // its items in d_items
+  int32_t max_nnz = 0;
+  int32_t max_stage = 0;  // staged table bytes, 0: tables read from global memory
+};
+
 struct mg_batch {
   std::vector<mg_particles *> sets;
-  void *dev = nullptr;  // GraphDev[n] + SetDev[n] + BatchItem[items] + item counter
+  void *dev = nullptr;  // GraphDev[n] + SetDev[n] + BatchItem[items] + item counters
   GraphDev *d_graphs = nullptr;
   SetDev *d_sets = nullptr;
   BatchItem *d_items = nullptr;
-  uint32_t *d_claim = nullptr;  // item counter of the persistent pool launch
+  uint32_t *d_claim = nullptr;  // item counters of the persistent launches, one per group
   int32_t n_items = 0;
-  int32_t max_nnz = 0;
-  int32_t max_stage = 0;  // staged table bytes if every set's graph fits, else 0
+  std::vector<BatchGroup> groups;
   bool gen = false;       // some set's graph has a general method variant
   int32_t gen_level = 0;  // the highest method-variant level of its graphs
   int32_t kernel = 1;     // FP32 schedule fixed at creation (tile size follows it)
@@ -1351,30 +1361,76 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
   mg_batch *b = new mg_batch();
   b->sets.assign(sets, sets + n_sets);
   b->kernel = fp32_kernel(sets[0]);
-  std::vector<BatchItem> items;
-  bool all_stage = true;
-  const int32_t tile = batch_tile(sets[0]->prec == MG_FP64, fp32_kernel(sets[0]));
+  const bool fp64 = sets[0]->prec == MG_FP64;
+  const bool trace = sets[0]->trace;
   for (int32_t i = 0; i < n_sets; ++i) {
-    for (int64_t f = 0; f < sets[i]->n; f += tile) items.push_back({i, (uint32_t)f});
-    b->max_nnz = std::max(b->max_nnz, sets[i]->g->nnz);
-    const GraphDev &gd = sets[i]->g->gd;
-    const int32_t st = sets[i]->prec == MG_FP64 ? gd.stage_bytes64 : gd.stage_bytes32;
-    all_stage = all_stage && st > 0;
-    b->max_stage = std::max(b->max_stage, st);
     b->gen = b->gen || sets[i]->g->gen;
     b->gen_level = std::max(b->gen_level, sets[i]->g->gd.gen);
   }
-  if (!all_stage) b->max_stage = 0;
-  // Largest sets first so the tail of the launch is made of small tiles.
-  std::stable_sort(items.begin(), items.end(), [&](const BatchItem &x, const BatchItem &y) {
-    return sets[x.set]->n > sets[y.set]->n;
-  });
+  // Group the sets by the blocks per CU that their exit counters leave
+  // resident (the tables are staged within a group only where that costs
+  // no occupancy); a group with under 1/32 of the particles joins the next
+  // group of larger LDS need, whose plan covers it.
+  StepArgs qa{};
+  qa.kernel = b->kernel;
+  std::vector<int32_t> occ(n_sets);
+  int64_t total_n = 0;
+  for (int32_t i = 0; i < n_sets; ++i) {
+    occ[i] = batch_blocks_per_cu(sets[i]->g->nnz, 0, qa, fp64, trace, b->gen_level, nullptr);
+    total_n += sets[i]->n;
+  }
+  std::vector<int32_t> classes(occ);
+  std::sort(classes.begin(), classes.end(), std::greater<int32_t>());
+  classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+  std::vector<std::vector<int32_t>> members(classes.size());
+  for (int32_t i = 0; i < n_sets; ++i)
+    members[std::find(classes.begin(), classes.end(), occ[i]) - classes.begin()].push_back(i);
+  for (size_t c = 0; c + 1 < members.size(); ++c) {
+    int64_t nc = 0;
+    for (int32_t i : members[c]) nc += sets[i]->n;
+    if (nc * 32 < total_n) {
+      members[c + 1].insert(members[c + 1].end(), members[c].begin(), members[c].end());
+      members[c].clear();
+    }
+  }
+  std::vector<BatchItem> items;
+  const int32_t tile = batch_tile(fp64, fp32_kernel(sets[0]));
+  for (const std::vector<int32_t> &mem : members) {
+    if (mem.empty()) continue;
+    BatchGroup grp;
+    grp.first = (int32_t)items.size();
+    bool all_stage = true;
+    int32_t max_stage = 0;
+    for (int32_t i : mem) {
+      for (int64_t f = 0; f < sets[i]->n; f += tile) items.push_back({i, (uint32_t)f});
+      grp.max_nnz = std::max(grp.max_nnz, sets[i]->g->nnz);
+      const GraphDev &gd = sets[i]->g->gd;
+      const int32_t st = fp64 ? gd.stage_bytes64 : gd.stage_bytes32;
+      all_stage = all_stage && st > 0;
+      max_stage = std::max(max_stage, st);
+    }
+    if (all_stage && max_stage > 0) {
+      bool staged = false;
+      const int32_t with = batch_blocks_per_cu(grp.max_nnz, max_stage, qa, fp64, trace,
+                                               b->gen_level, &staged);
+      const int32_t without =
+          batch_blocks_per_cu(grp.max_nnz, 0, qa, fp64, trace, b->gen_level, nullptr);
+      if (staged && with >= without) grp.max_stage = max_stage;
+    }
+    grp.count = (int32_t)items.size() - grp.first;
+    // largest sets first, so that each launch ends with small tiles
+    std::stable_sort(items.begin() + grp.first, items.end(),
+                     [&](const BatchItem &x, const BatchItem &y) {
+                       return sets[x.set]->n > sets[y.set]->n;
+                     });
+    b->groups.push_back(grp);
+  }
   b->n_items = (int32_t)items.size();
   const size_t og = 0;
   const size_t os = align_up(sizeof(GraphDev) * n_sets, 256);
   const size_t oi = align_up(os + sizeof(SetDev) * n_sets, 256);
   const size_t oc = align_up(oi + sizeof(BatchItem) * items.size(), 256);
-  const size_t total = oc + 256;
+  const size_t total = oc + align_up(sizeof(uint32_t) * b->groups.size(), 256);
   hipError_t he = hipMalloc(&b->dev, total);
   if (he != hipSuccess) {
     delete b;
@@ -1409,12 +1465,57 @@ static void drop_graph(mg_batch *b) {
   b->key_steps = -1;
 }
 
-// Kernel nodes of one call: one launch per chunk of steps, chained.
+// Kernel nodes of one call: per chunk of steps, one launch per group (each
+// persistent launch after a node that clears its counters), all chained.
+static hipError_t add_group_launch(mg_batch *b, size_t gi, const StepArgs &a0,
+                                   hipGraphNode_t &prev) {
+  const BatchGroup &grp = b->groups[gi];
+  mg_particles *p0 = b->sets[0];
+  StepArgs a = a0;
+  a.batch_items = (uint32_t)grp.count;
+  a.batch_claim = b->d_claim + gi;
+  const KernelLaunch k = batch_launch(grp.count, grp.max_nnz, grp.max_stage, a,
+                                      p0->prec == MG_FP64, p0->trace, b->key_obs, b->gen_level);
+  const GraphDev *g = b->d_graphs;
+  const SetDev *sd = b->d_sets;
+  const BatchItem *it = b->d_items + grp.first;
+  hipError_t he = hipSuccess;
+  if (k.persistent) {
+    // the sets' particle counters and the group's item counter start at
+    // zero (no other group's launch runs meanwhile: the nodes are chained)
+    int32_t n_sets = (int32_t)b->sets.size();
+    uint32_t *claim = a.batch_claim;
+    void *rargs[] = {(void *)&sd, (void *)&n_sets, (void *)&claim};
+    hipKernelNodeParams rp{};
+    rp.func = (void *)batch_reset_kernel();
+    rp.gridDim = dim3((unsigned)((n_sets + 255) / 256));
+    rp.blockDim = dim3(256);
+    rp.sharedMemBytes = 0;
+    rp.kernelParams = rargs;
+    rp.extra = nullptr;
+    hipGraphNode_t rnode;
+    he = hipGraphAddKernelNode(&rnode, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &rp);
+    if (he != hipSuccess) return he;
+    prev = rnode;
+  }
+  void *args[] = {(void *)&g, (void *)&sd, (void *)&it, (void *)&a};
+  hipKernelNodeParams np{};
+  np.func = (void *)k.func;
+  np.gridDim = k.grid;
+  np.blockDim = k.block;
+  np.sharedMemBytes = (unsigned)k.shm;
+  np.kernelParams = args;
+  np.extra = nullptr;
+  hipGraphNode_t node;
+  he = hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+  if (he == hipSuccess) prev = node;
+  return he;
+}
+
 static hipError_t build_graph(mg_batch *b, int64_t n_steps, const StepArgs &base,
                               uint32_t chunk) {
   hipError_t he = hipGraphCreate(&b->graph, 0);
   if (he != hipSuccess) return he;
-  mg_particles *p0 = b->sets[0];
   hipGraphNode_t prev = nullptr;
   uint32_t done = 0;
   int64_t left = n_steps;
@@ -1422,41 +1523,8 @@ static hipError_t build_graph(mg_batch *b, int64_t n_steps, const StepArgs &base
     StepArgs a = base;
     a.nsteps = (uint32_t)std::min<int64_t>(left, chunk);
     a.n0_offset = done;
-    a.batch_items = (uint32_t)b->n_items;
-    a.batch_claim = b->d_claim;
-    const KernelLaunch k = batch_launch(b->n_items, b->max_nnz, b->max_stage, a,
-                                        p0->prec == MG_FP64, p0->trace, b->key_obs, b->gen_level);
-    const GraphDev *g = b->d_graphs;
-    const SetDev *sd = b->d_sets;
-    const BatchItem *it = b->d_items;
-    if (k.persistent) {
-      // the sets' particle counters and the item counter start at zero
-      int32_t n_sets = (int32_t)b->sets.size();
-      uint32_t *claim = b->d_claim;
-      void *rargs[] = {(void *)&sd, (void *)&n_sets, (void *)&claim};
-      hipKernelNodeParams rp{};
-      rp.func = (void *)batch_reset_kernel();
-      rp.gridDim = dim3((unsigned)((n_sets + 255) / 256));
-      rp.blockDim = dim3(256);
-      rp.sharedMemBytes = 0;
-      rp.kernelParams = rargs;
-      rp.extra = nullptr;
-      hipGraphNode_t rnode;
-      he = hipGraphAddKernelNode(&rnode, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &rp);
-      if (he != hipSuccess) break;
-      prev = rnode;
-    }
-    void *args[] = {(void *)&g, (void *)&sd, (void *)&it, (void *)&a};
-    hipKernelNodeParams np{};
-    np.func = (void *)k.func;
-    np.gridDim = k.grid;
-    np.blockDim = k.block;
-    np.sharedMemBytes = (unsigned)k.shm;
-    np.kernelParams = args;
-    np.extra = nullptr;
-    hipGraphNode_t node;
-    he = hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &np);
-    prev = node;
+    for (size_t gi = 0; gi < b->groups.size() && he == hipSuccess; ++gi)
+      he = add_group_launch(b, gi, a, prev);
     done += a.nsteps;
     left -= a.nsteps;
   }

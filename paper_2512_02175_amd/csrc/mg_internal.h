@@ -246,6 +246,11 @@ struct KernelLaunch {
 const void *batch_reset_kernel();
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
                           const StepArgs &a, bool fp64, bool trace, bool obs, int32_t gen);
+// Blocks per CU that a batch launch over graphs with at most max_nnz exit
+// slots and max_stage staged table bytes keeps resident (the occupancy of
+// its LDS plan), and whether that plan stages the tables.
+int32_t batch_blocks_per_cu(int32_t max_nnz, int32_t max_stage, const StepArgs &a, bool fp64,
+                            bool trace, int32_t gen, bool *staged);
 // tiled: edge-range LDS tiles when E * nb exceeds one LDS copy (else 64-bit
 // global atomics); below that size both take the single LDS copy.
 hipError_t launch_histogram(const GraphDev &g, const SetDev &s, int32_t nb,

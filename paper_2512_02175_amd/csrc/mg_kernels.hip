@@ -2450,6 +2450,22 @@ hipError_t launch_step(const GraphDev &g, const SetDev &s, const StepArgs &a,
 
 const void *batch_reset_kernel() { return (const void *)k_batch_reset; }
 
+int32_t batch_blocks_per_cu(int32_t max_nnz, int32_t max_stage, const StepArgs &a, bool fp64,
+                            bool trace, int32_t gen, bool *staged) {
+  const KernelLaunch k = batch_launch(1, max_nnz, max_stage, a, fp64, trace, false, gen);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k.func, kBlock, k.shm) !=
+          hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  if (staged) {
+    // the plan stages the tables when their bytes are part of its LDS
+    const KernelLaunch k0 = batch_launch(1, max_nnz, 0, a, fp64, trace, false, gen);
+    *staged = max_stage > 0 && k.shm > k0.shm;
+  }
+  return per_cu;
+}
+
 int32_t batch_tile(bool fp64, int32_t kernel) {
   return (!fp64 && kernel >= 1) ? pool_per_wave(kernel) * kWavesPerBlock * kBatchGens : kBlock;
 }

@@ -505,3 +505,36 @@ def test_tuning_file_outlives_the_graph(B, monkeypatch, tmp_path):
     ra, rb = B.mg_particles_read(p2), B.mg_particles_read(lanes)
     for f in ra:
         assert np.array_equal(ra[f], rb[f]), f
+
+
+def test_batch_groups_by_lds_need_equal_individual_runs(B):
+    """A batch whose graphs need very different LDS (a 3000-edge star's 6000
+    exit slots against small stars and a tree) runs one launch per
+    occupancy group; every set still equals its run alone, in both
+    precisions, across two calls and a launch chunk."""
+    rng = np.random.default_rng(11)
+    big = workloads.star_graph(3000, rng.uniform(0.2, 2.0, size=3000))
+    graphs = [big, workloads.config2()[0], workloads.random_tree(25, rng, quadratic=True),
+              workloads.star_graph(5, [0.3, 0.5, 0.2, 0.8, 0.4])]
+    counts = [40_000, 30_000, 20_000, 9_000]
+    for prec in (0, 1):
+        print(f"lds groups: precision={prec}", flush=True)
+        sets_b, sets_a = [], []
+        for i, (g, n) in enumerate(zip(graphs, counts)):
+            G = B.mg_graph_create(g)
+            kw = dict(init_seed=i + 3, precision=prec, graph_tag=i, trace=True,
+                      steps_per_launch=150)
+            sets_b.append(B.mg_particles_init(G, n, 2, **kw))
+            sets_a.append(B.mg_particles_init(G, n, 2, **kw))
+        b = B.mg_batch_create(sets_b)
+        B.mg_batch_simulate(b, 240, 5e-3, 31)
+        B.mg_batch_simulate(b, 160, 5e-3, 31)
+        for pa in sets_a:
+            B.mg_simulate(pa, 400, 5e-3, 31)
+        for pa, pb in zip(sets_a, sets_b):
+            ra, rb = B.mg_particles_read(pa, trace=True), B.mg_particles_read(pb, trace=True)
+            for f in ("edge", "x", "alive", "seqhash", "hits"):
+                assert np.array_equal(ra[f], rb[f]), (prec, f)
+            for x, y in zip(B.mg_exit_counts(pa), B.mg_exit_counts(pb)):
+                assert np.array_equal(x, y), prec
+            assert int(B.mg_exit_counts(pb)[2][2]) > 0
