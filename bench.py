@@ -53,7 +53,7 @@ ALG_FP32_CUBIC = 10.0
 # HBM bytes per k_pool32 launch on this workload from the FETCH_SIZE and
 # WRITE_SIZE counter passes (scaled by a 1 GiB copy), valid for the kernel
 # source whose sha256 prefix is given; reported as null for any other build.
-TRAFFIC = {"kernel_sha256": "1393a8e72afd0038", "bytes_per_launch": 334.1e6}
+TRAFFIC = {"kernel_sha256": "026c390e53df4f3b", "bytes_per_launch": 334.1e6}
 
 
 def kernel_traffic():
@@ -190,8 +190,8 @@ def batch_leg(B, torch):
     """The batched form on the default line: 512 independent uneven graphs
     (stars and random recursive trees, 3..4096 edges, 1e4..1e6 particles
     each, half with quadratic potentials), 1000 steps of dt 1e-3 in FP32,
-    one batched launch against one launch per graph; the batched kernel's
-    roofline fraction from its HIP-event time."""
+    one batched call (a launch per LDS group) against one launch per graph;
+    the batched call's roofline fraction from its HIP-event time."""
     import numpy as np
     import workloads
     graphs, counts, run = workloads.config4()
@@ -233,7 +233,7 @@ def batch_leg(B, torch):
     wall_solo = time.perf_counter() - t1
     return {"workload": "batch512: 512 stars/random trees, 3..4096 edges, 1e4..1e6 particles "
                         "each, zero drift or quadratic potentials, dt=1e-3, 1000 steps, FP32, "
-                        "one batched launch",
+                        "one batched call (a launch per LDS group)",
             "n_particles": int(sum(counts)), "value": float(tot[1]) / wall,
             "kernel_substeps_per_s": float(tot[1]) / k,
             "unbatched_value": float(tot[1]) / wall_solo, "batch_speedup": wall_solo / wall,
@@ -370,7 +370,8 @@ def run_vascular(args, B, torch):
 def run_batch(args, B, torch):
     """512 independent uneven graphs (stars and random trees, edges
     loguniform 3..4096, particles loguniform 1e4..1e6, half with quadratic
-    potentials): one batched launch per call against one launch per graph."""
+    potentials): one batched call (a launch per LDS group) against one launch
+    per graph."""
     import numpy as np
     import workloads
     graphs, counts, run = workloads.config4()
@@ -433,7 +434,8 @@ def run_batch(args, B, torch):
             "data": "synthetic",
             "config": {"workload": "batch512: 512 stars/random trees, 3..4096 edges, 1e4..1e6 "
                                    "particles each, zero drift or quadratic potentials, dt=1e-3, "
-                                   "1000 steps per call, one batched launch",
+                                   "1000 steps per call, one batched call (a launch per "
+                                   "LDS group)",
                        "n_graphs": len(graphs), "n_particles": int(sum(counts)),
                        "n_edges": int(sum(g.n_edges for g in graphs))},
             "unbatched_value": float(tot[1]) / args.steps / wall_solo,
