@@ -18,8 +18,8 @@
  *   - Corollary 1 (Sec. 3): the edge a particle leaves a vertex on is the
  *     exit that the exit counts record;
  *   - the uniform-bin histogram of the appendix kernels (A.6).
- * Readings where the paper is silent or garbled are listed in the design doc
- * ("Readings of the paper"); each one is named where it is applied below.
+ * Where the paper is silent or garbled, the reading taken is stated where
+ * it is applied below.
  *
  * Floating point: FP64, compiled with -ffp-contract=off; every fused
  * multiply-add is written as fma().  log/sqrt/cos/sin come from libm.
@@ -216,7 +216,7 @@ static double sigma_at(const or_graph *g, int32_t e, double x) {
 }
 
 /*
- * Integer slot thresholds (reading: slot draw, A10 in the design doc).  Per
+ * Integer slot thresholds (the reading of the slot draw).  Per
  * vertex, b is divided by its sum, accumulated left to right in FP64 into
  * C_s, and T_s = floor(C_s * 2^32).  From the last slot with b > 0 onward
  * T_s = 2^32, so a trailing zero-probability slot is never drawn.  The slot
