@@ -39,7 +39,13 @@ PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 # multiply, select) = 2.
 ALG_FP32_STEP = 27.5
 ALG_FP32_HIT = 80.0      # per vertex hit: Philox, one normal, root, time, slot, edge
-ALG_FP64_STEP = 62.5
+# FP64 particle-step: 1/4 Philox = 10; 1/2 Box-Muller pair (2 converts and
+# 2 scalings of the uniforms; the logarithm by range reduction and the atanh
+# series, 34; the factor -2, 1; the square root, 9; the angle, 1; sine and
+# cosine by quarter-turn reduction and two polynomials, 27; 2 multiplies) =
+# 39; the first sub-step (2 fma, 2 compares, 2 selects of 64-bit values) =
+# 8.5.
+ALG_FP64_STEP = 57.5
 ALG_FP64_HIT = 130.0
 # cubic drift and diffusion: two Horner steps more for mu and three for
 # sigma at every sub-step start (a step, or a restart from a vertex)
