@@ -218,7 +218,7 @@ struct mg_batch {
   std::vector<BatchGroup> groups;
   bool gen = false;       // some set's graph has a general method variant
   int32_t gen_level = 0;  // the highest method-variant level of its graphs
-  int32_t kernel = 1;     // FP32 schedule fixed at creation (tile size follows it)
+  int32_t kernel = 1;     // step schedule fixed at creation (tile size follows it)
   // Per-call set descriptors go up from pinned memory; the launch chain of a
   // call is a HIP graph of kernel nodes, re-instantiated only when the
   // call's shape (steps, dt, seed, schedule) changes.
@@ -1347,7 +1347,7 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
     if (sets[i]->prec != sets[0]->prec) return fail(MG_EINVAL, "sets differ in precision");
     if (sets[i]->max_splits != sets[0]->max_splits) return fail(MG_EINVAL, "sets differ in max_splits");
     if (sets[i]->trace != sets[0]->trace) return fail(MG_EINVAL, "sets differ in trace");
-    if (fp32_kernel(sets[i]) != fp32_kernel(sets[0]))
+    if (step_kernel(sets[i]) != step_kernel(sets[0]))
       return fail(MG_EINVAL, "sets differ in schedule");
     // the FP32 general step (cubic coefficients, Wentzell vertices)
     // evaluates the coefficients at the position, the affine one uses
@@ -1360,7 +1360,7 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
   }
   mg_batch *b = new mg_batch();
   b->sets.assign(sets, sets + n_sets);
-  b->kernel = fp32_kernel(sets[0]);
+  b->kernel = step_kernel(sets[0]);
   const bool fp64 = sets[0]->prec == MG_FP64;
   const bool trace = sets[0]->trace;
   for (int32_t i = 0; i < n_sets; ++i) {
@@ -1394,7 +1394,7 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
     }
   }
   std::vector<BatchItem> items;
-  const int32_t tile = batch_tile(fp64, fp32_kernel(sets[0]));
+  const int32_t tile = batch_tile(fp64, b->kernel);
   for (const std::vector<int32_t> &mem : members) {
     if (mem.empty()) continue;
     BatchGroup grp;

@@ -2016,9 +2016,42 @@ void k_pool32_batch(const GraphDev *graphs, const SetDev *sets, const BatchItem 
   }
 }
 
+// The same over FP64 sets: FP64 wave pools (128 per wave, 8-step windows).
+template <bool TRACE, bool LDS, bool STAGED, bool OBS, int GEN = 0>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MG_POOL64_WAVES_PER_EU)))
+void k_pool64_batch(const GraphDev *graphs, const SetDev *sets, const BatchItem *items,
+                    StepArgs A) {
+  extern __shared__ uint4 smem4[];
+  __shared__ unsigned long long s_tot[4];
+  __shared__ int32_t s_set;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const uint32_t i = atomicAdd(A.batch_claim, 1u);
+      int32_t set = -1;  // -1: no items left
+      if (i < A.batch_items) {
+        set = items[i].set;
+        const SetDev &Si = sets[set];
+        if (__hip_atomic_load(Si.work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= Si.n)
+          set = -2;  // that set has run out
+      }
+      s_set = set;
+    }
+    __syncthreads();
+    const int32_t set = s_set;
+    __syncthreads();  // every thread has read s_set before thread 0 writes it again
+    if (set == -1) break;
+    if (set < 0) continue;
+    SetDev S = sets[set];
+    S.n0 += A.n0_offset;
+    const GraphDev G = graphs[set];
+    pool_block<true, TRACE, LDS, STAGED, OBS, kPoolSmall, 2, GEN>(G, S, A, s_tot,
+                                                                  (char *)smem4);
+  }
+}
+
 // Clears the particle counters of a batch's sets and its item counter
-// before a launch of k_pool32_batch (a kernel, so that the launch chain can
-// be a HIP graph of kernel nodes).
+// before a launch of k_pool32_batch or k_pool64_batch (a kernel, so that the
+// launch chain can be a HIP graph of kernel nodes).
 __global__ void k_batch_reset(const SetDev *sets, int32_t n_sets, uint32_t *claim) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_sets) *sets[i].work = 0u;
@@ -2430,27 +2463,32 @@ KernelLaunch batch_launch_t(int32_t n_items, int32_t max_nnz, int32_t max_stage,
   k.grid = dim3(n_items);
   k.block = dim3(kBlock);
   k.persistent = false;
-  const bool pools = !FP64 && a.kernel >= 1 && (!gen || a.kernel == 3);
+  // FP32: the wave pools of the set's schedule (only pools of 128 with
+  // 8-step windows for the general levels); FP64: its wave pools
+  const bool pools = FP64 ? a.kernel == 3 : (a.kernel >= 1 && (!gen || a.kernel == 3));
   with_pool(a.kernel, [&](auto PWc, auto NGc) {
     constexpr int PW = decltype(PWc)::value, NG = decltype(NGc)::value;
-    const LdsPlan lp = plan_lds(max_nnz, max_stage,
-                                pools ? sizeof(PoolLds32<TRACE, PW>) * kWavesPerBlock : 0,
-                                nullptr, 0);
+    const size_t pool_bytes = FP64 ? sizeof(PoolLds64<TRACE, kPoolSmall>) * kWavesPerBlock
+                                   : sizeof(PoolLds32<TRACE, PW>) * kWavesPerBlock;
+    const LdsPlan lp = plan_lds(max_nnz, max_stage, pools ? pool_bytes : 0, nullptr, 0);
     k.shm = lp.shm;
     with_gen(gen, [&](auto Gn) {
       constexpr int gn = decltype(Gn)::value;
       with_flags([&](auto L, auto T, auto O) {
         constexpr bool l = decltype(L)::value, t = decltype(T)::value, o = decltype(O)::value;
-        if constexpr (!FP64)
-          if (pools) {
+        if (pools) {
+          if constexpr (FP64) {
+            k.func = (const void *)k_pool64_batch<TRACE, l, t, o, gn>;
+          } else {
             k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG>;
             if constexpr (PW == kPoolSmall && NG == 2 && gn != 0)
               k.func = (const void *)k_pool32_batch<TRACE, l, t, o, PW, NG, gn>;
-            // a resident grid takes the items from the batch's counter
-            k.persistent = true;
-            k.grid = dim3(resident_blocks(k.func, k.shm, (uint32_t)n_items));
-            return;
           }
+          // a resident grid takes the items from the batch's counter
+          k.persistent = true;
+          k.grid = dim3(resident_blocks(k.func, k.shm, (uint32_t)n_items));
+          return;
+        }
         k.func = (const void *)k_batch<FP64, TRACE, l, t, o, gn>;
       }, lp.lds_exit, lp.staged, obs);
     });
@@ -2501,7 +2539,8 @@ int32_t batch_blocks_per_cu(int32_t max_nnz, int32_t max_stage, const StepArgs &
 }
 
 int32_t batch_tile(bool fp64, int32_t kernel) {
-  return (!fp64 && kernel >= 1) ? pool_per_wave(kernel) * kWavesPerBlock * kBatchGens : kBlock;
+  const bool pools = fp64 ? kernel == 3 : kernel >= 1;
+  return pools ? pool_per_wave(kernel) * kWavesPerBlock * kBatchGens : kBlock;
 }
 
 KernelLaunch batch_launch(int32_t n_items, int32_t max_nnz, int32_t max_stage,
