@@ -204,7 +204,7 @@ void mg_graph_destroy(mg_graph *g);
  *                 run MG_SCHED_LANES or MG_SCHED_POOLS_W8 (FP64 wave pools
  *                 of 128 with 8-step windows, also the automatic choice;
  *                 MG_SCHED_POOLS and MG_SCHED_POOLS256 are refused), with
- *                 identical results; FP64 batches run the lane schedule.
+ *                 identical results, in mg_simulate and in batches.
  *                 On a graph with higher coefficient terms (mg_graph_desc)
  *                 FP32 sets accept only MG_SCHED_AUTO, MG_SCHED_LANES and
  *                 MG_SCHED_POOLS_W8.
