@@ -413,14 +413,21 @@ def run_batch(args, B, torch):
         s64 = make(B.MG_FP64)
         b64 = B.mg_batch_create(s64)
         B.mg_batch_simulate(b64, 8, run["dt"], run["seed"])
+        torch.cuda.synchronize()
+        t64_before = totals(s64)
+        t64 = time.perf_counter()
         for _ in range(args.steps):
             B.mg_batch_simulate(b64, run["n_steps"], run["dt"], run["seed"])
+        torch.cuda.synchronize()
+        wall64 = time.perf_counter() - t64
+        sub64 = float((totals(s64) - t64_before)[1])
         tv = ee = em = 0.0
         for g, a, c in zip(graphs, sets, s64):
             tv = max(tv, _tv(B.mg_histogram(a, run["bins"]), B.mg_histogram(c, run["bins"])))
             w, m = exit_err(B.mg_exit_counts(a)[0], B.mg_exit_counts(c)[0], g.vtx_offsets)
             ee, em = max(ee, w), max(em, m)
-        acc = {"tv_fp32_vs_fp64_max": tv, "exit_prob_err_fp32_vs_fp64_max": ee,
+        acc = {"fp64_value": sub64 / wall64, "fp32_speedup_over_fp64": value / (sub64 / wall64),
+               "tv_fp32_vs_fp64_max": tv, "exit_prob_err_fp32_vs_fp64_max": ee,
                "exit_prob_err_weighted_mean_max": em,
                "exit_err_min_exits_per_vertex": MIN_EXITS}
         del b64, s64
