@@ -90,6 +90,21 @@ static uint32_t drain_env() {
   const unsigned long long x = std::strtoull(v, &end, 10);
   return (end && *end == 0 && x >= 1 && x <= kDrainMax) ? (uint32_t)x : 0;
 }
+// Particle ids a wave of the pool kernels reserves from a set's counter at
+// a time, for launches of nsteps steps over sets of at most n_max
+// particles: about 2^15 particle-steps per reservation (64 ids from 512
+// steps on, up to 1024 for short launches, where the counter's atomic
+// would otherwise bound the launch), and small enough that the counter,
+// passed by at most one reservation per resident wave, cannot wrap.
+uint32_t claim_chunk(uint32_t nsteps, int64_t n_max) {
+  uint32_t r = 64;
+  while (r < 1024 && (uint64_t)r * nsteps < 32768) r *= 2;
+  const uint64_t waves = (uint64_t)kMaxPersistBlocks * (kBlock / 64);
+  const uint64_t room = (0xFFFFFFFFull - (uint64_t)n_max) / waves;
+  const uint32_t cap = (uint32_t)std::min<uint64_t>(room, 1024) & ~15u;
+  return std::max<uint32_t>(16u, std::min(r, cap));
+}
+
 void set_drain(StepArgs &a) {
   const uint32_t d = drain_env();
   a.drain = d ? d : kDrainMax;
@@ -215,6 +230,7 @@ struct mg_batch {
   BatchItem *d_items = nullptr;
   uint32_t *d_claim = nullptr;  // item counters of the persistent launches, one per group
   int32_t n_items = 0;
+  int64_t max_n = 0;  // particles of the largest set
   std::vector<BatchGroup> groups;
   bool gen = false;       // some set's graph has a general method variant
   int32_t gen_level = 0;  // the highest method-variant level of its graphs
@@ -1036,6 +1052,7 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
   while (left > 0) {
     const uint32_t now = (uint32_t)std::min<int64_t>(left, chunk);
     a.nsteps = now;
+    a.claim_chunk = claim_chunk(now, p->n);
     p->sd.n0 = (uint32_t)p->step;
     hipError_t he = launch_step(p->g->gd, p->sd, a, p->prec == MG_FP64, p->trace, p->stream);
     if (he != hipSuccess) return hip_fail(he, "launching the step kernel");
@@ -1366,26 +1383,33 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
   for (int32_t i = 0; i < n_sets; ++i) {
     b->gen = b->gen || sets[i]->g->gen;
     b->gen_level = std::max(b->gen_level, sets[i]->g->gd.gen);
+    b->max_n = std::max(b->max_n, sets[i]->n);
   }
   // Group the sets by the blocks per CU that their exit counters leave
   // resident (the tables are staged within a group only where that costs
-  // no occupancy); a group with under 1/32 of the particles joins the next
-  // group of larger LDS need, whose plan covers it.
+  // no occupancy), and apart from sets whose graphs have too many exit
+  // slots for LDS (a group counts exits in LDS only if all of its graphs
+  // can); a group with under 1/32 of the particles joins the next group of
+  // larger LDS need with the same exit counting, whose plan covers it.
   StepArgs qa{};
   qa.kernel = b->kernel;
-  std::vector<int32_t> occ(n_sets);
+  std::vector<std::pair<int32_t, int32_t>> key(n_sets);  // (global exits, -occupancy)
   int64_t total_n = 0;
   for (int32_t i = 0; i < n_sets; ++i) {
-    occ[i] = batch_blocks_per_cu(sets[i]->g->nnz, 0, qa, fp64, trace, b->gen_level, nullptr);
+    const int32_t nnz = sets[i]->g->nnz;
+    key[i] = {nnz > kLdsExitMax ? 1 : 0,
+              -batch_blocks_per_cu(nnz, 0, qa, fp64, trace, b->gen_level, nullptr)};
     total_n += sets[i]->n;
   }
-  std::vector<int32_t> classes(occ);
-  std::sort(classes.begin(), classes.end(), std::greater<int32_t>());
+  std::vector<std::pair<int32_t, int32_t>> classes(key);
+  std::sort(classes.begin(), classes.end());
   classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
   std::vector<std::vector<int32_t>> members(classes.size());
   for (int32_t i = 0; i < n_sets; ++i)
-    members[std::find(classes.begin(), classes.end(), occ[i]) - classes.begin()].push_back(i);
+    members[std::lower_bound(classes.begin(), classes.end(), key[i]) - classes.begin()]
+        .push_back(i);
   for (size_t c = 0; c + 1 < members.size(); ++c) {
+    if (classes[c + 1].first != classes[c].first) continue;
     int64_t nc = 0;
     for (int32_t i : members[c]) nc += sets[i]->n;
     if (nc * 32 < total_n) {
@@ -1522,6 +1546,7 @@ static hipError_t build_graph(mg_batch *b, int64_t n_steps, const StepArgs &base
   while (left > 0 && he == hipSuccess) {
     StepArgs a = base;
     a.nsteps = (uint32_t)std::min<int64_t>(left, chunk);
+    a.claim_chunk = claim_chunk(a.nsteps, b->max_n);
     a.n0_offset = done;
     for (size_t gi = 0; gi < b->groups.size() && he == hipSuccess; ++gi)
       he = add_group_launch(b, gi, a, prev);
@@ -1664,6 +1689,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   StepArgs a{};
   set_drain(a);
   a.nsteps = steps;
+  a.claim_chunk = claim_chunk(steps, n);
   a.max_splits = p->max_splits;
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
@@ -1712,6 +1738,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
     if (he == hipSuccess) he = hipEventRecord(e0, p->stream);
     for (uint32_t done = 0; done < 2 * steps && he == hipSuccess;) {
       a.nsteps = i == 0 ? 2 * steps : steps;
+      a.claim_chunk = claim_chunk(a.nsteps, n);
       sd.n0 = (uint32_t)p->step + done;
       he = launch_step(p->g->gd, sd, a, false, false, p->stream);
       done += a.nsteps;

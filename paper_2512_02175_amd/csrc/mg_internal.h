@@ -177,6 +177,8 @@ struct StepArgs {
   uint32_t drain_lds;  // and between moves of the block's u32 LDS exit and
                        // snapshot counters into the set's 64-bit ones
                        // (1 .. 2^20; tests lower it)
+  uint32_t claim_chunk;   // wave pools: particle ids a wave reserves from a
+                          // set's counter at a time (a multiple of 16)
   uint32_t batch_items;   // batched wave pools: work items (set indices)
   uint32_t *batch_claim;  // and the counter their resident grid takes them from
 };

@@ -1698,12 +1698,17 @@ __device__ __forceinline__ void drain_lds(uint32_t *lds, uint64_t *glob, int32_t
 // device-scope atomics on the set's counters, which go past the XCD's L2.
 
 // Where a wave's particles come from: the set's counter.  The grid stays
-// resident; every wave claims the next particle ids from the counter as its
-// home slots free up, so pools stay nearly full until the set runs out and
-// a launch ends with one short tail instead of one per block.  A wave that
-// finds the set run out stops claiming, so every wave passes n by at most
-// one claim of 64 per set and launch (a batched launch lets a block join a
-// set only while its counter is below n, so this holds there too).
+// resident; every wave reserves the next A.claim_chunk particle ids from the
+// counter (one atomic) and moves them into its pool as its home slots free
+// up, so pools stay nearly full until the set runs out and a launch ends
+// with one short tail instead of one per block.  The reservation is larger
+// for short launches (up to 1024 ids): the set's counter is one address
+// that every wave of the grid updates, and with 16 ids per update a
+// 100-step launch over 1e8 particles spent most of its time on it.  A wave
+// that finds the set run out stops reserving, so every wave passes n by at
+// most one reservation per set and launch (a batched launch lets a block
+// join a set only while its counter is below n, so this holds there too);
+// the host bounds the reservation so that the counter cannot wrap.
 // Q: the particle type (Particle32 or Particle64, each with its pool type
 // in LDS).
 template <bool TRACE, bool LDS, bool OBS, int PW, int NG, int GEN, class Q, class Pool>
@@ -1726,7 +1731,9 @@ __device__ void run_pool(const GView &G, int32_t n_edges, const SetDev &S,
   uint32_t f_head = 0, f_tail = K;
   for (uint32_t i = lane; i < K; i += 64u) P.freeq[i] = (uint8_t)i;
   const uint32_t lim = S.n;
-  bool exhausted = false;
+  bool exhausted = false;   // the reservation is used up and the set has run out
+  bool last_chunk = false;  // the set ran out with the current reservation
+  uint32_t res_next = 0, res_end = 0;  // the wave's reserved ids [res_next, res_end)
   uint32_t iter = 0, iter_lds = 0;
   wave_lds_fence();
 
@@ -1741,22 +1748,33 @@ __device__ void run_pool(const GView &G, int32_t n_edges, const SetDev &S,
       if (OBS && sink.lds) drain_lds(sink.lds, S.obs, A.obs_lds);
     }
     // Claim more particles: a wave takes as many ids as it has free home
-    // slots, in multiples of kClaimMin up to 64, so a pool refills while its
-    // first particles finish rather than after half of them have.  Claims
-    // stay multiples of kClaimMin, so every claim starts at a multiple of
-    // it: a claim's 128-byte lines of positions belong to one wave (its
+    // slots, in multiples of kClaimMin up to 64, from its reservation, so a
+    // pool refills while its first particles finish rather than after half
+    // of them have.  Reservations and claims stay multiples of kClaimMin
+    // (but for the last ids below n), so every claim starts at a multiple
+    // of it: a claim's 128-byte lines of positions belong to one wave (its
     // state words share a line with one neighbouring claim).
     while (!exhausted && f_tail - f_head >= (uint32_t)kClaimMin) {
-      const uint32_t want = min(64u, f_tail - f_head) & ~((uint32_t)kClaimMin - 1u);
-      uint32_t v = 0u;
-      if (lane == 0u) v = atomicAdd(S.work, want);
-      const uint32_t b = __builtin_amdgcn_readfirstlane(v);
-      if (b >= lim) {
-        exhausted = true;
-        break;
+      if (res_next == res_end) {
+        if (last_chunk) {
+          exhausted = true;
+          break;
+        }
+        uint32_t v = 0u;
+        if (lane == 0u) v = atomicAdd(S.work, A.claim_chunk);
+        const uint32_t b = __builtin_amdgcn_readfirstlane(v);
+        if (b >= lim) {
+          exhausted = true;
+          break;
+        }
+        last_chunk = lim - b <= A.claim_chunk;
+        res_next = b;
+        res_end = last_chunk ? lim : b + A.claim_chunk;
       }
-      if (b + want >= lim) exhausted = true;
-      const uint32_t id = b + lane;
+      const uint32_t want =
+          min(min(64u, f_tail - f_head) & ~((uint32_t)kClaimMin - 1u), res_end - res_next);
+      const uint32_t id = res_next + lane;
+      res_next += want;
       const bool mine = lane < want;
       const uint32_t hs = mine ? P.freeq[(f_head + lane) % K] : 0u;
       const bool ok = pool_claim<TRACE, PW, GEN>(G, S, n_edges, id, P, hs, mine && id < lim);
