@@ -91,14 +91,22 @@ static uint32_t drain_env() {
   return (end && *end == 0 && x >= 1 && x <= kDrainMax) ? (uint32_t)x : 0;
 }
 // Particle ids a wave of the pool kernels reserves from a set's counter at
-// a time, for launches of nsteps steps over sets of at most n_max
-// particles: about 2^15 particle-steps per reservation (64 ids from 512
-// steps on, up to 1024 for short launches, where the counter's atomic
-// would otherwise bound the launch), and small enough that the counter,
-// passed by at most one reservation per resident wave, cannot wrap.
-uint32_t claim_chunk(uint32_t nsteps, int64_t n_max) {
+// a time, for launches of nsteps steps over sets of about n_typ and at
+// most n_max particles.  Every reservation is one atomic on one address
+// (about 10 ns each, one after another), and a wave works through its
+// reservation alone: reservations of about 1.2e5 / nsteps ids keep the
+// atomics under a tenth of the launch's work (64 ids from 2048 steps on),
+// and at most about sqrt(0.43 n_typ) ids (the balance of the atomics
+// against one wave's work on a one-step launch) keep a small set's ids
+// spread over many waves; 64 <= ids <= 1024, a power of two, and small
+// enough that the counter, passed by at most one reservation per resident
+// wave, cannot wrap.
+uint32_t claim_chunk(uint32_t nsteps, int64_t n_typ, int64_t n_max) {
+  const double by_steps = 1.2e5 / (double)std::max<uint32_t>(nsteps, 1u);
+  const double by_n = std::sqrt(0.43 * (double)std::max<int64_t>(n_typ, 1));
+  const double want = std::min(by_steps, by_n);
   uint32_t r = 64;
-  while (r < 1024 && (uint64_t)r * nsteps < 32768) r *= 2;
+  while (r < 1024 && (double)r < want) r *= 2;
   const uint64_t waves = (uint64_t)kMaxPersistBlocks * (kBlock / 64);
   const uint64_t room = (0xFFFFFFFFull - (uint64_t)n_max) / waves;
   const uint32_t cap = (uint32_t)std::min<uint64_t>(room, 1024) & ~15u;
@@ -230,7 +238,8 @@ struct mg_batch {
   BatchItem *d_items = nullptr;
   uint32_t *d_claim = nullptr;  // item counters of the persistent launches, one per group
   int32_t n_items = 0;
-  int64_t max_n = 0;  // particles of the largest set
+  int64_t max_n = 0;   // particles of the largest set
+  int64_t mean_n = 0;  // and per set
   std::vector<BatchGroup> groups;
   bool gen = false;       // some set's graph has a general method variant
   int32_t gen_level = 0;  // the highest method-variant level of its graphs
@@ -1052,7 +1061,7 @@ mg_status mg_simulate(mg_particles *p, int64_t n_steps, double dt, uint64_t seed
   while (left > 0) {
     const uint32_t now = (uint32_t)std::min<int64_t>(left, chunk);
     a.nsteps = now;
-    a.claim_chunk = claim_chunk(now, p->n);
+    a.claim_chunk = claim_chunk(now, p->n, p->n);
     p->sd.n0 = (uint32_t)p->step;
     hipError_t he = launch_step(p->g->gd, p->sd, a, p->prec == MG_FP64, p->trace, p->stream);
     if (he != hipSuccess) return hip_fail(he, "launching the step kernel");
@@ -1384,7 +1393,9 @@ mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **
     b->gen = b->gen || sets[i]->g->gen;
     b->gen_level = std::max(b->gen_level, sets[i]->g->gd.gen);
     b->max_n = std::max(b->max_n, sets[i]->n);
+    b->mean_n += sets[i]->n;
   }
+  b->mean_n /= n_sets;
   // Group the sets by the blocks per CU that their exit counters leave
   // resident (the tables are staged within a group only where that costs
   // no occupancy), and apart from sets whose graphs have too many exit
@@ -1546,7 +1557,7 @@ static hipError_t build_graph(mg_batch *b, int64_t n_steps, const StepArgs &base
   while (left > 0 && he == hipSuccess) {
     StepArgs a = base;
     a.nsteps = (uint32_t)std::min<int64_t>(left, chunk);
-    a.claim_chunk = claim_chunk(a.nsteps, b->max_n);
+    a.claim_chunk = claim_chunk(a.nsteps, b->mean_n, b->max_n);
     a.n0_offset = done;
     for (size_t gi = 0; gi < b->groups.size() && he == hipSuccess; ++gi)
       he = add_group_launch(b, gi, a, prev);
@@ -1689,7 +1700,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
   StepArgs a{};
   set_drain(a);
   a.nsteps = steps;
-  a.claim_chunk = claim_chunk(steps, n);
+  a.claim_chunk = claim_chunk(steps, n, n);
   a.max_splits = p->max_splits;
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
@@ -1738,7 +1749,7 @@ mg_status mg_autotune(mg_particles *p, double dt, uint64_t seed, int32_t probe_s
     if (he == hipSuccess) he = hipEventRecord(e0, p->stream);
     for (uint32_t done = 0; done < 2 * steps && he == hipSuccess;) {
       a.nsteps = i == 0 ? 2 * steps : steps;
-      a.claim_chunk = claim_chunk(a.nsteps, n);
+      a.claim_chunk = claim_chunk(a.nsteps, n, n);
       sd.n0 = (uint32_t)p->step + done;
       he = launch_step(p->g->gd, sd, a, false, false, p->stream);
       done += a.nsteps;

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "mg_internal.h"
 
@@ -2103,19 +2104,43 @@ __global__ void k_clear_word(uint32_t *w) {
 // Blocks of a persistent launch: as many as stay resident at once (CUs x
 // blocks per CU for this kernel and LDS size), fewer if the set is small.
 uint32_t resident_blocks(const void *func, size_t shm, uint32_t need) {
-  // the current device's CU count (queried per launch: a host-side call of
-  // microseconds, and correct whichever device the caller has made current)
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus <= 0)
-    cus = 256;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kBlock, shm) != hipSuccess ||
-      per_cu <= 0)
-    per_cu = 1;
-  uint32_t r = (uint32_t)cus * (uint32_t)per_cu;
-  if (r > kMaxPersistBlocks) r = kMaxPersistBlocks;  // bounds the claim counter
+  // blocks per CU of (device, kernel, LDS bytes) times the device's CU
+  // count, queried once and kept: the occupancy query costs microseconds,
+  // which short launches would pay on every call
+  struct Entry {
+    int dev;
+    const void *func;
+    size_t shm;
+    uint32_t blocks;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  uint32_t r = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry &e : cache)
+      if (e.dev == dev && e.func == func && e.shm == shm) {
+        r = e.blocks;
+        break;
+      }
+  }
+  if (r == 0) {
+    int cus = 0;
+    if (dev < 0 ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kBlock, shm) != hipSuccess ||
+        per_cu <= 0)
+      per_cu = 1;
+    r = (uint32_t)cus * (uint32_t)per_cu;
+    if (r > kMaxPersistBlocks) r = kMaxPersistBlocks;  // bounds the claim counter
+    std::lock_guard<std::mutex> lock(mu);
+    if (cache.size() < 4096) cache.push_back({dev, func, shm, r});
+  }
   return need < r ? need : r;
 }
 
