@@ -538,3 +538,28 @@ def test_batch_groups_by_lds_need_equal_individual_runs(B):
             for x, y in zip(B.mg_exit_counts(pa), B.mg_exit_counts(pb)):
                 assert np.array_equal(x, y), prec
             assert int(B.mg_exit_counts(pb)[2][2]) > 0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pool_reservations_on_short_launches_equal_lanes(B, prec):
+    """Short launches make the pool waves reserve large chunks of particle
+    ids (up to 512 here) from the set's counter; on an odd set size, with
+    calls of 1, 5 and 100 steps, the pools still give the lane schedule's
+    bits in both precisions."""
+    g, _ = workloads.config2()
+    G = B.mg_graph_create(g)
+    n = 300_003
+    out = []
+    for sched in (B.MG_SCHED_LANES, B.MG_SCHED_POOLS_W8):
+        print(f"reservations: precision={prec} schedule={sched}", flush=True)
+        p = B.mg_particles_init(G, n, 2, init_seed=5, precision=prec, trace=True,
+                                schedule=sched)
+        for k in (1, 5, 100, 1, 5):
+            B.mg_simulate(p, k, 1e-2, 41)
+        out.append((B.mg_particles_read(p, trace=True), B.mg_exit_counts(p)))
+    (ra, ca), (rb, cb) = out
+    for f in ("edge", "x", "alive", "seqhash", "hits"):
+        assert np.array_equal(ra[f], rb[f]), f
+    for x, y in zip(ca, cb):
+        assert np.array_equal(x, y)
+    assert int(ca[2][3]) == n * 112
