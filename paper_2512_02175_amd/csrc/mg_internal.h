@@ -184,9 +184,10 @@ struct StepArgs {
 };
 
 // Largest particle set.  A persistent pool launch hands out particle ids
-// from a 32-bit counter; every wave overshoots it by at most one claim of
-// 64 ids, and a persistent grid has at most kMaxPersistBlocks blocks of four
-// waves, so the counter stays below n + 2^19 < 2^32 and ids below 2^32.
+// from a 32-bit counter; every wave overshoots it by at most one
+// reservation, a persistent grid has at most kMaxPersistBlocks blocks of
+// four waves, and the host caps a reservation at (2^32 - 1 - n) / 8192 ids
+// (at least 112 at this n), so the counter cannot wrap and ids stay below n.
 constexpr int64_t kMaxParticles = 0xFFFFFFFFll - 0xFFFFFll;  // 2^32 - 2^20
 constexpr uint32_t kMaxPersistBlocks = 2048;
 constexpr uint32_t kDrainMax = 1024;
