@@ -386,6 +386,63 @@ mg_status mg_particles_read(const mg_particles *p, int64_t first, int64_t count,
 int64_t mg_particles_step(const mg_particles *p);
 
 /*
+ * Checkpoint and resume.  The appendix's kernels leave every particle's
+ * state in global memory between launches; with counter-based draws that
+ * state and the step counter are all a later step depends on, so a set
+ * saved after k steps and loaded again continues exactly as the original
+ * would: the same states, counters and histograms, bit for bit, under any
+ * schedule.
+ *
+ * mg_particles_image_bytes: size of p's image (-1 if p is NULL).
+ *
+ * mg_particles_save writes the image into caller-owned HOST memory
+ * image[0 .. image_bytes) after every step queued on the set's stream has
+ * finished (it synchronises the stream).  The image is an mg_image_header
+ * (below) followed by, at 8-byte aligned offsets: the state words [n]
+ * (u32: edge | FP32 reference-end bit 30 | removed bit 31), positions [n]
+ * (FP64: f64 from the initial vertex; FP32: the (distance, compensation)
+ * float pair from the reference end), with trace the hashes [n] (u64) and
+ * hit counts [n] (u32), exit counts [nnz], absorbed counts [V], the four
+ * totals (u64 each), and the streamed histogram [E * bins] (u64) when it is
+ * on; all in the host's byte order.  Errors: MG_EINVAL for NULL arguments,
+ * a short or device buffer; MG_EDEVICE when the set's device error word is
+ * set (its state is not saved).
+ *
+ * mg_particles_load creates a new set on g from an image.  g must be a
+ * graph created from the same description (the header's fingerprint and
+ * sizes must match).  The image fixes precision, max_splits, graph_tag and
+ * trace (opt's values for them are ignored); opt gives the stream, arena,
+ * schedule and steps_per_launch (NULL: defaults).  Every particle is
+ * checked on the host as the step kernels would check it (edge in range, a
+ * finite position on the edge or owing a stay on a Wentzell end); a bad or
+ * truncated image returns MG_EINVAL and creates nothing.  The image stays
+ * the caller's.  Tuning results are not part of the image: an automatic
+ * FP32 schedule is tuned again (or read from the tuning file) on the first
+ * mg_simulate, which changes no result.
+ */
+typedef struct {
+  char magic[8];           /* "MGSETIMG" */
+  uint32_t version;        /* 1 */
+  uint32_t header_bytes;   /* sizeof(mg_image_header) = 96 */
+  uint64_t total_bytes;    /* the whole image */
+  uint64_t graph;          /* fingerprint of the graph's packed tables */
+  int64_t n;
+  int32_t n_vertices, n_edges, nnz;
+  int32_t precision, max_splits;
+  uint32_t graph_tag;
+  int32_t trace;
+  int32_t obs_bins;        /* streamed histogram: bins per edge, 0 when off */
+  uint64_t obs_every;      /* its period in steps */
+  uint64_t obs_start;      /* the step counter when it started */
+  uint64_t step;           /* the set's step counter */
+} mg_image_header;
+
+int64_t mg_particles_image_bytes(const mg_particles *p);
+mg_status mg_particles_save(const mg_particles *p, void *image, int64_t image_bytes);
+mg_status mg_particles_load(const mg_graph *g, const void *image, int64_t image_bytes,
+                            const mg_options *opt, mg_particles **out);
+
+/*
  * Batch of independent particle sets (possibly on different graphs) that
  * mg_batch_simulate advances in one launch per steps_per_launch chunk and
  * LDS group: mg_batch_create groups the sets by the kernel occupancy that

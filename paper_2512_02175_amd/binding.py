@@ -28,7 +28,8 @@ EXPORTED = (
     "mg_graph_create", "mg_graph_destroy", "mg_particles_arena_bytes",
     "mg_particles_init", "mg_particles_init_sources", "mg_particles_destroy", "mg_simulate",
     "mg_histogram",
-    "mg_exit_counts", "mg_particles_read", "mg_particles_step", "mg_batch_create",
+    "mg_exit_counts", "mg_particles_read", "mg_particles_step", "mg_particles_image_bytes",
+    "mg_particles_save", "mg_particles_load", "mg_batch_create",
     "mg_batch_simulate", "mg_batch_destroy", "mg_autotune", "mg_histogram_csr",
     "mg_histogram_csr_noalloc", "mg_observe_histogram",
     "mg_observed_histogram", "mg_density_l2", "mg_valu_rate", "mg_last_error",
@@ -72,6 +73,23 @@ class mg_tuning(C.Structure):
                 ("launch_ms", C.c_float * 2)]
 
 
+class mg_image_header(C.Structure):
+    _fields_ = [("magic", C.c_char * 8), ("version", C.c_uint32), ("header_bytes", C.c_uint32),
+                ("total_bytes", C.c_uint64), ("graph", C.c_uint64), ("n", C.c_int64),
+                ("n_vertices", C.c_int32), ("n_edges", C.c_int32), ("nnz", C.c_int32),
+                ("precision", C.c_int32), ("max_splits", C.c_int32),
+                ("graph_tag", C.c_uint32), ("trace", C.c_int32), ("obs_bins", C.c_int32),
+                ("obs_every", C.c_uint64), ("obs_start", C.c_uint64), ("step", C.c_uint64)]
+
+
+def image_header(image) -> mg_image_header:
+    """The header of a set image (a host byte array)."""
+    b = np.ascontiguousarray(image, np.uint8)
+    if b.size < C.sizeof(mg_image_header):
+        raise ValueError("image shorter than its header")
+    return mg_image_header.from_buffer_copy(b[:C.sizeof(mg_image_header)].tobytes())
+
+
 _lib = None
 
 
@@ -99,6 +117,10 @@ def lib() -> C.CDLL:
         L.mg_particles_read.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
         L.mg_particles_step.argtypes = [vp]
         L.mg_particles_step.restype = i64
+        L.mg_particles_image_bytes.argtypes = [vp]
+        L.mg_particles_image_bytes.restype = i64
+        L.mg_particles_save.argtypes = [vp, vp, i64]
+        L.mg_particles_load.argtypes = [vp, vp, i64, vp, vp]
         L.mg_batch_create.argtypes = [i32, vp, vp]
         L.mg_batch_simulate.argtypes = [vp, i64, C.c_double, u64]
         L.mg_batch_destroy.argtypes = [vp]
@@ -114,7 +136,8 @@ def lib() -> C.CDLL:
         for name in EXPORTED:
             if name not in ("mg_graph_destroy", "mg_particles_destroy",
                             "mg_batch_destroy", "mg_last_error",
-                            "mg_particles_arena_bytes", "mg_particles_step"):
+                            "mg_particles_arena_bytes", "mg_particles_step",
+                            "mg_particles_image_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -414,6 +437,31 @@ def mg_particles_read(p: Particles, first: int = 0, count: int | None = None, tr
 
 def mg_particles_step(p: Particles) -> int:
     return int(lib().mg_particles_step(p.handle))
+
+
+def mg_particles_image_bytes(p: Particles) -> int:
+    return int(lib().mg_particles_image_bytes(p.handle))
+
+
+def mg_particles_save(p: Particles) -> np.ndarray:
+    """The set's image (a host uint8 array) after every queued step."""
+    img = np.empty(mg_particles_image_bytes(p), np.uint8)
+    _check(lib().mg_particles_save(p.handle, _p(img), int(img.size)))
+    return img
+
+
+def mg_particles_load(g: Graph, image, *, steps_per_launch: int = 0, stream=None,
+                      schedule: int = MG_SCHED_AUTO) -> Particles:
+    """A new set on ``g`` from an image of mg_particles_save; precision,
+    max_splits, graph_tag and trace come from the image."""
+    img = np.ascontiguousarray(image, np.uint8)
+    o = _options(MG_FP64, 0, 0, False, steps_per_launch, stream, schedule=schedule)
+    h = C.c_void_p()
+    _check(lib().mg_particles_load(g.handle, _p(img), int(img.size), C.byref(o), C.byref(h)))
+    hd = image_header(img)
+    q = Particles(h, g, int(hd.n), int(hd.precision))
+    q.obs_bins = int(hd.obs_bins)
+    return q
 
 
 def mg_batch_create(sets) -> Batch:

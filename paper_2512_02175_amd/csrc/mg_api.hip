@@ -176,6 +176,8 @@ struct mg_graph {
   mutable std::vector<std::pair<double, mg_tuning>> tune_cache;
   std::vector<double> length;  // host copy for readback conversion
   std::vector<double> span;    // length binned by the uniform histograms
+  std::vector<int32_t> vinit_host, vterm_host;  // end vertices of each edge
+  std::vector<uint8_t> wentzell_host;           // [V] Wentzell vertex
   std::vector<VtxBlk> vtx_host;
   // semi-infinite edges (length +infinity): their terminal vertices are
   // the vertices at infinity, which no particle reaches
@@ -699,6 +701,11 @@ mg_status mg_graph_create(const mg_graph_desc *d, mg_graph **out) {
   g->E = E;
   g->nnz = nnz;
   g->length.assign(d->length, d->length + E);
+  g->vinit_host.assign(d->edge_init, d->edge_init + E);
+  g->vterm_host.assign(d->edge_term, d->edge_term + E);
+  g->wentzell_host.assign(V, 0);
+  for (int32_t v = 0; v < V; ++v)
+    g->wentzell_host[v] = d->vtx_kind && d->vtx_kind[v] == MG_VTX_WENTZELL;
   g->span = d->bin_span ? std::vector<double>(d->bin_span, d->bin_span + E) : g->length;
   g->vtx_host = vtx;
   g->infinite = infinite;
@@ -787,18 +794,10 @@ int64_t mg_particles_arena_bytes(const mg_graph *g, int64_t n, const mg_options 
   return (int64_t)set_layout(g->V, g->nnz, n, prec, trace).total;
 }
 
-// Mode 3 (internal): injection at source vertices.
-static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t *edge,
-                           const double *pos, int32_t vertex, int32_t n_src,
-                           const int32_t *src_v, const double *src_rate,
-                           uint64_t init_seed, const mg_options *opt, mg_particles **out) {
-  if (!out) return fail(MG_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (n < 1 || n > kMaxParticles) return fail(MG_EINVAL, "n must be in [1, 2^32 - 2^20]");
-  if (!g) return fail(MG_EINVAL, "graph is NULL");
-  mg_options o{};
-  o.precision = MG_FP64;
-  if (opt) o = *opt;
+// Options of a new set on g (NULL: defaults; opt may point to o), with
+// the defaults filled in and refused combinations reported.
+static mg_status set_options(const mg_graph *g, const mg_options *opt, mg_options &o) {
+  o = opt ? *opt : mg_options{};
   if (o.precision != MG_FP64 && o.precision != MG_FP32) return fail(MG_EINVAL, "unknown precision");
   if (o.max_splits < 0 || o.max_splits > 255)
     return fail(MG_EINVAL, "max_splits must be in [0, 255] (0: default)");
@@ -813,37 +812,14 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
   if (o.precision == MG_FP64 &&
       (o.schedule == MG_SCHED_POOLS || o.schedule == MG_SCHED_POOLS256))
     return fail(MG_EINVAL, "FP64 sets run MG_SCHED_LANES, MG_SCHED_POOLS_W8 or MG_SCHED_AUTO");
-  if (mode == MG_INIT_EXPLICIT) {
-    if (!edge || !pos) return fail(MG_EINVAL, "explicit init needs edge and pos");
-    for (int64_t i = 0; i < n; ++i) {
-      if (edge[i] < 0 || edge[i] >= g->E) return fail(MG_EINVAL, "particle %lld: edge out of range", (long long)i);
-      if (!(pos[i] >= 0.0 && pos[i] <= g->length[edge[i]]))
-        return fail(MG_EINVAL, "particle %lld: position outside [0, L]", (long long)i);
-    }
-  } else if (mode == MG_INIT_AT_VERTEX) {
-    if (vertex < 0 || vertex >= g->V) return fail(MG_EINVAL, "vertex out of range");
-    if (g->vtx_host[vertex].deg <= 0)
-      return fail(MG_EINVAL, "vertex %d is absorbing or isolated", vertex);
-    if (g->at_infinity[vertex]) return fail(MG_EINVAL, "vertex %d is at infinity", vertex);
-  } else if (mode == 3) {
-    if (n_src < 1 || !src_v || !src_rate) return fail(MG_EINVAL, "need at least one source");
-    double total = 0.0;
-    for (int32_t j = 0; j < n_src; ++j) {
-      const int32_t v = src_v[j];
-      if (v < 0 || v >= g->V) return fail(MG_EINVAL, "source %d: vertex out of range", j);
-      if (g->vtx_host[v].deg <= 0)
-        return fail(MG_EINVAL, "source %d: vertex %d is absorbing or isolated", j, v);
-      if (g->at_infinity[v]) return fail(MG_EINVAL, "source %d: vertex %d is at infinity", j, v);
-      if (!is_finite(src_rate[j]) || src_rate[j] < 0.0)
-        return fail(MG_EINVAL, "source %d: rate must be finite and >= 0", j);
-      total += src_rate[j];
-    }
-    if (!(total > 0.0)) return fail(MG_EINVAL, "the source rates sum to 0");
-  } else if (mode != MG_INIT_UNIFORM_LENGTH) {
-    return fail(MG_EINVAL, "unknown init mode");
-  } else if (g->infinite) {
-    return fail(MG_EINVAL, "uniform-by-length init needs finite edges");
-  }
+  return MG_OK;
+}
+
+// Allocates a set of n particles with options o (checked by set_options),
+// or places it in the caller's arena, and clears its counters on the set's
+// stream; the particle arrays are left for the caller to fill.
+static mg_status alloc_set(const mg_graph *g, int64_t n, const mg_options &o,
+                           mg_particles **out) {
   const SetLayout L = set_layout(g->V, g->nnz, n, o.precision, o.trace != 0);
   mg_particles *p = new mg_particles();
   p->g = g;
@@ -889,13 +865,68 @@ static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t
   s.n = (uint32_t)n;
   s.n0 = 0;
   s.tag = p->tag;
+  // counters start at zero (a kernel-free clear: the region is contiguous)
+  hipError_t he = hipMemsetAsync(base + L.exitc, 0, L.total - L.exitc, p->stream);
+  if (he != hipSuccess) {
+    mg_particles_destroy(p);
+    return hip_fail(he, "clearing the counters");
+  }
+  *out = p;
+  return MG_OK;
+}
+
+// Mode 3 (internal): injection at source vertices.
+static mg_status init_impl(const mg_graph *g, int64_t n, int mode, const int32_t *edge,
+                           const double *pos, int32_t vertex, int32_t n_src,
+                           const int32_t *src_v, const double *src_rate,
+                           uint64_t init_seed, const mg_options *opt, mg_particles **out) {
+  if (!out) return fail(MG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > kMaxParticles) return fail(MG_EINVAL, "n must be in [1, 2^32 - 2^20]");
+  if (!g) return fail(MG_EINVAL, "graph is NULL");
+  mg_options o;
+  mg_status ost = set_options(g, opt, o);
+  if (ost != MG_OK) return ost;
+  if (mode == MG_INIT_EXPLICIT) {
+    if (!edge || !pos) return fail(MG_EINVAL, "explicit init needs edge and pos");
+    for (int64_t i = 0; i < n; ++i) {
+      if (edge[i] < 0 || edge[i] >= g->E) return fail(MG_EINVAL, "particle %lld: edge out of range", (long long)i);
+      if (!(pos[i] >= 0.0 && pos[i] <= g->length[edge[i]]))
+        return fail(MG_EINVAL, "particle %lld: position outside [0, L]", (long long)i);
+    }
+  } else if (mode == MG_INIT_AT_VERTEX) {
+    if (vertex < 0 || vertex >= g->V) return fail(MG_EINVAL, "vertex out of range");
+    if (g->vtx_host[vertex].deg <= 0)
+      return fail(MG_EINVAL, "vertex %d is absorbing or isolated", vertex);
+    if (g->at_infinity[vertex]) return fail(MG_EINVAL, "vertex %d is at infinity", vertex);
+  } else if (mode == 3) {
+    if (n_src < 1 || !src_v || !src_rate) return fail(MG_EINVAL, "need at least one source");
+    double total = 0.0;
+    for (int32_t j = 0; j < n_src; ++j) {
+      const int32_t v = src_v[j];
+      if (v < 0 || v >= g->V) return fail(MG_EINVAL, "source %d: vertex out of range", j);
+      if (g->vtx_host[v].deg <= 0)
+        return fail(MG_EINVAL, "source %d: vertex %d is absorbing or isolated", j, v);
+      if (g->at_infinity[v]) return fail(MG_EINVAL, "source %d: vertex %d is at infinity", j, v);
+      if (!is_finite(src_rate[j]) || src_rate[j] < 0.0)
+        return fail(MG_EINVAL, "source %d: rate must be finite and >= 0", j);
+      total += src_rate[j];
+    }
+    if (!(total > 0.0)) return fail(MG_EINVAL, "the source rates sum to 0");
+  } else if (mode != MG_INIT_UNIFORM_LENGTH) {
+    return fail(MG_EINVAL, "unknown init mode");
+  } else if (g->infinite) {
+    return fail(MG_EINVAL, "uniform-by-length init needs finite edges");
+  }
+  mg_particles *p = nullptr;
+  ost = alloc_set(g, n, o, &p);
+  if (ost != MG_OK) return ost;
+  SetDev &s = p->sd;
   auto bail = [&](mg_status st) {
     mg_particles_destroy(p);
     return st;
   };
-  // counters start at zero (a kernel-free clear: the region is contiguous)
-  hipError_t he = hipMemsetAsync(base + L.exitc, 0, L.total - L.exitc, p->stream);
-  if (he != hipSuccess) return bail(hip_fail(he, "clearing the counters"));
+  hipError_t he = hipSuccess;
   int32_t *d_edge = nullptr;
   double *d_pos = nullptr;
   void *tmp = nullptr;
@@ -1361,6 +1392,228 @@ mg_status mg_particles_read(const mg_particles *p, int64_t first, int64_t count,
     }
   }
   return check_device_error(p);
+}
+
+// ------------------------------------------------------ checkpoints --
+// Image of a particle set: mg_image_header, then the sections of
+// ckpt_layout at 8-byte aligned offsets, all in the host's byte order.
+namespace {
+
+constexpr char kCkptMagic[8] = {'M', 'G', 'S', 'E', 'T', 'I', 'M', 'G'};
+constexpr uint32_t kCkptVersion = 1;
+static_assert(sizeof(mg_image_header) == 96, "image header layout");
+
+struct CkptLayout {
+  size_t ef, pos, hash, hits, exitc, absorbed, totals, obs, total;
+};
+
+CkptLayout ckpt_layout(int64_t n, int32_t V, int32_t E, int32_t nnz, bool trace,
+                       int32_t obs_nb) {
+  CkptLayout L{};
+  size_t off = sizeof(mg_image_header);
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 8);
+    return o;
+  };
+  L.ef = take((size_t)n * 4);
+  L.pos = take((size_t)n * 8);
+  L.hash = trace ? take((size_t)n * 8) : 0;
+  L.hits = trace ? take((size_t)n * 4) : 0;
+  L.exitc = take((size_t)nnz * 8);
+  L.absorbed = take((size_t)V * 8);
+  L.totals = take(4 * 8);
+  L.obs = obs_nb ? take((size_t)E * (size_t)obs_nb * 8) : 0;
+  L.total = off;
+  return L;
+}
+
+CkptLayout ckpt_layout_of(const mg_particles *p) {
+  return ckpt_layout(p->n, p->g->V, p->g->E, p->g->nnz, p->trace,
+                     p->sd.obs ? p->sd.obs_nb : 0);
+}
+
+// A particle state of an image the kernels accept: an edge of the graph,
+// the FP32 reference-end flag only in FP32 images, and (alive particles) a
+// finite position on the edge, or owing a stay on a Wentzell end (at or
+// beyond that end).  The position tests are the step kernels' own.
+mg_status check_image_particles(const mg_graph *g, const mg_image_header &h, const char *img,
+                                const CkptLayout &L) {
+  const bool fp64 = h.precision == MG_FP64;
+  auto wz_end = [&](int32_t e, bool term) {
+    const int32_t v = term ? g->vterm_host[e] : g->vinit_host[e];
+    return g->wentzell_host[v] != 0;
+  };
+  for (int64_t i = 0; i < h.n; ++i) {
+    uint32_t ef;
+    std::memcpy(&ef, img + L.ef + (size_t)i * 4, 4);
+    const int32_t e = (int32_t)(ef & kEdgeMask);
+    if (e >= g->E) return fail(MG_EINVAL, "image particle %lld: edge out of range", (long long)i);
+    if (fp64 && (ef & kSideBit))
+      return fail(MG_EINVAL, "image particle %lld: FP32 reference-end flag in an FP64 image",
+                  (long long)i);
+    if (ef & kDeadBit) continue;
+    const double Le = g->length[e];
+    bool ok;
+    if (fp64) {
+      double x;
+      std::memcpy(&x, img + L.pos + (size_t)i * 8, 8);
+      ok = std::isfinite(x) && ((x >= 0.0 && x <= Le) || (x <= 0.0 && wz_end(e, false)) ||
+                                (x >= Le && wz_end(e, true)));
+    } else {
+      float y[2];
+      std::memcpy(y, img + L.pos + (size_t)i * 8, 8);
+      ok = std::isfinite(y[0]) && std::isfinite(y[1]) &&
+           ((y[0] >= 0.0f && y[0] <= (float)Le) ||
+            (y[0] < 0.0f && wz_end(e, (ef & kSideBit) != 0)));
+    }
+    if (!ok)
+      return fail(MG_EINVAL, "image particle %lld: position outside its edge", (long long)i);
+  }
+  return MG_OK;
+}
+
+}  // namespace
+
+int64_t mg_particles_image_bytes(const mg_particles *p) {
+  if (!p) return -1;
+  return (int64_t)ckpt_layout_of(p).total;
+}
+
+mg_status mg_particles_save(const mg_particles *p, void *image, int64_t image_bytes) {
+  g_err.clear();
+  if (!p || !image) return fail(MG_EINVAL, "NULL argument");
+  const CkptLayout L = ckpt_layout_of(p);
+  if (image_bytes < (int64_t)L.total)
+    return fail(MG_EINVAL, "image_bytes %lld < %zu", (long long)image_bytes, L.total);
+  if (is_device_pointer(image)) return fail(MG_EINVAL, "the image must be in host memory");
+  // waits for every queued step; a set whose error word is set has no
+  // state worth keeping
+  mg_status st = check_device_error(p);
+  if (st != MG_OK) return st;
+  char *img = (char *)image;
+  const SetDev &s = p->sd;
+  const size_t n = (size_t)p->n;
+  auto get = [&](size_t off, const void *src, size_t bytes) {
+    return hipMemcpyAsync(img + off, src, bytes, hipMemcpyDeviceToHost, p->stream);
+  };
+  hipError_t he = get(L.ef, s.ef, n * 4);
+  if (he == hipSuccess)
+    he = get(L.pos, p->prec == MG_FP64 ? (const void *)s.x64 : (const void *)s.y32, n * 8);
+  if (he == hipSuccess && p->trace) he = get(L.hash, s.seqhash, n * 8);
+  if (he == hipSuccess && p->trace) he = get(L.hits, s.hits, n * 4);
+  if (he == hipSuccess) he = get(L.exitc, s.exit_cnt, (size_t)p->g->nnz * 8);
+  if (he == hipSuccess) he = get(L.absorbed, s.absorbed, (size_t)p->g->V * 8);
+  if (he == hipSuccess) he = get(L.totals, s.totals, 4 * 8);
+  if (he == hipSuccess && s.obs) he = get(L.obs, s.obs, (size_t)p->g->E * s.obs_nb * 8);
+  if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
+  if (he != hipSuccess) return hip_fail(he, "copying the set's state");
+  // the bytes between sections are zero, so equal states give equal images
+  // (only the u32 sections can end off the 8-byte grid)
+  auto pad = [&](size_t end) { std::memset(img + end, 0, align_up(end, 8) - end); };
+  pad(L.ef + n * 4);
+  if (p->trace) pad(L.hits + n * 4);
+  mg_image_header h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = kCkptVersion;
+  h.header_bytes = sizeof(mg_image_header);
+  h.total_bytes = L.total;
+  h.graph = p->g->fingerprint;
+  h.n = p->n;
+  h.n_vertices = p->g->V;
+  h.n_edges = p->g->E;
+  h.nnz = p->g->nnz;
+  h.precision = p->prec;
+  h.max_splits = p->max_splits;
+  h.graph_tag = p->tag;
+  h.trace = p->trace ? 1 : 0;
+  h.obs_bins = s.obs ? s.obs_nb : 0;
+  h.obs_every = s.obs ? s.obs_every : 0;
+  h.obs_start = s.obs ? p->obs_start : 0;
+  h.step = p->step;
+  std::memcpy(img, &h, sizeof h);
+  return MG_OK;
+}
+
+mg_status mg_particles_load(const mg_graph *g, const void *image, int64_t image_bytes,
+                            const mg_options *opt, mg_particles **out) {
+  g_err.clear();
+  if (!out) return fail(MG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!g || !image) return fail(MG_EINVAL, "NULL argument");
+  if (image_bytes < (int64_t)sizeof(mg_image_header))
+    return fail(MG_EINVAL, "image of %lld bytes is shorter than its header",
+                (long long)image_bytes);
+  if (is_device_pointer(image)) return fail(MG_EINVAL, "the image must be in host memory");
+  const char *img = (const char *)image;
+  mg_image_header h;
+  std::memcpy(&h, img, sizeof h);
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0)
+    return fail(MG_EINVAL, "not a particle-set image");
+  if (h.version != kCkptVersion || h.header_bytes != sizeof(mg_image_header))
+    return fail(MG_EINVAL, "image version %u is not %u", h.version, kCkptVersion);
+  if (h.graph != g->fingerprint || h.n_vertices != g->V || h.n_edges != g->E ||
+      h.nnz != g->nnz)
+    return fail(MG_EINVAL, "the image was saved on another graph");
+  if (h.n < 1 || h.n > kMaxParticles) return fail(MG_EINVAL, "image particle count out of range");
+  if ((h.precision != MG_FP64 && h.precision != MG_FP32) || h.max_splits < 1 ||
+      h.max_splits > 255 || (h.trace != 0 && h.trace != 1) || h.step > 0xFFFFFFFFull)
+    return fail(MG_EINVAL, "image header out of range");
+  if (h.obs_every == 0 ? (h.obs_bins != 0 || h.obs_start != 0)
+                       : (h.obs_every > (1u << 30) || h.obs_bins < 1 ||
+                          (int64_t)g->E * h.obs_bins > 0x7FFFFFFF || h.obs_start > h.step))
+    return fail(MG_EINVAL, "image streamed-histogram fields out of range");
+  const CkptLayout L =
+      ckpt_layout(h.n, h.n_vertices, h.n_edges, h.nnz, h.trace != 0, h.obs_bins);
+  if (h.total_bytes != L.total || image_bytes < (int64_t)L.total)
+    return fail(MG_EINVAL, "image of %lld bytes, %zu expected", (long long)image_bytes, L.total);
+  mg_status st = check_image_particles(g, h, img, L);
+  if (st != MG_OK) return st;
+  // the image fixes what the sample paths depend on; opt gives the rest
+  mg_options o = opt ? *opt : mg_options{};
+  o.precision = (mg_precision)h.precision;
+  o.max_splits = h.max_splits;
+  o.graph_tag = h.graph_tag;
+  o.trace = h.trace;
+  st = set_options(g, &o, o);
+  if (st != MG_OK) return st;
+  mg_particles *p = nullptr;
+  st = alloc_set(g, h.n, o, &p);
+  if (st != MG_OK) return st;
+  const SetDev &s = p->sd;
+  const size_t n = (size_t)h.n;
+  auto put = [&](void *dst, size_t off, size_t bytes) {
+    return hipMemcpyAsync(dst, img + off, bytes, hipMemcpyHostToDevice, p->stream);
+  };
+  hipError_t he = put(s.ef, L.ef, n * 4);
+  if (he == hipSuccess)
+    he = put(p->prec == MG_FP64 ? (void *)s.x64 : (void *)s.y32, L.pos, n * 8);
+  if (he == hipSuccess && p->trace) he = put(s.seqhash, L.hash, n * 8);
+  if (he == hipSuccess && p->trace) he = put(s.hits, L.hits, n * 4);
+  if (he == hipSuccess) he = put(s.exit_cnt, L.exitc, (size_t)h.nnz * 8);
+  if (he == hipSuccess) he = put(s.absorbed, L.absorbed, (size_t)h.n_vertices * 8);
+  if (he == hipSuccess) he = put(s.totals, L.totals, 4 * 8);
+  if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
+  if (he != hipSuccess) {
+    mg_particles_destroy(p);
+    return hip_fail(he, "copying the image's state");
+  }
+  p->step = h.step;
+  if (h.obs_every) {
+    st = mg_observe_histogram(p, h.obs_bins, (int32_t)h.obs_every);
+    if (st == MG_OK) {
+      he = put(p->sd.obs, L.obs, (size_t)h.n_edges * h.obs_bins * 8);
+      if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
+      if (he != hipSuccess) st = hip_fail(he, "copying the streamed histogram");
+    }
+    if (st != MG_OK) {
+      mg_particles_destroy(p);
+      return st;
+    }
+    p->obs_start = h.obs_start;
+  }
+  *out = p;
+  return MG_OK;
 }
 
 mg_status mg_batch_create(int32_t n_sets, mg_particles *const *sets, mg_batch **out) {

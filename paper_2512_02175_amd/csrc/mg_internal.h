@@ -15,7 +15,7 @@ constexpr uint32_t kSideBit = 0x40000000u;
 constexpr uint32_t kDeadBit = 0x80000000u;
 constexpr int32_t kMaxEdges = 0x3FFFFFFF;
 
-// Edge record for the FP64 path: 96 bytes, one per edge.  span is the
+// Edge record for the FP64 path: 112 bytes, one per edge.  span is the
 // length the uniform histograms bin (the edge length unless the caller gave
 // another; finite on a semi-infinite edge).  The end vertex ids of both
 // records carry kMirrorEnd when that end is a mirror vertex (a reflecting
@@ -40,7 +40,9 @@ struct alignas(16) EdgeRec64 {
   // first at row tab0 of the graph's table records; inv_h = tab_k / L
   double inv_h;
   int32_t tab0, tab_k;
+  int32_t pad[2];  // explicit, so a packed table's bytes are all defined
 };
+static_assert(sizeof(EdgeRec64) == 112, "EdgeRec64 has no implicit padding");
 
 // One interval of a tabulated edge: drift and diffusion as cubics in the
 // interval's local coordinate t in [0, 1] (c0 + c1 t + c2 t^2 + c3 t^3),

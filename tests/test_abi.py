@@ -200,7 +200,7 @@ def test_struct_layouts_match_the_header(B, tmp_path):
     """The binding's ctypes structs have the header's field offsets and
     sizes (compiled with the host C compiler from include/metricgraph.h)."""
     structs = {"mg_graph_desc": B.mg_graph_desc, "mg_options": B.mg_options,
-               "mg_tuning": B.mg_tuning}
+               "mg_tuning": B.mg_tuning, "mg_image_header": B.mg_image_header}
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "metricgraph.h"',
              "int main(void) {"]
     for name, cls in structs.items():
@@ -234,3 +234,19 @@ def test_valu_rate_arguments_checked(B, args):
     st = B.lib().mg_valu_rate(*args, C.byref(rate), None)
     assert st == B.MG_EINVAL, (args, st)
     assert B.mg_last_error()
+
+
+def test_checkpoint_arguments_checked(B):
+    """Save and load refuse NULL handles and buffers before touching the
+    device."""
+    L = B.lib()
+    h = C.c_void_p()
+    buf = np.zeros(256, np.uint8)
+    assert L.mg_particles_image_bytes(None) == -1
+    assert L.mg_particles_save(None, B._p(buf), buf.size) == B.MG_EINVAL
+    assert L.mg_particles_load(None, B._p(buf), buf.size, None, None) == B.MG_EINVAL
+    assert "out is NULL" in B.mg_last_error()
+    assert L.mg_particles_load(None, B._p(buf), buf.size, None, C.byref(h)) == B.MG_EINVAL
+    assert "NULL argument" in B.mg_last_error() and not h.value
+    with pytest.raises(ValueError):
+        B.image_header(buf[:95])
