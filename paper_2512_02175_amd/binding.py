@@ -451,15 +451,24 @@ def mg_particles_save(p: Particles) -> np.ndarray:
 
 
 def mg_particles_load(g: Graph, image, *, steps_per_launch: int = 0, stream=None,
-                      schedule: int = MG_SCHED_AUTO) -> Particles:
+                      schedule: int = MG_SCHED_AUTO, arena=None) -> Particles:
     """A new set on ``g`` from an image of mg_particles_save; precision,
-    max_splits, graph_tag and trace come from the image."""
+    max_splits, graph_tag and trace come from the image.  ``arena`` as in
+    mg_particles_init."""
     img = np.ascontiguousarray(image, np.uint8)
-    o = _options(MG_FP64, 0, 0, False, steps_per_launch, stream, schedule=schedule)
+    arena_obj, aptr, abytes = None, None, 0
+    if arena is not None:
+        import torch
+        hd = image_header(img)
+        need = mg_particles_arena_bytes(g, int(hd.n), int(hd.precision), bool(hd.trace))
+        arena_obj = (torch.empty(need, dtype=torch.uint8, device="cuda")
+                     if isinstance(arena, str) else arena)
+        aptr, abytes = C.c_void_p(arena_obj.data_ptr()), arena_obj.numel() * arena_obj.element_size()
+    o = _options(MG_FP64, 0, 0, False, steps_per_launch, stream, aptr, abytes, schedule)
     h = C.c_void_p()
     _check(lib().mg_particles_load(g.handle, _p(img), int(img.size), C.byref(o), C.byref(h)))
     hd = image_header(img)
-    q = Particles(h, g, int(hd.n), int(hd.precision))
+    q = Particles(h, g, int(hd.n), int(hd.precision), arena_obj)
     q.obs_bins = int(hd.obs_bins)
     return q
 

@@ -113,6 +113,35 @@ def test_resume_keeps_the_streamed_histogram(B):
     assert np.array_equal(B.mg_histogram(q, 12), B.mg_histogram(ref, 12))
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_members_resume(B, prec):
+    """Members of a batch saved after 300 batched steps, loaded (one into a
+    torch arena) and batched again for 200: equal to 500 steps of each set
+    alone."""
+    rng = np.random.default_rng(4)
+    graphs = [workloads.star_graph(3, [1.0, 2.0, 0.5]), workloads.random_tree(40, rng),
+              workloads.config2()[0]]
+    counts = [700, 2000, 5000]
+    Gs = [B.mg_graph_create(g) for g in graphs]
+    alone, members = [], []
+    for i, (G, n) in enumerate(zip(Gs, counts)):
+        kw = dict(init_seed=i, precision=prec, graph_tag=i, trace=True)
+        alone.append(B.mg_particles_init(G, n, 2, **kw))
+        members.append(B.mg_particles_init(G, n, 2, **kw))
+    for p in alone:
+        B.mg_simulate(p, 500, 1e-2, 9)
+    b = B.mg_batch_create(members)
+    B.mg_batch_simulate(b, 300, 1e-2, 9)
+    imgs = [B.mg_particles_save(p) for p in members]
+    del b, members
+    loaded = [B.mg_particles_load(G, img, arena="torch" if i == 1 else None)
+              for i, (G, img) in enumerate(zip(Gs, imgs))]
+    b2 = B.mg_batch_create(loaded)
+    B.mg_batch_simulate(b2, 200, 1e-2, 9)
+    for pa, pb in zip(alone, loaded):
+        _assert_same(_state(B, pb), _state(B, pa))
+
+
 def _image(B, prec=0, n=257):
     g, _ = workloads.config2()
     G = B.mg_graph_create(g)
