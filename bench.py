@@ -139,6 +139,22 @@ def run_pass(B, G, g, run, prec, dt, torch, kernel_times, schedules=None, schedu
                 trunc=int(tot[0]), exit=ex, hist=hist, launches=launches)
 
 
+def environment(torch) -> dict:
+    """The machine and software a line was measured on."""
+    props = torch.cuda.get_device_properties(0)
+    return {"gpu": torch.cuda.get_device_name(0),
+            "arch": getattr(props, "gcnArchName", None),
+            "compute_units": props.multi_processor_count,
+            "hbm_gib": round(props.total_memory / 2**30, 1),
+            "hip": torch.version.hip, "torch": torch.__version__,
+            "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+
+
+def emit(line: dict, torch) -> None:
+    line["env"] = environment(torch)
+    print(json.dumps(line), flush=True)
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -790,25 +806,25 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(torch)
     if args.workload == "vascular_tracer":
-        print(json.dumps(run_tracer(args, B, torch)), flush=True)
+        emit(run_tracer(args, B, torch), torch)
         return
     if args.workload == "nohit_segment":
-        print(json.dumps(run_nohit(args, B, torch)), flush=True)
+        emit(run_nohit(args, B, torch), torch)
         return
     if args.workload == "double_well_star64":
-        print(json.dumps(run_double_well(args, B, torch)), flush=True)
+        emit(run_double_well(args, B, torch), torch)
         return
     if args.workload == "vascular20k":
-        print(json.dumps(run_vascular(args, B, torch)), flush=True)
+        emit(run_vascular(args, B, torch), torch)
         return
     if args.workload == "batch512":
-        print(json.dumps(run_batch(args, B, torch)), flush=True)
+        emit(run_batch(args, B, torch), torch)
         return
     if args.workload == "accuracy_sweep":
-        print(json.dumps(run_sweep(args, B, torch)), flush=True)
+        emit(run_sweep(args, B, torch), torch)
         return
     if args.workload == "density_error":
-        print(json.dumps(run_density(args, B, torch)), flush=True)
+        emit(run_density(args, B, torch), torch)
         return
     g, run = workloads.config2()
     mirror = args.workload == "langevin_star64_mirror"
@@ -921,7 +937,7 @@ def main():
         line["batch512"] = batch_leg(B, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, run, args.cpu_sample)
-    print(json.dumps(line), flush=True)
+    emit(line, torch)
 
 
 if __name__ == "__main__":
