@@ -386,6 +386,43 @@ mg_status mg_particles_read(const mg_particles *p, int64_t first, int64_t count,
 int64_t mg_particles_step(const mg_particles *p);
 
 /*
+ * Event trace of chosen particles (a parity and debugging aid): with the
+ * trace on, every vertex hit of a chosen particle (Alg. 2's crossing: the
+ * fraction alpha = u^2 of the sub-step's time, the vertex, the slot drawn
+ * there by Alg. 1's rule) appends one record, in every schedule and in
+ * batches.
+ *
+ * mg_trace_events chooses n_ids distinct particle ids (0 <= id < n,
+ * n_ids <= 4096, any order) and keeps at most `capacity` records
+ * (1 .. 2^26) in device memory the library allocates; n_ids = 0 turns the
+ * trace off and frees it.  Every call clears the records and the count.
+ * The set must have been created with trace (MG_ESTATE otherwise).  Waits
+ * for the set's stream first.
+ *
+ * mg_trace_read copies min(count, out_len) records into host memory out
+ * (NULL with out_len 0: count only) and sets *n_events to the number of
+ * hits recorded since mg_trace_events (records past the capacity are
+ * dropped, so *n_events may exceed it).  Records of one particle come in
+ * step and hit order; different particles interleave.  Synchronises the
+ * stream.
+ */
+typedef struct {
+  uint32_t pid;       /* particle id */
+  uint32_t step;      /* the step counter value of the step */
+  int32_t k;          /* hit index within the step, from 1 */
+  int32_t vertex;     /* the vertex hit */
+  int32_t slot;       /* slot drawn, -1 when the particle was removed there */
+  int32_t reserved;
+  double u;           /* sqrt(alpha): the crossing root of the sub-step */
+  double h_after;     /* time left in the step after the crossing */
+} mg_event;
+
+mg_status mg_trace_events(mg_particles *p, int32_t n_ids, const int64_t *ids,
+                          int64_t capacity);
+mg_status mg_trace_read(const mg_particles *p, mg_event *out, int64_t out_len,
+                        int64_t *n_events);
+
+/*
  * Checkpoint and resume.  The appendix's kernels leave every particle's
  * state in global memory between launches; with counter-based draws that
  * state and the step counter are all a later step depends on, so a set

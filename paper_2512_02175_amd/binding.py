@@ -29,7 +29,8 @@ EXPORTED = (
     "mg_particles_init", "mg_particles_init_sources", "mg_particles_destroy", "mg_simulate",
     "mg_histogram",
     "mg_exit_counts", "mg_particles_read", "mg_particles_step", "mg_particles_image_bytes",
-    "mg_particles_save", "mg_particles_load", "mg_batch_create",
+    "mg_particles_save", "mg_particles_load", "mg_trace_events", "mg_trace_read",
+    "mg_batch_create",
     "mg_batch_simulate", "mg_batch_destroy", "mg_autotune", "mg_histogram_csr",
     "mg_histogram_csr_noalloc", "mg_observe_histogram",
     "mg_observed_histogram", "mg_density_l2", "mg_valu_rate", "mg_last_error",
@@ -82,6 +83,16 @@ class mg_image_header(C.Structure):
                 ("obs_every", C.c_uint64), ("obs_start", C.c_uint64), ("step", C.c_uint64)]
 
 
+class mg_event(C.Structure):
+    _fields_ = [("pid", C.c_uint32), ("step", C.c_uint32), ("k", C.c_int32),
+                ("vertex", C.c_int32), ("slot", C.c_int32), ("reserved", C.c_int32),
+                ("u", C.c_double), ("h_after", C.c_double)]
+
+
+EVENT_DTYPE = np.dtype([(f[0], {C.c_uint32: "<u4", C.c_int32: "<i4", C.c_double: "<f8"}[f[1]])
+                        for f in mg_event._fields_])
+
+
 def image_header(image) -> mg_image_header:
     """The header of a set image (a host byte array)."""
     b = np.ascontiguousarray(image, np.uint8)
@@ -121,6 +132,8 @@ def lib() -> C.CDLL:
         L.mg_particles_image_bytes.restype = i64
         L.mg_particles_save.argtypes = [vp, vp, i64]
         L.mg_particles_load.argtypes = [vp, vp, i64, vp, vp]
+        L.mg_trace_events.argtypes = [vp, i32, vp, i64]
+        L.mg_trace_read.argtypes = [vp, vp, i64, vp]
         L.mg_batch_create.argtypes = [i32, vp, vp]
         L.mg_batch_simulate.argtypes = [vp, i64, C.c_double, u64]
         L.mg_batch_destroy.argtypes = [vp]
@@ -471,6 +484,26 @@ def mg_particles_load(g: Graph, image, *, steps_per_launch: int = 0, stream=None
     q = Particles(h, g, int(hd.n), int(hd.precision), arena_obj)
     q.obs_bins = int(hd.obs_bins)
     return q
+
+
+def mg_trace_events(p: Particles, ids, capacity: int = 1 << 16) -> None:
+    """Records every vertex hit of particles ``ids`` (empty: trace off)."""
+    a = np.ascontiguousarray(ids, np.int64)
+    _check(lib().mg_trace_events(p.handle, int(a.size), _p(a) if a.size else None,
+                                 int(capacity)))
+    p.ev_cap = int(capacity) if a.size else 0
+
+
+def mg_trace_read(p: Particles):
+    """(records as a structured array sorted by particle, step and hit
+    index, number of hits recorded including dropped ones)."""
+    n = C.c_int64()
+    _check(lib().mg_trace_read(p.handle, None, 0, C.byref(n)))
+    kept = min(int(n.value), getattr(p, "ev_cap", 0))
+    out = np.zeros(max(kept, 1), EVENT_DTYPE)
+    _check(lib().mg_trace_read(p.handle, _p(out), kept, C.byref(n)))
+    out = out[:kept]
+    return out[np.lexsort((out["k"], out["step"], out["pid"]))], int(n.value)
 
 
 def mg_batch_create(sets) -> Batch:

@@ -217,6 +217,7 @@ struct mg_particles {
   SetDev sd{};
   uint64_t step = 0;
   uint64_t obs_start = 0;  // step counter when the streamed histogram started
+  void *ev_mem = nullptr;  // event trace: counter, ids and records
   // histogram kernel choice for large E * nb (timed on the first call)
   mutable int32_t hist_nb = 0;
   mutable bool hist_tiled = false;
@@ -995,9 +996,10 @@ mg_status mg_particles_init_sources(const mg_graph *g, int64_t n, int32_t n_sour
 
 void mg_particles_destroy(mg_particles *p) {
   if (!p) return;
-  if ((p->owns && p->mem) || p->sd.obs) (void)hipStreamSynchronize(p->stream);
+  if ((p->owns && p->mem) || p->sd.obs || p->ev_mem) (void)hipStreamSynchronize(p->stream);
   if (p->owns && p->mem) (void)hipFree(p->mem);
   if (p->sd.obs) (void)hipFree(p->sd.obs);
+  if (p->ev_mem) (void)hipFree(p->ev_mem);
   delete p;
 }
 
@@ -1394,6 +1396,83 @@ mg_status mg_particles_read(const mg_particles *p, int64_t first, int64_t count,
   return check_device_error(p);
 }
 
+// ----------------------------------------------------- event trace --
+mg_status mg_trace_events(mg_particles *p, int32_t n_ids, const int64_t *ids,
+                          int64_t capacity) {
+  g_err.clear();
+  if (!p) return fail(MG_EINVAL, "particles is NULL");
+  if (!p->trace) return fail(MG_ESTATE, "the set was created without trace");
+  if (n_ids < 0 || n_ids > 4096) return fail(MG_EINVAL, "n_ids must be in [0, 4096]");
+  std::vector<uint32_t> sorted;
+  if (n_ids > 0) {
+    if (!ids) return fail(MG_EINVAL, "ids is NULL");
+    if (capacity < 1 || capacity > (1 << 26))
+      return fail(MG_EINVAL, "capacity must be in [1, 2^26]");
+    sorted.resize((size_t)n_ids);
+    for (int32_t i = 0; i < n_ids; ++i) {
+      if (ids[i] < 0 || ids[i] >= p->n) return fail(MG_EINVAL, "id %d out of range", i);
+      sorted[i] = (uint32_t)ids[i];
+    }
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(MG_EINVAL, "ids must be distinct");
+  }
+  // kernels already queued may still write the old records
+  MG_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+  if (p->ev_mem) (void)hipFree(p->ev_mem);
+  p->ev_mem = nullptr;
+  p->sd.ev = nullptr;
+  p->sd.ev_cnt = nullptr;
+  p->sd.ev_ids = nullptr;
+  p->sd.ev_nids = 0;
+  p->sd.ev_cap = 0;
+  if (n_ids == 0) return MG_OK;
+  const size_t o_ids = 256, o_ev = align_up(o_ids + (size_t)n_ids * 4, 256);
+  const size_t bytes = o_ev + (size_t)capacity * sizeof(mg_event);
+  void *mem = nullptr;
+  hipError_t he = hipMalloc(&mem, bytes);
+  if (he != hipSuccess)
+    return fail(MG_ENOMEM, "hipMalloc for the event trace: %s", hipGetErrorString(he));
+  char *base = (char *)mem;
+  he = hipMemsetAsync(base, 0, 8, p->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(base + o_ids, sorted.data(), (size_t)n_ids * 4, hipMemcpyHostToDevice,
+                        p->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
+  if (he != hipSuccess) {
+    (void)hipFree(mem);
+    return hip_fail(he, "setting up the event trace");
+  }
+  p->ev_mem = mem;
+  p->sd.ev_cnt = (unsigned long long *)base;
+  p->sd.ev_ids = (const uint32_t *)(base + o_ids);
+  p->sd.ev = (mg_event *)(base + o_ev);
+  p->sd.ev_nids = n_ids;
+  p->sd.ev_cap = (uint32_t)capacity;
+  return MG_OK;
+}
+
+mg_status mg_trace_read(const mg_particles *p, mg_event *out, int64_t out_len,
+                        int64_t *n_events) {
+  g_err.clear();
+  if (!p || !n_events) return fail(MG_EINVAL, "NULL argument");
+  if (!p->ev_mem) return fail(MG_ESTATE, "the event trace is off");
+  if (out_len < 0 || (out_len > 0 && !out)) return fail(MG_EINVAL, "bad output buffer");
+  unsigned long long cnt = 0;
+  MG_HIP(hipMemcpyAsync(&cnt, p->sd.ev_cnt, 8, hipMemcpyDeviceToHost, p->stream),
+         "reading the event count");
+  MG_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+  const int64_t kept = (int64_t)std::min<unsigned long long>(cnt, p->sd.ev_cap);
+  const int64_t copy = std::min<int64_t>(kept, out_len);
+  if (copy > 0) {
+    MG_HIP(hipMemcpyAsync(out, p->sd.ev, (size_t)copy * sizeof(mg_event), hipMemcpyDefault,
+                          p->stream), "copying the events");
+    MG_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+  }
+  *n_events = (int64_t)cnt;
+  return check_device_error(p);
+}
+
 // ------------------------------------------------------ checkpoints --
 // Image of a particle set: mg_image_header, then the sections of
 // ckpt_layout at 8-byte aligned offsets, all in the host's byte order.
@@ -1402,6 +1481,7 @@ namespace {
 constexpr char kCkptMagic[8] = {'M', 'G', 'S', 'E', 'T', 'I', 'M', 'G'};
 constexpr uint32_t kCkptVersion = 1;
 static_assert(sizeof(mg_image_header) == 96, "image header layout");
+static_assert(sizeof(mg_event) == 40, "event record layout");
 
 struct CkptLayout {
   size_t ef, pos, hash, hits, exitc, absorbed, totals, obs, total;

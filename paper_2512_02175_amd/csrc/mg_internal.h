@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/metricgraph.h"
+
 namespace mg {
 
 // Particle state word: edge id in the low 30 bits, bit 30 = the FP32 path's
@@ -158,6 +160,14 @@ struct SetDev {
   uint32_t n;
   uint32_t n0;         // first step of this launch (set's step counter)
   uint32_t tag;
+  // event trace (trace sets only, else null): one record per vertex hit of
+  // the particles in ev_ids (ev_nids ids, ascending); ev_cnt counts every
+  // event, the first ev_cap are kept
+  mg_event *ev;
+  unsigned long long *ev_cnt;
+  const uint32_t *ev_ids;
+  int32_t ev_nids;
+  uint32_t ev_cap;
 };
 
 enum : uint32_t { kErrEdge = 1u, kErrPos = 2u };

@@ -248,6 +248,37 @@ __device__ __forceinline__ uint64_t fnv(uint64_t h, uint32_t w) {
   return (h ^ (uint64_t)w) * kFnvPrime;
 }
 
+// Event trace: a vertex hit of a chosen particle (ids ascending in S.ev_ids)
+// appends its record (step, hit index, vertex, slot or -1 when the particle
+// is removed there, u = sqrt(alpha) and the time left after the hit); the
+// counter counts every event, records past the capacity are dropped.  Only
+// sets with trace call it.
+__device__ void trace_hit(const SetDev &S, uint32_t pid, uint32_t step, int32_t k, int32_t v,
+                          int32_t slot, double u, double h_after) {
+  if (!S.ev) return;
+  int32_t lo = 0, hi = S.ev_nids;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (S.ev_ids[mid] < pid)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  if (lo == S.ev_nids || S.ev_ids[lo] != pid) return;
+  const unsigned long long i = atomicAdd(S.ev_cnt, 1ull);
+  if (i < (unsigned long long)S.ev_cap) {
+    mg_event &r = S.ev[i];
+    r.pid = pid;
+    r.step = step;
+    r.k = k;
+    r.vertex = v;
+    r.slot = slot;
+    r.reserved = 0;
+    r.u = u;
+    r.h_after = h_after;
+  }
+}
+
 // Vertex stream of a Wentzell visit: word 0 of Philox (p, n, 0x100 + k, tag)
 // decides the killing at the visit of the k-th hit of step n (k = 0: the
 // visit at the start of a step that begins on the vertex).  Hit streams use
@@ -718,6 +749,7 @@ struct Particle64 {
                           h_move, owed);
       }
       if (vb.deg < 0 || killed) {  // absorbing vertex, or killed at the visit
+        if (TRACE) trace_hit(S, pid, step, H.k, v, -1, u, h);
         die(v, step, S);
         return true;
       }
@@ -727,7 +759,10 @@ struct Particle64 {
       R = G.e64[e];
       x = (sp.eo & 1u) ? R.L : 0.0;
       H.last = sp.s;
-      if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)sp.s);
+      if (TRACE) {
+        hash = fnv(fnv(hash, step), (uint32_t)sp.s);
+        trace_hit(S, pid, step, H.k, v, sp.s, u, h);
+      }
       if (GEN == kGenFull && vb.wz) {
         h = h_move;
         if (h == 0.0) {  // stays on the vertex for the rest of the step
@@ -1170,6 +1205,7 @@ struct Particle32 {
                           (double)hh + (double)hl, vertex_draw(pid, step, (uint32_t)h.k, S, A),
                           hm, owed);
       if (vb.deg < 0 || killed) {
+        if (TRACE) trace_hit(S, pid, step, h.k, v, -1, u, (double)hh + (double)hl);
         die(v, step, S);
         return true;
       }
@@ -1182,7 +1218,10 @@ struct Particle32 {
       yl = 0.0f;
       frame();
       h.last = sp.s;
-      if (TRACE) hash = fnv(fnv(hash, step), (uint32_t)sp.s);
+      if (TRACE) {
+        hash = fnv(fnv(hash, step), (uint32_t)sp.s);
+        trace_hit(S, pid, step, h.k, v, sp.s, u, (double)hh + (double)hl);
+      }
       bool stays = false;
       if (GEN == kGenFull && vb.wz) {
         if (hm == 0.0) {  // stays on the vertex for the rest of the step

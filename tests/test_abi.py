@@ -200,7 +200,8 @@ def test_struct_layouts_match_the_header(B, tmp_path):
     """The binding's ctypes structs have the header's field offsets and
     sizes (compiled with the host C compiler from include/metricgraph.h)."""
     structs = {"mg_graph_desc": B.mg_graph_desc, "mg_options": B.mg_options,
-               "mg_tuning": B.mg_tuning, "mg_image_header": B.mg_image_header}
+               "mg_tuning": B.mg_tuning, "mg_image_header": B.mg_image_header,
+               "mg_event": B.mg_event}
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "metricgraph.h"',
              "int main(void) {"]
     for name, cls in structs.items():
