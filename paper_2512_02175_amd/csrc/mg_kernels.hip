@@ -74,6 +74,18 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
   return {c0, c1, c2, c3};
 }
 
+// Keys of a Philox call in an FP64 kernel.  The FP64 polynomial constants
+// fill the scalar registers there, so the round keys, which the compiler
+// computes once outside the loops, are spilled to lanes of a vector
+// register and read back with a readlane (a vector issue slot) per round.
+// Hiding the two keys from the optimiser at the call keeps each Weyl
+// increment next to its round, as a scalar add.  FP32 kernels keep their
+// round keys in scalar registers and are left as they are.
+template <class real>
+__device__ __forceinline__ void fresh_keys(uint32_t &k0, uint32_t &k1) {
+  if constexpr (sizeof(real) == 8) asm volatile("" : "+s"(k0), "+s"(k1));
+}
+
 // Sine and cosine of t in [0, 2 pi) (the Box-Muller angle, t = 2 pi u with
 // u in (0, 1)): the argument is reduced by quarter turns, r = t - q pi/2
 // with pi/2 in two parts (Cody and Waite); for q <= 4 the first step
@@ -472,7 +484,9 @@ __device__ __forceinline__ void step_loop(P &q, const SetDev &S, const StepArgs 
     typename P::real W[NW];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      const U4 o = philox(pid, (base >> 2) + g, 0u, S.tag, A.key0, A.key1);
+      uint32_t k0 = A.key0, k1 = A.key1;
+      fresh_keys<typename P::real>(k0, k1);
+      const U4 o = philox(pid, (base >> 2) + g, 0u, S.tag, k0, k1);
       P::box_muller(o.x, o.y, W[4 * g + 0], W[4 * g + 1]);
       P::box_muller(o.z, o.w, W[4 * g + 2], W[4 * g + 3]);
     }
@@ -753,7 +767,9 @@ struct Particle64 {
         die(v, step, S);
         return true;
       }
-      const U4 hd = philox(pid, step, (uint32_t)H.k, S.tag, A.key0, A.key1);
+      uint32_t k0 = A.key0, k1 = A.key1;
+      fresh_keys<double>(k0, k1);
+      const U4 hd = philox(pid, step, (uint32_t)H.k, S.tag, k0, k1);
       const SlotPick sp = pick_slot(G, vb, hd.x);
       e = eo_edge(sp.eo);
       R = G.e64[e];
@@ -1870,7 +1886,9 @@ __device__ void run_pool(const GView &G, int32_t n_edges, const SetDev &S,
       real W[NW];
 #pragma unroll
       for (uint32_t g = 0; g < (uint32_t)NG; ++g) {
-        const U4 o = philox(pid, (base >> 2) + g, 0u, S.tag, A.key0, A.key1);
+        uint32_t k0 = A.key0, k1 = A.key1;
+        fresh_keys<real>(k0, k1);
+        const U4 o = philox(pid, (base >> 2) + g, 0u, S.tag, k0, k1);
         Q::box_muller(o.x, o.y, W[4 * g + 0], W[4 * g + 1]);
         Q::box_muller(o.z, o.w, W[4 * g + 2], W[4 * g + 3]);
       }
