@@ -264,6 +264,7 @@ mg_status mg_particles_init_sources(const mg_graph *g, int64_t n, int32_t n_sour
                                     const int32_t *vertices, const double *rates,
                                     uint64_t init_seed, const mg_options *opt,
                                     mg_particles **out);
+/* Frees a set (NULL-safe) once all work on the device has finished. */
 void mg_particles_destroy(mg_particles *p);
 
 /*
@@ -333,8 +334,8 @@ mg_status mg_histogram_csr_noalloc(const mg_particles *p, const int32_t *bin_off
  * stationary density after burn-in, Sec. 4.1's error measurement).  The
  * accumulator starts at zero; calling again discards it and starts a new
  * one; every = 0 turns streaming off.  Allocates device memory for the
- * accumulator (outside any arena); synchronises the stream.  Batched sets
- * stream too.
+ * accumulator (outside any arena); first waits for all work on the device
+ * (a batch may run the set on another stream).  Batched sets stream too.
  */
 mg_status mg_observe_histogram(mg_particles *p, int32_t bins_per_edge, int32_t every);
 
@@ -396,8 +397,9 @@ int64_t mg_particles_step(const mg_particles *p);
  * n_ids <= 4096, any order) and keeps at most `capacity` records
  * (1 .. 2^26) in device memory the library allocates; n_ids = 0 turns the
  * trace off and frees it.  Every call clears the records and the count.
- * The set must have been created with trace (MG_ESTATE otherwise).  Waits
- * for the set's stream first.
+ * The set must have been created with trace (MG_ESTATE otherwise).  First
+ * waits for all work on the device (a batch may run the set on another
+ * stream).
  *
  * mg_trace_read copies min(count, out_len) records into host memory out
  * (NULL with out_len 0: count only) and sets *n_events to the number of

@@ -996,7 +996,8 @@ mg_status mg_particles_init_sources(const mg_graph *g, int64_t n, int32_t n_sour
 
 void mg_particles_destroy(mg_particles *p) {
   if (!p) return;
-  if ((p->owns && p->mem) || p->sd.obs || p->ev_mem) (void)hipStreamSynchronize(p->stream);
+  // a batch may still run the set on its own stream
+  if ((p->owns && p->mem) || p->sd.obs || p->ev_mem) (void)hipDeviceSynchronize();
   if (p->owns && p->mem) (void)hipFree(p->mem);
   if (p->sd.obs) (void)hipFree(p->sd.obs);
   if (p->ev_mem) (void)hipFree(p->ev_mem);
@@ -1244,8 +1245,9 @@ mg_status mg_observe_histogram(mg_particles *p, int32_t bins_per_edge, int32_t e
     if ((int64_t)p->g->E * bins_per_edge > 0x7FFFFFFF)
       return fail(MG_EINVAL, "E * bins_per_edge too large");
   }
-  // kernels already queued may still add to the old counters
-  MG_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+  // kernels already queued may still add to the old counters, on the
+  // set's stream or, in a batch, on the batch's
+  MG_HIP(hipDeviceSynchronize(), "synchronising the device");
   if (p->sd.obs) (void)hipFree(p->sd.obs);
   p->sd.obs = nullptr;
   p->sd.obs_nb = 0;
@@ -1417,8 +1419,9 @@ mg_status mg_trace_events(mg_particles *p, int32_t n_ids, const int64_t *ids,
     if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
       return fail(MG_EINVAL, "ids must be distinct");
   }
-  // kernels already queued may still write the old records
-  MG_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+  // kernels already queued may still write the old records, on the set's
+  // stream or, in a batch, on the batch's
+  MG_HIP(hipDeviceSynchronize(), "synchronising the device");
   if (p->ev_mem) (void)hipFree(p->ev_mem);
   p->ev_mem = nullptr;
   p->sd.ev = nullptr;
