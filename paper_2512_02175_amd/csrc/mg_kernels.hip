@@ -126,9 +126,45 @@ __device__ __forceinline__ void sincos_small(double t, double &s_out, double &c_
   c_out = (iq == 1 || iq == 2) ? -b : b;
 }
 
+// Quotient n / d for d in [1, 4) and |n| < 1, where no range scaling,
+// overflow or special value can arise: the hardware reciprocal estimate
+// refined by two Newton-Raphson steps, the product, and one correction by
+// the residual (Markstein's sequence).  These are the device library's
+// division steps without its operand scaling and special-value fix-up,
+// which leave such operands unchanged, so the quotient is the library's.
+__device__ __forceinline__ double div_unit(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  const double q = n * r;
+  return fma(fma(-d, q, n), r, q);
+}
+
+// Square root of x in [2^-767, 2^1023) (normal, positive, finite): the
+// hardware reciprocal square root y refined in Markstein's coupled form
+// (g ~ sqrt(x) and h ~ 1/(2 sqrt(x)) updated together, then two residual
+// corrections of g).  These are the device library's steps without its
+// scaling of tiny arguments and its zero, infinity and NaN checks, which
+// leave such arguments unchanged, so the root is the library's.  The
+// Box-Muller radius argument -2 ln u lies in [2.3e-10, 44.4].
+__device__ __forceinline__ double sqrt_normal(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = y * 0.5;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  double d = fma(-g, g, x);
+  h = fma(h, r, h);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 // Natural logarithm of a Box-Muller uniform u in (0, 1) (no zero, infinite
 // or negative arguments reach it): u = 2^e m with m in [sqrt(1/2), sqrt(2)),
-// f = m - 1 (exact), s = f / (2 + f), and log(1 + f) = 2 atanh(s) written as
+// f = m - 1 (exact), s = f / (2 + f) (div_unit), and log(1 + f) = 2 atanh(s) written as
 // f - (f^2/2 - s (f^2/2 + R)), R = sum over k = 1..10 of 2 s^(2k) / (2k + 1)
 // (the atanh Taylor series; |s| <= 0.1716 leaves a truncation below 1e-18);
 // e ln 2 with ln 2 in two parts (its first 32 bits, exact times e, and the
@@ -142,7 +178,7 @@ __device__ __forceinline__ double log_unit(double u) {
   m = low ? m * 2.0 : m;
   e = low ? e - 1 : e;
   const double f = m - 1.0;
-  const double s = f / (2.0 + f);
+  const double s = div_unit(f, 2.0 + f);
   const double z = s * s;
   double r = 0.09523809523809523;  // 2 / (2k + 1), k = 10 .. 1
   r = fma(r, z, 0.10526315789473684);
@@ -165,7 +201,7 @@ __device__ __forceinline__ void box_muller64(uint32_t a, uint32_t b, double &wc,
                                              double &ws) {
   const double u1 = ((double)a + 0.5) * 0x1p-32;
   const double u2 = ((double)b + 0.5) * 0x1p-32;
-  const double r = sqrt(-2.0 * log_unit(u1));
+  const double r = sqrt_normal(-2.0 * log_unit(u1));
   double s, c;
   sincos_small(kTwoPi * u2, s, c);
   wc = r * c;
@@ -177,7 +213,7 @@ __device__ __forceinline__ double box_muller64_cos(uint32_t a, uint32_t b) {
   const double u2 = ((double)b + 0.5) * 0x1p-32;
   double s, c;
   sincos_small(kTwoPi * u2, s, c);
-  return sqrt(-2.0 * log_unit(u1)) * c;
+  return sqrt_normal(-2.0 * log_unit(u1)) * c;
 }
 
 // Box-Muller in FP32 on the transcendental unit: v_log_f32 is log2 and
