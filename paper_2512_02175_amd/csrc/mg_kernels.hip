@@ -90,33 +90,32 @@ __device__ __forceinline__ void fresh_keys(uint32_t &k0, uint32_t &k1) {
 // u in (0, 1)): the argument is reduced by quarter turns, r = t - q pi/2
 // with pi/2 in two parts (Cody and Waite); for q <= 4 the first step
 // fma(-q, hi, t) is exact, so r carries the error of the second alone.
-// On |r| <= pi/4 the Taylor polynomials of degree 17 (sine) and 16
-// (cosine) leave a truncation below 1e-17, and Horner's rule with fused
-// multiply-adds keeps the result within one ulp of the correctly rounded
-// value (the general library routine handles any argument and costs several
+// On |r| <= pi/4, sin r = r + r^3 P(r^2) and cos r = 1 - r^2/2 + r^4 C(r^2)
+// with P of degree 5 and C of degree 5, minimax polynomials for the
+// relative error of sine and cosine (Remez exchange; the fit is
+// minimax_fit.py beside this file): their approximation errors are below
+// 2^-57 and 2^-63 of the value, and Horner's rule with fused multiply-adds
+// keeps the result within one ulp of glibc's sin and cos on 2e7 angles
+// (the general library routine handles any argument and costs several
 // times as much).  The quadrant then picks and signs the two.
 __device__ __forceinline__ void sincos_small(double t, double &s_out, double &c_out) {
   const double q = rint(t * 0.6366197723675814);
   double r = fma(-q, 1.5707963267948966, t);
   r = fma(-q, 6.123233995736766e-17, r);
   const double x2 = r * r;
-  double ps = -8.22063524662433e-18;  // (-1)^k / (2k+1)!, k = 8 .. 1
-  ps = fma(ps, x2, 2.8114572543455206e-15);
-  ps = fma(ps, x2, -7.647163731819816e-13);
-  ps = fma(ps, x2, 1.6059043836821613e-10);
-  ps = fma(ps, x2, -2.505210838544172e-08);
-  ps = fma(ps, x2, 2.7557319223985893e-06);
-  ps = fma(ps, x2, -0.0001984126984126984);
-  ps = fma(ps, x2, 0.008333333333333333);
-  ps = fma(ps, x2, -0.16666666666666666);
+  double ps = 1.5896230157095365e-10;  // P, highest degree first
+  ps = fma(ps, x2, -2.5050747762851854e-08);
+  ps = fma(ps, x2, 2.755731362138572e-06);
+  ps = fma(ps, x2, -0.0001984126982958954);
+  ps = fma(ps, x2, 0.008333333333322118);
+  ps = fma(ps, x2, -0.1666666666666663);
   const double sn = fma(r * x2, ps, r);
-  double pc = 4.779477332387385e-14;  // (-1)^k / (2k)!, k = 8 .. 0
-  pc = fma(pc, x2, -1.1470745597729725e-11);
-  pc = fma(pc, x2, 2.08767569878681e-09);
-  pc = fma(pc, x2, -2.755731922398589e-07);
-  pc = fma(pc, x2, 2.48015873015873e-05);
-  pc = fma(pc, x2, -0.001388888888888889);
-  pc = fma(pc, x2, 0.041666666666666664);
+  double pc = -1.1358536524507801e-11;  // C, highest degree first
+  pc = fma(pc, x2, 2.087570084203873e-09);
+  pc = fma(pc, x2, -2.7557314179297243e-07);
+  pc = fma(pc, x2, 2.4801587288851707e-05);
+  pc = fma(pc, x2, -0.0013888888888873056);
+  pc = fma(pc, x2, 0.041666666666666595);
   pc = fma(pc, x2, -0.5);
   const double cs = fma(pc, x2, 1.0);
   const int iq = (int)q & 3;
@@ -165,12 +164,13 @@ __device__ __forceinline__ double sqrt_normal(double x) {
 // Natural logarithm of a Box-Muller uniform u in (0, 1) (no zero, infinite
 // or negative arguments reach it): u = 2^e m with m in [sqrt(1/2), sqrt(2)),
 // f = m - 1 (exact), s = f / (2 + f) (div_unit), and log(1 + f) = 2 atanh(s) written as
-// f - (f^2/2 - s (f^2/2 + R)), R = sum over k = 1..10 of 2 s^(2k) / (2k + 1)
-// (the atanh Taylor series; |s| <= 0.1716 leaves a truncation below 1e-18);
-// e ln 2 with ln 2 in two parts (its first 32 bits, exact times e, and the
-// rest).  Within 0.81 ulp of the exact value on 2e7 draws of (a + 1/2) 2^-32
-// (the general library routine, with its extended-precision steps, costs
-// about twice as many FP64 operations).
+// f - (f^2/2 - s (f^2/2 + R)), R = 2 atanh(s)/s - 2 = 2 z/3 + 2 z^2/5 + ...
+// in z = s^2 <= 0.0295, here z Q(z) with Q the degree-6 minimax polynomial
+// for R (Remez exchange; minimax_fit.py beside this file), whose error is
+// below 2^-59 of log(1 + f); e ln 2 with ln 2 in two parts (its first 32
+// bits, exact times e, and the rest).  Within 0.80 ulp of the exact value
+// on 2e7 draws of (a + 1/2) 2^-32 (the general library routine, with its
+// extended-precision steps, costs about twice as many FP64 operations).
 __device__ __forceinline__ double log_unit(double u) {
   int e;
   double m = frexp(u, &e);  // m in [1/2, 1)
@@ -180,16 +180,13 @@ __device__ __forceinline__ double log_unit(double u) {
   const double f = m - 1.0;
   const double s = div_unit(f, 2.0 + f);
   const double z = s * s;
-  double r = 0.09523809523809523;  // 2 / (2k + 1), k = 10 .. 1
-  r = fma(r, z, 0.10526315789473684);
-  r = fma(r, z, 0.11764705882352941);
-  r = fma(r, z, 0.13333333333333333);
-  r = fma(r, z, 0.15384615384615385);
-  r = fma(r, z, 0.18181818181818182);
-  r = fma(r, z, 0.2222222222222222);
-  r = fma(r, z, 0.2857142857142857);
-  r = fma(r, z, 0.4);
-  r = fma(r, z, 0.6666666666666666);
+  double r = 0.1479594963458122;  // Q, highest degree first
+  r = fma(r, z, 0.15314050559867082);
+  r = fma(r, z, 0.18183564325758253);
+  r = fma(r, z, 0.22222198573192972);
+  r = fma(r, z, 0.2857142874238752);
+  r = fma(r, z, 0.3999999999941468);
+  r = fma(r, z, 0.6666666666666734);
   r = r * z;
   const double hfsq = 0.5 * f * f;
   const double de = (double)e;
