@@ -909,6 +909,10 @@ def main():
             "alg_lane_ops_per_hit": ALG_FP32_HIT,
             "measured_issue_rates": rates,
             "frac_of_measured_v_fma_f32": achieved / 1e12 / rates["v_fma_f32"]}
+    if out_fp64 is not None:
+        # the FP64 path's algorithmic rate against the measured FP64 FMA rate
+        out_fp64["frac_of_measured_v_fma_f64"] = (
+            out_fp64["alg_frac_of_alu_peak"] * PEAK_LANE_OPS / 1e12 / rates["v_fma_f64"])
 
     line = {
         "metric": METRIC, "value": value, "unit": "particle-substeps/s", "n_gpus": 1,
