@@ -40,12 +40,12 @@ PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 ALG_FP32_STEP = 27.5
 ALG_FP32_HIT = 80.0      # per vertex hit: Philox, one normal, root, time, slot, edge
 # FP64 particle-step: 1/4 Philox = 10; 1/2 Box-Muller pair (2 converts and
-# 2 scalings of the uniforms; the logarithm by range reduction and a
-# degree-6 polynomial for the atanh series, 31; the factor -2, 1; the square
-# root, 9; the angle, 1; sine and cosine by quarter-turn reduction and two
-# degree-5 polynomials, 23; 2 multiplies) = 35.5; the first sub-step (2 fma,
-# 2 compares, 2 selects of 64-bit values) = 8.5.
-ALG_FP64_STEP = 54.0
+# 2 scalings of the uniforms; the logarithm by an integer range reduction
+# and a degree-6 polynomial for the atanh series, 29; the factor -2, 1; the
+# square root, 9; the angle, 1; sine and cosine by quarter-turn reduction
+# and two degree-5 polynomials, 23; 2 multiplies) = 34.5; the first sub-step
+# (2 fma, 2 compares, 2 selects of 64-bit values) = 8.5.
+ALG_FP64_STEP = 53.0
 ALG_FP64_HIT = 130.0
 # cubic drift and diffusion: two Horner steps more for mu and three for
 # sigma at every sub-step start (a step, or a restart from a vertex)
@@ -59,7 +59,7 @@ ALG_FP32_CUBIC = 10.0
 # HBM bytes per k_pool32 launch on this workload from the FETCH_SIZE and
 # WRITE_SIZE counter passes (scaled by a 1 GiB copy), valid for the kernel
 # source whose sha256 prefix is given; reported as null for any other build.
-TRAFFIC = {"kernel_sha256": "fb8c08c26a6b1ffb", "bytes_per_launch": 270.8e6}
+TRAFFIC = {"kernel_sha256": "ef2cc7cec6d26aa1", "bytes_per_launch": 270.6e6}
 
 
 def kernel_traffic():

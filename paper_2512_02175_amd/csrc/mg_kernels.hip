@@ -162,7 +162,9 @@ __device__ __forceinline__ double sqrt_normal(double x) {
 }
 
 // Natural logarithm of a Box-Muller uniform u in (0, 1) (no zero, infinite
-// or negative arguments reach it): u = 2^e m with m in [sqrt(1/2), sqrt(2)),
+// or negative arguments reach it): u = 2^e m with m in [sqrt(1/2), sqrt(2))
+// shifted down by at most 3e-7 of itself (the split is decided on the high
+// word of the mantissa),
 // f = m - 1 (exact), s = f / (2 + f) (div_unit), and log(1 + f) = 2 atanh(s) written as
 // f - (f^2/2 - s (f^2/2 + R)), R = 2 atanh(s)/s - 2 = 2 z/3 + 2 z^2/5 + ...
 // in z = s^2 <= 0.0295, here z Q(z) with Q the degree-6 minimax polynomial
@@ -172,11 +174,15 @@ __device__ __forceinline__ double sqrt_normal(double x) {
 // on 2e7 draws of (a + 1/2) 2^-32 (the general library routine, with its
 // extended-precision steps, costs about twice as many FP64 operations).
 __device__ __forceinline__ double log_unit(double u) {
-  int e;
-  double m = frexp(u, &e);  // m in [1/2, 1)
-  const bool low = m < 0.7071067811865476;
-  m = low ? m * 2.0 : m;
-  e = low ? e - 1 : e;
+  // exponent and mantissa from the bits: adding 2^20 (1 - sqrt(1/2)) to the
+  // high word carries into the exponent exactly when the mantissa's high
+  // word is at least sqrt 2's, which picks m in [sqrt(1/2), sqrt(2)) with
+  // integer operations alone (u is normal and positive)
+  const uint64_t bits = (uint64_t)__double_as_longlong(u);
+  const uint32_t hx = (uint32_t)(bits >> 32) + 0x00095f62u;
+  const int e = (int)(hx >> 20) - 0x3ff;
+  const double m = __longlong_as_double(
+      (long long)(((uint64_t)((hx & 0x000fffffu) + 0x3fe6a09eu) << 32) | (bits & 0xffffffffull)));
   const double f = m - 1.0;
   const double s = div_unit(f, 2.0 + f);
   const double z = s * s;
